@@ -1,0 +1,79 @@
+"""Second-order finite differences for L = div(c^2 grad) on the unit box.
+
+Follows Section 2.2 (eq. discreteHelmholtz): grid points x_j = j h,
+j = 0..n, h = 1/n, with the interior equation on j = 1..n-1 and the Dirichlet
+condition W = 0 on the boundary nodes (eq. helmholtzBVP, operator eq. L).
+
+The variable-coefficient operator is the conservative 2d+1-point form
+    (L_h W)_p = (1/h^2) sum_{faces (p,q)} c2_f (W_q - W_p),
+    c2_f = (c2_p + c2_q)/2,
+which is symmetric; with c2 = 1 it is the standard 5-/7-point Laplacian.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+
+def n_unknowns(dim: int, n: int) -> int:
+    return (n - 1) ** dim
+
+
+def to_interior(a: np.ndarray) -> np.ndarray:
+    """Nodal array (n+1,)*dim -> flat interior vector (x fastest)."""
+    return np.ascontiguousarray(a[(slice(1, -1),) * a.ndim]).reshape(-1)
+
+
+def to_nodal(v: np.ndarray, dim: int, n: int) -> np.ndarray:
+    """Flat interior vector -> nodal array with a zero boundary ring."""
+    a = np.zeros((n + 1,) * dim, dtype=v.dtype)
+    a[(slice(1, -1),) * dim] = v.reshape((n - 1,) * dim)
+    return a
+
+
+def laplacian(dim: int, n: int, c2: np.ndarray | None = None) -> sp.csr_matrix:
+    """L_h as a sparse matrix on the interior unknowns."""
+    h = 1.0 / n
+    shape = (n + 1,) * dim
+    if c2 is None:
+        c2 = np.ones(shape)
+    c2 = np.asarray(c2, dtype=np.float64)
+    assert c2.shape == shape
+    # interior numbering, -1 on the boundary
+    idx = -np.ones(shape, dtype=np.int64)
+    idx[(slice(1, -1),) * dim] = np.arange((n - 1) ** dim).reshape((n - 1,) * dim)
+    inner = (slice(1, -1),) * dim
+    p_idx = idx[inner].ravel()
+    c2p = c2[inner].ravel()
+    rows, cols, vals = [], [], []
+    diag = np.zeros(p_idx.size)
+    for ax in range(dim):
+        for s in (-1, 1):
+            nb = list(inner)
+            nb[ax] = slice(1 + s, n + s)
+            q_idx = idx[tuple(nb)].ravel()
+            cf = 0.5 * (c2p + c2[tuple(nb)].ravel()) / h ** 2
+            diag -= cf
+            m = q_idx >= 0
+            rows.append(p_idx[m]); cols.append(q_idx[m]); vals.append(cf[m])
+    rows.append(p_idx); cols.append(p_idx); vals.append(diag)
+    N = p_idx.size
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(N, N))
+
+
+def helmholtz_matrix(L: sp.spmatrix, omega: float) -> sp.csc_matrix:
+    """L_h + omega^2 I  (eq. discreteHelmholtz)."""
+    return (L + omega ** 2 * sp.identity(L.shape[0], format="csr")).tocsc()
+
+
+def direct_solve(L: sp.spmatrix, omega: float, f: np.ndarray) -> np.ndarray:
+    """U* = (L_h + omega^2)^{-1} f by sparse LU: the discrete Helmholtz solution
+    that the WaveHoltz fixed point equals (Sections 2.1-2.2)."""
+    return spla.splu(helmholtz_matrix(L, omega)).solve(np.asarray(f, dtype=np.float64))
+
+
+def helmholtz_residual(L, omega, U, f) -> float:
+    """||f - (L_h + omega^2) U|| / ||f||."""
+    r = f - (L @ U + omega ** 2 * U)
+    return float(np.linalg.norm(r) / np.linalg.norm(f))
