@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Benchmark of the WaveHoltz hot path on one MI355X.
+
+One step = one complete Helmholtz solve to a true FP64 WaveHoltz residual of 1e-8
+on the 2D workload: unit square, homogeneous Dirichlet, 1024x1024 cells, c = 1,
+omega = 100.3, Gaussian source of width 0.02 at a seeded centre, deflated CG with
+the 32 analytic sine modes nearest resonance, FP32 stepping with FP64 filter sum,
+Krylov and deflation.  Inputs are resident on the GPU before timing starts.
+
+Prints one JSON line: the metric is wave-step throughput (interior points x time
+steps of every wave solve in the solve, divided by the solve's wall time), with
+the roofline of the dominant kernel (the FP32 leapfrog + filter step) and the CPU
+oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "wave-step Gpts/s (HBM roofline %) + time-to-1e-8 residual per Helmholtz solve"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per interior point per time step of the streaming FP32 step
+# kernel (c = 1, no forcing): read W^n 4 + W^{n-1} 4, write W^{n+1} 4, V read+write 16
+B_PER_PT_STEP_F32 = 28.0
+B_PER_PT_STEP_F64 = 40.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def cpu_baseline(p, nt, budget_s=12.0):
+    """The oracle (scipy CSR leapfrog, FP64) on the same operator: wave solves until
+    the time budget is used, reported as wave-step Gpts/s."""
+    import numpy as np
+    from oracle import discretization as disc, timeparams as tpm, wavesolve as ws
+    L = disc.laplacian(2, p.n)
+    tp = tpm.time_parameters(p.omega, 1.0 / p.n, 1.0)
+    v = disc.to_interior(p.f)
+    t0 = time.perf_counter()
+    k = 0
+    while time.perf_counter() - t0 < budget_s or k == 0:
+        v = ws.apply_S(L, v, tp)
+        k += 1
+    dt = time.perf_counter() - t0
+    pts = (p.n - 1) ** 2
+    return {"value": pts * tp.nt * k / dt / 1e9, "unit": "Gpts/s", "cores": 1, "kind": "oracle",
+            "sample": f"{k} FP64 wave solves (N_t={tp.nt}) of the {p.n}^2 operator with oracle.wavesolve "
+                      f"(scipy CSR, one thread) in {dt:.1f} s; host {cpu_model()}, "
+                      f"{len(os.sched_getaffinity(0))} cores visible"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-f64", action="store_true", help="skip the FP64 single-solve comparison")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solves of this workload are "
+              "single-GPU and nothing here shards across GPUs", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2606_31842_amd as wh
+    import workloads as wl
+
+    p = wl.config2()
+    n = p.n
+    pts = (n - 1) ** 2
+    f = torch.from_numpy(p.f).cuda()
+    defl = wh.sine_deflation(2, n, p.omega, 32)
+    kw = dict(solver="dcg", defl=defl, precision="mixed", tol=1e-8, max_iters=50000)
+    need = wh.workspace_bytes(2, n, wh.params(p.omega, **{k: v for k, v in kw.items() if k != "defl"}), defl)
+    wsp = torch.empty(need, dtype=torch.uint8, device="cuda")
+
+    log(f"bench: workload {p.name}, warmup {args.warmup}, steps {args.steps}")
+    for i in range(args.warmup):
+        u, info = wh.solve(f, p.omega, workspace=wsp, **kw)
+        log(f"warmup {i}: {info['ms']:.1f} ms iters {info['iters']} outer {info['outer']} "
+            f"f32 {info['wave_solves_f32']} f64 {info['wave_solves']} res {info['true_rel_res']:.2e}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for i in range(args.steps):
+        u, info = wh.solve(f, p.omega, workspace=wsp, **kw)
+        infos.append(info)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) / args.steps * 1e3
+    info = infos[-1]
+    nt = info["nt"]
+    steps_per_solve = (info["wave_solves"] + info["wave_solves_f32"]) * nt
+    value = pts * steps_per_solve / (ms / 1e3) / 1e9
+    log(f"timed: {ms:.2f} ms/solve, {steps_per_solve} wave steps/solve, {value:.1f} Gpts/s")
+
+    # error against the oracle's exact solution (DST diagonalisation, c = 1)
+    from oracle import discretization as disc
+    U = disc.direct_solve_dst(2, n, p.omega, p.f)
+    err = float(np.linalg.norm(u.cpu().numpy() - U) / np.linalg.norm(U))
+
+    # roofline of the dominant kernel: the FP32 streaming step, timed on the stream the
+    # library launches on (torch's current stream) over whole wave solves
+    v = torch.from_numpy(U).cuda()
+    out = torch.empty_like(v)
+    reps = 20
+    wh.apply_filter(v, p.omega, out=out, precision="mixed")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        wh.apply_filter(v, p.omega, out=out, precision="mixed")
+    e1.record()
+    torch.cuda.synchronize()
+    per_solve_ms = e0.elapsed_time(e1) / reps
+    per_launch_s = per_solve_ms / 1e3 / nt
+    achieved = B_PER_PT_STEP_F32 * pts / per_launch_s / 1e9
+    filt_gpts = pts * nt / (per_solve_ms / 1e3) / 1e9
+    log(f"filter: {per_solve_ms:.3f} ms per wave solve, {per_launch_s*1e6:.2f} us per step launch, "
+        f"{achieved:.0f} GB/s algorithmic")
+
+    extra = {}
+    if not args.no_f64:
+        kw64 = dict(kw, precision="f64")
+        wh.solve(f, p.omega, **kw64)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        u64, i64 = wh.solve(f, p.omega, **kw64)
+        torch.cuda.synchronize()
+        extra["f64_single_solve"] = {
+            "time_to_tol_ms": (time.perf_counter() - ta) * 1e3, "iters": i64["iters"],
+            "wave_solves": i64["wave_solves"], "true_rel_res": i64["true_rel_res"],
+            "rel_err_vs_oracle": float(np.linalg.norm(u64.cpu().numpy() - U) / np.linalg.norm(U))}
+
+    line = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gpts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32/f64",
+        "data": "synthetic",
+        "config": {"workload": "2D unit square Dirichlet 1024x1024, c=1, omega=100.3, Gaussian source "
+                               "w=0.02 at seeded centre (seed 2), DCG with the 32 sine modes nearest "
+                               "resonance, FP32 stepping / FP64 filter+Krylov, true residual 1e-8",
+                   "n": n, "omega": p.omega, "n_defl": 32, "solver": "dcg", "precision": "mixed", "tol": 1e-8},
+        "time_to_tol_ms": round(ms, 3),
+        "solve": {"iters": info["iters"], "outer": info["outer"], "wave_solves_f32": info["wave_solves_f32"],
+                  "wave_solves_f64": info["wave_solves"], "nt": nt, "true_rel_res": info["true_rel_res"],
+                  "rel_err_vs_oracle": err},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_step2d<float, M_MID> (FP32 leapfrog + FP64 filter sum)",
+                     "bytes_per_launch": B_PER_PT_STEP_F32 * pts, "launch_us": round(per_launch_s * 1e6, 3),
+                     "filter_gpts": round(filt_gpts, 2)},
+        **extra,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(p, nt)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

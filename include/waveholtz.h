@@ -1,0 +1,190 @@
+/*
+ * waveholtz.h -- C ABI of libwaveholtz, a gfx950 (MI355X) implementation of the
+ * WaveHoltz filter operator and its deflated Krylov acceleration.
+ *
+ * The operations follow "Numerical Study of Eigenvector Deflation to Accelerate
+ * the WaveHoltz Method" (Appelo, Henshaw, Peng):
+ *   - the Helmholtz problem  L u + omega^2 u = f,  L = div(c^2 grad), homogeneous
+ *     Dirichlet data on the unit box (Section 2.1, eq. helmholtzBVP, eq. L);
+ *   - the filter  Pi v = (2/Tbar) int_0^Tbar (cos(omega t) - 1/4) w(t; v) dt
+ *     (eq. waveHoltzFilter) evaluated by the explicit scheme eq. discreteWaveExplicit
+ *     and the trapezoid rule eq. quadrature, with the time-discretisation error
+ *     removed by an adjusted frequency (Section 2.2);
+ *   - the linear system A u = (I - S_h) u = b, b = Pi_h 0 (eq. WaveHoltzMatrixEquation),
+ *     solved by the fixed-point iteration (Algorithm 1), CG / deflated CG
+ *     (Algorithm 3) or restarted GMRES (Algorithm 4 with no augmentation).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid.    Unit box [0,1]^dim, dim in {2,3}, n cells per side, h = 1/n, nodes
+ *          x_j = j h, j = 0..n (eq. discreteHelmholtz).  Second-order differences
+ *          only (order == 2):  (L_h W)_p = h^-2 sum_faces c2_f (W_q - W_p),
+ *          c2_f = (c2_p + c2_q)/2.
+ * Layout.  Every grid function is a nodal array of (n+1)^dim doubles, C order with
+ *          x fastest (index (k*(n+1) + j)*(n+1) + i).  Boundary entries of inputs
+ *          v, f, u are ignored (read as 0); boundary entries of outputs are written 0.
+ *          c2 is nodal including the boundary (boundary faces use it).
+ * Memory.  Arrays marked "device" are device pointers on the context's GPU;
+ *          "host" are host pointers.  The caller owns every buffer, including the
+ *          workspace; the library allocates no device memory (it keeps a small
+ *          pinned host block per context for scalar read-backs).
+ * Stream.  All device work is enqueued on the context stream.  wh_apply_filter is
+ *          asynchronous when params->c_max > 0; solvers block until they return.
+ * Errors.  Nothing aborts or throws across the ABI.  Negative status: outputs are
+ *          not valid; WH_ENOCONV: the best iterate is returned with its residual
+ *          in wh_info.  wh_last_error() gives a message for the last failure.
+ */
+#ifndef WAVEHOLTZ_H
+#define WAVEHOLTZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WH_OK = 0,
+  WH_ENOCONV = 1,        /* tolerance not met within max_iters / max_outer; result valid */
+  WH_EINVAL = -1,        /* bad argument (null pointer, size, range, c2 <= 0)            */
+  WH_EUNSUPPORTED = -2,  /* dim not in {2,3}, order != 2, unsupported combination        */
+  WH_EHIP = -3,          /* a HIP runtime call failed                                    */
+  WH_EWORKSPACE = -4,    /* workspace missing, too small or misaligned (256 B)           */
+  WH_EUNSTABLE = -5,     /* wave solve blew up (non-finite), e.g. CFL violated           */
+  WH_EBREAKDOWN = -6     /* Krylov breakdown: p^T A p = 0, zero Arnoldi vector norm      */
+} wh_status;
+
+typedef enum { WH_F64 = 0, WH_MIXED = 1 } wh_precision;
+typedef enum { WH_FPI = 0, WH_CG = 1, WH_DCG = 2, WH_GMRES = 3 } wh_solver;
+
+/* Deflation sets (Section 2.1 "deflation set", Algorithm 3 matrix W). */
+typedef enum {
+  WH_DEFL_NONE = 0,
+  WH_DEFL_SINE = 1,        /* analytic Dirichlet modes (2/n)^{dim/2} prod sin(k pi x) (c == 1 only);
+                              the eigenvalues of A on them are known in closed form      */
+  WH_DEFL_DENSE_EXACT = 2, /* dense columns that are eigenvectors of L_h with given lambda2 */
+  WH_DEFL_DENSE = 3        /* any dense l2-orthonormal columns; A W costs n_d wave solves   */
+} wh_defl_kind;
+
+typedef struct wh_ctx wh_ctx;
+
+typedef struct {
+  int32_t dim;    /* 2 or 3 */
+  int32_t n;      /* cells per side, n >= 4 */
+  int32_t order;  /* spatial order; only 2 */
+} wh_grid;
+
+typedef struct {
+  double omega;             /* Helmholtz frequency, > 0                                    */
+  int32_t n_periods;        /* N_p >= 1: filter window Tbar = N_p periods (eq. waveHoltzFilter) */
+  double cfl;               /* c_max dt / h, 0 < cfl < 1/sqrt(dim); default 0.5             */
+  int32_t steps_per_period; /* m; 0: smallest m >= 3 with dt <= cfl h / c_max               */
+  int32_t freq_correction;  /* 1 (default): dt = 2 sin(pi/m)/omega, wave solve at
+                               omega_tilde = (2 pi/m)/dt, fixed point solves L_h + omega^2;
+                               0: dt = 2 pi/(m omega), wave solve at omega                  */
+  double c_max;             /* max_x c(x); 0: computed from c2 on the device (one read-back) */
+  int32_t precision;        /* wh_precision: WH_MIXED steps the wave equation in FP32 and
+                               keeps the filter sum, Krylov and deflation in FP64          */
+  int32_t solver;           /* wh_solver                                                    */
+  int32_t restart;          /* GMRES restart length (default 40)                            */
+  double tol;               /* stop when ||b - A u||_2 / ||b||_2 <= tol                      */
+  int32_t max_iters;        /* solver iterations (inner iterations for WH_MIXED)            */
+  double inner_tol;         /* WH_MIXED: relative tolerance of each FP32 inner solve (1e-3)  */
+  int32_t max_outer;        /* WH_MIXED: FP64 refinement sweeps (default 30)                 */
+  int32_t k_fuse;           /* time steps per stencil launch; 0: library choice             */
+  int32_t reproject;        /* DCG A-orthogonalisation against W each iteration:
+                               -1 auto (on unless F64 with exact eigenvectors), 0 off, 1 on  */
+  int32_t check_every;      /* read the residual back every this many iterations (1)        */
+} wh_params;
+
+typedef struct {
+  int32_t kind;          /* wh_defl_kind                                                   */
+  int32_t n_d;           /* number of vectors N_D >= 0 (<= 256)                             */
+  const int32_t* modes;  /* host, WH_DEFL_SINE: n_d*dim mode numbers, x first, each 1..n-1   */
+  const double* V;       /* device, dense kinds: column-major nodal columns, zero boundary  */
+  int64_t ldv;           /* leading dimension of V, >= (n+1)^dim                           */
+  const double* lambda2; /* host, WH_DEFL_DENSE_EXACT: lambda_h^2 with L_h v = -lambda2 v   */
+} wh_deflation;
+
+typedef struct {
+  int32_t status;          /* wh_status of the call                                         */
+  int32_t iters;           /* Krylov / FPI iterations (all inner iterations for WH_MIXED)  */
+  int32_t wave_solves;     /* applications of Pi_h in FP64                                  */
+  int32_t wave_solves_f32; /* applications of Pi_h with FP32 stepping                       */
+  int32_t outer;           /* WH_MIXED refinement sweeps                                    */
+  int32_t nt;              /* time steps per wave solve N_t = N_p m                         */
+  int32_t m;               /* steps per period                                              */
+  int32_t k_fuse;          /* time steps per stencil launch that was used                   */
+  double rel_res;          /* last residual the solver tracked, relative to ||b||           */
+  double true_rel_res;     /* ||b - A u|| / ||b|| recomputed with FP64 wave solves at exit   */
+  double omega_tilde;      /* frequency used inside the wave solve                          */
+  double dt;               /* time step                                                     */
+  double c_max;            /* wave speed bound used for the time step                       */
+  double ms;               /* wall time of the call in milliseconds                         */
+} wh_info;
+
+typedef struct {
+  wh_grid grid;
+  const double* c2;   /* device, nodal; NULL means c == 1                                   */
+  const double* f;    /* device, nodal source                                               */
+  double omega;       /* overrides common->omega                                            */
+  double* u;          /* device, nodal; in: initial guess, out: solution                    */
+} wh_problem;
+
+/* ------------------------------------------------------------------ context */
+void wh_params_default(wh_params* p);
+/* Create a context bound to HIP device `device`; `hip_stream` is a hipStream_t
+ * (NULL = the default stream).  The stream must outlive the context. */
+wh_status wh_create(wh_ctx** ctx, int device, void* hip_stream);
+wh_status wh_destroy(wh_ctx* ctx);
+wh_status wh_set_stream(wh_ctx* ctx, void* hip_stream);
+const char* wh_last_error(const wh_ctx* ctx);
+const char* wh_status_string(wh_status s);
+
+/* ------------------------------------------------------------------ host helpers */
+/* Time step, steps per period, N_t and adjusted frequency for given c_max (Section 2.2). */
+wh_status wh_time_params(const wh_grid* grid, const wh_params* params, double c_max,
+                         int32_t* m, int32_t* nt, double* dt, double* omega_tilde);
+/* beta_h(lambda2) = sum_n w_n T_n(1 - lambda2 dt^2/2): the eigenvalue of S_h on an
+ * eigenvector of L_h with L_h v = -lambda2 v (Section 2.3, eq. beta_fun, discrete form).
+ * lambda2 and beta are host arrays of length count. */
+wh_status wh_transfer(const wh_grid* grid, const wh_params* params, double c_max,
+                      int32_t count, const double* lambda2, double* beta);
+/* The n_d analytic Dirichlet modes whose discrete eigenvalue lambda2 is nearest to
+ * omega^2 (Section 2.3: deflate the eigenvectors with eigenvalues closest to omega),
+ * ties broken lexicographically by the mode numbers.  modes: host n_d*dim ints,
+ * lambda2: host n_d doubles (may be NULL). */
+wh_status wh_select_sine_modes(int32_t dim, int32_t n, double omega, int32_t n_d,
+                               int32_t* modes, double* lambda2);
+
+/* ------------------------------------------------------------------ workspace */
+/* Bytes of device workspace (256-byte aligned base) needed by wh_apply_filter and
+ * wh_solve with these arguments (defl may be NULL). */
+size_t wh_workspace_bytes(const wh_grid* grid, const wh_params* params, const wh_deflation* defl);
+
+/* ------------------------------------------------------------------ operations */
+/* v_out = Pi_h(v_in; f): one wave solve over N_p periods with the trapezoid filter
+ * (eq. WaveHoltzDiscreteFPI).  f == NULL gives S_h v_in; c2 == NULL means c == 1.
+ * v_in, v_out, f, c2: device nodal; v_in and v_out must not overlap. */
+wh_status wh_apply_filter(wh_ctx* ctx, const wh_grid* grid, const double* c2, const double* f,
+                          const double* v_in, double* v_out, const wh_params* params,
+                          void* ws, size_t ws_bytes, wh_info* info);
+
+/* Solve A u = b, b = Pi_h(0; f), by params->solver; the fixed point is the discrete
+ * Helmholtz solution (L_h + omega^2) u = f (Sections 2.1-2.2).  u: device nodal, in:
+ * initial guess, out: solution.  defl may be NULL (required for WH_DCG). */
+wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const double* f,
+                   const wh_deflation* defl, const wh_params* params, double* u,
+                   void* ws, size_t ws_bytes, wh_info* info);
+
+/* Relative discrete Helmholtz residual ||f - (L_h + omega^2) u|| / ||f|| over the
+ * interior (eq. discreteHelmholtz); result written to *rel (host). */
+wh_status wh_helmholtz_residual(wh_ctx* ctx, const wh_grid* grid, const double* c2,
+                                const double* f, double omega, const double* u,
+                                void* ws, size_t ws_bytes, double* rel);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WAVEHOLTZ_H */

@@ -77,3 +77,21 @@ def helmholtz_residual(L, omega, U, f) -> float:
     """||f - (L_h + omega^2) U|| / ||f||."""
     r = f - (L @ U + omega ** 2 * U)
     return float(np.linalg.norm(r) / np.linalg.norm(f))
+
+
+def direct_solve_dst(dim: int, n: int, omega: float, f_nodal: np.ndarray) -> np.ndarray:
+    """U* for c = 1 by diagonalising L_h with the type-I discrete sine transform:
+    L_h = -S diag(lam2) S with the orthonormal sine basis S (eq. discreteEigenvalueProblem;
+    lam2 = (4/h^2) sum_axes sin^2(k pi h/2)), so U = S diag(1/(omega^2 - lam2)) S f.
+    Exact up to rounding; returns the nodal solution."""
+    from scipy.fft import dstn, idstn
+    h = 1.0 / n
+    k = np.arange(1, n)
+    e1 = (4.0 / h ** 2) * np.sin(k * np.pi * h / 2.0) ** 2
+    lam2 = sum(np.meshgrid(*([e1] * dim), indexing="ij"))
+    fi = np.asarray(f_nodal, dtype=np.float64)[(slice(1, -1),) * dim]
+    fh = dstn(fi, type=1, norm="ortho")
+    U = idstn(fh / (omega ** 2 - lam2), type=1, norm="ortho")
+    out = np.zeros((n + 1,) * dim)
+    out[(slice(1, -1),) * dim] = U
+    return out

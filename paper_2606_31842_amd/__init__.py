@@ -1,0 +1,241 @@
+"""Python binding of libwaveholtz (the WaveHoltz filter and deflated Krylov solvers
+on MI355X).  PyTorch supplies device memory and the stream; every computation
+runs in the library's HIP kernels.  There is no CPU fallback: if the library is
+missing or no GPU is present, calls raise.
+
+Arrays are nodal torch float64 tensors of shape (n+1,)*dim on the GPU (last axis
+x); boundary entries of inputs are ignored and of outputs are zero.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import threading
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _native as nat
+from ._native import (WH_F64, WH_MIXED, WH_FPI, WH_CG, WH_DCG, WH_GMRES, WH_DEFL_NONE,  # noqa: F401
+                      WH_DEFL_SINE, WH_DEFL_DENSE_EXACT, WH_DEFL_DENSE, WH_OK, WH_ENOCONV)
+
+_SOLVERS = {"fpi": WH_FPI, "cg": WH_CG, "dcg": WH_DCG, "gmres": WH_GMRES}
+_PRECISIONS = {"f64": WH_F64, "mixed": WH_MIXED}
+
+
+class WaveHoltzError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"waveholtz status {status}: {msg}")
+        self.status = status
+
+
+def _torch():
+    import torch
+    return torch
+
+
+_ctx_lock = threading.Lock()
+_ctxs = {}
+
+
+def context(device: Optional[int] = None):
+    """A library context bound to the device and torch's current stream."""
+    torch = _torch()
+    if not torch.cuda.is_available():
+        raise RuntimeError("libwaveholtz needs a ROCm GPU; none is visible")
+    lib = nat.load()
+    dev = torch.cuda.current_device() if device is None else device
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    with _ctx_lock:
+        ctx = _ctxs.get(dev)
+        if ctx is None:
+            h = C.c_void_p()
+            st = lib.wh_create(C.byref(h), dev, C.c_void_p(stream))
+            if st != 0:
+                raise WaveHoltzError(st, "wh_create failed")
+            ctx = h
+            _ctxs[dev] = ctx
+        lib.wh_set_stream(ctx, C.c_void_p(stream))
+    return ctx
+
+
+def params(omega: float, **kw) -> nat.WhParams:
+    p = nat.WhParams()
+    nat.load().wh_params_default(C.byref(p))
+    p.omega = float(omega)
+    for k, v in kw.items():
+        if k == "solver":
+            v = _SOLVERS[v] if isinstance(v, str) else v
+        if k == "precision":
+            v = _PRECISIONS[v] if isinstance(v, str) else v
+        if not hasattr(p, k):
+            raise TypeError(f"unknown parameter {k}")
+        setattr(p, k, v)
+    return p
+
+
+def _grid(dim, n):
+    return nat.WhGrid(dim, n, 2)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _check(lib, ctx, st, allow_noconv=True):
+    if st < 0 or (st > 0 and not allow_noconv):
+        raise WaveHoltzError(st, lib.wh_last_error(ctx).decode())
+
+
+def _nodal(t, dim, n, name):
+    torch = _torch()
+    if t is None:
+        return None
+    if t.dtype != torch.float64 or not t.is_cuda or tuple(t.shape) != (n + 1,) * dim or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of shape {(n + 1,) * dim}")
+    return t
+
+
+def _workspace(bytes_):
+    torch = _torch()
+    return torch.empty(max(int(bytes_), 256), dtype=torch.uint8, device="cuda")
+
+
+@dataclass
+class Deflation:
+    """A deflation set: analytic sine modes (``modes``: (n_d, dim) ints) or dense
+    eigenvector columns ``V`` ((n_d, (n+1)^dim) float64 CUDA tensor, row k = column k)
+    with their ``lambda2``."""
+    kind: int
+    modes: Optional[np.ndarray] = None
+    V: Optional[object] = None
+    lambda2: Optional[np.ndarray] = None
+
+    @property
+    def n_d(self):
+        if self.kind == WH_DEFL_SINE:
+            return int(self.modes.shape[0])
+        return int(self.V.shape[0])
+
+    def to_c(self):
+        d = nat.WhDeflation()
+        d.kind = self.kind
+        d.n_d = self.n_d
+        self._keep = []
+        if self.modes is not None:
+            m = np.ascontiguousarray(self.modes, dtype=np.int32)
+            self._keep.append(m)
+            d.modes = m.ctypes.data_as(C.POINTER(C.c_int32))
+        if self.V is not None:
+            d.V = C.c_void_p(self.V.data_ptr())
+            d.ldv = int(self.V.stride(0))
+        if self.lambda2 is not None:
+            l2 = np.ascontiguousarray(self.lambda2, dtype=np.float64)
+            self._keep.append(l2)
+            d.lambda2 = l2.ctypes.data_as(C.POINTER(C.c_double))
+        return d
+
+
+def select_sine_modes(dim: int, n: int, omega: float, n_d: int):
+    """(modes (n_d, dim) int32, lambda2 (n_d,)) nearest to resonance."""
+    lib = nat.load()
+    modes = np.zeros((n_d, dim), dtype=np.int32)
+    lam2 = np.zeros(n_d)
+    st = lib.wh_select_sine_modes(dim, n, float(omega), n_d, modes.ctypes.data_as(C.POINTER(C.c_int32)),
+                                  lam2.ctypes.data_as(C.POINTER(C.c_double)))
+    if st != 0:
+        raise WaveHoltzError(st, "wh_select_sine_modes")
+    return modes, lam2
+
+
+def sine_deflation(dim, n, omega, n_d) -> Deflation:
+    modes, lam2 = select_sine_modes(dim, n, omega, n_d)
+    return Deflation(WH_DEFL_SINE, modes=modes, lambda2=None)
+
+
+def time_params(dim, n, omega, c_max=1.0, **kw):
+    lib = nat.load()
+    p = params(omega, **kw)
+    g = _grid(dim, n)
+    m, nt = C.c_int32(), C.c_int32()
+    dt, om = C.c_double(), C.c_double()
+    st = lib.wh_time_params(C.byref(g), C.byref(p), float(c_max), C.byref(m), C.byref(nt), C.byref(dt),
+                            C.byref(om))
+    if st != 0:
+        raise WaveHoltzError(st, "wh_time_params")
+    return {"m": m.value, "nt": nt.value, "dt": dt.value, "omega_tilde": om.value}
+
+
+def transfer(dim, n, omega, lambda2, c_max=1.0, **kw):
+    lib = nat.load()
+    p = params(omega, **kw)
+    g = _grid(dim, n)
+    lam = np.ascontiguousarray(lambda2, dtype=np.float64).ravel()
+    out = np.zeros_like(lam)
+    st = lib.wh_transfer(C.byref(g), C.byref(p), float(c_max), lam.size,
+                         lam.ctypes.data_as(C.POINTER(C.c_double)), out.ctypes.data_as(C.POINTER(C.c_double)))
+    if st != 0:
+        raise WaveHoltzError(st, "wh_transfer")
+    return out
+
+
+def workspace_bytes(dim, n, p: nat.WhParams, defl: Optional[Deflation] = None) -> int:
+    lib = nat.load()
+    g = _grid(dim, n)
+    d = defl.to_c() if defl is not None else None
+    return int(lib.wh_workspace_bytes(C.byref(g), C.byref(p), C.byref(d) if d is not None else None))
+
+
+def apply_filter(v, omega, f=None, c2=None, out=None, **kw):
+    """Pi_h(v; f) on the GPU.  Returns (out, info)."""
+    torch = _torch()
+    dim = v.dim()
+    n = v.shape[0] - 1
+    _nodal(v, dim, n, "v"); _nodal(f, dim, n, "f"); _nodal(c2, dim, n, "c2")
+    lib = nat.load()
+    ctx = context(v.device.index)
+    p = params(omega, **kw)
+    g = _grid(dim, n)
+    out = torch.empty_like(v) if out is None else _nodal(out, dim, n, "out")
+    ws = _workspace(lib.wh_workspace_bytes(C.byref(g), C.byref(p), None))
+    info = nat.WhInfo()
+    st = lib.wh_apply_filter(ctx, C.byref(g), _ptr(c2), _ptr(f), _ptr(v), _ptr(out), C.byref(p), _ptr(ws),
+                             ws.numel(), C.byref(info))
+    _check(lib, ctx, st)
+    return out, info.as_dict()
+
+
+def solve(f, omega, c2=None, u0=None, defl: Optional[Deflation] = None, workspace=None, **kw):
+    """Solve the WaveHoltz system for L u + omega^2 u = f.  Returns (u, info)."""
+    torch = _torch()
+    dim = f.dim()
+    n = f.shape[0] - 1
+    _nodal(f, dim, n, "f"); _nodal(c2, dim, n, "c2")
+    lib = nat.load()
+    ctx = context(f.device.index)
+    p = params(omega, **kw)
+    g = _grid(dim, n)
+    d = defl.to_c() if defl is not None else None
+    need = lib.wh_workspace_bytes(C.byref(g), C.byref(p), C.byref(d) if d is not None else None)
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need)
+    u = torch.zeros_like(f) if u0 is None else _nodal(u0, dim, n, "u0").clone()
+    info = nat.WhInfo()
+    st = lib.wh_solve(ctx, C.byref(g), _ptr(c2), _ptr(f), C.byref(d) if d is not None else None, C.byref(p),
+                      _ptr(u), _ptr(ws), ws.numel(), C.byref(info))
+    _check(lib, ctx, st)
+    return u, info.as_dict()
+
+
+def helmholtz_residual(u, f, omega, c2=None):
+    torch = _torch()
+    dim = u.dim()
+    n = u.shape[0] - 1
+    lib = nat.load()
+    ctx = context(u.device.index)
+    g = _grid(dim, n)
+    ws = _workspace(16 * 1024 + 4096)
+    rel = C.c_double()
+    st = lib.wh_helmholtz_residual(ctx, C.byref(g), _ptr(c2), _ptr(f), float(omega), _ptr(u), _ptr(ws),
+                                   ws.numel(), C.byref(rel))
+    _check(lib, ctx, st)
+    return rel.value

@@ -1,0 +1,1028 @@
+// Host side of libwaveholtz: argument validation, time parameters, the wave-solve
+// driver (one application of Pi_h) and the Krylov drivers.  All device work is
+// enqueued on the context stream; scalars live in a small device block inside the
+// caller's workspace and are read back through pinned host memory only where a
+// host decision is needed (convergence tests, Givens rotations).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "wh_common.h"
+
+using namespace wh;
+
+struct wh_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  double* hbuf = nullptr;  // pinned host scalars
+  int hbuf_len = 0;
+};
+
+namespace {
+
+constexpr int kHostScalars = 4096;
+
+// ----------------------------------------------------------------- errors
+#define WH_FAIL(ctx, code, ...)                                   \
+  do {                                                            \
+    char _b[512];                                                 \
+    snprintf(_b, sizeof(_b), __VA_ARGS__);                        \
+    if (ctx) (ctx)->err = _b;                                     \
+    return (code);                                                \
+  } while (0)
+
+#define HIPCHK(ctx, call)                                                         \
+  do {                                                                            \
+    hipError_t _e = (call);                                                       \
+    if (_e != hipSuccess)                                                         \
+      WH_FAIL(ctx, WH_EHIP, "%s failed: %s", #call, hipGetErrorString(_e));      \
+  } while (0)
+
+#define WHCHK(call)                 \
+  do {                              \
+    wh_status _s = (call);          \
+    if (_s < 0) return _s;          \
+  } while (0)
+
+// ----------------------------------------------------------------- time parameters
+struct TimeParams {
+  int m = 0, nt = 0;
+  double dt = 0, omega_w = 0, tbar = 0, c_max = 0;
+  std::vector<double> w, cosv;
+};
+
+// Section 2.2: dt from the CFL bound, m whole steps per period, the adjusted
+// frequency omega_tilde = (2 pi/m)/dt with dt = 2 sin(pi/m)/omega (so that the
+// leapfrog dispersion relation maps omega_tilde to omega), trapezoid weights
+// w_n = (2/Tbar) eta_n dt (cos(omega_tilde t^n) - 1/4).
+wh_status make_time_params(wh_ctx* ctx, int dim, int n, const wh_params& P, double c_max,
+                           TimeParams& tp) {
+  const double h = 1.0 / n;
+  if (!(c_max > 0) || !std::isfinite(c_max)) WH_FAIL(ctx, WH_EINVAL, "c_max must be > 0");
+  int m = P.steps_per_period;
+  if (m <= 0) {
+    const double dt_cfl = P.cfl * h / c_max;
+    m = std::max(3, (int)std::ceil(2.0 * M_PI / (P.omega * dt_cfl) - 1e-12));
+  }
+  if (m < 3) WH_FAIL(ctx, WH_EINVAL, "steps_per_period must be >= 3");
+  const double theta = 2.0 * M_PI / m;
+  double dt, omw;
+  if (P.freq_correction) {
+    dt = 2.0 * std::sin(theta / 2.0) / P.omega;
+    omw = theta / dt;
+  } else {
+    dt = theta / P.omega;
+    omw = P.omega;
+  }
+  const double cfl_eff = c_max * dt / h;
+  if (cfl_eff >= 1.0 / std::sqrt((double)dim))
+    WH_FAIL(ctx, WH_EINVAL, "time step violates the leapfrog stability bound (c dt/h = %g)", cfl_eff);
+  tp.m = m;
+  tp.nt = P.n_periods * m;
+  tp.dt = dt;
+  tp.omega_w = omw;
+  tp.tbar = tp.nt * dt;
+  tp.c_max = c_max;
+  tp.w.resize(tp.nt + 1);
+  tp.cosv.resize(tp.nt + 1);
+  for (int k = 0; k <= tp.nt; ++k) {
+    // cos(omega_w k dt) = cos(k theta) exactly under either reading; reduce k mod m first
+    const double c = P.freq_correction ? std::cos(theta * (k % m)) : std::cos(omw * dt * k);
+    const double eta = (k == 0 || k == tp.nt) ? 0.5 : 1.0;
+    tp.cosv[k] = c;
+    tp.w[k] = (2.0 / tp.tbar) * eta * dt * (c - 0.25);
+  }
+  return WH_OK;
+}
+
+// beta_h(lambda2) = sum_n w_n T_n(1 - lambda2 dt^2 / 2)
+double transfer(const TimeParams& tp, double lam2) {
+  const double x = 1.0 - 0.5 * lam2 * tp.dt * tp.dt;
+  double t0 = 1.0, t1 = x;
+  double s = tp.w[0] * t0 + tp.w[1] * t1;
+  for (int k = 1; k < tp.nt; ++k) {
+    double t2 = 2.0 * x * t1 - t0;
+    s += tp.w[k + 1] * t2;
+    t0 = t1;
+    t1 = t2;
+  }
+  return s;
+}
+
+// ----------------------------------------------------------------- workspace layout
+struct Layout {
+  size_t total = 0;
+  size_t Wa = 0, Wb = 0, V = 0, kap64 = 0, fs64 = 0, kap32 = 0, fs32 = 0;
+  size_t b = 0, r = 0, p = 0, q = 0, ro = 0, d = 0, basis = 0;
+  size_t partials = 0, partials2 = 0, slots = 0, tab = 0, modes = 0, invmu = 0, ones = 0;
+  int64_t N = 0;
+  int nslots = 0, npart = 0;
+};
+
+size_t take(Layout& L, size_t bytes) {
+  size_t off = L.total;
+  L.total += (bytes + 255) & ~(size_t)255;
+  return off;
+}
+
+int64_t nodal_count(int dim, int n) {
+  int64_t P = n + 1;
+  return dim == 2 ? P * P : P * P * P;
+}
+
+int defl_n(const wh_deflation* d) { return (d && d->kind != WH_DEFL_NONE) ? d->n_d : 0; }
+
+Layout make_layout(const wh_grid& g, const wh_params& P, const wh_deflation* defl) {
+  Layout L;
+  const int64_t N = nodal_count(g.dim, g.n);
+  L.N = N;
+  const int nd = defl_n(defl);
+  const bool mixed = P.precision == WH_MIXED;
+  const int restart = std::max(1, P.restart);
+  L.Wa = take(L, 8 * N);
+  L.Wb = take(L, 8 * N);
+  L.V = take(L, 8 * N);
+  L.kap64 = take(L, 8 * N);
+  L.fs64 = take(L, 8 * N);
+  if (mixed) {
+    L.kap32 = take(L, 4 * N);
+    L.fs32 = take(L, 4 * N);
+  }
+  L.b = take(L, 8 * N);
+  L.r = take(L, 8 * N);
+  L.p = take(L, 8 * N);
+  L.q = take(L, 8 * N);
+  if (mixed) {
+    L.ro = take(L, 8 * N);
+    L.d = take(L, 8 * N);
+  }
+  if (P.solver == WH_GMRES) L.basis = take(L, 8 * N * (size_t)(restart + 1));
+  Defl dd;
+  dd.kind = nd ? defl->kind : WH_DEFL_NONE;
+  dd.nd = nd;
+  dd.dim = g.dim;
+  dd.n = g.n;
+  int np = std::max(kReduceBlocks, step_partial_blocks(g.dim, g.n));
+  if (nd) np = std::max(np, defl_partial_blocks(dd) * nd);
+  L.npart = np;
+  L.partials = take(L, 8 * (size_t)np);
+  L.partials2 = take(L, 8 * (size_t)kReduceBlocks);
+  L.nslots = S_H + restart + 2 + 2 * nd + 2 * (restart + 2) + 16;
+  L.slots = take(L, 8 * (size_t)L.nslots);
+  if (nd) {
+    L.tab = take(L, 8 * (size_t)nd * g.dim * (g.n + 1));
+    L.modes = take(L, 4 * (size_t)nd * g.dim);
+    L.invmu = take(L, 8 * (size_t)nd);
+    L.ones = take(L, 8 * (size_t)nd);
+  }
+  return L;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+// ----------------------------------------------------------------- validation
+wh_status check_grid(wh_ctx* ctx, const wh_grid* g) {
+  if (!g) WH_FAIL(ctx, WH_EINVAL, "grid is NULL");
+  if (g->dim != 2 && g->dim != 3) WH_FAIL(ctx, WH_EUNSUPPORTED, "dim must be 2 or 3");
+  if (g->order != 2) WH_FAIL(ctx, WH_EUNSUPPORTED, "only second-order differences are built");
+  if (g->n < 4) WH_FAIL(ctx, WH_EINVAL, "n must be >= 4");
+  if (g->dim == 2 && g->n > 46340) WH_FAIL(ctx, WH_EINVAL, "n too large");
+  if (g->dim == 3 && g->n > 1290) WH_FAIL(ctx, WH_EINVAL, "n too large");
+  return WH_OK;
+}
+
+wh_status check_params(wh_ctx* ctx, const wh_grid* g, const wh_params* P) {
+  if (!P) WH_FAIL(ctx, WH_EINVAL, "params is NULL");
+  if (!(P->omega > 0) || !std::isfinite(P->omega)) WH_FAIL(ctx, WH_EINVAL, "omega must be > 0");
+  if (P->n_periods < 1) WH_FAIL(ctx, WH_EINVAL, "n_periods must be >= 1");
+  if (P->steps_per_period == 0 && !(P->cfl > 0 && P->cfl < 1.0 / std::sqrt((double)g->dim)))
+    WH_FAIL(ctx, WH_EINVAL, "cfl must lie in (0, 1/sqrt(dim))");
+  if (P->steps_per_period < 0 || (P->steps_per_period > 0 && P->steps_per_period < 3))
+    WH_FAIL(ctx, WH_EINVAL, "steps_per_period must be 0 or >= 3");
+  if (P->precision != WH_F64 && P->precision != WH_MIXED) WH_FAIL(ctx, WH_EINVAL, "bad precision");
+  if (P->c_max < 0) WH_FAIL(ctx, WH_EINVAL, "c_max must be >= 0");
+  if (P->k_fuse < 0 || P->k_fuse > 64) WH_FAIL(ctx, WH_EINVAL, "k_fuse must be in [0, 64]");
+  return WH_OK;
+}
+
+wh_status check_defl(wh_ctx* ctx, const wh_grid* g, const wh_deflation* d, bool varc) {
+  if (!d || d->kind == WH_DEFL_NONE) return WH_OK;
+  if (d->n_d < 0 || d->n_d > 256) WH_FAIL(ctx, WH_EINVAL, "n_d must be in [0, 256]");
+  if (d->n_d == 0) return WH_OK;
+  if (d->kind == WH_DEFL_SINE) {
+    if (varc) WH_FAIL(ctx, WH_EUNSUPPORTED, "analytic sine modes need c == 1 (c2 == NULL)");
+    if (!d->modes) WH_FAIL(ctx, WH_EINVAL, "deflation modes is NULL");
+    for (int k = 0; k < d->n_d * g->dim; ++k)
+      if (d->modes[k] < 1 || d->modes[k] > g->n - 1) WH_FAIL(ctx, WH_EINVAL, "mode number out of range");
+  } else if (d->kind == WH_DEFL_DENSE_EXACT) {
+    if (!d->V || !d->lambda2) WH_FAIL(ctx, WH_EINVAL, "dense deflation needs V and lambda2");
+    if (d->ldv < nodal_count(g->dim, g->n)) WH_FAIL(ctx, WH_EINVAL, "ldv too small");
+  } else if (d->kind == WH_DEFL_DENSE) {
+    WH_FAIL(ctx, WH_EUNSUPPORTED, "general dense deflation (A W by wave solves) is not built");
+  } else {
+    WH_FAIL(ctx, WH_EINVAL, "bad deflation kind");
+  }
+  return WH_OK;
+}
+
+wh_status check_ws(wh_ctx* ctx, void* ws, size_t ws_bytes, size_t need) {
+  if (!ws) WH_FAIL(ctx, WH_EWORKSPACE, "workspace is NULL (need %zu bytes)", need);
+  if (((uintptr_t)ws) & 255) WH_FAIL(ctx, WH_EWORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < need) WH_FAIL(ctx, WH_EWORKSPACE, "workspace too small: %zu < %zu", ws_bytes, need);
+  return WH_OK;
+}
+
+// ----------------------------------------------------------------- host read-back
+wh_status readback(wh_ctx* ctx, const double* dev, int count) {
+  if (count > ctx->hbuf_len) WH_FAIL(ctx, WH_EINVAL, "read-back too large");
+  HIPCHK(ctx, hipMemcpyAsync(ctx->hbuf, dev, sizeof(double) * count, hipMemcpyDeviceToHost,
+                             ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return WH_OK;
+}
+
+wh_status upload(wh_ctx* ctx, double* dev, const double* host, int count) {
+  if (count > ctx->hbuf_len) WH_FAIL(ctx, WH_EINVAL, "upload too large");
+  // stage through pinned memory; the copy is complete before this returns
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  std::memcpy(ctx->hbuf, host, sizeof(double) * count);
+  HIPCHK(ctx, hipMemcpyAsync(dev, ctx->hbuf, sizeof(double) * count, hipMemcpyHostToDevice,
+                             ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return WH_OK;
+}
+
+// ----------------------------------------------------------------- wave solve
+struct WaveOp {
+  int dim = 2, n = 0;
+  bool varc = false, f32 = false;
+  void* Wa = nullptr;
+  void* Wb = nullptr;
+  double* V = nullptr;
+  const void* kap = nullptr;
+  const void* fs = nullptr;
+  double a = 0;  // dt^2/h^2
+  const TimeParams* tp = nullptr;
+  double* partials = nullptr;
+  int k_fuse = 1;
+};
+
+// One wave solve from W^0 = vin.  last = M_LAST_V: V holds Pi_h(vin);
+// M_LAST_AQ: out = x - Pi_h(vin) with partial sums of x.out (x == vin);
+// M_LAST_FPI: out = Pi_h(vin) with partial sums of (out - x)^2.
+int wave_solve(const WaveOp& op, const double* vin, bool force, StepMode last, const double* x,
+               double* out, hipStream_t s) {
+  const TimeParams& tp = *op.tp;
+  StepArgs a{};
+  a.n = op.n;
+  a.kap = op.kap;
+  a.fs = force ? op.fs : nullptr;
+  a.a = op.a;
+  a.vin = vin;
+  a.prev = op.Wa;
+  a.cur_out = op.Wb;
+  a.V = op.V;
+  a.w0 = tp.w[0];
+  a.wn = tp.w[1];
+  a.cosn = tp.cosv[0];
+  launch_step(op.dim, op.f32, op.varc, force, M_FIRST, a, s);
+  void* cur = op.Wb;
+  void* prev = op.Wa;
+  int nblk = 0;
+  for (int k = 1; k < tp.nt; ++k) {
+    a.cur = cur;
+    a.prev = prev;
+    a.cosn = tp.cosv[k];
+    a.wn = tp.w[k + 1];
+    a.x = x;
+    a.out = out;
+    a.partials = op.partials;
+    const StepMode md = (k == tp.nt - 1) ? last : M_MID;
+    nblk = launch_step(op.dim, op.f32, op.varc, force, md, a, s);
+    std::swap(cur, prev);
+  }
+  return nblk;
+}
+
+// ----------------------------------------------------------------- solver state
+struct Solver {
+  wh_ctx* ctx;
+  hipStream_t s;
+  int64_t N;
+  WaveOp op64, op32;
+  double* slots;
+  double* partials;
+  double* partials2;
+  Defl defl;
+  const double* invmu = nullptr;   // 1/mu_k (device)
+  const double* negmu = nullptr;   // -1/mu_k (device) for the deflated start
+  int ws64 = 0, ws32 = 0;          // wave-solve counters
+  int iters = 0;
+};
+
+// q = A x (x nonzero).  Leaves partial sums of x.q in op.partials.
+int applyA(Solver& S, bool f32, const double* x, double* q) {
+  const WaveOp& op = f32 ? S.op32 : S.op64;
+  (f32 ? S.ws32 : S.ws64)++;
+  return wave_solve(op, x, false, M_LAST_AQ, x, q, S.s);
+}
+
+// slots[dst] = a . b
+void dot(Solver& S, const double* a, const double* b, int dst) {
+  launch_dot_partials(a, b, S.N, S.partials2, S.s);
+  launch_reduce(S.partials2, kReduceBlocks, S.slots, dst, 0, S.s);
+}
+
+struct KrylovResult {
+  double rel = 0;
+  int iters = 0;
+  wh_status st = WH_OK;
+};
+
+// CG / DCG (Algorithm 3) for A x = rhs with A applied in the requested precision.
+// x holds the initial guess (x_nonzero says whether it can be nonzero).  Stops on
+// ||r|| <= tol * ||rhs||.  Uses S.partials for step partials.
+wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_nonzero, double* r,
+                   double* p, double* q, double tol, int maxit, bool use_defl, bool reproject,
+                   int check_every, KrylovResult& res) {
+  wh_ctx* ctx = S.ctx;
+  const int64_t N = S.N;
+  const int nd = use_defl ? S.defl.nd : 0;
+  // ||rhs||^2
+  dot(S, rhs, rhs, S_NB);
+  // r_{-1}
+  if (x_nonzero) {
+    applyA(S, f32, x, q);
+    launch_sub(r, rhs, q, N, S.s);
+  } else {
+    launch_copy(r, rhs, N, S.s);
+  }
+  if (nd) {
+    // x_0 = x_{-1} + W (W^T A W)^{-1} W^T r_{-1}
+    launch_defl_project(S.defl, r, S.partials, S.s);
+    launch_defl_reduce(S.partials, defl_partial_blocks(S.defl), nd, S.slots, S_H, S.negmu, S.s);
+    launch_defl_combine(S.defl, x, 1.0, nullptr, 0.0, S.slots, S_H, N, S.s);
+    // r_0 = rhs - A x_0
+    applyA(S, f32, x, q);
+    launch_sub(r, rhs, q, N, S.s);
+    // mu_0 = (W^T A W)^{-1} (A W)^T r_0 = W^T r_0 for eigenvectors; p_0 = r_0 - W mu_0
+    launch_defl_project(S.defl, r, S.partials, S.s);
+    launch_defl_reduce(S.partials, defl_partial_blocks(S.defl), nd, S.slots, S_H, nullptr, S.s);
+    launch_defl_combine(S.defl, p, 0.0, r, 1.0, S.slots, S_H, N, S.s);
+  } else {
+    launch_copy(p, r, N, S.s);
+  }
+  dot(S, r, r, S_R2);
+  WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
+  const double nb2 = ctx->hbuf[S_NB];
+  double r2 = ctx->hbuf[S_R2];
+  if (!(nb2 > 0)) {
+    res.rel = 0;
+    res.iters = 0;
+    res.st = WH_OK;
+    return WH_OK;
+  }
+  double rel = std::sqrt(r2 / nb2);
+  if (!std::isfinite(rel)) WH_FAIL(ctx, WH_EUNSTABLE, "non-finite residual (unstable wave solve?)");
+  int k = 0;
+  const int ce = std::max(1, check_every);
+  while (rel > tol && k < maxit) {
+    int nb = applyA(S, f32, p, q);
+    launch_reduce(S.partials, nb, S.slots, S_PQ, 1, S.s);
+    launch_cg_update1(x, r, p, q, S.slots, N, S.partials2, S.s);
+    launch_reduce(S.partials2, kReduceBlocks, S.slots, S_R2, 2, S.s);
+    if (nd && reproject) {
+      launch_defl_project(S.defl, r, S.partials, S.s);
+      launch_defl_reduce(S.partials, defl_partial_blocks(S.defl), nd, S.slots, S_H, nullptr, S.s);
+      launch_dcg_update2(S.defl, p, r, S.slots, S_H, N, S.s);
+    } else {
+      launch_cg_update2(p, r, S.slots, N, S.s);
+    }
+    ++k;
+    if (k % ce == 0 || k == maxit) {
+      WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
+      const double pq = ctx->hbuf[S_PQ];
+      r2 = ctx->hbuf[S_R2];
+      if (!std::isfinite(pq) || !std::isfinite(r2))
+        WH_FAIL(ctx, WH_EUNSTABLE, "non-finite p^T A p or residual at iteration %d", k);
+      if (pq == 0.0) WH_FAIL(ctx, WH_EBREAKDOWN, "CG breakdown: p^T A p = 0 at iteration %d", k);
+      rel = std::sqrt(r2 / nb2);
+    }
+  }
+  res.rel = rel;
+  res.iters = k;
+  res.st = rel <= tol ? WH_OK : WH_ENOCONV;
+  return WH_OK;
+}
+
+// Restarted GMRES(m) (Algorithm 4 with no augmentation), modified Gram-Schmidt on
+// the device, Givens rotations and the triangular solve on the host.
+wh_status gmres_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_nonzero,
+                      double* r, double* basis, int m, double tol, int maxit, KrylovResult& res) {
+  wh_ctx* ctx = S.ctx;
+  const int64_t N = S.N;
+  dot(S, rhs, rhs, S_NB);
+  WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
+  const double nb = std::sqrt(ctx->hbuf[S_NB]);
+  if (!(nb > 0)) {
+    res = KrylovResult{};
+    return WH_OK;
+  }
+  std::vector<double> H((size_t)(m + 1) * m, 0.0), g(m + 1), cs(m), sn(m), y(m);
+  auto Hc = [&](int i, int j) -> double& { return H[(size_t)j * (m + 1) + i]; };
+  int its = 0;
+  bool first = true;
+  double rel = 1.0;
+  while (true) {
+    if (first && !x_nonzero) {
+      launch_copy(r, rhs, N, S.s);
+    } else {
+      applyA(S, f32, x, basis);  // basis[0] as scratch for A x
+      launch_sub(r, rhs, basis, N, S.s);
+    }
+    first = false;
+    dot(S, r, r, S_TMP);
+    WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
+    const double beta0 = std::sqrt(ctx->hbuf[S_TMP]);
+    if (!std::isfinite(beta0)) WH_FAIL(ctx, WH_EUNSTABLE, "non-finite residual in GMRES");
+    rel = beta0 / nb;
+    if (rel <= tol || its >= maxit) break;
+    launch_scale_copy(basis, r, S.slots, S_TMP, N, S.s);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta0;
+    int kk = 0;
+    bool done = false;
+    for (int k = 0; k < m; ++k) {
+      double* vk = basis + (size_t)k * N;
+      double* w = basis + (size_t)(k + 1) * N;
+      applyA(S, f32, vk, w);
+      // MGS: h_ik = v_i . w ; w -= h_ik v_i, fused pairwise
+      launch_axpy_dot(w, nullptr, S.slots, 0, basis, N, S.partials2, S.s);
+      launch_reduce(S.partials2, kReduceBlocks, S.slots, S_H + 0, 0, S.s);
+      for (int i = 1; i <= k; ++i) {
+        launch_axpy_dot(w, basis + (size_t)(i - 1) * N, S.slots, S_H + i - 1,
+                        basis + (size_t)i * N, N, S.partials2, S.s);
+        launch_reduce(S.partials2, kReduceBlocks, S.slots, S_H + i, 0, S.s);
+      }
+      launch_axpy_dot(w, vk, S.slots, S_H + k, nullptr, N, S.partials2, S.s);
+      launch_reduce(S.partials2, kReduceBlocks, S.slots, S_H + k + 1, 0, S.s);
+      WHCHK(readback(ctx, S.slots, S_H + k + 2));
+      for (int i = 0; i <= k; ++i) Hc(i, k) = ctx->hbuf[S_H + i];
+      const double hn2 = ctx->hbuf[S_H + k + 1];
+      if (!std::isfinite(hn2)) WH_FAIL(ctx, WH_EUNSTABLE, "non-finite Arnoldi vector");
+      Hc(k + 1, k) = std::sqrt(std::max(hn2, 0.0));
+      if (Hc(k + 1, k) > 0) launch_scale_copy(w, w, S.slots, S_H + k + 1, N, S.s);
+      for (int i = 0; i < k; ++i) {
+        const double t = cs[i] * Hc(i, k) + sn[i] * Hc(i + 1, k);
+        Hc(i + 1, k) = -sn[i] * Hc(i, k) + cs[i] * Hc(i + 1, k);
+        Hc(i, k) = t;
+      }
+      const double a = Hc(k, k), b = Hc(k + 1, k);
+      const double dd = std::hypot(a, b);
+      cs[k] = dd == 0 ? 1.0 : a / dd;
+      sn[k] = dd == 0 ? 0.0 : b / dd;
+      Hc(k, k) = dd;
+      Hc(k + 1, k) = 0.0;
+      g[k + 1] = -sn[k] * g[k];
+      g[k] = cs[k] * g[k];
+      ++its;
+      kk = k + 1;
+      if (std::fabs(g[k + 1]) < tol * nb || its >= maxit) {
+        done = true;
+        break;
+      }
+      if (dd == 0.0) WH_FAIL(ctx, WH_EBREAKDOWN, "GMRES breakdown (singular Hessenberg)");
+      if (b == 0.0) {  // lucky breakdown: exact solution in the space
+        done = true;
+        break;
+      }
+    }
+    for (int i = kk - 1; i >= 0; --i) {
+      double sacc = g[i];
+      for (int j = i + 1; j < kk; ++j) sacc -= Hc(i, j) * y[j];
+      y[i] = sacc / Hc(i, i);
+    }
+    WHCHK(upload(ctx, S.slots + S_H, y.data(), kk));
+    launch_gemv_acc(x, basis, N, kk, S.slots + S_H, N, S.s);
+    if (done && its >= maxit) {
+      applyA(S, f32, x, basis);
+      launch_sub(r, rhs, basis, N, S.s);
+      dot(S, r, r, S_TMP);
+      WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
+      rel = std::sqrt(ctx->hbuf[S_TMP]) / nb;
+      break;
+    }
+    (void)done;
+  }
+  res.rel = rel;
+  res.iters = its;
+  res.st = rel <= tol ? WH_OK : WH_ENOCONV;
+  return WH_OK;
+}
+
+// Fixed-point iteration (Algorithm 1): x <- Pi_h(x; f) until ||Pi x - x|| <= tol ||b||.
+wh_status fpi_solve(Solver& S, double* x, double tol, int maxit, int check_every,
+                    KrylovResult& res) {
+  wh_ctx* ctx = S.ctx;
+  // ||b||^2 (b = Pi_h(0; f)) is expected in slots[S_NB]
+  double nb2 = 0;
+  res = KrylovResult{};
+  int k = 0;
+  double rel = 1.0;
+  const int ce = std::max(1, check_every);
+  while (k < maxit) {
+    int nb = wave_solve(S.op64, x, true, M_LAST_FPI, x, x, S.s);
+    S.ws64++;
+    launch_reduce(S.partials, nb, S.slots, S_TMP, 0, S.s);
+    ++k;
+    if (k % ce == 0 || k == maxit) {
+      WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
+      nb2 = ctx->hbuf[S_NB];
+      rel = nb2 > 0 ? std::sqrt(ctx->hbuf[S_TMP] / nb2) : 0.0;
+      if (!std::isfinite(rel)) WH_FAIL(ctx, WH_EUNSTABLE, "non-finite FPI update");
+      if (rel <= tol) break;
+    }
+  }
+  res.rel = rel;
+  res.iters = k;
+  res.st = rel <= tol ? WH_OK : WH_ENOCONV;
+  return WH_OK;
+}
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Common setup for wh_apply_filter / wh_solve: c_max, time parameters, coefficient
+// arrays in the stepping precisions.
+wh_status setup_ops(wh_ctx* ctx, const wh_grid& g, const wh_params& P, const double* c2,
+                    const double* f, void* ws, const Layout& L, TimeParams& tp, Solver& S) {
+  hipStream_t s = ctx->stream;
+  const bool varc = c2 != nullptr;
+  const bool mixed = P.precision == WH_MIXED;
+  double c_max = P.c_max;
+  if (c_max == 0) {
+    if (varc) {
+      double* part = at<double>(ws, L.partials2);
+      double* slots = at<double>(ws, L.slots);
+      launch_max_partials(c2, L.N, part, false, s);
+      launch_max_finalize(part, kReduceBlocks, slots + S_TMP2, s);
+      launch_max_partials(c2, L.N, part, true, s);
+      launch_max_finalize(part, kReduceBlocks, slots + S_TMP, s);
+      WHCHK(readback(ctx, slots, S_NSLOTS_FIXED));
+      const double m = ctx->hbuf[S_TMP2];
+      const double negmin = ctx->hbuf[S_TMP];
+      if (!(m > 0) || !std::isfinite(m) || !(negmin < 0))
+        WH_FAIL(ctx, WH_EINVAL, "c2 must be positive and finite at every node");
+      c_max = std::sqrt(m);
+    } else {
+      c_max = 1.0;
+    }
+  }
+  WHCHK(make_time_params(ctx, g.dim, g.n, P, c_max, tp));
+  const double h = 1.0 / g.n;
+  const double dt2 = tp.dt * tp.dt;
+  const double ks = dt2 / (2.0 * h * h);
+  launch_prep_coeffs(c2, f, at<void>(ws, L.kap64), at<void>(ws, L.fs64), false, ks, dt2, L.N, g.n,
+                     g.dim, s);
+  if (mixed)
+    launch_prep_coeffs(c2, f, at<void>(ws, L.kap32), at<void>(ws, L.fs32), true, ks, dt2, L.N, g.n,
+                       g.dim, s);
+  S.ctx = ctx;
+  S.s = s;
+  S.N = L.N;
+  S.slots = at<double>(ws, L.slots);
+  S.partials = at<double>(ws, L.partials);
+  S.partials2 = at<double>(ws, L.partials2);
+  WaveOp base;
+  base.dim = g.dim;
+  base.n = g.n;
+  base.varc = varc;
+  base.Wa = at<void>(ws, L.Wa);
+  base.Wb = at<void>(ws, L.Wb);
+  base.V = at<double>(ws, L.V);
+  base.a = dt2 / (h * h);
+  base.tp = &tp;
+  base.partials = S.partials;
+  S.op64 = base;
+  S.op64.f32 = false;
+  S.op64.kap = at<void>(ws, L.kap64);
+  S.op64.fs = at<void>(ws, L.fs64);
+  S.op32 = base;
+  S.op32.f32 = true;
+  if (mixed) {
+    S.op32.kap = at<void>(ws, L.kap32);
+    S.op32.fs = at<void>(ws, L.fs32);
+  }
+  return WH_OK;
+}
+
+void fill_info(wh_info* info, const TimeParams& tp) {
+  if (!info) return;
+  info->nt = tp.nt;
+  info->m = tp.m;
+  info->dt = tp.dt;
+  info->omega_tilde = tp.omega_w;
+  info->c_max = tp.c_max;
+  info->k_fuse = 1;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+void wh_params_default(wh_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->omega = 1.0;
+  p->n_periods = 1;
+  p->cfl = 0.5;
+  p->steps_per_period = 0;
+  p->freq_correction = 1;
+  p->c_max = 0.0;
+  p->precision = WH_F64;
+  p->solver = WH_CG;
+  p->restart = 40;
+  p->tol = 1e-8;
+  p->max_iters = 10000;
+  p->inner_tol = 1e-3;
+  p->max_outer = 30;
+  p->k_fuse = 0;
+  p->reproject = -1;
+  p->check_every = 1;
+}
+
+const char* wh_status_string(wh_status s) {
+  switch (s) {
+    case WH_OK: return "ok";
+    case WH_ENOCONV: return "tolerance not reached";
+    case WH_EINVAL: return "invalid argument";
+    case WH_EUNSUPPORTED: return "unsupported";
+    case WH_EHIP: return "HIP runtime error";
+    case WH_EWORKSPACE: return "workspace missing or too small";
+    case WH_EUNSTABLE: return "unstable wave solve";
+    case WH_EBREAKDOWN: return "Krylov breakdown";
+  }
+  return "unknown status";
+}
+
+wh_status wh_create(wh_ctx** out, int device, void* stream) {
+  if (!out) return WH_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return WH_EHIP;
+  if (hipSetDevice(device) != hipSuccess) return WH_EHIP;
+  wh_ctx* c = new wh_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  if (hipHostMalloc((void**)&c->hbuf, sizeof(double) * kHostScalars, hipHostMallocDefault) !=
+      hipSuccess) {
+    delete c;
+    return WH_EHIP;
+  }
+  c->hbuf_len = kHostScalars;
+  *out = c;
+  return WH_OK;
+}
+
+wh_status wh_destroy(wh_ctx* ctx) {
+  if (!ctx) return WH_EINVAL;
+  if (ctx->hbuf) (void)hipHostFree(ctx->hbuf);
+  delete ctx;
+  return WH_OK;
+}
+
+wh_status wh_set_stream(wh_ctx* ctx, void* stream) {
+  if (!ctx) return WH_EINVAL;
+  ctx->stream = (hipStream_t)stream;
+  return WH_OK;
+}
+
+const char* wh_last_error(const wh_ctx* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+wh_status wh_time_params(const wh_grid* grid, const wh_params* params, double c_max, int32_t* m,
+                         int32_t* nt, double* dt, double* omega_tilde) {
+  WHCHK(check_grid(nullptr, grid));
+  WHCHK(check_params(nullptr, grid, params));
+  TimeParams tp;
+  WHCHK(make_time_params(nullptr, grid->dim, grid->n, *params, c_max > 0 ? c_max : 1.0, tp));
+  if (m) *m = tp.m;
+  if (nt) *nt = tp.nt;
+  if (dt) *dt = tp.dt;
+  if (omega_tilde) *omega_tilde = tp.omega_w;
+  return WH_OK;
+}
+
+wh_status wh_transfer(const wh_grid* grid, const wh_params* params, double c_max, int32_t count,
+                      const double* lambda2, double* beta) {
+  WHCHK(check_grid(nullptr, grid));
+  WHCHK(check_params(nullptr, grid, params));
+  if (count < 0 || (count > 0 && (!lambda2 || !beta))) return WH_EINVAL;
+  TimeParams tp;
+  WHCHK(make_time_params(nullptr, grid->dim, grid->n, *params, c_max > 0 ? c_max : 1.0, tp));
+  for (int i = 0; i < count; ++i) beta[i] = transfer(tp, lambda2[i]);
+  return WH_OK;
+}
+
+wh_status wh_select_sine_modes(int32_t dim, int32_t n, double omega, int32_t n_d, int32_t* modes,
+                               double* lambda2) {
+  if ((dim != 2 && dim != 3) || n < 4 || n_d < 0 || !(omega > 0) || (n_d > 0 && !modes))
+    return WH_EINVAL;
+  const double h = 1.0 / n;
+  std::vector<double> e(n);
+  for (int k = 1; k < n; ++k) {
+    const double sv = std::sin(M_PI * k * h / 2.0);
+    e[k] = 4.0 / (h * h) * sv * sv;
+  }
+  const double om2 = omega * omega;
+  struct Cand {
+    double dist, lam2;
+    int k[3];
+  };
+  std::vector<Cand> c;
+  const int K = n - 1;
+  if ((int64_t)K * K * (dim == 3 ? K : 1) < n_d) return WH_EINVAL;
+  // Enumerate in lexicographic order; keep all (the sort below is stable).
+  if (dim == 2) {
+    c.reserve((size_t)K * K);
+    for (int p = 1; p <= K; ++p)
+      for (int q = 1; q <= K; ++q) {
+        double l2 = e[p] + e[q];
+        c.push_back({std::fabs(l2 - om2), l2, {p, q, 0}});
+      }
+  } else {
+    for (int p = 1; p <= K; ++p)
+      for (int q = 1; q <= K; ++q)
+        for (int r = 1; r <= K; ++r) {
+          double l2 = e[p] + e[q] + e[r];
+          c.push_back({std::fabs(l2 - om2), l2, {p, q, r}});
+        }
+  }
+  std::stable_sort(c.begin(), c.end(), [](const Cand& a, const Cand& b) { return a.dist < b.dist; });
+  for (int i = 0; i < n_d; ++i) {
+    for (int a = 0; a < dim; ++a) modes[i * dim + a] = c[i].k[a];
+    if (lambda2) lambda2[i] = c[i].lam2;
+  }
+  return WH_OK;
+}
+
+size_t wh_workspace_bytes(const wh_grid* grid, const wh_params* params, const wh_deflation* defl) {
+  if (!grid || !params || check_grid(nullptr, grid) != WH_OK) return 0;
+  return make_layout(*grid, *params, defl).total;
+}
+
+wh_status wh_apply_filter(wh_ctx* ctx, const wh_grid* grid, const double* c2, const double* f,
+                          const double* v_in, double* v_out, const wh_params* params, void* ws,
+                          size_t ws_bytes, wh_info* info) {
+  if (!ctx) return WH_EINVAL;
+  const double t0 = now_ms();
+  WHCHK(check_grid(ctx, grid));
+  WHCHK(check_params(ctx, grid, params));
+  if (!v_in || !v_out) WH_FAIL(ctx, WH_EINVAL, "v_in / v_out is NULL");
+  const Layout L = make_layout(*grid, *params, nullptr);
+  WHCHK(check_ws(ctx, ws, ws_bytes, L.total));
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  TimeParams tp;
+  Solver S{};
+  WHCHK(setup_ops(ctx, *grid, *params, c2, f, ws, L, tp, S));
+  WaveOp op = params->precision == WH_MIXED ? S.op32 : S.op64;
+  op.V = v_out;  // accumulate straight into the output
+  wave_solve(op, v_in, f != nullptr, M_LAST_V, nullptr, nullptr, ctx->stream);
+  HIPCHK(ctx, hipGetLastError());
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    fill_info(info, tp);
+    info->wave_solves = params->precision == WH_MIXED ? 0 : 1;
+    info->wave_solves_f32 = params->precision == WH_MIXED ? 1 : 0;
+    info->ms = now_ms() - t0;
+  }
+  return WH_OK;
+}
+
+wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const double* f,
+                   const wh_deflation* defl, const wh_params* params, double* u, void* ws,
+                   size_t ws_bytes, wh_info* info) {
+  if (!ctx) return WH_EINVAL;
+  const double t0 = now_ms();
+  if (info) std::memset(info, 0, sizeof(*info));
+  WHCHK(check_grid(ctx, grid));
+  WHCHK(check_params(ctx, grid, params));
+  if (!f || !u) WH_FAIL(ctx, WH_EINVAL, "f / u is NULL");
+  const wh_params& P = *params;
+  if (P.solver < WH_FPI || P.solver > WH_GMRES) WH_FAIL(ctx, WH_EINVAL, "bad solver");
+  if (!(P.tol > 0)) WH_FAIL(ctx, WH_EINVAL, "tol must be > 0");
+  if (P.max_iters < 0) WH_FAIL(ctx, WH_EINVAL, "max_iters must be >= 0");
+  if (P.solver == WH_GMRES && (P.restart < 1 || P.restart > 1000))
+    WH_FAIL(ctx, WH_EINVAL, "restart must be in [1, 1000]");
+  WHCHK(check_defl(ctx, grid, defl, c2 != nullptr));
+  const int nd = defl_n(defl);
+  if (P.solver == WH_DCG && nd == 0) WH_FAIL(ctx, WH_EINVAL, "DCG needs a deflation set");
+  if (P.solver != WH_DCG && nd > 0)
+    WH_FAIL(ctx, WH_EUNSUPPORTED, "deflation is used by DCG only");
+  const bool mixed = P.precision == WH_MIXED;
+  if (mixed && P.solver == WH_FPI) WH_FAIL(ctx, WH_EUNSUPPORTED, "FPI runs in FP64 only");
+  const Layout L = make_layout(*grid, P, defl);
+  WHCHK(check_ws(ctx, ws, ws_bytes, L.total));
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  TimeParams tp;
+  Solver S{};
+  WHCHK(setup_ops(ctx, *grid, P, c2, f, ws, L, tp, S));
+  const int64_t N = L.N;
+  launch_zero_boundary(u, grid->n, grid->dim, s);
+  double* b = at<double>(ws, L.b);
+  double* r = at<double>(ws, L.r);
+  double* p = at<double>(ws, L.p);
+  double* q = at<double>(ws, L.q);
+  HIPCHK(ctx, hipMemsetAsync(r, 0, 8 * N, s));
+  HIPCHK(ctx, hipMemsetAsync(p, 0, 8 * N, s));
+  HIPCHK(ctx, hipMemsetAsync(q, 0, 8 * N, s));
+  HIPCHK(ctx, hipMemsetAsync(S.slots, 0, 8 * (size_t)L.nslots, s));
+  // the stencil epilogues write interior nodes only: Krylov vectors keep a zero boundary
+  if (P.solver == WH_GMRES)
+    HIPCHK(ctx, hipMemsetAsync(at<double>(ws, L.basis), 0, 8 * (size_t)N * (std::max(1, P.restart) + 1), s));
+  if (mixed) {
+    HIPCHK(ctx, hipMemsetAsync(at<double>(ws, L.ro), 0, 8 * N, s));
+    HIPCHK(ctx, hipMemsetAsync(at<double>(ws, L.d), 0, 8 * N, s));
+  }
+  // deflation set
+  bool reproject = P.reproject == 1 || (P.reproject < 0 && mixed);
+  if (nd) {
+    S.defl.kind = defl->kind;
+    S.defl.nd = nd;
+    S.defl.dim = grid->dim;
+    S.defl.n = grid->n;
+    std::vector<double> lam2(nd);
+    if (defl->kind == WH_DEFL_SINE) {
+      const double h = 1.0 / grid->n;
+      for (int k = 0; k < nd; ++k) {
+        double l2 = 0;
+        for (int a = 0; a < grid->dim; ++a) {
+          const double sv = std::sin(M_PI * defl->modes[k * grid->dim + a] * h / 2.0);
+          l2 += 4.0 / (h * h) * sv * sv;
+        }
+        lam2[k] = l2;
+      }
+      // mode numbers to the device (through the pinned block as doubles -> ints)
+      std::vector<int32_t> md(defl->modes, defl->modes + nd * grid->dim);
+      HIPCHK(ctx, hipStreamSynchronize(s));
+      std::memcpy(ctx->hbuf, md.data(), md.size() * sizeof(int32_t));
+      HIPCHK(ctx, hipMemcpyAsync(at<int32_t>(ws, L.modes), ctx->hbuf, md.size() * sizeof(int32_t),
+                                 hipMemcpyHostToDevice, s));
+      HIPCHK(ctx, hipStreamSynchronize(s));
+      launch_sine_tables(at<double>(ws, L.tab), at<int32_t>(ws, L.modes), nd, grid->dim, grid->n, s);
+      S.defl.tab = at<double>(ws, L.tab);
+    } else {
+      for (int k = 0; k < nd; ++k) lam2[k] = defl->lambda2[k];
+      S.defl.V = defl->V;
+      S.defl.ldv = defl->ldv;
+    }
+    std::vector<double> inv(nd), neg(nd);
+    for (int k = 0; k < nd; ++k) {
+      const double mu = 1.0 - transfer(tp, lam2[k]);
+      if (mu == 0.0) WH_FAIL(ctx, WH_EBREAKDOWN, "deflation vector %d is at resonance (mu = 0)", k);
+      inv[k] = 1.0 / mu;
+      neg[k] = -1.0 / mu;
+    }
+    WHCHK(upload(ctx, at<double>(ws, L.invmu), inv.data(), nd));
+    WHCHK(upload(ctx, at<double>(ws, L.ones), neg.data(), nd));
+    S.invmu = at<double>(ws, L.invmu);
+    S.negmu = at<double>(ws, L.ones);
+    if (defl->kind == WH_DEFL_DENSE_EXACT && P.reproject < 0) reproject = mixed;
+  }
+  // b = Pi_h(0; f) in FP64: one wave solve from zero, accumulated into b
+  {
+    WaveOp ob = S.op64;
+    ob.V = b;
+    HIPCHK(ctx, hipMemsetAsync(q, 0, 8 * N, s));
+    wave_solve(ob, q, true, M_LAST_V, nullptr, nullptr, s);
+    S.ws64++;
+  }
+  // is the initial guess nonzero?
+  dot(S, u, u, S_TMP2);
+  WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
+  const bool u_nonzero = ctx->hbuf[S_TMP2] > 0;
+  wh_status st = WH_OK;
+  KrylovResult kr;
+  int outer = 0;
+  double true_rel = -1.0;
+  const int restart = std::max(1, P.restart);
+  if (!mixed) {
+    if (P.solver == WH_FPI) {
+      // FPI: x <- Pi x with the forcing on; ||b||^2 for the relative update
+      dot(S, b, b, S_NB);
+      WHCHK(fpi_solve(S, u, P.tol, P.max_iters, P.check_every, kr));
+    } else if (P.solver == WH_GMRES) {
+      WHCHK(gmres_solve(S, false, b, u, u_nonzero, r, at<double>(ws, L.basis), restart, P.tol,
+                        P.max_iters, kr));
+    } else {
+      WHCHK(cg_solve(S, false, b, u, u_nonzero, r, p, q, P.tol, P.max_iters, P.solver == WH_DCG,
+                     reproject, P.check_every, kr));
+    }
+    st = kr.st;
+    S.iters = kr.iters;
+    // true FP64 residual at exit
+    applyA(S, false, u, q);
+    launch_sub(r, b, q, N, s);
+    dot(S, r, r, S_TMP);
+    dot(S, b, b, S_NB);
+    WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
+    true_rel = ctx->hbuf[S_NB] > 0 ? std::sqrt(ctx->hbuf[S_TMP] / ctx->hbuf[S_NB]) : 0.0;
+  } else {
+    // FP64 outer residual, FP32 inner solves
+    double* ro = at<double>(ws, L.ro);
+    double* dv = at<double>(ws, L.d);
+    dot(S, b, b, S_NB);
+    WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
+    const double nb = std::sqrt(ctx->hbuf[S_NB]);
+    const int max_outer = P.max_outer > 0 ? P.max_outer : 30;
+    const double itol = P.inner_tol > 0 ? P.inner_tol : 1e-3;
+    bool nonzero = u_nonzero;
+    int inner_total = 0;
+    st = WH_ENOCONV;
+    double rel = 1.0;
+    for (outer = 0; outer <= max_outer; ++outer) {
+      if (nonzero) {
+        applyA(S, false, u, q);
+        launch_sub(ro, b, q, N, s);
+      } else {
+        launch_copy(ro, b, N, s);
+      }
+      dot(S, ro, ro, S_TMP);
+      WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
+      rel = nb > 0 ? std::sqrt(ctx->hbuf[S_TMP]) / nb : 0.0;
+      if (!std::isfinite(rel)) WH_FAIL(ctx, WH_EUNSTABLE, "non-finite outer residual");
+      if (rel <= P.tol) {
+        st = WH_OK;
+        break;
+      }
+      if (outer == max_outer || inner_total >= P.max_iters) break;
+      // inner: A32 d = ro to a relative tolerance (never tighter than needed)
+      const double t_in = std::max(itol, 0.3 * P.tol / rel);
+      HIPCHK(ctx, hipMemsetAsync(dv, 0, 8 * N, s));
+      KrylovResult ir;
+      if (P.solver == WH_GMRES) {
+        WHCHK(gmres_solve(S, true, ro, dv, false, r, at<double>(ws, L.basis), restart, t_in,
+                          P.max_iters - inner_total, ir));
+      } else {
+        WHCHK(cg_solve(S, true, ro, dv, false, r, p, q, t_in, P.max_iters - inner_total,
+                       P.solver == WH_DCG, reproject, P.check_every, ir));
+      }
+      inner_total += ir.iters;
+      launch_axpy(u, dv, 1.0, N, s);
+      nonzero = true;
+    }
+    S.iters = inner_total;
+    kr.rel = rel;
+    true_rel = rel;
+  }
+  HIPCHK(ctx, hipGetLastError());
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  if (info) {
+    fill_info(info, tp);
+    info->status = st;
+    info->iters = S.iters;
+    info->wave_solves = S.ws64;
+    info->wave_solves_f32 = S.ws32;
+    info->outer = outer;
+    info->rel_res = kr.rel;
+    info->true_rel_res = true_rel;
+    info->ms = now_ms() - t0;
+  }
+  if (st == WH_ENOCONV) ctx->err = "tolerance not reached";
+  return st;
+}
+
+wh_status wh_helmholtz_residual(wh_ctx* ctx, const wh_grid* grid, const double* c2,
+                                const double* f, double omega, const double* u, void* ws,
+                                size_t ws_bytes, double* rel) {
+  if (!ctx) return WH_EINVAL;
+  WHCHK(check_grid(ctx, grid));
+  if (!f || !u || !rel) WH_FAIL(ctx, WH_EINVAL, "NULL argument");
+  const size_t need = 16 * (size_t)kReduceBlocks + 256;
+  WHCHK(check_ws(ctx, ws, ws_bytes, need));
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  double* pr = at<double>(ws, 0);
+  double* pf = pr + kReduceBlocks;
+  double* out = at<double>(ws, 16 * (size_t)kReduceBlocks);
+  const double ih2 = (double)grid->n * grid->n;
+  launch_helmholtz_residual(c2, f, u, omega * omega, ih2, grid->n, grid->dim, pr, pf, ctx->stream);
+  launch_reduce(pr, kReduceBlocks, out, 0, 0, ctx->stream);
+  launch_reduce(pf, kReduceBlocks, out, 1, 0, ctx->stream);
+  HIPCHK(ctx, hipGetLastError());
+  WHCHK(readback(ctx, out, 2));
+  *rel = ctx->hbuf[1] > 0 ? std::sqrt(ctx->hbuf[0] / ctx->hbuf[1]) : 0.0;
+  return WH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,474 @@
+// Vector kernels of the Krylov solvers (Section 3): FP64 reductions, CG updates,
+// Gram-Schmidt steps and the deflation projections W^T r / W c.
+//
+// Reductions are two-pass and deterministic: a fixed grid writes one partial sum
+// per block (wave64 shuffle tree, then the four waves in order), and a single
+// block adds the partials in index order.  No floating-point atomics are used.
+#include "wh_common.h"
+#include "wh_reduce.h"
+
+namespace wh {
+
+#define GRID_STRIDE(idx, N) \
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (N); \
+       idx += (int64_t)gridDim.x * blockDim.x)
+
+static inline unsigned grid_for(int64_t N) {
+  int64_t b = (N + kBlock - 1) / kBlock;
+  return (unsigned)(b < 1 ? 1 : (b > kReduceBlocks ? kReduceBlocks : b));
+}
+
+// ----------------------------------------------------------------- coefficients
+template <typename T>
+__global__ void k_prep(const double* c2, const double* f, T* kap, T* fs, double ks, double fsc,
+                       int64_t N, int n, int dim) {
+  const int64_t P = n + 1;
+  GRID_STRIDE(p, N) {
+    if (c2) kap[p] = (T)(c2[p] * ks);
+    if (f) {
+      int i = (int)(p % P), j = (int)((p / P) % P), k = dim == 3 ? (int)(p / (P * P)) : 1;
+      bool in = i > 0 && i < n && j > 0 && j < n && (dim == 2 || (k > 0 && k < n));
+      fs[p] = in ? (T)(f[p] * fsc) : T(0);
+    }
+  }
+}
+
+void launch_prep_coeffs(const double* c2, const double* f, void* kap, void* fs, bool f32,
+                        double ks, double fsc, int64_t N, int n, int dim, hipStream_t s) {
+  if (f32)
+    hipLaunchKernelGGL(k_prep<float>, dim3(grid_for(N)), dim3(kBlock), 0, s, c2, f, (float*)kap,
+                       (float*)fs, ks, fsc, N, n, dim);
+  else
+    hipLaunchKernelGGL(k_prep<double>, dim3(grid_for(N)), dim3(kBlock), 0, s, c2, f,
+                       (double*)kap, (double*)fs, ks, fsc, N, n, dim);
+}
+
+__global__ void k_zero_boundary(double* u, int n, int dim, int64_t N) {
+  const int64_t P = n + 1;
+  GRID_STRIDE(p, N) {
+    int i = (int)(p % P), j = (int)((p / P) % P), k = dim == 3 ? (int)(p / (P * P)) : 1;
+    bool in = i > 0 && i < n && j > 0 && j < n && (dim == 2 || (k > 0 && k < n));
+    if (!in) u[p] = 0.0;
+  }
+}
+
+void launch_zero_boundary(double* u, int n, int dim, hipStream_t s) {
+  int64_t P = n + 1, N = dim == 2 ? P * P : P * P * P;
+  hipLaunchKernelGGL(k_zero_boundary, dim3(grid_for(N)), dim3(kBlock), 0, s, u, n, dim, N);
+}
+
+// ----------------------------------------------------------------- reductions
+__global__ void k_max_partials(const double* a, int64_t N, double* partials, bool neg) {
+  double m = -1.0e308;
+  GRID_STRIDE(p, N) m = fmax(m, neg ? -a[p] : a[p]);
+  double r = block_max256(m, threadIdx.x);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+void launch_max_partials(const double* a, int64_t N, double* partials, bool neg, hipStream_t s) {
+  hipLaunchKernelGGL(k_max_partials, dim3(kReduceBlocks), dim3(kBlock), 0, s, a, N, partials, neg);
+}
+
+__global__ void k_max_finalize(const double* partials, int count, double* out) {
+  double m = -1.0e308;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) m = fmax(m, partials[i]);
+  double r = block_max256(m, threadIdx.x);
+  if (threadIdx.x == 0) out[0] = r;
+}
+
+void launch_max_finalize(const double* partials, int count, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_max_finalize, dim3(1), dim3(kBlock), 0, s, partials, count, out);
+}
+
+__global__ void k_dot_partials(const double* a, const double* b, int64_t N, double* partials) {
+  double acc = 0.0;
+  GRID_STRIDE(p, N) acc += a[p] * b[p];
+  double r = block_sum256(acc, threadIdx.x);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+void launch_dot_partials(const double* a, const double* b, int64_t N, double* partials,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_partials, dim3(kReduceBlocks), dim3(kBlock), 0, s, a, b, N, partials);
+}
+
+__global__ void k_reduce(const double* partials, int count, double* slots, int dst, int mode) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) acc += partials[i];
+  double s = block_sum256(acc, threadIdx.x);
+  if (threadIdx.x == 0) {
+    if (mode == 0) {
+      slots[dst] = s;
+    } else if (mode == 1) {        // p^T q -> alpha
+      slots[S_PQ] = s;
+      slots[S_ALPHA] = slots[S_R2] / s;
+    } else if (mode == 2) {        // r^T r -> beta
+      slots[S_BETA] = s / slots[S_R2];
+      slots[S_R2] = s;
+    }
+  }
+}
+
+void launch_reduce(const double* partials, int count, double* slots, int dst, int mode,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, partials, count, slots, dst, mode);
+}
+
+// ----------------------------------------------------------------- CG updates
+__global__ void k_cg_update1(double* x, double* r, const double* p, const double* q,
+                             const double* slots, int64_t N, double* partials) {
+  const double alpha = slots[S_ALPHA];
+  double acc = 0.0;
+  GRID_STRIDE(i, N) {
+    x[i] += alpha * p[i];
+    double rv = r[i] - alpha * q[i];
+    r[i] = rv;
+    acc += rv * rv;
+  }
+  double s = block_sum256(acc, threadIdx.x);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+void launch_cg_update1(double* x, double* r, const double* p, const double* q, const double* slots,
+                       int64_t N, double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_update1, dim3(kReduceBlocks), dim3(kBlock), 0, s, x, r, p, q, slots, N,
+                     partials);
+}
+
+__global__ void k_cg_update2(double* p, const double* r, const double* slots, int64_t N) {
+  const double beta = slots[S_BETA];
+  GRID_STRIDE(i, N) p[i] = r[i] + beta * p[i];
+}
+
+void launch_cg_update2(double* p, const double* r, const double* slots, int64_t N, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_update2, dim3(grid_for(N)), dim3(kBlock), 0, s, p, r, slots, N);
+}
+
+__global__ void k_axpy_slot(double* y, const double* x, const double* slots, int slot,
+                            double sign, int64_t N) {
+  const double a = sign * slots[slot];
+  GRID_STRIDE(i, N) y[i] += a * x[i];
+}
+
+void launch_axpy_slot(double* y, const double* x, const double* slots, int slot, double sign,
+                      int64_t N, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_slot, dim3(grid_for(N)), dim3(kBlock), 0, s, y, x, slots, slot, sign, N);
+}
+
+__global__ void k_axpy(double* y, const double* x, double a, int64_t N) {
+  GRID_STRIDE(i, N) y[i] += a * x[i];
+}
+
+void launch_axpy(double* y, const double* x, double a, int64_t N, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy, dim3(grid_for(N)), dim3(kBlock), 0, s, y, x, a, N);
+}
+
+__global__ void k_scale_copy(double* y, const double* x, const double* slots, int slot, int64_t N) {
+  const double inv = 1.0 / sqrt(slots[slot]);
+  GRID_STRIDE(i, N) y[i] = x[i] * inv;
+}
+
+void launch_scale_copy(double* y, const double* x, const double* slots, int slot, int64_t N,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(N)), dim3(kBlock), 0, s, y, x, slots, slot, N);
+}
+
+__global__ void k_sub(double* y, const double* a, const double* b, int64_t N) {
+  GRID_STRIDE(i, N) y[i] = a[i] - b[i];
+}
+
+void launch_sub(double* y, const double* a, const double* b, int64_t N, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub, dim3(grid_for(N)), dim3(kBlock), 0, s, y, a, b, N);
+}
+
+__global__ void k_copy(double* y, const double* x, int64_t N) {
+  GRID_STRIDE(i, N) y[i] = x[i];
+}
+
+void launch_copy(double* y, const double* x, int64_t N, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy, dim3(grid_for(N)), dim3(kBlock), 0, s, y, x, N);
+}
+
+// Modified Gram-Schmidt step: w -= h v (h = slots[hslot]); partial sums of w . vnext.
+__global__ void k_axpy_dot(double* w, const double* v, const double* slots, int hslot,
+                           const double* vnext, int64_t N, double* partials) {
+  const double h = v ? slots[hslot] : 0.0;
+  double acc = 0.0;
+  GRID_STRIDE(i, N) {
+    double wv = w[i];
+    if (v) {
+      wv -= h * v[i];
+      w[i] = wv;
+    }
+    acc += vnext ? wv * vnext[i] : wv * wv;
+  }
+  double s = block_sum256(acc, threadIdx.x);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+void launch_axpy_dot(double* w, const double* v, const double* slots, int hslot,
+                     const double* vnext, int64_t N, double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_dot, dim3(kReduceBlocks), dim3(kBlock), 0, s, w, v, slots, hslot, vnext,
+                     N, partials);
+}
+
+// x += sum_{c<k} y[c] V[:, c]
+__global__ void k_gemv_acc(double* x, const double* V, int64_t ldv, int k, const double* y,
+                           int64_t N) {
+  GRID_STRIDE(i, N) {
+    double acc = 0.0;
+    for (int c = 0; c < k; ++c) acc += y[c] * V[(int64_t)c * ldv + i];
+    x[i] += acc;
+  }
+}
+
+void launch_gemv_acc(double* x, const double* V, int64_t ldv, int k, const double* y, int64_t N,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_gemv_acc, dim3(grid_for(N)), dim3(kBlock), 0, s, x, V, ldv, k, y, N);
+}
+
+// ----------------------------------------------------------------- Helmholtz residual
+__global__ void k_helm_res(const double* c2, const double* f, const double* u, double om2,
+                           double ih2, int n, int dim, double* pr, double* pf) {
+  const int64_t P = n + 1;
+  const int64_t N = dim == 2 ? P * P : P * P * P;
+  double ar = 0.0, af = 0.0;
+  GRID_STRIDE(p, N) {
+    int i = (int)(p % P), j = (int)((p / P) % P), k = dim == 3 ? (int)(p / (P * P)) : 1;
+    bool in = i > 0 && i < n && j > 0 && j < n && (dim == 2 || (k > 0 && k < n));
+    if (!in) continue;
+    auto U = [&](int64_t q, bool inside) { return inside ? u[q] : 0.0; };
+    const double uc = u[p];
+    int64_t nb[6] = {p - 1, p + 1, p - P, p + P, p - P * P, p + P * P};
+    bool ins[6] = {i > 1, i < n - 1, j > 1, j < n - 1, k > 1, k < n - 1};
+    double lap = 0.0;
+    for (int t = 0; t < 2 * dim; ++t) {
+      double cf = c2 ? 0.5 * (c2[p] + c2[nb[t]]) : 1.0;
+      lap += cf * (U(nb[t], ins[t]) - uc);
+    }
+    double r = f[p] - (lap * ih2 + om2 * uc);
+    ar += r * r;
+    af += f[p] * f[p];
+  }
+  double sr = block_sum256(ar, threadIdx.x);
+  double sf = block_sum256(af, threadIdx.x);
+  if (threadIdx.x == 0) {
+    pr[blockIdx.x] = sr;
+    pf[blockIdx.x] = sf;
+  }
+}
+
+int helmholtz_partial_blocks(int, int) { return kReduceBlocks; }
+
+void launch_helmholtz_residual(const double* c2, const double* f, const double* u, double om2,
+                               double ih2, int n, int dim, double* pr, double* pf, hipStream_t s) {
+  hipLaunchKernelGGL(k_helm_res, dim3(kReduceBlocks), dim3(kBlock), 0, s, c2, f, u, om2, ih2, n, dim,
+                     pr, pf);
+}
+
+// ----------------------------------------------------------------- deflation
+// Analytic sine modes: tab[(k*dim + axis)*(n+1) + i] = sqrt(2/n) sin(pi m_{k,axis} i / n).
+__global__ void k_sine_tables(double* tab, const int32_t* modes, int nd, int dim, int n) {
+  const int P = n + 1;
+  const int total = nd * dim * P;
+  const double nrm = sqrt(2.0 / n);
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
+    int i = t % P;
+    int ka = t / P;  // k*dim + axis
+    long m = modes[ka];
+    long r = (m * (long)i) % (2L * n);
+    tab[t] = nrm * sinpi((double)r / (double)n);
+  }
+}
+
+void launch_sine_tables(double* tab, const int32_t* modes_dev, int nd, int dim, int n,
+                        hipStream_t s) {
+  int total = nd * dim * (n + 1);
+  hipLaunchKernelGGL(k_sine_tables, dim3((total + 255) / 256), dim3(256), 0, s, tab, modes_dev, nd,
+                     dim, n);
+}
+
+constexpr int kDChunk = 16;   // modes per register pass
+constexpr int kRowsPerBlock = 16;
+
+// Multi-value block sum: vals[c] summed over the 256 threads, written by thread c.
+template <int C>
+__device__ __forceinline__ void block_sum_multi(double (&vals)[C], double* out, int tid) {
+  __shared__ double sm[4][C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    double v = wave_sum(vals[c]);
+    if ((tid & 63) == 0) sm[tid >> 6][c] = v;
+  }
+  __syncthreads();
+  if (tid < C) out[tid] = (sm[0][tid] + sm[1][tid]) + (sm[2][tid] + sm[3][tid]);
+  __syncthreads();
+}
+
+// Sine modes: rows of length P (the x axis); each row has factor prod_{axis>=1} tab.
+// Grid: x = column chunks of 256, y = row bands of kRowsPerBlock.  Partials layout
+// [block][nd].
+__global__ __launch_bounds__(256) void k_sine_project(const double* tab, int nd, int dim, int n,
+                                                      const double* r, double* partials) {
+  const int P = n + 1;
+  const int64_t rows = dim == 2 ? (int64_t)P : (int64_t)P * P;
+  const int tid = threadIdx.x;
+  const int i = blockIdx.x * 256 + tid;
+  const int64_t r0 = (int64_t)blockIdx.y * kRowsPerBlock;
+  const int64_t r1 = min(r0 + kRowsPerBlock, rows);
+  const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+  for (int k0 = 0; k0 < nd; k0 += kDChunk) {
+    double sx[kDChunk], acc[kDChunk];
+#pragma unroll
+    for (int c = 0; c < kDChunk; ++c) {
+      int k = k0 + c;
+      sx[c] = (i < P && k < nd) ? tab[(int64_t)(k * dim) * P + i] : 0.0;
+      acc[c] = 0.0;
+    }
+    for (int64_t rr = r0; rr < r1; ++rr) {
+      const int j = (int)(rr % P);
+      const int kz = (int)(rr / P);
+      const double rv = i < P ? r[rr * P + i] : 0.0;
+#pragma unroll
+      for (int c = 0; c < kDChunk; ++c) {
+        int k = k0 + c;
+        if (k < nd) {
+          double fac = tab[(int64_t)(k * dim + 1) * P + j];
+          if (dim == 3) fac *= tab[(int64_t)(k * dim + 2) * P + kz];
+          acc[c] += (rv * fac) * sx[c];
+        }
+      }
+    }
+    double outv[kDChunk];
+    __shared__ double red[kDChunk];
+    block_sum_multi<kDChunk>(acc, red, tid);
+    if (tid < kDChunk && k0 + tid < nd) partials[(int64_t)blk * nd + k0 + tid] = red[tid];
+    (void)outv;
+    __syncthreads();
+  }
+}
+
+// Dense columns: grid-stride over rows; partials [block][nd].
+__global__ __launch_bounds__(256) void k_dense_project(const double* V, int64_t ldv, int nd,
+                                                       int64_t N, const double* r,
+                                                       double* partials) {
+  const int tid = threadIdx.x;
+  for (int k0 = 0; k0 < nd; k0 += kDChunk) {
+    double acc[kDChunk];
+#pragma unroll
+    for (int c = 0; c < kDChunk; ++c) acc[c] = 0.0;
+    GRID_STRIDE(p, N) {
+      const double rv = r[p];
+#pragma unroll
+      for (int c = 0; c < kDChunk; ++c)
+        if (k0 + c < nd) acc[c] += V[(int64_t)(k0 + c) * ldv + p] * rv;
+    }
+    __shared__ double red[kDChunk];
+    block_sum_multi<kDChunk>(acc, red, tid);
+    if (tid < kDChunk && k0 + tid < nd) partials[(int64_t)blockIdx.x * nd + k0 + tid] = red[tid];
+    __syncthreads();
+  }
+}
+
+static dim3 sine_grid(const Defl& d) {
+  int P = d.n + 1;
+  int64_t rows = d.dim == 2 ? (int64_t)P : (int64_t)P * P;
+  return dim3((P + 255) / 256, (unsigned)((rows + kRowsPerBlock - 1) / kRowsPerBlock));
+}
+
+int defl_partial_blocks(const Defl& d) {
+  if (d.kind == WH_DEFL_SINE) {
+    dim3 g = sine_grid(d);
+    return (int)(g.x * g.y);
+  }
+  return kReduceBlocks;
+}
+
+void launch_defl_project(const Defl& d, const double* r, double* partials, hipStream_t s) {
+  if (d.kind == WH_DEFL_SINE) {
+    hipLaunchKernelGGL(k_sine_project, sine_grid(d), dim3(256), 0, s, d.tab, d.nd, d.dim, d.n, r,
+                       partials);
+  } else {
+    int64_t P = d.n + 1, N = d.dim == 2 ? P * P : P * P * P;
+    hipLaunchKernelGGL(k_dense_project, dim3(kReduceBlocks), dim3(256), 0, s, d.V, d.ldv, d.nd, N, r,
+                       partials);
+  }
+}
+
+__global__ void k_defl_reduce(const double* partials, int count, int nd, double* slots, int dst,
+                              const double* scale) {
+  for (int k = threadIdx.x; k < nd; k += blockDim.x) {
+    double acc = 0.0;
+    for (int b = 0; b < count; ++b) acc += partials[(int64_t)b * nd + k];
+    slots[dst + k] = scale ? acc * scale[k] : acc;
+  }
+}
+
+void launch_defl_reduce(const double* partials, int count, int nd, double* slots, int dst,
+                        const double* scale_dev, hipStream_t s) {
+  hipLaunchKernelGGL(k_defl_reduce, dim3(1), dim3(256), 0, s, partials, count, nd, slots, dst,
+                     scale_dev);
+}
+
+// y = alpha*y + beta*r - sum_k c_k W_k ; alpha taken from slots[aslot] if aslot >= 0
+__global__ __launch_bounds__(256) void k_sine_combine(const double* tab, int nd, int dim, int n,
+                                                      double* y, double alpha, int aslot,
+                                                      const double* r, double beta,
+                                                      const double* slots, int src) {
+  const int P = n + 1;
+  const int64_t rows = dim == 2 ? (int64_t)P : (int64_t)P * P;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.y * kRowsPerBlock;
+  const int64_t r1 = min(r0 + kRowsPerBlock, rows);
+  if (i >= P) return;
+  const double al = aslot >= 0 ? slots[aslot] : alpha;
+  for (int64_t rr = r0; rr < r1; ++rr) {
+    const int j = (int)(rr % P);
+    const int kz = (int)(rr / P);
+    double s = 0.0;
+    for (int k = 0; k < nd; ++k) {
+      double fac = tab[(int64_t)(k * dim + 1) * P + j];
+      if (dim == 3) fac *= tab[(int64_t)(k * dim + 2) * P + kz];
+      s += slots[src + k] * fac * tab[(int64_t)(k * dim) * P + i];
+    }
+    const int64_t p = rr * P + i;
+    double v = (al == 0.0 ? 0.0 : al * y[p]) - s;
+    if (r) v += beta * r[p];
+    y[p] = v;
+  }
+}
+
+__global__ void k_dense_combine(const double* V, int64_t ldv, int nd, int64_t N, double* y,
+                                double alpha, int aslot, const double* r, double beta,
+                                const double* slots, int src) {
+  const double al = aslot >= 0 ? slots[aslot] : alpha;
+  GRID_STRIDE(p, N) {
+    double s = 0.0;
+    for (int k = 0; k < nd; ++k) s += slots[src + k] * V[(int64_t)k * ldv + p];
+    double v = (al == 0.0 ? 0.0 : al * y[p]) - s;
+    if (r) v += beta * r[p];
+    y[p] = v;
+  }
+}
+
+static void combine_impl(const Defl& d, double* y, double alpha, int aslot, const double* r,
+                         double beta, const double* slots, int src, int64_t N, hipStream_t s) {
+  if (d.kind == WH_DEFL_SINE)
+    hipLaunchKernelGGL(k_sine_combine, sine_grid(d), dim3(256), 0, s, d.tab, d.nd, d.dim, d.n, y,
+                       alpha, aslot, r, beta, slots, src);
+  else
+    hipLaunchKernelGGL(k_dense_combine, dim3(grid_for(N)), dim3(256), 0, s, d.V, d.ldv, d.nd, N, y,
+                       alpha, aslot, r, beta, slots, src);
+}
+
+void launch_defl_combine(const Defl& d, double* y, double alpha, const double* r, double beta,
+                         const double* slots, int src, int64_t N, hipStream_t s) {
+  combine_impl(d, y, alpha, -1, r, beta, slots, src, N, s);
+}
+
+void launch_dcg_update2(const Defl& d, double* p, const double* r, const double* slots, int src,
+                        int64_t N, hipStream_t s) {
+  combine_impl(d, p, 0.0, S_BETA, r, 1.0, slots, src, N, s);
+}
+
+}  // namespace wh

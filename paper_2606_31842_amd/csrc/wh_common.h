@@ -1,0 +1,140 @@
+// Internal declarations shared by the libwaveholtz translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/waveholtz.h"
+
+namespace wh {
+
+// ----------------------------------------------------------------- device scalars
+// Slots of the per-solve FP64 scalar block in the workspace.
+enum Slot : int {
+  S_R2 = 0,      // r^T r of the current residual
+  S_PQ = 1,      // p^T A p
+  S_ALPHA = 2,   // CG step length
+  S_BETA = 3,    // CG direction update
+  S_TMP = 4,     // scratch reduction target
+  S_NB = 5,      // ||b||^2
+  S_TMP2 = 6,
+  S_NSLOTS_FIXED = 8,
+  S_H = 8        // GMRES: Hessenberg column h_{0..m}, then deflation coefficients
+};
+
+constexpr int kBlock = 256;          // threads per block for 1D kernels
+constexpr int kReduceBlocks = 1024;  // partial-sum slots for grid-stride 1D reductions
+
+// ----------------------------------------------------------------- stencil launch
+enum StepMode : int {
+  M_FIRST = 0,   // W^1 from W^0 = v (D_0t W^0 = 0), V = w0 W^0 + w1 W^1, writes both states
+  M_MID = 1,     // W^{n+1} = 2W^n - W^{n-1} + ...,  V += w W^{n+1}
+  M_LAST_V = 2,  // last step, V += w W^{N_t}, state not stored
+  M_LAST_AQ = 3, // last step, q = x - (V + w W^{N_t}); partial sums of x.q
+  M_LAST_FPI = 4 // last step, out = V + w W^{N_t}; partial sums of (out - x)^2
+};
+
+struct StepArgs {
+  const void* cur;        // W^n (state type)
+  void* prev;             // in: W^{n-1}; out: W^{n+1}  (M_FIRST: out W^0)
+  void* cur_out;          // M_FIRST: out W^1
+  const double* vin;      // M_FIRST: W^0 in FP64 (nodal; boundary read as 0)
+  double* V;              // filter accumulator (FP64 nodal)
+  const void* kap;        // variable c: c2 dt^2 / (2 h^2) nodal (state type)
+  const void* fs;         // forcing: f dt^2 nodal, zero boundary (state type)
+  double a;               // constant c: dt^2 / h^2
+  double cosn;            // cos(omega_w t^n) for the forcing at step n
+  double w0;              // M_FIRST: w_0
+  double wn;              // weight of the new state (w_{n+1})
+  const double* x;        // M_LAST_AQ / M_LAST_FPI: the vector being filtered
+  double* out;            // M_LAST_AQ: q ; M_LAST_FPI: Pi x
+  double* partials;       // per-block partial sums
+  int n;
+};
+
+// Launch one time step of a d-dimensional wave solve. T: float or double.
+// Returns the number of blocks that wrote partial sums.
+int launch_step(int dim, bool f32, bool varc, bool force, StepMode mode, const StepArgs& a,
+                hipStream_t s);
+int step_partial_blocks(int dim, int n);
+
+// Fused k-step 2D launch (temporal blocking).  Advances (cur, prev) by k steps and
+// accumulates sum_{j=1..k} w[j-1] W^{n+j} into V.  Returns false if unsupported.
+struct FusedArgs {
+  const void* cur;   // W^n
+  const void* prev;  // W^{n-1}
+  void* cur_out;     // W^{n+k}
+  void* prev_out;    // W^{n+k-1}
+  double* V;
+  const void* kap;
+  const void* fs;
+  double a;
+  const double* wts;     // device: w_{n+1..n+k}
+  const double* cosv;    // device: cos(omega_w t^{n..n+k-1})
+  int n;
+  int k;
+};
+bool fused2d_supported(bool f32, int k);
+void launch_fused2d(bool f32, bool varc, bool force, const FusedArgs& a, hipStream_t s);
+
+// ----------------------------------------------------------------- BLAS-like kernels
+void launch_prep_coeffs(const double* c2, const double* f, void* kap, void* fs, bool f32,
+                        double kap_scale, double f_scale, int64_t N, int n, int dim,
+                        hipStream_t s);
+void launch_zero_boundary(double* u, int n, int dim, hipStream_t s);
+void launch_max_partials(const double* a, int64_t N, double* partials, bool neg, hipStream_t s);
+void launch_max_finalize(const double* partials, int count, double* out, hipStream_t s);
+void launch_dot_partials(const double* a, const double* b, int64_t N, double* partials,
+                         hipStream_t s);
+// slot[dst] = sum(partials[0..count)); mode 0 plain, 1: alpha = slot[R2]/sum (sum -> PQ),
+// 2: beta = sum/slot[R2], slot[R2] = sum
+void launch_reduce(const double* partials, int count, double* slots, int dst, int mode,
+                   hipStream_t s);
+void launch_cg_update1(double* x, double* r, const double* p, const double* q,
+                       const double* slots, int64_t N, double* partials, hipStream_t s);
+void launch_cg_update2(double* p, const double* r, const double* slots, int64_t N,
+                       hipStream_t s);
+void launch_axpy_slot(double* y, const double* x, const double* slots, int slot, double sign,
+                      int64_t N, hipStream_t s);
+void launch_axpy(double* y, const double* x, double alpha, int64_t N, hipStream_t s);
+void launch_scale_copy(double* y, const double* x, const double* slots, int slot, int64_t N,
+                       hipStream_t s);  // y = x / sqrt(slot)
+void launch_sub(double* y, const double* a, const double* b, int64_t N, hipStream_t s);  // y=a-b
+void launch_copy(double* y, const double* x, int64_t N, hipStream_t s);
+void launch_axpy_dot(double* w, const double* v, const double* slots, int hslot,
+                     const double* vnext, int64_t N, double* partials, hipStream_t s);
+void launch_gemv_acc(double* x, const double* V, int64_t ldv, int k, const double* y_dev,
+                     int64_t N, hipStream_t s);  // x += V[:, :k] y
+void launch_helmholtz_residual(const double* c2, const double* f, const double* u, double omega2,
+                               double inv_h2, int n, int dim, double* partials_r,
+                               double* partials_f, hipStream_t s);
+int helmholtz_partial_blocks(int n, int dim);
+
+// Deflation: W^T r into slots[dst..dst+nd) and y -= W c (c from slots[src..]).
+struct Defl {
+  int kind = WH_DEFL_NONE;
+  int nd = 0;
+  int dim = 2;
+  int n = 0;
+  const double* tab = nullptr;  // sine: nd x dim x (n+1) table, [k][axis][i]
+  const double* V = nullptr;    // dense
+  int64_t ldv = 0;
+};
+int defl_partial_blocks(const Defl& d);
+void launch_defl_project(const Defl& d, const double* r, double* partials, hipStream_t s);
+// reduce nd columns of partials (count rows) into slots[dst + k]; scale by scale_dev[k] if set
+void launch_defl_reduce(const double* partials, int count, int nd, double* slots, int dst,
+                        const double* scale_dev, hipStream_t s);
+// y = alpha*y + beta*r - sum_k slots[src+k] W_k     (r may be null)
+void launch_defl_combine(const Defl& d, double* y, double alpha, const double* r, double beta,
+                         const double* slots, int src, int64_t N, hipStream_t s);
+// p = beta_slot * p + r - W c  for CG with deflation
+void launch_dcg_update2(const Defl& d, double* p, const double* r, const double* slots, int src,
+                        int64_t N, hipStream_t s);
+void launch_sine_tables(double* tab, const int32_t* modes_dev, int nd, int dim, int n,
+                        hipStream_t s);
+
+}  // namespace wh

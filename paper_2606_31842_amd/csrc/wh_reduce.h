@@ -1,0 +1,44 @@
+// Deterministic FP64 block reductions for 256-thread blocks (four 64-wide waves).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace wh {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  return v;
+}
+
+// Sum over the 256 threads of the block; the result is valid in thread 0.  Fixed
+// order (shuffle tree per wave, then waves 0..3 in order), so results are
+// reproducible run to run.  Every thread of the block must call it.
+__device__ __forceinline__ double block_sum256(double v, int tid) {
+  __shared__ double sm[4];
+  v = wave_sum(v);
+  if ((tid & 63) == 0) sm[tid >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (tid == 0) s = (sm[0] + sm[1]) + (sm[2] + sm[3]);
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ double block_max256(double v, int tid) {
+  __shared__ double sm[4];
+  v = wave_max(v);
+  if ((tid & 63) == 0) sm[tid >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (tid == 0) s = fmax(fmax(sm[0], sm[1]), fmax(sm[2], sm[3]));
+  __syncthreads();
+  return s;
+}
+
+}  // namespace wh

@@ -1,0 +1,103 @@
+"""CPU checks of the C-ABI library: it loads, exports every entry point the header
+declares, and its host-side helpers (time parameters, transfer function, mode
+selection) agree with the oracle.  No device computation runs here."""
+import ctypes as C
+import math
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "waveholtz.h")
+LIB = os.path.join(ROOT, "paper_2606_31842_amd", "libwaveholtz.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libwaveholtz.so not built")
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(wh_[a-z_0-9]+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = header_functions()
+    assert "wh_solve" in names and "wh_apply_filter" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT\s+(wh_[a-z_0-9]+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    from paper_2606_31842_amd import _native
+    lib = _native.load()
+    for n in names:
+        getattr(lib, n)
+    assert set(_native.exported_symbols()) == set(names)
+
+
+def test_param_struct_matches_header_defaults():
+    import paper_2606_31842_amd as wh
+    p = wh.params(3.0)
+    assert p.cfl == 0.5 and p.freq_correction == 1 and p.restart == 40 and p.n_periods == 1
+
+
+@pytest.mark.parametrize("omega,n,c_max,fc", [(20.5, 64, 1.0, 1), (100.3, 1024, 1.0, 1), (30.0, 512, math.sqrt(1.2), 1),
+                                              (12.0, 40, 1.3, 0)])
+def test_time_params_match_oracle(omega, n, c_max, fc):
+    import paper_2606_31842_amd as wh
+    from oracle import timeparams as tpm
+    got = wh.time_params(2, n, omega, c_max=c_max, freq_correction=fc)
+    tp = tpm.time_parameters(omega, 1 / n, c_max, freq_correction=bool(fc))
+    assert got["m"] == tp.m and got["nt"] == tp.nt
+    assert abs(got["dt"] - tp.dt) < 1e-15 * tp.dt * 10
+    assert abs(got["omega_tilde"] - tp.omega_w) < 1e-12 * omega
+
+
+def test_transfer_matches_oracle():
+    import paper_2606_31842_amd as wh
+    from oracle import timeparams as tpm, transfer as tr
+    lam2 = np.linspace(0, 8 * 64 ** 2, 257)
+    for Np in (1, 2):
+        got = wh.transfer(2, 64, 20.5, lam2, n_periods=Np)
+        tp = tpm.time_parameters(20.5, 1 / 64, 1.0, n_periods=Np)
+        assert np.abs(got - tr.beta_discrete(lam2, tp)).max() < 1e-12
+
+
+@pytest.mark.parametrize("dim,n,omega,nd", [(2, 1024, 100.3, 32), (2, 64, 20.5, 7), (3, 16, 12.0, 9)])
+def test_mode_selection_matches_oracle(dim, n, omega, nd):
+    import paper_2606_31842_amd as wh
+    from oracle import modes
+    got, lam2 = wh.select_sine_modes(dim, n, omega, nd)
+    ref, ref_l2 = modes.select_modes(dim, n, omega, nd)
+    assert [tuple(r) for r in got.tolist()] == ref
+    assert np.allclose(lam2, ref_l2, rtol=1e-13)
+
+
+def test_invalid_arguments_rejected_on_host():
+    import paper_2606_31842_amd as wh
+    from paper_2606_31842_amd import _native as nat
+    lib = nat.load()
+    g = nat.WhGrid(2, 64, 2)
+    p = wh.params(10.0)
+    m = C.c_int32()
+    # cfl beyond the stability bound
+    p.cfl = 0.75
+    assert lib.wh_time_params(C.byref(g), C.byref(p), 1.0, C.byref(m), None, None, None) == nat.WH_EINVAL
+    p.cfl = 0.5
+    g4 = nat.WhGrid(4, 64, 2)
+    assert lib.wh_time_params(C.byref(g4), C.byref(p), 1.0, C.byref(m), None, None, None) == nat.WH_EUNSUPPORTED
+    go = nat.WhGrid(2, 64, 4)
+    assert lib.wh_time_params(C.byref(go), C.byref(p), 1.0, C.byref(m), None, None, None) == nat.WH_EUNSUPPORTED
+    p.omega = -1.0
+    assert lib.wh_time_params(C.byref(g), C.byref(p), 1.0, C.byref(m), None, None, None) == nat.WH_EINVAL
+    assert lib.wh_select_sine_modes(4, 10, 1.0, 1, None, None) == nat.WH_EINVAL
+    # a NULL context is rejected before any device call
+    assert lib.wh_solve(None, C.byref(g), None, None, None, C.byref(p), None, None, 0, None) == nat.WH_EINVAL
+    # workspace size grows with deflation and GMRES restart
+    p.omega = 10.0
+    b0 = lib.wh_workspace_bytes(C.byref(g), C.byref(p), None)
+    p.solver = nat.WH_GMRES
+    b1 = lib.wh_workspace_bytes(C.byref(g), C.byref(p), None)
+    assert b1 > b0 > 0

@@ -166,3 +166,11 @@ def test_mixed_precision_error_size():
     v = disc.to_interior(wl.random_nodal(2, 64, 1))
     e = np.linalg.norm(ws.apply_S(L, v, tp, state_dtype=np.float32) - ws.apply_S(L, v, tp)) / np.linalg.norm(v)
     assert 1e-9 < e < 1e-5
+
+
+@pytest.mark.parametrize("dim,n,omega", [(2, 40, 17.3), (3, 9, 6.2)])
+def test_dst_direct_solve_matches_sparse_lu(dim, n, omega):
+    f = wl.gaussian(dim, n, (0.3, 0.6, 0.5)[:dim], 0.1)
+    L = disc.laplacian(dim, n)
+    U = disc.to_nodal(disc.direct_solve(L, omega, disc.to_interior(f)), dim, n)
+    assert np.abs(disc.direct_solve_dst(dim, n, omega, f) - U).max() < 1e-12 * np.abs(U).max()
