@@ -93,8 +93,9 @@ typedef struct {
   double inner_tol;         /* WH_MIXED: relative tolerance of each FP32 inner solve (1e-3)  */
   int32_t max_outer;        /* WH_MIXED: FP64 refinement sweeps (default 30)                 */
   int32_t k_fuse;           /* time steps per stencil launch; 0: library choice             */
-  int32_t reproject;        /* DCG A-orthogonalisation against W each iteration:
-                               -1 auto (on unless F64 with exact eigenvectors), 0 off, 1 on  */
+  int32_t reproject;        /* DCG A-orthogonalisation against W each iteration (Algorithm 3,
+                               optional for exact eigenvectors): -1 auto (= off, every
+                               deflation kind here is exact), 0 off, 1 on                  */
   int32_t check_every;      /* read the residual back every this many iterations (1)        */
 } wh_params;
 
@@ -183,6 +184,16 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
 wh_status wh_helmholtz_residual(wh_ctx* ctx, const wh_grid* grid, const double* c2,
                                 const double* f, double omega, const double* u,
                                 void* ws, size_t ws_bytes, double* rel);
+
+/* Measurement helper: the average duration in microseconds of one launch of the
+ * time-stepping kernel that wh_apply_filter / wh_solve would use for these
+ * arguments (the K-step temporally blocked kernel, or the single-step kernel when
+ * K = 1), with no forcing.  `reps` launches run back to back on the context stream
+ * between two HIP events; *k_used receives K.  The state arrays in the workspace
+ * are zeroed first and overwritten; nothing else is touched. */
+wh_status wh_time_step_kernel(wh_ctx* ctx, const wh_grid* grid, const double* c2,
+                              const wh_params* params, int32_t reps, void* ws, size_t ws_bytes,
+                              double* us_per_launch, int32_t* k_used);
 
 #ifdef __cplusplus
 }

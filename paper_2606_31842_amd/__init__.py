@@ -239,3 +239,21 @@ def helmholtz_residual(u, f, omega, c2=None):
                                    ws.numel(), C.byref(rel))
     _check(lib, ctx, st)
     return rel.value
+
+
+def time_step_kernel(v, omega, c2=None, reps=50, **kw):
+    """Average milliseconds per launch of the time-stepping kernel the library picks
+    for this grid (see wh_time_step_kernel)."""
+    dim = v.dim()
+    n = v.shape[0] - 1
+    lib = nat.load()
+    ctx = context(v.device.index)
+    p = params(omega, **kw)
+    g = _grid(dim, n)
+    ws = _workspace(lib.wh_workspace_bytes(C.byref(g), C.byref(p), None))
+    us = C.c_double()
+    k = C.c_int32()
+    st = lib.wh_time_step_kernel(ctx, C.byref(g), _ptr(c2), C.byref(p), int(reps), _ptr(ws), ws.numel(),
+                                 C.byref(us), C.byref(k))
+    _check(lib, ctx, st)
+    return us.value / 1e3

@@ -77,7 +77,10 @@ _SIGS = {
 }
 
 # entry points added as they are built (declared in include/waveholtz.h)
-_OPTIONAL = {}
+_OPTIONAL = {
+    "wh_time_step_kernel": (C.c_int, [C.c_void_p, P(WhGrid), C.c_void_p, P(WhParams), C.c_int32, C.c_void_p,
+                                      C.c_size_t, P(C.c_double), P(C.c_int32)]),
+}
 
 _lib = None
 

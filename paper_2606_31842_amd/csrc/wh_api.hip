@@ -5,6 +5,8 @@
 // host decision is needed (convergence tests, Givens rotations).
 #include <algorithm>
 #include <chrono>
+#include <map>
+#include <tuple>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -21,6 +23,7 @@ struct wh_ctx {
   std::string err;
   double* hbuf = nullptr;  // pinned host scalars
   int hbuf_len = 0;
+  std::map<std::tuple<int, int, int, int, int>, int> ktune;  // (dim, n, f32, varc, force) -> K
 };
 
 namespace {
@@ -117,7 +120,7 @@ double transfer(const TimeParams& tp, double lam2) {
 // ----------------------------------------------------------------- workspace layout
 struct Layout {
   size_t total = 0;
-  size_t Wa = 0, Wb = 0, V = 0, kap64 = 0, fs64 = 0, kap32 = 0, fs32 = 0;
+  size_t Wa = 0, Wb = 0, Wc = 0, Wd = 0, V = 0, kap64 = 0, fs64 = 0, kap32 = 0, fs32 = 0;
   size_t b = 0, r = 0, p = 0, q = 0, ro = 0, d = 0, basis = 0;
   size_t partials = 0, partials2 = 0, slots = 0, tab = 0, modes = 0, invmu = 0, ones = 0;
   int64_t N = 0;
@@ -146,6 +149,8 @@ Layout make_layout(const wh_grid& g, const wh_params& P, const wh_deflation* def
   const int restart = std::max(1, P.restart);
   L.Wa = take(L, 8 * N);
   L.Wb = take(L, 8 * N);
+  L.Wc = take(L, 8 * N);
+  L.Wd = take(L, 8 * N);
   L.V = take(L, 8 * N);
   L.kap64 = take(L, 8 * N);
   L.fs64 = take(L, 8 * N);
@@ -266,6 +271,8 @@ struct WaveOp {
   bool varc = false, f32 = false;
   void* Wa = nullptr;
   void* Wb = nullptr;
+  void* Wc = nullptr;   // second state pair for the temporally blocked kernel
+  void* Wd = nullptr;
   double* V = nullptr;
   const void* kap = nullptr;
   const void* fs = nullptr;
@@ -293,11 +300,45 @@ int wave_solve(const WaveOp& op, const double* vin, bool force, StepMode last, c
   a.w0 = tp.w[0];
   a.wn = tp.w[1];
   a.cosn = tp.cosv[0];
+  a.zb0 = op.Wc;
+  a.zb1 = op.Wd;
   launch_step(op.dim, op.f32, op.varc, force, M_FIRST, a, s);
+  a.zb0 = a.zb1 = nullptr;
   void* cur = op.Wb;
   void* prev = op.Wa;
+  void* oc = op.Wc;
+  void* op_ = op.Wd;
+  int nn = 1;  // cur holds W^nn
+  const int K = op.k_fuse;
+  if (K > 1 && op.dim == 2 && fused2d_supported(op.f32, K)) {
+    FusedArgs fa{};
+    fa.V = op.V;
+    fa.kap = op.kap;
+    fa.fs = force ? op.fs : nullptr;
+    fa.a = op.a;
+    fa.n = op.n;
+    fa.k = K;
+    // the last step stays with the streaming kernel (it carries the epilogue); the
+    // remainder is covered by the largest supported K that still fits
+    int Kc = K;
+    while (true) {
+      while (Kc > 1 && (nn + Kc > tp.nt - 1 || !fused2d_supported(op.f32, Kc))) --Kc;
+      if (Kc <= 1) break;
+      fa.k = Kc;
+      fa.cur = cur;
+      fa.prev = prev;
+      fa.cur_out = oc;
+      fa.prev_out = op_;
+      fa.wts = &tp.w[nn + 1];
+      fa.cosv = &tp.cosv[nn];
+      launch_fused2d(op.f32, op.varc, force, fa, s);
+      std::swap(cur, oc);
+      std::swap(prev, op_);
+      nn += Kc;
+    }
+  }
   int nblk = 0;
-  for (int k = 1; k < tp.nt; ++k) {
+  for (int k = nn; k < tp.nt; ++k) {
     a.cur = cur;
     a.prev = prev;
     a.cosn = tp.cosv[k];
@@ -310,6 +351,77 @@ int wave_solve(const WaveOp& op, const double* vin, bool force, StepMode last, c
     std::swap(cur, prev);
   }
   return nblk;
+}
+
+// ----------------------------------------------------------------- autotuner
+// Steps per launch for the temporally blocked 2D kernel: time each supported K on
+// this grid (after one warm-up launch) and keep the fastest per-step time.  The
+// state buffers and V serve as scratch; every caller initialises them afterwards.
+int autotune_k(wh_ctx* ctx, const WaveOp& op, bool force) {
+  if (op.dim != 2) return 1;
+  const auto key = std::make_tuple(op.dim, op.n, (int)op.f32, (int)op.varc, (int)force);
+  auto it = ctx->ktune.find(key);
+  if (it != ctx->ktune.end()) return it->second;
+  const TimeParams& tp = *op.tp;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return 4;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return 4;
+  }
+  int best = 1;
+  float best_t = 1e30f;
+  const int cands[] = {1, 2, 3, 4, 6, 8};
+  for (int K : cands) {
+    if (K > 1 && (!fused2d_supported(op.f32, K) || K + 2 > tp.nt)) continue;
+    auto run = [&]() {
+      if (K == 1) {
+        StepArgs a{};
+        a.n = op.n;
+        a.kap = op.kap;
+        a.fs = force ? op.fs : nullptr;
+        a.a = op.a;
+        a.cur = op.Wb;
+        a.prev = op.Wa;
+        a.V = op.V;
+        a.cosn = tp.cosv[1];
+        a.wn = tp.w[2];
+        launch_step(op.dim, op.f32, op.varc, force, M_MID, a, ctx->stream);
+      } else {
+        FusedArgs fa{};
+        fa.V = op.V;
+        fa.kap = op.kap;
+        fa.fs = force ? op.fs : nullptr;
+        fa.a = op.a;
+        fa.n = op.n;
+        fa.k = K;
+        fa.cur = op.Wb;
+        fa.prev = op.Wa;
+        fa.cur_out = op.Wc;
+        fa.prev_out = op.Wd;
+        fa.wts = &tp.w[2];
+        fa.cosv = &tp.cosv[1];
+        launch_fused2d(op.f32, op.varc, force, fa, ctx->stream);
+      }
+    };
+    run();
+    const int reps = 3;
+    (void)hipEventRecord(e0, ctx->stream);
+    for (int r = 0; r < reps; ++r) run();
+    (void)hipEventRecord(e1, ctx->stream);
+    if (hipEventSynchronize(e1) != hipSuccess) break;
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    const float per_step = ms / (reps * K);
+    if (per_step < best_t) {
+      best_t = per_step;
+      best = K;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->ktune[key] = best;
+  return best;
 }
 
 // ----------------------------------------------------------------- solver state
@@ -609,6 +721,9 @@ wh_status setup_ops(wh_ctx* ctx, const wh_grid& g, const wh_params& P, const dou
   base.varc = varc;
   base.Wa = at<void>(ws, L.Wa);
   base.Wb = at<void>(ws, L.Wb);
+  base.Wc = at<void>(ws, L.Wc);
+  base.Wd = at<void>(ws, L.Wd);
+  base.k_fuse = 1;
   base.V = at<double>(ws, L.V);
   base.a = dt2 / (h * h);
   base.tp = &tp;
@@ -623,17 +738,27 @@ wh_status setup_ops(wh_ctx* ctx, const wh_grid& g, const wh_params& P, const dou
     S.op32.kap = at<void>(ws, L.kap32);
     S.op32.fs = at<void>(ws, L.fs32);
   }
+  // steps per launch: fixed by the caller, else autotuned (cached per context).  The
+  // operator without forcing dominates every solve, so it sets K for both precisions.
+  auto pick = [&](WaveOp& op) {
+    if (g.dim != 2) return 1;
+    if (P.k_fuse > 0) return (P.k_fuse == 1 || fused2d_supported(op.f32, P.k_fuse)) ? P.k_fuse : 1;
+    return autotune_k(ctx, op, false);
+  };
+  S.op64.k_fuse = pick(S.op64);
+  if (mixed) S.op32.k_fuse = pick(S.op32);
+  HIPCHK(ctx, hipGetLastError());
   return WH_OK;
 }
 
-void fill_info(wh_info* info, const TimeParams& tp) {
+void fill_info(wh_info* info, const TimeParams& tp, int k_fuse) {
   if (!info) return;
   info->nt = tp.nt;
   info->m = tp.m;
   info->dt = tp.dt;
   info->omega_tilde = tp.omega_w;
   info->c_max = tp.c_max;
-  info->k_fuse = 1;
+  info->k_fuse = k_fuse;
 }
 
 }  // namespace
@@ -801,7 +926,7 @@ wh_status wh_apply_filter(wh_ctx* ctx, const wh_grid* grid, const double* c2, co
   HIPCHK(ctx, hipGetLastError());
   if (info) {
     std::memset(info, 0, sizeof(*info));
-    fill_info(info, tp);
+    fill_info(info, tp, params->precision == WH_MIXED ? S.op32.k_fuse : S.op64.k_fuse);
     info->wave_solves = params->precision == WH_MIXED ? 0 : 1;
     info->wave_solves_f32 = params->precision == WH_MIXED ? 1 : 0;
     info->ms = now_ms() - t0;
@@ -856,7 +981,9 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
     HIPCHK(ctx, hipMemsetAsync(at<double>(ws, L.d), 0, 8 * N, s));
   }
   // deflation set
-  bool reproject = P.reproject == 1 || (P.reproject < 0 && mixed);
+  // Algorithm 3 may skip the per-iteration A-orthogonalisation with exact eigenvectors;
+  // every deflation kind built here is exact (for the FP64 operator), so auto = off.
+  bool reproject = P.reproject == 1;
   if (nd) {
     S.defl.kind = defl->kind;
     S.defl.nd = nd;
@@ -898,7 +1025,6 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
     WHCHK(upload(ctx, at<double>(ws, L.ones), neg.data(), nd));
     S.invmu = at<double>(ws, L.invmu);
     S.negmu = at<double>(ws, L.ones);
-    if (defl->kind == WH_DEFL_DENSE_EXACT && P.reproject < 0) reproject = mixed;
   }
   // b = Pi_h(0; f) in FP64: one wave solve from zero, accumulated into b
   {
@@ -989,7 +1115,7 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
   HIPCHK(ctx, hipGetLastError());
   HIPCHK(ctx, hipStreamSynchronize(s));
   if (info) {
-    fill_info(info, tp);
+    fill_info(info, tp, params->precision == WH_MIXED ? S.op32.k_fuse : S.op64.k_fuse);
     info->status = st;
     info->iters = S.iters;
     info->wave_solves = S.ws64;
@@ -1022,6 +1148,71 @@ wh_status wh_helmholtz_residual(wh_ctx* ctx, const wh_grid* grid, const double* 
   HIPCHK(ctx, hipGetLastError());
   WHCHK(readback(ctx, out, 2));
   *rel = ctx->hbuf[1] > 0 ? std::sqrt(ctx->hbuf[0] / ctx->hbuf[1]) : 0.0;
+  return WH_OK;
+}
+
+wh_status wh_time_step_kernel(wh_ctx* ctx, const wh_grid* grid, const double* c2,
+                              const wh_params* params, int32_t reps, void* ws, size_t ws_bytes,
+                              double* us_per_launch, int32_t* k_used) {
+  if (!ctx) return WH_EINVAL;
+  WHCHK(check_grid(ctx, grid));
+  WHCHK(check_params(ctx, grid, params));
+  if (reps < 1 || !us_per_launch) WH_FAIL(ctx, WH_EINVAL, "reps must be >= 1 and us_per_launch set");
+  const Layout L = make_layout(*grid, *params, nullptr);
+  WHCHK(check_ws(ctx, ws, ws_bytes, L.total));
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  TimeParams tp;
+  Solver S{};
+  WHCHK(setup_ops(ctx, *grid, *params, c2, nullptr, ws, L, tp, S));
+  const WaveOp& op = params->precision == WH_MIXED ? S.op32 : S.op64;
+  for (size_t off : {L.Wa, L.Wb, L.Wc, L.Wd, L.V})
+    HIPCHK(ctx, hipMemsetAsync(at<void>(ws, off), 0, 8 * (size_t)L.N, s));
+  const int K = op.k_fuse;
+  if (K > 1 && K + 2 > tp.nt) WH_FAIL(ctx, WH_EINVAL, "K larger than the wave solve");
+  auto run = [&](int r) {
+    if (K <= 1) {
+      StepArgs a{};
+      a.n = op.n;
+      a.kap = op.kap;
+      a.a = op.a;
+      a.cur = (r & 1) ? op.Wa : op.Wb;
+      a.prev = (r & 1) ? op.Wb : op.Wa;
+      a.V = op.V;
+      a.cosn = tp.cosv[1];
+      a.wn = tp.w[2];
+      launch_step(op.dim, op.f32, op.varc, false, M_MID, a, s);
+    } else {
+      FusedArgs fa{};
+      fa.V = op.V;
+      fa.kap = op.kap;
+      fa.a = op.a;
+      fa.n = op.n;
+      fa.k = K;
+      fa.cur = (r & 1) ? op.Wc : op.Wb;
+      fa.prev = (r & 1) ? op.Wd : op.Wa;
+      fa.cur_out = (r & 1) ? op.Wb : op.Wc;
+      fa.prev_out = (r & 1) ? op.Wa : op.Wd;
+      fa.wts = &tp.w[1];
+      fa.cosv = &tp.cosv[1];
+      launch_fused2d(op.f32, op.varc, false, fa, s);
+    }
+  };
+  run(0);
+  hipEvent_t e0, e1;
+  HIPCHK(ctx, hipEventCreate(&e0));
+  HIPCHK(ctx, hipEventCreate(&e1));
+  (void)hipEventRecord(e0, s);
+  for (int r = 0; r < reps; ++r) run(r + 1);
+  (void)hipEventRecord(e1, s);
+  hipError_t e = hipEventSynchronize(e1);
+  float ms = 0;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) WH_FAIL(ctx, WH_EHIP, "event timing failed: %s", hipGetErrorString(e));
+  *us_per_launch = 1e3 * (double)ms / reps;
+  if (k_used) *k_used = K;
   return WH_OK;
 }
 

@@ -288,8 +288,8 @@ void launch_sine_tables(double* tab, const int32_t* modes_dev, int nd, int dim, 
                      dim, n);
 }
 
-constexpr int kDChunk = 16;   // modes per register pass
-constexpr int kRowsPerBlock = 16;
+constexpr int kDChunk = 32;   // modes per register pass
+constexpr int kRowsPerBlock = 8;
 
 // Multi-value block sum: vals[c] summed over the 256 threads, written by thread c.
 template <int C>
@@ -305,9 +305,11 @@ __device__ __forceinline__ void block_sum_multi(double (&vals)[C], double* out, 
   __syncthreads();
 }
 
-// Sine modes: rows of length P (the x axis); each row has factor prod_{axis>=1} tab.
-// Grid: x = column chunks of 256, y = row bands of kRowsPerBlock.  Partials layout
-// [block][nd].
+// Sine modes, W^T r.  Rows of length P run along x; a row's mode factor is
+// prod_{axis>=1} tab[k][axis][coord], uniform across the row.  Each thread owns one
+// column i for the whole band of kRowsPerBlock rows: it keeps sx_k(i) in registers,
+// issues all the row loads first, then accumulates.  Grid: x = column chunks of 256,
+// y = row bands.  Partials layout [block][nd].
 __global__ __launch_bounds__(256) void k_sine_project(const double* tab, int nd, int dim, int n,
                                                       const double* r, double* partials) {
   const int P = n + 1;
@@ -315,35 +317,36 @@ __global__ __launch_bounds__(256) void k_sine_project(const double* tab, int nd,
   const int tid = threadIdx.x;
   const int i = blockIdx.x * 256 + tid;
   const int64_t r0 = (int64_t)blockIdx.y * kRowsPerBlock;
-  const int64_t r1 = min(r0 + kRowsPerBlock, rows);
   const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+  const bool col_ok = i < P;
+  double rv[kRowsPerBlock];
+#pragma unroll
+  for (int t = 0; t < kRowsPerBlock; ++t) {
+    const int64_t rr = r0 + t;
+    rv[t] = (col_ok && rr < rows) ? r[rr * P + i] : 0.0;
+  }
   for (int k0 = 0; k0 < nd; k0 += kDChunk) {
-    double sx[kDChunk], acc[kDChunk];
+    double acc[kDChunk];
 #pragma unroll
     for (int c = 0; c < kDChunk; ++c) {
-      int k = k0 + c;
-      sx[c] = (i < P && k < nd) ? tab[(int64_t)(k * dim) * P + i] : 0.0;
-      acc[c] = 0.0;
-    }
-    for (int64_t rr = r0; rr < r1; ++rr) {
-      const int j = (int)(rr % P);
-      const int kz = (int)(rr / P);
-      const double rv = i < P ? r[rr * P + i] : 0.0;
+      const int k = k0 + c;
+      const double sx = (col_ok && k < nd) ? tab[(int64_t)(k * dim) * P + i] : 0.0;
+      double a = 0.0;
+      if (k < nd) {
 #pragma unroll
-      for (int c = 0; c < kDChunk; ++c) {
-        int k = k0 + c;
-        if (k < nd) {
+        for (int t = 0; t < kRowsPerBlock; ++t) {
+          const int64_t rr = min(r0 + t, rows - 1);
+          const int j = (int)(rr % P);
           double fac = tab[(int64_t)(k * dim + 1) * P + j];
-          if (dim == 3) fac *= tab[(int64_t)(k * dim + 2) * P + kz];
-          acc[c] += (rv * fac) * sx[c];
+          if (dim == 3) fac *= tab[(int64_t)(k * dim + 2) * P + (int)(rr / P)];
+          a += rv[t] * fac;
         }
       }
+      acc[c] = a * sx;
     }
-    double outv[kDChunk];
     __shared__ double red[kDChunk];
     block_sum_multi<kDChunk>(acc, red, tid);
     if (tid < kDChunk && k0 + tid < nd) partials[(int64_t)blk * nd + k0 + tid] = red[tid];
-    (void)outv;
     __syncthreads();
   }
 }
@@ -397,16 +400,16 @@ void launch_defl_project(const Defl& d, const double* r, double* partials, hipSt
 
 __global__ void k_defl_reduce(const double* partials, int count, int nd, double* slots, int dst,
                               const double* scale) {
-  for (int k = threadIdx.x; k < nd; k += blockDim.x) {
-    double acc = 0.0;
-    for (int b = 0; b < count; ++b) acc += partials[(int64_t)b * nd + k];
-    slots[dst + k] = scale ? acc * scale[k] : acc;
-  }
+  const int k = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < count; b += blockDim.x) acc += partials[(int64_t)b * nd + k];
+  double s = block_sum256(acc, threadIdx.x);
+  if (threadIdx.x == 0) slots[dst + k] = scale ? s * scale[k] : s;
 }
 
 void launch_defl_reduce(const double* partials, int count, int nd, double* slots, int dst,
                         const double* scale_dev, hipStream_t s) {
-  hipLaunchKernelGGL(k_defl_reduce, dim3(1), dim3(256), 0, s, partials, count, nd, slots, dst,
+  hipLaunchKernelGGL(k_defl_reduce, dim3(nd), dim3(256), 0, s, partials, count, nd, slots, dst,
                      scale_dev);
 }
 
@@ -419,20 +422,32 @@ __global__ __launch_bounds__(256) void k_sine_combine(const double* tab, int nd,
   const int64_t rows = dim == 2 ? (int64_t)P : (int64_t)P * P;
   const int i = blockIdx.x * 256 + threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.y * kRowsPerBlock;
-  const int64_t r1 = min(r0 + kRowsPerBlock, rows);
   if (i >= P) return;
   const double al = aslot >= 0 ? slots[aslot] : alpha;
-  for (int64_t rr = r0; rr < r1; ++rr) {
-    const int j = (int)(rr % P);
-    const int kz = (int)(rr / P);
-    double s = 0.0;
-    for (int k = 0; k < nd; ++k) {
-      double fac = tab[(int64_t)(k * dim + 1) * P + j];
-      if (dim == 3) fac *= tab[(int64_t)(k * dim + 2) * P + kz];
-      s += slots[src + k] * fac * tab[(int64_t)(k * dim) * P + i];
+  double sum[kRowsPerBlock];
+#pragma unroll
+  for (int t = 0; t < kRowsPerBlock; ++t) sum[t] = 0.0;
+  for (int k0 = 0; k0 < nd; k0 += kDChunk) {
+#pragma unroll 4
+    for (int c = 0; c < kDChunk; ++c) {
+      const int k = k0 + c;
+      if (k >= nd) break;
+      const double coef = slots[src + k] * tab[(int64_t)(k * dim) * P + i];
+#pragma unroll
+      for (int t = 0; t < kRowsPerBlock; ++t) {
+        const int64_t rr = min(r0 + t, rows - 1);
+        double fac = tab[(int64_t)(k * dim + 1) * P + (int)(rr % P)];
+        if (dim == 3) fac *= tab[(int64_t)(k * dim + 2) * P + (int)(rr / P)];
+        sum[t] += coef * fac;
+      }
     }
+  }
+#pragma unroll
+  for (int t = 0; t < kRowsPerBlock; ++t) {
+    const int64_t rr = r0 + t;
+    if (rr >= rows) break;
     const int64_t p = rr * P + i;
-    double v = (al == 0.0 ? 0.0 : al * y[p]) - s;
+    double v = (al == 0.0 ? 0.0 : al * y[p]) - sum[t];
     if (r) v += beta * r[p];
     y[p] = v;
   }

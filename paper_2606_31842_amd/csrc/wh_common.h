@@ -52,6 +52,8 @@ struct StepArgs {
   const double* x;        // M_LAST_AQ / M_LAST_FPI: the vector being filtered
   double* out;            // M_LAST_AQ: q ; M_LAST_FPI: Pi x
   double* partials;       // per-block partial sums
+  void* zb0;              // M_FIRST: second state pair whose boundary ring is zeroed
+  void* zb1;
   int n;
 };
 
@@ -72,8 +74,8 @@ struct FusedArgs {
   const void* kap;
   const void* fs;
   double a;
-  const double* wts;     // device: w_{n+1..n+k}
-  const double* cosv;    // device: cos(omega_w t^{n..n+k-1})
+  const double* wts;     // host: w_{n+1..n+k}
+  const double* cosv;    // host: cos(omega_w t^{n..n+k-1})
   int n;
   int k;
 };

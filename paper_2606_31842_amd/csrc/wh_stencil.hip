@@ -167,6 +167,8 @@ __global__ __launch_bounds__(256) void k_first(StepArgs a) {
   if (!interior) {
     w0o[p] = T(0);
     w1o[p] = T(0);
+    if (a.zb0) ((T*)a.zb0)[p] = T(0);
+    if (a.zb1) ((T*)a.zb1)[p] = T(0);
     a.V[p] = 0.0;
     return;
   }

@@ -93,3 +93,25 @@ def test_filter_fixed_point_config1():
     U = disc.to_nodal(disc.direct_solve(L, p.omega, disc.to_interior(p.f)), 2, p.n)
     out, _ = wh.apply_filter(cuda(U), p.omega, f=cuda(p.f))
     assert rel(host(out), U) < 1e-13
+
+
+@pytest.mark.parametrize("k_fuse", [1, 2, 3, 4, 6, 8])
+@pytest.mark.parametrize("dim,n,omega,varc,force", [(2, 37, 11.3, False, True), (2, 130, 31.7, True, True),
+                                                     (2, 257, 40.2, True, False), (2, 5, 3.3, False, False)])
+def test_fused_steps_match_oracle(k_fuse, dim, n, omega, varc, force):
+    print(f"case fused k={k_fuse} n={n} varc={varc} force={force}", flush=True)
+    import paper_2606_31842_amd as wh
+    v = wl.random_nodal(dim, n, seed=3 * n)
+    c2 = None
+    if varc:
+        rng = np.random.default_rng(n)
+        c = 1 + wl.gaussian_sum_field(dim, n, rng.uniform(-.3, .3, 3), rng.uniform(.2, .8, (3, dim)), 0.2)
+        c2 = c * c
+    f = wl.gaussian(dim, n, (0.4, 0.6), 0.15) if force else None
+    ref = _oracle_filter(dim, n, omega, v, f, c2)
+    args = dict(f=None if f is None else cuda(f), c2=None if c2 is None else cuda(c2), k_fuse=k_fuse)
+    out, info = wh.apply_filter(cuda(v), omega, **args)
+    assert rel(host(out), ref) < 1e-12
+    out32, _ = wh.apply_filter(cuda(v), omega, precision="mixed", **args)
+    emu = rel(_oracle_filter(dim, n, omega, v, f, c2, state_dtype=np.float32), ref)
+    assert rel(host(out32), ref) < 20 * emu + 1e-7
