@@ -185,6 +185,21 @@ wh_status wh_helmholtz_residual(wh_ctx* ctx, const wh_grid* grid, const double* 
                                 const double* f, double omega, const double* u,
                                 void* ws, size_t ws_bytes, double* rel);
 
+/* Bytes of device workspace needed by wh_solve_batched for these problems. */
+size_t wh_workspace_bytes_batched(int32_t nb, const wh_problem* probs, const wh_params* params);
+
+/* Solve nb independent 2D problems (grids of any size, own omega, source and
+ * optional c2) with CG on the WaveHoltz system (Algorithm 3 without deflation),
+ * in one device-driven batch: every problem's wave solves and Krylov updates are
+ * advanced by shared launches captured in a hipGraph (the paper's motivation of
+ * many right-hand sides and frequencies, Section 1).  probs: host array; each
+ * problem's omega overrides params->omega; u is output only (batched solves start
+ * from zero).  All problems must have c2 or none; with c2, params->c_max must bound
+ * c.  params->k_fuse in {2, 4, 8} sets the time steps per launch (0: 4).
+ * infos: host array of nb (may be NULL).  Returns the worst status over problems. */
+wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
+                           const wh_params* params, void* ws, size_t ws_bytes, wh_info* infos);
+
 /* Measurement helper: the average duration in microseconds of one launch of the
  * time-stepping kernel that wh_apply_filter / wh_solve would use for these
  * arguments (the K-step temporally blocked kernel, or the single-step kernel when

@@ -257,3 +257,39 @@ def time_step_kernel(v, omega, c2=None, reps=50, **kw):
                                  C.byref(us), C.byref(k))
     _check(lib, ctx, st)
     return us.value / 1e3
+
+
+def solve_batched(problems, workspace=None, **kw):
+    """Solve many 2D problems in one device-driven batch (wh_solve_batched).
+
+    problems: sequence of (f, omega) or (f, omega, c2) with nodal float64 CUDA tensors.
+    Returns (list of solutions, list of info dicts)."""
+    torch = _torch()
+    lib = nat.load()
+    nb = len(problems)
+    arr = (nat.WhProblem * nb)()
+    outs = []
+    ctx = None
+    for i, pr in enumerate(problems):
+        f, om = pr[0], pr[1]
+        c2 = pr[2] if len(pr) > 2 else None
+        n = f.shape[0] - 1
+        _nodal(f, 2, n, "f"); _nodal(c2, 2, n, "c2")
+        u = torch.empty_like(f)
+        outs.append(u)
+        arr[i].grid = _grid(2, n)
+        arr[i].c2 = None if c2 is None else c2.data_ptr()
+        arr[i].f = f.data_ptr()
+        arr[i].omega = float(om)
+        arr[i].u = u.data_ptr()
+        if ctx is None:
+            ctx = context(f.device.index)
+    p = params(float(problems[0][1]), **kw)
+    need = lib.wh_workspace_bytes_batched(nb, arr, C.byref(p))
+    if need == 0:
+        raise WaveHoltzError(-1, "invalid batch (wh_workspace_bytes_batched returned 0)")
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need)
+    infos = (nat.WhInfo * nb)()
+    st = lib.wh_solve_batched(ctx, nb, arr, C.byref(p), _ptr(ws), ws.numel(), infos)
+    _check(lib, ctx, st)
+    return outs, [infos[i].as_dict() for i in range(nb)]

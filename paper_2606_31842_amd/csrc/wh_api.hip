@@ -17,14 +17,6 @@
 
 using namespace wh;
 
-struct wh_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  std::string err;
-  double* hbuf = nullptr;  // pinned host scalars
-  int hbuf_len = 0;
-  std::map<std::tuple<int, int, int, int, int>, int> ktune;  // (dim, n, f32, varc, force) -> K
-};
 
 namespace {
 
@@ -53,12 +45,10 @@ constexpr int kHostScalars = 4096;
   } while (0)
 
 // ----------------------------------------------------------------- time parameters
-struct TimeParams {
-  int m = 0, nt = 0;
-  double dt = 0, omega_w = 0, tbar = 0, c_max = 0;
-  std::vector<double> w, cosv;
-};
 
+}  // namespace
+
+namespace wh {
 // Section 2.2: dt from the CFL bound, m whole steps per period, the adjusted
 // frequency omega_tilde = (2 pi/m)/dt with dt = 2 sin(pi/m)/omega (so that the
 // leapfrog dispersion relation maps omega_tilde to omega), trapezoid weights
@@ -116,6 +106,10 @@ double transfer(const TimeParams& tp, double lam2) {
   }
   return s;
 }
+
+}  // namespace wh
+
+namespace {
 
 // ----------------------------------------------------------------- workspace layout
 struct Layout {

@@ -1,0 +1,833 @@
+// Batched WaveHoltz solves: many 2D problems of different sizes, frequencies and
+// sources advanced together by device-side phase machines.
+//
+// Every problem runs the same method as wh_solve (the filter of eq. WaveHoltzDiscreteFPI
+// applied by the leapfrog scheme with the trapezoid sum, and CG on A = I - S_h,
+// Algorithm 3 without deflation; in mixed precision an FP64 outer residual around
+// FP32-stepped inner CG solves).  Instead of host-driven loops, each problem keeps
+// its phase, time-step counter and Krylov scalars in device memory:
+//
+//   B_FIRST -> B_STEP* -> B_LAST         b = Pi_h(0; f)                        (FP64)
+//   INIT                                 r = p = rhs, d = 0
+//   A_FIRST -> A_STEP* -> A_LAST         q = A p, partial sums of p.q          (CG precision)
+//   UPD1                                 y += alpha p, r -= alpha q, partial r.r
+//   UPD2                                 p = r + beta p            -> A_FIRST
+//   ADD_D                                x += d                    (mixed only)
+//   R_FIRST -> R_STEP* -> R_LAST         ro = b - A x, partial ro.ro          (FP64)
+//
+// One round = FP64 work kernel + FP32 work kernel + control kernel.  A work kernel
+// covers every tile of every problem (a static block -> (problem, tile) table laid
+// out so each XCD gets a contiguous run of tiles); a block does the work of its
+// problem's current phase on its tile, or returns.  The control kernel (one block
+// per problem) reduces the tile partial sums in a fixed order, updates alpha/beta
+// and the convergence state and advances the phase.  Rounds contain no host
+// decisions, so the host captures several of them in one hipGraph and replays it,
+// reading back one counter of unfinished problems per replay.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "wh_common.h"
+#include "wh_reduce.h"
+
+namespace wh {
+
+enum BPhase : int {
+  BP_B_FIRST = 0, BP_B_STEP, BP_B_LAST,
+  BP_INIT,
+  BP_A_FIRST, BP_A_STEP, BP_A_LAST,
+  BP_UPD1, BP_UPD2,
+  BP_ADD_D,
+  BP_R_FIRST, BP_R_STEP, BP_R_LAST,
+  BP_DONE
+};
+
+struct BDesc {
+  int n, nt, ntx, nty, tile0, mixed, max_iters, max_outer;
+  double a, tol, itol;
+  double *x, *b, *r, *p, *q, *ro, *d, *V;
+  void* W[4];                 // FP64 (prev, cur) pairs 0 and 1; 8 bytes per node each
+  void* W32[4];               // FP32 pairs (mixed only): the FP32 view of W[] would alias
+                              // boundary nodes onto halves of interior doubles
+  const double* kap64;
+  const double* fs64;
+  const float* kap32;
+  const float* fs32;
+  const double* w;            // trapezoid weights, N_t + 1
+  const double* cosv;         // cos(omega_w t^n), N_t + 1
+  double* partials;           // one per tile
+};
+
+struct BState {
+  int phase, step, pair, iters, outer, status, inner, pad;
+  double r2, rhs2, nb2, alpha, beta, rel, itol, pq;
+};
+
+__device__ __forceinline__ int phase_prec(int ph, int mixed) {
+  if (ph == BP_A_FIRST || ph == BP_A_STEP || ph == BP_A_LAST) return mixed ? 1 : 0;
+  return 0;  // FP64 stepping phases and the element-wise phases
+}
+
+__device__ __forceinline__ int xcd_tile_b(int bid, int nb) {
+  const int xcd = bid & 7, idx = bid >> 3;
+  const int q = nb >> 3, r = nb & 7;
+  return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+template <typename T>
+__device__ __forceinline__ T* state_of(const BDesc& D, int k) {
+  return sizeof(T) == 8 ? (T*)D.W[k] : (T*)D.W32[k];
+}
+
+template <typename T>
+__device__ __forceinline__ const T* kap_of(const BDesc& D);
+template <>
+__device__ __forceinline__ const double* kap_of<double>(const BDesc& D) { return D.kap64; }
+template <>
+__device__ __forceinline__ const float* kap_of<float>(const BDesc& D) { return D.kap32; }
+template <typename T>
+__device__ __forceinline__ const T* fs_of(const BDesc& D);
+template <>
+__device__ __forceinline__ const double* fs_of<double>(const BDesc& D) { return D.fs64; }
+template <>
+__device__ __forceinline__ const float* fs_of<float>(const BDesc& D) { return D.fs32; }
+
+// 5-point update at interior node p from state arrays (global reads).
+template <typename T, bool VARC>
+__device__ __forceinline__ T lap_term(const T* c, const T* kap, int64_t p, int64_t P, T A) {
+  const T cc = c[p];
+  if (VARC) {
+    const T kc = kap[p];
+    return (kc + kap[p - 1]) * (c[p - 1] - cc) + (kc + kap[p + 1]) * (c[p + 1] - cc) +
+           ((kc + kap[p - P]) * (c[p - P] - cc) + (kc + kap[p + P]) * (c[p + P] - cc));
+  }
+  return A * (((c[p - 1] + c[p + 1]) + (c[p - P] + c[p + P])) - T(4) * cc);
+}
+
+template <typename T, int K, int R, bool VARC>
+__global__ __launch_bounds__(256) void k_batch_work(const BDesc* __restrict__ descs,
+                                                    const BState* __restrict__ states,
+                                                    const int* __restrict__ tile_solve, int ntiles,
+                                                    int want) {
+  constexpr int TXO = 64 - 2 * K;
+  constexpr int TYO = 4 * R - 2 * K;
+  const int gt = xcd_tile_b(blockIdx.x, ntiles);
+  const int sid = tile_solve[gt];
+  const BDesc& D = descs[sid];
+  const int ph = states[sid].phase;
+  if (ph == BP_DONE) return;
+  const int prec = phase_prec(ph, D.mixed);
+  const bool stepping = ph != BP_INIT && ph != BP_UPD1 && ph != BP_UPD2 && ph != BP_ADD_D;
+  if (want == 1 && !(stepping && prec == 1)) return;
+  if (want == 0 && stepping && prec == 1) return;
+  const int n = D.n;
+  const int64_t P = (int64_t)n + 1;
+  const int lt = gt - D.tile0;
+  const int x0 = 1 + (lt % D.ntx) * TXO;
+  const int y0 = 1 + (lt / D.ntx) * TYO;
+  const int tid = threadIdx.y * 64 + threadIdx.x;
+  const BState& S = states[sid];
+  double acc = 0.0;
+  bool reduce = false;
+  const T A = (T)D.a;
+
+  // element-wise loop over the tile's interior nodes
+#define TILE_FOR(p)                                                                  \
+  for (int e = tid; e < TXO * TYO; e += 256)                                         \
+    if (x0 + e % TXO <= n - 1 && y0 + e / TXO <= n - 1)                              \
+      for (int64_t p = (int64_t)(y0 + e / TXO) * P + (x0 + e % TXO), _o = 0; _o < 1; ++_o)
+
+  switch (ph) {
+    case BP_INIT: {
+      const double* rhs = (D.mixed && S.outer > 0) ? D.ro : D.b;
+      TILE_FOR(p) {
+        const double v = rhs[p];
+        D.r[p] = v;
+        D.p[p] = v;
+        if (D.mixed) D.d[p] = 0.0;
+      }
+      break;
+    }
+    case BP_UPD1: {
+      double* y = D.mixed ? D.d : D.x;
+      const double al = S.alpha;
+      reduce = true;
+      TILE_FOR(p) {
+        y[p] += al * D.p[p];
+        const double rv = D.r[p] - al * D.q[p];
+        D.r[p] = rv;
+        acc += rv * rv;
+      }
+      break;
+    }
+    case BP_UPD2: {
+      const double be = S.beta;
+      TILE_FOR(p) { D.p[p] = D.r[p] + be * D.p[p]; }
+      break;
+    }
+    case BP_ADD_D: {
+      TILE_FOR(p) { D.x[p] += D.d[p]; }
+      break;
+    }
+    case BP_B_FIRST:
+    case BP_A_FIRST:
+    case BP_R_FIRST: {
+      // W^0 = src (B: zero), W^1 = W^0 + dt^2/2 (L_h W^0 - f), V = w0 W^0 + w1 W^1
+      const double* src = ph == BP_A_FIRST ? D.p : (ph == BP_R_FIRST ? D.x : nullptr);
+      const bool force = ph == BP_B_FIRST;
+      T* w0o = state_of<T>(D, 0);
+      T* w1o = state_of<T>(D, 1);
+      const T* kap = kap_of<T>(D);
+      const T* fs = fs_of<T>(D);
+      TILE_FOR(p) {
+        T c = T(0), lap = T(0);
+        if (src) {
+          const int i = (int)(p % P), j = (int)(p / P);
+          c = (T)src[p];
+          const T wv = i > 1 ? (T)src[p - 1] : T(0);
+          const T ev = i < n - 1 ? (T)src[p + 1] : T(0);
+          const T sv = j > 1 ? (T)src[p - P] : T(0);
+          const T nv = j < n - 1 ? (T)src[p + P] : T(0);
+          if (VARC) {
+            const T kc = kap[p];
+            lap = (kc + kap[p - 1]) * (wv - c) + (kc + kap[p + 1]) * (ev - c) +
+                  ((kc + kap[p - P]) * (sv - c) + (kc + kap[p + P]) * (nv - c));
+          } else {
+            lap = A * (((wv + ev) + (sv + nv)) - T(4) * c);
+          }
+        }
+        if (force) lap -= (T)D.cosv[0] * fs[p];
+        const T w1 = c + T(0.5) * lap;
+        w0o[p] = c;
+        w1o[p] = w1;
+        D.V[p] = D.w[0] * (src ? src[p] : 0.0) + D.w[1] * (double)w1;
+      }
+      break;
+    }
+    case BP_B_LAST:
+    case BP_A_LAST:
+    case BP_R_LAST: {
+      const int pr = S.pair;
+      const T* cur = state_of<T>(D, 2 * pr + 1);
+      const T* prv = state_of<T>(D, 2 * pr);
+      const T* kap = kap_of<T>(D);
+      const T* fs = fs_of<T>(D);
+      const int k = D.nt - 1;
+      const double wn = D.w[k + 1];
+      const T cn = (T)D.cosv[k];
+      reduce = true;
+      TILE_FOR(p) {
+        T nw = (cur[p] + cur[p]) - prv[p] + lap_term<T, VARC>(cur, kap, p, P, A);
+        if (ph == BP_B_LAST) nw -= cn * fs[p];
+        const double vf = D.V[p] + wn * (double)nw;
+        if (ph == BP_B_LAST) {
+          D.b[p] = vf;
+          acc += vf * vf;
+        } else if (ph == BP_A_LAST) {
+          const double pv = D.p[p];
+          const double qv = pv - vf;
+          D.q[p] = qv;
+          acc += pv * qv;
+        } else {
+          // ro exists only in mixed precision; an FP64 batch takes this residual once,
+          // after CG has finished with r, so r holds it
+          const double rv = D.b[p] - (D.x[p] - vf);
+          (D.mixed ? D.ro : D.r)[p] = rv;
+          acc += rv * rv;
+        }
+      }
+      break;
+    }
+    case BP_B_STEP:
+    case BP_A_STEP:
+    case BP_R_STEP: {
+      // K' <= K fused steps on a register tile (see k_fused2d)
+      const int Kp = min(K, D.nt - 1 - S.step);
+      const bool force = ph == BP_B_STEP;
+      const int pr = S.pair;
+      const T* cin = state_of<T>(D, 2 * pr + 1);
+      const T* pin = state_of<T>(D, 2 * pr);
+      T* cout = state_of<T>(D, 2 * (pr ^ 1) + 1);
+      T* pout = state_of<T>(D, 2 * (pr ^ 1));
+      const T* kap = kap_of<T>(D);
+      const T* fsv = fs_of<T>(D);
+      const int lane = threadIdx.x, wv = threadIdx.y;
+      const int xg = x0 - K + lane;
+      const int yb = y0 - K + wv * R;
+      const bool xin = xg >= 1 && xg <= n - 1;
+      T cur[R], prv[R];
+      double ac[R];
+      T cw[VARC ? R : 1], ce[VARC ? R : 1], cu[VARC ? R : 1], cd[VARC ? R : 1];
+      T frc[R];
+      uint32_t mask = 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int y = yb + r;
+        const bool in = xin && y >= 1 && y <= n - 1;
+        const int64_t p = (int64_t)y * P + xg;
+        cur[r] = in ? cin[p] : T(0);
+        prv[r] = in ? pin[p] : T(0);
+        ac[r] = 0.0;
+        if (in) mask |= 1u << r;
+        if (VARC) {
+          T kc = T(0), kw = T(0), ke = T(0), ku = T(0), kd = T(0);
+          if (in) {
+            kc = kap[p];
+            kw = kap[p - 1];
+            ke = kap[p + 1];
+            ku = kap[p - P];
+            kd = kap[p + P];
+          }
+          cw[VARC ? r : 0] = kc + kw;
+          ce[VARC ? r : 0] = kc + ke;
+          cu[VARC ? r : 0] = kc + ku;
+          cd[VARC ? r : 0] = kc + kd;
+        }
+        frc[r] = (force && in) ? fsv[p] : T(0);
+      }
+      __shared__ T edge[2][4][2][64];
+      for (int s = 0; s < Kp; ++s) {
+        const int bb = s & 1;
+        edge[bb][wv][0][threadIdx.x] = cur[0];
+        edge[bb][wv][1][threadIdx.x] = cur[R - 1];
+        __syncthreads();
+        const T up_e = wv > 0 ? edge[bb][wv - 1][1][lane] : T(0);
+        const T dn_e = wv < 3 ? edge[bb][wv + 1][0][lane] : T(0);
+        const T cn = (T)D.cosv[S.step + s];
+        const double ws = D.w[S.step + s + 1];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const T c = cur[r];
+          const T u = r > 0 ? cur[r - 1] : up_e;
+          const T dd = r < R - 1 ? cur[r + 1] : dn_e;
+          const T w = __shfl_up(c, 1, 64);
+          const T e = __shfl_down(c, 1, 64);
+          T nw;
+          if (VARC) {
+            const int q = VARC ? r : 0;
+            nw = (c + c) - prv[r] +
+                 (cw[q] * (w - c) + ce[q] * (e - c) + (cu[q] * (u - c) + cd[q] * (dd - c)));
+          } else {
+            nw = (c + c) - prv[r] + A * (((w + e) + (u + dd)) - T(4) * c);
+          }
+          nw -= cn * frc[r];
+          nw = ((mask >> r) & 1u) ? nw : T(0);
+          prv[r] = nw;            // rows r+1.. still read the old cur[r]
+          ac[r] += ws * (double)nw;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const T tmp = cur[r];
+          cur[r] = prv[r];
+          prv[r] = tmp;
+        }
+      }
+      if (lane >= K && lane < 64 - K && xin) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int ry = wv * R + r;
+          if (ry >= K && ry < 4 * R - K && ((mask >> r) & 1u)) {
+            const int64_t p = (int64_t)(yb + r) * P + xg;
+            cout[p] = cur[r];
+            pout[p] = prv[r];
+            D.V[p] += ac[r];
+          }
+        }
+      }
+      break;
+    }
+    default:
+      break;
+  }
+#undef TILE_FOR
+  if (reduce) {
+    const double sres = block_sum256(acc, tid);
+    if (tid == 0) D.partials[lt] = sres;
+  }
+}
+
+// One block per problem: reduce the tile partials in order and advance the phase.
+__global__ __launch_bounds__(256) void k_batch_control(const BDesc* __restrict__ descs,
+                                                       BState* __restrict__ states, int K) {
+  const int sid = blockIdx.x;
+  const BDesc& D = descs[sid];
+  BState& S = states[sid];
+  const int ph = S.phase;
+  if (ph == BP_DONE) return;
+  const bool red = ph == BP_B_LAST || ph == BP_A_LAST || ph == BP_R_LAST || ph == BP_UPD1;
+  double sum = 0.0;
+  if (red) {
+    double acc = 0.0;
+    const int nt = D.ntx * D.nty;
+    for (int t = threadIdx.x; t < nt; t += 256) acc += D.partials[t];
+    sum = block_sum256(acc, threadIdx.x);
+  }
+  if (threadIdx.x != 0) return;
+  auto after_first = [&](int step_phase, int last_phase) {
+    S.step = 1;
+    S.pair = 0;
+    S.phase = (D.nt - 1 == 1) ? last_phase : step_phase;
+  };
+  auto after_step = [&](int last_phase) {
+    const int Kp = min(K, D.nt - 1 - S.step);
+    S.step += Kp;
+    S.pair ^= 1;
+    if (S.step >= D.nt - 1) S.phase = last_phase;
+  };
+  switch (ph) {
+    case BP_B_FIRST: after_first(BP_B_STEP, BP_B_LAST); break;
+    case BP_A_FIRST: after_first(BP_A_STEP, BP_A_LAST); break;
+    case BP_R_FIRST: after_first(BP_R_STEP, BP_R_LAST); break;
+    case BP_B_STEP: after_step(BP_B_LAST); break;
+    case BP_A_STEP: after_step(BP_A_LAST); break;
+    case BP_R_STEP: after_step(BP_R_LAST); break;
+    case BP_B_LAST:
+      S.nb2 = sum;
+      if (!(sum > 0)) {         // f = 0: u = 0 is the solution
+        S.rel = 0.0;
+        S.status = WH_OK;
+        S.phase = BP_DONE;
+      } else if (!isfinite(sum)) {
+        S.status = WH_EUNSTABLE;
+        S.phase = BP_DONE;
+      } else {
+        S.rhs2 = sum;
+        S.rel = 1.0;
+        S.phase = BP_INIT;
+      }
+      break;
+    case BP_INIT:
+      S.r2 = S.rhs2;
+      S.inner = 0;
+      S.itol = D.mixed ? fmax(D.itol, 0.3 * D.tol / S.rel) : D.tol;
+      S.phase = BP_A_FIRST;
+      break;
+    case BP_A_LAST:
+      S.pq = sum;
+      if (!isfinite(sum)) {
+        S.status = WH_EUNSTABLE;
+        S.phase = BP_DONE;
+      } else if (sum == 0.0) {
+        S.status = WH_EBREAKDOWN;
+        S.phase = BP_DONE;
+      } else {
+        S.alpha = S.r2 / sum;
+        S.phase = BP_UPD1;
+      }
+      break;
+    case BP_UPD1: {
+      S.beta = sum / S.r2;
+      S.r2 = sum;
+      S.iters++;
+      S.inner++;
+      const double rel_in = sqrt(sum / S.rhs2);
+      const bool conv = rel_in <= S.itol;
+      const bool cap = S.iters >= D.max_iters;
+      if (!isfinite(rel_in)) {
+        S.status = WH_EUNSTABLE;
+        S.phase = BP_DONE;
+      } else if (!D.mixed) {
+        S.rel = rel_in;
+        if (conv || cap) {
+          S.status = conv ? WH_OK : WH_ENOCONV;
+          S.phase = BP_R_FIRST;          // true FP64 residual for the report
+        } else {
+          S.phase = BP_UPD2;
+        }
+      } else {
+        S.phase = (conv || cap) ? BP_ADD_D : BP_UPD2;
+      }
+      break;
+    }
+    case BP_UPD2: S.phase = BP_A_FIRST; break;
+    case BP_ADD_D: S.phase = BP_R_FIRST; break;
+    case BP_R_LAST: {
+      const double rel = sqrt(sum / S.nb2);
+      S.outer++;
+      if (!D.mixed) {
+        S.pq = rel;                      // true residual (status already set)
+        S.phase = BP_DONE;
+      } else {
+        S.rel = rel;
+        if (rel <= D.tol) {
+          S.status = WH_OK;
+          S.phase = BP_DONE;
+        } else if (!isfinite(rel)) {
+          S.status = WH_EUNSTABLE;
+          S.phase = BP_DONE;
+        } else if (S.outer > D.max_outer || S.iters >= D.max_iters) {
+          S.status = WH_ENOCONV;
+          S.phase = BP_DONE;
+        } else {
+          S.rhs2 = sum;
+          S.phase = BP_INIT;
+        }
+      }
+      break;
+    }
+    default: break;
+  }
+}
+
+__global__ void k_batch_count(const BState* states, int nb, int* remaining) {
+  int c = 0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) c += states[i].phase != BP_DONE;
+  __shared__ int sm[256];
+  sm[threadIdx.x] = c;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) remaining[0] = sm[0];
+}
+
+// ------------------------------------------------------------------ host side
+constexpr int kBR = 16;  // rows per thread of the batched tile
+
+static bool batch_k_ok(int K) { return K == 2 || K == 4 || K == 8; }
+
+template <int K, bool VARC>
+static void launch_round_k(const BDesc* descs, BState* states, const int* ts, int ntiles,
+                           hipStream_t s) {
+  dim3 g(ntiles), b(64, 4);
+  hipLaunchKernelGGL((k_batch_work<double, K, kBR, VARC>), g, b, 0, s, descs, (const BState*)states, ts,
+                     ntiles, 0);
+  hipLaunchKernelGGL((k_batch_work<float, K, kBR, VARC>), g, b, 0, s, descs, (const BState*)states, ts,
+                     ntiles, 1);
+}
+
+static void launch_round(int K, bool varc, int nb, const BDesc* descs, BState* states,
+                         const int* ts, int ntiles, hipStream_t s) {
+  switch (K) {
+    case 2: varc ? launch_round_k<2, true>(descs, states, ts, ntiles, s)
+                 : launch_round_k<2, false>(descs, states, ts, ntiles, s); break;
+    case 4: varc ? launch_round_k<4, true>(descs, states, ts, ntiles, s)
+                 : launch_round_k<4, false>(descs, states, ts, ntiles, s); break;
+    default: varc ? launch_round_k<8, true>(descs, states, ts, ntiles, s)
+                  : launch_round_k<8, false>(descs, states, ts, ntiles, s); break;
+  }
+  hipLaunchKernelGGL(k_batch_control, dim3(nb), dim3(256), 0, s, descs, states, K);
+}
+
+static int tile_dim(int n, int K, int axis) {
+  const int t = axis == 0 ? 64 - 2 * K : 4 * kBR - 2 * K;
+  return (n - 1 + t - 1) / t;
+}
+
+struct BatchLayout {
+  size_t total = 0;
+  std::vector<size_t> off;  // per problem base offsets
+  std::vector<size_t> bytes;
+  size_t descs = 0, states = 0, tiles = 0, remaining = 0;
+  int ntiles = 0;
+};
+
+static size_t take_b(BatchLayout& L, size_t bytes) {
+  size_t o = L.total;
+  L.total += (bytes + 255) & ~(size_t)255;
+  return o;
+}
+
+// per problem: 4 state arrays + V, b, r, p, q (+ ro, d mixed) (8N each), kap64/fs64 (8N),
+// kap32/fs32 (4N, mixed), partials (tiles), weights 2(N_t+1)
+static size_t problem_bytes(int n, int nt, int K, bool mixed, bool varc) {
+  const size_t N = (size_t)(n + 1) * (n + 1);
+  size_t b = 0;
+  auto add = [&](size_t x) { b += (x + 255) & ~(size_t)255; };
+  for (int i = 0; i < 4; ++i) add(8 * N);
+  if (mixed) for (int i = 0; i < 4; ++i) add(4 * N);
+  for (int i = 0; i < 5; ++i) add(8 * N);
+  if (mixed) { add(8 * N); add(8 * N); }
+  if (varc) add(8 * N);
+  add(8 * N);
+  if (mixed) { if (varc) add(4 * N); add(4 * N); }
+  add(8 * (size_t)tile_dim(n, K, 0) * tile_dim(n, K, 1));
+  add(16 * (size_t)(nt + 1));
+  return b;
+}
+
+}  // namespace wh
+
+using namespace wh;
+
+namespace {
+
+#define WHB_FAIL(ctx, code, ...)                                  \
+  do {                                                            \
+    char _b[512];                                                 \
+    snprintf(_b, sizeof(_b), __VA_ARGS__);                        \
+    if (ctx) (ctx)->err = _b;                                     \
+    return (code);                                                \
+  } while (0)
+
+#define HIPB(ctx, call)                                                           \
+  do {                                                                            \
+    hipError_t _e = (call);                                                       \
+    if (_e != hipSuccess)                                                         \
+      WHB_FAIL(ctx, WH_EHIP, "%s failed: %s", #call, hipGetErrorString(_e));     \
+  } while (0)
+
+struct Prepared {
+  std::vector<TimeParams> tp;
+  std::vector<double> cmax;
+};
+
+wh_status batch_validate(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const wh_params* P) {
+  if (nb < 1 || !probs || !P) WHB_FAIL(ctx, WH_EINVAL, "need nb >= 1 problems and params");
+  if (P->precision != WH_F64 && P->precision != WH_MIXED) WHB_FAIL(ctx, WH_EINVAL, "bad precision");
+  if (P->solver != WH_CG) WHB_FAIL(ctx, WH_EUNSUPPORTED, "batched solves use CG");
+  if (!(P->tol > 0)) WHB_FAIL(ctx, WH_EINVAL, "tol must be > 0");
+  const bool varc0 = probs[0].c2 != nullptr;
+  for (int i = 0; i < nb; ++i) {
+    const wh_problem& q = probs[i];
+    if (q.grid.dim != 2) WHB_FAIL(ctx, WH_EUNSUPPORTED, "batched solves are 2D (problem %d)", i);
+    if (q.grid.order != 2) WHB_FAIL(ctx, WH_EUNSUPPORTED, "order must be 2 (problem %d)", i);
+    if (q.grid.n < 4 || q.grid.n > 46340) WHB_FAIL(ctx, WH_EINVAL, "bad n (problem %d)", i);
+    if (!(q.omega > 0)) WHB_FAIL(ctx, WH_EINVAL, "omega must be > 0 (problem %d)", i);
+    if (!q.f || !q.u) WHB_FAIL(ctx, WH_EINVAL, "f / u is NULL (problem %d)", i);
+    if ((q.c2 != nullptr) != varc0)
+      WHB_FAIL(ctx, WH_EUNSUPPORTED, "all problems of a batch must have c2 or none");
+  }
+  if (varc0 && !(P->c_max > 0))
+    WHB_FAIL(ctx, WH_EINVAL, "batched solves with variable c need params->c_max > 0");
+  return WH_OK;
+}
+
+int batch_K(const wh_params* P) { return batch_k_ok(P->k_fuse) ? P->k_fuse : 4; }
+
+}  // namespace
+
+extern "C" {
+
+size_t wh_workspace_bytes_batched(int32_t nb, const wh_problem* probs, const wh_params* params) {
+  if (batch_validate(nullptr, nb, probs, params) != WH_OK) return 0;
+  const bool mixed = params->precision == WH_MIXED;
+  const bool varc = probs[0].c2 != nullptr;
+  const int K = batch_K(params);
+  const double cmax = params->c_max > 0 ? params->c_max : 1.0;
+  size_t total = 0;
+  int ntiles = 0;
+  for (int i = 0; i < nb; ++i) {
+    wh_params p = *params;
+    p.omega = probs[i].omega;
+    TimeParams tp;
+    if (make_time_params(nullptr, 2, probs[i].grid.n, p, cmax, tp) != WH_OK) return 0;
+    total += problem_bytes(probs[i].grid.n, tp.nt, K, mixed, varc);
+    ntiles += tile_dim(probs[i].grid.n, K, 0) * tile_dim(probs[i].grid.n, K, 1);
+  }
+  total += 16 * (size_t)kReduceBlocks;  // c_max reductions (multiple of 256)
+  total += ((sizeof(BDesc) * nb + 255) & ~(size_t)255) + ((sizeof(BState) * nb + 255) & ~(size_t)255);
+  total += ((4 * (size_t)ntiles + 255) & ~(size_t)255) + 256;
+  return total;
+}
+
+wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
+                           const wh_params* params, void* ws, size_t ws_bytes, wh_info* infos) {
+  if (!ctx) return WH_EINVAL;
+  const auto t0 = std::chrono::steady_clock::now();
+  wh_status vs = batch_validate(ctx, nb, probs, params);
+  if (vs != WH_OK) return vs;
+  const size_t need = wh_workspace_bytes_batched(nb, probs, params);
+  if (!ws || ((uintptr_t)ws & 255)) WHB_FAIL(ctx, WH_EWORKSPACE, "workspace NULL or misaligned");
+  if (ws_bytes < need) WHB_FAIL(ctx, WH_EWORKSPACE, "workspace too small: %zu < %zu", ws_bytes, need);
+  HIPB(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  const bool mixed = params->precision == WH_MIXED;
+  const bool varc = probs[0].c2 != nullptr;
+  char* base = (char*)ws;
+  size_t cur_off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = cur_off;
+    cur_off += (bytes + 255) & ~(size_t)255;
+    return (void*)(base + o);
+  };
+  // time parameters (c = 1, or the caller's c_max bound for variable c)
+  double* red = (double*)take(16 * (size_t)kReduceBlocks);
+  (void)red;
+  std::vector<TimeParams> tps(nb);
+  for (int i = 0; i < nb; ++i) {
+    const double cmax = params->c_max > 0 ? params->c_max : 1.0;
+    wh_params p = *params;
+    p.omega = probs[i].omega;
+    wh_status st = make_time_params(ctx, 2, probs[i].grid.n, p, cmax, tps[i]);
+    if (st != WH_OK) return st;
+  }
+  const int K = batch_K(params);
+  // pass 1: carve the workspace (no device writes until the layout is known to fit)
+  std::vector<BDesc> D(nb);
+  std::vector<int> tile_solve;
+  for (int i = 0; i < nb; ++i) {
+    const int n = probs[i].grid.n;
+    const size_t N = (size_t)(n + 1) * (n + 1);
+    BDesc& d = D[i];
+    std::memset(&d, 0, sizeof(d));
+    d.n = n;
+    d.nt = tps[i].nt;
+    d.ntx = tile_dim(n, K, 0);
+    d.nty = tile_dim(n, K, 1);
+    d.tile0 = (int)tile_solve.size();
+    for (int t = 0; t < d.ntx * d.nty; ++t) tile_solve.push_back(i);
+    d.mixed = mixed;
+    d.max_iters = params->max_iters > 0 ? params->max_iters : 10000;
+    d.max_outer = params->max_outer > 0 ? params->max_outer : 30;
+    const double h = 1.0 / n;
+    d.a = tps[i].dt * tps[i].dt / (h * h);
+    d.tol = params->tol;
+    d.itol = params->inner_tol > 0 ? params->inner_tol : 1e-3;
+    for (int k = 0; k < 4; ++k) d.W[k] = take(8 * N);
+    if (mixed)
+      for (int k = 0; k < 4; ++k) d.W32[k] = take(4 * N);
+    d.V = (double*)take(8 * N);
+    d.b = (double*)take(8 * N);
+    d.r = (double*)take(8 * N);
+    d.p = (double*)take(8 * N);
+    d.q = (double*)take(8 * N);
+    if (mixed) {
+      d.ro = (double*)take(8 * N);
+      d.d = (double*)take(8 * N);
+    }
+    d.x = probs[i].u;
+    double* kap64 = varc ? (double*)take(8 * N) : nullptr;
+    double* fs64 = (double*)take(8 * N);
+    float* kap32 = (mixed && varc) ? (float*)take(4 * N) : nullptr;
+    float* fs32 = mixed ? (float*)take(4 * N) : nullptr;
+    d.kap64 = kap64;
+    d.fs64 = fs64;
+    d.kap32 = kap32;
+    d.fs32 = fs32;
+    d.partials = (double*)take(8 * (size_t)d.ntx * d.nty);
+    double* wtab = (double*)take(16 * (size_t)(d.nt + 1));
+    d.w = wtab;
+    d.cosv = wtab + d.nt + 1;
+  }
+  const int ntiles = (int)tile_solve.size();
+  BDesc* ddesc = (BDesc*)take(sizeof(BDesc) * nb);
+  BState* dstate = (BState*)take(sizeof(BState) * nb);
+  int* dtiles = (int*)take(4 * (size_t)ntiles);
+  int* dremain = (int*)take(256);
+  if (cur_off > ws_bytes) WHB_FAIL(ctx, WH_EWORKSPACE, "workspace too small (layout %zu)", cur_off);
+  // pass 2: coefficient arrays, zeroed state, weight tables
+  for (int i = 0; i < nb; ++i) {
+    const int n = probs[i].grid.n;
+    const size_t N = (size_t)(n + 1) * (n + 1);
+    const double h = 1.0 / n;
+    BDesc& d = D[i];
+    double* kap64 = (double*)d.kap64;
+    double* fs64 = (double*)d.fs64;
+    float* kap32 = (float*)d.kap32;
+    float* fs32 = (float*)d.fs32;
+    double* wtab = (double*)d.w;
+    const double dt2 = tps[i].dt * tps[i].dt;
+    const double ks = dt2 / (2.0 * h * h);
+    launch_prep_coeffs(probs[i].c2, probs[i].f, kap64, fs64, false, ks, dt2, (int64_t)N, n, 2, s);
+    if (mixed) launch_prep_coeffs(probs[i].c2, probs[i].f, kap32, fs32, true, ks, dt2, (int64_t)N, n, 2, s);
+    for (int k = 0; k < 4; ++k) HIPB(ctx, hipMemsetAsync(d.W[k], 0, 8 * N, s));
+    if (mixed)
+      for (int k = 0; k < 4; ++k) HIPB(ctx, hipMemsetAsync(d.W32[k], 0, 4 * N, s));
+    for (double* v : {d.V, d.b, d.r, d.p, d.q}) HIPB(ctx, hipMemsetAsync(v, 0, 8 * N, s));
+    if (mixed) for (double* v : {d.ro, d.d}) HIPB(ctx, hipMemsetAsync(v, 0, 8 * N, s));
+    HIPB(ctx, hipMemsetAsync(d.x, 0, 8 * N, s));   // batched solves start from zero
+    // weights (staged through the pinned block)
+    std::vector<double> tab(2 * (d.nt + 1));
+    for (int k = 0; k <= d.nt; ++k) {
+      tab[k] = tps[i].w[k];
+      tab[d.nt + 1 + k] = tps[i].cosv[k];
+    }
+    for (size_t o = 0; o < tab.size(); o += ctx->hbuf_len) {
+      const size_t cnt = std::min(tab.size() - o, (size_t)ctx->hbuf_len);
+      HIPB(ctx, hipStreamSynchronize(s));
+      std::memcpy(ctx->hbuf, tab.data() + o, cnt * sizeof(double));
+      HIPB(ctx, hipMemcpyAsync(wtab + o, ctx->hbuf, cnt * sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    HIPB(ctx, hipStreamSynchronize(s));
+  }
+  // upload descriptors, tile table and the initial states (synchronous copies from host memory)
+  HIPB(ctx, hipMemcpyAsync(ddesc, D.data(), sizeof(BDesc) * nb, hipMemcpyHostToDevice, s));
+  HIPB(ctx, hipMemcpyAsync(dtiles, tile_solve.data(), 4 * (size_t)ntiles, hipMemcpyHostToDevice, s));
+  std::vector<BState> S0(nb);
+  std::memset(S0.data(), 0, sizeof(BState) * nb);
+  for (auto& st : S0) st.phase = BP_B_FIRST;
+  HIPB(ctx, hipMemcpyAsync(dstate, S0.data(), sizeof(BState) * nb, hipMemcpyHostToDevice, s));
+  HIPB(ctx, hipStreamSynchronize(s));
+  HIPB(ctx, hipGetLastError());
+
+  // capture G rounds + the counter in one graph on a private stream
+  const int G = 16;
+  hipStream_t cs;
+  HIPB(ctx, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    for (int g = 0; g < G; ++g) launch_round(K, varc, nb, ddesc, dstate, dtiles, ntiles, cs);
+    hipLaunchKernelGGL(k_batch_count, dim3(1), dim3(256), 0, cs, (const BState*)dstate, nb, dremain);
+    e = hipStreamEndCapture(cs, &graph);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cs);
+    WHB_FAIL(ctx, WH_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+  }
+  // bound on replays: every problem needs at most max_iters iterations of
+  // (N_t/K + 6) rounds plus its outer sweeps
+  long long max_rounds = 0;
+  for (int i = 0; i < nb; ++i) {
+    const long long per_it = (D[i].nt + K - 1) / K + 6;
+    const long long outer = mixed ? (D[i].max_outer + 1) * (per_it + 4) : per_it + 4;
+    max_rounds = std::max(max_rounds, (long long)D[i].max_iters * per_it + outer + 8 + per_it);
+  }
+  const long long max_replays = max_rounds / G + 2;
+  long long rep = 0;
+  int remaining = nb;
+  wh_status st = WH_OK;
+  while (remaining > 0 && rep < max_replays) {
+    e = hipGraphLaunch(exec, s);
+    if (e != hipSuccess) break;
+    ++rep;
+    e = hipMemcpyAsync(ctx->hbuf, dremain, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) break;
+    std::memcpy(&remaining, ctx->hbuf, sizeof(int));
+  }
+  (void)hipGraphExecDestroy(exec);
+  (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) WHB_FAIL(ctx, WH_EHIP, "batched replay failed: %s", hipGetErrorString(e));
+  // results
+  std::vector<BState> SF(nb);
+  HIPB(ctx, hipMemcpyAsync(SF.data(), dstate, sizeof(BState) * nb, hipMemcpyDeviceToHost, s));
+  HIPB(ctx, hipStreamSynchronize(s));
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  for (int i = 0; i < nb; ++i) {
+    int status = SF[i].phase == BP_DONE ? SF[i].status : WH_ENOCONV;
+    if (status < 0 && st >= 0) st = (wh_status)status;
+    else if (status == WH_ENOCONV && st == WH_OK) st = WH_ENOCONV;
+    if (infos) {
+      wh_info& in = infos[i];
+      std::memset(&in, 0, sizeof(in));
+      in.status = status;
+      in.iters = SF[i].iters;
+      in.outer = mixed ? SF[i].outer : 0;
+      const int wsol = SF[i].iters + SF[i].outer + 1;  // A applies + residual solves + b
+      in.wave_solves = mixed ? SF[i].outer + 1 : wsol;
+      in.wave_solves_f32 = mixed ? SF[i].iters : 0;
+      in.nt = tps[i].nt;
+      in.m = tps[i].m;
+      in.k_fuse = K;
+      in.rel_res = SF[i].rel;
+      in.true_rel_res = mixed ? SF[i].rel : SF[i].pq;
+      in.omega_tilde = tps[i].omega_w;
+      in.dt = tps[i].dt;
+      in.c_max = tps[i].c_max;
+      in.ms = ms;
+    }
+  }
+  if (st == WH_ENOCONV) ctx->err = "some batched problems did not reach the tolerance";
+  return st;
+}
+
+}  // extern "C"

@@ -5,11 +5,33 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <map>
 #include <string>
+#include <tuple>
+#include <vector>
 
 #include "../../include/waveholtz.h"
 
+struct wh_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  double* hbuf = nullptr;  // pinned host scalars
+  int hbuf_len = 0;
+  std::map<std::tuple<int, int, int, int, int>, int> ktune;  // (dim, n, f32, varc, force) -> K
+};
+
 namespace wh {
+
+// Time discretisation of one wave solve (host, FP64).
+struct TimeParams {
+  int m = 0, nt = 0;
+  double dt = 0, omega_w = 0, tbar = 0, c_max = 0;
+  std::vector<double> w, cosv;
+};
+wh_status make_time_params(wh_ctx* ctx, int dim, int n, const wh_params& P, double c_max,
+                           TimeParams& tp);
+double transfer(const TimeParams& tp, double lam2);
 
 // ----------------------------------------------------------------- device scalars
 // Slots of the per-solve FP64 scalar block in the workspace.

@@ -1,0 +1,71 @@
+"""GPU parity of wh_solve_batched: every problem of a mixed-size, mixed-frequency
+batch against the oracle's direct Helmholtz solve, and against wh_solve."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import discretization as disc
+from _gpu import cuda, host, rel, direct
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch(sizes=(24, 40, 64, 101), per=2, seed=9, omega=(8.0, 30.0)):
+    rng = np.random.default_rng(seed)
+    probs = []
+    for n in sizes:
+        for _ in range(per):
+            while True:
+                om = float(rng.uniform(*omega))
+                if wl.gap_ok(n, om, 0.05):
+                    break
+            x0 = rng.uniform(0.2, 0.8, 2)
+            probs.append((n, om, wl.gaussian(2, n, x0, 1.0 / om, amplitude=om * om)))
+    return probs
+
+
+@pytest.mark.parametrize("precision,k_fuse", [("f64", 4), ("mixed", 4), ("f64", 8), ("mixed", 2)])
+def test_batched_matches_direct_and_single(precision, k_fuse):
+    print(f"case batched {precision} K={k_fuse}", flush=True)
+    import paper_2606_31842_amd as wh
+    probs = _batch()
+    tol = 1e-9
+    us, infos = wh.solve_batched([(cuda(f), om) for (n, om, f) in probs], precision=precision, tol=tol,
+                                 k_fuse=k_fuse, max_iters=20000)
+    for (n, om, f), u, info in zip(probs, us, infos):
+        U = disc.direct_solve_dst(2, n, om, f)
+        e = rel(host(u), U)
+        print(f"n={n} omega={om:.3f} status={info['status']} iters={info['iters']} outer={info['outer']} "
+              f"true={info['true_rel_res']:.2e} err={e:.2e}", flush=True)
+        assert info["status"] == 0
+        assert info["true_rel_res"] <= (1.5 * tol if precision == "f64" else tol)
+        assert e < (1e-6 if precision == "f64" else 2e-5)
+        if precision == "f64":
+            # same algorithm as the single solve: same iteration count, same iterate
+            us1, i1 = wh.solve(cuda(f), om, solver="cg", tol=tol, max_iters=20000)
+            assert abs(i1["iters"] - info["iters"]) <= 1
+            assert rel(host(u), host(us1)) < 1e-8
+
+
+def test_batched_variable_c():
+    import paper_2606_31842_amd as wh
+    rng = np.random.default_rng(4)
+    probs = []
+    for n, om in ((32, 11.3), (48, 17.9), (30, 9.1)):
+        c2 = wl.config5_c2(n, rng)
+        probs.append((n, om, wl.gaussian(2, n, rng.uniform(.3, .7, 2), 0.1), c2))
+    us, infos = wh.solve_batched([(cuda(f), om, cuda(c2)) for (n, om, f, c2) in probs], precision="f64",
+                                 tol=1e-11, c_max=float(np.sqrt(1.2)), max_iters=20000)
+    for (n, om, f, c2), u, info in zip(probs, us, infos):
+        U = direct(2, n, om, f, c2)
+        assert info["status"] == 0
+        assert rel(host(u), U) < 1e-8
+
+
+def test_batched_rejects_bad_input():
+    import paper_2606_31842_amd as wh
+    f = cuda(wl.gaussian(2, 16, (0.5, 0.5), 0.1))
+    with pytest.raises(wh.WaveHoltzError):
+        wh.solve_batched([(f, 5.0)], solver="gmres")
+    with pytest.raises(wh.WaveHoltzError):
+        wh.solve_batched([(f, 5.0, cuda(np.ones((17, 17))))])   # variable c without c_max
