@@ -85,18 +85,28 @@ typedef struct {
                                0: dt = 2 pi/(m omega), wave solve at omega                  */
   double c_max;             /* max_x c(x); 0: computed from c2 on the device (one read-back) */
   int32_t precision;        /* wh_precision: WH_MIXED steps the wave equation in FP32 and
-                               keeps the filter sum, Krylov and deflation in FP64          */
+                               keeps the filter sum, Krylov and deflation in FP64.  CG/DCG
+                               replace their residual by the true FP64 residual each time
+                               it has dropped tenfold; GMRES refines FP32 inner solves with
+                               FP64 outer residuals.  A problem whose FP32 operator error
+                               stalls the true residual continues in FP64.                 */
   int32_t solver;           /* wh_solver                                                    */
   int32_t restart;          /* GMRES restart length (default 40)                            */
   double tol;               /* stop when ||b - A u||_2 / ||b||_2 <= tol                      */
-  int32_t max_iters;        /* solver iterations (inner iterations for WH_MIXED)            */
-  double inner_tol;         /* WH_MIXED: relative tolerance of each FP32 inner solve (1e-3)  */
-  int32_t max_outer;        /* WH_MIXED: FP64 refinement sweeps (default 30)                 */
+  int32_t max_iters;        /* solver iterations                                            */
+  double inner_tol;         /* WH_MIXED GMRES: relative tolerance of each FP32 inner restart
+                               cycle between FP64 residuals (1e-3)                          */
+  int32_t max_outer;        /* WH_MIXED GMRES: FP64 refinement sweeps (default 30)           */
   int32_t k_fuse;           /* time steps per stencil launch; 0: library choice             */
   int32_t reproject;        /* DCG A-orthogonalisation against W each iteration (Algorithm 3,
                                optional for exact eigenvectors): -1 auto (= off, every
                                deflation kind here is exact), 0 off, 1 on                  */
   int32_t check_every;      /* read the residual back every this many iterations (1)        */
+  int32_t mixed_form;       /* WH_MIXED A-apply: 0 steps the defect W^n - cos(omega_w t^n) v
+                               in FP32, using A v = Pi_h(0; H v) with H = L_h + omega^2
+                               (exact under the corrected frequency); 1 steps W^n from
+                               W^0 = v in FP32; -1 (default): 0 for CG/GMRES and batched
+                               solves, 1 for DCG                                           */
 } wh_params;
 
 typedef struct {
@@ -113,7 +123,8 @@ typedef struct {
   int32_t iters;           /* Krylov / FPI iterations (all inner iterations for WH_MIXED)  */
   int32_t wave_solves;     /* applications of Pi_h in FP64                                  */
   int32_t wave_solves_f32; /* applications of Pi_h with FP32 stepping                       */
-  int32_t outer;           /* WH_MIXED refinement sweeps                                    */
+  int32_t outer;           /* WH_MIXED: FP64 true-residual evaluations (CG/DCG) or
+                               refinement sweeps (GMRES)                                     */
   int32_t nt;              /* time steps per wave solve N_t = N_p m                         */
   int32_t m;               /* steps per period                                              */
   int32_t k_fuse;          /* time steps per stencil launch that was used                   */

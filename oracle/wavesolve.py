@@ -73,3 +73,17 @@ def dense_A(L, tp: TimeParams) -> np.ndarray:
         A[:, j] = apply_A(L, e, tp)
         e[j] = 0.0
     return A
+
+
+def apply_A_defect(L, v, tp: TimeParams, **kw) -> np.ndarray:
+    """A v computed as B (L_h + omega^2) v with B f = Pi_h(0; f).
+
+    With the corrected frequency, a trajectory started at W^0 = v splits as
+    W^n = cos(omega_w t^n) v + E^n, where E solves the same scheme from zero data with
+    forcing (L_h + omega^2) v in place of -f (the term cos(n theta) v absorbs the rest
+    because (2/dt^2)(cos theta - 1) = -omega^2), and the trapezoid weights integrate
+    cos^2 to one, so  A v = v - Pi_h(v; 0) = -sum_n w_n E^n = Pi_h(0; (L_h + omega^2) v).
+    Stepping E instead of W keeps rounding errors proportional to |E|, which is small
+    for the near-resonant components of v."""
+    g = L @ v + tp.omega ** 2 * np.asarray(v, dtype=np.float64)
+    return wave_filter(L, np.zeros(L.shape[0]), -g, tp, **kw) * -1.0

@@ -432,12 +432,22 @@ struct Solver {
   const double* negmu = nullptr;   // -1/mu_k (device) for the deflated start
   int ws64 = 0, ws32 = 0;          // wave-solve counters
   int iters = 0;
+  bool defect = true;              // FP32 A-applies in the defect form
+  double om2dt2 = 0;               // omega^2 dt^2
 };
 
 // q = A x (x nonzero).  Leaves partial sums of x.q in op.partials.
+// FP32 stepping uses the defect form A x = Pi_h(0; (L_h + omega^2) x): the state that is
+// stepped (and rounded) is W^n - cos(omega_w t^n) x, which is small for the components
+// of x near resonance, where A's eigenvalues are small.
 int applyA(Solver& S, bool f32, const double* x, double* q) {
   const WaveOp& op = f32 ? S.op32 : S.op64;
   (f32 ? S.ws32 : S.ws64)++;
+  if (f32 && S.defect) {
+    launch_defect_forcing(x, op.varc ? (const double*)S.op64.kap : nullptr, op.a, S.om2dt2,
+                          (void*)op.fs, true, op.n, op.dim, S.s);
+    return wave_solve(op, nullptr, true, M_LAST_EQ, x, q, S.s);
+  }
   return wave_solve(op, x, false, M_LAST_AQ, x, q, S.s);
 }
 
@@ -451,22 +461,37 @@ struct KrylovResult {
   double rel = 0;
   int iters = 0;
   wh_status st = WH_OK;
+  bool diverged = false;   // residual grew past 1e3 x the right-hand side (abandoned)
+  int replacements = 0;    // reliable-update residual replacements (FP64 wave solves)
 };
 
 // CG / DCG (Algorithm 3) for A x = rhs with A applied in the requested precision.
 // x holds the initial guess (x_nonzero says whether it can be nonzero).  Stops on
 // ||r|| <= tol * ||rhs||.  Uses S.partials for step partials.
+//
+// reliable = true (mixed precision): the recurrence applies the FP32-stepped operator,
+// and whenever the recursive residual has fallen by kReliableDrop since the last
+// replacement (or looks converged) it is replaced by the true residual rhs - A x
+// computed with an FP64 wave solve, beta being formed from the replaced residual.
+// The CG recurrence itself is never restarted.  If two consecutive replacements do
+// not halve the true residual, the FP32 operator error is too large for this
+// problem and the remaining iterations apply the FP64 operator.
+constexpr double kReliableDrop = 0.1;
+
 wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_nonzero, double* r,
                    double* p, double* q, double tol, int maxit, bool use_defl, bool reproject,
-                   int check_every, KrylovResult& res) {
+                   int check_every, KrylovResult& res, bool stop_on_divergence = false,
+                   bool reliable = false) {
   wh_ctx* ctx = S.ctx;
   const int64_t N = S.N;
   const int nd = use_defl ? S.defl.nd : 0;
+  // true residuals are always formed with the FP64 operator in reliable mode
+  const bool f32_true = reliable ? false : f32;
   // ||rhs||^2
   dot(S, rhs, rhs, S_NB);
   // r_{-1}
   if (x_nonzero) {
-    applyA(S, f32, x, q);
+    applyA(S, f32_true, x, q);
     launch_sub(r, rhs, q, N, S.s);
   } else {
     launch_copy(r, rhs, N, S.s);
@@ -477,7 +502,7 @@ wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_non
     launch_defl_reduce(S.partials, defl_partial_blocks(S.defl), nd, S.slots, S_H, S.negmu, S.s);
     launch_defl_combine(S.defl, x, 1.0, nullptr, 0.0, S.slots, S_H, N, S.s);
     // r_0 = rhs - A x_0
-    applyA(S, f32, x, q);
+    applyA(S, f32_true, x, q);
     launch_sub(r, rhs, q, N, S.s);
     // mu_0 = (W^T A W)^{-1} (A W)^T r_0 = W^T r_0 for eigenvectors; p_0 = r_0 - W mu_0
     launch_defl_project(S.defl, r, S.partials, S.s);
@@ -499,12 +524,50 @@ wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_non
   double rel = std::sqrt(r2 / nb2);
   if (!std::isfinite(rel)) WH_FAIL(ctx, WH_EUNSTABLE, "non-finite residual (unstable wave solve?)");
   int k = 0;
-  const int ce = std::max(1, check_every);
+  const int ce = reliable ? 1 : std::max(1, check_every);
+  bool op32 = f32;
+  double anchor = rel;        // relative true residual at the last replacement
+  int stalls = 0, last_repl = 0;
+  res.replacements = 0;
   while (rel > tol && k < maxit) {
-    int nb = applyA(S, f32, p, q);
+    const double r2_old = r2;
+    int nb = applyA(S, op32, p, q);
     launch_reduce(S.partials, nb, S.slots, S_PQ, 1, S.s);
     launch_cg_update1(x, r, p, q, S.slots, N, S.partials2, S.s);
     launch_reduce(S.partials2, kReduceBlocks, S.slots, S_R2, 2, S.s);
+    if (reliable) {
+      WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
+      const double pq = ctx->hbuf[S_PQ];
+      r2 = ctx->hbuf[S_R2];
+      if (!std::isfinite(pq) || !std::isfinite(r2))
+        WH_FAIL(ctx, WH_EUNSTABLE, "non-finite p^T A p or residual at iteration %d", k + 1);
+      if (pq == 0.0) WH_FAIL(ctx, WH_EBREAKDOWN, "CG breakdown: p^T A p = 0 at iteration %d", k + 1);
+      rel = std::sqrt(r2 / nb2);
+      if (rel <= kReliableDrop * anchor || rel >= anchor / kReliableDrop || rel <= tol ||
+          k + 1 - last_repl >= 500) {
+        applyA(S, false, x, q);
+        launch_sub(r, rhs, q, N, S.s);
+        dot(S, r, r, S_TMP);
+        launch_set_beta(S.slots, S_TMP, r2_old, S.s);
+        WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
+        r2 = ctx->hbuf[S_TMP];
+        rel = std::sqrt(r2 / nb2);
+        res.replacements++;
+        if (!std::isfinite(rel)) WH_FAIL(ctx, WH_EUNSTABLE, "non-finite true residual");
+        stalls = (rel > 0.5 * anchor) ? stalls + 1 : 0;
+        last_repl = k + 1;
+        if (stalls >= 2 && op32) {
+          // the FP32 operator error dominates: continue in FP64 from the true residual
+          op32 = false;
+          launch_set_beta(S.slots, S_TMP, HUGE_VAL, S.s);   // beta = 0: p = r
+        }
+        anchor = rel;
+        if (rel <= tol) {
+          ++k;
+          break;
+        }
+      }
+    }
     if (nd && reproject) {
       launch_defl_project(S.defl, r, S.partials, S.s);
       launch_defl_reduce(S.partials, defl_partial_blocks(S.defl), nd, S.slots, S_H, nullptr, S.s);
@@ -513,7 +576,7 @@ wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_non
       launch_cg_update2(p, r, S.slots, N, S.s);
     }
     ++k;
-    if (k % ce == 0 || k == maxit) {
+    if (!reliable && (k % ce == 0 || k == maxit)) {
       WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
       const double pq = ctx->hbuf[S_PQ];
       r2 = ctx->hbuf[S_R2];
@@ -521,6 +584,13 @@ wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_non
         WH_FAIL(ctx, WH_EUNSTABLE, "non-finite p^T A p or residual at iteration %d", k);
       if (pq == 0.0) WH_FAIL(ctx, WH_EBREAKDOWN, "CG breakdown: p^T A p = 0 at iteration %d", k);
       rel = std::sqrt(r2 / nb2);
+      if (stop_on_divergence && rel > 1e3) {
+        res.rel = rel;
+        res.iters = k;
+        res.st = WH_ENOCONV;
+        res.diverged = true;
+        return WH_OK;
+      }
     }
   }
   res.rel = rel;
@@ -726,6 +796,12 @@ wh_status setup_ops(wh_ctx* ctx, const wh_grid& g, const wh_params& P, const dou
   S.op64.f32 = false;
   S.op64.kap = at<void>(ws, L.kap64);
   S.op64.fs = at<void>(ws, L.fs64);
+  // (omega_fp dt)^2 with omega_fp the frequency the fixed point solves for:
+  // (2/dt) sin(omega_w dt / 2) (= omega under the corrected frequency)
+  S.om2dt2 = 4.0 * std::sin(0.5 * tp.omega_w * tp.dt) * std::sin(0.5 * tp.omega_w * tp.dt);
+  // defect form by default for CG/GMRES; DCG has removed the near-resonant modes, where
+  // the defect form gains, so it steps W directly (one stencil pass less per iteration)
+  S.defect = P.mixed_form == 0 || (P.mixed_form < 0 && P.solver != WH_DCG);
   S.op32 = base;
   S.op32.f32 = true;
   if (mixed) {
@@ -779,6 +855,7 @@ void wh_params_default(wh_params* p) {
   p->k_fuse = 0;
   p->reproject = -1;
   p->check_every = 1;
+  p->mixed_form = -1;
 }
 
 const char* wh_status_string(wh_status s) {
@@ -1058,8 +1135,16 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
     dot(S, b, b, S_NB);
     WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
     true_rel = ctx->hbuf[S_NB] > 0 ? std::sqrt(ctx->hbuf[S_TMP] / ctx->hbuf[S_NB]) : 0.0;
+  } else if (P.solver != WH_GMRES) {
+    // CG / DCG with FP32 stepping and reliable updates (true FP64 residuals)
+    WHCHK(cg_solve(S, true, b, u, u_nonzero, r, p, q, P.tol, P.max_iters, P.solver == WH_DCG,
+                   reproject, 1, kr, false, true));
+    st = kr.st;
+    S.iters = kr.iters;
+    outer = kr.replacements;
+    true_rel = kr.rel;
   } else {
-    // FP64 outer residual, FP32 inner solves
+    // GMRES: FP64 outer residual, FP32 inner restarted solves
     double* ro = at<double>(ws, L.ro);
     double* dv = at<double>(ws, L.d);
     dot(S, b, b, S_NB);
@@ -1070,7 +1155,8 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
     bool nonzero = u_nonzero;
     int inner_total = 0;
     st = WH_ENOCONV;
-    double rel = 1.0;
+    double rel = 1.0, prev_rel = 1.0;
+    bool inner_f32 = true;   // cleared when FP32 refinement stops contracting
     for (outer = 0; outer <= max_outer; ++outer) {
       if (nonzero) {
         applyA(S, false, u, q);
@@ -1087,18 +1173,26 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
         break;
       }
       if (outer == max_outer || inner_total >= P.max_iters) break;
-      // inner: A32 d = ro to a relative tolerance (never tighter than needed)
-      const double t_in = std::max(itol, 0.3 * P.tol / rel);
+      // refinement must contract; if a sweep did not halve the true residual the FP32
+      // operator error is too large for this problem and the inner solves go to FP64
+      if (outer >= 2 && rel > 0.5 * prev_rel) inner_f32 = false;
+      prev_rel = rel;
+      // inner: A d = ro to a relative tolerance (never tighter than needed)
+      const double t_in = inner_f32 ? std::max(itol, 0.3 * P.tol / rel) : 0.3 * P.tol / rel;
       HIPCHK(ctx, hipMemsetAsync(dv, 0, 8 * N, s));
       KrylovResult ir;
       if (P.solver == WH_GMRES) {
-        WHCHK(gmres_solve(S, true, ro, dv, false, r, at<double>(ws, L.basis), restart, t_in,
+        WHCHK(gmres_solve(S, inner_f32, ro, dv, false, r, at<double>(ws, L.basis), restart, t_in,
                           P.max_iters - inner_total, ir));
       } else {
-        WHCHK(cg_solve(S, true, ro, dv, false, r, p, q, t_in, P.max_iters - inner_total,
-                       P.solver == WH_DCG, reproject, P.check_every, ir));
+        WHCHK(cg_solve(S, inner_f32, ro, dv, false, r, p, q, t_in, P.max_iters - inner_total,
+                       P.solver == WH_DCG, reproject, P.check_every, ir, inner_f32));
       }
       inner_total += ir.iters;
+      if (ir.diverged) {       // discard the sweep and redo it in FP64
+        inner_f32 = false;
+        continue;
+      }
       launch_axpy(u, dv, 1.0, N, s);
       nonzero = true;
     }

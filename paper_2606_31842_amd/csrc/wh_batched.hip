@@ -3,17 +3,17 @@
 //
 // Every problem runs the same method as wh_solve (the filter of eq. WaveHoltzDiscreteFPI
 // applied by the leapfrog scheme with the trapezoid sum, and CG on A = I - S_h,
-// Algorithm 3 without deflation; in mixed precision an FP64 outer residual around
-// FP32-stepped inner CG solves).  Instead of host-driven loops, each problem keeps
+// Algorithm 3 without deflation; in mixed precision the CG recurrence applies the
+// FP32-stepped operator and its residual is replaced by the true FP64 residual each
+// time it has dropped tenfold).  Instead of host-driven loops, each problem keeps
 // its phase, time-step counter and Krylov scalars in device memory:
 //
 //   B_FIRST -> B_STEP* -> B_LAST         b = Pi_h(0; f)                        (FP64)
-//   INIT                                 r = p = rhs, d = 0
+//   INIT                                 r = p = b
 //   A_FIRST -> A_STEP* -> A_LAST         q = A p, partial sums of p.q          (CG precision)
-//   UPD1                                 y += alpha p, r -= alpha q, partial r.r
+//   UPD1                                 x += alpha p, r -= alpha q, partial r.r
+//   R_FIRST -> R_STEP* -> R_LAST         r = b - A x, partial r.r              (FP64)
 //   UPD2                                 p = r + beta p            -> A_FIRST
-//   ADD_D                                x += d                    (mixed only)
-//   R_FIRST -> R_STEP* -> R_LAST         ro = b - A x, partial ro.ro          (FP64)
 //
 // One round = FP64 work kernel + FP32 work kernel + control kernel.  A work kernel
 // covers every tile of every problem (a static block -> (problem, tile) table laid
@@ -39,15 +39,14 @@ enum BPhase : int {
   BP_INIT,
   BP_A_FIRST, BP_A_STEP, BP_A_LAST,
   BP_UPD1, BP_UPD2,
-  BP_ADD_D,
   BP_R_FIRST, BP_R_STEP, BP_R_LAST,
   BP_DONE
 };
 
 struct BDesc {
-  int n, nt, ntx, nty, tile0, mixed, max_iters, max_outer;
-  double a, tol, itol;
-  double *x, *b, *r, *p, *q, *ro, *d, *V;
+  int n, nt, ntx, nty, tile0, mixed, max_iters, max_outer, defect, pad0;
+  double a, tol, itol, om2dt2;   // om2dt2 = (omega dt)^2 of the fixed point
+  double *x, *b, *r, *p, *q, *V;
   void* W[4];                 // FP64 (prev, cur) pairs 0 and 1; 8 bytes per node each
   void* W32[4];               // FP32 pairs (mixed only): the FP32 view of W[] would alias
                               // boundary nodes onto halves of interior doubles
@@ -61,13 +60,15 @@ struct BDesc {
 };
 
 struct BState {
-  int phase, step, pair, iters, outer, status, inner, pad;
-  double r2, rhs2, nb2, alpha, beta, rel, itol, pq;
+  int phase, step, pair, iters, outer, status, stalls, force64, last_repl, pad_[3];
+  double r2, rhs2, nb2, alpha, beta, rel, itol, pq, prev_rel, it64;  // it64: FP64 inner iterations
 };
 
+// Stepping precision of a phase: 1 = FP32 (inner CG of a mixed problem that has not
+// fallen back to FP64), 0 = FP64 (everything else, including element-wise phases).
 __device__ __forceinline__ int phase_prec(int ph, int mixed) {
   if (ph == BP_A_FIRST || ph == BP_A_STEP || ph == BP_A_LAST) return mixed ? 1 : 0;
-  return 0;  // FP64 stepping phases and the element-wise phases
+  return 0;
 }
 
 __device__ __forceinline__ int xcd_tile_b(int bid, int nb) {
@@ -118,8 +119,8 @@ __global__ __launch_bounds__(256) void k_batch_work(const BDesc* __restrict__ de
   const BDesc& D = descs[sid];
   const int ph = states[sid].phase;
   if (ph == BP_DONE) return;
-  const int prec = phase_prec(ph, D.mixed);
-  const bool stepping = ph != BP_INIT && ph != BP_UPD1 && ph != BP_UPD2 && ph != BP_ADD_D;
+  const int prec = phase_prec(ph, D.mixed && !states[sid].force64);
+  const bool stepping = ph != BP_INIT && ph != BP_UPD1 && ph != BP_UPD2;
   if (want == 1 && !(stepping && prec == 1)) return;
   if (want == 0 && stepping && prec == 1) return;
   const int n = D.n;
@@ -141,17 +142,15 @@ __global__ __launch_bounds__(256) void k_batch_work(const BDesc* __restrict__ de
 
   switch (ph) {
     case BP_INIT: {
-      const double* rhs = (D.mixed && S.outer > 0) ? D.ro : D.b;
       TILE_FOR(p) {
-        const double v = rhs[p];
+        const double v = D.b[p];
         D.r[p] = v;
         D.p[p] = v;
-        if (D.mixed) D.d[p] = 0.0;
       }
       break;
     }
     case BP_UPD1: {
-      double* y = D.mixed ? D.d : D.x;
+      double* y = D.x;
       const double al = S.alpha;
       reduce = true;
       TILE_FOR(p) {
@@ -167,12 +166,33 @@ __global__ __launch_bounds__(256) void k_batch_work(const BDesc* __restrict__ de
       TILE_FOR(p) { D.p[p] = D.r[p] + be * D.p[p]; }
       break;
     }
-    case BP_ADD_D: {
-      TILE_FOR(p) { D.x[p] += D.d[p]; }
-      break;
-    }
-    case BP_B_FIRST:
     case BP_A_FIRST:
+      if (sizeof(T) == 4 && D.defect) {
+        // FP32 inner operator in the defect form A p = Pi_h(0; H p): forcing
+        // fs = -dt^2 H p, W^0 = 0, W^1 = -fs/2, V = w1 W^1
+        T* w0o = state_of<T>(D, 0);
+        T* w1o = state_of<T>(D, 1);
+        T* fso = (T*)D.fs32;
+        TILE_FOR(p) {
+          const int i = (int)(p % P), j = (int)(p / P);
+          const double pc = D.p[p];
+          const double nbv[4] = {i > 1 ? D.p[p - 1] : 0.0, i < n - 1 ? D.p[p + 1] : 0.0,
+                                 j > 1 ? D.p[p - P] : 0.0, j < n - 1 ? D.p[p + P] : 0.0};
+          const int64_t nbi[4] = {p - 1, p + 1, p - P, p + P};
+          double lap = 0.0;
+          for (int t = 0; t < 4; ++t)
+            lap += (VARC ? D.kap64[p] + D.kap64[nbi[t]] : D.a) * (nbv[t] - pc);
+          const T fsv = (T)(-(lap + D.om2dt2 * pc));
+          fso[p] = fsv;
+          const T w1 = T(-0.5) * fsv;
+          w0o[p] = T(0);
+          w1o[p] = w1;
+          D.V[p] = D.w[1] * (double)w1;
+        }
+        break;
+      }
+      [[fallthrough]];
+    case BP_B_FIRST:
     case BP_R_FIRST: {
       // W^0 = src (B: zero), W^1 = W^0 + dt^2/2 (L_h W^0 - f), V = w0 W^0 + w1 W^1
       const double* src = ph == BP_A_FIRST ? D.p : (ph == BP_R_FIRST ? D.x : nullptr);
@@ -217,24 +237,24 @@ __global__ __launch_bounds__(256) void k_batch_work(const BDesc* __restrict__ de
       const int k = D.nt - 1;
       const double wn = D.w[k + 1];
       const T cn = (T)D.cosv[k];
+      const bool defect = sizeof(T) == 4 && D.defect && ph == BP_A_LAST;
       reduce = true;
       TILE_FOR(p) {
         T nw = (cur[p] + cur[p]) - prv[p] + lap_term<T, VARC>(cur, kap, p, P, A);
-        if (ph == BP_B_LAST) nw -= cn * fs[p];
+        if (ph == BP_B_LAST || defect) nw -= cn * fs[p];
         const double vf = D.V[p] + wn * (double)nw;
         if (ph == BP_B_LAST) {
           D.b[p] = vf;
           acc += vf * vf;
         } else if (ph == BP_A_LAST) {
           const double pv = D.p[p];
-          const double qv = pv - vf;
+          const double qv = defect ? -vf : pv - vf;
           D.q[p] = qv;
           acc += pv * qv;
         } else {
-          // ro exists only in mixed precision; an FP64 batch takes this residual once,
-          // after CG has finished with r, so r holds it
+          // true residual b - A x replaces r (FP64 batches take it once, at the end)
           const double rv = D.b[p] - (D.x[p] - vf);
-          (D.mixed ? D.ro : D.r)[p] = rv;
+          D.r[p] = rv;
           acc += rv * rv;
         }
       }
@@ -245,7 +265,7 @@ __global__ __launch_bounds__(256) void k_batch_work(const BDesc* __restrict__ de
     case BP_R_STEP: {
       // K' <= K fused steps on a register tile (see k_fused2d)
       const int Kp = min(K, D.nt - 1 - S.step);
-      const bool force = ph == BP_B_STEP;
+      const bool force = ph == BP_B_STEP || (sizeof(T) == 4 && D.defect && ph == BP_A_STEP);
       const int pr = S.pair;
       const T* cin = state_of<T>(D, 2 * pr + 1);
       const T* pin = state_of<T>(D, 2 * pr);
@@ -385,6 +405,7 @@ __global__ __launch_bounds__(256) void k_batch_control(const BDesc* __restrict__
     case BP_R_STEP: after_step(BP_R_LAST); break;
     case BP_B_LAST:
       S.nb2 = sum;
+      S.prev_rel = 1.0;
       if (!(sum > 0)) {         // f = 0: u = 0 is the solution
         S.rel = 0.0;
         S.status = WH_OK;
@@ -399,9 +420,8 @@ __global__ __launch_bounds__(256) void k_batch_control(const BDesc* __restrict__
       }
       break;
     case BP_INIT:
-      S.r2 = S.rhs2;
-      S.inner = 0;
-      S.itol = D.mixed ? fmax(D.itol, 0.3 * D.tol / S.rel) : D.tol;
+      S.r2 = S.nb2;
+      S.prev_rel = 1.0;       // relative true residual at the last replacement
       S.phase = BP_A_FIRST;
       break;
     case BP_A_LAST:
@@ -418,52 +438,66 @@ __global__ __launch_bounds__(256) void k_batch_control(const BDesc* __restrict__
       }
       break;
     case BP_UPD1: {
-      S.beta = sum / S.r2;
+      const double r2_old = S.r2;
+      S.beta = sum / r2_old;
       S.r2 = sum;
       S.iters++;
-      S.inner++;
-      const double rel_in = sqrt(sum / S.rhs2);
-      const bool conv = rel_in <= S.itol;
+      if (D.mixed && S.force64) S.it64 += 1.0;
+      const double rel = sqrt(sum / S.nb2);
       const bool cap = S.iters >= D.max_iters;
-      if (!isfinite(rel_in)) {
+      S.rel = rel;
+      if (!isfinite(rel)) {
         S.status = WH_EUNSTABLE;
         S.phase = BP_DONE;
       } else if (!D.mixed) {
-        S.rel = rel_in;
-        if (conv || cap) {
-          S.status = conv ? WH_OK : WH_ENOCONV;
-          S.phase = BP_R_FIRST;          // true FP64 residual for the report
+        if (rel <= D.tol || cap) {
+          S.status = rel <= D.tol ? WH_OK : WH_ENOCONV;
+          S.phase = BP_R_FIRST;        // true FP64 residual for the report
         } else {
           S.phase = BP_UPD2;
         }
+      } else if (rel <= 0.1 * S.prev_rel || rel >= 10.0 * S.prev_rel || rel <= D.tol || cap ||
+                 S.iters - S.last_repl >= 500) {
+        S.pq = r2_old;                 // kept for beta after the replacement
+        S.phase = BP_R_FIRST;
       } else {
-        S.phase = (conv || cap) ? BP_ADD_D : BP_UPD2;
+        S.phase = BP_UPD2;
       }
       break;
     }
     case BP_UPD2: S.phase = BP_A_FIRST; break;
-    case BP_ADD_D: S.phase = BP_R_FIRST; break;
     case BP_R_LAST: {
       const double rel = sqrt(sum / S.nb2);
       S.outer++;
       if (!D.mixed) {
-        S.pq = rel;                      // true residual (status already set)
+        S.pq = rel;                    // true residual (status already set)
+        S.phase = BP_DONE;
+        break;
+      }
+      // residual replacement: beta from the true residual, the recurrence continues
+      S.beta = sum / S.pq;
+      S.r2 = sum;
+      S.rel = rel;
+      S.stalls = rel > 0.5 * S.prev_rel ? S.stalls + 1 : 0;
+      S.last_repl = S.iters;
+      if (S.stalls >= 2 && !S.force64) {
+        // the FP32 operator error dominates: continue in FP64, restarting the
+        // recurrence from the true residual (p = r)
+        S.force64 = 1;
+        S.beta = 0.0;
+      }
+      S.prev_rel = rel;
+      if (!isfinite(rel)) {
+        S.status = WH_EUNSTABLE;
+        S.phase = BP_DONE;
+      } else if (rel <= D.tol) {
+        S.status = WH_OK;
+        S.phase = BP_DONE;
+      } else if (S.iters >= D.max_iters) {
+        S.status = WH_ENOCONV;
         S.phase = BP_DONE;
       } else {
-        S.rel = rel;
-        if (rel <= D.tol) {
-          S.status = WH_OK;
-          S.phase = BP_DONE;
-        } else if (!isfinite(rel)) {
-          S.status = WH_EUNSTABLE;
-          S.phase = BP_DONE;
-        } else if (S.outer > D.max_outer || S.iters >= D.max_iters) {
-          S.status = WH_ENOCONV;
-          S.phase = BP_DONE;
-        } else {
-          S.rhs2 = sum;
-          S.phase = BP_INIT;
-        }
+        S.phase = BP_UPD2;
       }
       break;
     }
@@ -531,7 +565,7 @@ static size_t take_b(BatchLayout& L, size_t bytes) {
   return o;
 }
 
-// per problem: 4 state arrays + V, b, r, p, q (+ ro, d mixed) (8N each), kap64/fs64 (8N),
+// per problem: 4 state arrays + V, b, r, p, q (8N each), FP32 states (4 x 4N, mixed), kap64/fs64 (8N),
 // kap32/fs32 (4N, mixed), partials (tiles), weights 2(N_t+1)
 static size_t problem_bytes(int n, int nt, int K, bool mixed, bool varc) {
   const size_t N = (size_t)(n + 1) * (n + 1);
@@ -540,7 +574,6 @@ static size_t problem_bytes(int n, int nt, int K, bool mixed, bool varc) {
   for (int i = 0; i < 4; ++i) add(8 * N);
   if (mixed) for (int i = 0; i < 4; ++i) add(4 * N);
   for (int i = 0; i < 5; ++i) add(8 * N);
-  if (mixed) { add(8 * N); add(8 * N); }
   if (varc) add(8 * N);
   add(8 * N);
   if (mixed) { if (varc) add(4 * N); add(4 * N); }
@@ -677,6 +710,8 @@ wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
     d.a = tps[i].dt * tps[i].dt / (h * h);
     d.tol = params->tol;
     d.itol = params->inner_tol > 0 ? params->inner_tol : 1e-3;
+    d.defect = params->mixed_form != 1;
+    d.om2dt2 = 4.0 * std::sin(0.5 * tps[i].omega_w * tps[i].dt) * std::sin(0.5 * tps[i].omega_w * tps[i].dt);
     for (int k = 0; k < 4; ++k) d.W[k] = take(8 * N);
     if (mixed)
       for (int k = 0; k < 4; ++k) d.W32[k] = take(4 * N);
@@ -685,10 +720,6 @@ wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
     d.r = (double*)take(8 * N);
     d.p = (double*)take(8 * N);
     d.q = (double*)take(8 * N);
-    if (mixed) {
-      d.ro = (double*)take(8 * N);
-      d.d = (double*)take(8 * N);
-    }
     d.x = probs[i].u;
     double* kap64 = varc ? (double*)take(8 * N) : nullptr;
     double* fs64 = (double*)take(8 * N);
@@ -728,7 +759,6 @@ wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
     if (mixed)
       for (int k = 0; k < 4; ++k) HIPB(ctx, hipMemsetAsync(d.W32[k], 0, 4 * N, s));
     for (double* v : {d.V, d.b, d.r, d.p, d.q}) HIPB(ctx, hipMemsetAsync(v, 0, 8 * N, s));
-    if (mixed) for (double* v : {d.ro, d.d}) HIPB(ctx, hipMemsetAsync(v, 0, 8 * N, s));
     HIPB(ctx, hipMemsetAsync(d.x, 0, 8 * N, s));   // batched solves start from zero
     // weights (staged through the pinned block)
     std::vector<double> tab(2 * (d.nt + 1));
@@ -777,8 +807,8 @@ wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
   long long max_rounds = 0;
   for (int i = 0; i < nb; ++i) {
     const long long per_it = (D[i].nt + K - 1) / K + 6;
-    const long long outer = mixed ? (D[i].max_outer + 1) * (per_it + 4) : per_it + 4;
-    max_rounds = std::max(max_rounds, (long long)D[i].max_iters * per_it + outer + 8 + per_it);
+    // an iteration is at most one A wave solve plus one residual replacement
+    max_rounds = std::max(max_rounds, (long long)D[i].max_iters * 2 * per_it + 2 * per_it + 8);
   }
   const long long max_replays = max_rounds / G + 2;
   long long rep = 0;
@@ -813,8 +843,9 @@ wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
       in.iters = SF[i].iters;
       in.outer = mixed ? SF[i].outer : 0;
       const int wsol = SF[i].iters + SF[i].outer + 1;  // A applies + residual solves + b
-      in.wave_solves = mixed ? SF[i].outer + 1 : wsol;
-      in.wave_solves_f32 = mixed ? SF[i].iters : 0;
+      const int it64 = (int)SF[i].it64;
+      in.wave_solves = mixed ? SF[i].outer + 1 + it64 : wsol;
+      in.wave_solves_f32 = mixed ? SF[i].iters - it64 : 0;
       in.nt = tps[i].nt;
       in.m = tps[i].m;
       in.k_fuse = K;

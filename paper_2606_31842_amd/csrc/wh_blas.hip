@@ -57,6 +57,39 @@ void launch_zero_boundary(double* u, int n, int dim, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_boundary, dim3(grid_for(N)), dim3(kBlock), 0, s, u, n, dim, N);
 }
 
+// Defect forcing for the A-apply in the form A v = Pi_h(0; (L_h + omega^2) v): the
+// scaled forcing array fs = f dt^2 with f = -(L_h + omega^2) v.
+template <typename T>
+__global__ void k_defect(const double* v, const double* kap, double a, double om2dt2, T* fs, int n,
+                         int dim, int64_t N) {
+  const int64_t P = n + 1;
+  GRID_STRIDE(p, N) {
+    int i = (int)(p % P), j = (int)((p / P) % P), k = dim == 3 ? (int)(p / (P * P)) : 1;
+    bool in = i > 0 && i < n && j > 0 && j < n && (dim == 2 || (k > 0 && k < n));
+    if (!in) continue;
+    const int64_t nb[6] = {p - 1, p + 1, p - P, p + P, p - P * P, p + P * P};
+    const bool ins[6] = {i > 1, i < n - 1, j > 1, j < n - 1, k > 1, k < n - 1};
+    const double vc = v[p];
+    double lap = 0.0;
+    for (int t = 0; t < 2 * dim; ++t) {
+      const double vq = ins[t] ? v[nb[t]] : 0.0;
+      lap += (kap ? kap[p] + kap[nb[t]] : a) * (vq - vc);
+    }
+    fs[p] = (T)(-(lap + om2dt2 * vc));
+  }
+}
+
+void launch_defect_forcing(const double* v, const double* kap64, double a, double om2dt2, void* fs,
+                           bool f32, int n, int dim, hipStream_t s) {
+  int64_t P = n + 1, N = dim == 2 ? P * P : P * P * P;
+  if (f32)
+    hipLaunchKernelGGL(k_defect<float>, dim3(grid_for(N)), dim3(kBlock), 0, s, v, kap64, a, om2dt2,
+                       (float*)fs, n, dim, N);
+  else
+    hipLaunchKernelGGL(k_defect<double>, dim3(grid_for(N)), dim3(kBlock), 0, s, v, kap64, a, om2dt2,
+                       (double*)fs, n, dim, N);
+}
+
 // ----------------------------------------------------------------- reductions
 __global__ void k_max_partials(const double* a, int64_t N, double* partials, bool neg) {
   double m = -1.0e308;
@@ -112,6 +145,18 @@ __global__ void k_reduce(const double* partials, int count, double* slots, int d
 void launch_reduce(const double* partials, int count, double* slots, int dst, int mode,
                    hipStream_t s) {
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, partials, count, slots, dst, mode);
+}
+
+// After a residual replacement: beta = slots[src] / r2_old, slots[R2] = slots[src].
+__global__ void k_set_beta(double* slots, int src, double r2_old) {
+  if (threadIdx.x == 0) {
+    slots[S_BETA] = slots[src] / r2_old;
+    slots[S_R2] = slots[src];
+  }
+}
+
+void launch_set_beta(double* slots, int src, double r2_old, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_beta, dim3(1), dim3(64), 0, s, slots, src, r2_old);
 }
 
 // ----------------------------------------------------------------- CG updates

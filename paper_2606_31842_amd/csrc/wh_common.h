@@ -56,7 +56,8 @@ enum StepMode : int {
   M_MID = 1,     // W^{n+1} = 2W^n - W^{n-1} + ...,  V += w W^{n+1}
   M_LAST_V = 2,  // last step, V += w W^{N_t}, state not stored
   M_LAST_AQ = 3, // last step, q = x - (V + w W^{N_t}); partial sums of x.q
-  M_LAST_FPI = 4 // last step, out = V + w W^{N_t}; partial sums of (out - x)^2
+  M_LAST_FPI = 4,// last step, out = V + w W^{N_t}; partial sums of (out - x)^2
+  M_LAST_EQ = 5  // last step of the defect form: out = -(V + w W^{N_t}); partial sums of x.out
 };
 
 struct StepArgs {
@@ -109,6 +110,10 @@ void launch_prep_coeffs(const double* c2, const double* f, void* kap, void* fs, 
                         double kap_scale, double f_scale, int64_t N, int n, int dim,
                         hipStream_t s);
 void launch_zero_boundary(double* u, int n, int dim, hipStream_t s);
+// fs = -(dt^2 L_h + omega^2 dt^2) v at interior nodes (state type); boundary untouched.
+// kap64: c2 dt^2/(2h^2) or NULL (then a = dt^2/h^2 is used).
+void launch_defect_forcing(const double* v, const double* kap64, double a, double om2dt2, void* fs,
+                           bool f32, int n, int dim, hipStream_t s);
 void launch_max_partials(const double* a, int64_t N, double* partials, bool neg, hipStream_t s);
 void launch_max_finalize(const double* partials, int count, double* out, hipStream_t s);
 void launch_dot_partials(const double* a, const double* b, int64_t N, double* partials,
@@ -117,6 +122,7 @@ void launch_dot_partials(const double* a, const double* b, int64_t N, double* pa
 // 2: beta = sum/slot[R2], slot[R2] = sum
 void launch_reduce(const double* partials, int count, double* slots, int dst, int mode,
                    hipStream_t s);
+void launch_set_beta(double* slots, int src, double r2_old, hipStream_t s);
 void launch_cg_update1(double* x, double* r, const double* p, const double* q,
                        const double* slots, int64_t N, double* partials, hipStream_t s);
 void launch_cg_update2(double* p, const double* r, const double* slots, int64_t N,

@@ -35,6 +35,10 @@ __device__ __forceinline__ void step_epilogue(const StepArgs& a, size_t p, T nw,
     double q = xv - vf;
     a.out[p] = q;
     acc += xv * q;
+  } else if (MODE == M_LAST_EQ) {
+    const double q = -(a.V[p] + a.wn * (double)nw);
+    a.out[p] = q;
+    acc += a.x[p] * q;
   } else if (MODE == M_LAST_FPI) {
     // x and out may be the same array: read x before writing out
     double vf = a.V[p] + a.wn * (double)nw;
@@ -88,7 +92,7 @@ __global__ __launch_bounds__(256) void k_step2d(StepArgs a) {
       c = dn;
     }
   }
-  if (MODE == M_LAST_AQ || MODE == M_LAST_FPI) {
+  if (MODE == M_LAST_AQ || MODE == M_LAST_FPI || MODE == M_LAST_EQ) {
     double s = block_sum256(acc, tid);
     if (tid == 0) a.partials[blockIdx.y * gridDim.x + blockIdx.x] = s;
   }
@@ -141,7 +145,7 @@ __global__ __launch_bounds__(256) void k_step3d(StepArgs a) {
       c = fw;
     }
   }
-  if (MODE == M_LAST_AQ || MODE == M_LAST_FPI) {
+  if (MODE == M_LAST_AQ || MODE == M_LAST_FPI || MODE == M_LAST_EQ) {
     double s = block_sum256(acc, tid);
     if (tid == 0)
       a.partials[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
@@ -174,6 +178,13 @@ __global__ __launch_bounds__(256) void k_first(StepArgs a) {
   }
   const double* __restrict__ v = a.vin;
   const T* __restrict__ kap = (const T*)a.kap;
+  if (!v) {  // W^0 = 0
+    const T w1 = FORCE ? T(-0.5) * (T)a.cosn * ((const T*)a.fs)[p] : T(0);
+    w0o[p] = T(0);
+    w1o[p] = w1;
+    a.V[p] = a.wn * (double)w1;
+    return;
+  }
   const T c = (T)v[p];
   const T w = i > 1 ? (T)v[p - 1] : T(0);
   const T e = i < n - 1 ? (T)v[p + 1] : T(0);
@@ -224,6 +235,7 @@ static void dispatch_dim(int dim, StepMode mode, const StepArgs& a, hipStream_t 
       case M_LAST_V: hipLaunchKernelGGL((k_step2d<T, M_LAST_V, VARC, FORCE>), g, b, 0, s, a); break;
       case M_LAST_AQ: hipLaunchKernelGGL((k_step2d<T, M_LAST_AQ, VARC, FORCE>), g, b, 0, s, a); break;
       case M_LAST_FPI: hipLaunchKernelGGL((k_step2d<T, M_LAST_FPI, VARC, FORCE>), g, b, 0, s, a); break;
+      case M_LAST_EQ: hipLaunchKernelGGL((k_step2d<T, M_LAST_EQ, VARC, FORCE>), g, b, 0, s, a); break;
       default: break;
     }
   } else {
@@ -233,6 +245,7 @@ static void dispatch_dim(int dim, StepMode mode, const StepArgs& a, hipStream_t 
       case M_LAST_V: hipLaunchKernelGGL((k_step3d<T, M_LAST_V, VARC, FORCE>), g, b, 0, s, a); break;
       case M_LAST_AQ: hipLaunchKernelGGL((k_step3d<T, M_LAST_AQ, VARC, FORCE>), g, b, 0, s, a); break;
       case M_LAST_FPI: hipLaunchKernelGGL((k_step3d<T, M_LAST_FPI, VARC, FORCE>), g, b, 0, s, a); break;
+      case M_LAST_EQ: hipLaunchKernelGGL((k_step3d<T, M_LAST_EQ, VARC, FORCE>), g, b, 0, s, a); break;
       default: break;
     }
   }
