@@ -192,14 +192,15 @@ def test_A_equals_B_times_helmholtz_operator(dim, n, omega, varc):
 
 
 def test_defect_form_reduces_fp32_error_near_resonance():
-    # FP32 stepping of W versus FP32 stepping of the defect E, on the mode nearest resonance
+    # FP32 stepping of W versus FP32 stepping of the defect E, measured on the coefficient
+    # of the mode nearest resonance (where A's eigenvalue is small and CG is slow)
     n = 64
     lam2 = modes.mode_lam2(2, n, (5, 6))
     omega = np.sqrt(lam2) * (1 - 1e-3)
     L, tp, _ = setup(2, n, omega)
     phi = disc.to_interior(modes.mode_nodal(2, n, (5, 6)))
-    v = phi + 1e-3 * disc.to_interior(wl.random_nodal(2, n, 8))
-    exact = ws.apply_A(L, v, tp)
-    e_w = np.linalg.norm(ws.apply_A(L, v, tp, state_dtype=np.float32) - exact) / np.linalg.norm(exact)
-    e_e = np.linalg.norm(ws.apply_A_defect(L, v, tp, state_dtype=np.float32) - exact) / np.linalg.norm(exact)
-    assert e_e < e_w / 20, (e_e, e_w)
+    v = phi + 0.3 * disc.to_interior(wl.random_nodal(2, n, 8))
+    c = phi @ ws.apply_A(L, v, tp)
+    e_w = abs(phi @ ws.apply_A(L, v, tp, state_dtype=np.float32) - c) / abs(c)
+    e_e = abs(phi @ ws.apply_A_defect(L, v, tp, state_dtype=np.float32) - c) / abs(c)
+    assert e_e < e_w / 5, (e_e, e_w)
