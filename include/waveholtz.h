@@ -211,6 +211,34 @@ size_t wh_workspace_bytes_batched(int32_t nb, const wh_problem* probs, const wh_
 wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
                            const wh_params* params, void* ws, size_t ws_bytes, wh_info* infos);
 
+/* ------------------------------------------------------------------ gradient (2D) */
+/* Workspace for wh_solve_vjp / wh_adjoint_grad (params->c_max > 0 required). */
+size_t wh_workspace_bytes_adjoint(const wh_grid* grid, const wh_params* params, int32_t ckpt_every);
+
+/* grad_c2 += (d Pi_h / d c2)^T A^{-1} grad_u at the fixed point u = Pi_h(u; f, c2): the
+ * vector-Jacobian product of the map c2 -> u (Sections 2.1-2.2: u solves A u = b, so
+ * du/dc2 = A^{-1} dPi_h/dc2).  A^{-1} grad_u is one CG solve (A is symmetric); the
+ * product with (dPi_h/dc2)^T runs the time-reversed, transposed leapfrog recurrence
+ * with the trapezoid weights as its source, recomputing the forward trajectory from
+ * checkpoints kept every ckpt_every steps (0: 16).  2D only; c2 required (device,
+ * nodal); params->c_max must bound c; u, grad_u, f device nodal; grad_c2 device nodal
+ * (all nodes, accumulated).  The time step is held fixed: the fixed point does not
+ * depend on it under the corrected frequency. */
+wh_status wh_solve_vjp(wh_ctx* ctx, const wh_grid* grid, const double* c2, const double* f,
+                       const double* u, const double* grad_u, const wh_params* params,
+                       int32_t ckpt_every, double* grad_c2, void* ws, size_t ws_bytes,
+                       wh_info* info);
+
+/* Receiver misfit J = 1/2 sum_s ||R u_s - d_s||^2 over n_src sources and its gradient
+ * dJ/dc2 (overwrites grad_c2).  f: host array of n_src device source pointers;
+ * rec_idx: device array of n_rec nodal linear indices (interior nodes, checked);
+ * d: device n_src x n_rec data; J: host.  Each source costs two CG solves and one
+ * checkpointed reverse sweep. */
+wh_status wh_adjoint_grad(wh_ctx* ctx, const wh_grid* grid, const double* c2, int32_t n_src,
+                          const double* const* f, int32_t n_rec, const int64_t* rec_idx,
+                          const double* d, const wh_params* params, int32_t ckpt_every,
+                          double* grad_c2, double* J, void* ws, size_t ws_bytes, wh_info* info);
+
 /* Measurement helper: the average duration in microseconds of one launch of the
  * time-stepping kernel that wh_apply_filter / wh_solve would use for these
  * arguments (the K-step temporally blocked kernel, or the single-step kernel when

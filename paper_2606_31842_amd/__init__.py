@@ -293,3 +293,96 @@ def solve_batched(problems, workspace=None, **kw):
     st = lib.wh_solve_batched(ctx, nb, arr, C.byref(p), _ptr(ws), ws.numel(), infos)
     _check(lib, ctx, st)
     return outs, [infos[i].as_dict() for i in range(nb)]
+
+
+def solve_vjp(u, grad_u, f, omega, c2, ckpt_every=16, grad_c2=None, **kw):
+    """grad_c2 (+)= (dPi_h/dc2)^T A^{-1} grad_u at the fixed point u (wh_solve_vjp)."""
+    torch = _torch()
+    n = u.shape[0] - 1
+    for t, nm in ((u, "u"), (grad_u, "grad_u"), (f, "f"), (c2, "c2")):
+        _nodal(t, 2, n, nm)
+    lib = nat.load()
+    ctx = context(u.device.index)
+    if "c_max" not in kw:
+        kw["c_max"] = float(torch.sqrt(c2.max()).item())
+    p = params(omega, **kw)
+    g = _grid(2, n)
+    need = lib.wh_workspace_bytes_adjoint(C.byref(g), C.byref(p), int(ckpt_every))
+    if need == 0:
+        raise WaveHoltzError(-1, "invalid arguments for the adjoint workspace")
+    ws = _workspace(need)
+    out = torch.zeros_like(u) if grad_c2 is None else _nodal(grad_c2, 2, n, "grad_c2")
+    info = nat.WhInfo()
+    st = lib.wh_solve_vjp(ctx, C.byref(g), _ptr(c2), _ptr(f), _ptr(u), _ptr(grad_u), C.byref(p),
+                          int(ckpt_every), _ptr(out), _ptr(ws), ws.numel(), C.byref(info))
+    _check(lib, ctx, st)
+    return out, info.as_dict()
+
+
+def adjoint_grad(c2, sources, rec_idx, data, omega, ckpt_every=16, **kw):
+    """(J, dJ/dc2, info) for J = 1/2 sum_s ||R u_s - d_s||^2 (wh_adjoint_grad)."""
+    torch = _torch()
+    n = c2.shape[0] - 1
+    _nodal(c2, 2, n, "c2")
+    lib = nat.load()
+    ctx = context(c2.device.index)
+    if "c_max" not in kw:
+        kw["c_max"] = float(torch.sqrt(c2.max()).item())
+    p = params(omega, **kw)
+    g = _grid(2, n)
+    srcs = [_nodal(f, 2, n, "source") for f in sources]
+    fptr = (C.c_void_p * len(srcs))(*[f.data_ptr() for f in srcs])
+    idx = rec_idx.to(device=c2.device, dtype=torch.int64).contiguous()
+    d = data.to(device=c2.device, dtype=torch.float64).contiguous()
+    assert d.shape == (len(srcs), idx.numel())
+    need = lib.wh_workspace_bytes_adjoint(C.byref(g), C.byref(p), int(ckpt_every))
+    if need == 0:
+        raise WaveHoltzError(-1, "invalid arguments for the adjoint workspace")
+    ws = _workspace(need)
+    grad = torch.empty_like(c2)
+    J = C.c_double()
+    info = nat.WhInfo()
+    st = lib.wh_adjoint_grad(ctx, C.byref(g), _ptr(c2), len(srcs), fptr, idx.numel(), _ptr(idx), _ptr(d),
+                             C.byref(p), int(ckpt_every), _ptr(grad), C.byref(J), _ptr(ws), ws.numel(),
+                             C.byref(info))
+    _check(lib, ctx, st)
+    return J.value, grad, info.as_dict()
+
+
+class WaveHoltzSolve:
+    """torch.autograd.Function wrapper: u = WaveHoltzSolve.apply(f, c2, omega, kwargs)
+    solves the 2D Helmholtz problem with the library; backward gives
+    dL/df = H^{-1} dL/du (one more solve, H = L_h + omega^2 is symmetric) and
+    dL/dc2 = (dPi_h/dc2)^T A^{-1} dL/du (wh_solve_vjp)."""
+
+    @staticmethod
+    def _fn():
+        import torch
+
+        class _F(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx_, f, c2, omega, opts):
+                u, _ = solve(f, omega, c2=c2, **opts)
+                ctx_.save_for_backward(f, c2, u)
+                ctx_.omega = omega
+                ctx_.opts = opts
+                return u
+
+            @staticmethod
+            def backward(ctx_, gu):
+                f, c2, u = ctx_.saved_tensors
+                gu = gu.contiguous()
+                opts = {k: v for k, v in ctx_.opts.items() if k != "defl"}
+                gf = gc2 = None
+                if ctx_.needs_input_grad[0]:
+                    gf, _ = solve(gu, ctx_.omega, c2=c2, **ctx_.opts)
+                if ctx_.needs_input_grad[1]:
+                    gc2, _ = solve_vjp(u, gu, f, ctx_.omega, c2, **{k: v for k, v in opts.items()
+                                                                   if k not in ("solver",)})
+                return gf, gc2, None, None
+
+        return _F
+
+    @classmethod
+    def apply(cls, f, c2, omega, opts=None):
+        return cls._fn().apply(f, c2, omega, opts or {})

@@ -78,6 +78,12 @@ _SIGS = {
 
 # entry points added as they are built (declared in include/waveholtz.h)
 _OPTIONAL = {
+    "wh_workspace_bytes_adjoint": (C.c_size_t, [P(WhGrid), P(WhParams), C.c_int32]),
+    "wh_solve_vjp": (C.c_int, [C.c_void_p, P(WhGrid), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                               P(WhParams), C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t, P(WhInfo)]),
+    "wh_adjoint_grad": (C.c_int, [C.c_void_p, P(WhGrid), C.c_void_p, C.c_int32, P(C.c_void_p), C.c_int32,
+                                  C.c_void_p, C.c_void_p, P(WhParams), C.c_int32, C.c_void_p,
+                                  P(C.c_double), C.c_void_p, C.c_size_t, P(WhInfo)]),
     "wh_workspace_bytes_batched": (C.c_size_t, [C.c_int32, P(WhProblem), P(WhParams)]),
     "wh_solve_batched": (C.c_int, [C.c_void_p, C.c_int32, P(WhProblem), P(WhParams), C.c_void_p, C.c_size_t,
                                    P(WhInfo)]),

@@ -8,13 +8,14 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwaveholtz.so")
-SOURCES = ["wh_stencil.hip", "wh_fused.hip", "wh_blas.hip", "wh_batched.hip", "wh_api.hip"]
+SOURCES = ["wh_stencil.hip", "wh_fused.hip", "wh_blas.hip", "wh_batched.hip", "wh_adjoint.hip", "wh_api.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
+    "-Wl,--no-undefined",
 ]
 
 

@@ -1304,4 +1304,275 @@ wh_status wh_time_step_kernel(wh_ctx* ctx, const wh_grid* grid, const double* c2
   return WH_OK;
 }
 
+// ------------------------------------------------------------------ adjoint
+}  // extern "C"
+
+namespace {
+
+struct VjpLayout {
+  Layout L;           // solver part (CG on A)
+  size_t ck = 0, seg = 0, lam = 0, z = 0, g = 0, u = 0, misc = 0, total = 0;
+  int nseg = 0, K = 16, nt = 0;
+};
+
+VjpLayout make_vjp_layout(const wh_grid& g, const wh_params& P0, int ckpt, int nt) {
+  wh_params P = P0;
+  if (P.solver != WH_CG) P.solver = WH_CG;
+  VjpLayout V;
+  V.L = make_layout(g, P, nullptr);
+  V.K = ckpt > 0 ? ckpt : 16;
+  V.nt = nt;
+  V.nseg = (nt + V.K - 1) / V.K;
+  const size_t N = (size_t)V.L.N;
+  size_t off = V.L.total;
+  auto take2 = [&](size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  V.ck = take2(8 * N * 2 * (size_t)V.nseg);
+  V.seg = take2(8 * N * (size_t)(V.K + 1));
+  V.lam = take2(8 * N * 3);
+  V.z = take2(8 * N);
+  V.g = take2(8 * N);
+  V.u = take2(8 * N);
+  V.misc = take2(4096);
+  V.total = off;
+  return V;
+}
+
+// grad += (dPi_h/dc2)^T A^{-1} g at the fixed point u of Pi_h(.; f) (2D, c2 given).
+// g must have a zero boundary; u too.  Uses the solver part of the workspace for
+// the CG solve of A z = g.
+wh_status vjp_core(wh_ctx* ctx, const wh_grid& G, const double* c2, const double* f,
+                   const double* u, double* g, const wh_params& P, void* ws,
+                   const VjpLayout& V, double* grad, wh_info* info) {
+  hipStream_t s = ctx->stream;
+  TimeParams tp;
+  Solver S{};
+  WHCHK(setup_ops(ctx, G, P, c2, f, ws, V.L, tp, S));
+  if (tp.nt != V.nt) WH_FAIL(ctx, WH_EINVAL, "time steps changed between sizing and use");
+  const int64_t N = V.L.N;
+  const int n = G.n;
+  double* z = at<double>(ws, V.z);
+  double* r = at<double>(ws, V.L.r);
+  double* p = at<double>(ws, V.L.p);
+  double* q = at<double>(ws, V.L.q);
+  HIPCHK(ctx, hipMemsetAsync(z, 0, 8 * N, s));
+  for (double* v : {r, p, q}) HIPCHK(ctx, hipMemsetAsync(v, 0, 8 * N, s));
+  HIPCHK(ctx, hipMemsetAsync(S.slots, 0, 8 * (size_t)V.L.nslots, s));
+  // z = A^{-1} g (A symmetric)
+  KrylovResult kr;
+  const bool mixed = P.precision == WH_MIXED;
+  WHCHK(cg_solve(S, mixed, g, z, false, r, p, q, P.tol, P.max_iters, false, false,
+                 P.check_every, kr, false, mixed));
+  if (info) {
+    info->iters += kr.iters;
+    info->rel_res = std::max(info->rel_res, kr.rel);
+  }
+  const double* kap = (const double*)S.op64.kap;   // c2 dt^2 / (2 h^2), FP64
+  const double* fs = (const double*)S.op64.fs;     // f dt^2
+  double* ck = at<double>(ws, V.ck);
+  double* seg = at<double>(ws, V.seg);
+  double* lamb = at<double>(ws, V.lam);
+  for (size_t o : {V.seg, V.lam}) HIPCHK(ctx, hipMemsetAsync(at<void>(ws, o), 0,
+                                                           8 * (size_t)N * (o == V.seg ? V.K + 1 : 3), s));
+  HIPCHK(ctx, hipMemsetAsync(ck, 0, 8 * (size_t)N * 2 * V.nseg, s));
+  const int K = V.K, NT = tp.nt;
+  auto CK = [&](int j, int w) { return ck + ((size_t)2 * j + w) * N; };
+  auto SEG = [&](int m) { return seg + (size_t)m * N; };
+  // forward pass from W^0 = u with the forcing, keeping (W^{jK}, W^{jK+1})
+  {
+    // three rotating slots of the segment buffer (K >= 2): bufs[m % 3] holds W^m
+    double* bufs[3] = {SEG(0), SEG(1), SEG(2)};
+    HIPCHK(ctx, hipMemcpyAsync(bufs[0], u, 8 * N, hipMemcpyDeviceToDevice, s));
+    launch_fwd_out2d(bufs[0], nullptr, bufs[1], kap, fs, tp.cosv[0], true, n, s);
+    for (int m = 0; m < NT; ++m) {
+      if (m >= 2) launch_fwd_out2d(bufs[(m - 1) % 3], bufs[(m - 2) % 3], bufs[m % 3], kap, fs,
+                                   tp.cosv[m - 1], false, n, s);
+      if (m % K == 0)
+        HIPCHK(ctx, hipMemcpyAsync(CK(m / K, 0), bufs[m % 3], 8 * N, hipMemcpyDeviceToDevice, s));
+      if (m % K == 1)
+        HIPCHK(ctx, hipMemcpyAsync(CK(m / K, 1), bufs[m % 3], 8 * N, hipMemcpyDeviceToDevice, s));
+    }
+  }
+  // reverse sweep
+  double* L0 = lamb;          // Lam^n (output)
+  double* L1 = lamb + N;      // Lam^{n+1}
+  double* L2 = lamb + 2 * N;  // Lam^{n+2}
+  HIPCHK(ctx, hipMemsetAsync(lamb, 0, 8 * (size_t)N * 3, s));
+  launch_axpy(L1, z, tp.w[NT], N, s);  // Lam^N = w_N z
+  const double h = 1.0 / n;
+  const double gscale = -tp.dt * tp.dt / (2.0 * h * h);
+  for (int j = V.nseg - 1; j >= 0; --j) {
+    const int n0 = j * K, n1 = std::min(n0 + K, NT);
+    HIPCHK(ctx, hipMemcpyAsync(SEG(0), CK(j, 0), 8 * N, hipMemcpyDeviceToDevice, s));
+    if (n1 - n0 >= 2)
+      HIPCHK(ctx, hipMemcpyAsync(SEG(1), CK(j, 1), 8 * N, hipMemcpyDeviceToDevice, s));
+    for (int m = 2; m < n1 - n0; ++m)
+      launch_fwd_out2d(SEG(m - 1), SEG(m - 2), SEG(m), kap, fs, tp.cosv[n0 + m - 1], false, n, s);
+    for (int nn = n1 - 1; nn >= n0; --nn) {
+      const double* W = SEG(nn - n0);
+      if (nn >= 1) {
+        launch_adj_step2d(L1, L2, L0, W, kap, z, tp.w[nn], gscale, grad, true, n, s);
+        double* t = L2;
+        L2 = L1;
+        L1 = L0;
+        L0 = t;
+      } else {
+        launch_adj_step2d(L1, L2, L0, W, kap, z, 0.0, 0.5 * gscale, grad, false, n, s);
+      }
+    }
+  }
+  HIPCHK(ctx, hipGetLastError());
+  if (info) {
+    fill_info(info, tp, 1);
+    info->wave_solves += S.ws64 + 3;
+    info->wave_solves_f32 += S.ws32;
+  }
+  return WH_OK;
+}
+
+wh_status adjoint_validate(wh_ctx* ctx, const wh_grid* grid, const double* c2, const wh_params* P,
+                           int ckpt) {
+  WHCHK(check_grid(ctx, grid));
+  WHCHK(check_params(ctx, grid, P));
+  if (grid->dim != 2) WH_FAIL(ctx, WH_EUNSUPPORTED, "the adjoint gradient is built for 2D grids");
+  if (!c2) WH_FAIL(ctx, WH_EINVAL, "c2 is required (the gradient is taken with respect to it)");
+  if (ckpt < 0 || ckpt == 1 || ckpt > 4096)
+    WH_FAIL(ctx, WH_EINVAL, "ckpt_every must be 0 (default 16) or in [2, 4096]");
+  if (!(P->tol > 0)) WH_FAIL(ctx, WH_EINVAL, "tol must be > 0");
+  return WH_OK;
+}
+
+// N_t needs c_max: the caller's bound, else computed on the device from c2.
+wh_status adjoint_nt(wh_ctx* ctx, const wh_grid& G, const double* c2, const wh_params& P,
+                     void* ws, int* nt) {
+  double cmax = P.c_max;
+  if (!(cmax > 0)) {
+    if (!ctx || !ws) return WH_EINVAL;
+    const int64_t N = nodal_count(G.dim, G.n);
+    double* part = at<double>(ws, 0);
+    launch_max_partials(c2, N, part, false, ctx->stream);
+    launch_max_finalize(part, kReduceBlocks, part + kReduceBlocks, ctx->stream);
+    WHCHK(readback(ctx, part + kReduceBlocks, 1));
+    cmax = std::sqrt(ctx->hbuf[0]);
+  }
+  TimeParams tp;
+  WHCHK(make_time_params(ctx, G.dim, G.n, P, cmax, tp));
+  *nt = tp.nt;
+  return WH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t wh_workspace_bytes_adjoint(const wh_grid* grid, const wh_params* params, int32_t ckpt_every) {
+  if (!grid || !params || check_grid(nullptr, grid) != WH_OK || grid->dim != 2) return 0;
+  if (!(params->c_max > 0)) return 0;
+  TimeParams tp;
+  if (make_time_params(nullptr, 2, grid->n, *params, params->c_max, tp) != WH_OK) return 0;
+  return make_vjp_layout(*grid, *params, ckpt_every, tp.nt).total;
+}
+
+wh_status wh_solve_vjp(wh_ctx* ctx, const wh_grid* grid, const double* c2, const double* f,
+                       const double* u, const double* grad_u, const wh_params* params,
+                       int32_t ckpt_every, double* grad_c2, void* ws, size_t ws_bytes,
+                       wh_info* info) {
+  if (!ctx) return WH_EINVAL;
+  const double t0 = now_ms();
+  if (info) std::memset(info, 0, sizeof(*info));
+  WHCHK(adjoint_validate(ctx, grid, c2, params, ckpt_every));
+  if (!f || !u || !grad_u || !grad_c2) WH_FAIL(ctx, WH_EINVAL, "NULL argument");
+  if (!(params->c_max > 0)) WH_FAIL(ctx, WH_EINVAL, "params->c_max must bound c (sizes the workspace)");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  int nt = 0;
+  WHCHK(adjoint_nt(ctx, *grid, c2, *params, nullptr, &nt));
+  const VjpLayout V = make_vjp_layout(*grid, *params, ckpt_every, nt);
+  WHCHK(check_ws(ctx, ws, ws_bytes, V.total));
+  const int64_t N = V.L.N;
+  double* g = at<double>(ws, V.g);
+  double* uu = at<double>(ws, V.u);
+  HIPCHK(ctx, hipMemcpyAsync(g, grad_u, 8 * N, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(ctx, hipMemcpyAsync(uu, u, 8 * N, hipMemcpyDeviceToDevice, ctx->stream));
+  launch_zero_boundary(g, grid->n, 2, ctx->stream);
+  launch_zero_boundary(uu, grid->n, 2, ctx->stream);
+  WHCHK(vjp_core(ctx, *grid, c2, f, uu, g, *params, ws, V, grad_c2, info));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  if (info) info->ms = now_ms() - t0;
+  return WH_OK;
+}
+
+wh_status wh_adjoint_grad(wh_ctx* ctx, const wh_grid* grid, const double* c2, int32_t n_src,
+                          const double* const* f, int32_t n_rec, const int64_t* rec_idx,
+                          const double* d, const wh_params* params, int32_t ckpt_every,
+                          double* grad_c2, double* J, void* ws, size_t ws_bytes, wh_info* info) {
+  if (!ctx) return WH_EINVAL;
+  const double t0 = now_ms();
+  if (info) std::memset(info, 0, sizeof(*info));
+  WHCHK(adjoint_validate(ctx, grid, c2, params, ckpt_every));
+  if (n_src < 1 || !f || n_rec < 1 || !rec_idx || !d || !grad_c2 || !J)
+    WH_FAIL(ctx, WH_EINVAL, "need n_src >= 1 sources, n_rec >= 1 receivers and outputs");
+  for (int s_ = 0; s_ < n_src; ++s_)
+    if (!f[s_]) WH_FAIL(ctx, WH_EINVAL, "source %d is NULL", s_);
+  if (!(params->c_max > 0)) WH_FAIL(ctx, WH_EINVAL, "params->c_max must bound c (sizes the workspace)");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  int nt = 0;
+  WHCHK(adjoint_nt(ctx, *grid, c2, *params, nullptr, &nt));
+  const VjpLayout V = make_vjp_layout(*grid, *params, ckpt_every, nt);
+  WHCHK(check_ws(ctx, ws, ws_bytes, V.total));
+  const int64_t N = V.L.N;
+  // receivers: interior nodes only, checked before any read through them
+  int* bad = at<int>(ws, V.misc);
+  HIPCHK(ctx, hipMemsetAsync(bad, 0, 4, s));
+  launch_check_idx(rec_idx, n_rec, grid->n, bad, s);
+  HIPCHK(ctx, hipMemcpyAsync(ctx->hbuf, bad, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  int badv = 0;
+  std::memcpy(&badv, ctx->hbuf, 4);
+  if (badv) WH_FAIL(ctx, WH_EINVAL, "receiver indices must be interior nodes of the grid");
+  HIPCHK(ctx, hipMemsetAsync(grad_c2, 0, 8 * N, s));
+  double* u = at<double>(ws, V.u);
+  double* g = at<double>(ws, V.g);
+  double* jslot = at<double>(ws, V.misc) + 8;
+  wh_params P = *params;
+  P.solver = WH_CG;
+  double Jsum = 0.0;
+  wh_status worst = WH_OK;
+  for (int si = 0; si < n_src; ++si) {
+    wh_info in{};
+    HIPCHK(ctx, hipMemsetAsync(u, 0, 8 * N, s));
+    wh_status st = wh_solve(ctx, grid, c2, f[si], nullptr, &P, u, ws, V.L.total, &in);
+    if (st < 0) return st;
+    if (st == WH_ENOCONV) worst = WH_ENOCONV;
+    HIPCHK(ctx, hipMemsetAsync(g, 0, 8 * N, s));
+    launch_misfit(u, rec_idx, d + (size_t)si * n_rec, n_rec, g, jslot, s);
+    WHCHK(readback(ctx, jslot, 1));
+    Jsum += ctx->hbuf[0];
+    wh_info vi{};
+    WHCHK(vjp_core(ctx, *grid, c2, f[si], u, g, P, ws, V, grad_c2, &vi));
+    if (info) {
+      info->iters += in.iters + vi.iters;
+      info->wave_solves += in.wave_solves + vi.wave_solves;
+      info->wave_solves_f32 += in.wave_solves_f32 + vi.wave_solves_f32;
+      info->true_rel_res = std::max(info->true_rel_res, in.true_rel_res);
+      info->rel_res = std::max(info->rel_res, vi.rel_res);
+      info->nt = in.nt;
+      info->m = in.m;
+      info->dt = in.dt;
+      info->omega_tilde = in.omega_tilde;
+      info->c_max = in.c_max;
+    }
+  }
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  *J = Jsum;
+  if (info) {
+    info->status = worst;
+    info->ms = now_ms() - t0;
+  }
+  return worst;
+}
+
 }  // extern "C"

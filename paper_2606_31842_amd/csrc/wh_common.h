@@ -143,6 +143,16 @@ void launch_helmholtz_residual(const double* c2, const double* f, const double* 
                                double* partials_f, hipStream_t s);
 int helmholtz_partial_blocks(int n, int dim);
 
+// ----------------------------------------------------------------- adjoint (2D)
+void launch_fwd_out2d(const double* cur, const double* prev, double* out, const double* kap,
+                      const double* fs, double cosn, bool first, int n, hipStream_t s);
+void launch_adj_step2d(const double* lam1, const double* lam2, double* lam_out, const double* W,
+                       const double* kap, const double* z, double wn, double gscale, double* grad,
+                       bool do_lam, int n, hipStream_t s);
+void launch_misfit(const double* u, const int64_t* idx, const double* d, int nrec, double* g,
+                   double* out, hipStream_t s);
+void launch_check_idx(const int64_t* idx, int nrec, int n, int* bad, hipStream_t s);
+
 // Deflation: W^T r into slots[dst..dst+nd) and y -= W c (c from slots[src..]).
 struct Defl {
   int kind = WH_DEFL_NONE;

@@ -1,0 +1,108 @@
+"""GPU parity of the misfit gradient (wh_solve_vjp, wh_adjoint_grad) against the
+oracle's time-domain VJP, its direct-solve adjoint and central finite differences."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import adjoint, discretization as disc, timeparams as tpm, wavesolve as ws
+from _gpu import cuda, host, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(n=24, n_src=2, seed=11, omega=9.7):
+    rng = np.random.default_rng(seed)
+    c2 = wl.config5_c2(n, rng)
+    c2_ref = wl.config5_c2(n, rng)
+    srcs = [wl.gaussian(2, n, rng.uniform(0.25, 0.75, 2), 0.08) for _ in range(n_src)]
+    rec = wl.receivers(n, per_line=max(2, n // 4))
+    _, us_ref = adjoint.forward(2, n, c2_ref, omega, srcs, rec)
+    d = np.array([adjoint.restrict(u, rec) for u in us_ref])
+    return n, c2, omega, srcs, rec, d
+
+
+@pytest.mark.parametrize("ckpt", [2, 5, 16])
+def test_vjp_matches_oracle(ckpt):
+    print(f"case vjp ckpt={ckpt}", flush=True)
+    import paper_2606_31842_amd as wh
+    n, c2, omega, srcs, rec, d = _case()
+    L = disc.laplacian(2, n, c2)
+    f = srcs[0]
+    u = disc.direct_solve(L, omega, disc.to_interior(f))
+    gu = wl.random_nodal(2, n, 4)
+    cmax = float(np.sqrt(c2.max()))
+    tp = tpm.time_parameters(omega, 1.0 / n, cmax)
+    A = ws.dense_A(L, tp)
+    z = np.linalg.solve(A, disc.to_interior(gu))
+    ref = adjoint.vjp_time_domain(L, 2, n, u, z, disc.to_interior(f), tp)
+    got, info = wh.solve_vjp(cuda(disc.to_nodal(u, 2, n)), cuda(gu), cuda(f), omega, cuda(c2),
+                             ckpt_every=ckpt, tol=1e-13, c_max=cmax, max_iters=5000)
+    print(f"vjp rel err {rel(host(got), ref):.2e} cg iters {info['iters']}", flush=True)
+    assert rel(host(got), ref) < 1e-8
+    # the same product from the direct-solve adjoint: -lam^T (dL/dc2) u, lam = H^{-1} g
+    lam = disc.to_nodal(disc.direct_solve(L, omega, disc.to_interior(gu)), 2, n)
+    direct = adjoint.face_sum(lam, disc.to_nodal(u, 2, n)) * (n * n) / 2.0
+    assert rel(host(got), direct) < 1e-8
+
+
+def test_adjoint_grad_matches_oracle_and_fd():
+    print("case adjoint grad", flush=True)
+    import torch
+    import paper_2606_31842_amd as wh
+    n, c2, omega, srcs, rec, d = _case(n=32, n_src=3)
+    J_ref, g_ref = adjoint.grad_direct(2, n, c2, omega, srcs, rec, d)
+    cmax = float(np.sqrt(c2.max()))
+    J, g, info = wh.adjoint_grad(cuda(c2), [cuda(f) for f in srcs], torch.from_numpy(rec), torch.from_numpy(d),
+                                 omega, tol=1e-12, c_max=cmax, max_iters=5000)
+    print(f"J {J:.6e} vs {J_ref:.6e}; grad rel err {rel(host(g), g_ref):.2e}", flush=True)
+    assert abs(J - J_ref) < 1e-9 * J_ref
+    assert rel(host(g), g_ref) < 1e-7
+    # central differences of the oracle's exact J in random directions
+    rng = np.random.default_rng(2)
+    for _ in range(3):
+        delta = rng.standard_normal(c2.shape)
+        delta /= np.abs(delta).max()
+        fd = adjoint.fd_directional(2, n, c2, omega, srcs, rec, d, delta, eps=1e-6)
+        an = float(np.sum(host(g) * delta))
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * np.abs(host(g)).sum())
+
+
+def test_adjoint_fd_on_gpu_solves():
+    # the GPU's own J under +-eps perturbations (FP64 solves at tight tolerance)
+    import torch
+    import paper_2606_31842_amd as wh
+    n, c2, omega, srcs, rec, d = _case(n=40, n_src=2, seed=5)
+    cmax = float(np.sqrt(c2.max() * 1.01))
+    J, g, _ = wh.adjoint_grad(cuda(c2), [cuda(f) for f in srcs], torch.from_numpy(rec), torch.from_numpy(d),
+                              omega, tol=1e-13, c_max=cmax, max_iters=8000)
+    rng = np.random.default_rng(9)
+    delta = rng.standard_normal(c2.shape)
+    delta /= np.abs(delta).max()
+    eps = 1e-6
+    Jp, _, _ = wh.adjoint_grad(cuda(c2 + eps * delta), [cuda(f) for f in srcs], torch.from_numpy(rec),
+                               torch.from_numpy(d), omega, tol=1e-13, c_max=cmax, max_iters=8000)
+    Jm, _, _ = wh.adjoint_grad(cuda(c2 - eps * delta), [cuda(f) for f in srcs], torch.from_numpy(rec),
+                               torch.from_numpy(d), omega, tol=1e-13, c_max=cmax, max_iters=8000)
+    fd = (Jp - Jm) / (2 * eps)
+    an = float(np.sum(host(g) * delta))
+    print(f"gpu fd {fd:.8e} adjoint {an:.8e}", flush=True)
+    assert abs(fd - an) <= 1e-5 * abs(an)
+
+
+def test_autograd_function():
+    import torch
+    import paper_2606_31842_amd as wh
+    n, c2, omega, srcs, rec, d = _case(n=24, n_src=1)
+    cmax = float(np.sqrt(c2.max()))
+    f = cuda(srcs[0]).requires_grad_(True)
+    c2t = cuda(c2).requires_grad_(True)
+    w = cuda(wl.random_nodal(2, n, 6))
+    u = wh.WaveHoltzSolve.apply(f, c2t, omega, {"tol": 1e-13, "c_max": cmax, "max_iters": 5000})
+    loss = (u * w).sum()
+    loss.backward()
+    # dL/dc2 against the direct-solve adjoint, dL/df against H^{-1} w
+    L = disc.laplacian(2, n, c2)
+    U = disc.to_nodal(disc.direct_solve(L, omega, disc.to_interior(srcs[0])), 2, n)
+    lam = disc.to_nodal(disc.direct_solve(L, omega, disc.to_interior(host(w))), 2, n)
+    assert rel(host(c2t.grad), adjoint.face_sum(lam, U) * (n * n) / 2.0) < 1e-8
+    assert rel(host(f.grad), lam) < 1e-9
