@@ -31,6 +31,13 @@ HBM_PEAK_GBS = 8000.0
 # kernel (c = 1, no forcing): read W^n 4 + W^{n-1} 4, write W^{n+1} 4, V read+write 16
 B_PER_PT_STEP_F32 = 28.0
 B_PER_PT_STEP_F64 = 40.0
+# HBM bytes per dispatch of the K=8 FP32 fused kernel on this grid, from the two
+# rocprofv3 counter passes summarised in profiles/hbm_traffic_fused2d_f32_k8_2d1024.md
+# (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 after calibration on a plain copy).  Valid
+# only for the kernel source it was taken on.
+TRAFFIC = {"kernel": "k_fused2d<float,8,16,false,false>", "k_fuse": 8,
+           "src_sha1": "ace13012828772a42fc8ebdd72da1a040fe6b5dc",
+           "fetch_kib": 8891.8, "write_kib": 16427.0, "fetch_scale": 2.000, "write_scale": 1.000}
 
 
 def log(*a):
@@ -75,6 +82,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 single-solve comparison")
+    ap.add_argument("--probe-traffic", action="store_true",
+                    help="for hardware-counter runs: a plain 256 MiB device copy, then 5 wave solves "
+                         "of the workload's FP32 operator, and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solves of this workload are "
@@ -90,6 +100,18 @@ def main():
     n = p.n
     pts = (n - 1) ** 2
     f = torch.from_numpy(p.f).cuda()
+    if args.probe_traffic:
+        # reference copy: 256 MiB read + 256 MiB written, for scaling FETCH_SIZE / WRITE_SIZE
+        a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        v = torch.from_numpy(wl.random_nodal(2, n, 1)).cuda()
+        for _ in range(5):
+            wh.apply_filter(v, p.omega, precision="mixed")
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "traffic", "copy_bytes_each_way": a.numel() * 8}), flush=True)
+        return
     defl = wh.sine_deflation(2, n, p.omega, 32)
     kw = dict(solver="dcg", defl=defl, precision="mixed", tol=1e-8, max_iters=50000)
     need = wh.workspace_bytes(2, n, wh.params(p.omega, **{k: v for k, v in kw.items() if k != "defl"}), defl)
@@ -156,6 +178,12 @@ def main():
             "wave_solves": i64["wave_solves"], "true_rel_res": i64["true_rel_res"],
             "rel_err_vs_oracle": float(np.linalg.norm(u64.cpu().numpy() - U) / np.linalg.norm(U))}
 
+    traffic = None
+    src = os.path.join(ROOT, "paper_2606_31842_amd", "csrc", "wh_fused.hip")
+    import hashlib
+    if kf == TRAFFIC["k_fuse"] and hashlib.sha1(open(src, "rb").read()).hexdigest() == TRAFFIC["src_sha1"]:
+        traffic = round(1024 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] +
+                                TRAFFIC["write_kib"] * TRAFFIC["write_scale"]))
     line = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gpts/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
@@ -170,12 +198,13 @@ def main():
                   "wave_solves_f64": info["wave_solves"], "nt": nt, "true_rel_res": info["true_rel_res"],
                   "rel_err_vs_oracle": err},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": (f"k_fused2d<float,{kf},16,false,false> ({kf} FP32 leapfrog steps + FP64 filter "
                                 "sum per launch)") if kf > 1 else "k_step2d<float,M_MID> (FP32 leapfrog + FP64 filter)",
                      "k_fuse": kf, "bytes_per_pt_step": B_PER_PT_STEP_F32, "pt_steps_per_launch": units,
                      "bytes_per_launch": B_PER_PT_STEP_F32 * units, "launch_us": round(launch_us, 3),
-                     "filter_gpts": round(filt_gpts, 2)},
+                     "filter_gpts": round(filt_gpts, 2),
+                     "hbm_gbs_from_traffic": None if traffic is None else round(traffic / (launch_us * 1e-6) / 1e9, 1)},
         **extra,
     }
     if not args.no_cpu:
