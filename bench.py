@@ -82,6 +82,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 single-solve comparison")
+    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"],
+                    help="cfg2 (default) is the benchmark line; the others report the remaining "
+                         "workloads (2D 64^2 FP64 CG; 3D 256^3 variable c; 256 batched solves; "
+                         "513^2 adjoint gradient)")
+    ap.add_argument("--max-iters", type=int, default=0, help="iteration cap (cfg3)")
+    ap.add_argument("--per-size", type=int, default=64, help="problems per grid size (cfg4)")
     ap.add_argument("--probe-traffic", action="store_true",
                     help="for hardware-counter runs: a plain 256 MiB device copy, then 5 wave solves "
                          "of the workload's FP32 operator, and exit")
@@ -95,6 +101,10 @@ def main():
     import torch
     import paper_2606_31842_amd as wh
     import workloads as wl
+
+    if args.workload != "cfg2":
+        print(json.dumps(EXTRA[args.workload](args, np, torch, wh, wl)), flush=True)
+        return
 
     p = wl.config2()
     n = p.n
@@ -210,6 +220,116 @@ def main():
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(p, nt)
     print(json.dumps(line), flush=True)
+
+
+def _timed(torch, fn):
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t
+
+
+def run_cfg1(args, np, torch, wh, wl):
+    """2D 64^2, c = 1, omega = 20.5, FP64 CG to 1e-10 (oracle: the direct solve)."""
+    from oracle import discretization as disc
+    p = wl.config1()
+    f = torch.from_numpy(p.f).cuda()
+    kw = dict(solver="cg", precision="f64", tol=1e-10)
+    wh.solve(f, p.omega, **kw)
+    (u, info), dt = _timed(torch, lambda: wh.solve(f, p.omega, **kw))
+    U = disc.direct_solve(disc.laplacian(2, p.n), p.omega, disc.to_interior(p.f))
+    err = float(np.linalg.norm(disc.to_interior(u.cpu().numpy()) - U) / np.linalg.norm(U))
+    steps = (info["wave_solves"] + info["wave_solves_f32"]) * info["nt"]
+    return {"workload": "cfg1 2D 64^2 FP64 CG tol 1e-10", "time_to_tol_ms": dt * 1e3,
+            "gpts": (p.n - 1) ** 2 * steps / dt / 1e9, "iters": info["iters"], "nt": info["nt"],
+            "true_rel_res": info["true_rel_res"], "rel_err_vs_direct": err}
+
+
+def run_cfg3(args, np, torch, wh, wl):
+    """3D 256^3, seeded variable c, omega = 40: GMRES(40) and CG, mixed precision, tol 1e-8."""
+    p = wl.config3()
+    f = torch.from_numpy(p.f).cuda()
+    c2 = torch.from_numpy(p.c2).cuda()
+    pts = (p.n - 1) ** 3
+    out = {"workload": "cfg3 3D 256^3 variable c omega=40 mixed tol 1e-8"}
+    v = torch.from_numpy(wl.random_nodal(3, p.n, 1)).cuda()
+    for prec in ("mixed", "f64"):
+        us = wh.time_step_kernel(v, p.omega, c2=c2, precision=prec, reps=20) * 1e3
+        bpp = 32.0 if prec == "mixed" else 48.0
+        out[f"step_kernel_{prec}"] = {"us": us, "gpts": pts / us / 1e3, "bytes_per_pt_step": bpp,
+                                      "achieved_gbs": bpp * pts / (us * 1e-6) / 1e9}
+    cap = args.max_iters or 2000
+    for solver in ("gmres", "cg"):
+        (u, info), dt = _timed(torch, lambda: wh.solve(f, p.omega, c2=c2, solver=solver, precision="mixed",
+                                                      tol=1e-8, max_iters=cap, restart=40))
+        out[solver] = {"seconds": dt, "status": info["status"], "iters": info["iters"],
+                       "true_rel_res": info["true_rel_res"], "helmholtz_rel_res":
+                       wh.helmholtz_residual(u, f, p.omega, c2), "nt": info["nt"],
+                       "wave_solves_f32": info["wave_solves_f32"], "wave_solves_f64": info["wave_solves"]}
+    return out
+
+
+def run_cfg4(args, np, torch, wh, wl):
+    """256 (64 per size) batched 2D solves of mixed sizes and frequencies, mixed precision in one
+    graph-replayed batch, against the same problems solved one by one with FP64 wh_solve."""
+    from oracle import discretization as disc
+    probs = wl.config4(per_size=args.per_size)
+    fs = [torch.from_numpy(q.f).cuda() for q in probs]
+    # one-by-one FP64 (a warm-up per grid size first)
+    seen = set()
+    for f, q in zip(fs, probs):
+        if q.n not in seen:
+            wh.solve(f, q.omega, solver="cg", tol=1e-8, max_iters=100000)
+            seen.add(q.n)
+    (singles), dt1 = _timed(torch, lambda: [wh.solve(f, q.omega, solver="cg", tol=1e-8, max_iters=100000)
+                                            for f, q in zip(fs, probs)])
+    out = {"workload": f"cfg4 batched {len(probs)} 2D solves n in 128..1024, omega~U(10,80), tol 1e-8",
+           "single_f64_seconds": dt1, "single_f64_iters": int(sum(i["iters"] for _, i in singles))}
+    for prec in ("mixed", "f64"):
+        (res), dt = _timed(torch, lambda: wh.solve_batched([(f, q.omega) for f, q in zip(fs, probs)],
+                                                           precision=prec, tol=1e-8, k_fuse=8, max_iters=100000))
+        us, infos = res
+        errs = []
+        for u, q in zip(us, probs):
+            U = disc.direct_solve_dst(2, q.n, q.omega, q.f)
+            errs.append(float(np.linalg.norm(u.cpu().numpy() - U) / np.linalg.norm(U)))
+        out[f"batched_{prec}"] = {"seconds": dt, "iters": int(sum(i["iters"] for i in infos)),
+                                  "max_true_rel_res": max(i["true_rel_res"] for i in infos),
+                                  "status_counts": {str(k): sum(1 for i in infos if i["status"] == k)
+                                                    for k in sorted(set(i["status"] for i in infos))},
+                                  "max_rel_err_vs_oracle": max(errs), "median_rel_err": float(np.median(errs)),
+                                  "speedup_vs_single_f64": dt1 / dt}
+    return out
+
+
+def run_cfg5(args, np, torch, wh, wl):
+    """Adjoint gradient on 513^2 with 16 sources and 4 x 128 receivers; one GPU central
+    difference of J in a random direction as a check."""
+    from oracle import adjoint
+    wk = wl.config5()
+    c2 = torch.from_numpy(wk.c2).cuda()
+    srcs = [torch.from_numpy(f).cuda() for f in wk.sources]
+    rec = torch.from_numpy(wk.rec_idx)
+    # data from the reference c2 with the library's own solves
+    c2r = torch.from_numpy(wk.c2_ref).cuda()
+    d = torch.stack([wh.solve(f, wk.omega, c2=c2r, tol=1e-12, max_iters=20000, c_max=wk.c_max)[0].reshape(-1)[rec.cuda()]
+                     for f in srcs])
+    kw = dict(tol=1e-10, c_max=wk.c_max, max_iters=20000)
+    (J, g, info), dt = _timed(torch, lambda: wh.adjoint_grad(c2, srcs, rec, d, wk.omega, ckpt_every=16, **kw))
+    delta = torch.from_numpy(wk.directions[0]).cuda()
+    eps = 1e-6
+    kw12 = dict(kw, tol=1e-12)
+    Jp = wh.adjoint_grad(c2 + eps * delta, srcs, rec, d, wk.omega, **kw12)[0]
+    Jm = wh.adjoint_grad(c2 - eps * delta, srcs, rec, d, wk.omega, **kw12)[0]
+    fd = (Jp - Jm) / (2 * eps)
+    an = float((g * delta).sum())
+    return {"workload": "cfg5 adjoint 513^2, 16 sources, 512 receivers, omega=30, ckpt 16",
+            "seconds": dt, "J": J, "iters": info["iters"], "nt": info["nt"], "wave_solves": info["wave_solves"],
+            "fd_directional": fd, "adjoint_directional": an, "fd_rel_diff": abs(fd - an) / abs(an)}
+
+
+EXTRA = {"cfg1": run_cfg1, "cfg3": run_cfg3, "cfg4": run_cfg4, "cfg5": run_cfg5}
 
 
 if __name__ == "__main__":
