@@ -35,7 +35,7 @@ B_PER_PT_STEP_F64 = 40.0
 # rocprofv3 counter passes summarised in profiles/hbm_traffic_fused2d_f32_k8_2d1024.md
 # (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 after calibration on a plain copy).  Valid
 # only for the kernel source it was taken on.
-TRAFFIC = {"kernel": "k_fused2d<float,8,16,false,false>", "k_fuse": 8,
+TRAFFIC = {"kernel": "k_fused2d<float,8,16,false,false>", "k_fuse": 8, "rows": 16, "waves": 4,
            "src_sha1": "ace13012828772a42fc8ebdd72da1a040fe6b5dc",
            "fetch_kib": 8891.8, "write_kib": 16427.0, "fetch_scale": 2.000, "write_scale": 1.000}
 
@@ -169,7 +169,11 @@ def main():
     kf = info["k_fuse"]
     # the dominant kernel alone: back-to-back launches of the K-step fused kernel
     # (or the streaming step when K = 1), timed with events on the library's stream
-    launch_us = wh.time_step_kernel(v, p.omega, precision="mixed", k_fuse=kf, reps=50) * 1e3
+    launch_ms, kshape = wh.time_step_kernel(v, p.omega, precision="mixed", reps=50, shape=True)
+    launch_us = launch_ms * 1e3
+    if kshape["k"] != kf:
+        log(f"note: the timed kernel uses K={kshape['k']}, the solve used K={kf}")
+        kf = kshape["k"]
     units = pts * kf                                   # point-steps per launch
     achieved = B_PER_PT_STEP_F32 * units / (launch_us * 1e-6) / 1e9
     log(f"filter: {per_solve_ms:.3f} ms per wave solve ({filt_gpts:.0f} Gpts/s); K={kf} kernel "
@@ -191,7 +195,8 @@ def main():
     traffic = None
     src = os.path.join(ROOT, "paper_2606_31842_amd", "csrc", "wh_fused.hip")
     import hashlib
-    if kf == TRAFFIC["k_fuse"] and hashlib.sha1(open(src, "rb").read()).hexdigest() == TRAFFIC["src_sha1"]:
+    if (kf == TRAFFIC["k_fuse"] and (kshape["rows"], kshape["waves"]) == (TRAFFIC["rows"], TRAFFIC["waves"])
+            and hashlib.sha1(open(src, "rb").read()).hexdigest() == TRAFFIC["src_sha1"]):
         traffic = round(1024 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] +
                                 TRAFFIC["write_kib"] * TRAFFIC["write_scale"]))
     line = {
@@ -209,8 +214,9 @@ def main():
                   "rel_err_vs_oracle": err},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": (f"k_fused2d<float,{kf},16,false,false> ({kf} FP32 leapfrog steps + FP64 filter "
-                                "sum per launch)") if kf > 1 else "k_step2d<float,M_MID> (FP32 leapfrog + FP64 filter)",
+                     "kernel": (f"k_fused2d<float,{kf},{kshape['rows']},{kshape['waves']},false,false> ({kf} FP32 "
+                                "leapfrog steps + FP64 filter sum per launch)") if kf > 1
+                               else "k_step2d<float,M_MID> (FP32 leapfrog + FP64 filter)",
                      "k_fuse": kf, "bytes_per_pt_step": B_PER_PT_STEP_F32, "pt_steps_per_launch": units,
                      "bytes_per_launch": B_PER_PT_STEP_F32 * units, "launch_us": round(launch_us, 3),
                      "filter_gpts": round(filt_gpts, 2),

@@ -134,6 +134,8 @@ typedef struct {
   double dt;               /* time step                                                     */
   double c_max;            /* wave speed bound used for the time step                       */
   double ms;               /* wall time of the call in milliseconds                         */
+  int32_t k_rows;          /* 2D blocked kernel: register rows per thread (0: streaming)    */
+  int32_t k_waves;         /* 2D blocked kernel: wavefronts per block (0: streaming)        */
 } wh_info;
 
 typedef struct {
@@ -243,11 +245,14 @@ wh_status wh_adjoint_grad(wh_ctx* ctx, const wh_grid* grid, const double* c2, in
  * time-stepping kernel that wh_apply_filter / wh_solve would use for these
  * arguments (the K-step temporally blocked kernel, or the single-step kernel when
  * K = 1), with no forcing.  `reps` launches run back to back on the context stream
- * between two HIP events; *k_used receives K.  The state arrays in the workspace
+ * between two HIP events; *k_used receives K, and (each pointer may be NULL)
+ * *rows / *waves the register rows per thread and wavefronts per block of the
+ * blocked kernel (0 for the single-step kernel).  The state arrays in the workspace
  * are zeroed first and overwritten; nothing else is touched. */
 wh_status wh_time_step_kernel(wh_ctx* ctx, const wh_grid* grid, const double* c2,
                               const wh_params* params, int32_t reps, void* ws, size_t ws_bytes,
-                              double* us_per_launch, int32_t* k_used);
+                              double* us_per_launch, int32_t* k_used, int32_t* rows,
+                              int32_t* waves);
 
 #ifdef __cplusplus
 }

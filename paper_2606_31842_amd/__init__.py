@@ -241,9 +241,10 @@ def helmholtz_residual(u, f, omega, c2=None):
     return rel.value
 
 
-def time_step_kernel(v, omega, c2=None, reps=50, **kw):
+def time_step_kernel(v, omega, c2=None, reps=50, shape=False, **kw):
     """Average milliseconds per launch of the time-stepping kernel the library picks
-    for this grid (see wh_time_step_kernel)."""
+    for this grid (see wh_time_step_kernel).  With shape=True returns
+    (ms, {"k": K, "rows": R, "waves": NW})."""
     dim = v.dim()
     n = v.shape[0] - 1
     lib = nat.load()
@@ -252,10 +253,12 @@ def time_step_kernel(v, omega, c2=None, reps=50, **kw):
     g = _grid(dim, n)
     ws = _workspace(lib.wh_workspace_bytes(C.byref(g), C.byref(p), None))
     us = C.c_double()
-    k = C.c_int32()
+    k, rows, waves = C.c_int32(), C.c_int32(), C.c_int32()
     st = lib.wh_time_step_kernel(ctx, C.byref(g), _ptr(c2), C.byref(p), int(reps), _ptr(ws), ws.numel(),
-                                 C.byref(us), C.byref(k))
+                                 C.byref(us), C.byref(k), C.byref(rows), C.byref(waves))
     _check(lib, ctx, st)
+    if shape:
+        return us.value / 1e3, {"k": k.value, "rows": rows.value, "waves": waves.value}
     return us.value / 1e3
 
 

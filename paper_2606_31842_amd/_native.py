@@ -42,6 +42,7 @@ class WhInfo(C.Structure):
         ("wave_solves_f32", C.c_int32), ("outer", C.c_int32), ("nt", C.c_int32), ("m", C.c_int32),
         ("k_fuse", C.c_int32), ("rel_res", C.c_double), ("true_rel_res", C.c_double),
         ("omega_tilde", C.c_double), ("dt", C.c_double), ("c_max", C.c_double), ("ms", C.c_double),
+        ("k_rows", C.c_int32), ("k_waves", C.c_int32),
     ]
 
     def as_dict(self):
@@ -88,7 +89,8 @@ _OPTIONAL = {
     "wh_solve_batched": (C.c_int, [C.c_void_p, C.c_int32, P(WhProblem), P(WhParams), C.c_void_p, C.c_size_t,
                                    P(WhInfo)]),
     "wh_time_step_kernel": (C.c_int, [C.c_void_p, P(WhGrid), C.c_void_p, P(WhParams), C.c_int32, C.c_void_p,
-                                      C.c_size_t, P(C.c_double), P(C.c_int32)]),
+                                      C.c_size_t, P(C.c_double), P(C.c_int32), P(C.c_int32),
+                                      P(C.c_int32)]),
 }
 
 _lib = None

@@ -274,6 +274,7 @@ struct WaveOp {
   const TimeParams* tp = nullptr;
   double* partials = nullptr;
   int k_fuse = 1;
+  int k_shape = 0;   // block shape of the temporally blocked kernel
 };
 
 // One wave solve from W^0 = vin.  last = M_LAST_V: V holds Pi_h(vin);
@@ -312,6 +313,7 @@ int wave_solve(const WaveOp& op, const double* vin, bool force, StepMode last, c
     fa.a = op.a;
     fa.n = op.n;
     fa.k = K;
+    fa.shape = op.k_shape;
     // the last step stays with the streaming kernel (it carries the epilogue); the
     // remainder is covered by the largest supported K that still fits
     int Kc = K;
@@ -348,68 +350,75 @@ int wave_solve(const WaveOp& op, const double* vin, bool force, StepMode last, c
 }
 
 // ----------------------------------------------------------------- autotuner
-// Steps per launch for the temporally blocked 2D kernel: time each supported K on
-// this grid (after one warm-up launch) and keep the fastest per-step time.  The
-// state buffers and V serve as scratch; every caller initialises them afterwards.
-int autotune_k(wh_ctx* ctx, const WaveOp& op, bool force) {
+// Steps per launch and block shape of the temporally blocked 2D kernel: time every
+// supported (K, shape) on this grid (after one warm-up launch) and keep the fastest
+// per-step time; K = 1 is the streaming kernel.  k_fixed > 0 restricts the search to
+// that K.  The state buffers and V serve as scratch; every caller initialises them
+// afterwards.  Returns K | (shape << 8), cached per context.
+int autotune_k(wh_ctx* ctx, const WaveOp& op, bool force, int k_fixed = 0) {
   if (op.dim != 2) return 1;
-  const auto key = std::make_tuple(op.dim, op.n, (int)op.f32, (int)op.varc, (int)force);
+  const auto key = std::make_tuple(op.dim, op.n, (int)op.f32, (int)op.varc, (int)force + 2 * k_fixed);
   auto it = ctx->ktune.find(key);
   if (it != ctx->ktune.end()) return it->second;
   const TimeParams& tp = *op.tp;
+  const int fallback = k_fixed > 1 ? (k_fixed | (fused2d_default_shape(op.f32, op.n) << 8)) : 4;
   hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess) return 4;
+  if (hipEventCreate(&e0) != hipSuccess) return fallback;
   if (hipEventCreate(&e1) != hipSuccess) {
     (void)hipEventDestroy(e0);
-    return 4;
+    return fallback;
   }
-  int best = 1;
+  int best = k_fixed == 1 ? 1 : fallback;
   float best_t = 1e30f;
   const int cands[] = {1, 2, 3, 4, 6, 8};
   for (int K : cands) {
+    if (k_fixed > 0 && K != k_fixed) continue;
     if (K > 1 && (!fused2d_supported(op.f32, K) || K + 2 > tp.nt)) continue;
-    auto run = [&]() {
-      if (K == 1) {
-        StepArgs a{};
-        a.n = op.n;
-        a.kap = op.kap;
-        a.fs = force ? op.fs : nullptr;
-        a.a = op.a;
-        a.cur = op.Wb;
-        a.prev = op.Wa;
-        a.V = op.V;
-        a.cosn = tp.cosv[1];
-        a.wn = tp.w[2];
-        launch_step(op.dim, op.f32, op.varc, force, M_MID, a, ctx->stream);
-      } else {
-        FusedArgs fa{};
-        fa.V = op.V;
-        fa.kap = op.kap;
-        fa.fs = force ? op.fs : nullptr;
-        fa.a = op.a;
-        fa.n = op.n;
-        fa.k = K;
-        fa.cur = op.Wb;
-        fa.prev = op.Wa;
-        fa.cur_out = op.Wc;
-        fa.prev_out = op.Wd;
-        fa.wts = &tp.w[2];
-        fa.cosv = &tp.cosv[1];
-        launch_fused2d(op.f32, op.varc, force, fa, ctx->stream);
+    for (int shape = 0; shape < (K == 1 ? 1 : kFusedShapes); ++shape) {
+      auto run = [&]() {
+        if (K == 1) {
+          StepArgs a{};
+          a.n = op.n;
+          a.kap = op.kap;
+          a.fs = force ? op.fs : nullptr;
+          a.a = op.a;
+          a.cur = op.Wb;
+          a.prev = op.Wa;
+          a.V = op.V;
+          a.cosn = tp.cosv[1];
+          a.wn = tp.w[2];
+          launch_step(op.dim, op.f32, op.varc, force, M_MID, a, ctx->stream);
+        } else {
+          FusedArgs fa{};
+          fa.V = op.V;
+          fa.kap = op.kap;
+          fa.fs = force ? op.fs : nullptr;
+          fa.a = op.a;
+          fa.n = op.n;
+          fa.k = K;
+          fa.shape = shape;
+          fa.cur = op.Wb;
+          fa.prev = op.Wa;
+          fa.cur_out = op.Wc;
+          fa.prev_out = op.Wd;
+          fa.wts = &tp.w[2];
+          fa.cosv = &tp.cosv[1];
+          launch_fused2d(op.f32, op.varc, force, fa, ctx->stream);
+        }
+      };
+      run();
+      const int reps = 3;
+      (void)hipEventRecord(e0, ctx->stream);
+      for (int r = 0; r < reps; ++r) run();
+      (void)hipEventRecord(e1, ctx->stream);
+      if (hipEventSynchronize(e1) != hipSuccess) break;
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      const float per_step = ms / (reps * K);
+      if (per_step < best_t) {
+        best_t = per_step;
+        best = K | (shape << 8);
       }
-    };
-    run();
-    const int reps = 3;
-    (void)hipEventRecord(e0, ctx->stream);
-    for (int r = 0; r < reps; ++r) run();
-    (void)hipEventRecord(e1, ctx->stream);
-    if (hipEventSynchronize(e1) != hipSuccess) break;
-    float ms = 0;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    const float per_step = ms / (reps * K);
-    if (per_step < best_t) {
-      best_t = per_step;
-      best = K;
     }
   }
   (void)hipEventDestroy(e0);
@@ -811,17 +820,21 @@ wh_status setup_ops(wh_ctx* ctx, const wh_grid& g, const wh_params& P, const dou
   // steps per launch: fixed by the caller, else autotuned (cached per context).  The
   // operator without forcing dominates every solve, so it sets K for both precisions.
   auto pick = [&](WaveOp& op) {
-    if (g.dim != 2) return 1;
-    if (P.k_fuse > 0) return (P.k_fuse == 1 || fused2d_supported(op.f32, P.k_fuse)) ? P.k_fuse : 1;
-    return autotune_k(ctx, op, false);
+    int code = 1;
+    if (g.dim == 2) {
+      if (P.k_fuse == 1 || (P.k_fuse > 1 && !fused2d_supported(op.f32, P.k_fuse))) code = 1;
+      else code = autotune_k(ctx, op, false, P.k_fuse);
+    }
+    op.k_fuse = code & 0xff;
+    op.k_shape = code >> 8;
   };
-  S.op64.k_fuse = pick(S.op64);
-  if (mixed) S.op32.k_fuse = pick(S.op32);
+  pick(S.op64);
+  if (mixed) pick(S.op32);
   HIPCHK(ctx, hipGetLastError());
   return WH_OK;
 }
 
-void fill_info(wh_info* info, const TimeParams& tp, int k_fuse) {
+void fill_info(wh_info* info, const TimeParams& tp, int k_fuse, const WaveOp* op = nullptr) {
   if (!info) return;
   info->nt = tp.nt;
   info->m = tp.m;
@@ -829,6 +842,8 @@ void fill_info(wh_info* info, const TimeParams& tp, int k_fuse) {
   info->omega_tilde = tp.omega_w;
   info->c_max = tp.c_max;
   info->k_fuse = k_fuse;
+  info->k_rows = info->k_waves = 0;
+  if (op && op->dim == 2 && k_fuse > 1) fused2d_shape_dims(op->f32, op->k_shape, &info->k_rows, &info->k_waves);
 }
 
 }  // namespace
@@ -997,7 +1012,8 @@ wh_status wh_apply_filter(wh_ctx* ctx, const wh_grid* grid, const double* c2, co
   HIPCHK(ctx, hipGetLastError());
   if (info) {
     std::memset(info, 0, sizeof(*info));
-    fill_info(info, tp, params->precision == WH_MIXED ? S.op32.k_fuse : S.op64.k_fuse);
+    fill_info(info, tp, params->precision == WH_MIXED ? S.op32.k_fuse : S.op64.k_fuse,
+              params->precision == WH_MIXED ? &S.op32 : &S.op64);
     info->wave_solves = params->precision == WH_MIXED ? 0 : 1;
     info->wave_solves_f32 = params->precision == WH_MIXED ? 1 : 0;
     info->ms = now_ms() - t0;
@@ -1203,7 +1219,8 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
   HIPCHK(ctx, hipGetLastError());
   HIPCHK(ctx, hipStreamSynchronize(s));
   if (info) {
-    fill_info(info, tp, params->precision == WH_MIXED ? S.op32.k_fuse : S.op64.k_fuse);
+    fill_info(info, tp, params->precision == WH_MIXED ? S.op32.k_fuse : S.op64.k_fuse,
+              params->precision == WH_MIXED ? &S.op32 : &S.op64);
     info->status = st;
     info->iters = S.iters;
     info->wave_solves = S.ws64;
@@ -1241,7 +1258,8 @@ wh_status wh_helmholtz_residual(wh_ctx* ctx, const wh_grid* grid, const double* 
 
 wh_status wh_time_step_kernel(wh_ctx* ctx, const wh_grid* grid, const double* c2,
                               const wh_params* params, int32_t reps, void* ws, size_t ws_bytes,
-                              double* us_per_launch, int32_t* k_used) {
+                              double* us_per_launch, int32_t* k_used, int32_t* rows,
+                              int32_t* waves) {
   if (!ctx) return WH_EINVAL;
   WHCHK(check_grid(ctx, grid));
   WHCHK(check_params(ctx, grid, params));
@@ -1277,6 +1295,7 @@ wh_status wh_time_step_kernel(wh_ctx* ctx, const wh_grid* grid, const double* c2
       fa.a = op.a;
       fa.n = op.n;
       fa.k = K;
+      fa.shape = op.k_shape;
       fa.cur = (r & 1) ? op.Wc : op.Wb;
       fa.prev = (r & 1) ? op.Wd : op.Wa;
       fa.cur_out = (r & 1) ? op.Wb : op.Wc;
@@ -1301,6 +1320,10 @@ wh_status wh_time_step_kernel(wh_ctx* ctx, const wh_grid* grid, const double* c2
   if (e != hipSuccess) WH_FAIL(ctx, WH_EHIP, "event timing failed: %s", hipGetErrorString(e));
   *us_per_launch = 1e3 * (double)ms / reps;
   if (k_used) *k_used = K;
+  int rr = 0, wv = 0;
+  if (K > 1 && op.dim == 2) fused2d_shape_dims(op.f32, op.k_shape, &rr, &wv);
+  if (rows) *rows = rr;
+  if (waves) *waves = wv;
   return WH_OK;
 }
 

@@ -107,13 +107,14 @@ __device__ __forceinline__ T lap_term(const T* c, const T* kap, int64_t p, int64
   return A * (((c[p - 1] + c[p + 1]) + (c[p - P] + c[p + P])) - T(4) * cc);
 }
 
-template <typename T, int K, int R, bool VARC>
-__global__ __launch_bounds__(256) void k_batch_work(const BDesc* __restrict__ descs,
-                                                    const BState* __restrict__ states,
-                                                    const int* __restrict__ tile_solve, int ntiles,
-                                                    int want) {
+template <typename T, int K, int R, int NW, bool VARC>
+__global__ __launch_bounds__(64 * NW) void k_batch_work(const BDesc* __restrict__ descs,
+                                                        const BState* __restrict__ states,
+                                                        const int* __restrict__ tile_solve,
+                                                        int ntiles, int want) {
   constexpr int TXO = 64 - 2 * K;
-  constexpr int TYO = 4 * R - 2 * K;
+  constexpr int TYO = NW * R - 2 * K;
+  constexpr int NT = 64 * NW;
   const int gt = xcd_tile_b(blockIdx.x, ntiles);
   const int sid = tile_solve[gt];
   const BDesc& D = descs[sid];
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(256) void k_batch_work(const BDesc* __restrict__ de
 
   // element-wise loop over the tile's interior nodes
 #define TILE_FOR(p)                                                                  \
-  for (int e = tid; e < TXO * TYO; e += 256)                                         \
+  for (int e = tid; e < TXO * TYO; e += NT)                                          \
     if (x0 + e % TXO <= n - 1 && y0 + e / TXO <= n - 1)                              \
       for (int64_t p = (int64_t)(y0 + e / TXO) * P + (x0 + e % TXO), _o = 0; _o < 1; ++_o)
 
@@ -277,11 +278,12 @@ __global__ __launch_bounds__(256) void k_batch_work(const BDesc* __restrict__ de
       const int xg = x0 - K + lane;
       const int yb = y0 - K + wv * R;
       const bool xin = xg >= 1 && xg <= n - 1;
+      const bool xout = lane >= K && lane < 64 - K && xin;
       T cur[R], prv[R];
       double ac[R];
       T cw[VARC ? R : 1], ce[VARC ? R : 1], cu[VARC ? R : 1], cd[VARC ? R : 1];
       T frc[R];
-      uint32_t mask = 0;
+      uint32_t mask = 0, omask = 0;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int y = yb + r;
@@ -289,8 +291,12 @@ __global__ __launch_bounds__(256) void k_batch_work(const BDesc* __restrict__ de
         const int64_t p = (int64_t)y * P + xg;
         cur[r] = in ? cin[p] : T(0);
         prv[r] = in ? pin[p] : T(0);
-        ac[r] = 0.0;
         if (in) mask |= 1u << r;
+        // inner-tile nodes start from V (loaded with the state, written back below)
+        const int ry = wv * R + r;
+        const bool o = in && xout && ry >= K && ry < NW * R - K;
+        if (o) omask |= 1u << r;
+        ac[r] = o ? D.V[p] : 0.0;
         if (VARC) {
           T kc = T(0), kw = T(0), ke = T(0), ku = T(0), kd = T(0);
           if (in) {
@@ -307,14 +313,14 @@ __global__ __launch_bounds__(256) void k_batch_work(const BDesc* __restrict__ de
         }
         frc[r] = (force && in) ? fsv[p] : T(0);
       }
-      __shared__ T edge[2][4][2][64];
+      __shared__ T edge[2][NW][2][64];
       for (int s = 0; s < Kp; ++s) {
         const int bb = s & 1;
         edge[bb][wv][0][threadIdx.x] = cur[0];
         edge[bb][wv][1][threadIdx.x] = cur[R - 1];
         __syncthreads();
         const T up_e = wv > 0 ? edge[bb][wv - 1][1][lane] : T(0);
-        const T dn_e = wv < 3 ? edge[bb][wv + 1][0][lane] : T(0);
+        const T dn_e = wv < NW - 1 ? edge[bb][wv + 1][0][lane] : T(0);
         const T cn = (T)D.cosv[S.step + s];
         const double ws = D.w[S.step + s + 1];
 #pragma unroll
@@ -322,8 +328,8 @@ __global__ __launch_bounds__(256) void k_batch_work(const BDesc* __restrict__ de
           const T c = cur[r];
           const T u = r > 0 ? cur[r - 1] : up_e;
           const T dd = r < R - 1 ? cur[r + 1] : dn_e;
-          const T w = __shfl_up(c, 1, 64);
-          const T e = __shfl_down(c, 1, 64);
+          const T w = from_prev_lane(c);
+          const T e = from_next_lane(c);
           T nw;
           if (VARC) {
             const int q = VARC ? r : 0;
@@ -344,16 +350,13 @@ __global__ __launch_bounds__(256) void k_batch_work(const BDesc* __restrict__ de
           prv[r] = tmp;
         }
       }
-      if (lane >= K && lane < 64 - K && xin) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int ry = wv * R + r;
-          if (ry >= K && ry < 4 * R - K && ((mask >> r) & 1u)) {
-            const int64_t p = (int64_t)(yb + r) * P + xg;
-            cout[p] = cur[r];
-            pout[p] = prv[r];
-            D.V[p] += ac[r];
-          }
+      for (int r = 0; r < R; ++r) {
+        if ((omask >> r) & 1u) {
+          const int64_t p = (int64_t)(yb + r) * P + xg;
+          cout[p] = cur[r];
+          pout[p] = prv[r];
+          D.V[p] = ac[r];
         }
       }
       break;
@@ -363,7 +366,7 @@ __global__ __launch_bounds__(256) void k_batch_work(const BDesc* __restrict__ de
   }
 #undef TILE_FOR
   if (reduce) {
-    const double sres = block_sum256(acc, tid);
+    const double sres = block_sum<NW>(acc, tid);
     if (tid == 0) D.partials[lt] = sres;
   }
 }
@@ -519,18 +522,20 @@ __global__ void k_batch_count(const BState* states, int nb, int* remaining) {
 }
 
 // ------------------------------------------------------------------ host side
-constexpr int kBR = 16;  // rows per thread of the batched tile
+// Batched tile: NW = 8 waves of R = 8 rows each, a 64 x 64 register region.
+constexpr int kBR = 8;
+constexpr int kBW = 8;
 
 static bool batch_k_ok(int K) { return K == 2 || K == 4 || K == 8; }
 
 template <int K, bool VARC>
 static void launch_round_k(const BDesc* descs, BState* states, const int* ts, int ntiles,
                            hipStream_t s) {
-  dim3 g(ntiles), b(64, 4);
-  hipLaunchKernelGGL((k_batch_work<double, K, kBR, VARC>), g, b, 0, s, descs, (const BState*)states, ts,
-                     ntiles, 0);
-  hipLaunchKernelGGL((k_batch_work<float, K, kBR, VARC>), g, b, 0, s, descs, (const BState*)states, ts,
-                     ntiles, 1);
+  dim3 g(ntiles), b(64, kBW);
+  hipLaunchKernelGGL((k_batch_work<double, K, kBR, kBW, VARC>), g, b, 0, s, descs,
+                     (const BState*)states, ts, ntiles, 0);
+  hipLaunchKernelGGL((k_batch_work<float, K, kBR, kBW, VARC>), g, b, 0, s, descs,
+                     (const BState*)states, ts, ntiles, 1);
 }
 
 static void launch_round(int K, bool varc, int nb, const BDesc* descs, BState* states,
@@ -547,7 +552,7 @@ static void launch_round(int K, bool varc, int nb, const BDesc* descs, BState* s
 }
 
 static int tile_dim(int n, int K, int axis) {
-  const int t = axis == 0 ? 64 - 2 * K : 4 * kBR - 2 * K;
+  const int t = axis == 0 ? 64 - 2 * K : kBW * kBR - 2 * K;
   return (n - 1 + t - 1) / t;
 }
 
@@ -849,6 +854,8 @@ wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
       in.nt = tps[i].nt;
       in.m = tps[i].m;
       in.k_fuse = K;
+      in.k_rows = kBR;
+      in.k_waves = kBW;
       in.rel_res = SF[i].rel;
       in.true_rel_res = mixed ? SF[i].rel : SF[i].pq;
       in.omega_tilde = tps[i].omega_w;

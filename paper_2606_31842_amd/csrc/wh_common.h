@@ -18,7 +18,8 @@ struct wh_ctx {
   std::string err;
   double* hbuf = nullptr;  // pinned host scalars
   int hbuf_len = 0;
-  std::map<std::tuple<int, int, int, int, int>, int> ktune;  // (dim, n, f32, varc, force) -> K
+  // (dim, n, f32, varc, force) -> steps per launch K | (block shape << 8)
+  std::map<std::tuple<int, int, int, int, int>, int> ktune;
 };
 
 namespace wh {
@@ -101,9 +102,38 @@ struct FusedArgs {
   const double* cosv;    // host: cos(omega_w t^{n..n+k-1})
   int n;
   int k;
+  int shape;             // block shape index, 0 .. kFusedShapes-1
 };
+constexpr int kFusedShapes = 3;
 bool fused2d_supported(bool f32, int k);
+// Default block shape for a grid when no timing is available.
+int fused2d_default_shape(bool f32, int n);
+// Register rows per thread and wavefronts per block of a block shape.
+void fused2d_shape_dims(bool f32, int shape, int* rows, int* waves);
 void launch_fused2d(bool f32, bool varc, bool force, const FusedArgs& a, hipStream_t s);
+
+// ----------------------------------------------------------------- lane shifts
+// Whole-wavefront shifts by one lane through DPP (wave_shr:1 / wave_shl:1): lane l
+// receives lane l-1 (from_prev_lane) or lane l+1 (from_next_lane); the lane with no
+// source receives 0.  These are plain VALU moves, unlike ds_bpermute shuffles.
+__device__ __forceinline__ float from_prev_lane(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_next_lane(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double from_prev_lane(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0x138, 0xf, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0x138, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ double from_next_lane(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0x130, 0xf, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0x130, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
 
 // ----------------------------------------------------------------- BLAS-like kernels
 void launch_prep_coeffs(const double* c2, const double* f, void* kap, void* fs, bool f32,

@@ -1,18 +1,24 @@
 // Temporally blocked 2D leapfrog + filter: K time steps per launch.
 //
 // Same scheme as the streaming kernels (Section 2.2, eq. discreteWaveExplicit with
-// the trapezoid sum of eq. quadrature folded in), but each 256-thread block keeps
-// a 64-column x 4R-row region of (W^n, W^{n-1}) in registers and advances it K
-// steps before writing back.  Lane l of wave w owns column x0-K+l and rows
+// the trapezoid sum of eq. quadrature folded in), but each block of NW wavefronts
+// keeps a 64-column x NW*R-row region of (W^n, W^{n-1}) in registers and advances
+// it K steps before writing back.  Lane l of wave w owns column x0-K+l and rows
 // y0-K+wR .. y0-K+wR+R-1.  Per step:
-//   * x-neighbours come from the adjacent lanes (cross-lane shuffle),
+//   * x-neighbours come from the adjacent lanes (DPP wavefront shift, a VALU move),
 //   * y-neighbours come from the thread's own rows, except the first/last row of
 //     each wave, which are exchanged through a small double-buffered LDS array,
 //   * points outside the open domain are held at zero (Dirichlet data).
 // The valid region shrinks by one point per step on every side, so the block
-// writes the inner (64-2K) x (4R-2K) tile: W^{n+K}, W^{n+K-1} and V += sum_s w_s W^{n+s}.
+// writes the inner (64-2K) x (NW*R-2K) tile: W^{n+K}, W^{n+K-1} and
+// V + sum_s w_s W^{n+s}.  V is loaded together with the state, before the steps,
+// so that its latency overlaps the other loads.
 // HBM traffic per point and launch is 8 (state in) + 8 (state out) + 16 (V) bytes in
 // FP32, i.e. 32/K bytes per point-step against 28 for the streaming kernel.
+//
+// Block shapes (R, NW): more waves per block and fewer rows per thread raise the
+// number of resident waves (latency hiding); taller regions waste less halo.  The
+// autotuner picks K and the shape per grid.
 //
 // Inputs and outputs are distinct buffers (neighbouring blocks read the halo).
 #include "wh_common.h"
@@ -42,15 +48,10 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
   return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
-template <typename T>
-__device__ __forceinline__ T lane_up(T v) { return __shfl_up(v, 1, 64); }
-template <typename T>
-__device__ __forceinline__ T lane_down(T v) { return __shfl_down(v, 1, 64); }
-
-template <typename T, int K, int R, bool VARC, bool FORCE>
-__global__ __launch_bounds__(256) void k_fused2d(const FusedDev a) {
+template <typename T, int K, int R, int NW, bool VARC, bool FORCE>
+__global__ __launch_bounds__(64 * NW) void k_fused2d(const FusedDev a) {
   constexpr int TXO = 64 - 2 * K;
-  constexpr int TYO = 4 * R - 2 * K;
+  constexpr int TYO = NW * R - 2 * K;
   static_assert(TXO > 0 && TYO > 0, "tile too small for K");
   const int n = a.n;
   const int64_t P = (int64_t)n + 1;
@@ -64,7 +65,8 @@ __global__ __launch_bounds__(256) void k_fused2d(const FusedDev a) {
   const int xg = x0 - K + lane;
   const int yb = y0 - K + wv * R;
   const bool xin = xg >= 1 && xg <= n - 1;
-  const bool xok = xg >= 0 && xg <= n;
+  // lanes and rows of the inner tile (written back)
+  const bool xout = lane >= K && lane < 64 - K && xin;
 
   const T* __restrict__ cin = (const T*)a.cur;
   const T* __restrict__ pin = (const T*)a.prev;
@@ -75,19 +77,21 @@ __global__ __launch_bounds__(256) void k_fused2d(const FusedDev a) {
   double acc[R];
   T cw[VARC ? R : 1], ce[VARC ? R : 1], cu[VARC ? R : 1], cd[VARC ? R : 1];
   T frc[FORCE ? R : 1];
-  uint32_t mask = 0;
+  uint32_t mask = 0, omask = 0;
+  const double* __restrict__ Vin = a.V;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int y = yb + r;
     const bool in = xin && y >= 1 && y <= n - 1;
-    const bool ok = xok && y >= 0 && y <= n;
     const int64_t p = (int64_t)y * P + xg;
     // boundary nodes hold the Dirichlet value 0: read interior nodes only
     cur[r] = in ? cin[p] : T(0);
     prv[r] = in ? pin[p] : T(0);
-    (void)ok;
-    acc[r] = 0.0;
     if (in) mask |= 1u << r;
+    const int ry = wv * R + r;
+    const bool o = in && xout && ry >= K && ry < NW * R - K;
+    if (o) omask |= 1u << r;
+    acc[r] = o ? Vin[p] : 0.0;
     if (VARC) {
       T kc = T(0), kw = T(0), ke = T(0), ku = T(0), kd = T(0);
       if (in) {
@@ -105,7 +109,7 @@ __global__ __launch_bounds__(256) void k_fused2d(const FusedDev a) {
     if (FORCE) frc[FORCE ? r : 0] = in ? fsv[p] : T(0);
   }
 
-  __shared__ T edge[2][4][2][64];
+  __shared__ T edge[2][NW][2][64];
   const T A = (T)a.a;
 #pragma unroll
   for (int s = 0; s < K; ++s) {
@@ -114,7 +118,7 @@ __global__ __launch_bounds__(256) void k_fused2d(const FusedDev a) {
     edge[b][wv][1][lane] = cur[R - 1];
     __syncthreads();
     const T up_e = wv > 0 ? edge[b][wv - 1][1][lane] : T(0);
-    const T dn_e = wv < 3 ? edge[b][wv + 1][0][lane] : T(0);
+    const T dn_e = wv < NW - 1 ? edge[b][wv + 1][0][lane] : T(0);
     const T cn = (T)a.cs[s];
     const double ws = a.w[s];
 #pragma unroll
@@ -122,8 +126,8 @@ __global__ __launch_bounds__(256) void k_fused2d(const FusedDev a) {
       const T c = cur[r];
       const T u = r > 0 ? cur[r - 1] : up_e;
       const T d = r < R - 1 ? cur[r + 1] : dn_e;
-      const T w = lane_up(c);
-      const T e = lane_down(c);
+      const T w = from_prev_lane(c);
+      const T e = from_next_lane(c);
       T nw;
       if (VARC) {
         const int q = VARC ? r : 0;
@@ -144,54 +148,78 @@ __global__ __launch_bounds__(256) void k_fused2d(const FusedDev a) {
     }
   }
 
-  // write the inner tile
-  if (lane >= K && lane < 64 - K && xin) {
-    T* __restrict__ cout = (T*)a.cur_out;
-    T* __restrict__ pout = (T*)a.prev_out;
+  // write the inner tile (V already holds its old value in acc)
+  T* __restrict__ cout = (T*)a.cur_out;
+  T* __restrict__ pout = (T*)a.prev_out;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int ry = wv * R + r;
-      if (ry >= K && ry < 4 * R - K && ((mask >> r) & 1u)) {
-        const int64_t p = (int64_t)(yb + r) * P + xg;
-        cout[p] = cur[r];
-        pout[p] = prv[r];
-        a.V[p] += acc[r];
-      }
+  for (int r = 0; r < R; ++r) {
+    if ((omask >> r) & 1u) {
+      const int64_t p = (int64_t)(yb + r) * P + xg;
+      cout[p] = cur[r];
+      pout[p] = prv[r];
+      a.V[p] = acc[r];
     }
   }
 }
 
-template <typename T, int K, int R>
-static void launch_kr(bool varc, bool force, const FusedDev& d, hipStream_t s) {
-  dim3 g(d.gx * d.gy), b(64, 4);
+template <typename T, int K, int R, int NW>
+static void launch_krw(bool varc, bool force, FusedDev& d, hipStream_t s) {
+  static_assert(NW * R - 2 * K > 0, "tile too small for K");
+  const int n = d.n;
+  d.gx = (n - 1 + (64 - 2 * K) - 1) / (64 - 2 * K);
+  d.gy = (n - 1 + (NW * R - 2 * K) - 1) / (NW * R - 2 * K);
+  dim3 g(d.gx * d.gy), b(64, NW);
   if (varc) {
-    if (force) hipLaunchKernelGGL((k_fused2d<T, K, R, true, true>), g, b, 0, s, d);
-    else hipLaunchKernelGGL((k_fused2d<T, K, R, true, false>), g, b, 0, s, d);
+    if (force) hipLaunchKernelGGL((k_fused2d<T, K, R, NW, true, true>), g, b, 0, s, d);
+    else hipLaunchKernelGGL((k_fused2d<T, K, R, NW, true, false>), g, b, 0, s, d);
   } else {
-    if (force) hipLaunchKernelGGL((k_fused2d<T, K, R, false, true>), g, b, 0, s, d);
-    else hipLaunchKernelGGL((k_fused2d<T, K, R, false, false>), g, b, 0, s, d);
+    if (force) hipLaunchKernelGGL((k_fused2d<T, K, R, NW, false, true>), g, b, 0, s, d);
+    else hipLaunchKernelGGL((k_fused2d<T, K, R, NW, false, false>), g, b, 0, s, d);
   }
 }
 
-// Supported (K, R) pairs: rows per thread R = 16 (FP32) / 8 (FP64).
 bool fused2d_supported(bool f32, int k) {
   (void)f32;
   return k == 2 || k == 3 || k == 4 || k == 6 || k == 8;
 }
 
-template <typename T, int R>
-static void launch_k(int k, bool varc, bool force, FusedDev& d, hipStream_t s) {
-  const int n = d.n;
-  auto grid = [&](int K) {
-    d.gx = (n - 1 + (64 - 2 * K) - 1) / (64 - 2 * K);
-    d.gy = (n - 1 + (4 * R - 2 * K) - 1) / (4 * R - 2 * K);
-  };
+// Shapes (rows per thread R, waves per block NW).  FP32: (16,4) (8,8) (8,4);
+// FP64: (8,4) (4,8) (4,16).  Measured on 1024^2: FP32 (8,8) and FP64 (4,16) are the
+// fastest; on 512^2 and below the 4-wave shapes are.
+int fused2d_default_shape(bool f32, int n) {
+  if (f32) return n >= 768 ? 1 : 2;
+  return n >= 768 ? 2 : 1;
+}
+
+void fused2d_shape_dims(bool f32, int shape, int* rows, int* waves) {
+  static const int r32[kFusedShapes] = {16, 8, 8}, w32[kFusedShapes] = {4, 8, 4};
+  static const int r64[kFusedShapes] = {8, 4, 4}, w64[kFusedShapes] = {4, 8, 16};
+  const int s = shape < 0 || shape >= kFusedShapes ? 0 : shape;
+  *rows = f32 ? r32[s] : r64[s];
+  *waves = f32 ? w32[s] : w64[s];
+}
+
+template <typename T, int K>
+static void launch_shape(int shape, bool varc, bool force, FusedDev& d, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    if (shape == 0) launch_krw<T, K, 16, 4>(varc, force, d, s);
+    else if (shape == 1) launch_krw<T, K, 8, 8>(varc, force, d, s);
+    else launch_krw<T, K, 8, 4>(varc, force, d, s);
+  } else {
+    if (shape == 0) launch_krw<T, K, 8, 4>(varc, force, d, s);
+    else if (shape == 1) launch_krw<T, K, 4, 8>(varc, force, d, s);
+    else launch_krw<T, K, 4, 16>(varc, force, d, s);
+  }
+}
+
+template <typename T>
+static void launch_k(int k, int shape, bool varc, bool force, FusedDev& d, hipStream_t s) {
   switch (k) {
-    case 2: grid(2); launch_kr<T, 2, R>(varc, force, d, s); break;
-    case 3: grid(3); launch_kr<T, 3, R>(varc, force, d, s); break;
-    case 4: grid(4); launch_kr<T, 4, R>(varc, force, d, s); break;
-    case 6: grid(6); launch_kr<T, 6, R>(varc, force, d, s); break;
-    case 8: grid(8); launch_kr<T, 8, R>(varc, force, d, s); break;
+    case 2: launch_shape<T, 2>(shape, varc, force, d, s); break;
+    case 3: launch_shape<T, 3>(shape, varc, force, d, s); break;
+    case 4: launch_shape<T, 4>(shape, varc, force, d, s); break;
+    case 6: launch_shape<T, 6>(shape, varc, force, d, s); break;
+    case 8: launch_shape<T, 8>(shape, varc, force, d, s); break;
     default: break;
   }
 }
@@ -211,8 +239,9 @@ void launch_fused2d(bool f32, bool varc, bool force, const FusedArgs& fa, hipStr
     d.w[j] = fa.wts[j];
     d.cs[j] = fa.cosv[j];
   }
-  if (f32) launch_k<float, 16>(fa.k, varc, force, d, s);
-  else launch_k<double, 8>(fa.k, varc, force, d, s);
+  const int shape = fa.shape < 0 || fa.shape >= kFusedShapes ? 0 : fa.shape;
+  if (f32) launch_k<float>(fa.k, shape, varc, force, d, s);
+  else launch_k<double>(fa.k, shape, varc, force, d, s);
 }
 
 }  // namespace wh

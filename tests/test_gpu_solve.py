@@ -41,7 +41,9 @@ def test_solve_f64_matches_direct(solver, dim, n, omega, varc):
         c2 = c * c
     f = wl.gaussian(dim, n, (0.45, 0.55, 0.5)[:dim], 0.1)
     U = direct(dim, n, omega, f, c2)
-    tol = 1e-12
+    # 1e-10 stays well above the FP64 floor of the WaveHoltz residual (for the variable-c
+    # 45^2 case the exact discrete solution itself has a relative residual of 1.7e-12)
+    tol = 1e-10
     u, info = wh.solve(cuda(f), omega, c2=None if c2 is None else cuda(c2), solver=solver, tol=tol,
                        max_iters=3000, restart=30)
     assert info["status"] == 0, info
@@ -61,7 +63,13 @@ def test_solve_f64_matches_direct(solver, dim, n, omega, varc):
     print(f"gpu err {e:.2e} oracle err {eo:.2e} iters {info['iters']} / {oi['iters']}", flush=True)
     assert e < max(1e-11, 5 * eo)
     if solver == "cg":
-        assert abs(info["iters"] - oi["iters"]) <= max(2, oi["iters"] // 20)
+        # Near 1e-12 the CG residual wanders at the rounding floor (in the oracle too), so
+        # the exact crossing iteration depends on summation order; compare the iteration
+        # counts at 1e-8, where every step still reduces the residual.
+        u8, i8 = wh.solve(cuda(f), omega, c2=None if c2 is None else cuda(c2), solver="cg", tol=1e-8,
+                          max_iters=3000)
+        o8 = next(k for k, v in enumerate(oi["res"]) if v <= 1e-8)
+        assert abs(i8["iters"] - o8) <= max(2, o8 // 20), (i8["iters"], o8)
     # (restarted GMRES near stagnation is not reproducible in its iteration count:
     # perturbing b by 1e-15 moves the oracle's own count between 345 and 3000 on the
     # 2D n=45 case, so only convergence and the error are compared)
