@@ -35,9 +35,9 @@ B_PER_PT_STEP_F64 = 40.0
 # rocprofv3 counter passes summarised in profiles/hbm_traffic_fused2d_f32_k8_2d1024.md
 # (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 after calibration on a plain copy).  Valid
 # only for the kernel source it was taken on.
-TRAFFIC = {"kernel": "k_fused2d<float,8,16,false,false>", "k_fuse": 8, "rows": 16, "waves": 4,
-           "src_sha1": "ace13012828772a42fc8ebdd72da1a040fe6b5dc",
-           "fetch_kib": 8891.8, "write_kib": 16427.0, "fetch_scale": 2.000, "write_scale": 1.000}
+TRAFFIC = {"kernel": "k_fused2d<float,8,8,8,false,false>", "k_fuse": 8, "rows": 8, "waves": 8,
+           "src_sha1": "81314f257c03d4a51769c75ad3e8f1019245ff4b",
+           "fetch_kib": 8846.3, "write_kib": 16426.6, "fetch_scale": 2.000, "write_scale": 1.000}
 
 
 def log(*a):
