@@ -277,35 +277,54 @@ def run_cfg3(args, np, torch, wh, wl):
 
 
 def run_cfg4(args, np, torch, wh, wl):
-    """256 (64 per size) batched 2D solves of mixed sizes and frequencies, mixed precision in one
-    graph-replayed batch, against the same problems solved one by one with FP64 wh_solve."""
+    """256 (64 per size) 2D solves of mixed sizes and frequencies.  Baseline: the plain FP64
+    single-solve form (wh_solve, CG, one problem after another).  Batched forms: one
+    graph-replayed wh_solve_batched call, CG and DCG (the floor(3 omega / 2) sine modes
+    nearest omega^2 per problem), FP64 and mixed precision; FP64 single DCG for reference."""
     from oracle import discretization as disc
     probs = wl.config4(per_size=args.per_size)
     fs = [torch.from_numpy(q.f).cuda() for q in probs]
-    # one-by-one FP64 (a warm-up per grid size first)
+    nds = [int(math.floor(1.5 * q.omega)) for q in probs]
+    defl = [wh.sine_deflation(2, q.n, q.omega, nd) for q, nd in zip(probs, nds)]
     seen = set()
-    for f, q in zip(fs, probs):
+    for f, q in zip(fs, probs):     # warm-up (autotuner) per grid size
         if q.n not in seen:
-            wh.solve(f, q.omega, solver="cg", tol=1e-8, max_iters=100000)
+            for prec in ("f64", "mixed"):
+                wh.solve(f, q.omega, solver="cg", tol=1e-8, max_iters=100000, precision=prec)
             seen.add(q.n)
-    (singles), dt1 = _timed(torch, lambda: [wh.solve(f, q.omega, solver="cg", tol=1e-8, max_iters=100000)
-                                            for f, q in zip(fs, probs)])
-    out = {"workload": f"cfg4 batched {len(probs)} 2D solves n in 128..1024, omega~U(10,80), tol 1e-8",
-           "single_f64_seconds": dt1, "single_f64_iters": int(sum(i["iters"] for _, i in singles))}
-    for prec in ("mixed", "f64"):
-        (res), dt = _timed(torch, lambda: wh.solve_batched([(f, q.omega) for f, q in zip(fs, probs)],
-                                                           precision=prec, tol=1e-8, k_fuse=8, max_iters=100000))
-        us, infos = res
-        errs = []
+    out = {"workload": f"cfg4 {len(probs)} 2D solves n in 128..1024, omega~U(10,80), tol 1e-8",
+           "n_defl_rule": "floor(1.5 omega)"}
+    singles, dt1 = _timed(torch, lambda: [wh.solve(f, q.omega, solver="cg", tol=1e-8, max_iters=100000)
+                                          for f, q in zip(fs, probs)])
+    out["single_f64_cg_seconds"] = dt1
+    out["single_f64_cg_iters"] = int(sum(i["iters"] for _, i in singles))
+    sd, dtd = _timed(torch, lambda: [wh.solve(f, q.omega, solver="dcg", defl=d, tol=1e-8, max_iters=100000)
+                                     for f, q, d in zip(fs, probs, defl)])
+    out["single_f64_dcg_seconds"] = dtd
+    out["single_f64_dcg_iters"] = int(sum(i["iters"] for _, i in sd))
+
+    def errors(us):
+        e = []
         for u, q in zip(us, probs):
             U = disc.direct_solve_dst(2, q.n, q.omega, q.f)
-            errs.append(float(np.linalg.norm(u.cpu().numpy() - U) / np.linalg.norm(U)))
-        out[f"batched_{prec}"] = {"seconds": dt, "iters": int(sum(i["iters"] for i in infos)),
-                                  "max_true_rel_res": max(i["true_rel_res"] for i in infos),
-                                  "status_counts": {str(k): sum(1 for i in infos if i["status"] == k)
-                                                    for k in sorted(set(i["status"] for i in infos))},
-                                  "max_rel_err_vs_oracle": max(errs), "median_rel_err": float(np.median(errs)),
-                                  "speedup_vs_single_f64": dt1 / dt}
+            e.append(float(np.linalg.norm(u.cpu().numpy() - U) / np.linalg.norm(U)))
+        return e
+
+    for solver in ("dcg", "cg"):
+        for prec in ("mixed", "f64"):
+            kw = dict(precision=prec, tol=1e-8, k_fuse=8, max_iters=10000, solver=solver)
+            if solver == "dcg":
+                kw["n_defl"] = nds
+            (us, infos), dt = _timed(torch, lambda: wh.solve_batched([(f, q.omega) for f, q in zip(fs, probs)], **kw))
+            errs = errors(us)
+            out[f"batched_{solver}_{prec}"] = {
+                "seconds": dt, "iters": int(sum(i["iters"] for i in infos)),
+                "fp64_residual_solves": int(sum(i["outer"] for i in infos)),
+                "max_true_rel_res": max(i["true_rel_res"] for i in infos),
+                "status_counts": {str(k): sum(1 for i in infos if i["status"] == k)
+                                  for k in sorted(set(i["status"] for i in infos))},
+                "max_rel_err_vs_oracle": max(errs), "median_rel_err": float(np.median(errs)),
+                "speedup_vs_single_f64_cg": dt1 / dt, "speedup_vs_single_f64_dcg": dtd / dt}
     return out
 
 

@@ -94,8 +94,11 @@ typedef struct {
   int32_t restart;          /* GMRES restart length (default 40)                            */
   double tol;               /* stop when ||b - A u||_2 / ||b||_2 <= tol                      */
   int32_t max_iters;        /* solver iterations                                            */
-  double inner_tol;         /* WH_MIXED GMRES: relative tolerance of each FP32 inner restart
-                               cycle between FP64 residuals (1e-3)                          */
+  double inner_tol;         /* WH_MIXED, FP32 progress between FP64 residuals: GMRES, the
+                               relative tolerance of each FP32 inner restart cycle (0: 1e-3);
+                               CG/DCG, the residual reduction after which the recursive
+                               residual is replaced by the true one (0: 0.1 for CG, 1e-3
+                               for DCG and deflated batch problems)                         */
   int32_t max_outer;        /* WH_MIXED GMRES: FP64 refinement sweeps (default 30)           */
   int32_t k_fuse;           /* time steps per stencil launch; 0: library choice             */
   int32_t reproject;        /* DCG A-orthogonalisation against W each iteration (Algorithm 3,
@@ -144,6 +147,8 @@ typedef struct {
   const double* f;    /* device, nodal source                                               */
   double omega;       /* overrides common->omega                                            */
   double* u;          /* device, nodal; in: initial guess, out: solution                    */
+  int32_t n_defl;     /* wh_solve_batched with WH_DCG: deflate the n_defl analytic sine modes
+                         whose eigenvalues lie nearest omega^2 (c == 1 only); 0: none       */
 } wh_problem;
 
 /* ------------------------------------------------------------------ context */
@@ -202,14 +207,19 @@ wh_status wh_helmholtz_residual(wh_ctx* ctx, const wh_grid* grid, const double* 
 size_t wh_workspace_bytes_batched(int32_t nb, const wh_problem* probs, const wh_params* params);
 
 /* Solve nb independent 2D problems (grids of any size, own omega, source and
- * optional c2) with CG on the WaveHoltz system (Algorithm 3 without deflation),
- * in one device-driven batch: every problem's wave solves and Krylov updates are
- * advanced by shared launches captured in a hipGraph (the paper's motivation of
- * many right-hand sides and frequencies, Section 1).  probs: host array; each
+ * optional c2) with CG on the WaveHoltz system, in one device-driven batch: every
+ * problem's wave solves and Krylov updates are advanced by shared launches captured
+ * in a hipGraph (the paper's motivation of many right-hand sides and frequencies,
+ * Section 1).  params->solver WH_CG: Algorithm 3 without deflation.  WH_DCG:
+ * Algorithm 3 with each problem's n_defl sine modes nearest omega^2 as the
+ * deflation set (exact eigenvectors for c == 1, so the start x_0 = W (W^T A W)^{-1}
+ * W^T b is computed from the projections of f, and the iteration needs no
+ * re-projection); problems with n_defl == 0 run plain CG.  probs: host array; each
  * problem's omega overrides params->omega; u is output only (batched solves start
- * from zero).  All problems must have c2 or none; with c2, params->c_max must bound
- * c.  params->k_fuse in {2, 4, 8} sets the time steps per launch (0: 4).
- * infos: host array of nb (may be NULL).  Returns the worst status over problems. */
+ * from zero, or from x_0).  All problems must have c2 or none; with c2,
+ * params->c_max must bound c and n_defl must be 0.  params->k_fuse in {2, 4, 8}
+ * sets the time steps per launch (0: 4).  infos: host array of nb (may be NULL).
+ * Returns the worst status over problems. */
 wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
                            const wh_params* params, void* ws, size_t ws_bytes, wh_info* infos);
 

@@ -10,9 +10,12 @@ l2-orthonormal over the interior nodes (sum_i sin^2(p pi i/n) = n/2), with
     L_h Phi = -lam2 Phi,  lam2 = (4/h^2) sum_axes sin^2(k_axis pi h / 2)
 (eq. discreteEigenvalueProblem).  In 3D the factor is (2/n)^{3/2}.
 
-The deflation set takes the N_D modes whose lam2 lie nearest omega^2 (the
-Helmholtz resonance; Section 2.3: "deflate the eigenvectors with eigenvalues
-closest to omega"), ties broken by the mode index tuple in lexicographic order.
+The deflation set takes the N_D modes whose lam2 lie nearest omega^2, the
+Helmholtz resonance (Section 2.3 asks for the eigenvectors whose eigenvalues are
+closest to the frequency).  Distances are compared on a grid of 1e-9 omega^2, so
+that modes whose lam2 agree up to rounding (degenerate mode sets, summed in
+different orders) count as ties; ties are broken by the mode index tuple in
+lexicographic order.
 """
 from __future__ import annotations
 
@@ -44,8 +47,9 @@ def select_modes(dim: int, n: int, omega: float, n_defl: int):
         lam2 = e[P - 1] + e[Q - 1] + e[R - 1]
         tuples = np.stack([P.ravel(), Q.ravel(), R.ravel()], axis=1)
     dist = np.abs(lam2.ravel() - omega ** 2)
-    # lexicographic tie-break: sort by (dist, p, q[, r])
-    keys = [tuples[:, k] for k in range(dim - 1, -1, -1)] + [dist]
+    # distances on a grid of 1e-9 omega^2, then lexicographic tie-break: (dist, p, q[, r])
+    dq = np.floor(dist / (1e-9 * omega ** 2) + 0.5)
+    keys = [tuples[:, k] for k in range(dim - 1, -1, -1)] + [dq]
     order = np.lexsort(keys)[:n_defl]
     return [tuple(int(v) for v in tuples[i]) for i in order], lam2.ravel()[order]
 

@@ -262,14 +262,18 @@ def time_step_kernel(v, omega, c2=None, reps=50, shape=False, **kw):
     return us.value / 1e3
 
 
-def solve_batched(problems, workspace=None, **kw):
+def solve_batched(problems, workspace=None, n_defl=0, **kw):
     """Solve many 2D problems in one device-driven batch (wh_solve_batched).
 
     problems: sequence of (f, omega) or (f, omega, c2) with nodal float64 CUDA tensors.
-    Returns (list of solutions, list of info dicts)."""
+    n_defl: sine modes deflated per problem (an int for all, or one per problem; needs
+    solver="dcg" and c == 1).  Returns (list of solutions, list of info dicts)."""
     torch = _torch()
     lib = nat.load()
     nb = len(problems)
+    nds = [int(n_defl)] * nb if np.isscalar(n_defl) else [int(v) for v in n_defl]
+    if len(nds) != nb:
+        raise ValueError("n_defl needs one entry per problem")
     arr = (nat.WhProblem * nb)()
     outs = []
     ctx = None
@@ -285,6 +289,7 @@ def solve_batched(problems, workspace=None, **kw):
         arr[i].f = f.data_ptr()
         arr[i].omega = float(om)
         arr[i].u = u.data_ptr()
+        arr[i].n_defl = nds[i]
         if ctx is None:
             ctx = context(f.device.index)
     p = params(float(problems[0][1]), **kw)

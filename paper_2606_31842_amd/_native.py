@@ -51,7 +51,7 @@ class WhInfo(C.Structure):
 
 class WhProblem(C.Structure):
     _fields_ = [("grid", WhGrid), ("c2", C.c_void_p), ("f", C.c_void_p), ("omega", C.c_double),
-                ("u", C.c_void_p)]
+                ("u", C.c_void_p), ("n_defl", C.c_int32)]
 
 
 P = C.POINTER

@@ -337,6 +337,7 @@ int wave_solve(const WaveOp& op, const double* vin, bool force, StepMode last, c
   for (int k = nn; k < tp.nt; ++k) {
     a.cur = cur;
     a.prev = prev;
+    a.cur_next = oc;   // FP32: W^{n+1} goes to a free buffer, D is updated in place
     a.cosn = tp.cosv[k];
     a.wn = tp.w[k + 1];
     a.x = x;
@@ -344,7 +345,8 @@ int wave_solve(const WaveOp& op, const double* vin, bool force, StepMode last, c
     a.partials = op.partials;
     const StepMode md = (k == tp.nt - 1) ? last : M_MID;
     nblk = launch_step(op.dim, op.f32, op.varc, force, md, a, s);
-    std::swap(cur, prev);
+    if (op.f32) std::swap(cur, oc);
+    else std::swap(cur, prev);
   }
   return nblk;
 }
@@ -384,6 +386,7 @@ int autotune_k(wh_ctx* ctx, const WaveOp& op, bool force, int k_fixed = 0) {
           a.a = op.a;
           a.cur = op.Wb;
           a.prev = op.Wa;
+          a.cur_next = op.Wc;
           a.V = op.V;
           a.cosn = tp.cosv[1];
           a.wn = tp.w[2];
@@ -443,6 +446,7 @@ struct Solver {
   int iters = 0;
   bool defect = true;              // FP32 A-applies in the defect form
   double om2dt2 = 0;               // omega^2 dt^2
+  double reliable_drop = 0.1;  // mixed CG: residual reduction between FP64 replacements
 };
 
 // q = A x (x nonzero).  Leaves partial sums of x.q in op.partials.
@@ -479,13 +483,12 @@ struct KrylovResult {
 // ||r|| <= tol * ||rhs||.  Uses S.partials for step partials.
 //
 // reliable = true (mixed precision): the recurrence applies the FP32-stepped operator,
-// and whenever the recursive residual has fallen by kReliableDrop since the last
-// replacement (or looks converged) it is replaced by the true residual rhs - A x
-// computed with an FP64 wave solve, beta being formed from the replaced residual.
-// The CG recurrence itself is never restarted.  If two consecutive replacements do
-// not halve the true residual, the FP32 operator error is too large for this
-// problem and the remaining iterations apply the FP64 operator.
-constexpr double kReliableDrop = 0.1;
+// and whenever the recursive residual has fallen by the factor S.reliable_drop since
+// the last replacement, has grown tenfold, or looks converged, it is replaced by the
+// true residual rhs - A x computed with an FP64 wave solve, beta being formed from the
+// replaced residual.  The CG recurrence itself is never restarted.  If two
+// consecutive replacements do not halve the true residual, the FP32 operator error
+// is too large for this problem and the remaining iterations apply the FP64 operator.
 
 wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_nonzero, double* r,
                    double* p, double* q, double tol, int maxit, bool use_defl, bool reproject,
@@ -552,7 +555,7 @@ wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_non
         WH_FAIL(ctx, WH_EUNSTABLE, "non-finite p^T A p or residual at iteration %d", k + 1);
       if (pq == 0.0) WH_FAIL(ctx, WH_EBREAKDOWN, "CG breakdown: p^T A p = 0 at iteration %d", k + 1);
       rel = std::sqrt(r2 / nb2);
-      if (rel <= kReliableDrop * anchor || rel >= anchor / kReliableDrop || rel <= tol ||
+      if (rel <= S.reliable_drop * anchor || rel >= 10.0 * anchor || rel <= tol ||
           k + 1 - last_repl >= 500) {
         applyA(S, false, x, q);
         launch_sub(r, rhs, q, N, S.s);
@@ -811,6 +814,9 @@ wh_status setup_ops(wh_ctx* ctx, const wh_grid& g, const wh_params& P, const dou
   // defect form by default for CG/GMRES; DCG has removed the near-resonant modes, where
   // the defect form gains, so it steps W directly (one stencil pass less per iteration)
   S.defect = P.mixed_form == 0 || (P.mixed_form < 0 && P.solver != WH_DCG);
+  // exact deflation removes the near-resonant modes whose FP32 error would slow CG, so
+  // DCG can go longer between FP64 residual replacements
+  S.reliable_drop = (P.inner_tol > 0 && P.inner_tol < 1) ? P.inner_tol : (P.solver == WH_DCG ? 1e-3 : 0.1);
   S.op32 = base;
   S.op32.f32 = true;
   if (mixed) {
@@ -865,7 +871,7 @@ void wh_params_default(wh_params* p) {
   p->restart = 40;
   p->tol = 1e-8;
   p->max_iters = 10000;
-  p->inner_tol = 1e-3;
+  p->inner_tol = 0.0;
   p->max_outer = 30;
   p->k_fuse = 0;
   p->reproject = -1;
@@ -950,39 +956,90 @@ wh_status wh_select_sine_modes(int32_t dim, int32_t n, double omega, int32_t n_d
   if ((dim != 2 && dim != 3) || n < 4 || n_d < 0 || !(omega > 0) || (n_d > 0 && !modes))
     return WH_EINVAL;
   const double h = 1.0 / n;
-  std::vector<double> e(n);
+  const int K = n - 1;
+  if ((int64_t)K * K * (dim == 3 ? K : 1) < n_d) return WH_EINVAL;
+  std::vector<double> e(n);   // e[k] = lambda_k^2 of the 1D Dirichlet Laplacian, increasing in k
   for (int k = 1; k < n; ++k) {
     const double sv = std::sin(M_PI * k * h / 2.0);
     e[k] = 4.0 / (h * h) * sv * sv;
   }
   const double om2 = omega * omega;
-  struct Cand {
-    double dist, lam2;
+  // The n_d modes with the smallest |lambda^2 - omega^2|, the distance taken on a grid of
+  // 1e-9 omega^2 so that modes whose lambda^2 agree up to rounding (degenerate sets
+  // summed in different orders) tie; ties in lexicographic order of the mode numbers.
+  // For fixed leading mode numbers the distance grows monotonically
+  // as the last mode number moves away from the crossing point of omega^2, so each
+  // leading tuple gives two sorted streams (downwards and upwards from the crossing);
+  // a heap merges the streams in (distance, mode numbers) order.
+  struct Item {
+    double dist;
     int k[3];
+    int dir;  // -1: last mode number decreasing, +1: increasing
   };
-  std::vector<Cand> c;
-  const int K = n - 1;
-  if ((int64_t)K * K * (dim == 3 ? K : 1) < n_d) return WH_EINVAL;
-  // Enumerate in lexicographic order; keep all (the sort below is stable).
+  auto later = [&](const Item& a, const Item& b) {   // heap order: smallest key on top
+    if (a.dist != b.dist) return a.dist > b.dist;
+    for (int t = 0; t < dim; ++t)
+      if (a.k[t] != b.k[t]) return a.k[t] > b.k[t];
+    return false;
+  };
+  const double quantum = 1e-9 * om2;
+  auto dist_of = [&](const int* k) {
+    double l2 = e[k[0]] + e[k[1]];
+    if (dim == 3) l2 += e[k[2]];
+    return std::floor(std::fabs(l2 - om2) / quantum + 0.5);
+  };
+  std::vector<Item> heap;
+  auto push_streams = [&](int a, int b) {   // leading mode numbers (a) or (a, b)
+    double lead = e[a] + (dim == 3 ? e[b] : 0.0);
+    const double t = om2 - lead;
+    // first last-mode number with e >= t
+    const int j = (int)(std::lower_bound(e.begin() + 1, e.end(), t) - e.begin());
+    const int last = dim - 1;
+    if (j - 1 >= 1) {
+      Item it{};
+      it.k[0] = a;
+      if (dim == 3) it.k[1] = b;
+      it.k[last] = j - 1;
+      it.dir = -1;
+      it.dist = dist_of(it.k);
+      heap.push_back(it);
+      std::push_heap(heap.begin(), heap.end(), later);
+    }
+    if (j <= K) {
+      Item it{};
+      it.k[0] = a;
+      if (dim == 3) it.k[1] = b;
+      it.k[last] = j;
+      it.dir = 1;
+      it.dist = dist_of(it.k);
+      heap.push_back(it);
+      std::push_heap(heap.begin(), heap.end(), later);
+    }
+  };
   if (dim == 2) {
-    c.reserve((size_t)K * K);
-    for (int p = 1; p <= K; ++p)
-      for (int q = 1; q <= K; ++q) {
-        double l2 = e[p] + e[q];
-        c.push_back({std::fabs(l2 - om2), l2, {p, q, 0}});
-      }
+    for (int a = 1; a <= K; ++a) push_streams(a, 0);
   } else {
-    for (int p = 1; p <= K; ++p)
-      for (int q = 1; q <= K; ++q)
-        for (int r = 1; r <= K; ++r) {
-          double l2 = e[p] + e[q] + e[r];
-          c.push_back({std::fabs(l2 - om2), l2, {p, q, r}});
-        }
+    for (int a = 1; a <= K; ++a)
+      for (int b = 1; b <= K; ++b) push_streams(a, b);
   }
-  std::stable_sort(c.begin(), c.end(), [](const Cand& a, const Cand& b) { return a.dist < b.dist; });
+  const int last = dim - 1;
   for (int i = 0; i < n_d; ++i) {
-    for (int a = 0; a < dim; ++a) modes[i * dim + a] = c[i].k[a];
-    if (lambda2) lambda2[i] = c[i].lam2;
+    std::pop_heap(heap.begin(), heap.end(), later);
+    Item it = heap.back();
+    heap.pop_back();
+    for (int a = 0; a < dim; ++a) modes[i * dim + a] = it.k[a];
+    if (lambda2) {
+      double l2 = e[it.k[0]] + e[it.k[1]];
+      if (dim == 3) l2 += e[it.k[2]];
+      lambda2[i] = l2;
+    }
+    const int nxt = it.k[last] + it.dir;
+    if (nxt >= 1 && nxt <= K) {
+      it.k[last] = nxt;
+      it.dist = dist_of(it.k);
+      heap.push_back(it);
+      std::push_heap(heap.begin(), heap.end(), later);
+    }
   }
   return WH_OK;
 }
@@ -1284,6 +1341,7 @@ wh_status wh_time_step_kernel(wh_ctx* ctx, const wh_grid* grid, const double* c2
       a.a = op.a;
       a.cur = (r & 1) ? op.Wa : op.Wb;
       a.prev = (r & 1) ? op.Wb : op.Wa;
+      a.cur_next = op.Wc;
       a.V = op.V;
       a.cosn = tp.cosv[1];
       a.wn = tp.w[2];

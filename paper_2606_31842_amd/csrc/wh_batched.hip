@@ -9,7 +9,7 @@
 // its phase, time-step counter and Krylov scalars in device memory:
 //
 //   B_FIRST -> B_STEP* -> B_LAST         b = Pi_h(0; f)                        (FP64)
-//   INIT                                 r = p = b
+//   INIT                                 r = p = b - A x_0, partial r.r
 //   A_FIRST -> A_STEP* -> A_LAST         q = A p, partial sums of p.q          (CG precision)
 //   UPD1                                 x += alpha p, r -= alpha q, partial r.r
 //   R_FIRST -> R_STEP* -> R_LAST         r = b - A x, partial r.r              (FP64)
@@ -23,6 +23,13 @@
 // and the convergence state and advances the phase.  Rounds contain no host
 // decisions, so the host captures several of them in one hipGraph and replays it,
 // reading back one counter of unfinished problems per replay.
+//
+// Deflated problems (c = 1, n_defl sine modes W nearest omega^2) start from
+// x_0 = W (W^T A W)^{-1} W^T b.  With exact eigenvectors this is the projection of the
+// solution onto span W, W^T u = (omega^2 - lambda^2)^{-1} W^T f, and A x_0 =
+// W diag(mu) W^T u: the host computes both from f before the batch (x_0 into x,
+// A x_0 into q) and INIT forms r_0 = b - A x_0.  r_0 is orthogonal to W, and CG
+// continues without re-projection (Algorithm 3 with exact eigenvectors).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -44,7 +51,7 @@ enum BPhase : int {
 };
 
 struct BDesc {
-  int n, nt, ntx, nty, tile0, mixed, max_iters, max_outer, defect, pad0;
+  int n, nt, ntx, nty, tile0, mixed, max_iters, max_outer, defect, x0;  // x0: start from x_0, A x_0 in q
   double a, tol, itol, om2dt2;   // om2dt2 = (omega dt)^2 of the fixed point
   double *x, *b, *r, *p, *q, *V;
   void* W[4];                 // FP64 (prev, cur) pairs 0 and 1; 8 bytes per node each
@@ -95,8 +102,9 @@ __device__ __forceinline__ const double* fs_of<double>(const BDesc& D) { return 
 template <>
 __device__ __forceinline__ const float* fs_of<float>(const BDesc& D) { return D.fs32; }
 
-// 5-point update at interior node p from state arrays (global reads).
-template <typename T, bool VARC>
+// dt^2 L_h W at interior node p from state arrays (global reads); DIFF sums the
+// constant-c stencil as differences to the centre (FP32 increment form).
+template <typename T, bool VARC, bool DIFF>
 __device__ __forceinline__ T lap_term(const T* c, const T* kap, int64_t p, int64_t P, T A) {
   const T cc = c[p];
   if (VARC) {
@@ -104,6 +112,7 @@ __device__ __forceinline__ T lap_term(const T* c, const T* kap, int64_t p, int64
     return (kc + kap[p - 1]) * (c[p - 1] - cc) + (kc + kap[p + 1]) * (c[p + 1] - cc) +
            ((kc + kap[p - P]) * (c[p - P] - cc) + (kc + kap[p + P]) * (c[p + P] - cc));
   }
+  if (DIFF) return A * (((c[p - 1] - cc) + (c[p + 1] - cc)) + ((c[p - P] - cc) + (c[p + P] - cc)));
   return A * (((c[p - 1] + c[p + 1]) + (c[p - P] + c[p + P])) - T(4) * cc);
 }
 
@@ -115,6 +124,9 @@ __global__ __launch_bounds__(64 * NW) void k_batch_work(const BDesc* __restrict_
   constexpr int TXO = 64 - 2 * K;
   constexpr int TYO = NW * R - 2 * K;
   constexpr int NT = 64 * NW;
+  // FP32 state pairs are (W^n, D^{n-1/2} = W^n - W^{n-1}), stepped in the increment form
+  // D += dt^2 (L_h W - f cos), W += D; FP64 pairs are (W^n, W^{n-1}).
+  constexpr bool INC = sizeof(T) == 4;
   const int gt = xcd_tile_b(blockIdx.x, ntiles);
   const int sid = tile_solve[gt];
   const BDesc& D = descs[sid];
@@ -143,10 +155,12 @@ __global__ __launch_bounds__(64 * NW) void k_batch_work(const BDesc* __restrict_
 
   switch (ph) {
     case BP_INIT: {
+      reduce = true;
       TILE_FOR(p) {
-        const double v = D.b[p];
+        const double v = D.x0 ? D.b[p] - D.q[p] : D.b[p];
         D.r[p] = v;
         D.p[p] = v;
+        acc += v * v;
       }
       break;
     }
@@ -186,7 +200,7 @@ __global__ __launch_bounds__(64 * NW) void k_batch_work(const BDesc* __restrict_
           const T fsv = (T)(-(lap + D.om2dt2 * pc));
           fso[p] = fsv;
           const T w1 = T(-0.5) * fsv;
-          w0o[p] = T(0);
+          w0o[p] = w1;           // FP32 pair: D^{1/2} = W^1 - W^0 = W^1
           w1o[p] = w1;
           D.V[p] = D.w[1] * (double)w1;
         }
@@ -215,15 +229,25 @@ __global__ __launch_bounds__(64 * NW) void k_batch_work(const BDesc* __restrict_
             const T kc = kap[p];
             lap = (kc + kap[p - 1]) * (wv - c) + (kc + kap[p + 1]) * (ev - c) +
                   ((kc + kap[p - P]) * (sv - c) + (kc + kap[p + P]) * (nv - c));
+          } else if (INC) {
+            lap = A * (((wv - c) + (ev - c)) + ((sv - c) + (nv - c)));
           } else {
             lap = A * (((wv + ev) + (sv + nv)) - T(4) * c);
           }
         }
         if (force) lap -= (T)D.cosv[0] * fs[p];
-        const T w1 = c + T(0.5) * lap;
-        w0o[p] = c;
-        w1o[p] = w1;
-        D.V[p] = D.w[0] * (src ? src[p] : 0.0) + D.w[1] * (double)w1;
+        if (INC) {               // FP32 pair (W^1, D^{1/2})
+          const T d = T(0.5) * lap;
+          const T w1 = c + d;
+          w0o[p] = d;
+          w1o[p] = w1;
+          D.V[p] = D.w[0] * (src ? src[p] : 0.0) + D.w[1] * (double)w1;
+        } else {
+          const T w1 = c + T(0.5) * lap;
+          w0o[p] = c;
+          w1o[p] = w1;
+          D.V[p] = D.w[0] * (src ? src[p] : 0.0) + D.w[1] * (double)w1;
+        }
       }
       break;
     }
@@ -241,8 +265,15 @@ __global__ __launch_bounds__(64 * NW) void k_batch_work(const BDesc* __restrict_
       const bool defect = sizeof(T) == 4 && D.defect && ph == BP_A_LAST;
       reduce = true;
       TILE_FOR(p) {
-        T nw = (cur[p] + cur[p]) - prv[p] + lap_term<T, VARC>(cur, kap, p, P, A);
-        if (ph == BP_B_LAST || defect) nw -= cn * fs[p];
+        T nw;
+        if (INC) {
+          T lap = lap_term<T, VARC, true>(cur, kap, p, P, A);
+          if (ph == BP_B_LAST || defect) lap -= cn * fs[p];
+          nw = cur[p] + (prv[p] + lap);
+        } else {
+          nw = (cur[p] + cur[p]) - prv[p] + lap_term<T, VARC, false>(cur, kap, p, P, A);
+          if (ph == BP_B_LAST || defect) nw -= cn * fs[p];
+        }
         const double vf = D.V[p] + wn * (double)nw;
         if (ph == BP_B_LAST) {
           D.b[p] = vf;
@@ -323,31 +354,57 @@ __global__ __launch_bounds__(64 * NW) void k_batch_work(const BDesc* __restrict_
         const T dn_e = wv < NW - 1 ? edge[bb][wv + 1][0][lane] : T(0);
         const T cn = (T)D.cosv[S.step + s];
         const double ws = D.w[S.step + s + 1];
+        if constexpr (INC) {
+          T uo = up_e;             // old value of the row above (overwritten in place)
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const T c = cur[r];
-          const T u = r > 0 ? cur[r - 1] : up_e;
-          const T dd = r < R - 1 ? cur[r + 1] : dn_e;
-          const T w = from_prev_lane(c);
-          const T e = from_next_lane(c);
-          T nw;
-          if (VARC) {
-            const int q = VARC ? r : 0;
-            nw = (c + c) - prv[r] +
-                 (cw[q] * (w - c) + ce[q] * (e - c) + (cu[q] * (u - c) + cd[q] * (dd - c)));
-          } else {
-            nw = (c + c) - prv[r] + A * (((w + e) + (u + dd)) - T(4) * c);
+          for (int r = 0; r < R; ++r) {
+            const T c = cur[r];
+            const T dd = r < R - 1 ? cur[r + 1] : dn_e;
+            const T w = from_prev_lane(c);
+            const T e = from_next_lane(c);
+            T lap;
+            if (VARC) {
+              const int q = VARC ? r : 0;
+              lap = (cw[q] * (w - c) + ce[q] * (e - c)) + (cu[q] * (uo - c) + cd[q] * (dd - c));
+            } else {
+              lap = A * (((w - c) + (e - c)) + ((uo - c) + (dd - c)));
+            }
+            lap -= cn * frc[r];
+            // outside the open domain W = D = 0: masking D suffices, branch-free
+            const T dn = __int_as_float(__float_as_int(prv[r] + lap) & (int)(0u - ((mask >> r) & 1u)));
+            const T nw = c + dn;
+            prv[r] = dn;
+            uo = c;
+            cur[r] = nw;
+            ac[r] += ws * (double)nw;
           }
-          nw -= cn * frc[r];
-          nw = ((mask >> r) & 1u) ? nw : T(0);
-          prv[r] = nw;            // rows r+1.. still read the old cur[r]
-          ac[r] += ws * (double)nw;
-        }
+        } else {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const T tmp = cur[r];
-          cur[r] = prv[r];
-          prv[r] = tmp;
+          for (int r = 0; r < R; ++r) {
+            const T c = cur[r];
+            const T u = r > 0 ? cur[r - 1] : up_e;
+            const T dd = r < R - 1 ? cur[r + 1] : dn_e;
+            const T w = from_prev_lane(c);
+            const T e = from_next_lane(c);
+            T nw;
+            if (VARC) {
+              const int q = VARC ? r : 0;
+              nw = (c + c) - prv[r] +
+                   (cw[q] * (w - c) + ce[q] * (e - c) + (cu[q] * (u - c) + cd[q] * (dd - c)));
+            } else {
+              nw = (c + c) - prv[r] + A * (((w + e) + (u + dd)) - T(4) * c);
+            }
+            nw -= cn * frc[r];
+            nw = ((mask >> r) & 1u) ? nw : T(0);
+            prv[r] = nw;            // rows r+1.. still read the old cur[r]
+            ac[r] += ws * (double)nw;
+          }
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const T tmp = cur[r];
+            cur[r] = prv[r];
+            prv[r] = tmp;
+          }
         }
       }
 #pragma unroll
@@ -379,7 +436,7 @@ __global__ __launch_bounds__(256) void k_batch_control(const BDesc* __restrict__
   BState& S = states[sid];
   const int ph = S.phase;
   if (ph == BP_DONE) return;
-  const bool red = ph == BP_B_LAST || ph == BP_A_LAST || ph == BP_R_LAST || ph == BP_UPD1;
+  const bool red = ph == BP_B_LAST || ph == BP_INIT || ph == BP_A_LAST || ph == BP_R_LAST || ph == BP_UPD1;
   double sum = 0.0;
   if (red) {
     double acc = 0.0;
@@ -422,11 +479,25 @@ __global__ __launch_bounds__(256) void k_batch_control(const BDesc* __restrict__
         S.phase = BP_INIT;
       }
       break;
-    case BP_INIT:
-      S.r2 = S.nb2;
-      S.prev_rel = 1.0;       // relative true residual at the last replacement
-      S.phase = BP_A_FIRST;
+    case BP_INIT: {
+      // r_0 = b (no start vector) or b - A x_0 (deflated start), both exact in FP64
+      const double rel = sqrt(sum / S.nb2);
+      S.r2 = sum;
+      S.rel = rel;
+      S.prev_rel = rel;       // relative true residual at the last replacement
+      if (!isfinite(rel)) {
+        S.status = WH_EUNSTABLE;
+        S.phase = BP_DONE;
+      } else if (rel <= D.tol) {
+        // the start already meets the tolerance: report its true residual
+        S.status = WH_OK;
+        S.pq = sum;
+        S.phase = BP_R_FIRST;
+      } else {
+        S.phase = BP_A_FIRST;
+      }
       break;
+    }
     case BP_A_LAST:
       S.pq = sum;
       if (!isfinite(sum)) {
@@ -459,7 +530,7 @@ __global__ __launch_bounds__(256) void k_batch_control(const BDesc* __restrict__
         } else {
           S.phase = BP_UPD2;
         }
-      } else if (rel <= 0.1 * S.prev_rel || rel >= 10.0 * S.prev_rel || rel <= D.tol || cap ||
+      } else if (rel <= D.itol * S.prev_rel || rel >= 10.0 * S.prev_rel || rel <= D.tol || cap ||
                  S.iters - S.last_repl >= 500) {
         S.pq = r2_old;                 // kept for beta after the replacement
         S.phase = BP_R_FIRST;
@@ -587,6 +658,25 @@ static size_t problem_bytes(int n, int nt, int K, bool mixed, bool varc) {
   return b;
 }
 
+// Scratch for the deflated start of one problem (reused problem by problem): sine
+// tables, projection partials, mode numbers, two scale vectors and two coefficient sets.
+static size_t defl_scratch_bytes(int n, int nd) {
+  if (nd <= 0) return 0;
+  Defl dl;
+  dl.kind = WH_DEFL_SINE;
+  dl.nd = nd;
+  dl.dim = 2;
+  dl.n = n;
+  size_t b = 0;
+  auto add = [&](size_t x) { b += (x + 255) & ~(size_t)255; };
+  add(8 * (size_t)nd * 2 * (n + 1));
+  add(8 * (size_t)defl_partial_blocks(dl) * nd);
+  add(4 * (size_t)nd * 2);
+  add(8 * (size_t)nd * 2);
+  add(8 * (size_t)nd * 2);
+  return b;
+}
+
 }  // namespace wh
 
 using namespace wh;
@@ -616,7 +706,8 @@ struct Prepared {
 wh_status batch_validate(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const wh_params* P) {
   if (nb < 1 || !probs || !P) WHB_FAIL(ctx, WH_EINVAL, "need nb >= 1 problems and params");
   if (P->precision != WH_F64 && P->precision != WH_MIXED) WHB_FAIL(ctx, WH_EINVAL, "bad precision");
-  if (P->solver != WH_CG) WHB_FAIL(ctx, WH_EUNSUPPORTED, "batched solves use CG");
+  if (P->solver != WH_CG && P->solver != WH_DCG)
+    WHB_FAIL(ctx, WH_EUNSUPPORTED, "batched solves use CG or DCG");
   if (!(P->tol > 0)) WHB_FAIL(ctx, WH_EINVAL, "tol must be > 0");
   const bool varc0 = probs[0].c2 != nullptr;
   for (int i = 0; i < nb; ++i) {
@@ -628,6 +719,12 @@ wh_status batch_validate(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const
     if (!q.f || !q.u) WHB_FAIL(ctx, WH_EINVAL, "f / u is NULL (problem %d)", i);
     if ((q.c2 != nullptr) != varc0)
       WHB_FAIL(ctx, WH_EUNSUPPORTED, "all problems of a batch must have c2 or none");
+    if (q.n_defl < 0 || (int64_t)q.n_defl > (int64_t)(q.grid.n - 1) * (q.grid.n - 1))
+      WHB_FAIL(ctx, WH_EINVAL, "bad n_defl (problem %d)", i);
+    if (q.n_defl > 0 && P->solver != WH_DCG)
+      WHB_FAIL(ctx, WH_EINVAL, "n_defl > 0 needs solver WH_DCG (problem %d)", i);
+    if (q.n_defl > 0 && q.c2)
+      WHB_FAIL(ctx, WH_EUNSUPPORTED, "sine-mode deflation needs c == 1 (problem %d)", i);
   }
   if (varc0 && !(P->c_max > 0))
     WHB_FAIL(ctx, WH_EINVAL, "batched solves with variable c need params->c_max > 0");
@@ -635,6 +732,78 @@ wh_status batch_validate(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const
 }
 
 int batch_K(const wh_params* P) { return batch_k_ok(P->k_fuse) ? P->k_fuse : 4; }
+
+// Copy host data to the device through the context's pinned block (synchronous).
+wh_status stage_to_device(wh_ctx* ctx, void* dev, const void* host, size_t bytes, hipStream_t s) {
+  const size_t chunk = sizeof(double) * (size_t)ctx->hbuf_len;
+  for (size_t o = 0; o < bytes; o += chunk) {
+    const size_t cnt = std::min(bytes - o, chunk);
+    HIPB(ctx, hipStreamSynchronize(s));
+    std::memcpy(ctx->hbuf, (const char*)host + o, cnt);
+    HIPB(ctx, hipMemcpyAsync((char*)dev + o, ctx->hbuf, cnt, hipMemcpyHostToDevice, s));
+  }
+  HIPB(ctx, hipStreamSynchronize(s));
+  return WH_OK;
+}
+
+// Deflated start of one c = 1 problem: with the n_defl sine modes phi_k nearest
+// omega^2 (eigenvectors of L_h, L_h phi_k = -lambda_k^2 phi_k, and of A with
+// mu_k = 1 - beta_h(lambda_k^2)), the fixed point's coefficients are
+// c_k = phi_k^T f / (omega_fp^2 - lambda_k^2); x = sum c_k phi_k, q = A x = sum mu_k c_k phi_k.
+// x and q must be zero on entry.
+wh_status deflated_start(wh_ctx* ctx, const wh_problem& pr, const TimeParams& tp, BDesc& d,
+                         char* scratch, hipStream_t s) {
+  const int n = pr.grid.n, nd = pr.n_defl;
+  const int64_t N = (int64_t)(n + 1) * (n + 1);
+  Defl dl;
+  dl.kind = WH_DEFL_SINE;
+  dl.nd = nd;
+  dl.dim = 2;
+  dl.n = n;
+  const int blocks = defl_partial_blocks(dl);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = scratch + off;
+    off += (bytes + 255) & ~(size_t)255;
+    return (void*)p;
+  };
+  double* tab = (double*)take(8 * (size_t)nd * 2 * (n + 1));
+  double* partials = (double*)take(8 * (size_t)blocks * nd);
+  int32_t* modes_dev = (int32_t*)take(4 * (size_t)nd * 2);
+  double* scales = (double*)take(8 * (size_t)nd * 2);
+  double* coef = (double*)take(8 * (size_t)nd * 2);
+  std::vector<int32_t> modes(2 * (size_t)nd);
+  std::vector<double> lam2(nd);
+  if (wh_select_sine_modes(2, n, pr.omega, nd, modes.data(), lam2.data()) != WH_OK)
+    WHB_FAIL(ctx, WH_EINVAL, "sine mode selection failed (n = %d, n_defl = %d)", n, nd);
+  // the frequency whose Helmholtz problem the fixed point solves: (2/dt) sin(omega_w dt / 2)
+  const double sh = std::sin(0.5 * tp.omega_w * tp.dt);
+  const double om2 = 4.0 * sh * sh / (tp.dt * tp.dt);
+  std::vector<double> sc(2 * (size_t)nd);
+  for (int k = 0; k < nd; ++k) {
+    const double den = om2 - lam2[k];
+    if (den == 0.0) WHB_FAIL(ctx, WH_EBREAKDOWN, "sine mode %d is at resonance", k);
+    const double mu = 1.0 - transfer(tp, lam2[k]);
+    // launch_defl_combine subtracts sum_k slot_k phi_k: store the negated coefficients
+    sc[k] = -1.0 / den;
+    sc[nd + k] = -mu / den;
+  }
+  wh_status st = stage_to_device(ctx, modes_dev, modes.data(), 4 * modes.size(), s);
+  if (st != WH_OK) return st;
+  st = stage_to_device(ctx, scales, sc.data(), 8 * sc.size(), s);
+  if (st != WH_OK) return st;
+  launch_sine_tables(tab, modes_dev, nd, 2, n, s);
+  dl.tab = tab;
+  launch_defl_project(dl, pr.f, partials, s);
+  launch_defl_reduce(partials, blocks, nd, coef, 0, scales, s);
+  launch_defl_reduce(partials, blocks, nd, coef, nd, scales + nd, s);
+  launch_defl_combine(dl, d.x, 1.0, nullptr, 0.0, coef, 0, N, s);
+  launch_defl_combine(dl, d.q, 1.0, nullptr, 0.0, coef, nd, N, s);
+  HIPB(ctx, hipStreamSynchronize(s));
+  HIPB(ctx, hipGetLastError());
+  d.x0 = 1;
+  return WH_OK;
+}
 
 }  // namespace
 
@@ -656,6 +825,9 @@ size_t wh_workspace_bytes_batched(int32_t nb, const wh_problem* probs, const wh_
     total += problem_bytes(probs[i].grid.n, tp.nt, K, mixed, varc);
     ntiles += tile_dim(probs[i].grid.n, K, 0) * tile_dim(probs[i].grid.n, K, 1);
   }
+  size_t dscr = 0;
+  for (int i = 0; i < nb; ++i) dscr = std::max(dscr, defl_scratch_bytes(probs[i].grid.n, probs[i].n_defl));
+  total += dscr;
   total += 16 * (size_t)kReduceBlocks;  // c_max reductions (multiple of 256)
   total += ((sizeof(BDesc) * nb + 255) & ~(size_t)255) + ((sizeof(BState) * nb + 255) & ~(size_t)255);
   total += ((4 * (size_t)ntiles + 255) & ~(size_t)255) + 256;
@@ -714,8 +886,11 @@ wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
     const double h = 1.0 / n;
     d.a = tps[i].dt * tps[i].dt / (h * h);
     d.tol = params->tol;
-    d.itol = params->inner_tol > 0 ? params->inner_tol : 1e-3;
-    d.defect = params->mixed_form != 1;
+    d.itol = (params->inner_tol > 0 && params->inner_tol < 1) ? params->inner_tol
+                                                              : (probs[i].n_defl > 0 ? 1e-3 : 0.1);
+    // FP32 A-apply: the defect form for undeflated problems (near-resonant modes present),
+    // direct stepping when the near-resonant modes are deflated
+    d.defect = params->mixed_form == 0 || (params->mixed_form < 0 && probs[i].n_defl == 0);
     d.om2dt2 = 4.0 * std::sin(0.5 * tps[i].omega_w * tps[i].dt) * std::sin(0.5 * tps[i].omega_w * tps[i].dt);
     for (int k = 0; k < 4; ++k) d.W[k] = take(8 * N);
     if (mixed)
@@ -740,6 +915,9 @@ wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
     d.cosv = wtab + d.nt + 1;
   }
   const int ntiles = (int)tile_solve.size();
+  size_t dscr = 0;
+  for (int i = 0; i < nb; ++i) dscr = std::max(dscr, defl_scratch_bytes(probs[i].grid.n, probs[i].n_defl));
+  char* dscratch = dscr ? (char*)take(dscr) : nullptr;
   BDesc* ddesc = (BDesc*)take(sizeof(BDesc) * nb);
   BState* dstate = (BState*)take(sizeof(BState) * nb);
   int* dtiles = (int*)take(4 * (size_t)ntiles);
@@ -778,6 +956,10 @@ wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
       HIPB(ctx, hipMemcpyAsync(wtab + o, ctx->hbuf, cnt * sizeof(double), hipMemcpyHostToDevice, s));
     }
     HIPB(ctx, hipStreamSynchronize(s));
+    if (probs[i].n_defl > 0) {
+      wh_status ds = deflated_start(ctx, probs[i], tps[i], d, dscratch, s);
+      if (ds != WH_OK) return ds;
+    }
   }
   // upload descriptors, tile table and the initial states (synchronous copies from host memory)
   HIPB(ctx, hipMemcpyAsync(ddesc, D.data(), sizeof(BDesc) * nb, hipMemcpyHostToDevice, s));
@@ -789,22 +971,40 @@ wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
   HIPB(ctx, hipStreamSynchronize(s));
   HIPB(ctx, hipGetLastError());
 
-  // capture G rounds + the counter in one graph on a private stream
-  const int G = 16;
+  // Capture G rounds + the counter in a graph on a private stream, twice (two
+  // executables whose counters go to different slots).  Replays alternate between
+  // them and the host keeps one replay queued ahead: it reads the counter of replay
+  // k while replay k+1 runs, so the GPU does not wait for the host between replays.
+  // Rounds of finished problems return at once, so the replay that runs past the
+  // end costs little.
+  const int G = 32;
   hipStream_t cs;
   HIPB(ctx, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-  if (e == hipSuccess) {
-    for (int g = 0; g < G; ++g) launch_round(K, varc, nb, ddesc, dstate, dtiles, ntiles, cs);
-    hipLaunchKernelGGL(k_batch_count, dim3(1), dim3(256), 0, cs, (const BState*)dstate, nb, dremain);
-    e = hipStreamEndCapture(cs, &graph);
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int* dcount[2] = {dremain, dremain + 32};
+  hipError_t e = hipSuccess;
+  for (int gi = 0; gi < 2 && e == hipSuccess; ++gi) {
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      for (int g = 0; g < G; ++g) launch_round(K, varc, nb, ddesc, dstate, dtiles, ntiles, cs);
+      hipLaunchKernelGGL(k_batch_count, dim3(1), dim3(256), 0, cs, (const BState*)dstate, nb, dcount[gi]);
+      e = hipStreamEndCapture(cs, &graph[gi]);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec[gi], graph[gi], nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[gi], hipEventDisableTiming);
   }
-  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  if (e != hipSuccess) {
-    if (graph) (void)hipGraphDestroy(graph);
+  auto release = [&]() {
+    for (int gi = 0; gi < 2; ++gi) {
+      if (exec[gi]) (void)hipGraphExecDestroy(exec[gi]);
+      if (graph[gi]) (void)hipGraphDestroy(graph[gi]);
+      if (ev[gi]) (void)hipEventDestroy(ev[gi]);
+    }
     (void)hipStreamDestroy(cs);
+  };
+  if (e != hipSuccess) {
+    release();
     WHB_FAIL(ctx, WH_EHIP, "graph capture failed: %s", hipGetErrorString(e));
   }
   // bound on replays: every problem needs at most max_iters iterations of
@@ -816,21 +1016,35 @@ wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
     max_rounds = std::max(max_rounds, (long long)D[i].max_iters * 2 * per_it + 2 * per_it + 8);
   }
   const long long max_replays = max_rounds / G + 2;
-  long long rep = 0;
+  // host slots for the two counters in the pinned block
+  int* hcount[2] = {(int*)ctx->hbuf, (int*)(ctx->hbuf + 8)};
+  auto enqueue = [&](long long r) -> hipError_t {
+    const int k = (int)(r & 1);
+    hipError_t er = hipGraphLaunch(exec[k], s);
+    if (er == hipSuccess) er = hipMemcpyAsync(hcount[k], dcount[k], sizeof(int), hipMemcpyDeviceToHost, s);
+    if (er == hipSuccess) er = hipEventRecord(ev[k], s);
+    return er;
+  };
+  long long launched = 0, checked = 0;
   int remaining = nb;
   wh_status st = WH_OK;
-  while (remaining > 0 && rep < max_replays) {
-    e = hipGraphLaunch(exec, s);
+  e = enqueue(launched++);
+  while (e == hipSuccess && checked < launched) {
+    // keep the next replay queued before waiting for the current one
+    if (launched < max_replays) {
+      e = enqueue(launched++);
+      if (e != hipSuccess) break;
+    }
+    const int k = (int)(checked & 1);
+    e = hipEventSynchronize(ev[k]);
     if (e != hipSuccess) break;
-    ++rep;
-    e = hipMemcpyAsync(ctx->hbuf, dremain, sizeof(int), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) break;
-    std::memcpy(&remaining, ctx->hbuf, sizeof(int));
+    std::memcpy(&remaining, hcount[k], sizeof(int));
+    ++checked;
+    if (remaining == 0) break;
   }
-  (void)hipGraphExecDestroy(exec);
-  (void)hipGraphDestroy(graph);
-  (void)hipStreamDestroy(cs);
+  // the replay queued past the end (if any) must finish before the states are read
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  release();
   if (e != hipSuccess) WHB_FAIL(ctx, WH_EHIP, "batched replay failed: %s", hipGetErrorString(e));
   // results
   std::vector<BState> SF(nb);

@@ -78,8 +78,14 @@ struct StepArgs {
   double* partials;       // per-block partial sums
   void* zb0;              // M_FIRST: second state pair whose boundary ring is zeroed
   void* zb1;
+  void* cur_next;         // FP32 M_MID: out W^{n+1} (see below)
   int n;
 };
+// FP32 state pairs hold (W^n, D^{n-1/2} = W^n - W^{n-1}) instead of (W^n, W^{n-1}): the
+// step is D^{n+1/2} = D^{n-1/2} + dt^2 (L_h W^n - f cos), W^{n+1} = W^n + D^{n+1/2}
+// (the same recurrence; rounding no longer enters the low-frequency modes with the
+// 1/(lambda dt) gain of the three-level form).  The "prev" buffer of a pair holds D.
+// FP64 pairs keep (W^n, W^{n-1}).
 
 // Launch one time step of a d-dimensional wave solve. T: float or double.
 // Returns the number of blocks that wrote partial sums.
@@ -115,25 +121,27 @@ void launch_fused2d(bool f32, bool varc, bool force, const FusedArgs& a, hipStre
 // ----------------------------------------------------------------- lane shifts
 // Whole-wavefront shifts by one lane through DPP (wave_shr:1 / wave_shl:1): lane l
 // receives lane l-1 (from_prev_lane) or lane l+1 (from_next_lane); the lane with no
-// source receives 0.  These are plain VALU moves, unlike ds_bpermute shuffles.
+// source receives 0 (bound_ctrl).  These are VALU moves the compiler can fold into
+// the consuming instruction, unlike ds_bpermute shuffles.
 __device__ __forceinline__ float from_prev_lane(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float from_next_lane(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 __device__ __forceinline__ double from_prev_lane(double v) {
   const uint64_t b = (uint64_t)__double_as_longlong(v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0x138, 0xf, 0xf, false);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0x138, 0xf, 0xf, false);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, 0x138, 0xf, 0xf, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), 0x138, 0xf, 0xf, true);
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 __device__ __forceinline__ double from_next_lane(double v) {
   const uint64_t b = (uint64_t)__double_as_longlong(v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0x130, 0xf, 0xf, false);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0x130, 0xf, 0xf, false);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, 0x130, 0xf, 0xf, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), 0x130, 0xf, 0xf, true);
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
+
 
 // ----------------------------------------------------------------- BLAS-like kernels
 void launch_prep_coeffs(const double* c2, const double* f, void* kap, void* fs, bool f32,

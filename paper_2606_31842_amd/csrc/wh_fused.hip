@@ -20,6 +20,10 @@
 // number of resident waves (latency hiding); taller regions waste less halo.  The
 // autotuner picks K and the shape per grid.
 //
+// FP32 pairs are (W^n, D^{n-1/2} = W^n - W^{n-1}) and step in the increment form
+// D += dt^2 (L_h W - f cos), W += D, with the Laplacian summed as differences to the
+// centre; FP64 pairs are (W^n, W^{n-1}).
+//
 // Inputs and outputs are distinct buffers (neighbouring blocks read the halo).
 #include "wh_common.h"
 
@@ -121,30 +125,59 @@ __global__ __launch_bounds__(64 * NW) void k_fused2d(const FusedDev a) {
     const T dn_e = wv < NW - 1 ? edge[b][wv + 1][0][lane] : T(0);
     const T cn = (T)a.cs[s];
     const double ws = a.w[s];
+    if constexpr (sizeof(T) == 4) {
+      // FP32 pair (W, D = W^n - W^{n-1}): D += dt^2 (L_h W - f cos), W += D.  Row r-1
+      // is overwritten before row r reads it, so its old value is carried in uo.
+      T uo = up_e;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const T c = cur[r];
-      const T u = r > 0 ? cur[r - 1] : up_e;
-      const T d = r < R - 1 ? cur[r + 1] : dn_e;
-      const T w = from_prev_lane(c);
-      const T e = from_next_lane(c);
-      T nw;
-      if (VARC) {
-        const int q = VARC ? r : 0;
-        nw = (c + c) - prv[r] + (cw[q] * (w - c) + ce[q] * (e - c) + (cu[q] * (u - c) + cd[q] * (d - c)));
-      } else {
-        nw = (c + c) - prv[r] + A * (((w + e) + (u + d)) - T(4) * c);
+      for (int r = 0; r < R; ++r) {
+        const T c = cur[r];
+        const T d = r < R - 1 ? cur[r + 1] : dn_e;
+        const T w = from_prev_lane(c);
+        const T e = from_next_lane(c);
+        T lap;
+        if (VARC) {
+          const int q = VARC ? r : 0;
+          lap = (cw[q] * (w - c) + ce[q] * (e - c)) + (cu[q] * (uo - c) + cd[q] * (d - c));
+        } else {
+          lap = A * (((w - c) + (e - c)) + ((uo - c) + (d - c)));
+        }
+        if (FORCE) lap -= cn * frc[FORCE ? r : 0];
+        // points outside the open domain keep W = D = 0: masking D suffices (W = 0 + 0),
+        // and a bitwise AND keeps the update branch-free
+        const T dn = __int_as_float(__float_as_int(prv[r] + lap) & (int)(0u - ((mask >> r) & 1u)));
+        const T nw = c + dn;
+        prv[r] = dn;
+        uo = c;
+        cur[r] = nw;
+        acc[r] += ws * (double)nw;
       }
-      if (FORCE) nw -= cn * frc[FORCE ? r : 0];
-      nw = ((mask >> r) & 1u) ? nw : T(0);
-      prv[r] = nw;
-      acc[r] += ws * (double)nw;
-    }
+    } else {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const T tmp = cur[r];
-      cur[r] = prv[r];
-      prv[r] = tmp;
+      for (int r = 0; r < R; ++r) {
+        const T c = cur[r];
+        const T u = r > 0 ? cur[r - 1] : up_e;
+        const T d = r < R - 1 ? cur[r + 1] : dn_e;
+        const T w = from_prev_lane(c);
+        const T e = from_next_lane(c);
+        T nw;
+        if (VARC) {
+          const int q = VARC ? r : 0;
+          nw = (c + c) - prv[r] + (cw[q] * (w - c) + ce[q] * (e - c) + (cu[q] * (u - c) + cd[q] * (d - c)));
+        } else {
+          nw = (c + c) - prv[r] + A * (((w + e) + (u + d)) - T(4) * c);
+        }
+        if (FORCE) nw -= cn * frc[FORCE ? r : 0];
+        nw = ((mask >> r) & 1u) ? nw : T(0);
+        prv[r] = nw;   // rows r+1.. still read the old cur[r]
+        acc[r] += ws * (double)nw;
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const T tmp = cur[r];
+        cur[r] = prv[r];
+        prv[r] = tmp;
+      }
     }
   }
 

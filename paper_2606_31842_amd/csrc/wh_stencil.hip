@@ -10,6 +10,10 @@
 // holds f dt^2.  The state type T is double (FP64 path) or float (mixed path);
 // the accumulator V is always double.
 //
+// FP32 state pairs are (W^n, D^{n-1/2}) with D = W^n - W^{n-1} (the increment form of
+// the same recurrence, which keeps FP32 rounding out of the low-frequency modes), and
+// the Laplacian is summed as differences to the centre; FP64 pairs are (W^n, W^{n-1}).
+//
 // Streaming kernels: one thread per (x[, y]) column of interior nodes, marching
 // RB rows (2D) or planes (3D) so that the neighbours along the marching axis are
 // reused from registers; x/y neighbours come through the L1/L2 caches.
@@ -51,6 +55,7 @@ __device__ __forceinline__ void step_epilogue(const StepArgs& a, size_t p, T nw,
 // --------------------------------------------------------------------- 2D
 template <typename T, int MODE, bool VARC, bool FORCE>
 __global__ __launch_bounds__(256) void k_step2d(StepArgs a) {
+  constexpr bool INC = sizeof(T) == 4;   // increment form for FP32 pairs
   const int n = a.n;
   const size_t P = (size_t)n + 1;
   const int tid = threadIdx.y * 64 + threadIdx.x;
@@ -76,18 +81,41 @@ __global__ __launch_bounds__(256) void k_step2d(StepArgs a) {
       const T e = cur[p + 1];
       const T pv = prev[p];
       T nw;
-      if (VARC) {
-        const T kdn = kap[p + P];
-        const T lap = (kc + kap[p - 1]) * (w - c) + (kc + kap[p + 1]) * (e - c) +
-                      (kc + kup) * (up - c) + (kc + kdn) * (dn - c);
-        nw = (c + c) - pv + lap;
-        kup = kc;
-        kc = kdn;
+      if (INC) {
+        T lap;
+        if (VARC) {
+          const T kdn = kap[p + P];
+          lap = (kc + kap[p - 1]) * (w - c) + (kc + kap[p + 1]) * (e - c) +
+                ((kc + kup) * (up - c) + (kc + kdn) * (dn - c));
+          kup = kc;
+          kc = kdn;
+        } else {
+          lap = A * (((w - c) + (e - c)) + ((up - c) + (dn - c)));
+        }
+        if (FORCE) lap -= cn * fs[p];
+        const T dnew = pv + lap;
+        nw = c + dnew;
+        if (MODE == M_MID) {
+          prev[p] = dnew;
+          ((T*)a.cur_next)[p] = nw;
+          a.V[p] += a.wn * (double)nw;
+        } else {
+          step_epilogue<T, MODE>(a, p, nw, prev, acc);
+        }
       } else {
-        nw = (c + c) - pv + A * (((w + e) + (up + dn)) - T(4) * c);
+        if (VARC) {
+          const T kdn = kap[p + P];
+          const T lap = (kc + kap[p - 1]) * (w - c) + (kc + kap[p + 1]) * (e - c) +
+                        (kc + kup) * (up - c) + (kc + kdn) * (dn - c);
+          nw = (c + c) - pv + lap;
+          kup = kc;
+          kc = kdn;
+        } else {
+          nw = (c + c) - pv + A * (((w + e) + (up + dn)) - T(4) * c);
+        }
+        if (FORCE) nw -= cn * fs[p];
+        step_epilogue<T, MODE>(a, p, nw, prev, acc);
       }
-      if (FORCE) nw -= cn * fs[p];
-      step_epilogue<T, MODE>(a, p, nw, prev, acc);
       up = c;
       c = dn;
     }
@@ -101,6 +129,7 @@ __global__ __launch_bounds__(256) void k_step2d(StepArgs a) {
 // --------------------------------------------------------------------- 3D
 template <typename T, int MODE, bool VARC, bool FORCE>
 __global__ __launch_bounds__(256) void k_step3d(StepArgs a) {
+  constexpr bool INC = sizeof(T) == 4;   // increment form for FP32 pairs
   const int n = a.n;
   const size_t P = (size_t)n + 1;
   const size_t P2 = P * P;
@@ -128,19 +157,43 @@ __global__ __launch_bounds__(256) void k_step3d(StepArgs a) {
       const T s = cur[p - P], nn = cur[p + P];
       const T pv = prev[p];
       T nw;
-      if (VARC) {
-        const T kfw = kap[p + P2];
-        const T lap = (kc + kap[p - 1]) * (w - c) + (kc + kap[p + 1]) * (e - c) +
-                      (kc + kap[p - P]) * (s - c) + (kc + kap[p + P]) * (nn - c) +
-                      (kc + kbk) * (bk - c) + (kc + kfw) * (fw - c);
-        nw = (c + c) - pv + lap;
-        kbk = kc;
-        kc = kfw;
+      if (INC) {
+        T lap;
+        if (VARC) {
+          const T kfw = kap[p + P2];
+          lap = ((kc + kap[p - 1]) * (w - c) + (kc + kap[p + 1]) * (e - c)) +
+                ((kc + kap[p - P]) * (s - c) + (kc + kap[p + P]) * (nn - c)) +
+                ((kc + kbk) * (bk - c) + (kc + kfw) * (fw - c));
+          kbk = kc;
+          kc = kfw;
+        } else {
+          lap = A * ((((w - c) + (e - c)) + ((s - c) + (nn - c))) + ((bk - c) + (fw - c)));
+        }
+        if (FORCE) lap -= cn * fs[p];
+        const T dnew = pv + lap;
+        nw = c + dnew;
+        if (MODE == M_MID) {
+          prev[p] = dnew;
+          ((T*)a.cur_next)[p] = nw;
+          a.V[p] += a.wn * (double)nw;
+        } else {
+          step_epilogue<T, MODE>(a, p, nw, prev, acc);
+        }
       } else {
-        nw = (c + c) - pv + A * ((((w + e) + (s + nn)) + (bk + fw)) - T(6) * c);
+        if (VARC) {
+          const T kfw = kap[p + P2];
+          const T lap = (kc + kap[p - 1]) * (w - c) + (kc + kap[p + 1]) * (e - c) +
+                        (kc + kap[p - P]) * (s - c) + (kc + kap[p + P]) * (nn - c) +
+                        (kc + kbk) * (bk - c) + (kc + kfw) * (fw - c);
+          nw = (c + c) - pv + lap;
+          kbk = kc;
+          kc = kfw;
+        } else {
+          nw = (c + c) - pv + A * ((((w + e) + (s + nn)) + (bk + fw)) - T(6) * c);
+        }
+        if (FORCE) nw -= cn * fs[p];
+        step_epilogue<T, MODE>(a, p, nw, prev, acc);
       }
-      if (FORCE) nw -= cn * fs[p];
-      step_epilogue<T, MODE>(a, p, nw, prev, acc);
       bk = c;
       c = fw;
     }
@@ -176,11 +229,12 @@ __global__ __launch_bounds__(256) void k_first(StepArgs a) {
     a.V[p] = 0.0;
     return;
   }
+  constexpr bool INC = sizeof(T) == 4;   // FP32 pair: (W^1, D^{1/2} = W^1 - W^0)
   const double* __restrict__ v = a.vin;
   const T* __restrict__ kap = (const T*)a.kap;
   if (!v) {  // W^0 = 0
     const T w1 = FORCE ? T(-0.5) * (T)a.cosn * ((const T*)a.fs)[p] : T(0);
-    w0o[p] = T(0);
+    w0o[p] = INC ? w1 : T(0);
     w1o[p] = w1;
     a.V[p] = a.wn * (double)w1;
     return;
@@ -201,16 +255,28 @@ __global__ __launch_bounds__(256) void k_first(StepArgs a) {
     lap = (kc + kap[p - 1]) * (w - c) + (kc + kap[p + 1]) * (e - c) + (kc + kap[p - P]) * (s - c) +
           (kc + kap[p + P]) * (nn - c);
     if (DIM == 3) lap += (kc + kap[p - P * P]) * (bk - c) + (kc + kap[p + P * P]) * (fw - c);
+  } else if (INC) {
+    T sum = ((w - c) + (e - c)) + ((s - c) + (nn - c));
+    if (DIM == 3) sum += (bk - c) + (fw - c);
+    lap = (T)a.a * sum;
   } else {
     T sum = (w + e) + (s + nn);
     if (DIM == 3) sum += bk + fw;
     lap = (T)a.a * (sum - T(2 * DIM) * c);
   }
   if (FORCE) lap -= (T)a.cosn * ((const T*)a.fs)[p];
-  const T w1 = c + T(0.5) * lap;
-  w0o[p] = c;
-  w1o[p] = w1;
-  a.V[p] = a.w0 * v[p] + a.wn * (double)w1;
+  if (INC) {
+    const T d = T(0.5) * lap;
+    const T w1 = c + d;
+    w0o[p] = d;
+    w1o[p] = w1;
+    a.V[p] = a.w0 * v[p] + a.wn * (double)w1;
+  } else {
+    const T w1 = c + T(0.5) * lap;
+    w0o[p] = c;
+    w1o[p] = w1;
+    a.V[p] = a.w0 * v[p] + a.wn * (double)w1;
+  }
 }
 
 // --------------------------------------------------------------------- dispatch

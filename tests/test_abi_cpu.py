@@ -75,6 +75,24 @@ def test_mode_selection_matches_oracle(dim, n, omega, nd):
     assert np.allclose(lam2, ref_l2, rtol=1e-13)
 
 
+def test_mode_selection_sweep_matches_oracle():
+    # frequencies below, inside and above the spectrum; every mode; degenerate pairs
+    import paper_2606_31842_amd as wh
+    from oracle import modes
+    rng = np.random.default_rng(12)
+    cases = [(2, 8, 0.5, 49), (2, 8, 1e4, 49), (3, 6, 1.0, 125), (3, 6, 300.0, 17), (2, 12, 2 * np.pi, 5)]
+    for _ in range(30):
+        dim = int(rng.integers(2, 4))
+        n = int(rng.integers(5, 24 if dim == 2 else 10))
+        lam_max = dim * 4.0 * n * n
+        cases.append((dim, n, float(np.sqrt(rng.uniform(0, lam_max))), int(rng.integers(1, min(60, (n - 1) ** dim) + 1))))
+    for dim, n, omega, nd in cases:
+        got, lam2 = wh.select_sine_modes(dim, n, omega, nd)
+        ref, ref_l2 = modes.select_modes(dim, n, omega, nd)
+        assert [tuple(r) for r in got.tolist()] == ref, (dim, n, omega, nd)
+        assert np.allclose(lam2, ref_l2, rtol=1e-13)
+
+
 def test_invalid_arguments_rejected_on_host():
     import paper_2606_31842_amd as wh
     from paper_2606_31842_amd import _native as nat

@@ -69,3 +69,56 @@ def test_batched_rejects_bad_input():
         wh.solve_batched([(f, 5.0)], solver="gmres")
     with pytest.raises(wh.WaveHoltzError):
         wh.solve_batched([(f, 5.0, cuda(np.ones((17, 17))))])   # variable c without c_max
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_batched_dcg_matches_direct_and_single(precision):
+    """Deflated batches (sine modes nearest omega^2): the start x_0 = W (W^T A W)^{-1} W^T b
+    of Algorithm 3, then CG; one problem of the batch runs undeflated."""
+    print(f"case batched dcg {precision}", flush=True)
+    import paper_2606_31842_amd as wh
+    probs = _batch(seed=21, omega=(12.0, 40.0))
+    nds = [8 if i % 4 else 0 for i in range(len(probs))] if precision == "mixed" else [8] * len(probs)
+    tol = 1e-9
+    us, infos = wh.solve_batched([(cuda(f), om) for (n, om, f) in probs], precision=precision, tol=tol,
+                                 solver="dcg", n_defl=nds, k_fuse=4, max_iters=20000)
+    for (n, om, f), nd, u, info in zip(probs, nds, us, infos):
+        U = disc.direct_solve_dst(2, n, om, f)
+        e = rel(host(u), U)
+        print(f"n={n} omega={om:.3f} nd={nd} status={info['status']} iters={info['iters']} "
+              f"true={info['true_rel_res']:.2e} err={e:.2e}", flush=True)
+        assert info["status"] == 0
+        assert info["true_rel_res"] <= (1.5 * tol if precision == "f64" else tol)
+        assert e < (1e-6 if precision == "f64" else 2e-5)
+        if precision == "f64":
+            # the single solve with the same deflation set: same iteration count, same iterate
+            u1, i1 = wh.solve(cuda(f), om, solver="dcg", defl=wh.sine_deflation(2, n, om, nd), tol=tol,
+                              max_iters=20000)
+            assert abs(i1["iters"] - info["iters"]) <= 2, (i1["iters"], info["iters"])
+            assert rel(host(u), host(u1)) < 1e-7
+
+
+def test_batched_dcg_start_is_solution():
+    """f inside the deflation space: the deflated start is the solution; no CG iteration."""
+    import paper_2606_31842_amd as wh
+    n, om = 48, 17.3
+    modes, lam2 = wh.select_sine_modes(2, n, om, 4)
+    x = np.arange(n + 1) / n
+    f = sum((k + 1.0) * np.outer(np.sin(np.pi * b * x), np.sin(np.pi * a * x)) for k, (a, b) in enumerate(modes))
+    us, infos = wh.solve_batched([(cuda(f), om)], solver="dcg", n_defl=4, tol=1e-10, precision="f64")
+    U = disc.direct_solve_dst(2, n, om, f)
+    assert infos[0]["status"] == 0 and infos[0]["iters"] == 0
+    assert infos[0]["true_rel_res"] < 1e-10
+    assert rel(host(us[0]), U) < 1e-10
+
+
+def test_batched_dcg_rejects_bad_input():
+    import paper_2606_31842_amd as wh
+    f = cuda(wl.gaussian(2, 16, (0.5, 0.5), 0.1))
+    with pytest.raises(wh.WaveHoltzError):
+        wh.solve_batched([(f, 5.0)], solver="cg", n_defl=2)          # deflation needs DCG
+    with pytest.raises(wh.WaveHoltzError):
+        wh.solve_batched([(f, 5.0, cuda(np.ones((17, 17))))], solver="dcg", n_defl=2,
+                         c_max=1.0)                                   # sine modes need c == 1
+    with pytest.raises(wh.WaveHoltzError):
+        wh.solve_batched([(f, 5.0)], solver="dcg", n_defl=15 * 15 + 1)
