@@ -261,10 +261,15 @@ def run_cfg3(args, np, torch, wh, wl):
     out = {"workload": "cfg3 3D 256^3 variable c omega=40 mixed tol 1e-8"}
     v = torch.from_numpy(wl.random_nodal(3, p.n, 1)).cuda()
     for prec in ("mixed", "f64"):
-        us = wh.time_step_kernel(v, p.omega, c2=c2, precision=prec, reps=20) * 1e3
+        ms, sh = wh.time_step_kernel(v, p.omega, c2=c2, precision=prec, reps=20, shape=True)
+        us = ms * 1e3
+        k = max(1, sh["k"])
+        # streaming-form algorithmic bytes per point-step (variable c): FP32 state 4+4 in, 4 out,
+        # kap 4, V 16; FP64: 8+8 in, 8 out, kap 8, V 16
         bpp = 32.0 if prec == "mixed" else 48.0
-        out[f"step_kernel_{prec}"] = {"us": us, "gpts": pts / us / 1e3, "bytes_per_pt_step": bpp,
-                                      "achieved_gbs": bpp * pts / (us * 1e-6) / 1e9}
+        out[f"step_kernel_{prec}"] = {"us_per_launch": us, "k_fuse": k, "rows": sh["rows"], "waves": sh["waves"],
+                                      "us_per_step": us / k, "gpts": pts * k / us / 1e3, "bytes_per_pt_step": bpp,
+                                      "achieved_gbs": bpp * pts * k / (us * 1e-6) / 1e9}
     cap = args.max_iters or 2000
     for solver in ("gmres", "cg"):
         (u, info), dt = _timed(torch, lambda: wh.solve(f, p.omega, c2=c2, solver=solver, precision="mixed",

@@ -110,6 +110,9 @@ typedef struct {
                                (exact under the corrected frequency); 1 steps W^n from
                                W^0 = v in FP32; -1 (default): 0 for CG/GMRES and batched
                                solves, 1 for DCG                                           */
+  int32_t k_shape;          /* block shape of the temporally blocked kernel (2D: register rows
+                               per thread and waves per block; 3D: also planes per block),
+                               0..2; -1 (default): chosen with K by the autotuner           */
 } wh_params;
 
 typedef struct {

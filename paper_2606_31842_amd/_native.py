@@ -25,7 +25,7 @@ class WhParams(C.Structure):
         ("precision", C.c_int32), ("solver", C.c_int32), ("restart", C.c_int32),
         ("tol", C.c_double), ("max_iters", C.c_int32), ("inner_tol", C.c_double),
         ("max_outer", C.c_int32), ("k_fuse", C.c_int32), ("reproject", C.c_int32),
-        ("check_every", C.c_int32), ("mixed_form", C.c_int32),
+        ("check_every", C.c_int32), ("mixed_form", C.c_int32), ("k_shape", C.c_int32),
     ]
 
 

@@ -209,6 +209,8 @@ wh_status check_params(wh_ctx* ctx, const wh_grid* g, const wh_params* P) {
   if (P->precision != WH_F64 && P->precision != WH_MIXED) WH_FAIL(ctx, WH_EINVAL, "bad precision");
   if (P->c_max < 0) WH_FAIL(ctx, WH_EINVAL, "c_max must be >= 0");
   if (P->k_fuse < 0 || P->k_fuse > 64) WH_FAIL(ctx, WH_EINVAL, "k_fuse must be in [0, 64]");
+  if (P->k_shape < -1 || P->k_shape >= kFusedShapes)
+    WH_FAIL(ctx, WH_EINVAL, "k_shape must be -1 or in [0, %d)", kFusedShapes);
   return WH_OK;
 }
 
@@ -277,6 +279,23 @@ struct WaveOp {
   int k_shape = 0;   // block shape of the temporally blocked kernel
 };
 
+// The temporally blocked kernels: 2D (register tiles) and 3D (z-marching pipeline).
+bool fused_supported(int dim, bool f32, int k) {
+  return dim == 2 ? fused2d_supported(f32, k) : fused3d_supported(f32, k);
+}
+void launch_fused(int dim, bool f32, bool varc, bool force, const FusedArgs& fa, hipStream_t s) {
+  if (dim == 2) launch_fused2d(f32, varc, force, fa, s);
+  else launch_fused3d(f32, varc, force, fa, s);
+}
+void fused_shape_dims(int dim, bool f32, int shape, int* rows, int* waves) {
+  if (dim == 2) {
+    fused2d_shape_dims(f32, shape, rows, waves);
+  } else {
+    int zs = 0;
+    fused3d_shape_dims(f32, shape, rows, waves, &zs);
+  }
+}
+
 // One wave solve from W^0 = vin.  last = M_LAST_V: V holds Pi_h(vin);
 // M_LAST_AQ: out = x - Pi_h(vin) with partial sums of x.out (x == vin);
 // M_LAST_FPI: out = Pi_h(vin) with partial sums of (out - x)^2.
@@ -305,7 +324,7 @@ int wave_solve(const WaveOp& op, const double* vin, bool force, StepMode last, c
   void* op_ = op.Wd;
   int nn = 1;  // cur holds W^nn
   const int K = op.k_fuse;
-  if (K > 1 && op.dim == 2 && fused2d_supported(op.f32, K)) {
+  if (K > 1 && fused_supported(op.dim, op.f32, K)) {
     FusedArgs fa{};
     fa.V = op.V;
     fa.kap = op.kap;
@@ -318,7 +337,7 @@ int wave_solve(const WaveOp& op, const double* vin, bool force, StepMode last, c
     // remainder is covered by the largest supported K that still fits
     int Kc = K;
     while (true) {
-      while (Kc > 1 && (nn + Kc > tp.nt - 1 || !fused2d_supported(op.f32, Kc))) --Kc;
+      while (Kc > 1 && (nn + Kc > tp.nt - 1 || !fused_supported(op.dim, op.f32, Kc))) --Kc;
       if (Kc <= 1) break;
       fa.k = Kc;
       fa.cur = cur;
@@ -327,7 +346,7 @@ int wave_solve(const WaveOp& op, const double* vin, bool force, StepMode last, c
       fa.prev_out = op_;
       fa.wts = &tp.w[nn + 1];
       fa.cosv = &tp.cosv[nn];
-      launch_fused2d(op.f32, op.varc, force, fa, s);
+      launch_fused(op.dim, op.f32, op.varc, force, fa, s);
       std::swap(cur, oc);
       std::swap(prev, op_);
       nn += Kc;
@@ -358,12 +377,12 @@ int wave_solve(const WaveOp& op, const double* vin, bool force, StepMode last, c
 // that K.  The state buffers and V serve as scratch; every caller initialises them
 // afterwards.  Returns K | (shape << 8), cached per context.
 int autotune_k(wh_ctx* ctx, const WaveOp& op, bool force, int k_fixed = 0) {
-  if (op.dim != 2) return 1;
   const auto key = std::make_tuple(op.dim, op.n, (int)op.f32, (int)op.varc, (int)force + 2 * k_fixed);
   auto it = ctx->ktune.find(key);
   if (it != ctx->ktune.end()) return it->second;
   const TimeParams& tp = *op.tp;
-  const int fallback = k_fixed > 1 ? (k_fixed | (fused2d_default_shape(op.f32, op.n) << 8)) : 4;
+  const int fallback = k_fixed > 1 ? (k_fixed | ((op.dim == 2 ? fused2d_default_shape(op.f32, op.n) : 0) << 8))
+                                   : (op.dim == 2 ? 4 : 1);
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return fallback;
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -375,7 +394,7 @@ int autotune_k(wh_ctx* ctx, const WaveOp& op, bool force, int k_fixed = 0) {
   const int cands[] = {1, 2, 3, 4, 6, 8};
   for (int K : cands) {
     if (k_fixed > 0 && K != k_fixed) continue;
-    if (K > 1 && (!fused2d_supported(op.f32, K) || K + 2 > tp.nt)) continue;
+    if (K > 1 && (!fused_supported(op.dim, op.f32, K) || K + 2 > tp.nt)) continue;
     for (int shape = 0; shape < (K == 1 ? 1 : kFusedShapes); ++shape) {
       auto run = [&]() {
         if (K == 1) {
@@ -406,7 +425,7 @@ int autotune_k(wh_ctx* ctx, const WaveOp& op, bool force, int k_fixed = 0) {
           fa.prev_out = op.Wd;
           fa.wts = &tp.w[2];
           fa.cosv = &tp.cosv[1];
-          launch_fused2d(op.f32, op.varc, force, fa, ctx->stream);
+          launch_fused(op.dim, op.f32, op.varc, force, fa, ctx->stream);
         }
       };
       run();
@@ -827,10 +846,9 @@ wh_status setup_ops(wh_ctx* ctx, const wh_grid& g, const wh_params& P, const dou
   // operator without forcing dominates every solve, so it sets K for both precisions.
   auto pick = [&](WaveOp& op) {
     int code = 1;
-    if (g.dim == 2) {
-      if (P.k_fuse == 1 || (P.k_fuse > 1 && !fused2d_supported(op.f32, P.k_fuse))) code = 1;
-      else code = autotune_k(ctx, op, false, P.k_fuse);
-    }
+    if (P.k_fuse == 1 || (P.k_fuse > 1 && !fused_supported(g.dim, op.f32, P.k_fuse))) code = 1;
+    else if (P.k_fuse > 1 && P.k_shape >= 0) code = P.k_fuse | (P.k_shape << 8);
+    else code = autotune_k(ctx, op, false, P.k_fuse);
     op.k_fuse = code & 0xff;
     op.k_shape = code >> 8;
   };
@@ -849,7 +867,7 @@ void fill_info(wh_info* info, const TimeParams& tp, int k_fuse, const WaveOp* op
   info->c_max = tp.c_max;
   info->k_fuse = k_fuse;
   info->k_rows = info->k_waves = 0;
-  if (op && op->dim == 2 && k_fuse > 1) fused2d_shape_dims(op->f32, op->k_shape, &info->k_rows, &info->k_waves);
+  if (op && k_fuse > 1) fused_shape_dims(op->dim, op->f32, op->k_shape, &info->k_rows, &info->k_waves);
 }
 
 }  // namespace
@@ -877,6 +895,7 @@ void wh_params_default(wh_params* p) {
   p->reproject = -1;
   p->check_every = 1;
   p->mixed_form = -1;
+  p->k_shape = -1;
 }
 
 const char* wh_status_string(wh_status s) {
@@ -1360,7 +1379,7 @@ wh_status wh_time_step_kernel(wh_ctx* ctx, const wh_grid* grid, const double* c2
       fa.prev_out = (r & 1) ? op.Wa : op.Wd;
       fa.wts = &tp.w[1];
       fa.cosv = &tp.cosv[1];
-      launch_fused2d(op.f32, op.varc, false, fa, s);
+      launch_fused(op.dim, op.f32, op.varc, false, fa, s);
     }
   };
   run(0);
@@ -1379,7 +1398,7 @@ wh_status wh_time_step_kernel(wh_ctx* ctx, const wh_grid* grid, const double* c2
   *us_per_launch = 1e3 * (double)ms / reps;
   if (k_used) *k_used = K;
   int rr = 0, wv = 0;
-  if (K > 1 && op.dim == 2) fused2d_shape_dims(op.f32, op.k_shape, &rr, &wv);
+  if (K > 1) fused_shape_dims(op.dim, op.f32, op.k_shape, &rr, &wv);
   if (rows) *rows = rr;
   if (waves) *waves = wv;
   return WH_OK;

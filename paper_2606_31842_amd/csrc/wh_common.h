@@ -117,6 +117,10 @@ int fused2d_default_shape(bool f32, int n);
 // Register rows per thread and wavefronts per block of a block shape.
 void fused2d_shape_dims(bool f32, int shape, int* rows, int* waves);
 void launch_fused2d(bool f32, bool varc, bool force, const FusedArgs& a, hipStream_t s);
+// 3D: K in {2, 3}; shapes give rows per thread, waves per block and output planes per block.
+bool fused3d_supported(bool f32, int k);
+void fused3d_shape_dims(bool f32, int shape, int* rows, int* waves, int* zs);
+void launch_fused3d(bool f32, bool varc, bool force, const FusedArgs& a, hipStream_t s);
 
 // ----------------------------------------------------------------- lane shifts
 // Whole-wavefront shifts by one lane through DPP (wave_shr:1 / wave_shl:1): lane l

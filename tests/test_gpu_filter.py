@@ -99,7 +99,24 @@ def test_filter_fixed_point_config1():
 @pytest.mark.parametrize("dim,n,omega,varc,force", [(2, 37, 11.3, False, True), (2, 130, 31.7, True, True),
                                                      (2, 257, 40.2, True, False), (2, 5, 3.3, False, False)])
 def test_fused_steps_match_oracle(k_fuse, dim, n, omega, varc, force):
-    print(f"case fused k={k_fuse} n={n} varc={varc} force={force}", flush=True)
+    _fused_case(k_fuse, -1, dim, n, omega, varc, force)
+
+
+@pytest.mark.parametrize("k_fuse,shape", [(2, 0), (2, 1), (2, 2), (8, 0), (8, 1), (8, 2)])
+def test_fused2d_every_shape(k_fuse, shape):
+    _fused_case(k_fuse, shape, 2, 130, 31.7, True, True)
+
+
+@pytest.mark.parametrize("k_fuse,shape", [(1, -1), (2, 0), (2, 1), (2, 2), (3, 0), (3, 1), (3, 2)])
+@pytest.mark.parametrize("dim,n,omega,varc,force", [(3, 22, 9.7, True, True), (3, 40, 15.3, False, True),
+                                                     (3, 70, 20.1, True, False), (3, 5, 3.1, False, False)])
+def test_fused3d_steps_match_oracle(k_fuse, shape, dim, n, omega, varc, force):
+    """z-marching blocked 3D kernel: several x/y tiles and z segments, ragged tails."""
+    _fused_case(k_fuse, shape, dim, n, omega, varc, force)
+
+
+def _fused_case(k_fuse, shape, dim, n, omega, varc, force):
+    print(f"case fused k={k_fuse} shape={shape} dim={dim} n={n} varc={varc} force={force}", flush=True)
     import paper_2606_31842_amd as wh
     v = wl.random_nodal(dim, n, seed=3 * n)
     c2 = None
@@ -107,10 +124,12 @@ def test_fused_steps_match_oracle(k_fuse, dim, n, omega, varc, force):
         rng = np.random.default_rng(n)
         c = 1 + wl.gaussian_sum_field(dim, n, rng.uniform(-.3, .3, 3), rng.uniform(.2, .8, (3, dim)), 0.2)
         c2 = c * c
-    f = wl.gaussian(dim, n, (0.4, 0.6), 0.15) if force else None
+    f = wl.gaussian(dim, n, (0.4, 0.6, 0.5)[:dim], 0.15) if force else None
     ref = _oracle_filter(dim, n, omega, v, f, c2)
-    args = dict(f=None if f is None else cuda(f), c2=None if c2 is None else cuda(c2), k_fuse=k_fuse)
+    args = dict(f=None if f is None else cuda(f), c2=None if c2 is None else cuda(c2), k_fuse=k_fuse,
+                k_shape=shape)
     out, info = wh.apply_filter(cuda(v), omega, **args)
+    assert info["k_fuse"] == k_fuse or (k_fuse > 1 and info["k_fuse"] < k_fuse and info["nt"] < k_fuse + 2)
     assert rel(host(out), ref) < 1e-12
     out32, _ = wh.apply_filter(cuda(v), omega, precision="mixed", **args)
     emu = rel(_oracle_filter(dim, n, omega, v, f, c2, state_dtype=np.float32), ref)
