@@ -31,13 +31,16 @@ HBM_PEAK_GBS = 8000.0
 # kernel (c = 1, no forcing): read W^n 4 + W^{n-1} 4, write W^{n+1} 4, V read+write 16
 B_PER_PT_STEP_F32 = 28.0
 B_PER_PT_STEP_F64 = 40.0
-# HBM bytes per dispatch of the K=8 FP32 fused kernel on this grid, from the two
-# rocprofv3 counter passes summarised in profiles/hbm_traffic_fused2d_f32_k8_2d1024.md
-# (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 after calibration on a plain copy).  Valid
-# only for the kernel source it was taken on.
-TRAFFIC = {"kernel": "k_fused2d<float,8,8,8,false,false>", "k_fuse": 8, "rows": 8, "waves": 8,
-           "src_sha1": "81314f257c03d4a51769c75ad3e8f1019245ff4b",
-           "fetch_kib": 8846.3, "write_kib": 16426.6, "fetch_scale": 2.000, "write_scale": 1.000}
+# HBM KiB per dispatch (FETCH_SIZE, WRITE_SIZE) of every FP32 temporally blocked kernel
+# variant "K,R,NW" on this grid, from the two rocprofv3 counter passes summarised in
+# profiles/hbm_traffic_fused2d_f32_2d1024.md (scaled by FETCH x 2.000, WRITE x 1.000 from a
+# plain copy).  Valid only for the kernel source it was taken on.
+TRAFFIC = {"src_sha1": "e31d04c71e802e9ac7fbb9664fa002ddd0c4c7b2", "fetch_scale": 2.000, "write_scale": 1.000,
+           "kib": {"2,16,4": [8522.6, 16438.5], "2,8,4": [8408.5, 16408.1], "2,8,8": [8492.4, 16446.1],
+                   "3,16,4": [8590.1, 16436.6], "3,8,4": [8407.8, 16384.9], "3,8,8": [8554.6, 16441.6],
+                   "4,16,4": [8648.6, 16435.7], "4,8,4": [8528.6, 16405.0], "4,8,8": [8612.6, 16436.5],
+                   "6,16,4": [8719.4, 16412.2], "6,8,4": [8618.9, 16394.0], "6,8,8": [8665.4, 16416.4],
+                   "8,16,4": [8899.8, 16456.4], "8,8,4": [8711.8, 16384.2], "8,8,8": [8846.2, 16459.6]}}
 
 
 def log(*a):
@@ -195,10 +198,10 @@ def main():
     traffic = None
     src = os.path.join(ROOT, "paper_2606_31842_amd", "csrc", "wh_fused.hip")
     import hashlib
-    if (kf == TRAFFIC["k_fuse"] and (kshape["rows"], kshape["waves"]) == (TRAFFIC["rows"], TRAFFIC["waves"])
-            and hashlib.sha1(open(src, "rb").read()).hexdigest() == TRAFFIC["src_sha1"]):
-        traffic = round(1024 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] +
-                                TRAFFIC["write_kib"] * TRAFFIC["write_scale"]))
+    key = f"{kf},{kshape['rows']},{kshape['waves']}"
+    if key in TRAFFIC["kib"] and hashlib.sha1(open(src, "rb").read()).hexdigest() == TRAFFIC["src_sha1"]:
+        fk, wk = TRAFFIC["kib"][key]
+        traffic = round(1024 * (fk * TRAFFIC["fetch_scale"] + wk * TRAFFIC["write_scale"]))
     line = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gpts/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
