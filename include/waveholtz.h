@@ -12,7 +12,8 @@
  *     removed by an adjusted frequency (Section 2.2);
  *   - the linear system A u = (I - S_h) u = b, b = Pi_h 0 (eq. WaveHoltzMatrixEquation),
  *     solved by the fixed-point iteration (Algorithm 1), CG / deflated CG
- *     (Algorithm 3) or restarted GMRES (Algorithm 4 with no augmentation).
+ *     (Algorithm 3) or restarted GMRES (Algorithm 4, augmented by the deflation set when
+ *     one is given), or with direct eigenvector deflation around them (Algorithm 2).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -110,6 +111,13 @@ typedef struct {
                                (exact under the corrected frequency); 1 steps W^n from
                                W^0 = v in FP32; -1 (default): 0 for CG/GMRES and batched
                                solves, 1 for DCG                                           */
+  int32_t devd;             /* with a deflation set: 0 uses it in DCG (Algorithm 3); 1 runs
+                               Algorithm 2 (direct eigenvector deflation) around solver FPI,
+                               CG or GMRES: f_d = f - W W^T f, solve for f_d, then
+                               u += sum_k (phi_k^T f) / (omega^2 - lambda_k^2) phi_k; 2: as 1
+                               with every FPI iterate deflated (FPI only).  Exact
+                               eigenvectors only (WH_DEFL_SINE, WH_DEFL_DENSE_EXACT).  The
+                               reported residuals are those of the deflated system.        */
   int32_t k_shape;          /* block shape of the temporally blocked kernel (2D: register rows
                                per thread and waves per block; 3D: also planes per block),
                                0..2; -1 (default): chosen with K by the autotuner           */
@@ -161,6 +169,8 @@ void wh_params_default(wh_params* p);
 wh_status wh_create(wh_ctx** ctx, int device, void* hip_stream);
 wh_status wh_destroy(wh_ctx* ctx);
 wh_status wh_set_stream(wh_ctx* ctx, void* hip_stream);
+/* Message of the last failure on ctx; with ctx == NULL, of the calling thread's last failed
+ * wh_create. */
 const char* wh_last_error(const wh_ctx* ctx);
 const char* wh_status_string(wh_status s);
 
@@ -195,7 +205,9 @@ wh_status wh_apply_filter(wh_ctx* ctx, const wh_grid* grid, const double* c2, co
 
 /* Solve A u = b, b = Pi_h(0; f), by params->solver; the fixed point is the discrete
  * Helmholtz solution (L_h + omega^2) u = f (Sections 2.1-2.2).  u: device nodal, in:
- * initial guess, out: solution.  defl may be NULL (required for WH_DCG). */
+ * initial guess, out: solution.  defl (exact eigenvectors) is required for WH_DCG
+ * (Algorithm 3), augments WH_GMRES (Algorithm 4: W heads the Arnoldi basis, A W =
+ * W diag(mu)), or with params->devd wraps FPI / CG / GMRES in Algorithm 2; else NULL. */
 wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const double* f,
                    const wh_deflation* defl, const wh_params* params, double* u,
                    void* ws, size_t ws_bytes, wh_info* info);

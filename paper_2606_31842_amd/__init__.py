@@ -52,7 +52,7 @@ def context(device: Optional[int] = None):
             h = C.c_void_p()
             st = lib.wh_create(C.byref(h), dev, C.c_void_p(stream))
             if st != 0:
-                raise WaveHoltzError(st, "wh_create failed")
+                raise WaveHoltzError(st, "wh_create failed: " + lib.wh_last_error(None).decode())
             ctx = h
             _ctxs[dev] = ctx
         lib.wh_set_stream(ctx, C.c_void_p(stream))

@@ -25,7 +25,7 @@ class WhParams(C.Structure):
         ("precision", C.c_int32), ("solver", C.c_int32), ("restart", C.c_int32),
         ("tol", C.c_double), ("max_iters", C.c_int32), ("inner_tol", C.c_double),
         ("max_outer", C.c_int32), ("k_fuse", C.c_int32), ("reproject", C.c_int32),
-        ("check_every", C.c_int32), ("mixed_form", C.c_int32), ("k_shape", C.c_int32),
+        ("check_every", C.c_int32), ("mixed_form", C.c_int32), ("devd", C.c_int32), ("k_shape", C.c_int32),
     ]
 
 
@@ -103,6 +103,14 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"libwaveholtz.so not built ({LIB_PATH}); run __graft_entry__.build()")
+    # torch first: its HIP runtime (libamdhip64.so.7 and the HSA runtime it names) must be
+    # the one in the process.  Loading the library first would bring in the system copies,
+    # after which torch's own HSA runtime is mapped a second time and the library's HIP
+    # calls see no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     for name, (res, args) in {**_SIGS, **_OPTIONAL}.items():
         fn = getattr(lib, name)

@@ -466,6 +466,7 @@ struct Solver {
   bool defect = true;              // FP32 A-applies in the defect form
   double om2dt2 = 0;               // omega^2 dt^2
   double reliable_drop = 0.1;  // mixed CG: residual reduction between FP64 replacements
+  std::vector<double> mu;          // mu_k = 1 - beta_h(lambda_k^2) of the deflation set (host)
 };
 
 // q = A x (x nonzero).  Leaves partial sums of x.q in op.partials.
@@ -630,12 +631,20 @@ wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_non
   return WH_OK;
 }
 
-// Restarted GMRES(m) (Algorithm 4 with no augmentation), modified Gram-Schmidt on
-// the device, Givens rotations and the triangular solve on the host.
+// Restarted GMRES(m), Algorithm 4: modified Gram-Schmidt on the device, Givens
+// rotations and the triangular solve on the host.  With use_defl the Krylov space is
+// augmented by the deflation set W (exact eigenvectors, A W = W diag(mu)): the QR of A W
+// is W diag(mu), so W itself heads the basis, the restart vector is (I - W W^T) r, every
+// new Arnoldi vector is orthogonalised against W first (h_{W,k} = W^T A v_k, by the
+// table kernels), and the least-squares solution splits into the Krylov part y_K (back
+// substitution on the rotated rows) and y_W = (W^T r - H_{W,K} y_K) / mu; x += W y_W + V y_K.
 wh_status gmres_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_nonzero,
-                      double* r, double* basis, int m, double tol, int maxit, KrylovResult& res) {
+                      double* r, double* basis, int m, double tol, int maxit, KrylovResult& res,
+                      bool use_defl = false) {
   wh_ctx* ctx = S.ctx;
   const int64_t N = S.N;
+  const int nd = use_defl ? S.defl.nd : 0;
+  const int SW = S_H + m + 2;   // slots for the W coefficients
   dot(S, rhs, rhs, S_NB);
   WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
   const double nb = std::sqrt(ctx->hbuf[S_NB]);
@@ -644,6 +653,7 @@ wh_status gmres_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_
     return WH_OK;
   }
   std::vector<double> H((size_t)(m + 1) * m, 0.0), g(m + 1), cs(m), sn(m), y(m);
+  std::vector<double> gW(nd), HW((size_t)nd * m, 0.0), yW(nd);
   auto Hc = [&](int i, int j) -> double& { return H[(size_t)j * (m + 1) + i]; };
   int its = 0;
   bool first = true;
@@ -656,78 +666,116 @@ wh_status gmres_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_
       launch_sub(r, rhs, basis, N, S.s);
     }
     first = false;
+    if (nd) {
+      // g_W = W^T r; r <- (I - W W^T) r
+      launch_defl_project(S.defl, r, S.partials, S.s);
+      launch_defl_reduce(S.partials, defl_partial_blocks(S.defl), nd, S.slots, SW, nullptr, S.s);
+      launch_defl_combine(S.defl, r, 1.0, nullptr, 0.0, S.slots, SW, N, S.s);
+    }
     dot(S, r, r, S_TMP);
-    WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
-    const double beta0 = std::sqrt(ctx->hbuf[S_TMP]);
-    if (!std::isfinite(beta0)) WH_FAIL(ctx, WH_EUNSTABLE, "non-finite residual in GMRES");
-    rel = beta0 / nb;
+    WHCHK(readback(ctx, S.slots, nd ? SW + nd : S_NSLOTS_FIXED));
+    double r2 = ctx->hbuf[S_TMP];
+    const double beta0 = std::sqrt(r2);
+    for (int i = 0; i < nd; ++i) {
+      gW[i] = ctx->hbuf[SW + i];
+      r2 += gW[i] * gW[i];
+    }
+    if (!std::isfinite(r2)) WH_FAIL(ctx, WH_EUNSTABLE, "non-finite residual in GMRES");
+    rel = std::sqrt(r2) / nb;
     if (rel <= tol || its >= maxit) break;
-    launch_scale_copy(basis, r, S.slots, S_TMP, N, S.s);
     std::fill(g.begin(), g.end(), 0.0);
+    std::fill(HW.begin(), HW.end(), 0.0);
     g[0] = beta0;
     int kk = 0;
     bool done = false;
-    for (int k = 0; k < m; ++k) {
-      double* vk = basis + (size_t)k * N;
-      double* w = basis + (size_t)(k + 1) * N;
-      applyA(S, f32, vk, w);
-      // MGS: h_ik = v_i . w ; w -= h_ik v_i, fused pairwise
-      launch_axpy_dot(w, nullptr, S.slots, 0, basis, N, S.partials2, S.s);
-      launch_reduce(S.partials2, kReduceBlocks, S.slots, S_H + 0, 0, S.s);
-      for (int i = 1; i <= k; ++i) {
-        launch_axpy_dot(w, basis + (size_t)(i - 1) * N, S.slots, S_H + i - 1,
-                        basis + (size_t)i * N, N, S.partials2, S.s);
-        launch_reduce(S.partials2, kReduceBlocks, S.slots, S_H + i, 0, S.s);
+    if (beta0 > 0) {
+      launch_scale_copy(basis, r, S.slots, S_TMP, N, S.s);
+      for (int k = 0; k < m; ++k) {
+        double* vk = basis + (size_t)k * N;
+        double* w = basis + (size_t)(k + 1) * N;
+        applyA(S, f32, vk, w);
+        if (nd) {
+          // h_{W,k} = W^T w; w <- w - W h_{W,k}
+          launch_defl_project(S.defl, w, S.partials, S.s);
+          launch_defl_reduce(S.partials, defl_partial_blocks(S.defl), nd, S.slots, SW, nullptr, S.s);
+          launch_defl_combine(S.defl, w, 1.0, nullptr, 0.0, S.slots, SW, N, S.s);
+        }
+        // MGS: h_ik = v_i . w ; w -= h_ik v_i, fused pairwise
+        launch_axpy_dot(w, nullptr, S.slots, 0, basis, N, S.partials2, S.s);
+        launch_reduce(S.partials2, kReduceBlocks, S.slots, S_H + 0, 0, S.s);
+        for (int i = 1; i <= k; ++i) {
+          launch_axpy_dot(w, basis + (size_t)(i - 1) * N, S.slots, S_H + i - 1,
+                          basis + (size_t)i * N, N, S.partials2, S.s);
+          launch_reduce(S.partials2, kReduceBlocks, S.slots, S_H + i, 0, S.s);
+        }
+        launch_axpy_dot(w, vk, S.slots, S_H + k, nullptr, N, S.partials2, S.s);
+        launch_reduce(S.partials2, kReduceBlocks, S.slots, S_H + k + 1, 0, S.s);
+        WHCHK(readback(ctx, S.slots, nd ? SW + nd : S_H + k + 2));
+        for (int i = 0; i <= k; ++i) Hc(i, k) = ctx->hbuf[S_H + i];
+        for (int i = 0; i < nd; ++i) HW[(size_t)k * nd + i] = ctx->hbuf[SW + i];
+        const double hn2 = ctx->hbuf[S_H + k + 1];
+        if (!std::isfinite(hn2)) WH_FAIL(ctx, WH_EUNSTABLE, "non-finite Arnoldi vector");
+        Hc(k + 1, k) = std::sqrt(std::max(hn2, 0.0));
+        if (Hc(k + 1, k) > 0) launch_scale_copy(w, w, S.slots, S_H + k + 1, N, S.s);
+        for (int i = 0; i < k; ++i) {
+          const double t = cs[i] * Hc(i, k) + sn[i] * Hc(i + 1, k);
+          Hc(i + 1, k) = -sn[i] * Hc(i, k) + cs[i] * Hc(i + 1, k);
+          Hc(i, k) = t;
+        }
+        const double a = Hc(k, k), b = Hc(k + 1, k);
+        const double dd = std::hypot(a, b);
+        cs[k] = dd == 0 ? 1.0 : a / dd;
+        sn[k] = dd == 0 ? 0.0 : b / dd;
+        Hc(k, k) = dd;
+        Hc(k + 1, k) = 0.0;
+        g[k + 1] = -sn[k] * g[k];
+        g[k] = cs[k] * g[k];
+        ++its;
+        kk = k + 1;
+        if (std::fabs(g[k + 1]) < tol * nb || its >= maxit) {
+          done = true;
+          break;
+        }
+        if (dd == 0.0) WH_FAIL(ctx, WH_EBREAKDOWN, "GMRES breakdown (singular Hessenberg)");
+        if (b == 0.0) {  // lucky breakdown: exact solution in the space
+          done = true;
+          break;
+        }
       }
-      launch_axpy_dot(w, vk, S.slots, S_H + k, nullptr, N, S.partials2, S.s);
-      launch_reduce(S.partials2, kReduceBlocks, S.slots, S_H + k + 1, 0, S.s);
-      WHCHK(readback(ctx, S.slots, S_H + k + 2));
-      for (int i = 0; i <= k; ++i) Hc(i, k) = ctx->hbuf[S_H + i];
-      const double hn2 = ctx->hbuf[S_H + k + 1];
-      if (!std::isfinite(hn2)) WH_FAIL(ctx, WH_EUNSTABLE, "non-finite Arnoldi vector");
-      Hc(k + 1, k) = std::sqrt(std::max(hn2, 0.0));
-      if (Hc(k + 1, k) > 0) launch_scale_copy(w, w, S.slots, S_H + k + 1, N, S.s);
-      for (int i = 0; i < k; ++i) {
-        const double t = cs[i] * Hc(i, k) + sn[i] * Hc(i + 1, k);
-        Hc(i + 1, k) = -sn[i] * Hc(i, k) + cs[i] * Hc(i + 1, k);
-        Hc(i, k) = t;
-      }
-      const double a = Hc(k, k), b = Hc(k + 1, k);
-      const double dd = std::hypot(a, b);
-      cs[k] = dd == 0 ? 1.0 : a / dd;
-      sn[k] = dd == 0 ? 0.0 : b / dd;
-      Hc(k, k) = dd;
-      Hc(k + 1, k) = 0.0;
-      g[k + 1] = -sn[k] * g[k];
-      g[k] = cs[k] * g[k];
-      ++its;
-      kk = k + 1;
-      if (std::fabs(g[k + 1]) < tol * nb || its >= maxit) {
-        done = true;
-        break;
-      }
-      if (dd == 0.0) WH_FAIL(ctx, WH_EBREAKDOWN, "GMRES breakdown (singular Hessenberg)");
-      if (b == 0.0) {  // lucky breakdown: exact solution in the space
-        done = true;
-        break;
-      }
+    } else {
+      done = true;       // r lies in span W: the W part below is the whole correction
     }
     for (int i = kk - 1; i >= 0; --i) {
       double sacc = g[i];
       for (int j = i + 1; j < kk; ++j) sacc -= Hc(i, j) * y[j];
       y[i] = sacc / Hc(i, i);
     }
-    WHCHK(upload(ctx, S.slots + S_H, y.data(), kk));
-    launch_gemv_acc(x, basis, N, kk, S.slots + S_H, N, S.s);
-    if (done && its >= maxit) {
+    if (kk > 0) {
+      WHCHK(upload(ctx, S.slots + S_H, y.data(), kk));
+      launch_gemv_acc(x, basis, N, kk, S.slots + S_H, N, S.s);
+    }
+    if (nd) {
+      // y_W = (g_W - H_{W,K} y_K) / mu; x += W y_W (the combine kernel subtracts: store -y_W)
+      for (int i = 0; i < nd; ++i) {
+        double sacc = gW[i];
+        for (int j = 0; j < kk; ++j) sacc -= HW[(size_t)j * nd + i] * y[j];
+        yW[i] = -sacc / S.mu[i];
+      }
+      WHCHK(upload(ctx, S.slots + SW, yW.data(), nd));
+      launch_defl_combine(S.defl, x, 1.0, nullptr, 0.0, S.slots, SW, N, S.s);
+    }
+    if (done && (its >= maxit || nd)) {
+      // the true residual decides (with W the W part was solved exactly; check it)
       applyA(S, f32, x, basis);
       launch_sub(r, rhs, basis, N, S.s);
       dot(S, r, r, S_TMP);
       WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
       rel = std::sqrt(ctx->hbuf[S_TMP]) / nb;
-      break;
+      if (rel <= tol || its >= maxit) break;
+      x_nonzero = true;
+      first = true;
+      continue;
     }
-    (void)done;
   }
   res.rel = rel;
   res.iters = its;
@@ -736,8 +784,11 @@ wh_status gmres_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_
 }
 
 // Fixed-point iteration (Algorithm 1): x <- Pi_h(x; f) until ||Pi x - x|| <= tol ||b||.
+// deflate_iterates (Algorithm 2 with deflated iterates): after every step
+// x <- x - W W^T x; the update norm is then ||(I - W W^T)(Pi x - x)||, computed as
+// ||Pi x - x||^2 - ||W^T Pi x||^2 (x itself is deflated).
 wh_status fpi_solve(Solver& S, double* x, double tol, int maxit, int check_every,
-                    KrylovResult& res) {
+                    KrylovResult& res, bool deflate_iterates = false) {
   wh_ctx* ctx = S.ctx;
   // ||b||^2 (b = Pi_h(0; f)) is expected in slots[S_NB]
   double nb2 = 0;
@@ -745,15 +796,24 @@ wh_status fpi_solve(Solver& S, double* x, double tol, int maxit, int check_every
   int k = 0;
   double rel = 1.0;
   const int ce = std::max(1, check_every);
+  const int nd = deflate_iterates ? S.defl.nd : 0;
   while (k < maxit) {
     int nb = wave_solve(S.op64, x, true, M_LAST_FPI, x, x, S.s);
     S.ws64++;
     launch_reduce(S.partials, nb, S.slots, S_TMP, 0, S.s);
+    if (nd) {
+      // (S.partials is free again: the update-norm partials were reduced above)
+      launch_defl_project(S.defl, x, S.partials, S.s);
+      launch_defl_reduce(S.partials, defl_partial_blocks(S.defl), nd, S.slots, S_H, nullptr, S.s);
+      launch_defl_combine(S.defl, x, 1.0, nullptr, 0.0, S.slots, S_H, S.N, S.s);
+    }
     ++k;
     if (k % ce == 0 || k == maxit) {
-      WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
+      WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED + nd));
       nb2 = ctx->hbuf[S_NB];
-      rel = nb2 > 0 ? std::sqrt(ctx->hbuf[S_TMP] / nb2) : 0.0;
+      double d2 = ctx->hbuf[S_TMP];
+      for (int j = 0; j < nd; ++j) d2 -= ctx->hbuf[S_H + j] * ctx->hbuf[S_H + j];
+      rel = nb2 > 0 ? std::sqrt(std::max(d2, 0.0) / nb2) : 0.0;
       if (!std::isfinite(rel)) WH_FAIL(ctx, WH_EUNSTABLE, "non-finite FPI update");
       if (rel <= tol) break;
     }
@@ -895,6 +955,7 @@ void wh_params_default(wh_params* p) {
   p->reproject = -1;
   p->check_every = 1;
   p->mixed_form = -1;
+  p->devd = 0;
   p->k_shape = -1;
 }
 
@@ -912,17 +973,29 @@ const char* wh_status_string(wh_status s) {
   return "unknown status";
 }
 
+// Message of the last failed wh_create on this thread (there is no context to hold it).
+static thread_local std::string g_create_err;
+
 wh_status wh_create(wh_ctx** out, int device, void* stream) {
   if (!out) return WH_EINVAL;
   *out = nullptr;
   int count = 0;
-  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return WH_EHIP;
-  if (hipSetDevice(device) != hipSuccess) return WH_EHIP;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || device < 0 || device >= count) {
+    g_create_err = std::string("no such device (hipGetDeviceCount: ") + hipGetErrorString(e) + ")";
+    return WH_EHIP;
+  }
+  e = hipSetDevice(device);
+  if (e != hipSuccess) {
+    g_create_err = std::string("hipSetDevice: ") + hipGetErrorString(e);
+    return WH_EHIP;
+  }
   wh_ctx* c = new wh_ctx();
   c->device = device;
   c->stream = (hipStream_t)stream;
-  if (hipHostMalloc((void**)&c->hbuf, sizeof(double) * kHostScalars, hipHostMallocDefault) !=
-      hipSuccess) {
+  e = hipHostMalloc((void**)&c->hbuf, sizeof(double) * kHostScalars, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    g_create_err = std::string("hipHostMalloc: ") + hipGetErrorString(e);
     delete c;
     return WH_EHIP;
   }
@@ -944,7 +1017,7 @@ wh_status wh_set_stream(wh_ctx* ctx, void* stream) {
   return WH_OK;
 }
 
-const char* wh_last_error(const wh_ctx* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+const char* wh_last_error(const wh_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
 
 wh_status wh_time_params(const wh_grid* grid, const wh_params* params, double c_max, int32_t* m,
                          int32_t* nt, double* dt, double* omega_tilde) {
@@ -1115,8 +1188,15 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
   WHCHK(check_defl(ctx, grid, defl, c2 != nullptr));
   const int nd = defl_n(defl);
   if (P.solver == WH_DCG && nd == 0) WH_FAIL(ctx, WH_EINVAL, "DCG needs a deflation set");
-  if (P.solver != WH_DCG && nd > 0)
-    WH_FAIL(ctx, WH_EUNSUPPORTED, "deflation is used by DCG only");
+  if (P.devd < 0 || P.devd > 2) WH_FAIL(ctx, WH_EINVAL, "devd must be 0, 1 or 2");
+  const bool devd = P.devd > 0;
+  if (devd && (nd == 0 || P.solver == WH_DCG))
+    WH_FAIL(ctx, WH_EINVAL, "devd needs a deflation set and solver FPI, CG or GMRES");
+  if (P.devd == 2 && P.solver != WH_FPI) WH_FAIL(ctx, WH_EINVAL, "devd = 2 (deflated iterates) is for FPI");
+  if (!devd && P.solver != WH_DCG && P.solver != WH_GMRES && nd > 0)
+    WH_FAIL(ctx, WH_EUNSUPPORTED, "a deflation set is used by DCG, augmented GMRES or devd");
+  // GMRES with a deflation set (and no devd) is the augmented GMRES of Algorithm 4
+  const bool agmres = P.solver == WH_GMRES && nd > 0 && !devd;
   const bool mixed = P.precision == WH_MIXED;
   if (mixed && P.solver == WH_FPI) WH_FAIL(ctx, WH_EUNSUPPORTED, "FPI runs in FP64 only");
   const Layout L = make_layout(*grid, P, defl);
@@ -1178,8 +1258,10 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
       S.defl.ldv = defl->ldv;
     }
     std::vector<double> inv(nd), neg(nd);
+    S.mu.assign(nd, 0.0);
     for (int k = 0; k < nd; ++k) {
       const double mu = 1.0 - transfer(tp, lam2[k]);
+      S.mu[k] = mu;
       if (mu == 0.0) WH_FAIL(ctx, WH_EBREAKDOWN, "deflation vector %d is at resonance (mu = 0)", k);
       inv[k] = 1.0 / mu;
       neg[k] = -1.0 / mu;
@@ -1188,6 +1270,33 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
     WHCHK(upload(ctx, at<double>(ws, L.ones), neg.data(), nd));
     S.invmu = at<double>(ws, L.invmu);
     S.negmu = at<double>(ws, L.ones);
+    if (devd) {
+      // Algorithm 2: f_d = f - W W^T f (into r, then the forcing arrays are rebuilt from it);
+      // ones <- -(phi_k^T f) / (omega_fp^2 - lambda_k^2), added to the solution at the end
+      const double sh = std::sin(0.5 * tp.omega_w * tp.dt);
+      const double om2 = 4.0 * sh * sh / (tp.dt * tp.dt);
+      std::vector<double> sc(nd);
+      for (int k = 0; k < nd; ++k) {
+        const double den = om2 - lam2[k];
+        if (den == 0.0) WH_FAIL(ctx, WH_EBREAKDOWN, "deflation vector %d is at resonance", k);
+        sc[k] = -1.0 / den;
+      }
+      WHCHK(upload(ctx, at<double>(ws, L.invmu), sc.data(), nd));
+      const int pb = defl_partial_blocks(S.defl);
+      launch_defl_project(S.defl, f, S.partials, s);
+      launch_defl_reduce(S.partials, pb, nd, S.slots, S_H, nullptr, s);
+      launch_defl_reduce(S.partials, pb, nd, at<double>(ws, L.ones), 0, at<double>(ws, L.invmu), s);
+      launch_defl_combine(S.defl, r, 0.0, f, 1.0, S.slots, S_H, N, s);
+      const double h = 1.0 / grid->n;
+      const double dt2 = tp.dt * tp.dt;
+      const double ks = dt2 / (2.0 * h * h);
+      launch_prep_coeffs(c2, r, at<void>(ws, L.kap64), at<void>(ws, L.fs64), false, ks, dt2, N, grid->n,
+                         grid->dim, s);
+      if (mixed)
+        launch_prep_coeffs(c2, r, at<void>(ws, L.kap32), at<void>(ws, L.fs32), true, ks, dt2, N, grid->n,
+                           grid->dim, s);
+      HIPCHK(ctx, hipMemsetAsync(r, 0, 8 * N, s));
+    }
   }
   // b = Pi_h(0; f) in FP64: one wave solve from zero, accumulated into b
   {
@@ -1210,10 +1319,10 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
     if (P.solver == WH_FPI) {
       // FPI: x <- Pi x with the forcing on; ||b||^2 for the relative update
       dot(S, b, b, S_NB);
-      WHCHK(fpi_solve(S, u, P.tol, P.max_iters, P.check_every, kr));
+      WHCHK(fpi_solve(S, u, P.tol, P.max_iters, P.check_every, kr, P.devd == 2));
     } else if (P.solver == WH_GMRES) {
       WHCHK(gmres_solve(S, false, b, u, u_nonzero, r, at<double>(ws, L.basis), restart, P.tol,
-                        P.max_iters, kr));
+                        P.max_iters, kr, agmres));
     } else {
       WHCHK(cg_solve(S, false, b, u, u_nonzero, r, p, q, P.tol, P.max_iters, P.solver == WH_DCG,
                      reproject, P.check_every, kr));
@@ -1275,7 +1384,7 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
       KrylovResult ir;
       if (P.solver == WH_GMRES) {
         WHCHK(gmres_solve(S, inner_f32, ro, dv, false, r, at<double>(ws, L.basis), restart, t_in,
-                          P.max_iters - inner_total, ir));
+                          P.max_iters - inner_total, ir, agmres));
       } else {
         WHCHK(cg_solve(S, inner_f32, ro, dv, false, r, p, q, t_in, P.max_iters - inner_total,
                        P.solver == WH_DCG, reproject, P.check_every, ir, inner_f32));
@@ -1291,6 +1400,11 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
     S.iters = inner_total;
     kr.rel = rel;
     true_rel = rel;
+  }
+  if (devd) {
+    // Algorithm 2, inflation: u += sum_k (phi_k^T f) / (omega_fp^2 - lambda_k^2) phi_k
+    // (the coefficients were stored negated in the workspace before the solve)
+    launch_defl_combine(S.defl, u, 1.0, nullptr, 0.0, at<double>(ws, L.ones), 0, N, s);
   }
   HIPCHK(ctx, hipGetLastError());
   HIPCHK(ctx, hipStreamSynchronize(s));

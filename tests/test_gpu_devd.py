@@ -1,0 +1,110 @@
+"""GPU parity of direct eigenvector deflation (Algorithm 2: deflate the forcing, solve,
+inflate) against the oracle's DEVD and the direct Helmholtz solve."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import discretization as disc, modes, devd
+from _gpu import cuda, host, rel, oracle_tp
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(n=64, nd=6):
+    # a frequency just above a discrete eigenvalue: the near-resonant modes dominate
+    e = modes.eig1d(n)
+    omega = float(np.sqrt(e[6] + e[7]) * 1.0015)
+    f = wl.gaussian(2, n, (0.41, 0.57), 0.08)
+    sel, lam2 = modes.select_modes(2, n, omega, nd)
+    W = modes.mode_matrix(2, n, sel)
+    return n, omega, f, sel, lam2, W
+
+
+@pytest.mark.parametrize("solver,devd_mode", [("cg", 1), ("fpi", 1), ("fpi", 2), ("gmres", 1)])
+def test_devd_matches_oracle_and_direct(solver, devd_mode):
+    print(f"case devd {solver} mode={devd_mode}", flush=True)
+    import paper_2606_31842_amd as wh
+    # FPI converges at the rate max |beta_h| over the modes left: deflate more of them
+    n, omega, f, sel, lam2, W = _case(nd=40 if solver == "fpi" else 6)
+    tol = 1e-9 if solver == "fpi" else 1e-10
+    d = wh.sine_deflation(2, n, omega, len(sel))
+    u, info = wh.solve(cuda(f), omega, solver=solver, defl=d, devd=devd_mode, tol=tol, max_iters=20000,
+                       restart=30)
+    assert info["status"] == 0, info
+    L = disc.laplacian(2, n)
+    tp = oracle_tp(2, n, omega)
+    U = disc.direct_solve(L, omega, disc.to_interior(f))
+    xo, oi = devd.devd_solve(L, disc.to_interior(f), tp, W, lam2, method="cg" if solver == "gmres" else solver,
+                             tol=tol, maxit=20000, deflate_iterates=devd_mode == 2)
+    e, eo = rel(host(u), disc.to_nodal(U, 2, n)), rel(xo, U)
+    print(f"gpu err {e:.2e} oracle err {eo:.2e} iters {info['iters']} / {oi['iters']}", flush=True)
+    assert e < max(1e-8, 10 * eo)
+    if solver == "fpi":
+        # the fixed-point iteration is deterministic up to rounding: same iteration count
+        assert abs(info["iters"] - oi["iters"]) <= 1
+
+
+def test_devd_mixed_cg():
+    import paper_2606_31842_amd as wh
+    n, omega, f, sel, lam2, W = _case(n=96, nd=8)
+    d = wh.sine_deflation(2, n, omega, len(sel))
+    u, info = wh.solve(cuda(f), omega, solver="cg", defl=d, devd=1, tol=1e-9, precision="mixed",
+                       max_iters=20000)
+    U = disc.direct_solve_dst(2, n, omega, f)
+    assert info["status"] == 0
+    assert rel(host(u), U) < 2e-5
+
+
+def test_devd_deflation_speeds_up_fpi():
+    """FPI on the undeflated problem barely moves at this frequency; with the resonant
+    modes deflated it converges (the rate is max |beta_h| over the remaining modes)."""
+    import paper_2606_31842_amd as wh
+    n, omega, f, sel, lam2, W = _case(nd=40)
+    _, i0 = wh.solve(cuda(f), omega, solver="fpi", tol=1e-8, max_iters=300)
+    d = wh.sine_deflation(2, n, omega, len(sel))
+    _, i1 = wh.solve(cuda(f), omega, solver="fpi", defl=d, devd=2, tol=1e-8, max_iters=300)
+    assert i0["status"] == 1 and i1["status"] == 0 and i1["iters"] < 300
+
+
+def test_devd_rejects_bad_input():
+    import paper_2606_31842_amd as wh
+    n, omega, f, sel, lam2, W = _case(n=24, nd=2)
+    d = wh.sine_deflation(2, n, omega, 2)
+    with pytest.raises(wh.WaveHoltzError):
+        wh.solve(cuda(f), omega, solver="cg", devd=1)                 # no deflation set
+    with pytest.raises(wh.WaveHoltzError):
+        wh.solve(cuda(f), omega, solver="cg", defl=d, devd=2)         # deflated iterates: FPI only
+    with pytest.raises(wh.WaveHoltzError):
+        wh.solve(cuda(f), omega, solver="dcg", defl=d, devd=1)        # DEVD wraps FPI/CG/GMRES
+    with pytest.raises(wh.WaveHoltzError):
+        wh.solve(cuda(f), omega, solver="cg", defl=d)                 # a set without DCG or devd
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_augmented_gmres(precision):
+    """Algorithm 4 with the sine modes nearest resonance heading the basis: converges
+    where plain GMRES(m) stalls, to the oracle's solution."""
+    print(f"case agmres {precision}", flush=True)
+    import paper_2606_31842_amd as wh
+    from oracle import krylov, wavesolve as ws, transfer as tr
+    n, omega, f, sel, lam2, W = _case(nd=8)
+    d = wh.sine_deflation(2, n, omega, len(sel))
+    tol = 1e-9
+    u, info = wh.solve(cuda(f), omega, solver="gmres", defl=d, restart=20, tol=tol, max_iters=3000,
+                       precision=precision)
+    u0, info0 = wh.solve(cuda(f), omega, solver="gmres", restart=20, tol=tol, max_iters=3000,
+                         precision=precision)
+    assert info["status"] == 0, info
+    assert info["iters"] < info0["iters"]
+    U = disc.direct_solve_dst(2, n, omega, f)
+    assert rel(host(u), U) < (1e-7 if precision == "f64" else 2e-5)
+    if precision == "f64":
+        L = disc.laplacian(2, n)
+        tp = oracle_tp(2, n, omega)
+        b = ws.rhs(L, disc.to_interior(f), tp)
+        mu = 1 - tr.beta_discrete(lam2, tp)
+        xo, oi = krylov.agmres(lambda v: ws.apply_A(L, v, tp), b, W=W, AW=W * mu, restart=20, tol=tol,
+                               maxit=3000)
+        print(f"gpu iters {info['iters']} oracle iters {oi['iters']} (plain gpu {info0['iters']})", flush=True)
+        assert abs(info["iters"] - oi["iters"]) <= max(3, oi["iters"] // 10)
+        assert rel(host(u), disc.to_nodal(xo, 2, n)) < 1e-7
