@@ -196,7 +196,7 @@ def main():
             "rel_err_vs_oracle": float(np.linalg.norm(u64.cpu().numpy() - U) / np.linalg.norm(U))}
 
     traffic = None
-    src = os.path.join(ROOT, "paper_2606_31842_amd", "csrc", "wh_fused.hip")
+    src = os.path.join(ROOT, "paper_2606_31842_amd", "csrc", "wh_fused_kernel.h")
     import hashlib
     key = f"{kf},{kshape['rows']},{kshape['waves']}"
     if key in TRAFFIC["kib"] and hashlib.sha1(open(src, "rb").read()).hexdigest() == TRAFFIC["src_sha1"]:

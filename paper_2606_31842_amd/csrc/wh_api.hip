@@ -167,6 +167,8 @@ Layout make_layout(const wh_grid& g, const wh_params& P, const wh_deflation* def
   dd.dim = g.dim;
   dd.n = g.n;
   int np = std::max(kReduceBlocks, step_partial_blocks(g.dim, g.n));
+  // 2D blocked launches end with one partial per block; the smallest tile is 48 x 16
+  if (g.dim == 2) np = std::max(np, ((g.n - 1 + 47) / 48) * ((g.n - 1 + 15) / 16));
   if (nd) np = std::max(np, defl_partial_blocks(dd) * nd);
   L.npart = np;
   L.partials = take(L, 8 * (size_t)np);
@@ -299,9 +301,85 @@ void fused_shape_dims(int dim, bool f32, int shape, int* rows, int* waves) {
 // One wave solve from W^0 = vin.  last = M_LAST_V: V holds Pi_h(vin);
 // M_LAST_AQ: out = x - Pi_h(vin) with partial sums of x.out (x == vin);
 // M_LAST_FPI: out = Pi_h(vin) with partial sums of (out - x)^2.
+// Split N_t steps into blocked launches of supported sizes (K where possible).
+std::vector<int> plan_launches(int nt, int K, bool f32) {
+  std::vector<int> parts;
+  auto ok = [&](int k) { return k >= 2 && fused2d_supported(f32, k); };
+  // decompose r (>= 2) into supported sizes <= K, largest first (r <= 2K + 1)
+  auto split = [&](int r) {
+    std::vector<int> best;
+    for (int a = std::min(K, r); a >= 2; --a) {
+      if (!ok(a)) continue;
+      if (a == r) return std::vector<int>{a};
+      for (int b = std::min(a, r - a); b >= 2; --b) {
+        if (!ok(b)) continue;
+        if (a + b == r) return std::vector<int>{a, b};
+        for (int c = std::min(b, r - a - b); c >= 2; --c)
+          if (ok(c) && a + b + c == r) best = {a, b, c};
+      }
+      if (!best.empty()) return best;
+    }
+    return best;
+  };
+  int full = nt / K, rem = nt % K;
+  if (rem == 1 && full > 0) {
+    --full;
+    rem += K;
+  }
+  for (int i = 0; i < full; ++i) parts.push_back(K);
+  if (rem > 0) {
+    std::vector<int> tail = split(rem);
+    if (tail.empty()) return {};
+    parts.insert(parts.end(), tail.begin(), tail.end());
+  }
+  return parts;
+}
+
 int wave_solve(const WaveOp& op, const double* vin, bool force, StepMode last, const double* x,
                double* out, hipStream_t s) {
   const TimeParams& tp = *op.tp;
+  if (op.dim == 2 && op.k_fuse > 1 && fused2d_supported(op.f32, op.k_fuse)) {
+    // 2D: every step in blocked launches; the first starts from vin with the half step,
+    // the last ends in the epilogue (no streaming kernels)
+    const std::vector<int> parts = plan_launches(tp.nt, op.k_fuse, op.f32);
+    // at least two launches: vin (read with halo by the first) may alias out (written by
+    // the last), as in the fixed-point update x <- Pi x
+    if (parts.size() >= 2) {
+      FusedArgs fa{};
+      fa.V = op.V;
+      fa.kap = op.kap;
+      fa.fs = force ? op.fs : nullptr;
+      fa.a = op.a;
+      fa.n = op.n;
+      fa.shape = op.k_shape;
+      fa.vin = vin;
+      fa.w0 = tp.w[0];
+      fa.x = x;
+      fa.out = out;
+      fa.partials = op.partials;
+      void* cur = op.Wb;
+      void* prev = op.Wa;
+      void* oc = op.Wc;
+      void* op_ = op.Wd;
+      int nn = 0;
+      for (size_t i = 0; i < parts.size(); ++i) {
+        fa.k = parts[i];
+        fa.cur = cur;
+        fa.prev = prev;
+        fa.cur_out = oc;
+        fa.prev_out = op_;
+        fa.wts = &tp.w[nn + 1];
+        fa.cosv = &tp.cosv[nn];
+        fa.first = i == 0;
+        fa.last = i + 1 == parts.size() ? last : M_MID;
+        launch_fused2d(op.f32, op.varc, force, fa, s);
+        std::swap(cur, oc);
+        std::swap(prev, op_);
+        nn += parts[i];
+      }
+      return last == M_LAST_V ? 0 : fused2d_blocks(op.f32, parts.back(), op.k_shape, op.n);
+    }
+  }
   StepArgs a{};
   a.n = op.n;
   a.kap = op.kap;

@@ -109,6 +109,15 @@ struct FusedArgs {
   int n;
   int k;
   int shape;             // block shape index, 0 .. kFusedShapes-1
+  // 2D only: first launch of a wave solve (W^0 = vin, half step, V = w0 W^0 + ...) and
+  // last launch (final step ends in the epilogue `last` instead of storing the state)
+  int first = 0;
+  const double* vin = nullptr;
+  double w0 = 0;
+  int last = M_MID;
+  const double* x = nullptr;
+  double* out = nullptr;
+  double* partials = nullptr;
 };
 constexpr int kFusedShapes = 3;
 bool fused2d_supported(bool f32, int k);
@@ -117,6 +126,8 @@ int fused2d_default_shape(bool f32, int n);
 // Register rows per thread and wavefronts per block of a block shape.
 void fused2d_shape_dims(bool f32, int shape, int* rows, int* waves);
 void launch_fused2d(bool f32, bool varc, bool force, const FusedArgs& a, hipStream_t s);
+// Blocks (= partial sums) of a 2D blocked launch with this K and shape.
+int fused2d_blocks(bool f32, int k, int shape, int n);
 // 3D: K in {2, 3}; shapes give rows per thread, waves per block and output planes per block.
 bool fused3d_supported(bool f32, int k);
 void fused3d_shape_dims(bool f32, int shape, int* rows, int* waves, int* zs);
