@@ -35,12 +35,12 @@ B_PER_PT_STEP_F64 = 40.0
 # variant "K,R,NW" on this grid, from the two rocprofv3 counter passes summarised in
 # profiles/hbm_traffic_fused2d_f32_2d1024.md (scaled by FETCH x 2.000, WRITE x 1.000 from a
 # plain copy).  Valid only for the kernel source it was taken on.
-TRAFFIC = {"src_sha1": "e31d04c71e802e9ac7fbb9664fa002ddd0c4c7b2", "fetch_scale": 2.000, "write_scale": 1.000,
-           "kib": {"2,16,4": [8522.6, 16438.5], "2,8,4": [8408.5, 16408.1], "2,8,8": [8492.4, 16446.1],
-                   "3,16,4": [8590.1, 16436.6], "3,8,4": [8407.8, 16384.9], "3,8,8": [8554.6, 16441.6],
-                   "4,16,4": [8648.6, 16435.7], "4,8,4": [8528.6, 16405.0], "4,8,8": [8612.6, 16436.5],
-                   "6,16,4": [8719.4, 16412.2], "6,8,4": [8618.9, 16394.0], "6,8,8": [8665.4, 16416.4],
-                   "8,16,4": [8899.8, 16456.4], "8,8,4": [8711.8, 16384.2], "8,8,8": [8846.2, 16459.6]}}
+TRAFFIC = {"src_sha1": "457acf25e6cd650aa162e460476dab370fd59944", "fetch_scale": 2.000, "write_scale": 1.000,
+           "kib": {"2,16,4": [8526.6, 16439.8], "2,8,4": [8411.5, 16408.4], "2,8,8": [8495.4, 16445.4],
+                   "3,16,4": [8590.1, 16436.5], "3,8,4": [8407.8, 16384.8], "3,8,8": [8554.6, 16443.0],
+                   "4,16,4": [8652.1, 16435.2], "4,8,4": [8528.6, 16405.0], "4,8,8": [8612.6, 16435.9],
+                   "6,16,4": [8715.4, 16412.3], "6,8,4": [8611.4, 16394.0], "6,8,8": [8670.9, 16416.0],
+                   "8,16,4": [8903.8, 16460.9], "8,8,4": [8705.2, 16384.2], "8,8,8": [8846.2, 16455.9]}}
 
 
 def log(*a):
@@ -217,7 +217,7 @@ def main():
                   "rel_err_vs_oracle": err},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": (f"k_fused2d<float,{kf},{kshape['rows']},{kshape['waves']},false,false> ({kf} FP32 "
+                     "kernel": (f"k_fused2d<float,{kf},{kshape['rows']},{kshape['waves']},false,false,0> ({kf} FP32 "
                                 "leapfrog steps + FP64 filter sum per launch)") if kf > 1
                                else "k_step2d<float,M_MID> (FP32 leapfrog + FP64 filter)",
                      "k_fuse": kf, "bytes_per_pt_step": B_PER_PT_STEP_F32, "pt_steps_per_launch": units,
