@@ -85,10 +85,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 single-solve comparison")
-    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"],
+    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5", "solvers"],
                     help="cfg2 (default) is the benchmark line; the others report the remaining "
                          "workloads (2D 64^2 FP64 CG; 3D 256^3 variable c; 256 batched solves; "
-                         "513^2 adjoint gradient)")
+                         "513^2 adjoint gradient; the config-2 problem by every solver)")
     ap.add_argument("--max-iters", type=int, default=0, help="iteration cap (cfg3)")
     ap.add_argument("--per-size", type=int, default=64, help="problems per grid size (cfg4)")
     ap.add_argument("--probe-traffic", action="store_true",
@@ -362,7 +362,41 @@ def run_cfg5(args, np, torch, wh, wl):
             "fd_directional": fd, "adjoint_directional": an, "fd_rel_diff": abs(fd - an) / abs(an)}
 
 
-EXTRA = {"cfg1": run_cfg1, "cfg3": run_cfg3, "cfg4": run_cfg4, "cfg5": run_cfg5}
+def run_solvers(args, np, torch, wh, wl):
+    """The config-2 problem (2D 1024^2, omega = 100.3) by every solver of the library, true
+    residual 1e-8: CG, DCG with N_D sine modes, Algorithm 2 (DEVD) around CG, GMRES(40) and
+    GMRES(40) augmented with the modes in mixed precision; DEVD around FPI with deflated iterates
+    in FP64.  Errors against the oracle's DST solve."""
+    from oracle import discretization as disc
+    p = wl.config2()
+    n = p.n
+    f = torch.from_numpy(p.f).cuda()
+    U = disc.direct_solve_dst(2, n, p.omega, p.f)
+    cap = args.max_iters or 6000
+    runs = [("cg", 0, {}), ("dcg", 8, {}), ("dcg", 32, {}), ("dcg", 64, {}),
+            ("cg", 32, {"devd": 1}), ("fpi", 32, {"devd": 2}), ("gmres", 0, {}), ("gmres", 32, {})]
+    out = {"workload": "config-2 problem (2D 1024^2, c = 1, omega = 100.3) by every solver, tol 1e-8",
+           "max_iters": cap}
+    for solver, nd, extra in runs:
+        # the fixed-point iteration runs in FP64 only
+        kw = dict(solver=solver, precision="f64" if solver == "fpi" else "mixed", tol=1e-8, max_iters=cap,
+                  restart=40, **extra)
+        if nd:
+            kw["defl"] = wh.sine_deflation(2, n, p.omega, nd)
+        wh.solve(f, p.omega, **{**kw, "max_iters": 2})   # autotune and warm up outside the timing
+        (u, info), dt = _timed(torch, lambda: wh.solve(f, p.omega, **kw))
+        name = ("devd_" if extra.get("devd") else "") + solver + (f"_nd{nd}" if nd else "")
+        if solver == "gmres" and nd:
+            name = f"agmres_nd{nd}"
+        out[name] = {"seconds": dt, "precision": kw["precision"], "status": info["status"], "iters": info["iters"],
+                     "wave_solves_f32": info["wave_solves_f32"], "wave_solves_f64": info["wave_solves"],
+                     "true_rel_res": info["true_rel_res"],
+                     "rel_err_vs_oracle": float(np.linalg.norm(u.cpu().numpy() - U) / np.linalg.norm(U))}
+        log(name, out[name])
+    return out
+
+
+EXTRA = {"cfg1": run_cfg1, "solvers": run_solvers, "cfg3": run_cfg3, "cfg4": run_cfg4, "cfg5": run_cfg5}
 
 
 if __name__ == "__main__":
