@@ -170,6 +170,8 @@ Layout make_layout(const wh_grid& g, const wh_params& P, const wh_deflation* def
   // 2D blocked launches end with one partial per block; the smallest tile is 48 x 16
   if (g.dim == 2) np = std::max(np, ((g.n - 1 + 47) / 48) * ((g.n - 1 + 15) / 16));
   if (nd) np = std::max(np, defl_partial_blocks(dd) * nd);
+  // Gram-Schmidt partials of GMRES: [kReduceBlocks][restart + 1]
+  if (P.solver == WH_GMRES) np = std::max(np, kReduceBlocks * (restart + 2));
   L.npart = np;
   L.partials = take(L, 8 * (size_t)np);
   L.partials2 = take(L, 8 * (size_t)kReduceBlocks);
@@ -709,7 +711,7 @@ wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_non
   return WH_OK;
 }
 
-// Restarted GMRES(m), Algorithm 4: modified Gram-Schmidt on the device, Givens
+// Restarted GMRES(m), Algorithm 4: classical Gram-Schmidt (second pass when needed) on the device, Givens
 // rotations and the triangular solve on the host.  With use_defl the Krylov space is
 // augmented by the deflation set W (exact eigenvectors, A W = W diag(mu)): the QR of A W
 // is W diag(mu), so W itself heads the basis, the restart vector is (I - W W^T) r, every
@@ -723,6 +725,7 @@ wh_status gmres_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_
   const int64_t N = S.N;
   const int nd = use_defl ? S.defl.nd : 0;
   const int SW = S_H + m + 2;   // slots for the W coefficients
+  const int SH2 = SW + nd;      // Gram-Schmidt coefficients (m + 1 slots)
   dot(S, rhs, rhs, S_NB);
   WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
   const double nb = std::sqrt(ctx->hbuf[S_NB]);
@@ -778,18 +781,21 @@ wh_status gmres_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_
           launch_defl_reduce(S.partials, defl_partial_blocks(S.defl), nd, S.slots, SW, nullptr, S.s);
           launch_defl_combine(S.defl, w, 1.0, nullptr, 0.0, S.slots, SW, N, S.s);
         }
-        // MGS: h_ik = v_i . w ; w -= h_ik v_i, fused pairwise
-        launch_axpy_dot(w, nullptr, S.slots, 0, basis, N, S.partials2, S.s);
-        launch_reduce(S.partials2, kReduceBlocks, S.slots, S_H + 0, 0, S.s);
-        for (int i = 1; i <= k; ++i) {
-          launch_axpy_dot(w, basis + (size_t)(i - 1) * N, S.slots, S_H + i - 1,
-                          basis + (size_t)i * N, N, S.partials2, S.s);
-          launch_reduce(S.partials2, kReduceBlocks, S.slots, S_H + i, 0, S.s);
-        }
-        launch_axpy_dot(w, vk, S.slots, S_H + k, nullptr, N, S.partials2, S.s);
+        // classical Gram-Schmidt applied twice (CGS2), three passes over the basis and one
+        // read-back per step: h1 = V^T w; w -= V h1 with h2 = V^T w in the same pass;
+        // w -= V h2 with ||w||^2.  Column k of H is h1 + h2.  (For this operator the first
+        // pass nearly always cancels most of w, so the second is needed anyway.)
+        const int nv = k + 1;
+        launch_gs_project(basis, N, nv, w, S.partials, S.s);
+        launch_defl_reduce(S.partials, kReduceBlocks, nv, S.slots, SH2, nullptr, S.s);
+        launch_gs_update(basis, N, nv, S.slots, SH2, w, true, S.partials, S.s);
+        // partials [block][nv + 1]: h2, then an intermediate norm that lands in the slot the
+        // final norm overwrites
+        launch_defl_reduce(S.partials, kReduceBlocks, nv + 1, S.slots, S_H, nullptr, S.s);
+        launch_gs_update(basis, N, nv, S.slots, S_H, w, false, S.partials2, S.s);
         launch_reduce(S.partials2, kReduceBlocks, S.slots, S_H + k + 1, 0, S.s);
-        WHCHK(readback(ctx, S.slots, nd ? SW + nd : S_H + k + 2));
-        for (int i = 0; i <= k; ++i) Hc(i, k) = ctx->hbuf[S_H + i];
+        WHCHK(readback(ctx, S.slots, SH2 + nv));
+        for (int i = 0; i <= k; ++i) Hc(i, k) = ctx->hbuf[SH2 + i] + ctx->hbuf[S_H + i];
         for (int i = 0; i < nd; ++i) HW[(size_t)k * nd + i] = ctx->hbuf[SW + i];
         const double hn2 = ctx->hbuf[S_H + k + 1];
         if (!std::isfinite(hn2)) WH_FAIL(ctx, WH_EUNSTABLE, "non-finite Arnoldi vector");

@@ -234,29 +234,6 @@ void launch_copy(double* y, const double* x, int64_t N, hipStream_t s) {
   hipLaunchKernelGGL(k_copy, dim3(grid_for(N)), dim3(kBlock), 0, s, y, x, N);
 }
 
-// Modified Gram-Schmidt step: w -= h v (h = slots[hslot]); partial sums of w . vnext.
-__global__ void k_axpy_dot(double* w, const double* v, const double* slots, int hslot,
-                           const double* vnext, int64_t N, double* partials) {
-  const double h = v ? slots[hslot] : 0.0;
-  double acc = 0.0;
-  GRID_STRIDE(i, N) {
-    double wv = w[i];
-    if (v) {
-      wv -= h * v[i];
-      w[i] = wv;
-    }
-    acc += vnext ? wv * vnext[i] : wv * wv;
-  }
-  double s = block_sum256(acc, threadIdx.x);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
-}
-
-void launch_axpy_dot(double* w, const double* v, const double* slots, int hslot,
-                     const double* vnext, int64_t N, double* partials, hipStream_t s) {
-  hipLaunchKernelGGL(k_axpy_dot, dim3(kReduceBlocks), dim3(kBlock), 0, s, w, v, slots, hslot, vnext,
-                     N, partials);
-}
-
 // x += sum_{c<k} y[c] V[:, c]
 __global__ void k_gemv_acc(double* x, const double* V, int64_t ldv, int k, const double* y,
                            int64_t N) {
@@ -336,17 +313,40 @@ void launch_sine_tables(double* tab, const int32_t* modes_dev, int nd, int dim, 
 constexpr int kDChunk = 32;   // modes per register pass
 constexpr int kRowsPerBlock = 8;
 
-// Multi-value block sum: vals[c] summed over the 256 threads, written by thread c.
+// Multi-value block sum: vals[c] summed over the 256 threads (4 waves), out[c] written by
+// thread c.  C is a power of two <= 32.  Within a wave the value set is halved at every
+// exchange: at lane distance o the lane keeps the half selected by bit o of its index and
+// adds the partner's copy of that half (log2 C steps, C - 1 shuffles in all), after which
+// each lane holds one value summed over 64 / C lanes; plain exchanges finish the sum over
+// the wave.  The four wave sums are added in a fixed order, so results are reproducible.
+// one halving step at lane distance O: keep H of the 2H live values (compile-time indices)
+template <int C, int H, int O>
+__device__ __forceinline__ void halve_values(double (&vals)[C], int lane, int& idx) {
+  if constexpr (H >= 1) {
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const double give = up ? vals[i] : vals[i + H];
+      const double keep = up ? vals[i + H] : vals[i];
+      vals[i] = keep + __shfl_xor(give, O, 64);
+    }
+    if (up) idx += H;
+    halve_values<C, H / 2, O / 2>(vals, lane, idx);
+  }
+}
+
 template <int C>
 __device__ __forceinline__ void block_sum_multi(double (&vals)[C], double* out, int tid) {
-  __shared__ double sm[4][C];
+  static_assert(C >= 1 && C <= 32 && (C & (C - 1)) == 0, "power of two <= 32");
+  __shared__ double sw[4][C];
+  const int wv = tid >> 6, lane = tid & 63;
+  int idx = 0;
+  halve_values<C, C / 2, 32>(vals, lane, idx);
 #pragma unroll
-  for (int c = 0; c < C; ++c) {
-    double v = wave_sum(vals[c]);
-    if ((tid & 63) == 0) sm[tid >> 6][c] = v;
-  }
+  for (int o = 32 / C; o >= 1; o >>= 1) vals[0] += __shfl_xor(vals[0], o, 64);
+  if ((lane & (64 / C - 1)) == 0) sw[wv][idx] = vals[0];
   __syncthreads();
-  if (tid < C) out[tid] = (sm[0][tid] + sm[1][tid]) + (sm[2][tid] + sm[3][tid]);
+  if (tid < C) out[tid] = (sw[0][tid] + sw[1][tid]) + (sw[2][tid] + sw[3][tid]);
   __syncthreads();
 }
 
@@ -365,10 +365,14 @@ __global__ __launch_bounds__(256) void k_sine_project(const double* tab, int nd,
   const int blk = blockIdx.y * gridDim.x + blockIdx.x;
   const bool col_ok = i < P;
   double rv[kRowsPerBlock];
+  int jr[kRowsPerBlock], zr[kRowsPerBlock];   // y (and z) index of each row, hoisted
 #pragma unroll
   for (int t = 0; t < kRowsPerBlock; ++t) {
     const int64_t rr = r0 + t;
     rv[t] = (col_ok && rr < rows) ? r[rr * P + i] : 0.0;
+    const int rc = (int)min(rr, rows - 1);
+    jr[t] = rc % P;
+    zr[t] = rc / P;
   }
   for (int k0 = 0; k0 < nd; k0 += kDChunk) {
     double acc[kDChunk];
@@ -378,12 +382,12 @@ __global__ __launch_bounds__(256) void k_sine_project(const double* tab, int nd,
       const double sx = (col_ok && k < nd) ? tab[(int64_t)(k * dim) * P + i] : 0.0;
       double a = 0.0;
       if (k < nd) {
+        const double* ty = tab + (int64_t)(k * dim + 1) * P;
+        const double* tz = tab + (int64_t)(k * dim + 2) * P;
 #pragma unroll
         for (int t = 0; t < kRowsPerBlock; ++t) {
-          const int64_t rr = min(r0 + t, rows - 1);
-          const int j = (int)(rr % P);
-          double fac = tab[(int64_t)(k * dim + 1) * P + j];
-          if (dim == 3) fac *= tab[(int64_t)(k * dim + 2) * P + (int)(rr / P)];
+          double fac = ty[jr[t]];
+          if (dim == 3) fac *= tz[zr[t]];
           a += rv[t] * fac;
         }
       }
@@ -396,26 +400,38 @@ __global__ __launch_bounds__(256) void k_sine_project(const double* tab, int nd,
   }
 }
 
-// Dense columns: grid-stride over rows; partials [block][nd].
-__global__ __launch_bounds__(256) void k_dense_project(const double* V, int64_t ldv, int nd,
-                                                       int64_t N, const double* r,
-                                                       double* partials) {
+// Columns of a dense block V (column stride ldv): partials[bx][c] = sum over the block's
+// points of V_c . r.  blockIdx.y picks a chunk of KC columns, so every column is read once
+// and r once per chunk; all KC loads of a point are issued before the products.
+template <int KC>
+__global__ __launch_bounds__(256) void k_cols_project(const double* V, int64_t ldv, int ncols,
+                                                      int64_t N, const double* r, double* partials) {
   const int tid = threadIdx.x;
-  for (int k0 = 0; k0 < nd; k0 += kDChunk) {
-    double acc[kDChunk];
+  const int c0 = blockIdx.y * KC;
+  const int nc = min(KC, ncols - c0);
+  double acc[KC];
 #pragma unroll
-    for (int c = 0; c < kDChunk; ++c) acc[c] = 0.0;
-    GRID_STRIDE(p, N) {
-      const double rv = r[p];
+  for (int i = 0; i < KC; ++i) acc[i] = 0.0;
+  GRID_STRIDE(p, N) {
+    double v[KC];
 #pragma unroll
-      for (int c = 0; c < kDChunk; ++c)
-        if (k0 + c < nd) acc[c] += V[(int64_t)(k0 + c) * ldv + p] * rv;
-    }
-    __shared__ double red[kDChunk];
-    block_sum_multi<kDChunk>(acc, red, tid);
-    if (tid < kDChunk && k0 + tid < nd) partials[(int64_t)blockIdx.x * nd + k0 + tid] = red[tid];
-    __syncthreads();
+    for (int i = 0; i < KC; ++i) v[i] = i < nc ? V[(int64_t)(c0 + i) * ldv + p] : 0.0;
+    const double rv = r[p];
+#pragma unroll
+    for (int i = 0; i < KC; ++i) acc[i] += v[i] * rv;
   }
+  __shared__ double red[KC];
+  block_sum_multi<KC>(acc, red, tid);
+  if (tid < nc) partials[(int64_t)blockIdx.x * ncols + c0 + tid] = red[tid];
+}
+
+static void launch_cols_project(const double* V, int64_t ldv, int ncols, int64_t N, const double* r,
+                                double* partials, hipStream_t s) {
+  const int kc = ncols <= 8 ? 8 : ncols <= 16 ? 16 : 32;
+  const dim3 g(kReduceBlocks, (unsigned)((ncols + kc - 1) / kc)), b(256);
+  if (kc == 8) hipLaunchKernelGGL(k_cols_project<8>, g, b, 0, s, V, ldv, ncols, N, r, partials);
+  else if (kc == 16) hipLaunchKernelGGL(k_cols_project<16>, g, b, 0, s, V, ldv, ncols, N, r, partials);
+  else hipLaunchKernelGGL(k_cols_project<32>, g, b, 0, s, V, ldv, ncols, N, r, partials);
 }
 
 static dim3 sine_grid(const Defl& d) {
@@ -438,8 +454,7 @@ void launch_defl_project(const Defl& d, const double* r, double* partials, hipSt
                        partials);
   } else {
     int64_t P = d.n + 1, N = d.dim == 2 ? P * P : P * P * P;
-    hipLaunchKernelGGL(k_dense_project, dim3(kReduceBlocks), dim3(256), 0, s, d.V, d.ldv, d.nd, N, r,
-                       partials);
+    launch_cols_project(d.V, d.ldv, d.nd, N, r, partials, s);
   }
 }
 
@@ -470,19 +485,26 @@ __global__ __launch_bounds__(256) void k_sine_combine(const double* tab, int nd,
   if (i >= P) return;
   const double al = aslot >= 0 ? slots[aslot] : alpha;
   double sum[kRowsPerBlock];
+  int jr[kRowsPerBlock], zr[kRowsPerBlock];   // y (and z) index of each row, hoisted
 #pragma unroll
-  for (int t = 0; t < kRowsPerBlock; ++t) sum[t] = 0.0;
+  for (int t = 0; t < kRowsPerBlock; ++t) {
+    sum[t] = 0.0;
+    const int rc = (int)min(r0 + t, rows - 1);
+    jr[t] = rc % P;
+    zr[t] = rc / P;
+  }
   for (int k0 = 0; k0 < nd; k0 += kDChunk) {
 #pragma unroll 4
     for (int c = 0; c < kDChunk; ++c) {
       const int k = k0 + c;
       if (k >= nd) break;
       const double coef = slots[src + k] * tab[(int64_t)(k * dim) * P + i];
+      const double* ty = tab + (int64_t)(k * dim + 1) * P;
+      const double* tz = tab + (int64_t)(k * dim + 2) * P;
 #pragma unroll
       for (int t = 0; t < kRowsPerBlock; ++t) {
-        const int64_t rr = min(r0 + t, rows - 1);
-        double fac = tab[(int64_t)(k * dim + 1) * P + (int)(rr % P)];
-        if (dim == 3) fac *= tab[(int64_t)(k * dim + 2) * P + (int)(rr / P)];
+        double fac = ty[jr[t]];
+        if (dim == 3) fac *= tz[zr[t]];
         sum[t] += coef * fac;
       }
     }
@@ -498,17 +520,121 @@ __global__ __launch_bounds__(256) void k_sine_combine(const double* tab, int nd,
   }
 }
 
-__global__ void k_dense_combine(const double* V, int64_t ldv, int nd, int64_t N, double* y,
-                                double alpha, int aslot, const double* r, double beta,
-                                const double* slots, int src) {
+// s = sum_k c_k V_k in column order, 16 columns' loads issued at a time
+__device__ __forceinline__ double cols_sum(const double* V, int64_t ldv, int nd, const double* c,
+                                           int64_t p) {
+  double sacc = 0.0;
+  for (int k0 = 0; k0 < nd; k0 += 16) {
+    double v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = k0 + i < nd ? V[(int64_t)(k0 + i) * ldv + p] : 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (k0 + i < nd) sacc += c[k0 + i] * v[i];
+  }
+  return sacc;
+}
+
+__global__ __launch_bounds__(256) void k_dense_combine(const double* V, int64_t ldv, int nd, int64_t N,
+                                                       double* y, double alpha, int aslot,
+                                                       const double* r, double beta,
+                                                       const double* slots, int src) {
   const double al = aslot >= 0 ? slots[aslot] : alpha;
   GRID_STRIDE(p, N) {
-    double s = 0.0;
-    for (int k = 0; k < nd; ++k) s += slots[src + k] * V[(int64_t)k * ldv + p];
-    double v = (al == 0.0 ? 0.0 : al * y[p]) - s;
+    const double sacc = cols_sum(V, ldv, nd, slots + src, p);
+    double v = (al == 0.0 ? 0.0 : al * y[p]) - sacc;
     if (r) v += beta * r[p];
     y[p] = v;
   }
+}
+
+// w -= V h, h = slots[hsrc ..], subtracted column by column (bases wider than one register chunk)
+__global__ __launch_bounds__(256) void k_gs_sub(const double* V, int64_t N, int nv, const double* slots,
+                                                int hsrc, double* w) {
+  GRID_STRIDE(p, N) {
+    double wp = w[p];
+    for (int k0 = 0; k0 < nv; k0 += 16) {
+      double v[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = k0 + i < nv ? V[(int64_t)(k0 + i) * N + p] : 0.0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (k0 + i < nv) wp -= slots[hsrc + k0 + i] * v[i];
+    }
+    w[p] = wp;
+  }
+}
+
+// ---- classical Gram-Schmidt against an Arnoldi basis (column stride N)
+// h = V^T w over the first nv columns: partials [kReduceBlocks][nv] (the dense projection).
+void launch_gs_project(const double* V, int64_t N, int nv, const double* w, double* partials,
+                       hipStream_t s) {
+  launch_cols_project(V, N, nv, N, w, partials, s);
+}
+
+// w <- w - V h (h = slots[hsrc ..], subtracted in column order), then in the same pass either
+// the projection V^T w and ||w||^2 of the updated w (PROJ; partials [block][nv + 1], the norm
+// last) or ||w||^2 alone (partials [block]).  One read of the nv columns per point, kept in
+// registers between the two uses.
+template <int KC, bool PROJ>
+__global__ __launch_bounds__(256) void k_gs_update(const double* V, int64_t N, int nv,
+                                                   const double* slots, int hsrc, double* w,
+                                                   double* partials) {
+  const int tid = threadIdx.x;
+  double h[KC];
+#pragma unroll
+  for (int i = 0; i < KC; ++i) h[i] = i < nv ? slots[hsrc + i] : 0.0;
+  double acc[PROJ ? KC : 1];   // projections of the updated w
+#pragma unroll
+  for (int i = 0; i < (PROJ ? KC : 1); ++i) acc[i] = 0.0;
+  double nrm = 0.0;
+  GRID_STRIDE(p, N) {
+    double v[KC];
+#pragma unroll
+    for (int i = 0; i < KC; ++i) v[i] = i < nv ? V[(int64_t)i * N + p] : 0.0;
+    double wp = w[p];
+#pragma unroll
+    for (int i = 0; i < KC; ++i) wp -= h[i] * v[i];
+    w[p] = wp;
+    if constexpr (PROJ) {
+#pragma unroll
+      for (int i = 0; i < KC; ++i) acc[i] += v[i] * wp;
+    }
+    nrm += wp * wp;
+  }
+  const double t = block_sum256(nrm, tid);
+  if constexpr (PROJ) {
+    __shared__ double red[KC];
+    block_sum_multi<KC>(acc, red, tid);
+    if (tid < nv) partials[(int64_t)blockIdx.x * (nv + 1) + tid] = red[tid];
+    if (tid == 0) partials[(int64_t)blockIdx.x * (nv + 1) + nv] = t;
+  } else {
+    if (tid == 0) partials[blockIdx.x] = t;
+  }
+}
+
+template <bool PROJ>
+static void gs_update_kc(int kc, const double* V, int64_t N, int nv, const double* slots, int hsrc,
+                         double* w, double* partials, hipStream_t s) {
+  const dim3 g(kReduceBlocks), b(256);
+  if (kc == 8) hipLaunchKernelGGL((k_gs_update<8, PROJ>), g, b, 0, s, V, N, nv, slots, hsrc, w, partials);
+  else if (kc == 16) hipLaunchKernelGGL((k_gs_update<16, PROJ>), g, b, 0, s, V, N, nv, slots, hsrc, w, partials);
+  else hipLaunchKernelGGL((k_gs_update<32, PROJ>), g, b, 0, s, V, N, nv, slots, hsrc, w, partials);
+}
+
+void launch_gs_update(const double* V, int64_t N, int nv, const double* slots, int hsrc, double* w,
+                      bool proj, double* partials, hipStream_t s) {
+  if (nv <= 32) {
+    const int kc = nv <= 8 ? 8 : nv <= 16 ? 16 : 32;
+    if (proj) gs_update_kc<true>(kc, V, N, nv, slots, hsrc, w, partials, s);
+    else gs_update_kc<false>(kc, V, N, nv, slots, hsrc, w, partials, s);
+    return;
+  }
+  // wider bases: subtract, then project (w is the next column of the basis array, so the
+  // projection on nv + 1 columns ends with ||w||^2) or take the norm in a second pass
+  hipLaunchKernelGGL(k_gs_sub, dim3(grid_for(N)), dim3(256), 0, s, V, N, nv, slots, hsrc, w);
+  if (proj) launch_cols_project(V, N, nv + 1, N, w, partials, s);
+  else launch_dot_partials(w, w, N, partials, s);
 }
 
 static void combine_impl(const Defl& d, double* y, double alpha, int aslot, const double* r,

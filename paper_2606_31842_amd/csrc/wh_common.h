@@ -171,6 +171,14 @@ void launch_max_partials(const double* a, int64_t N, double* partials, bool neg,
 void launch_max_finalize(const double* partials, int count, double* out, hipStream_t s);
 void launch_dot_partials(const double* a, const double* b, int64_t N, double* partials,
                          hipStream_t s);
+// Classical Gram-Schmidt against the first nv columns of an Arnoldi basis V (column stride
+// N).  project: partials [kReduceBlocks][nv] of V^T w.  update: w <- w - V h with
+// h = slots[hsrc .. hsrc+nv), then partials of (V^T w, ||w||^2) (proj, [kReduceBlocks][nv+1];
+// w must be column nv of the basis array) or of ||w||^2 ([kReduceBlocks]) for the updated w.
+void launch_gs_project(const double* V, int64_t N, int nv, const double* w, double* partials,
+                       hipStream_t s);
+void launch_gs_update(const double* V, int64_t N, int nv, const double* slots, int hsrc, double* w,
+                      bool proj, double* partials, hipStream_t s);
 // slot[dst] = sum(partials[0..count)); mode 0 plain, 1: alpha = slot[R2]/sum (sum -> PQ),
 // 2: beta = sum/slot[R2], slot[R2] = sum
 void launch_reduce(const double* partials, int count, double* slots, int dst, int mode,
@@ -187,8 +195,6 @@ void launch_scale_copy(double* y, const double* x, const double* slots, int slot
                        hipStream_t s);  // y = x / sqrt(slot)
 void launch_sub(double* y, const double* a, const double* b, int64_t N, hipStream_t s);  // y=a-b
 void launch_copy(double* y, const double* x, int64_t N, hipStream_t s);
-void launch_axpy_dot(double* w, const double* v, const double* slots, int hslot,
-                     const double* vnext, int64_t N, double* partials, hipStream_t s);
 void launch_gemv_acc(double* x, const double* V, int64_t ldv, int k, const double* y_dev,
                      int64_t N, hipStream_t s);  // x += V[:, :k] y
 void launch_helmholtz_residual(const double* c2, const double* f, const double* u, double omega2,
