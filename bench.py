@@ -89,7 +89,10 @@ def main():
                     help="cfg2 (default) is the benchmark line; the others report the remaining "
                          "workloads (2D 64^2 FP64 CG; 3D 256^3 variable c; 256 batched solves; "
                          "513^2 adjoint gradient; the config-2 problem by every solver)")
-    ap.add_argument("--max-iters", type=int, default=0, help="iteration cap (cfg3)")
+    ap.add_argument("--max-iters", type=int, default=0, help="iteration cap (cfg3, solvers)")
+    ap.add_argument("--runs", default="", help="solvers: comma-separated subset of the run names "
+                                               "(cg, dcg_nd8, dcg_nd32, dcg_nd64, devd_cg_nd32, "
+                                               "devd_fpi_nd32, gmres, agmres_nd32)")
     ap.add_argument("--per-size", type=int, default=64, help="problems per grid size (cfg4)")
     ap.add_argument("--probe-traffic", action="store_true",
                     help="for hardware-counter runs: a plain 256 MiB device copy, then 5 wave solves "
@@ -377,7 +380,13 @@ def run_solvers(args, np, torch, wh, wl):
             ("cg", 32, {"devd": 1}), ("fpi", 32, {"devd": 2}), ("gmres", 0, {}), ("gmres", 32, {})]
     out = {"workload": "config-2 problem (2D 1024^2, c = 1, omega = 100.3) by every solver, tol 1e-8",
            "max_iters": cap}
+    only = [r for r in args.runs.split(",") if r]
     for solver, nd, extra in runs:
+        name = ("devd_" if extra.get("devd") else "") + solver + (f"_nd{nd}" if nd else "")
+        if solver == "gmres" and nd:
+            name = f"agmres_nd{nd}"
+        if only and name not in only:
+            continue
         # the fixed-point iteration runs in FP64 only
         kw = dict(solver=solver, precision="f64" if solver == "fpi" else "mixed", tol=1e-8, max_iters=cap,
                   restart=40, **extra)
@@ -385,9 +394,6 @@ def run_solvers(args, np, torch, wh, wl):
             kw["defl"] = wh.sine_deflation(2, n, p.omega, nd)
         wh.solve(f, p.omega, **{**kw, "max_iters": 2})   # autotune and warm up outside the timing
         (u, info), dt = _timed(torch, lambda: wh.solve(f, p.omega, **kw))
-        name = ("devd_" if extra.get("devd") else "") + solver + (f"_nd{nd}" if nd else "")
-        if solver == "gmres" and nd:
-            name = f"agmres_nd{nd}"
         out[name] = {"seconds": dt, "precision": kw["precision"], "status": info["status"], "iters": info["iters"],
                      "wave_solves_f32": info["wave_solves_f32"], "wave_solves_f64": info["wave_solves"],
                      "true_rel_res": info["true_rel_res"],

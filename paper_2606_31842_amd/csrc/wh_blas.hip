@@ -311,7 +311,6 @@ void launch_sine_tables(double* tab, const int32_t* modes_dev, int nd, int dim, 
 }
 
 constexpr int kDChunk = 32;   // modes per register pass
-constexpr int kRowsPerBlock = 8;
 
 // Multi-value block sum: vals[c] summed over the 256 threads (4 waves), out[c] written by
 // thread c.  C is a power of two <= 32.  Within a wave the value set is halved at every
@@ -350,53 +349,57 @@ __device__ __forceinline__ void block_sum_multi(double (&vals)[C], double* out, 
   __syncthreads();
 }
 
-// Sine modes, W^T r.  Rows of length P run along x; a row's mode factor is
-// prod_{axis>=1} tab[k][axis][coord], uniform across the row.  Each thread owns one
-// column i for the whole band of kRowsPerBlock rows: it keeps sx_k(i) in registers,
-// issues all the row loads first, then accumulates.  Grid: x = column chunks of 256,
-// y = row bands.  Partials layout [block][nd].
+// Sine modes, W^T r.  Rows of length P run along x; the mode factor of a row,
+// prod_{axis>=1} tab[k][axis][coord], is the same for the whole row.  A block covers 64
+// columns (one per lane) and 32 rows (8 per wave).  Per chunk of 32 modes the block first
+// stages the 32 x 32 row factors in LDS (four per thread) and every thread issues its 32
+// column-factor loads at once; then acc_k = sx_k(i) sum_t r(i, t) fy_k(t).  Partials
+// layout [block][nd].
+constexpr int kSineCols = 64, kSineRows = 32, kSineRowsPerWave = 8;
+
 __global__ __launch_bounds__(256) void k_sine_project(const double* tab, int nd, int dim, int n,
                                                       const double* r, double* partials) {
   const int P = n + 1;
-  const int64_t rows = dim == 2 ? (int64_t)P : (int64_t)P * P;
-  const int tid = threadIdx.x;
-  const int i = blockIdx.x * 256 + tid;
-  const int64_t r0 = (int64_t)blockIdx.y * kRowsPerBlock;
+  const int rows = dim == 2 ? P : P * P;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int i = blockIdx.x * kSineCols + lane;
+  const int rb = blockIdx.y * kSineRows;
   const int blk = blockIdx.y * gridDim.x + blockIdx.x;
   const bool col_ok = i < P;
-  double rv[kRowsPerBlock];
-  int jr[kRowsPerBlock], zr[kRowsPerBlock];   // y (and z) index of each row, hoisted
+  double rv[kSineRowsPerWave];
 #pragma unroll
-  for (int t = 0; t < kRowsPerBlock; ++t) {
-    const int64_t rr = r0 + t;
-    rv[t] = (col_ok && rr < rows) ? r[rr * P + i] : 0.0;
-    const int rc = (int)min(rr, rows - 1);
-    jr[t] = rc % P;
-    zr[t] = rc / P;
+  for (int t = 0; t < kSineRowsPerWave; ++t) {
+    const int row = rb + wv * kSineRowsPerWave + t;
+    rv[t] = (col_ok && row < rows) ? r[(int64_t)row * P + i] : 0.0;
   }
+  __shared__ double fy[kDChunk][kSineRows + 1];
+  __shared__ double red[kDChunk];
   for (int k0 = 0; k0 < nd; k0 += kDChunk) {
+    for (int e = tid; e < kDChunk * kSineRows; e += 256) {
+      const int c = e / kSineRows, t = e % kSineRows, k = k0 + c;
+      const int row = min(rb + t, rows - 1);
+      double fv = 0.0;
+      if (k < nd) {
+        fv = tab[(int64_t)(k * dim + 1) * P + row % P];
+        if (dim == 3) fv *= tab[(int64_t)(k * dim + 2) * P + row / P];
+      }
+      fy[c][t] = fv;
+    }
+    double sx[kDChunk];
+#pragma unroll
+    for (int c = 0; c < kDChunk; ++c)
+      sx[c] = (col_ok && k0 + c < nd) ? tab[(int64_t)((k0 + c) * dim) * P + i] : 0.0;
+    __syncthreads();
     double acc[kDChunk];
 #pragma unroll
     for (int c = 0; c < kDChunk; ++c) {
-      const int k = k0 + c;
-      const double sx = (col_ok && k < nd) ? tab[(int64_t)(k * dim) * P + i] : 0.0;
       double a = 0.0;
-      if (k < nd) {
-        const double* ty = tab + (int64_t)(k * dim + 1) * P;
-        const double* tz = tab + (int64_t)(k * dim + 2) * P;
 #pragma unroll
-        for (int t = 0; t < kRowsPerBlock; ++t) {
-          double fac = ty[jr[t]];
-          if (dim == 3) fac *= tz[zr[t]];
-          a += rv[t] * fac;
-        }
-      }
-      acc[c] = a * sx;
+      for (int t = 0; t < kSineRowsPerWave; ++t) a += rv[t] * fy[c][wv * kSineRowsPerWave + t];
+      acc[c] = a * sx[c];
     }
-    __shared__ double red[kDChunk];
-    block_sum_multi<kDChunk>(acc, red, tid);
+    block_sum_multi<kDChunk>(acc, red, tid);   // ends with a barrier: fy may be rewritten
     if (tid < kDChunk && k0 + tid < nd) partials[(int64_t)blk * nd + k0 + tid] = red[tid];
-    __syncthreads();
   }
 }
 
@@ -437,7 +440,7 @@ static void launch_cols_project(const double* V, int64_t ldv, int ncols, int64_t
 static dim3 sine_grid(const Defl& d) {
   int P = d.n + 1;
   int64_t rows = d.dim == 2 ? (int64_t)P : (int64_t)P * P;
-  return dim3((P + 255) / 256, (unsigned)((rows + kRowsPerBlock - 1) / kRowsPerBlock));
+  return dim3((P + kSineCols - 1) / kSineCols, (unsigned)((rows + kSineRows - 1) / kSineRows));
 }
 
 int defl_partial_blocks(const Defl& d) {
@@ -473,47 +476,52 @@ void launch_defl_reduce(const double* partials, int count, int nd, double* slots
                      scale_dev);
 }
 
-// y = alpha*y + beta*r - sum_k c_k W_k ; alpha taken from slots[aslot] if aslot >= 0
+// y = alpha*y + beta*r - sum_k c_k W_k ; alpha taken from slots[aslot] if aslot >= 0.
+// Same tiling as the projection: per chunk of 32 modes the row factors times c_k are staged
+// in LDS and the column factors loaded at once.
 __global__ __launch_bounds__(256) void k_sine_combine(const double* tab, int nd, int dim, int n,
                                                       double* y, double alpha, int aslot,
                                                       const double* r, double beta,
                                                       const double* slots, int src) {
   const int P = n + 1;
-  const int64_t rows = dim == 2 ? (int64_t)P : (int64_t)P * P;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.y * kRowsPerBlock;
-  if (i >= P) return;
+  const int rows = dim == 2 ? P : P * P;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int i = blockIdx.x * kSineCols + lane;
+  const int rb = blockIdx.y * kSineRows;
+  const bool col_ok = i < P;
   const double al = aslot >= 0 ? slots[aslot] : alpha;
-  double sum[kRowsPerBlock];
-  int jr[kRowsPerBlock], zr[kRowsPerBlock];   // y (and z) index of each row, hoisted
+  double sum[kSineRowsPerWave];
 #pragma unroll
-  for (int t = 0; t < kRowsPerBlock; ++t) {
-    sum[t] = 0.0;
-    const int rc = (int)min(r0 + t, rows - 1);
-    jr[t] = rc % P;
-    zr[t] = rc / P;
-  }
+  for (int t = 0; t < kSineRowsPerWave; ++t) sum[t] = 0.0;
+  __shared__ double fy[kDChunk][kSineRows + 1];
   for (int k0 = 0; k0 < nd; k0 += kDChunk) {
-#pragma unroll 4
-    for (int c = 0; c < kDChunk; ++c) {
-      const int k = k0 + c;
-      if (k >= nd) break;
-      const double coef = slots[src + k] * tab[(int64_t)(k * dim) * P + i];
-      const double* ty = tab + (int64_t)(k * dim + 1) * P;
-      const double* tz = tab + (int64_t)(k * dim + 2) * P;
-#pragma unroll
-      for (int t = 0; t < kRowsPerBlock; ++t) {
-        double fac = ty[jr[t]];
-        if (dim == 3) fac *= tz[zr[t]];
-        sum[t] += coef * fac;
+    for (int e = tid; e < kDChunk * kSineRows; e += 256) {
+      const int c = e / kSineRows, t = e % kSineRows, k = k0 + c;
+      const int row = min(rb + t, rows - 1);
+      double fv = 0.0;
+      if (k < nd) {
+        fv = slots[src + k] * tab[(int64_t)(k * dim + 1) * P + row % P];
+        if (dim == 3) fv *= tab[(int64_t)(k * dim + 2) * P + row / P];
       }
+      fy[c][t] = fv;
     }
-  }
+    double sx[kDChunk];
 #pragma unroll
-  for (int t = 0; t < kRowsPerBlock; ++t) {
-    const int64_t rr = r0 + t;
-    if (rr >= rows) break;
-    const int64_t p = rr * P + i;
+    for (int c = 0; c < kDChunk; ++c)
+      sx[c] = (col_ok && k0 + c < nd) ? tab[(int64_t)((k0 + c) * dim) * P + i] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kDChunk; ++c)
+#pragma unroll
+      for (int t = 0; t < kSineRowsPerWave; ++t) sum[t] += sx[c] * fy[c][wv * kSineRowsPerWave + t];
+    __syncthreads();   // fy is rewritten by the next chunk
+  }
+  if (!col_ok) return;
+#pragma unroll
+  for (int t = 0; t < kSineRowsPerWave; ++t) {
+    const int row = rb + wv * kSineRowsPerWave + t;
+    if (row >= rows) break;
+    const int64_t p = (int64_t)row * P + i;
     double v = (al == 0.0 ? 0.0 : al * y[p]) - sum[t];
     if (r) v += beta * r[p];
     y[p] = v;
