@@ -145,6 +145,28 @@ def config4(sizes=(128, 256, 512, 1024), per_size: int = 64, seed: int = 4,
     return out
 
 
+# ---------------------------------------------------------------- N_D sweep
+def ppw_grid_points(omega: float, order: int = 2, eps: float = 1e-3, size: float = 1.0,
+                    c: float = 1.0) -> float:
+    """Grid points per direction from the points-per-wavelength rule of thumb for an
+    order-p scheme (Section 2.2, eq. NxFromPPW): N = w (w b / (2 eps))^(1/p) with the
+    non-dimensional frequency w = omega size / c and b = 2 (q!)^2 / (2q+2)!, q = p/2."""
+    q = order // 2
+    b = 2.0 * math.factorial(q) ** 2 / math.factorial(2 * q + 2)
+    wn = omega * size / c
+    return wn * (wn * b / (2.0 * eps)) ** (1.0 / order)
+
+
+def ndsweep_problem(omega: float, eps: float = 1e-3) -> Problem:
+    """The frequency sweep of the deflation-size study (Section 4.2) on the unit square
+    with c = 1 and the second-order scheme: n from the PPW rule with relative error eps,
+    source omega^2 exp(-omega^2 |x - x0|^2) (eq. gaussianSource with a = omega^2,
+    b = omega) at the fixed interior point x0 = (0.3, 0.4)."""
+    n = int(math.ceil(ppw_grid_points(omega, 2, eps)))
+    f = gaussian(2, n, (0.3, 0.4), 1.0 / omega, amplitude=omega * omega)
+    return Problem(2, n, float(omega), f, None, f"ndsweep-{omega:g}", {"eps": eps})
+
+
 # ---------------------------------------------------------------- config 5
 def config5_c2(n: int, rng) -> np.ndarray:
     """c^2 = 1 + 0.2 P / max|P|, P a sum of 8 Gaussians (width 0.1) with a_i~U(-1,1)."""
