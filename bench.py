@@ -94,7 +94,8 @@ def main():
     ap.add_argument("--omegas", default="5:30", help="ndsweep: first:last (step 1) or a comma list")
     ap.add_argument("--runs", default="", help="solvers: comma-separated subset of the run names "
                                                "(cg, dcg_nd8, dcg_nd32, dcg_nd64, devd_cg_nd32, "
-                                               "devd_fpi_nd32, gmres, agmres_nd32)")
+                                               "devd_fpi_nd32, gmres, agmres_nd32, bicgstab, "
+                                               "abicgstab_nd32)")
     ap.add_argument("--per-size", type=int, default=64, help="problems per grid size (cfg4)")
     ap.add_argument("--probe-traffic", action="store_true",
                     help="for hardware-counter runs: a plain 256 MiB device copy, then 5 wave solves "
@@ -359,22 +360,23 @@ def run_cfg5(args, np, torch, wh, wl):
 
 def run_solvers(args, np, torch, wh, wl):
     """The config-2 problem (2D 1024^2, omega = 100.3) by every solver of the library, true
-    residual 1e-8: CG, DCG with N_D sine modes, Algorithm 2 (DEVD) around CG, GMRES(40) and
-    GMRES(40) augmented with the modes in mixed precision; DEVD around FPI with deflated iterates
+    residual 1e-8: CG, DCG with N_D sine modes, Algorithm 2 (DEVD) around CG, GMRES(40),
+    BiCGStab and both augmented with the modes (Algorithms 4, 5) in mixed precision; DEVD around FPI with deflated iterates
     in FP64.  Accuracy as the library's Helmholtz residual."""
     p = wl.config2()
     n = p.n
     f = torch.from_numpy(p.f).cuda()
     cap = args.max_iters or 6000
     runs = [("cg", 0, {}), ("dcg", 8, {}), ("dcg", 32, {}), ("dcg", 64, {}),
-            ("cg", 32, {"devd": 1}), ("fpi", 32, {"devd": 2}), ("gmres", 0, {}), ("gmres", 32, {})]
+            ("cg", 32, {"devd": 1}), ("fpi", 32, {"devd": 2}), ("gmres", 0, {}), ("gmres", 32, {}),
+            ("bicgstab", 0, {}), ("bicgstab", 32, {})]
     out = {"workload": "config-2 problem (2D 1024^2, c = 1, omega = 100.3) by every solver, tol 1e-8",
            "max_iters": cap}
     only = [r for r in args.runs.split(",") if r]
     for solver, nd, extra in runs:
         name = ("devd_" if extra.get("devd") else "") + solver + (f"_nd{nd}" if nd else "")
-        if solver == "gmres" and nd:
-            name = f"agmres_nd{nd}"
+        if solver in ("gmres", "bicgstab") and nd:
+            name = f"a{solver}_nd{nd}"
         if only and name not in only:
             continue
         # the fixed-point iteration runs in FP64 only

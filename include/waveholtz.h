@@ -57,7 +57,7 @@ typedef enum {
 } wh_status;
 
 typedef enum { WH_F64 = 0, WH_MIXED = 1 } wh_precision;
-typedef enum { WH_FPI = 0, WH_CG = 1, WH_DCG = 2, WH_GMRES = 3 } wh_solver;
+typedef enum { WH_FPI = 0, WH_CG = 1, WH_DCG = 2, WH_GMRES = 3, WH_BICGSTAB = 4 } wh_solver;
 
 /* Deflation sets (Section 2.1 "deflation set", Algorithm 3 matrix W). */
 typedef enum {
@@ -207,7 +207,11 @@ wh_status wh_apply_filter(wh_ctx* ctx, const wh_grid* grid, const double* c2, co
  * Helmholtz solution (L_h + omega^2) u = f (Sections 2.1-2.2).  u: device nodal, in:
  * initial guess, out: solution.  defl (exact eigenvectors) is required for WH_DCG
  * (Algorithm 3), augments WH_GMRES (Algorithm 4: W heads the Arnoldi basis, A W =
- * W diag(mu)), or with params->devd wraps FPI / CG / GMRES in Algorithm 2; else NULL. */
+ * W diag(mu)) and WH_BICGSTAB (Algorithm 5: the thin QR of A W is W diag(mu), every
+ * A-product is projected off W and the W part of the solution is recovered at the
+ * end), or with params->devd wraps FPI / CG / GMRES / BiCGStab in Algorithm 2; else
+ * NULL.  WH_BICGSTAB without defl is plain BiCGStab; in mixed precision it runs FP32
+ * inner solves inside FP64 residual refinement, like WH_GMRES. */
 wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const double* f,
                    const wh_deflation* defl, const wh_params* params, double* u,
                    void* ws, size_t ws_bytes, wh_info* info);

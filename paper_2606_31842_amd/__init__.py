@@ -16,10 +16,10 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _native as nat
-from ._native import (WH_F64, WH_MIXED, WH_FPI, WH_CG, WH_DCG, WH_GMRES, WH_DEFL_NONE,  # noqa: F401
+from ._native import (WH_F64, WH_MIXED, WH_FPI, WH_CG, WH_DCG, WH_GMRES, WH_BICGSTAB, WH_DEFL_NONE,  # noqa: F401
                       WH_DEFL_SINE, WH_DEFL_DENSE_EXACT, WH_DEFL_DENSE, WH_OK, WH_ENOCONV)
 
-_SOLVERS = {"fpi": WH_FPI, "cg": WH_CG, "dcg": WH_DCG, "gmres": WH_GMRES}
+_SOLVERS = {"fpi": WH_FPI, "cg": WH_CG, "dcg": WH_DCG, "gmres": WH_GMRES, "bicgstab": WH_BICGSTAB}
 _PRECISIONS = {"f64": WH_F64, "mixed": WH_MIXED}
 
 

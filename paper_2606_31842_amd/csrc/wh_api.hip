@@ -161,6 +161,7 @@ Layout make_layout(const wh_grid& g, const wh_params& P, const wh_deflation* def
     L.d = take(L, 8 * N);
   }
   if (P.solver == WH_GMRES) L.basis = take(L, 8 * N * (size_t)(restart + 1));
+  if (P.solver == WH_BICGSTAB) L.basis = take(L, 8 * N * 4);   // shadow residual, s, t, kept x
   Defl dd;
   dd.kind = nd ? defl->kind : WH_DEFL_NONE;
   dd.nd = nd;
@@ -867,6 +868,167 @@ wh_status gmres_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_
   return WH_OK;
 }
 
+// BiCGStab, Algorithm 5.  With use_defl the deflation set W (exact eigenvectors) plays
+// the part of the recycled space: the thin QR of A W is W diag(mu), so every A-product
+// is projected off W (e = W^T v, v -= W e), the W-coordinates xi gather -W^T r0 and
+// alpha e1 + omega e2 per step, and x -= W diag(mu)^{-1} xi recovers the W part at the
+// end of a run.  Scalars are formed on the host from FP64 device reductions (three
+// read-backs per step).  A run ends on the recursive residual; the true residual
+// b - A x then decides, and a further run restarts from it (new shadow residual).
+// BiCGStab's residual is not monotone: the iterate with the smallest recursive residual
+// is kept, and a run whose residual grows 1e3-fold past that minimum is abandoned for a
+// restart from it (after three such restarts the solve stops, res.diverged set, x the
+// kept iterate).  work: four vectors (shadow residual, s, t, kept x); r, p, v are the
+// caller's.
+wh_status bicgstab_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_nonzero,
+                         double* r, double* p, double* v, double* work, double tol, int maxit,
+                         KrylovResult& res, bool use_defl = false) {
+  wh_ctx* ctx = S.ctx;
+  const int64_t N = S.N;
+  const int nd = use_defl ? S.defl.nd : 0;
+  const int SE1 = S_H, SE2 = S_H + nd;   // W-projections of v and t
+  double* rt = work;
+  double* sv = work + N;
+  double* tv = work + 2 * N;
+  double* xb = work + 3 * N;   // kept iterate (W part applied)
+  dot(S, rhs, rhs, S_NB);
+  WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
+  const double nb = std::sqrt(ctx->hbuf[S_NB]);
+  res = KrylovResult{};
+  if (!(nb > 0)) return WH_OK;
+  std::vector<double> xi(nd, 0.0), e1(nd, 0.0), cW(nd, 0.0), xib(nd, 0.0);
+  bool xib_live = false;   // the kept iterate still lacks its W part (taken inside a run)
+  // e = W^T y into slots[dst]; y -= W e
+  auto project_off = [&](double* y, int dst) {
+    launch_defl_project(S.defl, y, S.partials, S.s);
+    launch_defl_reduce(S.partials, defl_partial_blocks(S.defl), nd, S.slots, dst, nullptr, S.s);
+    launch_defl_combine(S.defl, y, 1.0, nullptr, 0.0, S.slots, dst, N, S.s);
+  };
+  int its = 0, its_at_start = -1, blowups = 0;
+  double rel = 1.0, best = HUGE_VAL;
+  bool nonzero = x_nonzero;
+  while (true) {
+    // (re)start from the residual of the current x
+    if (nonzero) {
+      applyA(S, f32, x, v);
+      launch_sub(r, rhs, v, N, S.s);
+    } else {
+      launch_copy(r, rhs, N, S.s);
+    }
+    if (nd) project_off(r, SE1);
+    launch_copy(rt, r, N, S.s);
+    dot(S, r, r, S_R2);
+    WHCHK(readback(ctx, S.slots, nd ? SE1 + nd : S_NSLOTS_FIXED));
+    for (int i = 0; i < nd; ++i) xi[i] = -ctx->hbuf[SE1 + i];
+    double rho = ctx->hbuf[S_R2];   // rt^T r with rt = r
+    rel = std::sqrt(rho) / nb;
+    if (!std::isfinite(rel)) WH_FAIL(ctx, WH_EUNSTABLE, "non-finite residual in BiCGStab");
+    if (rel < best) {          // the run starts from the best iterate so far
+      best = rel;
+      launch_copy(xb, x, N, S.s);
+      xib_live = false;
+    }
+    if (rel <= tol || its >= maxit || res.diverged) {
+      res.rel = rel;
+      break;
+    }
+    if (its == its_at_start) WH_FAIL(ctx, WH_EBREAKDOWN, "BiCGStab breakdown at iteration %d", its);
+    its_at_start = its;
+    double rho_old = 1.0, alpha = 1.0, om = 1.0;
+    bool first = true, converged = false, blew_up = false;
+    while (its < maxit) {
+      if (rho == 0.0) break;   // breakdown of the shadow residual: restart
+      if (first) {
+        launch_copy(p, r, N, S.s);
+      } else {
+        const double beta = (rho / rho_old) * (alpha / om);
+        launch_lincomb3(p, 1.0, r, beta, p, -beta * om, v, N, S.s);
+      }
+      first = false;
+      applyA(S, f32, p, v);
+      if (nd) project_off(v, SE1);
+      dot(S, rt, v, S_TMP);
+      WHCHK(readback(ctx, S.slots, nd ? SE1 + nd : S_NSLOTS_FIXED));
+      const double rtv = ctx->hbuf[S_TMP];
+      for (int i = 0; i < nd; ++i) e1[i] = ctx->hbuf[SE1 + i];
+      if (!std::isfinite(rtv)) WH_FAIL(ctx, WH_EUNSTABLE, "non-finite BiCGStab scalar");
+      if (rtv == 0.0) break;   // restart
+      alpha = rho / rtv;
+      launch_lincomb3(sv, 1.0, r, -alpha, v, 0.0, nullptr, N, S.s);
+      dot(S, sv, sv, S_TMP2);
+      WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
+      if (std::sqrt(ctx->hbuf[S_TMP2]) <= tol * nb) {
+        launch_axpy(x, p, alpha, N, S.s);
+        launch_copy(r, sv, N, S.s);
+        for (int i = 0; i < nd; ++i) xi[i] += alpha * e1[i];
+        ++its;
+        rel = std::sqrt(ctx->hbuf[S_TMP2]) / nb;
+        converged = true;
+        break;
+      }
+      applyA(S, f32, sv, tv);
+      if (nd) project_off(tv, SE2);
+      dot(S, tv, sv, S_TMP);
+      dot(S, tv, tv, S_PQ);
+      WHCHK(readback(ctx, S.slots, nd ? SE2 + nd : S_NSLOTS_FIXED));
+      const double ts = ctx->hbuf[S_TMP], tt = ctx->hbuf[S_PQ];
+      if (!std::isfinite(ts) || !std::isfinite(tt)) WH_FAIL(ctx, WH_EUNSTABLE, "non-finite BiCGStab scalar");
+      om = tt > 0 ? ts / tt : 0.0;
+      for (int i = 0; i < nd; ++i) xi[i] += alpha * e1[i] + om * ctx->hbuf[SE2 + i];
+      launch_lincomb3(x, 1.0, x, alpha, p, om, sv, N, S.s);
+      launch_lincomb3(r, 1.0, sv, -om, tv, 0.0, nullptr, N, S.s);
+      rho_old = rho;
+      ++its;
+      dot(S, r, r, S_R2);
+      dot(S, rt, r, S_TMP);
+      WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
+      rel = std::sqrt(ctx->hbuf[S_R2]) / nb;
+      rho = ctx->hbuf[S_TMP];
+      if (!std::isfinite(rel)) WH_FAIL(ctx, WH_EUNSTABLE, "non-finite residual in BiCGStab");
+      if (rel <= tol) {
+        converged = true;
+        break;
+      }
+      if (rel < best) {
+        best = rel;
+        launch_copy(xb, x, N, S.s);
+        xib = xi;
+        xib_live = true;
+      } else if (rel > 1e3 * best) {   // abandon the run, restart from the kept iterate
+        blew_up = true;
+        break;
+      }
+      if (om == 0.0) break;    // stagnation of the stabilising step: restart
+    }
+    bool add_w = nd > 0;
+    if (blew_up) {
+      launch_copy(x, xb, N, S.s);
+      add_w = nd > 0 && xib_live;
+      xi = xib;
+      if (++blowups >= 3) res.diverged = true;
+    }
+    if (add_w) {
+      // x -= W diag(mu)^{-1} xi (the combine kernel subtracts sum_k c_k W_k)
+      for (int i = 0; i < nd; ++i) cW[i] = xi[i] / S.mu[i];
+      WHCHK(upload(ctx, S.slots + SE1, cW.data(), nd));
+      launch_defl_combine(S.defl, x, 1.0, nullptr, 0.0, S.slots, SE1, N, S.s);
+    }
+    if (blew_up) {
+      // the kept iterate is complete now: keep it so for a further blow-up
+      launch_copy(xb, x, N, S.s);
+      xib_live = false;
+    }
+    nonzero = true;
+    (void)converged;
+    // the next pass through the loop head forms the true residual b - A x and stops there
+    // if it meets tol or the iterations are spent; a pass that made no step is a breakdown
+  }
+  res.iters = its;
+  res.rel = rel;
+  res.st = rel <= tol ? WH_OK : WH_ENOCONV;
+  return WH_OK;
+}
+
 // Fixed-point iteration (Algorithm 1): x <- Pi_h(x; f) until ||Pi x - x|| <= tol ||b||.
 // deflate_iterates (Algorithm 2 with deflated iterates): after every step
 // x <- x - W W^T x; the update norm is then ||(I - W W^T)(Pi x - x)||, computed as
@@ -1264,7 +1426,7 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
   WHCHK(check_params(ctx, grid, params));
   if (!f || !u) WH_FAIL(ctx, WH_EINVAL, "f / u is NULL");
   const wh_params& P = *params;
-  if (P.solver < WH_FPI || P.solver > WH_GMRES) WH_FAIL(ctx, WH_EINVAL, "bad solver");
+  if (P.solver < WH_FPI || P.solver > WH_BICGSTAB) WH_FAIL(ctx, WH_EINVAL, "bad solver");
   if (!(P.tol > 0)) WH_FAIL(ctx, WH_EINVAL, "tol must be > 0");
   if (P.max_iters < 0) WH_FAIL(ctx, WH_EINVAL, "max_iters must be >= 0");
   if (P.solver == WH_GMRES && (P.restart < 1 || P.restart > 1000))
@@ -1275,12 +1437,14 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
   if (P.devd < 0 || P.devd > 2) WH_FAIL(ctx, WH_EINVAL, "devd must be 0, 1 or 2");
   const bool devd = P.devd > 0;
   if (devd && (nd == 0 || P.solver == WH_DCG))
-    WH_FAIL(ctx, WH_EINVAL, "devd needs a deflation set and solver FPI, CG or GMRES");
+    WH_FAIL(ctx, WH_EINVAL, "devd needs a deflation set and solver FPI, CG, GMRES or BiCGStab");
   if (P.devd == 2 && P.solver != WH_FPI) WH_FAIL(ctx, WH_EINVAL, "devd = 2 (deflated iterates) is for FPI");
-  if (!devd && P.solver != WH_DCG && P.solver != WH_GMRES && nd > 0)
-    WH_FAIL(ctx, WH_EUNSUPPORTED, "a deflation set is used by DCG, augmented GMRES or devd");
-  // GMRES with a deflation set (and no devd) is the augmented GMRES of Algorithm 4
-  const bool agmres = P.solver == WH_GMRES && nd > 0 && !devd;
+  if (!devd && (P.solver == WH_FPI || P.solver == WH_CG) && nd > 0)
+    WH_FAIL(ctx, WH_EUNSUPPORTED, "a deflation set is used by DCG, augmented GMRES / BiCGStab or devd");
+  // GMRES / BiCGStab with a deflation set (and no devd) are the augmented methods of
+  // Algorithms 4 and 5
+  const bool agmres = (P.solver == WH_GMRES || P.solver == WH_BICGSTAB) && nd > 0 && !devd;
+  const bool outer_refined = P.solver == WH_GMRES || P.solver == WH_BICGSTAB;
   const bool mixed = P.precision == WH_MIXED;
   if (mixed && P.solver == WH_FPI) WH_FAIL(ctx, WH_EUNSUPPORTED, "FPI runs in FP64 only");
   const Layout L = make_layout(*grid, P, defl);
@@ -1303,6 +1467,7 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
   // the stencil epilogues write interior nodes only: Krylov vectors keep a zero boundary
   if (P.solver == WH_GMRES)
     HIPCHK(ctx, hipMemsetAsync(at<double>(ws, L.basis), 0, 8 * (size_t)N * (std::max(1, P.restart) + 1), s));
+  if (P.solver == WH_BICGSTAB) HIPCHK(ctx, hipMemsetAsync(at<double>(ws, L.basis), 0, 8 * (size_t)N * 4, s));
   if (mixed) {
     HIPCHK(ctx, hipMemsetAsync(at<double>(ws, L.ro), 0, 8 * N, s));
     HIPCHK(ctx, hipMemsetAsync(at<double>(ws, L.d), 0, 8 * N, s));
@@ -1407,6 +1572,9 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
     } else if (P.solver == WH_GMRES) {
       WHCHK(gmres_solve(S, false, b, u, u_nonzero, r, at<double>(ws, L.basis), restart, P.tol,
                         P.max_iters, kr, agmres));
+    } else if (P.solver == WH_BICGSTAB) {
+      WHCHK(bicgstab_solve(S, false, b, u, u_nonzero, r, p, q, at<double>(ws, L.basis), P.tol,
+                           P.max_iters, kr, agmres));
     } else {
       WHCHK(cg_solve(S, false, b, u, u_nonzero, r, p, q, P.tol, P.max_iters, P.solver == WH_DCG,
                      reproject, P.check_every, kr));
@@ -1420,7 +1588,7 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
     dot(S, b, b, S_NB);
     WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
     true_rel = ctx->hbuf[S_NB] > 0 ? std::sqrt(ctx->hbuf[S_TMP] / ctx->hbuf[S_NB]) : 0.0;
-  } else if (P.solver != WH_GMRES) {
+  } else if (!outer_refined) {
     // CG / DCG with FP32 stepping and reliable updates (true FP64 residuals)
     WHCHK(cg_solve(S, true, b, u, u_nonzero, r, p, q, P.tol, P.max_iters, P.solver == WH_DCG,
                    reproject, 1, kr, false, true));
@@ -1429,7 +1597,7 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
     outer = kr.replacements;
     true_rel = kr.rel;
   } else {
-    // GMRES: FP64 outer residual, FP32 inner restarted solves
+    // GMRES / BiCGStab: FP64 outer residual, FP32 inner solves
     double* ro = at<double>(ws, L.ro);
     double* dv = at<double>(ws, L.d);
     dot(S, b, b, S_NB);
@@ -1469,6 +1637,9 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
       if (P.solver == WH_GMRES) {
         WHCHK(gmres_solve(S, inner_f32, ro, dv, false, r, at<double>(ws, L.basis), restart, t_in,
                           P.max_iters - inner_total, ir, agmres));
+      } else if (P.solver == WH_BICGSTAB) {
+        WHCHK(bicgstab_solve(S, inner_f32, ro, dv, false, r, p, q, at<double>(ws, L.basis), t_in,
+                             P.max_iters - inner_total, ir, agmres));
       } else {
         WHCHK(cg_solve(S, inner_f32, ro, dv, false, r, p, q, t_in, P.max_iters - inner_total,
                        P.solver == WH_DCG, reproject, P.check_every, ir, inner_f32));

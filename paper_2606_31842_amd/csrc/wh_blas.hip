@@ -208,6 +208,21 @@ void launch_axpy(double* y, const double* x, double a, int64_t N, hipStream_t s)
   hipLaunchKernelGGL(k_axpy, dim3(grid_for(N)), dim3(kBlock), 0, s, y, x, a, N);
 }
 
+// y = a x1 + b x2 + c x3 (element-wise; y may alias any input; a null x3 counts as 0)
+__global__ void k_lincomb3(double* y, double a, const double* x1, double b, const double* x2,
+                           double c, const double* x3, int64_t N) {
+  GRID_STRIDE(i, N) {
+    double v = a * x1[i] + b * x2[i];
+    if (x3) v += c * x3[i];
+    y[i] = v;
+  }
+}
+
+void launch_lincomb3(double* y, double a, const double* x1, double b, const double* x2, double c,
+                     const double* x3, int64_t N, hipStream_t s) {
+  hipLaunchKernelGGL(k_lincomb3, dim3(grid_for(N)), dim3(kBlock), 0, s, y, a, x1, b, x2, c, x3, N);
+}
+
 __global__ void k_scale_copy(double* y, const double* x, const double* slots, int slot, int64_t N) {
   const double inv = 1.0 / sqrt(slots[slot]);
   GRID_STRIDE(i, N) y[i] = x[i] * inv;

@@ -195,6 +195,9 @@ void launch_scale_copy(double* y, const double* x, const double* slots, int slot
                        hipStream_t s);  // y = x / sqrt(slot)
 void launch_sub(double* y, const double* a, const double* b, int64_t N, hipStream_t s);  // y=a-b
 void launch_copy(double* y, const double* x, int64_t N, hipStream_t s);
+// y = a x1 + b x2 + c x3 (y may alias an input; x3 may be NULL)
+void launch_lincomb3(double* y, double a, const double* x1, double b, const double* x2, double c,
+                     const double* x3, int64_t N, hipStream_t s);
 void launch_gemv_acc(double* x, const double* V, int64_t ldv, int k, const double* y_dev,
                      int64_t N, hipStream_t s);  // x += V[:, :k] y
 void launch_helmholtz_residual(const double* c2, const double* f, const double* u, double omega2,
