@@ -95,7 +95,7 @@ def main():
     ap.add_argument("--runs", default="", help="solvers: comma-separated subset of the run names "
                                                "(cg, dcg_nd8, dcg_nd32, dcg_nd64, devd_cg_nd32, "
                                                "devd_fpi_nd32, gmres, agmres_nd32, bicgstab, "
-                                               "abicgstab_nd32)")
+                                               "abicgstab_nd32, agmres_nd32_dense, agmres_nd32_factored)")
     ap.add_argument("--per-size", type=int, default=64, help="problems per grid size (cfg4)")
     ap.add_argument("--probe-traffic", action="store_true",
                     help="for hardware-counter runs: a plain 256 MiB device copy, then 5 wave solves "
@@ -358,6 +358,28 @@ def run_cfg5(args, np, torch, wh, wl):
             "fd_directional": fd, "adjoint_directional": an, "fd_rel_diff": abs(fd - an) / abs(an)}
 
 
+def _explicit_modes(np, torch, wh, n, omega, nd, form):
+    """The nd sine modes nearest resonance given explicitly instead of by mode numbers, each
+    degenerate pair (a, b), (b, a) rotated by 45 degrees (still eigenvectors, rank 2 on the
+    grid): as dense nodal columns, or as their separable factors."""
+    modes, lam2 = wh.select_sine_modes(2, n, omega, nd)
+    x = np.arange(n + 1) / n
+    s1 = lambda k: np.sqrt(2.0 / n) * np.sin(np.pi * k * x)
+    vecs = [np.outer(s1(b), s1(a)) for a, b in modes]          # [y][x]
+    pairs = {(int(a), int(b)): i for i, (a, b) in enumerate(modes)}
+    for (a, b), i in pairs.items():
+        j = pairs.get((b, a), -1)
+        if j > i:
+            u, v = vecs[i], vecs[j]
+            vecs[i], vecs[j] = (u + v) / np.sqrt(2.0), (u - v) / np.sqrt(2.0)
+    V = np.stack(vecs)
+    if form == "dense":
+        Vt = torch.from_numpy(V.reshape(nd, -1)).cuda()
+        return wh.Deflation(wh.WH_DEFL_DENSE_EXACT, V=Vt, lambda2=lam2)
+    fx, fy, tm, ranks = wh.compress_modes(V, tol=1e-12)
+    return wh.factored_deflation(fx, fy, tm, lam2)
+
+
 def run_solvers(args, np, torch, wh, wl):
     """The config-2 problem (2D 1024^2, omega = 100.3) by every solver of the library, true
     residual 1e-8: CG, DCG with N_D sine modes, Algorithm 2 (DEVD) around CG, GMRES(40),
@@ -369,21 +391,24 @@ def run_solvers(args, np, torch, wh, wl):
     cap = args.max_iters or 6000
     runs = [("cg", 0, {}), ("dcg", 8, {}), ("dcg", 32, {}), ("dcg", 64, {}),
             ("cg", 32, {"devd": 1}), ("fpi", 32, {"devd": 2}), ("gmres", 0, {}), ("gmres", 32, {}),
-            ("bicgstab", 0, {}), ("bicgstab", 32, {})]
+            ("bicgstab", 0, {}), ("bicgstab", 32, {}), ("gmres", 32, {"form": "dense"}),
+            ("gmres", 32, {"form": "factored"})]
     out = {"workload": "config-2 problem (2D 1024^2, c = 1, omega = 100.3) by every solver, tol 1e-8",
            "max_iters": cap}
     only = [r for r in args.runs.split(",") if r]
     for solver, nd, extra in runs:
         name = ("devd_" if extra.get("devd") else "") + solver + (f"_nd{nd}" if nd else "")
         if solver in ("gmres", "bicgstab") and nd:
-            name = f"a{solver}_nd{nd}"
+            name = f"a{solver}_nd{nd}" + (f"_{extra['form']}" if "form" in extra else "")
         if only and name not in only:
             continue
         # the fixed-point iteration runs in FP64 only
+        form = extra.pop("form", "sine") if "form" in extra else "sine"
         kw = dict(solver=solver, precision="f64" if solver == "fpi" else "mixed", tol=1e-8, max_iters=cap,
                   restart=40, **extra)
         if nd:
-            kw["defl"] = wh.sine_deflation(2, n, p.omega, nd)
+            kw["defl"] = wh.sine_deflation(2, n, p.omega, nd) if form == "sine" else \
+                _explicit_modes(np, torch, wh, n, p.omega, nd, form)
         wh.solve(f, p.omega, **{**kw, "max_iters": 2})   # autotune and warm up outside the timing
         (u, info), dt = _timed(torch, lambda: wh.solve(f, p.omega, **kw))
         out[name] = {"seconds": dt, "precision": kw["precision"], "status": info["status"], "iters": info["iters"],

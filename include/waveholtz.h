@@ -65,7 +65,11 @@ typedef enum {
   WH_DEFL_SINE = 1,        /* analytic Dirichlet modes (2/n)^{dim/2} prod sin(k pi x) (c == 1 only);
                               the eigenvalues of A on them are known in closed form      */
   WH_DEFL_DENSE_EXACT = 2, /* dense columns that are eigenvectors of L_h with given lambda2 */
-  WH_DEFL_DENSE = 3        /* any dense l2-orthonormal columns; A W costs n_d wave solves   */
+  WH_DEFL_DENSE = 3,       /* any dense l2-orthonormal columns; A W costs n_d wave solves   */
+  WH_DEFL_FACTORED = 4     /* 2D eigenvectors of L_h with given lambda2, each a sum of separable
+                              terms fy_t(y) fx_t(x) (e.g. a truncated SVD of the mode as an
+                              (n+1) x (n+1) array, the compression of Section 4.3); projected
+                              and combined from the factors without forming the vectors   */
 } wh_defl_kind;
 
 typedef struct wh_ctx wh_ctx;
@@ -116,7 +120,8 @@ typedef struct {
                                CG or GMRES: f_d = f - W W^T f, solve for f_d, then
                                u += sum_k (phi_k^T f) / (omega^2 - lambda_k^2) phi_k; 2: as 1
                                with every FPI iterate deflated (FPI only).  Exact
-                               eigenvectors only (WH_DEFL_SINE, WH_DEFL_DENSE_EXACT).  The
+                               eigenvectors only (WH_DEFL_SINE, WH_DEFL_DENSE_EXACT,
+                               WH_DEFL_FACTORED).  The
                                reported residuals are those of the deflated system.        */
   int32_t k_shape;          /* block shape of the temporally blocked kernel (2D: register rows
                                per thread and waves per block; 3D: also planes per block),
@@ -129,7 +134,13 @@ typedef struct {
   const int32_t* modes;  /* host, WH_DEFL_SINE: n_d*dim mode numbers, x first, each 1..n-1   */
   const double* V;       /* device, dense kinds: column-major nodal columns, zero boundary  */
   int64_t ldv;           /* leading dimension of V, >= (n+1)^dim                           */
-  const double* lambda2; /* host, WH_DEFL_DENSE_EXACT: lambda_h^2 with L_h v = -lambda2 v   */
+  const double* lambda2; /* host, WH_DEFL_DENSE_EXACT / FACTORED: lambda_h^2, L_h v = -lambda2 v */
+  int32_t n_terms;       /* WH_DEFL_FACTORED: separable terms T, n_d <= T <= 4096           */
+  const int32_t* term_mode; /* host, WH_DEFL_FACTORED: T mode indices, nondecreasing, every
+                              mode 0..n_d-1 present                                          */
+  const double* fx;      /* device, WH_DEFL_FACTORED: T x (n+1) x-factors, row t = term t    */
+  const double* fy;      /* device, WH_DEFL_FACTORED: T x (n+1) y-factors (singular values
+                              folded in); term t contributes fy_t(y_j) fx_t(x_i) at node (i, j) */
 } wh_deflation;
 
 typedef struct {

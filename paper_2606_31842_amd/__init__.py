@@ -17,7 +17,8 @@ import numpy as np
 
 from . import _native as nat
 from ._native import (WH_F64, WH_MIXED, WH_FPI, WH_CG, WH_DCG, WH_GMRES, WH_BICGSTAB, WH_DEFL_NONE,  # noqa: F401
-                      WH_DEFL_SINE, WH_DEFL_DENSE_EXACT, WH_DEFL_DENSE, WH_OK, WH_ENOCONV)
+                      WH_DEFL_SINE, WH_DEFL_DENSE_EXACT, WH_DEFL_DENSE, WH_DEFL_FACTORED, WH_OK,
+                      WH_ENOCONV)
 
 _SOLVERS = {"fpi": WH_FPI, "cg": WH_CG, "dcg": WH_DCG, "gmres": WH_GMRES, "bicgstab": WH_BICGSTAB}
 _PRECISIONS = {"f64": WH_F64, "mixed": WH_MIXED}
@@ -103,18 +104,25 @@ def _workspace(bytes_):
 
 @dataclass
 class Deflation:
-    """A deflation set: analytic sine modes (``modes``: (n_d, dim) ints) or dense
+    """A deflation set: analytic sine modes (``modes``: (n_d, dim) ints), dense
     eigenvector columns ``V`` ((n_d, (n+1)^dim) float64 CUDA tensor, row k = column k)
-    with their ``lambda2``."""
+    with their ``lambda2``, or 2D eigenvectors as separable terms (``fx``, ``fy``:
+    (T, n+1) float64 CUDA tensors, ``term_mode``: (T,) ints, mode k = sum over its
+    terms of fy_t(y) fx_t(x)) with their ``lambda2``."""
     kind: int
     modes: Optional[np.ndarray] = None
     V: Optional[object] = None
     lambda2: Optional[np.ndarray] = None
+    fx: Optional[object] = None
+    fy: Optional[object] = None
+    term_mode: Optional[np.ndarray] = None
 
     @property
     def n_d(self):
         if self.kind == WH_DEFL_SINE:
             return int(self.modes.shape[0])
+        if self.kind == WH_DEFL_FACTORED:
+            return int(len(self.lambda2))
         return int(self.V.shape[0])
 
     def to_c(self):
@@ -133,7 +141,45 @@ class Deflation:
             l2 = np.ascontiguousarray(self.lambda2, dtype=np.float64)
             self._keep.append(l2)
             d.lambda2 = l2.ctypes.data_as(C.POINTER(C.c_double))
+        if self.term_mode is not None:
+            tm = np.ascontiguousarray(self.term_mode, dtype=np.int32)
+            self._keep.append(tm)
+            d.n_terms = int(tm.shape[0])
+            d.term_mode = tm.ctypes.data_as(C.POINTER(C.c_int32))
+            d.fx = C.c_void_p(self.fx.data_ptr())
+            d.fy = C.c_void_p(self.fy.data_ptr())
         return d
+
+
+def compress_modes(V, tol: float = 1e-5):
+    """Host-side preparation of a factored deflation set (not part of any solve): each 2D
+    nodal mode V[k] ((n+1, n+1), y rows, x columns) is replaced by its truncated SVD,
+    keeping the singular values above tol times the largest (the compression of
+    Section 4.3).  Returns (fx, fy, term_mode, ranks) as numpy arrays: term t is
+    fy[t](y) fx[t](x) with the singular value folded into fy."""
+    V = np.asarray(V, dtype=np.float64)
+    fxs, fys, tm, ranks = [], [], [], []
+    for k in range(V.shape[0]):
+        U, sv, Vt = np.linalg.svd(V[k])
+        r = max(1, int(np.sum(sv > tol * sv[0])))
+        ranks.append(r)
+        for j in range(r):
+            fys.append(U[:, j] * sv[j])
+            fxs.append(Vt[j])
+            tm.append(k)
+    return np.array(fxs), np.array(fys), np.array(tm, dtype=np.int32), np.array(ranks)
+
+
+def factored_deflation(fx, fy, term_mode, lambda2) -> Deflation:
+    """Deflation set of 2D eigenvectors of L_h given as separable terms (see
+    compress_modes); fx, fy: (T, n+1) arrays (numpy or CUDA tensors)."""
+    torch = _torch()
+
+    def dev(a):
+        t = a if isinstance(a, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64))
+        return t.to(device="cuda", dtype=torch.float64).contiguous()
+    return Deflation(WH_DEFL_FACTORED, lambda2=np.asarray(lambda2, dtype=np.float64), fx=dev(fx), fy=dev(fy),
+                     term_mode=np.asarray(term_mode, dtype=np.int32))
 
 
 def select_sine_modes(dim: int, n: int, omega: float, n_d: int):

@@ -11,7 +11,7 @@ WH_OK, WH_ENOCONV = 0, 1
 WH_EINVAL, WH_EUNSUPPORTED, WH_EHIP, WH_EWORKSPACE, WH_EUNSTABLE, WH_EBREAKDOWN = -1, -2, -3, -4, -5, -6
 WH_F64, WH_MIXED = 0, 1
 WH_FPI, WH_CG, WH_DCG, WH_GMRES, WH_BICGSTAB = 0, 1, 2, 3, 4
-WH_DEFL_NONE, WH_DEFL_SINE, WH_DEFL_DENSE_EXACT, WH_DEFL_DENSE = 0, 1, 2, 3
+WH_DEFL_NONE, WH_DEFL_SINE, WH_DEFL_DENSE_EXACT, WH_DEFL_DENSE, WH_DEFL_FACTORED = 0, 1, 2, 3, 4
 
 
 class WhGrid(C.Structure):
@@ -33,6 +33,7 @@ class WhDeflation(C.Structure):
     _fields_ = [
         ("kind", C.c_int32), ("n_d", C.c_int32), ("modes", C.POINTER(C.c_int32)),
         ("V", C.c_void_p), ("ldv", C.c_int64), ("lambda2", C.POINTER(C.c_double)),
+        ("n_terms", C.c_int32), ("term_mode", C.POINTER(C.c_int32)), ("fx", C.c_void_p), ("fy", C.c_void_p),
     ]
 
 

@@ -116,7 +116,7 @@ struct Layout {
   size_t total = 0;
   size_t Wa = 0, Wb = 0, Wc = 0, Wd = 0, V = 0, kap64 = 0, fs64 = 0, kap32 = 0, fs32 = 0;
   size_t b = 0, r = 0, p = 0, q = 0, ro = 0, d = 0, basis = 0;
-  size_t partials = 0, partials2 = 0, slots = 0, tab = 0, modes = 0, invmu = 0, ones = 0;
+  size_t partials = 0, partials2 = 0, slots = 0, tab = 0, modes = 0, invmu = 0, ones = 0, tsum = 0;
   int64_t N = 0;
   int nslots = 0, npart = 0;
 };
@@ -133,6 +133,13 @@ int64_t nodal_count(int dim, int n) {
 }
 
 int defl_n(const wh_deflation* d) { return (d && d->kind != WH_DEFL_NONE) ? d->n_d : 0; }
+
+// rows of the projection table: modes, or the separable terms of factored modes
+int defl_rows(const wh_deflation* d) {
+  const int nd = defl_n(d);
+  if (nd && d->kind == WH_DEFL_FACTORED) return std::max(nd, std::min(d->n_terms, kMaxTerms));
+  return nd;
+}
 
 Layout make_layout(const wh_grid& g, const wh_params& P, const wh_deflation* defl) {
   Layout L;
@@ -170,7 +177,8 @@ Layout make_layout(const wh_grid& g, const wh_params& P, const wh_deflation* def
   int np = std::max(kReduceBlocks, step_partial_blocks(g.dim, g.n));
   // 2D blocked launches end with one partial per block; the smallest tile is 48 x 16
   if (g.dim == 2) np = std::max(np, ((g.n - 1 + 47) / 48) * ((g.n - 1 + 15) / 16));
-  if (nd) np = std::max(np, defl_partial_blocks(dd) * nd);
+  const int nrow = defl_rows(defl);
+  if (nd) np = std::max(np, defl_partial_blocks(dd) * nrow);
   // Gram-Schmidt partials of GMRES: [kReduceBlocks][restart + 1]
   if (P.solver == WH_GMRES) np = std::max(np, kReduceBlocks * (restart + 2));
   L.npart = np;
@@ -179,10 +187,12 @@ Layout make_layout(const wh_grid& g, const wh_params& P, const wh_deflation* def
   L.nslots = S_H + restart + 2 + 2 * nd + 2 * (restart + 2) + 16;
   L.slots = take(L, 8 * (size_t)L.nslots);
   if (nd) {
-    L.tab = take(L, 8 * (size_t)nd * g.dim * (g.n + 1));
-    L.modes = take(L, 4 * (size_t)nd * g.dim);
+    L.tab = take(L, 8 * (size_t)nrow * g.dim * (g.n + 1));
+    // sine: mode numbers; factored: term -> mode map and mode offsets
+    L.modes = take(L, 4 * (size_t)std::max(nd * g.dim, nrow + nd + 1));
     L.invmu = take(L, 8 * (size_t)nd);
     L.ones = take(L, 8 * (size_t)nd);
+    L.tsum = take(L, 8 * 2 * (size_t)nrow);   // factored: per-term sums and coefficients
   }
   return L;
 }
@@ -233,6 +243,20 @@ wh_status check_defl(wh_ctx* ctx, const wh_grid* g, const wh_deflation* d, bool 
     if (d->ldv < nodal_count(g->dim, g->n)) WH_FAIL(ctx, WH_EINVAL, "ldv too small");
   } else if (d->kind == WH_DEFL_DENSE) {
     WH_FAIL(ctx, WH_EUNSUPPORTED, "general dense deflation (A W by wave solves) is not built");
+  } else if (d->kind == WH_DEFL_FACTORED) {
+    if (g->dim != 2) WH_FAIL(ctx, WH_EUNSUPPORTED, "factored deflation vectors are 2D");
+    if (!d->fx || !d->fy || !d->lambda2 || !d->term_mode)
+      WH_FAIL(ctx, WH_EINVAL, "factored deflation needs fx, fy, term_mode and lambda2");
+    if (d->n_terms < d->n_d || d->n_terms > kMaxTerms)
+      WH_FAIL(ctx, WH_EINVAL, "n_terms must be in [n_d, %d]", kMaxTerms);
+    int prev = -1;
+    for (int t = 0; t < d->n_terms; ++t) {
+      const int k = d->term_mode[t];
+      if (k < prev || k > prev + 1 || k >= d->n_d)
+        WH_FAIL(ctx, WH_EINVAL, "term_mode must be nondecreasing and cover modes 0..n_d-1");
+      prev = k;
+    }
+    if (prev != d->n_d - 1) WH_FAIL(ctx, WH_EINVAL, "term_mode must cover modes 0..n_d-1");
   } else {
     WH_FAIL(ctx, WH_EINVAL, "bad deflation kind");
   }
@@ -612,14 +636,14 @@ wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_non
   if (nd) {
     // x_0 = x_{-1} + W (W^T A W)^{-1} W^T r_{-1}
     launch_defl_project(S.defl, r, S.partials, S.s);
-    launch_defl_reduce(S.partials, defl_partial_blocks(S.defl), nd, S.slots, S_H, S.negmu, S.s);
+    launch_defl_reduce_set(S.defl, S.partials, S.slots, S_H, S.negmu, S.s);
     launch_defl_combine(S.defl, x, 1.0, nullptr, 0.0, S.slots, S_H, N, S.s);
     // r_0 = rhs - A x_0
     applyA(S, f32_true, x, q);
     launch_sub(r, rhs, q, N, S.s);
     // mu_0 = (W^T A W)^{-1} (A W)^T r_0 = W^T r_0 for eigenvectors; p_0 = r_0 - W mu_0
     launch_defl_project(S.defl, r, S.partials, S.s);
-    launch_defl_reduce(S.partials, defl_partial_blocks(S.defl), nd, S.slots, S_H, nullptr, S.s);
+    launch_defl_reduce_set(S.defl, S.partials, S.slots, S_H, nullptr, S.s);
     launch_defl_combine(S.defl, p, 0.0, r, 1.0, S.slots, S_H, N, S.s);
   } else {
     launch_copy(p, r, N, S.s);
@@ -683,7 +707,7 @@ wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_non
     }
     if (nd && reproject) {
       launch_defl_project(S.defl, r, S.partials, S.s);
-      launch_defl_reduce(S.partials, defl_partial_blocks(S.defl), nd, S.slots, S_H, nullptr, S.s);
+      launch_defl_reduce_set(S.defl, S.partials, S.slots, S_H, nullptr, S.s);
       launch_dcg_update2(S.defl, p, r, S.slots, S_H, N, S.s);
     } else {
       launch_cg_update2(p, r, S.slots, N, S.s);
@@ -751,7 +775,7 @@ wh_status gmres_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_
     if (nd) {
       // g_W = W^T r; r <- (I - W W^T) r
       launch_defl_project(S.defl, r, S.partials, S.s);
-      launch_defl_reduce(S.partials, defl_partial_blocks(S.defl), nd, S.slots, SW, nullptr, S.s);
+      launch_defl_reduce_set(S.defl, S.partials, S.slots, SW, nullptr, S.s);
       launch_defl_combine(S.defl, r, 1.0, nullptr, 0.0, S.slots, SW, N, S.s);
     }
     dot(S, r, r, S_TMP);
@@ -779,7 +803,7 @@ wh_status gmres_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_
         if (nd) {
           // h_{W,k} = W^T w; w <- w - W h_{W,k}
           launch_defl_project(S.defl, w, S.partials, S.s);
-          launch_defl_reduce(S.partials, defl_partial_blocks(S.defl), nd, S.slots, SW, nullptr, S.s);
+          launch_defl_reduce_set(S.defl, S.partials, S.slots, SW, nullptr, S.s);
           launch_defl_combine(S.defl, w, 1.0, nullptr, 0.0, S.slots, SW, N, S.s);
         }
         // classical Gram-Schmidt applied twice (CGS2), three passes over the basis and one
@@ -901,7 +925,7 @@ wh_status bicgstab_solve(Solver& S, bool f32, const double* rhs, double* x, bool
   // e = W^T y into slots[dst]; y -= W e
   auto project_off = [&](double* y, int dst) {
     launch_defl_project(S.defl, y, S.partials, S.s);
-    launch_defl_reduce(S.partials, defl_partial_blocks(S.defl), nd, S.slots, dst, nullptr, S.s);
+    launch_defl_reduce_set(S.defl, S.partials, S.slots, dst, nullptr, S.s);
     launch_defl_combine(S.defl, y, 1.0, nullptr, 0.0, S.slots, dst, N, S.s);
   };
   int its = 0, its_at_start = -1, blowups = 0;
@@ -1050,7 +1074,7 @@ wh_status fpi_solve(Solver& S, double* x, double tol, int maxit, int check_every
     if (nd) {
       // (S.partials is free again: the update-norm partials were reduced above)
       launch_defl_project(S.defl, x, S.partials, S.s);
-      launch_defl_reduce(S.partials, defl_partial_blocks(S.defl), nd, S.slots, S_H, nullptr, S.s);
+      launch_defl_reduce_set(S.defl, S.partials, S.slots, S_H, nullptr, S.s);
       launch_defl_combine(S.defl, x, 1.0, nullptr, 0.0, S.slots, S_H, S.N, S.s);
     }
     ++k;
@@ -1501,6 +1525,31 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
       HIPCHK(ctx, hipStreamSynchronize(s));
       launch_sine_tables(at<double>(ws, L.tab), at<int32_t>(ws, L.modes), nd, grid->dim, grid->n, s);
       S.defl.tab = at<double>(ws, L.tab);
+    } else if (defl->kind == WH_DEFL_FACTORED) {
+      for (int k = 0; k < nd; ++k) lam2[k] = defl->lambda2[k];
+      // table [t][axis][i]: x-factor then y-factor of every term
+      const int T = defl->n_terms;
+      const size_t P1 = (size_t)grid->n + 1;
+      double* tab = at<double>(ws, L.tab);
+      HIPCHK(ctx, hipMemcpy2DAsync(tab, 2 * P1 * 8, defl->fx, P1 * 8, P1 * 8, T, hipMemcpyDeviceToDevice, s));
+      HIPCHK(ctx, hipMemcpy2DAsync(tab + P1, 2 * P1 * 8, defl->fy, P1 * 8, P1 * 8, T, hipMemcpyDeviceToDevice, s));
+      std::vector<int32_t> mp(T + nd + 1);
+      for (int t = 0; t < T; ++t) mp[t] = defl->term_mode[t];
+      for (int k = 0, t = 0; k <= nd; ++k) {
+        while (t < T && defl->term_mode[t] < k) ++t;
+        mp[T + k] = t;
+      }
+      HIPCHK(ctx, hipStreamSynchronize(s));
+      std::memcpy(ctx->hbuf, mp.data(), mp.size() * sizeof(int32_t));
+      int32_t* mdev = at<int32_t>(ws, L.modes);
+      HIPCHK(ctx, hipMemcpyAsync(mdev, ctx->hbuf, mp.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      HIPCHK(ctx, hipStreamSynchronize(s));
+      S.defl.tab = tab;
+      S.defl.nt = T;
+      S.defl.tmap = mdev;
+      S.defl.toff = mdev + T;
+      S.defl.tsum = at<double>(ws, L.tsum);
+      S.defl.tcoef = at<double>(ws, L.tsum) + T;
     } else {
       for (int k = 0; k < nd; ++k) lam2[k] = defl->lambda2[k];
       S.defl.V = defl->V;
@@ -1531,10 +1580,9 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
         sc[k] = -1.0 / den;
       }
       WHCHK(upload(ctx, at<double>(ws, L.invmu), sc.data(), nd));
-      const int pb = defl_partial_blocks(S.defl);
       launch_defl_project(S.defl, f, S.partials, s);
-      launch_defl_reduce(S.partials, pb, nd, S.slots, S_H, nullptr, s);
-      launch_defl_reduce(S.partials, pb, nd, at<double>(ws, L.ones), 0, at<double>(ws, L.invmu), s);
+      launch_defl_reduce_set(S.defl, S.partials, S.slots, S_H, nullptr, s);
+      launch_defl_reduce_set(S.defl, S.partials, at<double>(ws, L.ones), 0, at<double>(ws, L.invmu), s);
       launch_defl_combine(S.defl, r, 0.0, f, 1.0, S.slots, S_H, N, s);
       const double h = 1.0 / grid->n;
       const double dt2 = tp.dt * tp.dt;

@@ -459,7 +459,7 @@ static dim3 sine_grid(const Defl& d) {
 }
 
 int defl_partial_blocks(const Defl& d) {
-  if (d.kind == WH_DEFL_SINE) {
+  if (d.kind == WH_DEFL_SINE || d.kind == WH_DEFL_FACTORED) {
     dim3 g = sine_grid(d);
     return (int)(g.x * g.y);
   }
@@ -467,8 +467,10 @@ int defl_partial_blocks(const Defl& d) {
 }
 
 void launch_defl_project(const Defl& d, const double* r, double* partials, hipStream_t s) {
-  if (d.kind == WH_DEFL_SINE) {
-    hipLaunchKernelGGL(k_sine_project, sine_grid(d), dim3(256), 0, s, d.tab, d.nd, d.dim, d.n, r,
+  if (d.kind == WH_DEFL_SINE || d.kind == WH_DEFL_FACTORED) {
+    // factored modes: the same tiled kernel over the separable terms
+    const int nk = d.kind == WH_DEFL_FACTORED ? d.nt : d.nd;
+    hipLaunchKernelGGL(k_sine_project, sine_grid(d), dim3(256), 0, s, d.tab, nk, d.dim, d.n, r,
                        partials);
   } else {
     int64_t P = d.n + 1, N = d.dim == 2 ? P * P : P * P * P;
@@ -491,20 +493,49 @@ void launch_defl_reduce(const double* partials, int count, int nd, double* slots
                      scale_dev);
 }
 
-// y = alpha*y + beta*r - sum_k c_k W_k ; alpha taken from slots[aslot] if aslot >= 0.
+// factored modes: slots[dst + k] = sum of the projections of mode k's terms (* scale[k]),
+// in term order
+__global__ void k_terms_to_modes(const double* tsum, const int* toff, int nd, double* slots, int dst,
+                                 const double* scale) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nd) return;
+  double acc = 0.0;
+  for (int t = toff[k]; t < toff[k + 1]; ++t) acc += tsum[t];
+  slots[dst + k] = scale ? acc * scale[k] : acc;
+}
+
+// factored modes: per-term coefficients tcoef[t] = coef[tmap[t]]
+__global__ void k_modes_to_terms(const double* coef, const int* tmap, int nt, double* tcoef) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nt) tcoef[t] = coef[tmap[t]];
+}
+
+void launch_defl_reduce_set(const Defl& d, const double* partials, double* slots, int dst,
+                            const double* scale_dev, hipStream_t s) {
+  if (d.kind == WH_DEFL_FACTORED) {
+    hipLaunchKernelGGL(k_defl_reduce, dim3(d.nt), dim3(256), 0, s, partials, defl_partial_blocks(d), d.nt,
+                       d.tsum, 0, (const double*)nullptr);
+    hipLaunchKernelGGL(k_terms_to_modes, dim3((d.nd + 255) / 256), dim3(256), 0, s, (const double*)d.tsum,
+                       d.toff, d.nd, slots, dst, scale_dev);
+  } else {
+    launch_defl_reduce(partials, defl_partial_blocks(d), d.nd, slots, dst, scale_dev, s);
+  }
+}
+
+// y = alpha*y + beta*r - sum_k c_k W_k ; alpha taken from *aptr if aptr is set.
 // Same tiling as the projection: per chunk of 32 modes the row factors times c_k are staged
 // in LDS and the column factors loaded at once.
 __global__ __launch_bounds__(256) void k_sine_combine(const double* tab, int nd, int dim, int n,
-                                                      double* y, double alpha, int aslot,
+                                                      double* y, double alpha, const double* aptr,
                                                       const double* r, double beta,
-                                                      const double* slots, int src) {
+                                                      const double* coef) {
   const int P = n + 1;
   const int rows = dim == 2 ? P : P * P;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int i = blockIdx.x * kSineCols + lane;
   const int rb = blockIdx.y * kSineRows;
   const bool col_ok = i < P;
-  const double al = aslot >= 0 ? slots[aslot] : alpha;
+  const double al = aptr ? *aptr : alpha;
   double sum[kSineRowsPerWave];
 #pragma unroll
   for (int t = 0; t < kSineRowsPerWave; ++t) sum[t] = 0.0;
@@ -515,7 +546,7 @@ __global__ __launch_bounds__(256) void k_sine_combine(const double* tab, int nd,
       const int row = min(rb + t, rows - 1);
       double fv = 0.0;
       if (k < nd) {
-        fv = slots[src + k] * tab[(int64_t)(k * dim + 1) * P + row % P];
+        fv = coef[k] * tab[(int64_t)(k * dim + 1) * P + row % P];
         if (dim == 3) fv *= tab[(int64_t)(k * dim + 2) * P + row / P];
       }
       fy[c][t] = fv;
@@ -662,10 +693,16 @@ void launch_gs_update(const double* V, int64_t N, int nv, const double* slots, i
 
 static void combine_impl(const Defl& d, double* y, double alpha, int aslot, const double* r,
                          double beta, const double* slots, int src, int64_t N, hipStream_t s) {
-  if (d.kind == WH_DEFL_SINE)
+  const double* aptr = aslot >= 0 ? slots + aslot : nullptr;
+  if (d.kind == WH_DEFL_SINE) {
     hipLaunchKernelGGL(k_sine_combine, sine_grid(d), dim3(256), 0, s, d.tab, d.nd, d.dim, d.n, y,
-                       alpha, aslot, r, beta, slots, src);
-  else
+                       alpha, aptr, r, beta, slots + src);
+  } else if (d.kind == WH_DEFL_FACTORED) {
+    hipLaunchKernelGGL(k_modes_to_terms, dim3((d.nt + 255) / 256), dim3(256), 0, s, slots + src, d.tmap,
+                       d.nt, d.tcoef);
+    hipLaunchKernelGGL(k_sine_combine, sine_grid(d), dim3(256), 0, s, d.tab, d.nt, d.dim, d.n, y,
+                       alpha, aptr, r, beta, (const double*)d.tcoef);
+  } else
     hipLaunchKernelGGL(k_dense_combine, dim3(grid_for(N)), dim3(256), 0, s, d.V, d.ldv, d.nd, N, y,
                        alpha, aslot, r, beta, slots, src);
 }

@@ -49,6 +49,7 @@ enum Slot : int {
 };
 
 constexpr int kBlock = 256;          // threads per block for 1D kernels
+constexpr int kMaxTerms = 4096;       // separable terms of a factored deflation set
 constexpr int kReduceBlocks = 1024;  // partial-sum slots for grid-stride 1D reductions
 
 // ----------------------------------------------------------------- stencil launch
@@ -221,15 +222,24 @@ struct Defl {
   int nd = 0;
   int dim = 2;
   int n = 0;
-  const double* tab = nullptr;  // sine: nd x dim x (n+1) table, [k][axis][i]
+  const double* tab = nullptr;  // sine: nd x dim x (n+1) table, [k][axis][i]; factored: nt x 2 x (n+1)
   const double* V = nullptr;    // dense
   int64_t ldv = 0;
+  // factored (2D): nt separable terms, mode k owning terms toff[k] .. toff[k+1]-1
+  int nt = 0;
+  const int* tmap = nullptr;    // mode of each term
+  const int* toff = nullptr;    // nd + 1 offsets
+  double* tsum = nullptr;       // nt scratch: per-term projections
+  double* tcoef = nullptr;      // nt scratch: per-term combination coefficients
 };
 int defl_partial_blocks(const Defl& d);
 void launch_defl_project(const Defl& d, const double* r, double* partials, hipStream_t s);
 // reduce nd columns of partials (count rows) into slots[dst + k]; scale by scale_dev[k] if set
 void launch_defl_reduce(const double* partials, int count, int nd, double* slots, int dst,
                         const double* scale_dev, hipStream_t s);
+// the partials of launch_defl_project for this set -> slots[dst + k] = (W^T r)_k (* scale_dev[k])
+void launch_defl_reduce_set(const Defl& d, const double* partials, double* slots, int dst,
+                            const double* scale_dev, hipStream_t s);
 // y = alpha*y + beta*r - sum_k slots[src+k] W_k     (r may be null)
 void launch_defl_combine(const Defl& d, double* y, double alpha, const double* r, double beta,
                          const double* slots, int src, int64_t N, hipStream_t s);

@@ -33,3 +33,31 @@ def test_ndsweep_problem_shape_and_source():
     j, i = np.unravel_index(np.argmax(q.f), q.f.shape)
     assert abs(i / q.n - 0.3) <= 1.0 / q.n and abs(j / q.n - 0.4) <= 1.0 / q.n
     assert q.f.max() <= 144.0 + 1e-9 and q.f.max() > 0.9 * 144.0
+
+
+def test_compress_modes_round_trip():
+    """The SVD compression of 2D nodal modes: exact rank for separable and rotated
+    degenerate sine modes, reconstruction within the cut-off otherwise."""
+    import paper_2606_31842_amd as wh
+    from oracle import modes
+    n = 24
+    a, b = modes.mode_nodal(2, n, (2, 5)), modes.mode_nodal(2, n, (5, 2))
+    th = 0.3
+    rot = np.cos(th) * a + np.sin(th) * b                     # same eigenvalue, rank 2
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal((n + 1, n + 1))
+    g[0] = g[-1] = 0
+    g[:, 0] = g[:, -1] = 0
+    V = np.stack([a, rot, g])
+    fx, fy, tm, ranks = wh.compress_modes(V, tol=1e-12)
+    assert list(ranks[:2]) == [1, 2] and ranks[2] == n - 1
+    assert list(tm) == [0] + [1] * 2 + [2] * int(ranks[2])
+    for k in range(3):
+        rec = sum(np.outer(fy[t], fx[t]) for t in range(len(tm)) if tm[t] == k)
+        assert np.abs(rec - V[k]).max() < 1e-12 * np.abs(V[k]).max() * n
+    # a loose cut-off keeps the leading singular values only; the error is bounded by them
+    fx, fy, tm, ranks = wh.compress_modes(V[2:], tol=0.3)
+    s = np.linalg.svd(g, compute_uv=False)
+    rec = sum(np.outer(fy[t], fx[t]) for t in range(len(tm)))
+    assert ranks[0] == int(np.sum(s > 0.3 * s[0]))
+    assert abs(np.linalg.norm(rec - g, 2) - s[ranks[0]]) < 1e-10 * s[0]
