@@ -22,21 +22,25 @@ from __future__ import annotations
 import numpy as np
 
 
-def eig1d(n: int) -> np.ndarray:
-    """lam2 of the 1D operator for k = 1..n-1 (index k-1)."""
+def eig1d(n: int, order: int = 2) -> np.ndarray:
+    """lam2 of the 1D operator for k = 1..n-1 (index k-1); order 4: the fourth-order
+    difference with odd reflection at the ends (the sine vectors are its eigenvectors)."""
     h = 1.0 / n
     k = np.arange(1, n)
+    if order == 4:
+        t = k * np.pi * h
+        return (30.0 - 32.0 * np.cos(t) + 2.0 * np.cos(2.0 * t)) / (12.0 * h * h)
     return (4.0 / h ** 2) * np.sin(k * np.pi * h / 2.0) ** 2
 
 
-def mode_lam2(dim: int, n: int, idx) -> float:
-    e = eig1d(n)
+def mode_lam2(dim: int, n: int, idx, order: int = 2) -> float:
+    e = eig1d(n, order)
     return float(sum(e[k - 1] for k in idx))
 
 
-def select_modes(dim: int, n: int, omega: float, n_defl: int):
+def select_modes(dim: int, n: int, omega: float, n_defl: int, order: int = 2):
     """The n_defl mode index tuples (x index first) nearest to resonance."""
-    e = eig1d(n)
+    e = eig1d(n, order)
     ks = np.arange(1, n)
     if dim == 2:
         P, Q = np.meshgrid(ks, ks, indexing="ij")
