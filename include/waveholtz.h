@@ -18,9 +18,13 @@
  * Conventions shared by every entry point
  * ---------------------------------------
  * Grid.    Unit box [0,1]^dim, dim in {2,3}, n cells per side, h = 1/n, nodes
- *          x_j = j h, j = 0..n (eq. discreteHelmholtz).  Second-order differences
- *          only (order == 2):  (L_h W)_p = h^-2 sum_faces c2_f (W_q - W_p),
- *          c2_f = (c2_p + c2_q)/2.
+ *          x_j = j h, j = 0..n (eq. discreteHelmholtz).  order == 2:
+ *          (L_h W)_p = h^-2 sum_faces c2_f (W_q - W_p), c2_f = (c2_p + c2_q)/2.
+ *          order == 4 (c == 1 only; the paper's spatial order): per axis
+ *          h^-2 (-W_{i-2} + 16 W_{i-1} - 30 W_i + 16 W_{i+1} - W_{i+2}) / 12, the
+ *          boundary closed by odd reflection (W_{-1} = -W_1, W_{n+1} = -W_{n-1});
+ *          single-step kernels only, stability c dt / h < sqrt(3 / (4 dim)), no
+ *          batched or adjoint solves.
  * Layout.  Every grid function is a nodal array of (n+1)^dim doubles, C order with
  *          x fastest (index (k*(n+1) + j)*(n+1) + i).  Boundary entries of inputs
  *          v, f, u are ignored (read as 0); boundary entries of outputs are written 0.
@@ -77,7 +81,7 @@ typedef struct wh_ctx wh_ctx;
 typedef struct {
   int32_t dim;    /* 2 or 3 */
   int32_t n;      /* cells per side, n >= 4 */
-  int32_t order;  /* spatial order; only 2 */
+  int32_t order;  /* spatial order: 2, or 4 (c == 1) */
 } wh_grid;
 
 typedef struct {
@@ -194,11 +198,11 @@ wh_status wh_time_params(const wh_grid* grid, const wh_params* params, double c_
  * lambda2 and beta are host arrays of length count. */
 wh_status wh_transfer(const wh_grid* grid, const wh_params* params, double c_max,
                       int32_t count, const double* lambda2, double* beta);
-/* The n_d analytic Dirichlet modes whose discrete eigenvalue lambda2 is nearest to
- * omega^2 (Section 2.3: deflate the eigenvectors with eigenvalues closest to omega),
- * ties broken lexicographically by the mode numbers.  modes: host n_d*dim ints,
- * lambda2: host n_d doubles (may be NULL). */
-wh_status wh_select_sine_modes(int32_t dim, int32_t n, double omega, int32_t n_d,
+/* The n_d analytic Dirichlet modes whose discrete eigenvalue lambda2 (of the operator
+ * of this order, 2 or 4) is nearest to omega^2 (Section 2.3: deflate the eigenvectors
+ * with eigenvalues closest to omega), ties broken lexicographically by the mode
+ * numbers.  modes: host n_d*dim ints, lambda2: host n_d doubles (may be NULL). */
+wh_status wh_select_sine_modes(int32_t dim, int32_t n, int32_t order, double omega, int32_t n_d,
                                int32_t* modes, double* lambda2);
 
 /* ------------------------------------------------------------------ workspace */

@@ -75,8 +75,8 @@ def params(omega: float, **kw) -> nat.WhParams:
     return p
 
 
-def _grid(dim, n):
-    return nat.WhGrid(dim, n, 2)
+def _grid(dim, n, order=2):
+    return nat.WhGrid(dim, n, int(order))
 
 
 def _ptr(t):
@@ -182,27 +182,29 @@ def factored_deflation(fx, fy, term_mode, lambda2) -> Deflation:
                      term_mode=np.asarray(term_mode, dtype=np.int32))
 
 
-def select_sine_modes(dim: int, n: int, omega: float, n_d: int):
-    """(modes (n_d, dim) int32, lambda2 (n_d,)) nearest to resonance."""
+def select_sine_modes(dim: int, n: int, omega: float, n_d: int, order: int = 2):
+    """(modes (n_d, dim) int32, lambda2 (n_d,)) nearest to resonance for the operator of
+    this order (2, or 4)."""
     lib = nat.load()
     modes = np.zeros((n_d, dim), dtype=np.int32)
     lam2 = np.zeros(n_d)
-    st = lib.wh_select_sine_modes(dim, n, float(omega), n_d, modes.ctypes.data_as(C.POINTER(C.c_int32)),
+    st = lib.wh_select_sine_modes(dim, n, int(order), float(omega), n_d, modes.ctypes.data_as(C.POINTER(C.c_int32)),
                                   lam2.ctypes.data_as(C.POINTER(C.c_double)))
     if st != 0:
         raise WaveHoltzError(st, "wh_select_sine_modes")
     return modes, lam2
 
 
-def sine_deflation(dim, n, omega, n_d) -> Deflation:
-    modes, lam2 = select_sine_modes(dim, n, omega, n_d)
+def sine_deflation(dim, n, omega, n_d, order: int = 2) -> Deflation:
+    modes, lam2 = select_sine_modes(dim, n, omega, n_d, order)
     return Deflation(WH_DEFL_SINE, modes=modes, lambda2=None)
 
 
 def time_params(dim, n, omega, c_max=1.0, **kw):
     lib = nat.load()
+    order = kw.pop("order", 2)
     p = params(omega, **kw)
-    g = _grid(dim, n)
+    g = _grid(dim, n, order)
     m, nt = C.c_int32(), C.c_int32()
     dt, om = C.c_double(), C.c_double()
     st = lib.wh_time_params(C.byref(g), C.byref(p), float(c_max), C.byref(m), C.byref(nt), C.byref(dt),
@@ -214,8 +216,9 @@ def time_params(dim, n, omega, c_max=1.0, **kw):
 
 def transfer(dim, n, omega, lambda2, c_max=1.0, **kw):
     lib = nat.load()
+    order = kw.pop("order", 2)
     p = params(omega, **kw)
-    g = _grid(dim, n)
+    g = _grid(dim, n, order)
     lam = np.ascontiguousarray(lambda2, dtype=np.float64).ravel()
     out = np.zeros_like(lam)
     st = lib.wh_transfer(C.byref(g), C.byref(p), float(c_max), lam.size,
@@ -225,9 +228,9 @@ def transfer(dim, n, omega, lambda2, c_max=1.0, **kw):
     return out
 
 
-def workspace_bytes(dim, n, p: nat.WhParams, defl: Optional[Deflation] = None) -> int:
+def workspace_bytes(dim, n, p: nat.WhParams, defl: Optional[Deflation] = None, order: int = 2) -> int:
     lib = nat.load()
-    g = _grid(dim, n)
+    g = _grid(dim, n, order)
     d = defl.to_c() if defl is not None else None
     return int(lib.wh_workspace_bytes(C.byref(g), C.byref(p), C.byref(d) if d is not None else None))
 
@@ -240,8 +243,9 @@ def apply_filter(v, omega, f=None, c2=None, out=None, **kw):
     _nodal(v, dim, n, "v"); _nodal(f, dim, n, "f"); _nodal(c2, dim, n, "c2")
     lib = nat.load()
     ctx = context(v.device.index)
+    order = kw.pop("order", 2)
     p = params(omega, **kw)
-    g = _grid(dim, n)
+    g = _grid(dim, n, order)
     out = torch.empty_like(v) if out is None else _nodal(out, dim, n, "out")
     ws = _workspace(lib.wh_workspace_bytes(C.byref(g), C.byref(p), None))
     info = nat.WhInfo()
@@ -259,8 +263,9 @@ def solve(f, omega, c2=None, u0=None, defl: Optional[Deflation] = None, workspac
     _nodal(f, dim, n, "f"); _nodal(c2, dim, n, "c2")
     lib = nat.load()
     ctx = context(f.device.index)
+    order = kw.pop("order", 2)
     p = params(omega, **kw)
-    g = _grid(dim, n)
+    g = _grid(dim, n, order)
     d = defl.to_c() if defl is not None else None
     need = lib.wh_workspace_bytes(C.byref(g), C.byref(p), C.byref(d) if d is not None else None)
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need)
@@ -272,13 +277,13 @@ def solve(f, omega, c2=None, u0=None, defl: Optional[Deflation] = None, workspac
     return u, info.as_dict()
 
 
-def helmholtz_residual(u, f, omega, c2=None):
+def helmholtz_residual(u, f, omega, c2=None, order=2):
     torch = _torch()
     dim = u.dim()
     n = u.shape[0] - 1
     lib = nat.load()
     ctx = context(u.device.index)
-    g = _grid(dim, n)
+    g = _grid(dim, n, order)
     ws = _workspace(16 * 1024 + 4096)
     rel = C.c_double()
     st = lib.wh_helmholtz_residual(ctx, C.byref(g), _ptr(c2), _ptr(f), float(omega), _ptr(u), _ptr(ws),
@@ -295,8 +300,9 @@ def time_step_kernel(v, omega, c2=None, reps=50, shape=False, **kw):
     n = v.shape[0] - 1
     lib = nat.load()
     ctx = context(v.device.index)
+    order = kw.pop("order", 2)
     p = params(omega, **kw)
-    g = _grid(dim, n)
+    g = _grid(dim, n, order)
     ws = _workspace(lib.wh_workspace_bytes(C.byref(g), C.byref(p), None))
     us = C.c_double()
     k, rows, waves = C.c_int32(), C.c_int32(), C.c_int32()

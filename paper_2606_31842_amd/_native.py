@@ -67,7 +67,7 @@ _SIGS = {
                                  P(C.c_double), P(C.c_double)]),
     "wh_transfer": (C.c_int, [P(WhGrid), P(WhParams), C.c_double, C.c_int32, P(C.c_double),
                               P(C.c_double)]),
-    "wh_select_sine_modes": (C.c_int, [C.c_int32, C.c_int32, C.c_double, C.c_int32, P(C.c_int32),
+    "wh_select_sine_modes": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_int32, P(C.c_int32),
                                        P(C.c_double)]),
     "wh_workspace_bytes": (C.c_size_t, [P(WhGrid), P(WhParams), P(WhDeflation)]),
     "wh_apply_filter": (C.c_int, [C.c_void_p, P(WhGrid), C.c_void_p, C.c_void_p, C.c_void_p,

@@ -53,8 +53,26 @@ namespace wh {
 // frequency omega_tilde = (2 pi/m)/dt with dt = 2 sin(pi/m)/omega (so that the
 // leapfrog dispersion relation maps omega_tilde to omega), trapezoid weights
 // w_n = (2/Tbar) eta_n dt (cos(omega_tilde t^n) - 1/4).
+// Leapfrog stability: dt^2 max eig(-L_h) < 4.  Second order: max eig = 4 dim / h^2, so
+// c dt / h < 1/sqrt(dim); fourth order: 16 dim / (3 h^2), so c dt / h < sqrt(3 / (4 dim)).
+// 1D Dirichlet eigenvalue lambda_k^2 of the second- or fourth-order difference (the sine
+// vectors are eigenvectors of both; the fourth-order boundary is closed by odd reflection)
+double lam2_1d(int k, int n, int order) {
+  const double h = 1.0 / n;
+  if (order == 4) {
+    const double t = M_PI * k * h;
+    return (30.0 - 32.0 * std::cos(t) + 2.0 * std::cos(2.0 * t)) / (12.0 * h * h);
+  }
+  const double sv = std::sin(M_PI * k * h / 2.0);
+  return 4.0 / (h * h) * sv * sv;
+}
+
+double cfl_limit(int dim, int order) {
+  return order == 4 ? std::sqrt(3.0 / (4.0 * dim)) : 1.0 / std::sqrt((double)dim);
+}
+
 wh_status make_time_params(wh_ctx* ctx, int dim, int n, const wh_params& P, double c_max,
-                           TimeParams& tp) {
+                           TimeParams& tp, int order) {
   const double h = 1.0 / n;
   if (!(c_max > 0) || !std::isfinite(c_max)) WH_FAIL(ctx, WH_EINVAL, "c_max must be > 0");
   int m = P.steps_per_period;
@@ -73,7 +91,7 @@ wh_status make_time_params(wh_ctx* ctx, int dim, int n, const wh_params& P, doub
     omw = P.omega;
   }
   const double cfl_eff = c_max * dt / h;
-  if (cfl_eff >= 1.0 / std::sqrt((double)dim))
+  if (cfl_eff >= cfl_limit(dim, order))
     WH_FAIL(ctx, WH_EINVAL, "time step violates the leapfrog stability bound (c dt/h = %g)", cfl_eff);
   tp.m = m;
   tp.nt = P.n_periods * m;
@@ -177,6 +195,7 @@ Layout make_layout(const wh_grid& g, const wh_params& P, const wh_deflation* def
   int np = std::max(kReduceBlocks, step_partial_blocks(g.dim, g.n));
   // 2D blocked launches end with one partial per block; the smallest tile is 48 x 16
   if (g.dim == 2) np = std::max(np, ((g.n - 1 + 47) / 48) * ((g.n - 1 + 15) / 16));
+  if (g.order == 4) np = std::max(np, step4_blocks(g.dim, g.n));
   const int nrow = defl_rows(defl);
   if (nd) np = std::max(np, defl_partial_blocks(dd) * nrow);
   // Gram-Schmidt partials of GMRES: [kReduceBlocks][restart + 1]
@@ -206,7 +225,7 @@ T* at(void* ws, size_t off) {
 wh_status check_grid(wh_ctx* ctx, const wh_grid* g) {
   if (!g) WH_FAIL(ctx, WH_EINVAL, "grid is NULL");
   if (g->dim != 2 && g->dim != 3) WH_FAIL(ctx, WH_EUNSUPPORTED, "dim must be 2 or 3");
-  if (g->order != 2) WH_FAIL(ctx, WH_EUNSUPPORTED, "only second-order differences are built");
+  if (g->order != 2 && g->order != 4) WH_FAIL(ctx, WH_EUNSUPPORTED, "order must be 2 or 4");
   if (g->n < 4) WH_FAIL(ctx, WH_EINVAL, "n must be >= 4");
   if (g->dim == 2 && g->n > 46340) WH_FAIL(ctx, WH_EINVAL, "n too large");
   if (g->dim == 3 && g->n > 1290) WH_FAIL(ctx, WH_EINVAL, "n too large");
@@ -217,8 +236,8 @@ wh_status check_params(wh_ctx* ctx, const wh_grid* g, const wh_params* P) {
   if (!P) WH_FAIL(ctx, WH_EINVAL, "params is NULL");
   if (!(P->omega > 0) || !std::isfinite(P->omega)) WH_FAIL(ctx, WH_EINVAL, "omega must be > 0");
   if (P->n_periods < 1) WH_FAIL(ctx, WH_EINVAL, "n_periods must be >= 1");
-  if (P->steps_per_period == 0 && !(P->cfl > 0 && P->cfl < 1.0 / std::sqrt((double)g->dim)))
-    WH_FAIL(ctx, WH_EINVAL, "cfl must lie in (0, 1/sqrt(dim))");
+  if (P->steps_per_period == 0 && !(P->cfl > 0 && P->cfl <= cfl_limit(g->dim, g->order)))
+    WH_FAIL(ctx, WH_EINVAL, "cfl must lie in (0, %g] for this dim and order", cfl_limit(g->dim, g->order));
   if (P->steps_per_period < 0 || (P->steps_per_period > 0 && P->steps_per_period < 3))
     WH_FAIL(ctx, WH_EINVAL, "steps_per_period must be 0 or >= 3");
   if (P->precision != WH_F64 && P->precision != WH_MIXED) WH_FAIL(ctx, WH_EINVAL, "bad precision");
@@ -306,6 +325,7 @@ struct WaveOp {
   double* partials = nullptr;
   int k_fuse = 1;
   int k_shape = 0;   // block shape of the temporally blocked kernel
+  int order = 2;     // 4: the fourth-order single-step kernel (c == 1)
 };
 
 // The temporally blocked kernels: 2D (register tiles) and 3D (z-marching pipeline).
@@ -362,10 +382,16 @@ std::vector<int> plan_launches(int nt, int K, bool f32) {
   return parts;
 }
 
+// one single-step launch of the operator's order
+int step_any(const WaveOp& op, bool force, StepMode mode, const StepArgs& a, hipStream_t s) {
+  if (op.order == 4) return launch_step4(op.dim, op.f32, force, mode, a, s);
+  return launch_step(op.dim, op.f32, op.varc, force, mode, a, s);
+}
+
 int wave_solve(const WaveOp& op, const double* vin, bool force, StepMode last, const double* x,
                double* out, hipStream_t s) {
   const TimeParams& tp = *op.tp;
-  if (op.dim == 2 && op.k_fuse > 1 && fused2d_supported(op.f32, op.k_fuse)) {
+  if (op.order == 2 && op.dim == 2 && op.k_fuse > 1 && fused2d_supported(op.f32, op.k_fuse)) {
     // 2D: every step in blocked launches; the first starts from vin with the half step,
     // the last ends in the epilogue (no streaming kernels)
     const std::vector<int> parts = plan_launches(tp.nt, op.k_fuse, op.f32);
@@ -421,14 +447,14 @@ int wave_solve(const WaveOp& op, const double* vin, bool force, StepMode last, c
   a.cosn = tp.cosv[0];
   a.zb0 = op.Wc;
   a.zb1 = op.Wd;
-  launch_step(op.dim, op.f32, op.varc, force, M_FIRST, a, s);
+  step_any(op, force, M_FIRST, a, s);
   a.zb0 = a.zb1 = nullptr;
   void* cur = op.Wb;
   void* prev = op.Wa;
   void* oc = op.Wc;
   void* op_ = op.Wd;
   int nn = 1;  // cur holds W^nn
-  const int K = op.k_fuse;
+  const int K = op.order == 2 ? op.k_fuse : 1;
   if (K > 1 && fused_supported(op.dim, op.f32, K)) {
     FusedArgs fa{};
     fa.V = op.V;
@@ -468,7 +494,7 @@ int wave_solve(const WaveOp& op, const double* vin, bool force, StepMode last, c
     a.out = out;
     a.partials = op.partials;
     const StepMode md = (k == tp.nt - 1) ? last : M_MID;
-    nblk = launch_step(op.dim, op.f32, op.varc, force, md, a, s);
+    nblk = step_any(op, force, md, a, s);
     if (op.f32) std::swap(cur, oc);
     else std::swap(cur, prev);
   }
@@ -1125,7 +1151,9 @@ wh_status setup_ops(wh_ctx* ctx, const wh_grid& g, const wh_params& P, const dou
       c_max = 1.0;
     }
   }
-  WHCHK(make_time_params(ctx, g.dim, g.n, P, c_max, tp));
+  if (g.order == 4 && varc)
+    WH_FAIL(ctx, WH_EUNSUPPORTED, "fourth-order differences are built for c == 1 (c2 == NULL)");
+  WHCHK(make_time_params(ctx, g.dim, g.n, P, c_max, tp, g.order));
   const double h = 1.0 / g.n;
   const double dt2 = tp.dt * tp.dt;
   const double ks = dt2 / (2.0 * h * h);
@@ -1149,6 +1177,7 @@ wh_status setup_ops(wh_ctx* ctx, const wh_grid& g, const wh_params& P, const dou
   base.Wc = at<void>(ws, L.Wc);
   base.Wd = at<void>(ws, L.Wd);
   base.k_fuse = 1;
+  base.order = g.order;
   base.V = at<double>(ws, L.V);
   base.a = dt2 / (h * h);
   base.tp = &tp;
@@ -1162,7 +1191,7 @@ wh_status setup_ops(wh_ctx* ctx, const wh_grid& g, const wh_params& P, const dou
   S.om2dt2 = 4.0 * std::sin(0.5 * tp.omega_w * tp.dt) * std::sin(0.5 * tp.omega_w * tp.dt);
   // defect form by default for CG/GMRES; DCG has removed the near-resonant modes, where
   // the defect form gains, so it steps W directly (one stencil pass less per iteration)
-  S.defect = P.mixed_form == 0 || (P.mixed_form < 0 && P.solver != WH_DCG);
+  S.defect = (P.mixed_form == 0 || (P.mixed_form < 0 && P.solver != WH_DCG)) && g.order == 2;
   // exact deflation removes the near-resonant modes whose FP32 error would slow CG, so
   // DCG can go longer between FP64 residual replacements
   S.reliable_drop = (P.inner_tol > 0 && P.inner_tol < 1) ? P.inner_tol : (P.solver == WH_DCG ? 1e-3 : 0.1);
@@ -1176,7 +1205,7 @@ wh_status setup_ops(wh_ctx* ctx, const wh_grid& g, const wh_params& P, const dou
   // operator without forcing dominates every solve, so it sets K for both precisions.
   auto pick = [&](WaveOp& op) {
     int code = 1;
-    if (P.k_fuse == 1 || (P.k_fuse > 1 && !fused_supported(g.dim, op.f32, P.k_fuse))) code = 1;
+    if (g.order == 4 || P.k_fuse == 1 || (P.k_fuse > 1 && !fused_supported(g.dim, op.f32, P.k_fuse))) code = 1;
     else if (P.k_fuse > 1 && P.k_shape >= 0) code = P.k_fuse | (P.k_shape << 8);
     else code = autotune_k(ctx, op, false, P.k_fuse);
     op.k_fuse = code & 0xff;
@@ -1294,7 +1323,7 @@ wh_status wh_time_params(const wh_grid* grid, const wh_params* params, double c_
   WHCHK(check_grid(nullptr, grid));
   WHCHK(check_params(nullptr, grid, params));
   TimeParams tp;
-  WHCHK(make_time_params(nullptr, grid->dim, grid->n, *params, c_max > 0 ? c_max : 1.0, tp));
+  WHCHK(make_time_params(nullptr, grid->dim, grid->n, *params, c_max > 0 ? c_max : 1.0, tp, grid->order));
   if (m) *m = tp.m;
   if (nt) *nt = tp.nt;
   if (dt) *dt = tp.dt;
@@ -1308,23 +1337,20 @@ wh_status wh_transfer(const wh_grid* grid, const wh_params* params, double c_max
   WHCHK(check_params(nullptr, grid, params));
   if (count < 0 || (count > 0 && (!lambda2 || !beta))) return WH_EINVAL;
   TimeParams tp;
-  WHCHK(make_time_params(nullptr, grid->dim, grid->n, *params, c_max > 0 ? c_max : 1.0, tp));
+  WHCHK(make_time_params(nullptr, grid->dim, grid->n, *params, c_max > 0 ? c_max : 1.0, tp, grid->order));
   for (int i = 0; i < count; ++i) beta[i] = transfer(tp, lambda2[i]);
   return WH_OK;
 }
 
-wh_status wh_select_sine_modes(int32_t dim, int32_t n, double omega, int32_t n_d, int32_t* modes,
-                               double* lambda2) {
-  if ((dim != 2 && dim != 3) || n < 4 || n_d < 0 || !(omega > 0) || (n_d > 0 && !modes))
+wh_status wh_select_sine_modes(int32_t dim, int32_t n, int32_t order, double omega, int32_t n_d,
+                               int32_t* modes, double* lambda2) {
+  if ((dim != 2 && dim != 3) || n < 4 || n_d < 0 || !(omega > 0) || (n_d > 0 && !modes) ||
+      (order != 2 && order != 4))
     return WH_EINVAL;
-  const double h = 1.0 / n;
   const int K = n - 1;
   if ((int64_t)K * K * (dim == 3 ? K : 1) < n_d) return WH_EINVAL;
-  std::vector<double> e(n);   // e[k] = lambda_k^2 of the 1D Dirichlet Laplacian, increasing in k
-  for (int k = 1; k < n; ++k) {
-    const double sv = std::sin(M_PI * k * h / 2.0);
-    e[k] = 4.0 / (h * h) * sv * sv;
-  }
+  std::vector<double> e(n);   // e[k] = lambda_k^2 of the 1D Dirichlet operator, increasing in k
+  for (int k = 1; k < n; ++k) e[k] = lam2_1d(k, n, order);
   const double om2 = omega * omega;
   // The n_d modes with the smallest |lambda^2 - omega^2|, the distance taken on a grid of
   // 1e-9 omega^2 so that modes whose lambda^2 agree up to rounding (degenerate sets
@@ -1510,10 +1536,7 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
       const double h = 1.0 / grid->n;
       for (int k = 0; k < nd; ++k) {
         double l2 = 0;
-        for (int a = 0; a < grid->dim; ++a) {
-          const double sv = std::sin(M_PI * defl->modes[k * grid->dim + a] * h / 2.0);
-          l2 += 4.0 / (h * h) * sv * sv;
-        }
+        for (int a = 0; a < grid->dim; ++a) l2 += lam2_1d(defl->modes[k * grid->dim + a], grid->n, grid->order);
         lam2[k] = l2;
       }
       // mode numbers to the device (through the pinned block as doubles -> ints)
@@ -1740,7 +1763,10 @@ wh_status wh_helmholtz_residual(wh_ctx* ctx, const wh_grid* grid, const double* 
   double* pf = pr + kReduceBlocks;
   double* out = at<double>(ws, 16 * (size_t)kReduceBlocks);
   const double ih2 = (double)grid->n * grid->n;
-  launch_helmholtz_residual(c2, f, u, omega * omega, ih2, grid->n, grid->dim, pr, pf, ctx->stream);
+  if (grid->order == 4 && c2)
+    WH_FAIL(ctx, WH_EUNSUPPORTED, "fourth-order differences are built for c == 1 (c2 == NULL)");
+  launch_helmholtz_residual(c2, f, u, omega * omega, ih2, grid->n, grid->dim, grid->order, pr, pf,
+                            ctx->stream);
   launch_reduce(pr, kReduceBlocks, out, 0, 0, ctx->stream);
   launch_reduce(pf, kReduceBlocks, out, 1, 0, ctx->stream);
   HIPCHK(ctx, hipGetLastError());
@@ -1781,7 +1807,7 @@ wh_status wh_time_step_kernel(wh_ctx* ctx, const wh_grid* grid, const double* c2
       a.V = op.V;
       a.cosn = tp.cosv[1];
       a.wn = tp.w[2];
-      launch_step(op.dim, op.f32, op.varc, false, M_MID, a, s);
+      step_any(op, false, M_MID, a, s);
     } else {
       FusedArgs fa{};
       fa.V = op.V;
@@ -1954,7 +1980,8 @@ wh_status adjoint_validate(wh_ctx* ctx, const wh_grid* grid, const double* c2, c
                            int ckpt) {
   WHCHK(check_grid(ctx, grid));
   WHCHK(check_params(ctx, grid, P));
-  if (grid->dim != 2) WH_FAIL(ctx, WH_EUNSUPPORTED, "the adjoint gradient is built for 2D grids");
+  if (grid->dim != 2 || grid->order != 2)
+    WH_FAIL(ctx, WH_EUNSUPPORTED, "the adjoint gradient is built for 2D second-order grids");
   if (!c2) WH_FAIL(ctx, WH_EINVAL, "c2 is required (the gradient is taken with respect to it)");
   if (ckpt < 0 || ckpt == 1 || ckpt > 4096)
     WH_FAIL(ctx, WH_EINVAL, "ckpt_every must be 0 (default 16) or in [2, 4096]");
@@ -1986,7 +2013,7 @@ wh_status adjoint_nt(wh_ctx* ctx, const wh_grid& G, const double* c2, const wh_p
 extern "C" {
 
 size_t wh_workspace_bytes_adjoint(const wh_grid* grid, const wh_params* params, int32_t ckpt_every) {
-  if (!grid || !params || check_grid(nullptr, grid) != WH_OK || grid->dim != 2) return 0;
+  if (!grid || !params || check_grid(nullptr, grid) != WH_OK || grid->dim != 2 || grid->order != 2) return 0;
   if (!(params->c_max > 0)) return 0;
   TimeParams tp;
   if (make_time_params(nullptr, 2, grid->n, *params, params->c_max, tp) != WH_OK) return 0;

@@ -774,7 +774,7 @@ wh_status deflated_start(wh_ctx* ctx, const wh_problem& pr, const TimeParams& tp
   double* coef = (double*)take(8 * (size_t)nd * 2);
   std::vector<int32_t> modes(2 * (size_t)nd);
   std::vector<double> lam2(nd);
-  if (wh_select_sine_modes(2, n, pr.omega, nd, modes.data(), lam2.data()) != WH_OK)
+  if (wh_select_sine_modes(2, n, 2, pr.omega, nd, modes.data(), lam2.data()) != WH_OK)
     WHB_FAIL(ctx, WH_EINVAL, "sine mode selection failed (n = %d, n_defl = %d)", n, nd);
   // the frequency whose Helmholtz problem the fixed point solves: (2/dt) sin(omega_w dt / 2)
   const double sh = std::sin(0.5 * tp.omega_w * tp.dt);

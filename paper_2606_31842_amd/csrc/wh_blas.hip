@@ -265,8 +265,17 @@ void launch_gemv_acc(double* x, const double* V, int64_t ldv, int k, const doubl
 }
 
 // ----------------------------------------------------------------- Helmholtz residual
+// value at axis offset d of node coordinate c for the fourth-order residual (odd reflection)
+__device__ __forceinline__ double res_nb4(const double* u, int64_t p, int c, int d, int n, int64_t st) {
+  const int q = c + d;
+  if (q >= 1 && q <= n - 1) return u[p + d * st];
+  if (q == -1) return -u[p + (d + 2) * st];
+  if (q == n + 1) return -u[p + (d - 2) * st];
+  return 0.0;
+}
+
 __global__ void k_helm_res(const double* c2, const double* f, const double* u, double om2,
-                           double ih2, int n, int dim, double* pr, double* pf) {
+                           double ih2, int n, int dim, int order, double* pr, double* pf) {
   const int64_t P = n + 1;
   const int64_t N = dim == 2 ? P * P : P * P * P;
   double ar = 0.0, af = 0.0;
@@ -279,9 +288,17 @@ __global__ void k_helm_res(const double* c2, const double* f, const double* u, d
     int64_t nb[6] = {p - 1, p + 1, p - P, p + P, p - P * P, p + P * P};
     bool ins[6] = {i > 1, i < n - 1, j > 1, j < n - 1, k > 1, k < n - 1};
     double lap = 0.0;
-    for (int t = 0; t < 2 * dim; ++t) {
-      double cf = c2 ? 0.5 * (c2[p] + c2[nb[t]]) : 1.0;
-      lap += cf * (U(nb[t], ins[t]) - uc);
+    if (order == 4) {   // c == 1
+      const int crd[3] = {i, j, k};
+      int64_t st = 1;
+      for (int ax = 0; ax < dim; ++ax, st *= P)
+        lap += (16.0 * (res_nb4(u, p, crd[ax], -1, n, st) + res_nb4(u, p, crd[ax], 1, n, st)) -
+                (res_nb4(u, p, crd[ax], -2, n, st) + res_nb4(u, p, crd[ax], 2, n, st)) - 30.0 * uc) / 12.0;
+    } else {
+      for (int t = 0; t < 2 * dim; ++t) {
+        double cf = c2 ? 0.5 * (c2[p] + c2[nb[t]]) : 1.0;
+        lap += cf * (U(nb[t], ins[t]) - uc);
+      }
     }
     double r = f[p] - (lap * ih2 + om2 * uc);
     ar += r * r;
@@ -298,9 +315,10 @@ __global__ void k_helm_res(const double* c2, const double* f, const double* u, d
 int helmholtz_partial_blocks(int, int) { return kReduceBlocks; }
 
 void launch_helmholtz_residual(const double* c2, const double* f, const double* u, double om2,
-                               double ih2, int n, int dim, double* pr, double* pf, hipStream_t s) {
+                               double ih2, int n, int dim, int order, double* pr, double* pf,
+                               hipStream_t s) {
   hipLaunchKernelGGL(k_helm_res, dim3(kReduceBlocks), dim3(kBlock), 0, s, c2, f, u, om2, ih2, n, dim,
-                     pr, pf);
+                     order, pr, pf);
 }
 
 // ----------------------------------------------------------------- deflation

@@ -31,7 +31,7 @@ struct TimeParams {
   std::vector<double> w, cosv;
 };
 wh_status make_time_params(wh_ctx* ctx, int dim, int n, const wh_params& P, double c_max,
-                           TimeParams& tp);
+                           TimeParams& tp, int order = 2);
 double transfer(const TimeParams& tp, double lam2);
 
 // ----------------------------------------------------------------- device scalars
@@ -90,6 +90,10 @@ struct StepArgs {
 
 // Launch one time step of a d-dimensional wave solve. T: float or double.
 // Returns the number of blocks that wrote partial sums.
+// Fourth-order (c == 1) single step, every mode; one block per 256 nodes.  Returns the
+// number of blocks (= partial sums of the epilogue reductions).
+int launch_step4(int dim, bool f32, bool force, StepMode mode, const StepArgs& a, hipStream_t s);
+int step4_blocks(int dim, int n);
 int launch_step(int dim, bool f32, bool varc, bool force, StepMode mode, const StepArgs& a,
                 hipStream_t s);
 int step_partial_blocks(int dim, int n);
@@ -202,8 +206,8 @@ void launch_lincomb3(double* y, double a, const double* x1, double b, const doub
 void launch_gemv_acc(double* x, const double* V, int64_t ldv, int k, const double* y_dev,
                      int64_t N, hipStream_t s);  // x += V[:, :k] y
 void launch_helmholtz_residual(const double* c2, const double* f, const double* u, double omega2,
-                               double inv_h2, int n, int dim, double* partials_r,
-                               double* partials_f, hipStream_t s);
+                               double ih2, int n, int dim, int order, double* pr, double* pf,
+                               hipStream_t s);
 int helmholtz_partial_blocks(int n, int dim);
 
 // ----------------------------------------------------------------- adjoint (2D)

@@ -279,6 +279,131 @@ __global__ __launch_bounds__(256) void k_first(StepArgs a) {
   }
 }
 
+// --------------------------------------------------------------------- fourth order
+// c == 1: per axis h^-2 (-W_{i-2} + 16 W_{i-1} - 30 W_i + 16 W_{i+1} - W_{i+2}) / 12, the
+// Dirichlet boundary closed by odd reflection (W_{-1} = -W_1, W_{n+1} = -W_{n-1}), which
+// keeps the operator symmetric with the sine vectors as eigenvectors.  One thread per node;
+// the scheme, the state pairs (increment form in FP32) and the epilogues are those of the
+// second-order kernels, M_FIRST included.
+
+// value at axis offset d (|d| <= 2) of the node at axis coordinate c (1 <= c <= n-1)
+template <typename S>
+__device__ __forceinline__ double nb4(const S* u, int64_t p, int c, int d, int n, int64_t st) {
+  const int q = c + d;
+  if (q >= 1 && q <= n - 1) return (double)u[p + d * st];
+  if (q == -1) return -(double)u[p + (d + 2) * st];      // reflected node 1
+  if (q == n + 1) return -(double)u[p + (d - 2) * st];   // reflected node n-1
+  return 0.0;                                            // boundary node
+}
+
+// sum over axes of (-W_{-2} + 16 W_{-1} + 16 W_{+1} - W_{+2}) - 30 dim W, as differences to
+// the centre (c0 = W at the node)
+template <int DIM, typename S, typename T>
+__device__ __forceinline__ T lap4_sum(const S* u, int64_t p, const int* crd, int n, int64_t P, T c0) {
+  T sum = T(0);
+  int64_t st = 1;
+#pragma unroll
+  for (int ax = 0; ax < DIM; ++ax) {
+    const T m2 = (T)nb4(u, p, crd[ax], -2, n, st), m1 = (T)nb4(u, p, crd[ax], -1, n, st);
+    const T p1 = (T)nb4(u, p, crd[ax], 1, n, st), p2 = (T)nb4(u, p, crd[ax], 2, n, st);
+    sum += (T(16) * ((m1 - c0) + (p1 - c0))) - ((m2 - c0) + (p2 - c0));
+    st *= P;
+  }
+  return sum;
+}
+
+template <typename T, int DIM, int MODE, bool FORCE>
+__global__ __launch_bounds__(256) void k_step4(StepArgs a) {
+  constexpr bool INC = sizeof(T) == 4;
+  const int n = a.n;
+  const int64_t P = (int64_t)n + 1;
+  const int64_t N = DIM == 2 ? P * P : P * P * P;
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const T A12 = (T)(a.a / 12.0);
+  double acc = 0.0;
+  if (p < N) {
+    const int crd[3] = {(int)(p % P), (int)((p / P) % P), DIM == 3 ? (int)(p / (P * P)) : 1};
+    const bool interior = crd[0] > 0 && crd[0] < n && crd[1] > 0 && crd[1] < n &&
+                          (DIM == 2 || (crd[2] > 0 && crd[2] < n));
+    if (MODE == M_FIRST) {
+      T* __restrict__ w0o = (T*)a.prev;
+      T* __restrict__ w1o = (T*)a.cur_out;
+      if (!interior) {
+        w0o[p] = T(0);
+        w1o[p] = T(0);
+        if (a.zb0) ((T*)a.zb0)[p] = T(0);
+        if (a.zb1) ((T*)a.zb1)[p] = T(0);
+        a.V[p] = 0.0;
+      } else {
+        const double v0 = a.vin ? a.vin[p] : 0.0;
+        const T c = (T)v0;
+        T lap = a.vin ? A12 * lap4_sum<DIM>(a.vin, p, crd, n, P, c) : T(0);
+        if (FORCE) lap -= (T)a.cosn * ((const T*)a.fs)[p];
+        const T d = T(0.5) * lap;
+        const T w1 = c + d;
+        w0o[p] = INC ? d : c;
+        w1o[p] = w1;
+        a.V[p] = a.w0 * v0 + a.wn * (double)w1;
+      }
+    } else if (interior) {
+      const T* __restrict__ cur = (const T*)a.cur;
+      T* __restrict__ prev = (T*)a.prev;
+      const T c = cur[p];
+      T lap = A12 * lap4_sum<DIM>(cur, p, crd, n, P, c);
+      if (FORCE) lap -= (T)a.cosn * ((const T*)a.fs)[p];
+      if (INC) {
+        const T dnew = prev[p] + lap;
+        const T nw = c + dnew;
+        if (MODE == M_MID) {
+          prev[p] = dnew;
+          ((T*)a.cur_next)[p] = nw;
+          a.V[p] += a.wn * (double)nw;
+        } else {
+          step_epilogue<T, MODE>(a, (size_t)p, nw, prev, acc);
+        }
+      } else {
+        const T nw = (c + c) - prev[p] + lap;
+        step_epilogue<T, MODE>(a, (size_t)p, nw, prev, acc);
+      }
+    }
+  }
+  if (MODE == M_LAST_AQ || MODE == M_LAST_FPI || MODE == M_LAST_EQ) {
+    const double sm = block_sum256(acc, threadIdx.x);
+    if (threadIdx.x == 0) a.partials[blockIdx.x] = sm;
+  }
+}
+
+template <typename T, int DIM, bool FORCE>
+static void step4_mode(StepMode mode, dim3 g, const StepArgs& a, hipStream_t s) {
+  switch (mode) {
+    case M_FIRST: hipLaunchKernelGGL((k_step4<T, DIM, M_FIRST, FORCE>), g, dim3(256), 0, s, a); break;
+    case M_MID: hipLaunchKernelGGL((k_step4<T, DIM, M_MID, FORCE>), g, dim3(256), 0, s, a); break;
+    case M_LAST_V: hipLaunchKernelGGL((k_step4<T, DIM, M_LAST_V, FORCE>), g, dim3(256), 0, s, a); break;
+    case M_LAST_AQ: hipLaunchKernelGGL((k_step4<T, DIM, M_LAST_AQ, FORCE>), g, dim3(256), 0, s, a); break;
+    case M_LAST_FPI: hipLaunchKernelGGL((k_step4<T, DIM, M_LAST_FPI, FORCE>), g, dim3(256), 0, s, a); break;
+    case M_LAST_EQ: hipLaunchKernelGGL((k_step4<T, DIM, M_LAST_EQ, FORCE>), g, dim3(256), 0, s, a); break;
+    default: break;
+  }
+}
+
+int step4_blocks(int dim, int n) {
+  const int64_t P = (int64_t)n + 1;
+  return (int)(((dim == 2 ? P * P : P * P * P) + 255) / 256);
+}
+
+int launch_step4(int dim, bool f32, bool force, StepMode mode, const StepArgs& a, hipStream_t s) {
+  const int nb = step4_blocks(dim, a.n);
+  const dim3 g((unsigned)nb);
+  if (f32) {
+    if (dim == 2) force ? step4_mode<float, 2, true>(mode, g, a, s) : step4_mode<float, 2, false>(mode, g, a, s);
+    else force ? step4_mode<float, 3, true>(mode, g, a, s) : step4_mode<float, 3, false>(mode, g, a, s);
+  } else {
+    if (dim == 2) force ? step4_mode<double, 2, true>(mode, g, a, s) : step4_mode<double, 2, false>(mode, g, a, s);
+    else force ? step4_mode<double, 3, true>(mode, g, a, s) : step4_mode<double, 3, false>(mode, g, a, s);
+  }
+  return nb;
+}
+
 // --------------------------------------------------------------------- dispatch
 template <typename T, bool VARC, bool FORCE>
 static void dispatch_dim(int dim, StepMode mode, const StepArgs& a, hipStream_t s) {

@@ -86,11 +86,12 @@ def test_mode_selection_sweep_matches_oracle():
         n = int(rng.integers(5, 24 if dim == 2 else 10))
         lam_max = dim * 4.0 * n * n
         cases.append((dim, n, float(np.sqrt(rng.uniform(0, lam_max))), int(rng.integers(1, min(60, (n - 1) ** dim) + 1))))
-    for dim, n, omega, nd in cases:
-        got, lam2 = wh.select_sine_modes(dim, n, omega, nd)
-        ref, ref_l2 = modes.select_modes(dim, n, omega, nd)
-        assert [tuple(r) for r in got.tolist()] == ref, (dim, n, omega, nd)
-        assert np.allclose(lam2, ref_l2, rtol=1e-13)
+    for order in (2, 4):
+        for dim, n, omega, nd in cases:
+            got, lam2 = wh.select_sine_modes(dim, n, omega, nd, order=order)
+            ref, ref_l2 = modes.select_modes(dim, n, omega, nd, order=order)
+            assert [tuple(r) for r in got.tolist()] == ref, (order, dim, n, omega, nd)
+            assert np.allclose(lam2, ref_l2, rtol=1e-13)
 
 
 def test_invalid_arguments_rejected_on_host():
@@ -106,11 +107,21 @@ def test_invalid_arguments_rejected_on_host():
     p.cfl = 0.5
     g4 = nat.WhGrid(4, 64, 2)
     assert lib.wh_time_params(C.byref(g4), C.byref(p), 1.0, C.byref(m), None, None, None) == nat.WH_EUNSUPPORTED
-    go = nat.WhGrid(2, 64, 4)
+    go = nat.WhGrid(2, 64, 6)
     assert lib.wh_time_params(C.byref(go), C.byref(p), 1.0, C.byref(m), None, None, None) == nat.WH_EUNSUPPORTED
+    # fourth order: the stricter stability bound sqrt(3 / (4 dim)) = 0.612 in 2D, 0.5 in 3D
+    g42, g43 = nat.WhGrid(2, 64, 4), nat.WhGrid(3, 32, 4)
+    assert lib.wh_time_params(C.byref(g42), C.byref(p), 1.0, C.byref(m), None, None, None) == nat.WH_OK
+    p.cfl = 0.65
+    assert lib.wh_time_params(C.byref(g42), C.byref(p), 1.0, C.byref(m), None, None, None) == nat.WH_EINVAL
+    assert lib.wh_time_params(C.byref(g), C.byref(p), 1.0, C.byref(m), None, None, None) == nat.WH_OK
+    p.cfl = 0.51
+    assert lib.wh_time_params(C.byref(g43), C.byref(p), 1.0, C.byref(m), None, None, None) == nat.WH_EINVAL
+    p.cfl = 0.5
     p.omega = -1.0
     assert lib.wh_time_params(C.byref(g), C.byref(p), 1.0, C.byref(m), None, None, None) == nat.WH_EINVAL
-    assert lib.wh_select_sine_modes(4, 10, 1.0, 1, None, None) == nat.WH_EINVAL
+    assert lib.wh_select_sine_modes(4, 10, 2, 1.0, 1, None, None) == nat.WH_EINVAL
+    assert lib.wh_select_sine_modes(2, 10, 3, 1.0, 1, None, None) == nat.WH_EINVAL
     # a NULL context is rejected before any device call
     assert lib.wh_solve(None, C.byref(g), None, None, None, C.byref(p), None, None, 0, None) == nat.WH_EINVAL
     # workspace size grows with deflation and GMRES restart

@@ -1,0 +1,105 @@
+"""GPU parity of the fourth-order operator (c = 1, odd reflection at the Dirichlet
+boundary) against the oracle: the filter element-wise, the sine-mode eigen-relation,
+solves against the direct fourth-order solution, and the order of accuracy."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import discretization as disc, modes, krylov, wavesolve as ws, transfer as tr
+from _gpu import cuda, host, rel, oracle_tp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dim,n,omega,force", [(2, 37, 11.3, True), (2, 130, 31.7, False), (3, 21, 9.7, True)])
+def test_filter_order4_matches_oracle(dim, n, omega, force):
+    print(f"case order4 filter dim={dim} n={n}", flush=True)
+    import paper_2606_31842_amd as wh
+    v = wl.random_nodal(dim, n, seed=40 + n)
+    f = wl.gaussian(dim, n, (0.4, 0.6, 0.5)[:dim], 0.15) if force else None
+    L = disc.laplacian(dim, n, order=4)
+    tp = oracle_tp(dim, n, omega)
+    ref = disc.to_nodal(ws.wave_filter(L, disc.to_interior(v), None if f is None else disc.to_interior(f), tp),
+                        dim, n)
+    out, info = wh.apply_filter(cuda(v), omega, f=None if f is None else cuda(f), order=4)
+    assert info["nt"] == tp.nt and info["k_fuse"] == 1
+    e = rel(host(out), ref)
+    out32, _ = wh.apply_filter(cuda(v), omega, f=None if f is None else cuda(f), order=4, precision="mixed")
+    e32 = rel(host(out32), ref)
+    print(f"f64 err {e:.2e} mixed err {e32:.2e}", flush=True)
+    assert e < 1e-12 and e32 < 2e-5
+    assert np.all(host(out)[0] == 0)
+
+
+@pytest.mark.parametrize("dim,n,omega", [(2, 96, 23.4), (3, 20, 11.1)])
+def test_order4_sine_modes_are_eigenvectors_of_the_filter(dim, n, omega):
+    import paper_2606_31842_amd as wh
+    tp = oracle_tp(dim, n, omega)
+    for idx in [(1, 2, 3)[:dim], (n - 1, 5, 2)[:dim], (7, 7, 7)[:dim]]:
+        phi = modes.mode_nodal(dim, n, idx)
+        out, _ = wh.apply_filter(cuda(phi), omega, order=4)
+        beta = tr.beta_discrete(modes.mode_lam2(dim, n, idx, order=4), tp)
+        assert np.abs(host(out) - beta * phi).max() < 1e-13
+
+
+@pytest.mark.parametrize("solver,precision", [("cg", "f64"), ("dcg", "f64"), ("dcg", "mixed"), ("gmres", "f64"),
+                                              ("bicgstab", "mixed")])
+def test_order4_solves_match_direct(solver, precision):
+    print(f"case order4 {solver} {precision}", flush=True)
+    import paper_2606_31842_amd as wh
+    n = 64
+    e = modes.eig1d(n, order=4)
+    omega = float(np.sqrt(e[6] + e[7]) * 1.0015)
+    f = wl.gaussian(2, n, (0.41, 0.57), 0.08)
+    kw = dict(solver=solver, tol=1e-10 if precision == "f64" else 1e-9, max_iters=6000, order=4,
+              precision=precision, restart=30)
+    if solver in ("dcg", "gmres", "bicgstab"):
+        kw["defl"] = wh.sine_deflation(2, n, omega, 8, order=4)
+    u, info = wh.solve(cuda(f), omega, **kw)
+    assert info["status"] == 0, info
+    U = disc.direct_solve_dst(2, n, omega, f, order=4)
+    err = rel(host(u), U)
+    print(f"err {err:.2e} iters {info['iters']}", flush=True)
+    assert err < (1e-8 if precision == "f64" else 2e-5)
+    assert wh.helmholtz_residual(u, cuda(f), omega, order=4) < 1e-6
+    if solver == "dcg" and precision == "f64":
+        L = disc.laplacian(2, n, order=4)
+        tp = oracle_tp(2, n, omega)
+        sel, lam2 = modes.select_modes(2, n, omega, 8, order=4)
+        W = modes.mode_matrix(2, n, sel)
+        b = ws.rhs(L, disc.to_interior(f), tp)
+        _, oi = krylov.dcg(lambda v: ws.apply_A(L, v, tp), b, W, W * tr.mu_discrete(lam2, tp), tol=1e-10,
+                           reproject=False)
+        assert abs(info["iters"] - oi["iters"]) <= 2
+
+
+def test_order4_is_fourth_order_accurate():
+    """Helmholtz with the exact solution u = sin(pi x) sin(2 pi y): the GPU solutions on
+    grids 32 and 64 converge at rate 4 with order 4 (rate 2 with order 2)."""
+    import paper_2606_31842_amd as wh
+    omega = 5.3
+    errs = {2: [], 4: []}
+    for n in (32, 64):
+        x = np.arange(n + 1) / n
+        X, Y = np.meshgrid(x, x, indexing="xy")
+        uex = np.sin(np.pi * X) * np.sin(2 * np.pi * Y)
+        f = (omega ** 2 - 5 * np.pi ** 2) * uex
+        for order in (2, 4):
+            u, info = wh.solve(cuda(f), omega, solver="cg", tol=1e-12, max_iters=5000, order=order)
+            assert info["status"] == 0
+            errs[order].append(np.abs(host(u) - uex).max())
+    r2, r4 = errs[2][0] / errs[2][1], errs[4][0] / errs[4][1]
+    print(f"order 2 errors {errs[2]} rate {np.log2(r2):.2f}; order 4 errors {errs[4]} rate {np.log2(r4):.2f}",
+          flush=True)
+    assert 3.7 < r2 < 4.3 and 14 < r4 < 18
+
+
+def test_order4_rejections():
+    import paper_2606_31842_amd as wh
+    n = 24
+    f = cuda(wl.gaussian(2, n, (0.4, 0.6), 0.1))
+    c2 = cuda(np.ones((n + 1, n + 1)) * 1.1)
+    with pytest.raises(wh.WaveHoltzError):
+        wh.solve(f, 7.7, c2=c2, order=4)                         # fourth order is built for c == 1
+    with pytest.raises(wh.WaveHoltzError):
+        wh.apply_filter(f, 7.7, order=4, cfl=0.7)               # beyond sqrt(3/8)
