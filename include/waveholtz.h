@@ -107,7 +107,7 @@ typedef struct {
                                relative tolerance of each FP32 inner restart cycle (0: 1e-3);
                                CG/DCG, the residual reduction after which the recursive
                                residual is replaced by the true one (0: 0.1 for CG, 1e-3
-                               for DCG and deflated batch problems)                         */
+                               for DCG, 1e-4 for deflated batch problems)                   */
   int32_t max_outer;        /* WH_MIXED GMRES: FP64 refinement sweeps (default 30)           */
   int32_t k_fuse;           /* time steps per stencil launch; 0: library choice             */
   int32_t reproject;        /* DCG A-orthogonalisation against W each iteration (Algorithm 3,
