@@ -322,8 +322,11 @@ def run_cfg4(args, np, torch, wh, wl):
                 kw["n_defl"] = nds
             (us, infos), dt = _timed(torch, lambda: wh.solve_batched([(f, q.omega) for f, q in zip(fs, probs)], **kw))
             errs = residuals(us)
+            # wave-step throughput of the whole batch: every wave solve (FP32 and FP64) x N_t x points
+            psteps = sum((i["wave_solves"] + i["wave_solves_f32"]) * i["nt"] * (q.n - 1) ** 2
+                         for i, q in zip(infos, probs))
             out[f"batched_{solver}_{prec}"] = {
-                "seconds": dt, "iters": int(sum(i["iters"] for i in infos)),
+                "seconds": dt, "wave_gpts": psteps / dt / 1e9, "iters": int(sum(i["iters"] for i in infos)),
                 "fp64_residual_solves": int(sum(i["outer"] for i in infos)),
                 "max_true_rel_res": max(i["true_rel_res"] for i in infos),
                 "status_counts": {str(k): sum(1 for i in infos if i["status"] == k)
