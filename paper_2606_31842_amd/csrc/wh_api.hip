@@ -985,7 +985,7 @@ wh_status bicgstab_solve(Solver& S, bool f32, const double* rhs, double* x, bool
     if (its == its_at_start) WH_FAIL(ctx, WH_EBREAKDOWN, "BiCGStab breakdown at iteration %d", its);
     its_at_start = its;
     double rho_old = 1.0, alpha = 1.0, om = 1.0;
-    bool first = true, converged = false, blew_up = false;
+    bool first = true, blew_up = false;
     while (its < maxit) {
       if (rho == 0.0) break;   // breakdown of the shadow residual: restart
       if (first) {
@@ -1013,7 +1013,6 @@ wh_status bicgstab_solve(Solver& S, bool f32, const double* rhs, double* x, bool
         for (int i = 0; i < nd; ++i) xi[i] += alpha * e1[i];
         ++its;
         rel = std::sqrt(ctx->hbuf[S_TMP2]) / nb;
-        converged = true;
         break;
       }
       applyA(S, f32, sv, tv);
@@ -1035,10 +1034,7 @@ wh_status bicgstab_solve(Solver& S, bool f32, const double* rhs, double* x, bool
       rel = std::sqrt(ctx->hbuf[S_R2]) / nb;
       rho = ctx->hbuf[S_TMP];
       if (!std::isfinite(rel)) WH_FAIL(ctx, WH_EUNSTABLE, "non-finite residual in BiCGStab");
-      if (rel <= tol) {
-        converged = true;
-        break;
-      }
+      if (rel <= tol) break;
       if (rel < best) {
         best = rel;
         launch_copy(xb, x, N, S.s);
@@ -1069,7 +1065,6 @@ wh_status bicgstab_solve(Solver& S, bool f32, const double* rhs, double* x, bool
       xib_live = false;
     }
     nonzero = true;
-    (void)converged;
     // the next pass through the loop head forms the true residual b - A x and stops there
     // if it meets tol or the iterations are spent; a pass that made no step is a breakdown
   }
@@ -1533,7 +1528,6 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
     S.defl.n = grid->n;
     std::vector<double> lam2(nd);
     if (defl->kind == WH_DEFL_SINE) {
-      const double h = 1.0 / grid->n;
       for (int k = 0; k < nd; ++k) {
         double l2 = 0;
         for (int a = 0; a < grid->dim; ++a) l2 += lam2_1d(defl->modes[k * grid->dim + a], grid->n, grid->order);

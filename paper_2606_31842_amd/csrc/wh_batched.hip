@@ -635,12 +635,6 @@ struct BatchLayout {
   int ntiles = 0;
 };
 
-static size_t take_b(BatchLayout& L, size_t bytes) {
-  size_t o = L.total;
-  L.total += (bytes + 255) & ~(size_t)255;
-  return o;
-}
-
 // per problem: 4 state arrays + V, b, r, p, q (8N each), FP32 states (4 x 4N, mixed), kap64/fs64 (8N),
 // kap32/fs32 (4N, mixed), partials (tiles), weights 2(N_t+1)
 static size_t problem_bytes(int n, int nt, int K, bool mixed, bool varc) {
