@@ -1620,16 +1620,26 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
     wave_solve(ob, q, true, M_LAST_V, nullptr, nullptr, s);
     S.ws64++;
   }
-  // is the initial guess nonzero?
+  // is the initial guess nonzero?  Is b zero (then so is the solution: A is nonsingular,
+  // and no relative stopping test is defined)?
   dot(S, u, u, S_TMP2);
+  dot(S, b, b, S_NB);
   WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
-  const bool u_nonzero = ctx->hbuf[S_TMP2] > 0;
+  const bool b_zero = !(ctx->hbuf[S_NB] > 0);
+  if (b_zero) HIPCHK(ctx, hipMemsetAsync(u, 0, 8 * N, s));
+  const bool u_nonzero = !b_zero && ctx->hbuf[S_TMP2] > 0;
   wh_status st = WH_OK;
   KrylovResult kr;
   int outer = 0;
   double true_rel = -1.0;
   const int restart = std::max(1, P.restart);
-  if (!mixed) {
+  if (b_zero) {
+    // u = 0 is the solution (set above); no iteration
+    kr = KrylovResult{};
+    st = WH_OK;
+    S.iters = 0;
+    true_rel = 0.0;
+  } else if (!mixed) {
     if (P.solver == WH_FPI) {
       // FPI: x <- Pi x with the forcing on; ||b||^2 for the relative update
       dot(S, b, b, S_NB);
