@@ -481,6 +481,15 @@ __global__ __launch_bounds__(256) void k_batch_control(const BDesc* __restrict__
       break;
     case BP_INIT: {
       // r_0 = b (no start vector) or b - A x_0 (deflated start), both exact in FP64
+      if (!(S.nb2 > 0)) {
+        // b = 0: the solution is 0, and x is 0 here (no start, or the start from a zero f)
+        S.r2 = 0.0;
+        S.rel = 0.0;
+        S.prev_rel = 0.0;
+        S.status = WH_OK;
+        S.phase = BP_DONE;
+        break;
+      }
       const double rel = sqrt(sum / S.nb2);
       S.r2 = sum;
       S.rel = rel;

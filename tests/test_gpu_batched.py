@@ -112,6 +112,24 @@ def test_batched_dcg_start_is_solution():
     assert rel(host(us[0]), U) < 1e-10
 
 
+@pytest.mark.parametrize("solver,precision", [("cg", "f64"), ("cg", "mixed"), ("dcg", "mixed")])
+def test_batched_zero_forcing_problem(solver, precision):
+    """A problem with f = 0 inside a batch finishes at once with u = 0; the others solve."""
+    import paper_2606_31842_amd as wh
+    n1, n2, om = 48, 64, 17.3
+    f1 = np.zeros((n1 + 1, n1 + 1))
+    f2 = wl.gaussian(2, n2, (0.41, 0.57), 0.08)
+    kw = dict(solver=solver, tol=1e-9, precision=precision, max_iters=5000)
+    if solver == "dcg":
+        kw["n_defl"] = [4, 4]
+    us, infos = wh.solve_batched([(cuda(f1), om), (cuda(f2), om)], **kw)
+    assert infos[0]["status"] == 0 and infos[0]["iters"] == 0
+    assert np.abs(host(us[0])).max() == 0
+    assert infos[1]["status"] == 0
+    U = disc.direct_solve_dst(2, n2, om, f2)
+    assert rel(host(us[1]), U) < (1e-7 if precision == "f64" else 2e-5)
+
+
 def test_batched_dcg_rejects_bad_input():
     import paper_2606_31842_amd as wh
     f = cuda(wl.gaussian(2, 16, (0.5, 0.5), 0.1))
