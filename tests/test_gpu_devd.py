@@ -108,3 +108,23 @@ def test_augmented_gmres(precision):
         print(f"gpu iters {info['iters']} oracle iters {oi['iters']} (plain gpu {info0['iters']})", flush=True)
         assert abs(info["iters"] - oi["iters"]) <= max(3, oi["iters"] // 10)
         assert rel(host(u), disc.to_nodal(xo, 2, n)) < 1e-7
+
+
+@pytest.mark.parametrize("solver,devd_mode", [("cg", 1), ("gmres", 0)])
+def test_deflation_3d(solver, devd_mode):
+    """3D: Algorithm 2 around CG, and GMRES augmented with the sine modes (Algorithm 4),
+    against the direct solve."""
+    print(f"case 3d {solver} devd={devd_mode}", flush=True)
+    import paper_2606_31842_amd as wh
+    n = 20
+    e = modes.eig1d(n)
+    omega = float(np.sqrt(e[2] + e[3] + e[4]) * 1.002)
+    f = wl.gaussian(3, n, (0.41, 0.57, 0.5), 0.12)
+    d = wh.sine_deflation(3, n, omega, 10)
+    kw = dict(solver=solver, defl=d, tol=1e-10, max_iters=3000, restart=20)
+    if devd_mode:
+        kw["devd"] = devd_mode
+    u, info = wh.solve(cuda(f), omega, **kw)
+    assert info["status"] == 0, info
+    U = disc.direct_solve_dst(3, n, omega, f)
+    assert rel(host(u), U) < 1e-8

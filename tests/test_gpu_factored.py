@@ -122,3 +122,26 @@ def test_factored_rejects_bad_input():
     gap = wh.factored_deflation(fx, fy, np.array([0, 0], dtype=np.int32), lam2)   # mode 1 missing
     with pytest.raises(wh.WaveHoltzError):
         wh.solve(f, 7.7, solver="dcg", defl=gap)
+
+
+def test_factored_mixed_dcg():
+    """Mixed precision with the factored set: the same iterate as with the dense columns
+    (both step in FP32 and project in FP64), within the mixed-path bound of the direct solve."""
+    import torch
+    import paper_2606_31842_amd as wh
+    n = 96
+    e = modes.eig1d(n)
+    omega = float(np.sqrt(e[9] + e[11]) * 1.001)
+    f = wl.gaussian(2, n, (0.37, 0.6), 0.07)
+    V, lam2, npairs = _rotated_sine_set(n, omega, 12)
+    fx, fy, tm, ranks = wh.compress_modes(V, tol=1e-12)
+    dfac = wh.factored_deflation(fx, fy, tm, lam2)
+    dden = wh.Deflation(wh.WH_DEFL_DENSE_EXACT, V=torch.stack([cuda(v).reshape(-1) for v in V]), lambda2=lam2)
+    kw = dict(solver="dcg", tol=1e-9, max_iters=4000, precision="mixed")
+    uf, inf_ = wh.solve(cuda(f), omega, defl=dfac, **kw)
+    ud, ind = wh.solve(cuda(f), omega, defl=dden, **kw)
+    U = disc.direct_solve_dst(2, n, omega, f)
+    print(f"mixed factored iters {inf_['iters']} dense {ind['iters']} err {rel(host(uf), U):.1e}", flush=True)
+    assert inf_["status"] == 0 and ind["status"] == 0
+    assert abs(inf_["iters"] - ind["iters"]) <= 2
+    assert rel(host(uf), U) < 2e-5 and rel(host(uf), host(ud)) < 2e-5
