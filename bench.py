@@ -35,7 +35,7 @@ B_PER_PT_STEP_F64 = 40.0
 # variant "K,R,NW" on this grid, from the two rocprofv3 counter passes summarised in
 # profiles/hbm_traffic_fused2d_f32_2d1024.md (scaled by FETCH x 2.000, WRITE x 1.000 from a
 # plain copy).  Valid only for the kernel source it was taken on.
-TRAFFIC = {"src_sha1": "457acf25e6cd650aa162e460476dab370fd59944", "fetch_scale": 2.000, "write_scale": 1.000,
+TRAFFIC = {"src_sha1": "78373c1e402af794a188aff59c0ef4b3c1ff20d3", "fetch_scale": 2.000, "write_scale": 1.000,
            "kib": {"2,16,4": [8526.6, 16439.8], "2,8,4": [8411.5, 16408.4], "2,8,8": [8495.4, 16445.4],
                    "3,16,4": [8590.1, 16436.5], "3,8,4": [8407.8, 16384.8], "3,8,8": [8554.6, 16443.0],
                    "4,16,4": [8652.1, 16435.2], "4,8,4": [8528.6, 16405.0], "4,8,8": [8612.6, 16435.9],
@@ -57,34 +57,93 @@ def cpu_model():
     return platform.processor()
 
 
-def cpu_baseline(p, nt, budget_s=12.0):
+def cpu_baseline(p, nt, budget_s=12.0, wave_solves=0, direct=True):
     """The oracle (scipy CSR leapfrog, FP64) on the same operator: wave solves until
-    the time budget is used, reported as wave-step Gpts/s."""
-    import numpy as np
+    the time budget is used, reported as wave-step Gpts/s.  Beside it, the time the
+    oracle would take to the tolerance (extrapolated from the wave-solve count) and
+    two direct solves of the same discrete problem on one core: scipy's sparse LU and
+    the oracle's sine-transform solve."""
     from oracle import discretization as disc, timeparams as tpm, wavesolve as ws
     L = disc.laplacian(2, p.n)
     tp = tpm.time_parameters(p.omega, 1.0 / p.n, 1.0)
     v = disc.to_interior(p.f)
-    t0 = time.perf_counter()
-    k = 0
-    while time.perf_counter() - t0 < budget_s or k == 0:
-        v = ws.apply_S(L, v, tp)
-        k += 1
-    dt = time.perf_counter() - t0
+    with _one_thread():
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < budget_s or k == 0:
+            v = ws.apply_S(L, v, tp)
+            k += 1
+        dt = time.perf_counter() - t0
     pts = (p.n - 1) ** 2
-    return {"value": pts * tp.nt * k / dt / 1e9, "unit": "Gpts/s", "cores": 1, "kind": "oracle",
-            "sample": f"{k} FP64 wave solves (N_t={tp.nt}) of the {p.n}^2 operator with oracle.wavesolve "
-                      f"(scipy CSR, one thread) in {dt:.1f} s; host {cpu_model()}, "
-                      f"{len(os.sched_getaffinity(0))} cores visible"}
+    out = {"value": pts * tp.nt * k / dt / 1e9, "unit": "Gpts/s", "cores": 1, "kind": "oracle",
+           "sample": f"{k} FP64 wave solves (N_t={tp.nt}) of the {p.n}^2 operator with oracle.wavesolve "
+                     f"(scipy CSR, one thread) in {dt:.1f} s; host {cpu_model()}, "
+                     f"{len(os.sched_getaffinity(0))} cores visible",
+           "s_per_wave_solve": dt / k}
+    if wave_solves:
+        # the oracle's WaveHoltz iteration needs the same number of wave solves as the
+        # library's to reach the tolerance; its time is that count times the measured rate
+        out["extrapolated_time_to_tol_s"] = round(dt / k * wave_solves, 1)
+        out["extrapolated_from_wave_solves"] = wave_solves
+    if direct:
+        out["direct_splu"] = direct_splu(2, p.n, p.omega, p.f)
+        t0 = time.perf_counter()
+        disc.direct_solve_dst(2, p.n, p.omega, p.f)
+        out["direct_dst_s"] = round(time.perf_counter() - t0, 3)
+    return out
+
+
+def _one_thread():
+    """BLAS pools limited to one thread for the single-core oracle timings."""
+    from threadpoolctl import threadpool_limits
+    return threadpool_limits(1)
+
+
+def oracle_cg_solve(dim, n, omega, f_nodal, tol, c2=None, c_max=1.0):
+    """The oracle's FP64 WaveHoltz CG on one problem, one thread: (iterations, N_t, seconds)."""
+    from oracle import discretization as disc, krylov as kr, timeparams as tpm, wavesolve as ws
+    with _one_thread():
+        t0 = time.perf_counter()
+        L = disc.laplacian(dim, n, c2)
+        tp = tpm.time_parameters(omega, 1.0 / n, c_max)
+        b = ws.rhs(L, disc.to_interior(f_nodal), tp)
+        _, info = kr.cg(lambda v: ws.apply_A(L, v, tp), b, tol=tol, maxit=100000)
+        return info["iters"], tp.nt, time.perf_counter() - t0
+
+
+def _oracle_cg_job(args):
+    return oracle_cg_solve(*args)
+
+
+def direct_splu(dim, n, omega, f_nodal, c2=None):
+    """scipy's sparse LU of the same discrete Helmholtz matrix, one thread."""
+    import numpy as np
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+    from oracle import discretization as disc
+    with _one_thread():
+        L = disc.laplacian(dim, n, c2)
+        A = (L + omega ** 2 * sp.identity(L.shape[0])).tocsc()
+        b = disc.to_interior(f_nodal)
+        t0 = time.perf_counter()
+        lu = sla.splu(A)
+        t1 = time.perf_counter()
+        x = lu.solve(b)
+        t2 = time.perf_counter()
+        return {"factor_s": round(t1 - t0, 3), "solve_s": round(t2 - t1, 4), "lu_nnz": int(lu.L.nnz + lu.U.nnz),
+                "rel_res": float(np.linalg.norm(b - A @ x) / np.linalg.norm(b)),
+                "note": "scipy SuperLU of the same discrete Helmholtz matrix, one thread"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 single-solve comparison")
+    ap.add_argument("--no-direct", action="store_true",
+                    help="skip the CPU direct solves (scipy sparse LU, about 25 s, and the oracle's sine-transform solve)")
     ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5", "solvers", "ndsweep"],
                     help="cfg2 (default) is the benchmark line; the others report the remaining "
                          "workloads (2D 64^2 FP64 CG; 3D 256^3 variable c; 256 batched solves; "
@@ -132,7 +191,11 @@ def main():
         print(json.dumps({"probe": "traffic", "copy_bytes_each_way": a.numel() * 8}), flush=True)
         return
     defl = wh.sine_deflation(2, n, p.omega, 32)
-    kw = dict(solver="dcg", defl=defl, precision="mixed", tol=1e-8, max_iters=50000)
+    # steps per launch and block shape fixed at the autotuner's usual pick for this grid
+    # (K = 6 or 8 with 8 rows x 8 waves, within 1.3 % of each other over a whole solve), so
+    # that the bench line and a profiled run of it time the same kernel
+    kfix = dict(k_fuse=6, k_shape=1)
+    kw = dict(solver="dcg", defl=defl, precision="mixed", tol=1e-8, max_iters=50000, **kfix)
     need = wh.workspace_bytes(2, n, wh.params(p.omega, **{k: v for k, v in kw.items() if k != "defl"}), defl)
     wsp = torch.empty(need, dtype=torch.uint8, device="cuda")
 
@@ -143,10 +206,12 @@ def main():
             f"f32 {info['wave_solves_f32']} f64 {info['wave_solves']} res {info['true_rel_res']:.2e}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = []
+    infos, step_s = [], []
     for i in range(args.steps):
+        ts = time.perf_counter()
         u, info = wh.solve(f, p.omega, workspace=wsp, **kw)
         infos.append(info)
+        step_s.append(time.perf_counter() - ts)   # each solve ends in a host readback
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) / args.steps * 1e3
@@ -165,11 +230,11 @@ def main():
     v = u.clone()
     out = torch.empty_like(v)
     reps = 20
-    wh.apply_filter(v, p.omega, out=out, precision="mixed")
+    wh.apply_filter(v, p.omega, out=out, precision="mixed", **kfix)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        wh.apply_filter(v, p.omega, out=out, precision="mixed")
+        wh.apply_filter(v, p.omega, out=out, precision="mixed", **kfix)
     e1.record()
     torch.cuda.synchronize()
     per_solve_ms = e0.elapsed_time(e1) / reps
@@ -177,7 +242,7 @@ def main():
     kf = info["k_fuse"]
     # the dominant kernel alone: back-to-back launches of the K-step fused kernel
     # (or the streaming step when K = 1), timed with events on the library's stream
-    launch_ms, kshape = wh.time_step_kernel(v, p.omega, precision="mixed", reps=50, shape=True)
+    launch_ms, kshape = wh.time_step_kernel(v, p.omega, precision="mixed", reps=50, shape=True, **kfix)
     launch_us = launch_ms * 1e3
     if kshape["k"] != kf:
         log(f"note: the timed kernel uses K={kshape['k']}, the solve used K={kf}")
@@ -186,6 +251,19 @@ def main():
     achieved = B_PER_PT_STEP_F32 * units / (launch_us * 1e-6) / 1e9
     log(f"filter: {per_solve_ms:.3f} ms per wave solve ({filt_gpts:.0f} Gpts/s); K={kf} kernel "
         f"{launch_us:.2f} us per launch, {achieved:.0f} GB/s algorithmic")
+
+    # the box's attainable HBM rate: a plain 1 GiB device-to-device copy (read + write)
+    ca = torch.empty(128 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(1.0)
+    cb = torch.empty_like(ca)
+    cb.copy_(ca)
+    e0.record()
+    for _ in range(10):
+        cb.copy_(ca)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * ca.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del ca, cb
+    log(f"copy: {copy_gbs:.0f} GB/s")
 
     extra = {}
     if not args.no_f64:
@@ -215,8 +293,10 @@ def main():
         "config": {"workload": "2D unit square Dirichlet 1024x1024, c=1, omega=100.3, Gaussian source "
                                "w=0.02 at seeded centre (seed 2), DCG with the 32 sine modes nearest "
                                "resonance, FP32 stepping / FP64 filter+Krylov, true residual 1e-8",
-                   "n": n, "omega": p.omega, "n_defl": 32, "solver": "dcg", "precision": "mixed", "tol": 1e-8},
+                   "n": n, "omega": p.omega, "n_defl": 32, "solver": "dcg", "precision": "mixed", "tol": 1e-8,
+                   "k_fuse": kfix["k_fuse"], "block": "8 rows x 8 waves"},
         "time_to_tol_ms": round(ms, 3),
+        "ms_per_step_min_median": [round(min(step_s) * 1e3, 3), round(sorted(step_s)[len(step_s) // 2] * 1e3, 3)],
         "solve": {"iters": info["iters"], "outer": info["outer"], "wave_solves_f32": info["wave_solves_f32"],
                   "wave_solves_f64": info["wave_solves"], "nt": nt, "true_rel_res": info["true_rel_res"],
                   "helmholtz_rel_res": hres},
@@ -228,11 +308,16 @@ def main():
                      "k_fuse": kf, "bytes_per_pt_step": B_PER_PT_STEP_F32, "pt_steps_per_launch": units,
                      "bytes_per_launch": B_PER_PT_STEP_F32 * units, "launch_us": round(launch_us, 3),
                      "filter_gpts": round(filt_gpts, 2),
-                     "hbm_gbs_from_traffic": None if traffic is None else round(traffic / (launch_us * 1e-6) / 1e9, 1)},
+                     "hbm_gbs_from_traffic": None if traffic is None else round(traffic / (launch_us * 1e-6) / 1e9, 1),
+                     "traffic_frac_of_peak": None if traffic is None else
+                     round(traffic / (launch_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                     "copy_gbs": round(copy_gbs, 1),
+                     "traffic_frac_of_copy": None if traffic is None else
+                     round(traffic / (launch_us * 1e-6) / 1e9 / copy_gbs, 4)},
         **extra,
     }
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(p, nt)
+        line["cpu_baseline"] = cpu_baseline(p, nt, wave_solves=steps_per_solve // nt, direct=not args.no_direct)
     print(json.dumps(line), flush=True)
 
 
@@ -252,9 +337,15 @@ def run_cfg1(args, np, torch, wh, wl):
     wh.solve(f, p.omega, **kw)
     (u, info), dt = _timed(torch, lambda: wh.solve(f, p.omega, **kw))
     steps = (info["wave_solves"] + info["wave_solves_f32"]) * info["nt"]
-    return {"workload": "cfg1 2D 64^2 FP64 CG tol 1e-10", "time_to_tol_ms": dt * 1e3,
-            "gpts": (p.n - 1) ** 2 * steps / dt / 1e9, "iters": info["iters"], "nt": info["nt"],
-            "true_rel_res": info["true_rel_res"], "helmholtz_rel_res": wh.helmholtz_residual(u, f, p.omega)}
+    out = {"workload": "cfg1 2D 64^2 FP64 CG tol 1e-10", "time_to_tol_ms": dt * 1e3,
+           "gpts": (p.n - 1) ** 2 * steps / dt / 1e9, "iters": info["iters"], "nt": info["nt"],
+           "true_rel_res": info["true_rel_res"], "helmholtz_rel_res": wh.helmholtz_residual(u, f, p.omega)}
+    if not args.no_cpu:
+        it, nt, sec = oracle_cg_solve(2, p.n, p.omega, p.f, 1e-10)
+        out["cpu_baseline"] = {"kind": "oracle", "cores": 1, "oracle_cg_seconds": round(sec, 3), "oracle_cg_iters": it,
+                               "oracle_gpts": (p.n - 1) ** 2 * nt * (it + 1) / sec / 1e9,
+                               "direct_splu": direct_splu(2, p.n, p.omega, p.f), "host": cpu_model()}
+    return out
 
 
 def run_cfg3(args, np, torch, wh, wl):
@@ -283,6 +374,23 @@ def run_cfg3(args, np, torch, wh, wl):
                        "true_rel_res": info["true_rel_res"], "helmholtz_rel_res":
                        wh.helmholtz_residual(u, f, p.omega, c2), "nt": info["nt"],
                        "wave_solves_f32": info["wave_solves_f32"], "wave_solves_f64": info["wave_solves"]}
+    if not args.no_cpu:
+        from oracle import discretization as disc, timeparams as tpm, wavesolve as ws
+        with _one_thread():
+            L = disc.laplacian(3, p.n, p.c2)
+            tp = tpm.time_parameters(p.omega, 1.0 / p.n, float(np.sqrt(p.c2.max())))
+            v = disc.to_interior(p.f)
+            t0 = time.perf_counter()
+            for _ in range(3):
+                v = ws.apply_S(L, v, tp)
+            per = (time.perf_counter() - t0) / 3
+        cb = {"kind": "oracle", "cores": 1, "host": cpu_model(), "s_per_wave_solve": round(per, 2), "nt": tp.nt,
+              "oracle_gpts": pts * tp.nt / per / 1e9,
+              "sample": "3 FP64 wave solves of the variable-c 256^3 operator (scipy CSR, one thread)"}
+        for solver in ("gmres", "cg"):
+            nws = out[solver]["wave_solves_f32"] + out[solver]["wave_solves_f64"]
+            cb[f"{solver}_extrapolated_seconds"] = round(per * nws, 1)
+        out["cpu_baseline"] = cb
     return out
 
 
@@ -314,6 +422,28 @@ def run_cfg4(args, np, torch, wh, wl):
 
     def residuals(us):
         return [wh.helmholtz_residual(u, f, q.omega) for u, f, q in zip(us, fs, probs)]
+
+    if not args.no_cpu:
+        # the oracle's FP64 CG over a process pool (one problem per process, all host
+        # cores) on the smallest grid size; the whole batch is extrapolated from its
+        # point-step rate and the point-steps the FP64 single solves above took
+        import multiprocessing as mp
+        cores = len(os.sched_getaffinity(0))
+        sub = [q for q in probs if q.n == min(q.n for q in probs)]
+        ctx = mp.get_context("spawn")
+        t0 = time.perf_counter()
+        with ctx.Pool(cores) as pool:
+            res = pool.map(_oracle_cg_job, [(2, q.n, q.omega, q.f, 1e-8) for q in sub])
+        wall = time.perf_counter() - t0
+        sub_psteps = sum((it + 1) * nt * (q.n - 1) ** 2 for (it, nt, _), q in zip(res, sub))
+        all_psteps = sum((i["iters"] + 1) * i["nt"] * (q.n - 1) ** 2 for (_, i), q in zip(singles, probs))
+        out["cpu_baseline"] = {
+            "kind": "oracle", "cores": cores, "host": cpu_model(),
+            "sample": f"oracle FP64 CG to 1e-8 on the {len(sub)} problems of size {sub[0].n}, "
+                      f"a spawn pool of {cores} processes",
+            "sample_wall_s": round(wall, 2), "sample_iters": int(sum(r[0] for r in res)),
+            "pool_gpts": sub_psteps / wall / 1e9,
+            "extrapolated_batch_seconds": round(wall * all_psteps / sub_psteps, 1)}
 
     for solver in ("dcg", "cg"):
         for prec in ("mixed", "f64"):

@@ -504,9 +504,11 @@ int wave_solve(const WaveOp& op, const double* vin, bool force, StepMode last, c
 // ----------------------------------------------------------------- autotuner
 // Steps per launch and block shape of the temporally blocked 2D kernel: time every
 // supported (K, shape) on this grid (after one warm-up launch) and keep the fastest
-// per-step time; K = 1 is the streaming kernel.  k_fixed > 0 restricts the search to
-// that K.  The state buffers and V serve as scratch; every caller initialises them
-// afterwards.  Returns K | (shape << 8), cached per context.
+// per-step time; K = 1 is the streaming kernel.  Candidates within 3% of the fastest
+// count as equal and the largest K among them wins (then the earlier shape), so that
+// timing noise does not flip the choice from one context to the next.  k_fixed > 0
+// restricts the search to that K.  The state buffers and V serve as scratch; every
+// caller initialises them afterwards.  Returns K | (shape << 8), cached per context.
 int autotune_k(wh_ctx* ctx, const WaveOp& op, bool force, int k_fixed = 0) {
   const auto key = std::make_tuple(op.dim, op.n, (int)op.f32, (int)op.varc, (int)force + 2 * k_fixed);
   auto it = ctx->ktune.find(key);
@@ -522,6 +524,9 @@ int autotune_k(wh_ctx* ctx, const WaveOp& op, bool force, int k_fixed = 0) {
   }
   int best = k_fixed == 1 ? 1 : fallback;
   float best_t = 1e30f;
+  int tried_code[64];
+  float tried_t[64];
+  int n_tried = 0;
   const int cands[] = {1, 2, 3, 4, 6, 8};
   for (int K : cands) {
     if (k_fixed > 0 && K != k_fixed) continue;
@@ -560,7 +565,7 @@ int autotune_k(wh_ctx* ctx, const WaveOp& op, bool force, int k_fixed = 0) {
         }
       };
       run();
-      const int reps = 3;
+      const int reps = 5;
       (void)hipEventRecord(e0, ctx->stream);
       for (int r = 0; r < reps; ++r) run();
       (void)hipEventRecord(e1, ctx->stream);
@@ -568,10 +573,21 @@ int autotune_k(wh_ctx* ctx, const WaveOp& op, bool force, int k_fixed = 0) {
       float ms = 0;
       (void)hipEventElapsedTime(&ms, e0, e1);
       const float per_step = ms / (reps * K);
-      if (per_step < best_t) {
-        best_t = per_step;
-        best = K | (shape << 8);
+      if (n_tried < 64) {
+        tried_code[n_tried] = K | (shape << 8);
+        tried_t[n_tried++] = per_step;
       }
+      best_t = std::min(best_t, per_step);
+    }
+  }
+  // candidates are visited by increasing K, then shape: the last one within the
+  // tolerance has the largest K and, for that K, the first such shape
+  int best_k = 0;
+  for (int i = 0; i < n_tried; ++i) {
+    const int K = tried_code[i] & 0xff;
+    if (tried_t[i] <= 1.03f * best_t && K > best_k) {
+      best_k = K;
+      best = tried_code[i];
     }
   }
   (void)hipEventDestroy(e0);

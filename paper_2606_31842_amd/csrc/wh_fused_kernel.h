@@ -103,6 +103,9 @@ __global__ __launch_bounds__(64 * NW) void k_fused2d(const FusedDev a) {
   uint32_t mask = 0, omask = 0;
   const double* __restrict__ Vin = a.V;
   constexpr bool first = PH == kPhaseFirst;
+  // first launch: W^0 as loaded (FP64); converted only after every row's load has been
+  // issued, so that the loads overlap instead of waiting one by one
+  double v0[first ? R : 1];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int y = yb + r;
@@ -110,9 +113,7 @@ __global__ __launch_bounds__(64 * NW) void k_fused2d(const FusedDev a) {
     const int64_t p = (int64_t)y * P + xg;
     // boundary nodes hold the Dirichlet value 0: read interior nodes only
     if (first) {
-      const double v0 = (in && a.vin) ? a.vin[p] : 0.0;
-      cur[r] = (T)v0;
-      prv[r] = T(0);
+      v0[first ? r : 0] = (in && a.vin) ? a.vin[p] : 0.0;
     } else {
       cur[r] = in ? cin[p] : T(0);
       prv[r] = in ? pin[p] : T(0);
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(64 * NW) void k_fused2d(const FusedDev a) {
     const int ry = wv * R + r;
     const bool o = in && xout && ry >= K && ry < NW * R - K;
     if (o) omask |= 1u << r;
-    acc[r] = o ? (first ? a.w0 * ((in && a.vin) ? a.vin[p] : 0.0) : Vin[p]) : 0.0;
+    acc[r] = (o && !first) ? Vin[p] : 0.0;
     if (VARC) {
       T kc = T(0), kw = T(0), ke = T(0), ku = T(0), kd = T(0);
       if (in) {
@@ -137,6 +138,14 @@ __global__ __launch_bounds__(64 * NW) void k_fused2d(const FusedDev a) {
       cd[VARC ? r : 0] = kc + kd;
     }
     if (FORCE) frc[FORCE ? r : 0] = in ? fsv[p] : T(0);
+  }
+  if constexpr (first) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      cur[r] = (T)v0[r];
+      prv[r] = T(0);
+      acc[r] = ((omask >> r) & 1u) ? a.w0 * v0[r] : 0.0;
+    }
   }
 
   __shared__ T edge[2][NW][2][64];
@@ -248,30 +257,45 @@ __global__ __launch_bounds__(64 * NW) void k_fused2d(const FusedDev a) {
       }
     }
   } else {
-    // last launch: epilogue of the wave solve on V = acc
+    // last launch: epilogue of the wave solve on V = acc.  Every x value is loaded (rows
+    // outside the tile read a valid in-grid node) before any is used, and every result is
+    // formed before any store, so the block waits once for its loads.  With M_LAST_FPI x
+    // and out may alias; each block reads x only where it writes out, before writing.
     double part = 0.0;
+    double res[R];
+    if (a.last == M_LAST_V) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if ((omask >> r) & 1u) {
-        const int64_t p = (int64_t)(yb + r) * P + xg;
+      for (int r = 0; r < R; ++r) res[r] = acc[r];
+    } else {
+      double xr[R];
+      const int64_t p0 = (int64_t)y0 * P + x0;   // a node of this block's tile
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int64_t p = ((omask >> r) & 1u) ? (int64_t)(yb + r) * P + xg : p0;
+        xr[r] = a.x[p];
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const bool o = (omask >> r) & 1u;
         const double vf = acc[r];
-        if (a.last == M_LAST_V) {
-          a.V[p] = vf;
-        } else if (a.last == M_LAST_AQ) {
-          const double xv = a.x[p];
-          const double q = xv - vf;
-          a.out[p] = q;
-          part += xv * q;
+        const double xv = o ? xr[r] : 0.0;
+        if (a.last == M_LAST_AQ) {
+          res[r] = xv - vf;
+          part += xv * res[r];
         } else if (a.last == M_LAST_EQ) {
-          const double q = -vf;
-          a.out[p] = q;
-          part += a.x[p] * q;
-        } else {   // M_LAST_FPI: x and out may alias, read x first
-          const double d = vf - a.x[p];
-          a.out[p] = vf;
-          part += d * d;
+          res[r] = -vf;
+          part += xv * res[r];
+        } else {   // M_LAST_FPI
+          const double d = vf - xv;
+          res[r] = vf;
+          part += o ? d * d : 0.0;
         }
       }
+    }
+    double* __restrict__ dst = a.last == M_LAST_V ? a.V : a.out;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if ((omask >> r) & 1u) dst[(int64_t)(yb + r) * P + xg] = res[r];
     }
     if (a.last != M_LAST_V) {
       const double sum = block_sum<NW>(part, wv * 64 + lane);
