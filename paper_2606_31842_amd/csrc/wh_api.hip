@@ -133,7 +133,8 @@ namespace {
 struct Layout {
   size_t total = 0;
   size_t Wa = 0, Wb = 0, Wc = 0, Wd = 0, V = 0, kap64 = 0, fs64 = 0, kap32 = 0, fs32 = 0;
-  size_t b = 0, r = 0, p = 0, q = 0, ro = 0, d = 0, basis = 0;
+  size_t b = 0, r = 0, p = 0, q = 0, ro = 0, d = 0, basis = 0, p2 = 0;
+  bool has_p2 = false;   // CG/DCG: second direction buffer for the look-ahead
   size_t partials = 0, partials2 = 0, slots = 0, tab = 0, modes = 0, invmu = 0, ones = 0, tsum = 0;
   int64_t N = 0;
   int nslots = 0, npart = 0;
@@ -181,6 +182,10 @@ Layout make_layout(const wh_grid& g, const wh_params& P, const wh_deflation* def
   L.r = take(L, 8 * N);
   L.p = take(L, 8 * N);
   L.q = take(L, 8 * N);
+  if (P.solver == WH_CG || P.solver == WH_DCG) {
+    L.p2 = take(L, 8 * N);
+    L.has_p2 = true;
+  }
   if (mixed) {
     L.ro = take(L, 8 * N);
     L.d = take(L, 8 * N);
@@ -295,6 +300,21 @@ wh_status readback(wh_ctx* ctx, const double* dev, int count) {
   HIPCHK(ctx, hipMemcpyAsync(ctx->hbuf, dev, sizeof(double) * count, hipMemcpyDeviceToHost,
                              ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return WH_OK;
+}
+
+// Read-back in two halves: the copy is queued (and an event after it), work queued
+// next keeps the GPU busy, and readback_wait blocks until the copy alone has finished.
+wh_status readback_async(wh_ctx* ctx, const double* dev, int count) {
+  if (count > ctx->hbuf_len) WH_FAIL(ctx, WH_EINVAL, "read-back too large");
+  HIPCHK(ctx, hipMemcpyAsync(ctx->hbuf, dev, sizeof(double) * count, hipMemcpyDeviceToHost,
+                             ctx->stream));
+  HIPCHK(ctx, hipEventRecord(ctx->rb_event, ctx->stream));
+  return WH_OK;
+}
+
+wh_status readback_wait(wh_ctx* ctx) {
+  HIPCHK(ctx, hipEventSynchronize(ctx->rb_event));
   return WH_OK;
 }
 
@@ -608,6 +628,7 @@ struct Solver {
   Defl defl;
   const double* invmu = nullptr;   // 1/mu_k (device)
   const double* negmu = nullptr;   // -1/mu_k (device) for the deflated start
+  double* p2 = nullptr;            // CG: spare direction buffer (look-ahead); nullptr: none
   int ws64 = 0, ws32 = 0;          // wave-solve counters
   int iters = 0;
   bool defect = true;              // FP32 A-applies in the defect form
@@ -708,14 +729,39 @@ wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_non
   double anchor = rel;        // relative true residual at the last replacement
   int stalls = 0, last_repl = 0;
   res.replacements = 0;
+  // Look-ahead: while the host waits for an iteration's scalars, the GPU already forms
+  // the next direction p' = r + beta p in the spare buffer and applies A to it, as if the
+  // iteration went on unchanged.  When it does not (a residual replacement, convergence,
+  // a stop), that A-apply is discarded: its result is overwritten before use and it is not
+  // counted as a wave solve.  Needs S.p2 and the plain direction update (no re-projection).
+  double* pc = p;                 // this iteration's direction
+  int nb_ahead = -1;              // >= 0: A pc is already queued (its partial-sum count)
+  bool ahead_f32 = false;
+  const bool can_ahead = S.p2 != nullptr && !(nd && reproject);
+  auto discard_ahead = [&]() {
+    if (nb_ahead >= 0) (ahead_f32 ? S.ws32 : S.ws64)--;
+    nb_ahead = -1;
+  };
   while (rel > tol && k < maxit) {
     const double r2_old = r2;
-    int nb = applyA(S, op32, p, q);
+    const int nb = nb_ahead >= 0 ? nb_ahead : applyA(S, op32, pc, q);
+    nb_ahead = -1;
     launch_reduce(S.partials, nb, S.slots, S_PQ, 1, S.s);
-    launch_cg_update1(x, r, p, q, S.slots, N, S.partials2, S.s);
+    launch_cg_update1(x, r, pc, q, S.slots, N, S.partials2, S.s);
     launch_reduce(S.partials2, kReduceBlocks, S.slots, S_R2, 2, S.s);
+    const bool sync = reliable || (k + 1) % ce == 0 || k + 1 == maxit;
+    double* pn = nullptr;
+    if (sync) {
+      WHCHK(readback_async(ctx, S.slots, S_NSLOTS_FIXED));
+      if (can_ahead && k + 1 < maxit) {
+        pn = pc == p ? S.p2 : p;
+        launch_cg_update2_to(pn, r, pc, S.slots, N, S.s);
+        ahead_f32 = op32;
+        nb_ahead = applyA(S, op32, pn, q);
+      }
+      WHCHK(readback_wait(ctx));
+    }
     if (reliable) {
-      WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
       const double pq = ctx->hbuf[S_PQ];
       r2 = ctx->hbuf[S_R2];
       if (!std::isfinite(pq) || !std::isfinite(r2))
@@ -724,6 +770,7 @@ wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_non
       rel = std::sqrt(r2 / nb2);
       if (rel <= S.reliable_drop * anchor || rel >= 10.0 * anchor || rel <= tol ||
           k + 1 - last_repl >= 500) {
+        discard_ahead();
         applyA(S, false, x, q);
         launch_sub(r, rhs, q, N, S.s);
         dot(S, r, r, S_TMP);
@@ -747,16 +794,17 @@ wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_non
         }
       }
     }
-    if (nd && reproject) {
+    if (nb_ahead >= 0) {
+      pc = pn;   // the look-ahead direction stands
+    } else if (nd && reproject) {
       launch_defl_project(S.defl, r, S.partials, S.s);
       launch_defl_reduce_set(S.defl, S.partials, S.slots, S_H, nullptr, S.s);
-      launch_dcg_update2(S.defl, p, r, S.slots, S_H, N, S.s);
+      launch_dcg_update2(S.defl, pc, r, S.slots, S_H, N, S.s);
     } else {
-      launch_cg_update2(p, r, S.slots, N, S.s);
+      launch_cg_update2(pc, r, S.slots, N, S.s);
     }
     ++k;
-    if (!reliable && (k % ce == 0 || k == maxit)) {
-      WHCHK(readback(ctx, S.slots, S_NSLOTS_FIXED));
+    if (!reliable && sync) {
       const double pq = ctx->hbuf[S_PQ];
       r2 = ctx->hbuf[S_R2];
       if (!std::isfinite(pq) || !std::isfinite(r2))
@@ -764,14 +812,17 @@ wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_non
       if (pq == 0.0) WH_FAIL(ctx, WH_EBREAKDOWN, "CG breakdown: p^T A p = 0 at iteration %d", k);
       rel = std::sqrt(r2 / nb2);
       if (stop_on_divergence && rel > 1e3) {
+        discard_ahead();
         res.rel = rel;
         res.iters = k;
         res.st = WH_ENOCONV;
         res.diverged = true;
         return WH_OK;
       }
+      if (rel <= tol) discard_ahead();
     }
   }
+  discard_ahead();
   res.rel = rel;
   res.iters = k;
   res.st = rel <= tol ? WH_OK : WH_ENOCONV;
@@ -1310,12 +1361,20 @@ wh_status wh_create(wh_ctx** out, int device, void* stream) {
     return WH_EHIP;
   }
   c->hbuf_len = kHostScalars;
+  e = hipEventCreateWithFlags(&c->rb_event, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    g_create_err = std::string("hipEventCreateWithFlags: ") + hipGetErrorString(e);
+    (void)hipHostFree(c->hbuf);
+    delete c;
+    return WH_EHIP;
+  }
   *out = c;
   return WH_OK;
 }
 
 wh_status wh_destroy(wh_ctx* ctx) {
   if (!ctx) return WH_EINVAL;
+  if (ctx->rb_event) (void)hipEventDestroy(ctx->rb_event);
   if (ctx->hbuf) (void)hipHostFree(ctx->hbuf);
   delete ctx;
   return WH_OK;
@@ -1524,6 +1583,10 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
   HIPCHK(ctx, hipMemsetAsync(r, 0, 8 * N, s));
   HIPCHK(ctx, hipMemsetAsync(p, 0, 8 * N, s));
   HIPCHK(ctx, hipMemsetAsync(q, 0, 8 * N, s));
+  if (L.has_p2) {
+    S.p2 = at<double>(ws, L.p2);
+    HIPCHK(ctx, hipMemsetAsync(S.p2, 0, 8 * N, s));
+  }
   HIPCHK(ctx, hipMemsetAsync(S.slots, 0, 8 * (size_t)L.nslots, s));
   // the stencil epilogues write interior nodes only: Krylov vectors keep a zero boundary
   if (P.solver == WH_GMRES)
@@ -1923,6 +1986,10 @@ wh_status vjp_core(wh_ctx* ctx, const wh_grid& G, const double* c2, const double
   double* q = at<double>(ws, V.L.q);
   HIPCHK(ctx, hipMemsetAsync(z, 0, 8 * N, s));
   for (double* v : {r, p, q}) HIPCHK(ctx, hipMemsetAsync(v, 0, 8 * N, s));
+  if (V.L.has_p2) {
+    S.p2 = at<double>(ws, V.L.p2);
+    HIPCHK(ctx, hipMemsetAsync(S.p2, 0, 8 * N, s));
+  }
   HIPCHK(ctx, hipMemsetAsync(S.slots, 0, 8 * (size_t)V.L.nslots, s));
   // z = A^{-1} g (A symmetric)
   KrylovResult kr;

@@ -189,6 +189,17 @@ void launch_cg_update2(double* p, const double* r, const double* slots, int64_t 
   hipLaunchKernelGGL(k_cg_update2, dim3(grid_for(N)), dim3(kBlock), 0, s, p, r, slots, N);
 }
 
+__global__ void k_cg_update2_to(double* pn, const double* r, const double* p, const double* slots,
+                                int64_t N) {
+  const double beta = slots[S_BETA];
+  GRID_STRIDE(i, N) pn[i] = r[i] + beta * p[i];
+}
+
+void launch_cg_update2_to(double* pn, const double* r, const double* p, const double* slots,
+                          int64_t N, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_update2_to, dim3(grid_for(N)), dim3(kBlock), 0, s, pn, r, p, slots, N);
+}
+
 __global__ void k_axpy_slot(double* y, const double* x, const double* slots, int slot,
                             double sign, int64_t N) {
   const double a = sign * slots[slot];

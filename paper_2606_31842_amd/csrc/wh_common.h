@@ -18,6 +18,7 @@ struct wh_ctx {
   std::string err;
   double* hbuf = nullptr;  // pinned host scalars
   int hbuf_len = 0;
+  hipEvent_t rb_event = nullptr;   // marks the end of an asynchronous scalar read-back
   // (dim, n, f32, varc, force) -> steps per launch K | (block shape << 8)
   std::map<std::tuple<int, int, int, int, int>, int> ktune;
 };
@@ -193,6 +194,9 @@ void launch_cg_update1(double* x, double* r, const double* p, const double* q,
                        const double* slots, int64_t N, double* partials, hipStream_t s);
 void launch_cg_update2(double* p, const double* r, const double* slots, int64_t N,
                        hipStream_t s);
+// pn = r + beta p (beta from the slots), into a separate buffer
+void launch_cg_update2_to(double* pn, const double* r, const double* p, const double* slots,
+                          int64_t N, hipStream_t s);
 void launch_axpy_slot(double* y, const double* x, const double* slots, int slot, double sign,
                       int64_t N, hipStream_t s);
 void launch_axpy(double* y, const double* x, double alpha, int64_t N, hipStream_t s);
