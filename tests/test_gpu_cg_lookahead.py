@@ -1,0 +1,84 @@
+"""CG / DCG iterates at every stopping point.
+
+While the host reads an iteration's scalars back, the solver already forms the next
+direction in a spare buffer and queues its A-apply; the iterate it returns must still be
+exactly the k-th CG iterate whatever k, read-back interval or early stop.  The reference
+is the oracle's own CG / DCG (Algorithm 3) run for exactly k iterations."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import discretization as disc, krylov, modes, transfer as tr, wavesolve as ws
+from _gpu import cuda, host, rel, oracle_tp
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(n=48):
+    lam = math.sqrt(modes.mode_lam2(2, n, (5, 7)))
+    omega = lam * (1 - 2e-3)
+    f = wl.gaussian(2, n, (0.41, 0.57), 0.07)
+    return n, omega, f
+
+
+def _oracle_iterate(n, omega, f, k, nd=0):
+    L = disc.laplacian(2, n)
+    tp = oracle_tp(2, n, omega)
+    b = ws.rhs(L, disc.to_interior(f), tp)
+    A = lambda v: ws.apply_A(L, v, tp)
+    if nd:
+        sel, lam2 = modes.select_modes(2, n, omega, nd)
+        W = modes.mode_matrix(2, n, sel)
+        x, _ = krylov.dcg(A, b, W, W * tr.mu_discrete(lam2, tp), tol=0.0, maxit=k, reproject=False)
+    else:
+        x, _ = krylov.cg(A, b, tol=0.0, maxit=k)
+    return disc.to_nodal(x, 2, n)
+
+
+@pytest.mark.parametrize("nd", [0, 6])
+@pytest.mark.parametrize("check_every", [1, 2, 3])
+def test_kth_iterate_matches_oracle(nd, check_every):
+    import paper_2606_31842_amd as wh
+    n, omega, f = _problem()
+    d = wh.sine_deflation(2, n, omega, nd) if nd else None
+    solver = "dcg" if nd else "cg"
+    for k in (1, 2, 3, 4, 5, 7):
+        print(f"case {solver} nd={nd} check_every={check_every} k={k}", flush=True)
+        u, info = wh.solve(cuda(f), omega, solver=solver, defl=d, tol=1e-30, max_iters=k,
+                           check_every=check_every)
+        assert info["iters"] == k and info["status"] == 1, info
+        xo = _oracle_iterate(n, omega, f, k, nd)
+        assert rel(host(u), xo) < 1e-11, (k, rel(host(u), xo))
+
+
+@pytest.mark.parametrize("check_every", [1, 4])
+def test_converged_iterate_matches_oracle(check_every):
+    # a tolerance reached between read-backs: the solver stops at the next read-back,
+    # and its iterate is the oracle's iterate of the same index
+    import paper_2606_31842_amd as wh
+    n, omega, f = _problem()
+    print(f"case cg converged check_every={check_every}", flush=True)
+    u, info = wh.solve(cuda(f), omega, solver="cg", tol=1e-9, max_iters=5000, check_every=check_every)
+    assert info["status"] == 0 and info["iters"] % check_every == 0
+    xo = _oracle_iterate(n, omega, f, info["iters"])
+    assert rel(host(u), xo) < 1e-10
+
+
+def test_mixed_counts_and_repeatability():
+    # mixed DCG: one counted FP32 wave solve per iteration (the discarded look-ahead
+    # A-applies are not counted), and a repeated solve is bit-identical
+    import paper_2606_31842_amd as wh
+    n = 96
+    lam = math.sqrt(modes.mode_lam2(2, n, (9, 14)))
+    omega = lam * (1 - 1e-3)
+    f = wl.gaussian(2, n, (0.37, 0.61), 0.05)
+    d = wh.sine_deflation(2, n, omega, 10)
+    print("case mixed dcg counts", flush=True)
+    u1, i1 = wh.solve(cuda(f), omega, solver="dcg", defl=d, precision="mixed", tol=1e-9)
+    u2, i2 = wh.solve(cuda(f), omega, solver="dcg", defl=d, precision="mixed", tol=1e-9)
+    assert i1["status"] == 0 and i1["outer"] >= 1
+    assert i1["wave_solves_f32"] == i1["iters"]
+    assert i1["iters"] == i2["iters"] and i1["wave_solves"] == i2["wave_solves"]
+    assert np.array_equal(host(u1), host(u2))
