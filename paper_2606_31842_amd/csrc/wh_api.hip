@@ -408,13 +408,31 @@ int step_any(const WaveOp& op, bool force, StepMode mode, const StepArgs& a, hip
   return launch_step(op.dim, op.f32, op.varc, force, mode, a, s);
 }
 
+// A CG direction update p' = r + beta p (beta = slots[S_BETA]) that a wave solve forms as
+// its input; out receives p' (distinct from r and p).
+struct DirUpd {
+  const double* r;
+  const double* p;
+  const double* slots;
+  double* out;
+};
+
+// One wave solve from vin (or from the direction update du, whose result is also the
+// epilogue's x when x == du->out).  Returns the number of partial sums the epilogue wrote.
 int wave_solve(const WaveOp& op, const double* vin, bool force, StepMode last, const double* x,
-               double* out, hipStream_t s) {
+               double* out, hipStream_t s, const DirUpd* du = nullptr) {
   const TimeParams& tp = *op.tp;
-  if (op.order == 2 && op.dim == 2 && op.k_fuse > 1 && fused2d_supported(op.f32, op.k_fuse)) {
+  const bool fused2d = op.order == 2 && op.dim == 2 && op.k_fuse > 1 && fused2d_supported(op.f32, op.k_fuse);
+  const std::vector<int> parts = fused2d ? plan_launches(tp.nt, op.k_fuse, op.f32) : std::vector<int>{};
+  if (du && parts.size() < 2) {
+    // no blocked first launch to fuse the update into: form p' on its own
+    launch_cg_update2_to(du->out, du->r, du->p, du->slots, nodal_count(op.dim, op.n), s);
+    vin = du->out;
+    du = nullptr;
+  }
+  if (fused2d) {
     // 2D: every step in blocked launches; the first starts from vin with the half step,
     // the last ends in the epilogue (no streaming kernels)
-    const std::vector<int> parts = plan_launches(tp.nt, op.k_fuse, op.f32);
     // at least two launches: vin (read with halo by the first) may alias out (written by
     // the last), as in the fixed-point update x <- Pi x
     if (parts.size() >= 2) {
@@ -445,6 +463,15 @@ int wave_solve(const WaveOp& op, const double* vin, bool force, StepMode last, c
         fa.cosv = &tp.cosv[nn];
         fa.first = i == 0;
         fa.last = i + 1 == parts.size() ? last : M_MID;
+        if (du && i == 0) {
+          fa.dr = du->r;
+          fa.dp = du->p;
+          fa.dslots = du->slots;
+          fa.dout = du->out;
+        } else {
+          fa.dr = fa.dp = fa.dslots = nullptr;
+          fa.dout = nullptr;
+        }
         launch_fused2d(op.f32, op.varc, force, fa, s);
         std::swap(cur, oc);
         std::swap(prev, op_);
@@ -652,6 +679,19 @@ int applyA(Solver& S, bool f32, const double* x, double* q) {
   return wave_solve(op, x, false, M_LAST_AQ, x, q, S.s);
 }
 
+// pn = r + beta p, then q = A pn; in the blocked 2D form the update is part of the wave
+// solve's first launch.  Same values as launch_cg_update2_to followed by applyA.
+int applyA_dir(Solver& S, bool f32, const double* r, const double* p, double* pn, double* q) {
+  if (f32 && S.defect) {
+    launch_cg_update2_to(pn, r, p, S.slots, S.N, S.s);
+    return applyA(S, f32, pn, q);
+  }
+  const WaveOp& op = f32 ? S.op32 : S.op64;
+  (f32 ? S.ws32 : S.ws64)++;
+  const DirUpd du{r, p, S.slots, pn};
+  return wave_solve(op, nullptr, false, M_LAST_AQ, pn, q, S.s, &du);
+}
+
 // slots[dst] = a . b
 void dot(Solver& S, const double* a, const double* b, int dst) {
   launch_dot_partials(a, b, S.N, S.partials2, S.s);
@@ -755,9 +795,8 @@ wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_non
       WHCHK(readback_async(ctx, S.slots, S_NSLOTS_FIXED));
       if (can_ahead && k + 1 < maxit) {
         pn = pc == p ? S.p2 : p;
-        launch_cg_update2_to(pn, r, pc, S.slots, N, S.s);
         ahead_f32 = op32;
-        nb_ahead = applyA(S, op32, pn, q);
+        nb_ahead = applyA_dir(S, op32, r, pc, pn, q);
       }
       WHCHK(readback_wait(ctx));
     }

@@ -124,6 +124,12 @@ struct FusedArgs {
   const double* x = nullptr;
   double* out = nullptr;
   double* partials = nullptr;
+  // first launch only, instead of vin: W^0 = dr + beta dp with beta = dslots[S_BETA] (the
+  // CG direction update), also written to dout over the interior
+  const double* dr = nullptr;
+  const double* dp = nullptr;
+  const double* dslots = nullptr;
+  double* dout = nullptr;
 };
 constexpr int kFusedShapes = 3;
 bool fused2d_supported(bool f32, int k);

@@ -50,6 +50,10 @@ void launch_fused2d(bool f32, bool varc, bool force, const FusedArgs& fa, hipStr
   d.x = fa.x;
   d.out = fa.out;
   d.partials = fa.partials;
+  d.dr = fa.dr;
+  d.dp = fa.dp;
+  d.dslots = fa.dslots;
+  d.dout = fa.dout;
   const int shape = fa.shape < 0 || fa.shape >= kFusedShapes ? 0 : fa.shape;
   if (fa.first) launch_fused2d_first(f32, fa.k, shape, varc, force, d, s);
   else if (fa.last != M_MID) launch_fused2d_last(f32, fa.k, shape, varc, force, d, s);

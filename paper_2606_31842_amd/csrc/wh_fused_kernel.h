@@ -61,6 +61,12 @@ struct FusedDev {
   const double* x;
   double* out;
   double* partials;
+  // first launch, when dr is set: W^0 = dr + beta dp (beta = dslots[S_BETA]) instead of vin,
+  // i.e. the CG direction update fused into the load; dout receives it over the interior
+  const double* dr;
+  const double* dp;
+  const double* dslots;
+  double* dout;
 };
 
 // Tile order that gives each XCD a contiguous run of tiles (blocks are dispatched
@@ -105,16 +111,19 @@ __global__ __launch_bounds__(64 * NW) void k_fused2d(const FusedDev a) {
   constexpr bool first = PH == kPhaseFirst;
   // first launch: W^0 as loaded (FP64); converted only after every row's load has been
   // issued, so that the loads overlap instead of waiting one by one
+  // (rows outside the domain load a valid interior node of the tile and discard it, so
+  // the loads carry no branches)
   double v0[first ? R : 1];
+  const bool dirupd = first && a.dr != nullptr;
+  const double beta = dirupd ? a.dslots[S_BETA] : 0.0;
+  const int64_t p_in = (int64_t)y0 * P + x0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int y = yb + r;
     const bool in = xin && y >= 1 && y <= n - 1;
     const int64_t p = (int64_t)y * P + xg;
     // boundary nodes hold the Dirichlet value 0: read interior nodes only
-    if (first) {
-      v0[first ? r : 0] = (in && a.vin) ? a.vin[p] : 0.0;
-    } else {
+    if (!first) {
       cur[r] = in ? cin[p] : T(0);
       prv[r] = in ? pin[p] : T(0);
     }
@@ -140,6 +149,33 @@ __global__ __launch_bounds__(64 * NW) void k_fused2d(const FusedDev a) {
     if (FORCE) frc[FORCE ? r : 0] = in ? fsv[p] : T(0);
   }
   if constexpr (first) {
+    // one uniform branch around straight-line loads: every row's loads are issued before
+    // the first is used
+    if (dirupd) {
+      double rv[R], pv[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int64_t ps = ((mask >> r) & 1u) ? (int64_t)(yb + r) * P + xg : p_in;
+        rv[r] = a.dr[ps];
+        pv[r] = a.dp[ps];
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) v0[r] = ((mask >> r) & 1u) ? rv[r] + beta * pv[r] : 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if ((omask >> r) & 1u) a.dout[(int64_t)(yb + r) * P + xg] = v0[r];
+    } else if (a.vin) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int64_t ps = ((mask >> r) & 1u) ? (int64_t)(yb + r) * P + xg : p_in;
+        v0[r] = a.vin[ps];
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) v0[r] = ((mask >> r) & 1u) ? v0[r] : 0.0;
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v0[r] = 0.0;
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       cur[r] = (T)v0[r];
