@@ -786,8 +786,14 @@ wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_non
     const double r2_old = r2;
     const int nb = nb_ahead >= 0 ? nb_ahead : applyA(S, op32, pc, q);
     nb_ahead = -1;
-    launch_reduce(S.partials, nb, S.slots, S_PQ, 1, S.s);
-    launch_cg_update1(x, r, pc, q, S.slots, N, S.partials2, S.s);
+    // alpha from the A-apply's partial sums: inside the update kernel when they are few
+    // (each of its blocks sums them), else by a reduction launch of its own
+    if (nb <= 4096) {
+      launch_cg_update1(x, r, pc, q, S.slots, N, S.partials2, S.s, S.partials, nb);
+    } else {
+      launch_reduce(S.partials, nb, S.slots, S_PQ, 1, S.s);
+      launch_cg_update1(x, r, pc, q, S.slots, N, S.partials2, S.s);
+    }
     launch_reduce(S.partials2, kReduceBlocks, S.slots, S_R2, 2, S.s);
     const bool sync = reliable || (k + 1) % ce == 0 || k + 1 == maxit;
     double* pn = nullptr;

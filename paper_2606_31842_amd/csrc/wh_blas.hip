@@ -160,9 +160,30 @@ void launch_set_beta(double* slots, int src, double r2_old, hipStream_t s) {
 }
 
 // ----------------------------------------------------------------- CG updates
+// x += alpha p, r -= alpha q, partial sums of r.r.  With pq_parts, every block first
+// forms p^T q from the A-apply's pq_count partial sums (the same order as k_reduce, so the
+// same value) and alpha = r^T r / p^T q itself; block 0 stores both in the slots.
 __global__ void k_cg_update1(double* x, double* r, const double* p, const double* q,
-                             const double* slots, int64_t N, double* partials) {
-  const double alpha = slots[S_ALPHA];
+                             double* slots, int64_t N, double* partials, const double* pq_parts,
+                             int pq_count) {
+  double alpha;
+  if (pq_parts) {
+    __shared__ double sh_alpha;
+    double a = 0.0;
+    for (int i = threadIdx.x; i < pq_count; i += blockDim.x) a += pq_parts[i];
+    const double pq = block_sum256(a, threadIdx.x);
+    if (threadIdx.x == 0) {
+      sh_alpha = slots[S_R2] / pq;
+      if (blockIdx.x == 0) {
+        slots[S_PQ] = pq;
+        slots[S_ALPHA] = sh_alpha;
+      }
+    }
+    __syncthreads();
+    alpha = sh_alpha;
+  } else {
+    alpha = slots[S_ALPHA];
+  }
   double acc = 0.0;
   GRID_STRIDE(i, N) {
     x[i] += alpha * p[i];
@@ -174,10 +195,11 @@ __global__ void k_cg_update1(double* x, double* r, const double* p, const double
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-void launch_cg_update1(double* x, double* r, const double* p, const double* q, const double* slots,
-                       int64_t N, double* partials, hipStream_t s) {
+void launch_cg_update1(double* x, double* r, const double* p, const double* q, double* slots,
+                       int64_t N, double* partials, hipStream_t s, const double* pq_parts,
+                       int pq_count) {
   hipLaunchKernelGGL(k_cg_update1, dim3(kReduceBlocks), dim3(kBlock), 0, s, x, r, p, q, slots, N,
-                     partials);
+                     partials, pq_parts, pq_count);
 }
 
 __global__ void k_cg_update2(double* p, const double* r, const double* slots, int64_t N) {

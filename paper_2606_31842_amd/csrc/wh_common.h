@@ -196,8 +196,12 @@ void launch_gs_update(const double* V, int64_t N, int nv, const double* slots, i
 void launch_reduce(const double* partials, int count, double* slots, int dst, int mode,
                    hipStream_t s);
 void launch_set_beta(double* slots, int src, double r2_old, hipStream_t s);
-void launch_cg_update1(double* x, double* r, const double* p, const double* q,
-                       const double* slots, int64_t N, double* partials, hipStream_t s);
+// x += alpha p, r -= alpha q, partial sums of r.r into partials.  With pq_parts set, alpha
+// (and slots[S_PQ], slots[S_ALPHA]) is formed from the pq_count partial sums of p.q in the
+// same kernel, in place of a preceding launch_reduce(..., S_PQ, 1).
+void launch_cg_update1(double* x, double* r, const double* p, const double* q, double* slots,
+                       int64_t N, double* partials, hipStream_t s, const double* pq_parts = nullptr,
+                       int pq_count = 0);
 void launch_cg_update2(double* p, const double* r, const double* slots, int64_t N,
                        hipStream_t s);
 // pn = r + beta p (beta from the slots), into a separate buffer
