@@ -270,11 +270,53 @@ __global__ __launch_bounds__(64 * NW) void k_fused3d(const Fused3Dev a) {
   }
 }
 
+// Output planes per block when the shape leaves it open (zs = 0): every block marches its
+// run plus 2K lead planes, and blocks run in rounds of (CUs x resident blocks per CU), so
+// the launch takes about rounds x (zs + 2K) plane steps; take the z-split that minimises it,
+// with runs of at least 2K planes (the lead planes at most double the loads).
+static int balanced_zs(int n, int K, int tiles_xy, int slots) {
+  int best_zs = n - 1;
+  long best = -1;
+  for (int gz = 1; gz <= n - 1; ++gz) {
+    const int zs = (n - 1 + gz - 1) / gz;
+    if ((n - 1 + zs - 1) / zs != gz) continue;   // the same run length as a smaller gz
+    if (zs < 2 * K && gz > 1) break;
+    const long rounds = ((long)tiles_xy * gz + slots - 1) / slots;
+    const long cost = rounds * (zs + 2 * K);
+    if (best < 0 || cost < best) {
+      best = cost;
+      best_zs = zs;
+    }
+  }
+  return best_zs;
+}
+
+template <typename T, int K, int R, int NW, bool VARC, bool FORCE>
+static int resident_slots() {
+  static int slots = 0;   // per kernel: CUs x resident blocks per CU (of the first device used)
+  if (slots == 0) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_fused3d<T, K, R, NW, VARC, FORCE>, 64 * NW, 0) !=
+            hipSuccess)
+      return 256;
+    slots = std::max(1, cus * std::max(1, per));
+  }
+  return slots;
+}
+
 template <typename T, int K, int R, int NW>
 static void launch_3d(bool varc, bool force, Fused3Dev& d, hipStream_t s) {
   const int n = d.n;
   d.gx = (n - 1 + (64 - 2 * K) - 1) / (64 - 2 * K);
   d.gy = (n - 1 + (NW * R - 2 * K) - 1) / (NW * R - 2 * K);
+  if (d.zs <= 0) {
+    int slots;
+    if (varc) slots = force ? resident_slots<T, K, R, NW, true, true>() : resident_slots<T, K, R, NW, true, false>();
+    else slots = force ? resident_slots<T, K, R, NW, false, true>() : resident_slots<T, K, R, NW, false, false>();
+    d.zs = balanced_zs(n, K, d.gx * d.gy, slots);
+  }
   d.gz = (n - 1 + d.zs - 1) / d.zs;
   dim3 g(d.gx * d.gy * d.gz), b(64, NW);
   if (varc) {
@@ -291,11 +333,12 @@ bool fused3d_supported(bool f32, int k) {
   return k == 2 || k == 3;
 }
 
-// Shapes (rows per thread R, waves per block NW, output planes per block ZS):
-// FP32 (4,8,32) (4,8,16) (2,16,32); FP64 (2,16,32) (2,16,16) (4,8,32).
+// Shapes (rows per thread R, waves per block NW, output planes per block ZS; 0: balanced
+// over the resident blocks, see balanced_zs):
+// FP32 (4,8,0) (4,8,16) (2,16,0); FP64 (2,16,0) (2,16,16) (4,8,0).
 void fused3d_shape_dims(bool f32, int shape, int* rows, int* waves, int* zs) {
-  static const int r32[kFusedShapes] = {4, 4, 2}, w32[kFusedShapes] = {8, 8, 16}, z32[kFusedShapes] = {32, 16, 32};
-  static const int r64[kFusedShapes] = {2, 2, 4}, w64[kFusedShapes] = {16, 16, 8}, z64[kFusedShapes] = {32, 16, 32};
+  static const int r32[kFusedShapes] = {4, 4, 2}, w32[kFusedShapes] = {8, 8, 16}, z32[kFusedShapes] = {0, 16, 0};
+  static const int r64[kFusedShapes] = {2, 2, 4}, w64[kFusedShapes] = {16, 16, 8}, z64[kFusedShapes] = {0, 16, 0};
   const int sh = shape < 0 || shape >= kFusedShapes ? 0 : shape;
   *rows = f32 ? r32[sh] : r64[sh];
   *waves = f32 ? w32[sh] : w64[sh];
