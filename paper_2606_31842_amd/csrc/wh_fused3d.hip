@@ -125,6 +125,42 @@ __global__ __launch_bounds__(64 * NW) void k_fused3d(const Fused3Dev a) {
 
   __shared__ T edge[2][K > 1 ? K - 1 : 1][NW][2][64];
   const int zlast = min(z0 + a.zs - 1, n - 1);   // last output plane
+  // FP32: plane loads run one z-step ahead (the values of plane t+1 are requested before
+  // the levels are computed at plane t, so their latency overlaps that arithmetic).  FP64
+  // loads plane t where it is used: its staging registers would spill.
+  constexpr bool PF = sizeof(T) == 4;
+  T sw[R], sd[R], sk[VARC ? R : 1], sf[FORCE ? R : 1], seu, sed, sku = T(0), skd = T(0);
+  double sv[R];
+  auto load_plane = [&](int tt) {
+    const bool zin = tt >= 1 && tt <= n - 1;
+    const bool zok = tt >= 0 && tt <= n;
+    const int64_t pz = (int64_t)(zok ? tt : 0) * P2;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool in = zin && ((ymask >> r) & 1u);
+      const int64_t p = pz + (int64_t)(yb + r) * P + xg;
+      T w0 = T(0), d0 = T(0);
+      if (in) {
+        w0 = cin[p];
+        d0 = INC ? pin[p] : w0 - pin[p];
+      }
+      sw[r] = w0;
+      sd[r] = d0;
+      if (VARC) sk[VARC ? r : 0] = (zok && ((kmask >> r) & 1u)) ? kap[p] : T(0);
+      if (FORCE) sf[FORCE ? r : 0] = in ? fsv[p] : T(0);
+      // V of plane tt for the inner tile, added to as the levels pass this plane
+      sv[r] = (zin && tt >= z0 && tt <= zlast && ((omask >> r) & 1u)) ? a.V[p] : 0.0;
+    }
+    const int64_t pu = pz + (int64_t)(yb - 1) * P + xg;
+    const int64_t pd = pz + (int64_t)(yb + R) * P + xg;
+    seu = (zin && yup_in) ? cin[pu] : T(0);
+    sed = (zin && ydn_in) ? cin[pd] : T(0);
+    if (VARC) {
+      sku = (zok && yup_ok) ? kap[pu] : T(0);
+      skd = (zok && ydn_ok) ? kap[pd] : T(0);
+    }
+  };
+  if constexpr (PF) load_plane(z0 - K);
   for (int t = z0 - K; t <= zlast + K; ++t) {
     const int b = t & 1;
     // (a) edges of levels 1..K-1 at their centre planes, written one plane ago
@@ -134,8 +170,8 @@ __global__ __launch_bounds__(64 * NW) void k_fused3d(const Fused3Dev a) {
       eu[s - 1] = wv > 0 ? edge[b ^ 1][s - 1][wv - 1][1][lane] : T(0);
       ed[s - 1] = wv < NW - 1 ? edge[b ^ 1][s - 1][wv + 1][0][lane] : T(0);
     }
-    // (b) shift the rings and load plane t (zero outside the open domain)
-    const bool zin = t >= 1 && t <= n - 1;
+    // (b) shift the rings and take plane t (zero outside the open domain)
+    if constexpr (!PF) load_plane(t);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       Wr[0][0][r] = Wr[0][1][r];
@@ -163,33 +199,22 @@ __global__ __launch_bounds__(64 * NW) void k_fused3d(const Fused3Dev a) {
     for (int q = 0; q < K; ++q)
 #pragma unroll
       for (int r = 0; r < R; ++r) AC[q][r] = AC[q + 1][r];
-    const bool zok = t >= 0 && t <= n;
-    const int64_t pz = (int64_t)(zok ? t : 0) * P2;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const bool in = zin && ((ymask >> r) & 1u);
-      const int64_t p = pz + (int64_t)(yb + r) * P + xg;
-      T w0 = T(0), d0 = T(0);
-      if (in) {
-        w0 = cin[p];
-        d0 = INC ? pin[p] : w0 - pin[p];
-      }
-      Wr[0][2][r] = w0;
-      Dr[0][1][r] = d0;
-      if (VARC) KP[VARC ? K + 1 : 0][r] = (zok && ((kmask >> r) & 1u)) ? kap[p] : T(0);
-      if (FORCE) FS[FORCE ? K : 0][r] = in ? fsv[p] : T(0);
-      // V of plane t for the inner tile, added to as the levels pass this plane
-      AC[K][r] = (zin && t >= z0 && t <= zlast && ((omask >> r) & 1u)) ? a.V[p] : 0.0;
+      Wr[0][2][r] = sw[r];
+      Dr[0][1][r] = sd[r];
+      if (VARC) KP[VARC ? K + 1 : 0][r] = sk[VARC ? r : 0];
+      if (FORCE) FS[FORCE ? K : 0][r] = sf[FORCE ? r : 0];
+      AC[K][r] = sv[r];
     }
-    {
-      const int64_t pu = pz + (int64_t)(yb - 1) * P + xg;
-      const int64_t pd = pz + (int64_t)(yb + R) * P + xg;
-      E0[1][0] = (zin && yup_in) ? cin[pu] : T(0);
-      E0[1][1] = (zin && ydn_in) ? cin[pd] : T(0);
-      if (VARC) {
-        KE[VARC ? K + 1 : 0][0] = (zok && yup_ok) ? kap[pu] : T(0);
-        KE[VARC ? K + 1 : 0][1] = (zok && ydn_ok) ? kap[pd] : T(0);
-      }
+    E0[1][0] = seu;
+    E0[1][1] = sed;
+    if (VARC) {
+      KE[VARC ? K + 1 : 0][0] = sku;
+      KE[VARC ? K + 1 : 0][1] = skd;
+    }
+    if constexpr (PF) {
+      if (t < zlast + K) load_plane(t + 1);
     }
     // (c) levels s = 1..K at planes q = t - s
 #pragma unroll
