@@ -608,25 +608,44 @@ constexpr int kBW = 8;
 
 static bool batch_k_ok(int K) { return K == 2 || K == 4 || K == 8; }
 
+// Second stream of a round: the FP64 work kernel runs beside the FP32 one.  Every problem
+// is in one phase, and each phase's tiles are worked by exactly one of the two kernels
+// (the other returns before touching anything), so the two write disjoint data; both
+// only read the states, which the control kernel updates after both have finished.
+struct RoundFork {
+  hipStream_t s2 = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+
 template <int K, bool VARC>
 static void launch_round_k(const BDesc* descs, BState* states, const int* ts, int ntiles,
-                           hipStream_t s) {
+                           hipStream_t s, const RoundFork* rf) {
   dim3 g(ntiles), b(64, kBW);
-  hipLaunchKernelGGL((k_batch_work<double, K, kBR, kBW, VARC>), g, b, 0, s, descs,
+  hipStream_t s64 = s;
+  if (rf) {
+    (void)hipEventRecord(rf->fork, s);
+    (void)hipStreamWaitEvent(rf->s2, rf->fork, 0);
+    s64 = rf->s2;
+  }
+  hipLaunchKernelGGL((k_batch_work<double, K, kBR, kBW, VARC>), g, b, 0, s64, descs,
                      (const BState*)states, ts, ntiles, 0);
   hipLaunchKernelGGL((k_batch_work<float, K, kBR, kBW, VARC>), g, b, 0, s, descs,
                      (const BState*)states, ts, ntiles, 1);
+  if (rf) {
+    (void)hipEventRecord(rf->join, rf->s2);
+    (void)hipStreamWaitEvent(s, rf->join, 0);
+  }
 }
 
 static void launch_round(int K, bool varc, int nb, const BDesc* descs, BState* states,
-                         const int* ts, int ntiles, hipStream_t s) {
+                         const int* ts, int ntiles, hipStream_t s, const RoundFork* rf = nullptr) {
   switch (K) {
-    case 2: varc ? launch_round_k<2, true>(descs, states, ts, ntiles, s)
-                 : launch_round_k<2, false>(descs, states, ts, ntiles, s); break;
-    case 4: varc ? launch_round_k<4, true>(descs, states, ts, ntiles, s)
-                 : launch_round_k<4, false>(descs, states, ts, ntiles, s); break;
-    default: varc ? launch_round_k<8, true>(descs, states, ts, ntiles, s)
-                  : launch_round_k<8, false>(descs, states, ts, ntiles, s); break;
+    case 2: varc ? launch_round_k<2, true>(descs, states, ts, ntiles, s, rf)
+                 : launch_round_k<2, false>(descs, states, ts, ntiles, s, rf); break;
+    case 4: varc ? launch_round_k<4, true>(descs, states, ts, ntiles, s, rf)
+                 : launch_round_k<4, false>(descs, states, ts, ntiles, s, rf); break;
+    default: varc ? launch_round_k<8, true>(descs, states, ts, ntiles, s, rf)
+                  : launch_round_k<8, false>(descs, states, ts, ntiles, s, rf); break;
   }
   hipLaunchKernelGGL(k_batch_control, dim3(nb), dim3(256), 0, s, descs, states, K);
 }
@@ -985,6 +1004,10 @@ wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
   const int G = 32;
   hipStream_t cs;
   HIPB(ctx, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  RoundFork rf;
+  bool use_fork = hipStreamCreateWithFlags(&rf.s2, hipStreamNonBlocking) == hipSuccess;
+  use_fork = use_fork && hipEventCreateWithFlags(&rf.fork, hipEventDisableTiming) == hipSuccess;
+  use_fork = use_fork && hipEventCreateWithFlags(&rf.join, hipEventDisableTiming) == hipSuccess;
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -993,7 +1016,8 @@ wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
   for (int gi = 0; gi < 2 && e == hipSuccess; ++gi) {
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      for (int g = 0; g < G; ++g) launch_round(K, varc, nb, ddesc, dstate, dtiles, ntiles, cs);
+      for (int g = 0; g < G; ++g)
+        launch_round(K, varc, nb, ddesc, dstate, dtiles, ntiles, cs, use_fork ? &rf : nullptr);
       hipLaunchKernelGGL(k_batch_count, dim3(1), dim3(256), 0, cs, (const BState*)dstate, nb, dcount[gi]);
       e = hipStreamEndCapture(cs, &graph[gi]);
     }
@@ -1006,6 +1030,9 @@ wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
       if (graph[gi]) (void)hipGraphDestroy(graph[gi]);
       if (ev[gi]) (void)hipEventDestroy(ev[gi]);
     }
+    if (rf.fork) (void)hipEventDestroy(rf.fork);
+    if (rf.join) (void)hipEventDestroy(rf.join);
+    if (rf.s2) (void)hipStreamDestroy(rf.s2);
     (void)hipStreamDestroy(cs);
   };
   if (e != hipSuccess) {
