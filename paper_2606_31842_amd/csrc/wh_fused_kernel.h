@@ -280,13 +280,19 @@ __global__ __launch_bounds__(64 * NW) void k_fused2d(const FusedDev a) {
     }
   }
   // write the inner tile (acc holds V + sum_s w_s W^{n+s})
+  // the row addresses are formed again below rather than kept from the loads through the
+  // time loop (an opaque copy of the row index stops the compiler from reusing them):
+  // R 64-bit addresses per array held across the steps cost more registers than the
+  // few instructions that recompute them
+  int ys = yb;
+  asm volatile("" : "+v"(ys));
   if constexpr (PH != kPhaseLast) {
     T* __restrict__ cout = (T*)a.cur_out;
     T* __restrict__ pout = (T*)a.prev_out;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if ((omask >> r) & 1u) {
-        const int64_t p = (int64_t)(yb + r) * P + xg;
+        const int64_t p = (int64_t)(ys + r) * P + xg;
         cout[p] = cur[r];
         pout[p] = prv[r];
         a.V[p] = acc[r];
@@ -307,7 +313,7 @@ __global__ __launch_bounds__(64 * NW) void k_fused2d(const FusedDev a) {
       const int64_t p0 = (int64_t)y0 * P + x0;   // a node of this block's tile
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int64_t p = ((omask >> r) & 1u) ? (int64_t)(yb + r) * P + xg : p0;
+        const int64_t p = ((omask >> r) & 1u) ? (int64_t)(ys + r) * P + xg : p0;
         xr[r] = a.x[p];
       }
 #pragma unroll
@@ -331,7 +337,7 @@ __global__ __launch_bounds__(64 * NW) void k_fused2d(const FusedDev a) {
     double* __restrict__ dst = a.last == M_LAST_V ? a.V : a.out;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      if ((omask >> r) & 1u) dst[(int64_t)(yb + r) * P + xg] = res[r];
+      if ((omask >> r) & 1u) dst[(int64_t)(ys + r) * P + xg] = res[r];
     }
     if (a.last != M_LAST_V) {
       const double sum = block_sum<NW>(part, wv * 64 + lane);
