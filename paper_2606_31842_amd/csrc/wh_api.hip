@@ -198,8 +198,13 @@ Layout make_layout(const wh_grid& g, const wh_params& P, const wh_deflation* def
   dd.dim = g.dim;
   dd.n = g.n;
   int np = std::max(kReduceBlocks, step_partial_blocks(g.dim, g.n));
-  // 2D blocked launches end with one partial per block; the smallest tile is 48 x 16
-  if (g.dim == 2) np = std::max(np, ((g.n - 1 + 47) / 48) * ((g.n - 1 + 15) / 16));
+  // 2D blocked launches end with one partial per block: room for the most blocks any
+  // supported (precision, K, shape) launches on this grid
+  if (g.dim == 2)
+    for (int f = 0; f < 2; ++f)
+      for (int k = 2; k <= 9; ++k)
+        if (fused2d_supported(f == 1, k))
+          for (int sh = 0; sh < kFusedShapes; ++sh) np = std::max(np, fused2d_blocks(f == 1, k, sh, g.n));
   if (g.order == 4) np = std::max(np, step4_blocks(g.dim, g.n));
   const int nrow = defl_rows(defl);
   if (nd) np = std::max(np, defl_partial_blocks(dd) * nrow);
@@ -389,6 +394,12 @@ std::vector<int> plan_launches(int nt, int K, bool f32) {
     return best;
   };
   int full = nt / K, rem = nt % K;
+  if (rem == 1 && full > 0 && ok(K + 1)) {
+    // one launch of K + 1 takes the odd step
+    for (int i = 0; i < full - 1; ++i) parts.push_back(K);
+    parts.push_back(K + 1);
+    return parts;
+  }
   if (rem == 1 && full > 0) {
     --full;
     rem += K;

@@ -383,6 +383,9 @@ static void launch_k(int k, int shape, bool varc, bool force, FusedDev& d, hipSt
     case 4: launch_shape<T, 4, PH>(shape, varc, force, d, s); break;
     case 6: launch_shape<T, 6, PH>(shape, varc, force, d, s); break;
     case 8: launch_shape<T, 8, PH>(shape, varc, force, d, s); break;
+    case 9:
+      if constexpr (sizeof(T) == 4) launch_shape<T, 9, PH>(shape, varc, force, d, s);
+      break;
     default: break;
   }
 }
