@@ -134,3 +134,27 @@ def _fused_case(k_fuse, shape, dim, n, omega, varc, force):
     out32, _ = wh.apply_filter(cuda(v), omega, precision="mixed", **args)
     emu = rel(_oracle_filter(dim, n, omega, v, f, c2, state_dtype=np.float32), ref)
     assert rel(host(out32), ref) < 20 * emu + 1e-7
+
+
+@pytest.mark.parametrize("n,omega,force", [(96, 29.5, True), (130, 11.3, False), (64, 19.7, True)])
+def test_fused2d_odd_step_launch(n, omega, force):
+    """N_t = 8m + 1 with K = 8: FP32 ends in one K = 9 launch, FP64 (no K = 9) in 6 + 3."""
+    import paper_2606_31842_amd as wh
+    tp = wh.time_params(2, n, omega)
+    assert tp["nt"] % 8 == 1
+    _fused_case(8, -1, 2, n, omega, False, force)
+
+
+@pytest.mark.parametrize("shape", [0, 1, 2])
+def test_fused2d_k9_every_shape(shape):
+    """K = 9 (FP32 only) as the steps per launch, on every block shape."""
+    print(f"case fused k=9 shape={shape}", flush=True)
+    import paper_2606_31842_amd as wh
+    n, omega = 130, 31.7
+    v = wl.random_nodal(2, n, seed=3 * n)
+    f = wl.gaussian(2, n, (0.4, 0.6), 0.15)
+    ref = _oracle_filter(2, n, omega, v, f, None)
+    out32, info = wh.apply_filter(cuda(v), omega, f=cuda(f), precision="mixed", k_fuse=9, k_shape=shape)
+    assert info["k_fuse"] == 9
+    emu = rel(_oracle_filter(2, n, omega, v, f, None, state_dtype=np.float32), ref)
+    assert rel(host(out32), ref) < 20 * emu + 1e-7
