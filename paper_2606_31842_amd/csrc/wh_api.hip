@@ -394,10 +394,12 @@ std::vector<int> plan_launches(int nt, int K, bool f32) {
     return best;
   };
   int full = nt / K, rem = nt % K;
-  if (rem == 1 && full > 0 && ok(K + 1)) {
-    // one launch of K + 1 takes the odd step
-    for (int i = 0; i < full - 1; ++i) parts.push_back(K);
+  if (rem == 1 && full > 1 && ok(K + 1)) {
+    // one launch of K + 1 takes the odd step; it is the one before the last, so that the
+    // last launch (the epilogue) keeps the size of the others
+    for (int i = 0; i < full - 2; ++i) parts.push_back(K);
     parts.push_back(K + 1);
+    parts.push_back(K);
     return parts;
   }
   if (rem == 1 && full > 0) {

@@ -9,8 +9,8 @@ void launch_fused2d_mid(bool f32, int k, int shape, bool varc, bool force, Fused
 }
 
 bool fused2d_supported(bool f32, int k) {
-  // FP32 also K = 9: a wave solve of N_t = 8m + 1 steps is then 8s and one 9 instead of
-  // ending in a 6 and a 3
+  // FP32 also K = 9: a wave solve of N_t = 8m + 1 steps is then 8s, one 9 and a last 8
+  // instead of ending in a 6 and a 3
   return k == 2 || k == 3 || k == 4 || k == 6 || k == 8 || (f32 && k == 9);
 }
 
