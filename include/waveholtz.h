@@ -109,7 +109,9 @@ typedef struct {
                                residual is replaced by the true one (0: 0.1 for CG, 1e-3
                                for DCG, 1e-4 for deflated batch problems)                   */
   int32_t max_outer;        /* WH_MIXED GMRES: FP64 refinement sweeps (default 30)           */
-  int32_t k_fuse;           /* time steps per stencil launch; 0: library choice             */
+  int32_t k_fuse;           /* time steps per stencil launch; 0: library choice.  Blocked
+                               2D launches take 2, 3, 4, 6, 8 (FP32 also 9), 3D 2 or 3; any
+                               other value, fourth order, or too few steps: one per launch  */
   int32_t reproject;        /* DCG A-orthogonalisation against W each iteration (Algorithm 3,
                                optional for exact eigenvectors): -1 auto (= off, every
                                deflation kind here is exact), 0 off, 1 on                  */
