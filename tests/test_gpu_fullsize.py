@@ -26,7 +26,10 @@ def test_config2_filter_full_size():
     out, info = wh.apply_filter(cuda(v), p.omega, f=cuda(p.f))
     assert info["nt"] == tp.nt == 129
     e64 = rel(host(out), ref)
-    out32, info32 = wh.apply_filter(cuda(v), p.omega, f=cuda(p.f), precision="mixed")
+    # the launch configuration the benchmark times: K = 8 with 8 rows x 8 waves (N_t = 129
+    # is then 8s, one 9 and a last 8)
+    out32, info32 = wh.apply_filter(cuda(v), p.omega, f=cuda(p.f), precision="mixed", k_fuse=8, k_shape=1)
+    assert info32["k_fuse"] == 8 and (info32["k_rows"], info32["k_waves"]) == (8, 8)
     emu = disc.to_nodal(ws.wave_filter(L, disc.to_interior(v), disc.to_interior(p.f), tp,
                                        state_dtype=np.float32), 2, p.n)
     e32, eemu = rel(host(out32), ref), rel(emu, ref)
@@ -38,13 +41,15 @@ def test_config2_filter_full_size():
 
 def test_config2_solve_full_size():
     """The benchmarked solve: 1024^2, omega = 100.3, mixed DCG with the 32 sine modes
-    nearest resonance, true residual 1e-8; against the oracle's exact discrete solution."""
+    nearest resonance, true residual 1e-8, in the benchmark's launch configuration (K = 8,
+    8 rows x 8 waves); against the oracle's exact discrete solution."""
     print("case config2 solve 1024^2 mixed dcg 32", flush=True)
     import paper_2606_31842_amd as wh
     p = wl.config2()
     d = wh.sine_deflation(2, p.n, p.omega, 32)
     u, info = wh.solve(cuda(p.f), p.omega, solver="dcg", defl=d, precision="mixed", tol=1e-8,
-                       max_iters=50000)
+                       max_iters=50000, k_fuse=8, k_shape=1)
+    assert info["k_fuse"] == 8
     U = disc.direct_solve_dst(2, p.n, p.omega, p.f)
     e = rel(host(u), U)
     print(f"err {e:.2e} true res {info['true_rel_res']:.2e} iters {info['iters']}", flush=True)
