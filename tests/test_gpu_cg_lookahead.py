@@ -82,3 +82,26 @@ def test_mixed_counts_and_repeatability():
     assert i1["wave_solves_f32"] == i1["iters"]
     assert i1["iters"] == i2["iters"] and i1["wave_solves"] == i2["wave_solves"]
     assert np.array_equal(host(u1), host(u2))
+
+
+@pytest.mark.parametrize("solver,nd", [("cg", 0), ("dcg", 6)])
+def test_replacements_and_fp64_switch_with_lookahead(solver, nd):
+    # a drop factor near 1 replaces the residual at almost every iteration, and replacements
+    # that stop halving it move the recurrence to the FP64 operator: the look-ahead A-apply
+    # is discarded at each of them, and the solve still ends at the oracle's solution
+    import paper_2606_31842_amd as wh
+    n, omega, f = _problem()
+    d = wh.sine_deflation(2, n, omega, nd) if nd else None
+    U = disc.to_nodal(disc.direct_solve(disc.laplacian(2, n), omega, disc.to_interior(f)), 2, n)
+    print(f"case {solver} mixed inner_tol=0.9", flush=True)
+    u, info = wh.solve(cuda(f), omega, solver=solver, defl=d, precision="mixed", tol=1e-9,
+                       inner_tol=0.9, max_iters=5000)
+    assert info["status"] == 0 and info["true_rel_res"] <= 1e-9
+    assert info["outer"] >= 3
+    # every replacement is one FP64 wave solve; more than that means FP64 iterations ran
+    print(f"outer {info['outer']} f32 {info['wave_solves_f32']} f64 {info['wave_solves']} "
+          f"iters {info['iters']}", flush=True)
+    assert info["wave_solves_f32"] + info["wave_solves"] >= info["iters"]
+    assert info["wave_solves"] > info["outer"] + 2      # the FP64 continuation ran
+    ref, _ = wh.solve(cuda(f), omega, solver=solver, defl=d, tol=1e-9, max_iters=5000)
+    assert rel(host(u), U) < 50 * max(rel(host(ref), U), 1e-12)
