@@ -361,9 +361,9 @@ void launch_fused(int dim, bool f32, bool varc, bool force, const FusedArgs& fa,
   if (dim == 2) launch_fused2d(f32, varc, force, fa, s);
   else launch_fused3d(f32, varc, force, fa, s);
 }
-void fused_shape_dims(int dim, bool f32, int shape, int* rows, int* waves) {
+void fused_shape_dims(int dim, bool f32, int k, int shape, int* rows, int* waves) {
   if (dim == 2) {
-    fused2d_shape_dims(f32, shape, rows, waves);
+    fused2d_shape_dims(f32, k, shape, rows, waves);
   } else {
     int zs = 0;
     fused3d_shape_dims(f32, shape, rows, waves, &zs);
@@ -1346,7 +1346,7 @@ void fill_info(wh_info* info, const TimeParams& tp, int k_fuse, const WaveOp* op
   info->c_max = tp.c_max;
   info->k_fuse = k_fuse;
   info->k_rows = info->k_waves = 0;
-  if (op && k_fuse > 1) fused_shape_dims(op->dim, op->f32, op->k_shape, &info->k_rows, &info->k_waves);
+  if (op && k_fuse > 1) fused_shape_dims(op->dim, op->f32, k_fuse, op->k_shape, &info->k_rows, &info->k_waves);
 }
 
 }  // namespace
@@ -1982,7 +1982,7 @@ wh_status wh_time_step_kernel(wh_ctx* ctx, const wh_grid* grid, const double* c2
   *us_per_launch = 1e3 * (double)ms / reps;
   if (k_used) *k_used = K;
   int rr = 0, wv = 0;
-  if (K > 1) fused_shape_dims(op.dim, op.f32, op.k_shape, &rr, &wv);
+  if (K > 1) fused_shape_dims(op.dim, op.f32, K, op.k_shape, &rr, &wv);
   if (rows) *rows = rr;
   if (waves) *waves = wv;
   return WH_OK;

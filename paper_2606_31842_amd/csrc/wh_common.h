@@ -136,7 +136,7 @@ bool fused2d_supported(bool f32, int k);
 // Default block shape for a grid when no timing is available.
 int fused2d_default_shape(bool f32, int n);
 // Register rows per thread and wavefronts per block of a block shape.
-void fused2d_shape_dims(bool f32, int shape, int* rows, int* waves);
+void fused2d_shape_dims(bool f32, int k, int shape, int* rows, int* waves);
 void launch_fused2d(bool f32, bool varc, bool force, const FusedArgs& a, hipStream_t s);
 // Blocks (= partial sums) of a 2D blocked launch with this K and shape.
 int fused2d_blocks(bool f32, int k, int shape, int n);

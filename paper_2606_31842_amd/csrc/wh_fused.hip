@@ -22,12 +22,15 @@ int fused2d_default_shape(bool f32, int n) {
   return n >= 768 ? 2 : 1;
 }
 
-void fused2d_shape_dims(bool f32, int shape, int* rows, int* waves) {
+void fused2d_shape_dims(bool f32, int k, int shape, int* rows, int* waves) {
   static const int r32[kFusedShapes] = {16, 8, 8}, w32[kFusedShapes] = {4, 8, 4};
   static const int r64[kFusedShapes] = {8, 4, 4}, w64[kFusedShapes] = {4, 8, 16};
   const int s = shape < 0 || shape >= kFusedShapes ? 0 : shape;
   *rows = f32 ? r32[s] : r64[s];
   *waves = f32 ? w32[s] : w64[s];
+  // FP32 K = 9 with 8 waves takes 9 rows per thread: a 64 x 72 region, whose 46 x 54 inner
+  // tiles keep a 1024^2 launch within two blocks per CU (64 x 64 would need 529 blocks)
+  if (f32 && k == 9 && s == 1) *rows = 9;
 }
 
 void launch_fused2d(bool f32, bool varc, bool force, const FusedArgs& fa, hipStream_t s) {
@@ -63,7 +66,7 @@ void launch_fused2d(bool f32, bool varc, bool force, const FusedArgs& fa, hipStr
 
 int fused2d_blocks(bool f32, int k, int shape, int n) {
   int rows, waves;
-  fused2d_shape_dims(f32, shape, &rows, &waves);
+  fused2d_shape_dims(f32, k, shape, &rows, &waves);
   const int tx = 64 - 2 * k, ty = waves * rows - 2 * k;
   return ((n - 1 + tx - 1) / tx) * ((n - 1 + ty - 1) / ty);
 }

@@ -365,8 +365,10 @@ static void launch_krw(bool varc, bool force, FusedDev& d, hipStream_t s) {
 template <typename T, int K, int PH>
 static void launch_shape(int shape, bool varc, bool force, FusedDev& d, hipStream_t s) {
   if constexpr (sizeof(T) == 4) {
+    // (rows per thread, waves per block) as listed by fused2d_shape_dims
+    constexpr int R1 = K == 9 ? 9 : 8;
     if (shape == 0) launch_krw<T, K, 16, 4, PH>(varc, force, d, s);
-    else if (shape == 1) launch_krw<T, K, 8, 8, PH>(varc, force, d, s);
+    else if (shape == 1) launch_krw<T, K, R1, 8, PH>(varc, force, d, s);
     else launch_krw<T, K, 8, 4, PH>(varc, force, d, s);
   } else {
     if (shape == 0) launch_krw<T, K, 8, 4, PH>(varc, force, d, s);
