@@ -35,12 +35,12 @@ B_PER_PT_STEP_F64 = 40.0
 # variant "K,R,NW" on this grid, from the two rocprofv3 counter passes summarised in
 # profiles/hbm_traffic_fused2d_f32_2d1024.md (scaled by FETCH x 2.000, WRITE x 1.000 from a
 # plain copy).  Valid only for the kernel source it was taken on.
-TRAFFIC = {"src_sha1": "668ff9fbbdf1585abc4b7c80ad1e4f4fbc512209", "fetch_scale": 2.000, "write_scale": 1.000,
-           "kib": {"2,8,4": [8415.0, 16408.3], "2,8,8": [8498.4, 16445.4], "2,16,4": [8533.9, 16440.3],
-                   "3,8,4": [8404.2, 16384.3], "3,8,8": [8551.1, 16441.5], "3,16,4": [8591.1, 16437.1],
-                   "4,8,4": [8532.1, 16405.0], "4,8,8": [8616.1, 16436.9], "4,16,4": [8654.6, 16436.2],
-                   "6,8,4": [8621.4, 16394.0], "6,8,8": [8673.4, 16415.4], "6,16,4": [8725.4, 16412.2],
-                   "8,8,4": [8715.2, 16384.2], "8,8,8": [8849.8, 16426.2], "8,16,4": [8905.8, 16426.5]}}
+TRAFFIC = {"src_sha1": "e20c1609c19597223bdf79e5167b888778df7d6f", "fetch_scale": 2.000, "write_scale": 1.000,
+           "kib": {"2,8,4": [8415.0, 16408.0], "2,8,8": [8498.4, 16444.9], "2,16,4": [8533.9, 16438.6],
+                   "3,8,4": [8404.2, 16384.3], "3,8,8": [8551.1, 16440.4], "3,16,4": [8591.1, 16436.2],
+                   "4,8,4": [8532.1, 16405.0], "4,8,8": [8616.1, 16437.0], "4,16,4": [8654.6, 16435.8],
+                   "6,8,4": [8621.4, 16394.0], "6,8,8": [8673.4, 16415.7], "6,16,4": [8725.4, 16411.9],
+                   "8,8,4": [8715.2, 16384.4], "8,8,8": [8849.8, 16427.0], "8,16,4": [8905.8, 16427.3]}}
 
 
 def log(*a):
