@@ -35,9 +35,12 @@
  *          pinned host block per context for scalar read-backs).
  * Stream.  All device work is enqueued on the context stream.  wh_apply_filter is
  *          asynchronous when params->c_max > 0; solvers block until they return.
- * Errors.  Nothing aborts or throws across the ABI.  Negative status: outputs are
- *          not valid; WH_ENOCONV: the best iterate is returned with its residual
- *          in wh_info.  wh_last_error() gives a message for the last failure.
+ * Errors.  Nothing aborts or throws across the ABI: every entry point that can
+ *          allocate host memory catches any C++ exception and returns WH_EHOST.
+ *          Negative status: outputs are not valid; WH_ENOCONV: the best iterate is
+ *          returned with its residual in wh_info.  wh_last_error() gives a message for
+ *          the last failure (with ctx == NULL: the calling thread's last failure of a
+ *          call that has no context).
  */
 #ifndef WAVEHOLTZ_H
 #define WAVEHOLTZ_H
@@ -57,7 +60,10 @@ typedef enum {
   WH_EHIP = -3,          /* a HIP runtime call failed                                    */
   WH_EWORKSPACE = -4,    /* workspace missing, too small or misaligned (256 B)           */
   WH_EUNSTABLE = -5,     /* wave solve blew up (non-finite), e.g. CFL violated           */
-  WH_EBREAKDOWN = -6     /* Krylov breakdown: p^T A p = 0, zero Arnoldi vector norm      */
+  WH_EBREAKDOWN = -6,    /* Krylov breakdown: p^T A p = 0, zero Arnoldi vector norm      */
+  WH_EHOST = -7          /* host-side failure inside the library (memory allocation or an
+                            internal exception); caught at the entry point, message in
+                            wh_last_error                                                */
 } wh_status;
 
 typedef enum { WH_F64 = 0, WH_MIXED = 1 } wh_precision;

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwaveholtz.so")
 
 WH_OK, WH_ENOCONV = 0, 1
-WH_EINVAL, WH_EUNSUPPORTED, WH_EHIP, WH_EWORKSPACE, WH_EUNSTABLE, WH_EBREAKDOWN = -1, -2, -3, -4, -5, -6
+WH_EINVAL, WH_EUNSUPPORTED, WH_EHIP, WH_EWORKSPACE, WH_EUNSTABLE, WH_EBREAKDOWN, WH_EHOST = -1, -2, -3, -4, -5, -6, -7
 WH_F64, WH_MIXED = 0, 1
 WH_FPI, WH_CG, WH_DCG, WH_GMRES, WH_BICGSTAB = 0, 1, 2, 3, 4
 WH_DEFL_NONE, WH_DEFL_SINE, WH_DEFL_DENSE_EXACT, WH_DEFL_DENSE, WH_DEFL_FACTORED = 0, 1, 2, 3, 4

@@ -28,6 +28,7 @@ constexpr int kHostScalars = 4096;
     char _b[512];                                                 \
     snprintf(_b, sizeof(_b), __VA_ARGS__);                        \
     if (ctx) (ctx)->err = _b;                                     \
+    else wh::set_thread_error(_b);                                \
     return (code);                                                \
   } while (0)
 
@@ -1352,6 +1353,16 @@ void fill_info(wh_info* info, const TimeParams& tp, int k_fuse, const WaveOp* op
 }  // namespace
 
 // =================================================================== C ABI
+// Message of the last failure on this thread of a call with no context to hold it
+// (wh_create, the host helpers, workspace sizing).
+namespace {
+thread_local std::string g_create_err;
+}  // namespace
+
+namespace wh {
+void set_thread_error(const char* msg) { g_create_err = msg ? msg : ""; }
+}  // namespace wh
+
 extern "C" {
 
 void wh_params_default(wh_params* p) {
@@ -1388,14 +1399,14 @@ const char* wh_status_string(wh_status s) {
     case WH_EWORKSPACE: return "workspace missing or too small";
     case WH_EUNSTABLE: return "unstable wave solve";
     case WH_EBREAKDOWN: return "Krylov breakdown";
+    case WH_EHOST: return "host-side failure inside the library";
   }
   return "unknown status";
 }
 
-// Message of the last failed wh_create on this thread (there is no context to hold it).
-static thread_local std::string g_create_err;
 
 wh_status wh_create(wh_ctx** out, int device, void* stream) {
+  return guard(nullptr, [&]() -> wh_status {
   if (!out) return WH_EINVAL;
   *out = nullptr;
   int count = 0;
@@ -1428,6 +1439,7 @@ wh_status wh_create(wh_ctx** out, int device, void* stream) {
   }
   *out = c;
   return WH_OK;
+  });
 }
 
 wh_status wh_destroy(wh_ctx* ctx) {
@@ -1448,6 +1460,7 @@ const char* wh_last_error(const wh_ctx* ctx) { return ctx ? ctx->err.c_str() : g
 
 wh_status wh_time_params(const wh_grid* grid, const wh_params* params, double c_max, int32_t* m,
                          int32_t* nt, double* dt, double* omega_tilde) {
+  return guard(nullptr, [&]() -> wh_status {
   WHCHK(check_grid(nullptr, grid));
   WHCHK(check_params(nullptr, grid, params));
   TimeParams tp;
@@ -1457,10 +1470,12 @@ wh_status wh_time_params(const wh_grid* grid, const wh_params* params, double c_
   if (dt) *dt = tp.dt;
   if (omega_tilde) *omega_tilde = tp.omega_w;
   return WH_OK;
+  });
 }
 
 wh_status wh_transfer(const wh_grid* grid, const wh_params* params, double c_max, int32_t count,
                       const double* lambda2, double* beta) {
+  return guard(nullptr, [&]() -> wh_status {
   WHCHK(check_grid(nullptr, grid));
   WHCHK(check_params(nullptr, grid, params));
   if (count < 0 || (count > 0 && (!lambda2 || !beta))) return WH_EINVAL;
@@ -1468,10 +1483,12 @@ wh_status wh_transfer(const wh_grid* grid, const wh_params* params, double c_max
   WHCHK(make_time_params(nullptr, grid->dim, grid->n, *params, c_max > 0 ? c_max : 1.0, tp, grid->order));
   for (int i = 0; i < count; ++i) beta[i] = transfer(tp, lambda2[i]);
   return WH_OK;
+  });
 }
 
 wh_status wh_select_sine_modes(int32_t dim, int32_t n, int32_t order, double omega, int32_t n_d,
                                int32_t* modes, double* lambda2) {
+  return guard(nullptr, [&]() -> wh_status {
   if ((dim != 2 && dim != 3) || n < 4 || n_d < 0 || !(omega > 0) || (n_d > 0 && !modes) ||
       (order != 2 && order != 4))
     return WH_EINVAL;
@@ -1558,16 +1575,20 @@ wh_status wh_select_sine_modes(int32_t dim, int32_t n, int32_t order, double ome
     }
   }
   return WH_OK;
+  });
 }
 
 size_t wh_workspace_bytes(const wh_grid* grid, const wh_params* params, const wh_deflation* defl) {
+  return guard_size([&]() -> size_t {
   if (!grid || !params || check_grid(nullptr, grid) != WH_OK) return 0;
   return make_layout(*grid, *params, defl).total;
+  });
 }
 
 wh_status wh_apply_filter(wh_ctx* ctx, const wh_grid* grid, const double* c2, const double* f,
                           const double* v_in, double* v_out, const wh_params* params, void* ws,
                           size_t ws_bytes, wh_info* info) {
+  return guard(ctx, [&]() -> wh_status {
   if (!ctx) return WH_EINVAL;
   const double t0 = now_ms();
   WHCHK(check_grid(ctx, grid));
@@ -1592,11 +1613,13 @@ wh_status wh_apply_filter(wh_ctx* ctx, const wh_grid* grid, const double* c2, co
     info->ms = now_ms() - t0;
   }
   return WH_OK;
+  });
 }
 
 wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const double* f,
                    const wh_deflation* defl, const wh_params* params, double* u, void* ws,
                    size_t ws_bytes, wh_info* info) {
+  return guard(ctx, [&]() -> wh_status {
   if (!ctx) return WH_EINVAL;
   const double t0 = now_ms();
   if (info) std::memset(info, 0, sizeof(*info));
@@ -1889,11 +1912,13 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
   }
   if (st == WH_ENOCONV) ctx->err = "tolerance not reached";
   return st;
+  });
 }
 
 wh_status wh_helmholtz_residual(wh_ctx* ctx, const wh_grid* grid, const double* c2,
                                 const double* f, double omega, const double* u, void* ws,
                                 size_t ws_bytes, double* rel) {
+  return guard(ctx, [&]() -> wh_status {
   if (!ctx) return WH_EINVAL;
   WHCHK(check_grid(ctx, grid));
   if (!f || !u || !rel) WH_FAIL(ctx, WH_EINVAL, "NULL argument");
@@ -1914,12 +1939,14 @@ wh_status wh_helmholtz_residual(wh_ctx* ctx, const wh_grid* grid, const double* 
   WHCHK(readback(ctx, out, 2));
   *rel = ctx->hbuf[1] > 0 ? std::sqrt(ctx->hbuf[0] / ctx->hbuf[1]) : 0.0;
   return WH_OK;
+  });
 }
 
 wh_status wh_time_step_kernel(wh_ctx* ctx, const wh_grid* grid, const double* c2,
                               const wh_params* params, int32_t reps, void* ws, size_t ws_bytes,
                               double* us_per_launch, int32_t* k_used, int32_t* rows,
                               int32_t* waves) {
+  return guard(ctx, [&]() -> wh_status {
   if (!ctx) return WH_EINVAL;
   WHCHK(check_grid(ctx, grid));
   WHCHK(check_params(ctx, grid, params));
@@ -1986,6 +2013,7 @@ wh_status wh_time_step_kernel(wh_ctx* ctx, const wh_grid* grid, const double* c2
   if (rows) *rows = rr;
   if (waves) *waves = wv;
   return WH_OK;
+  });
 }
 
 // ------------------------------------------------------------------ adjoint
@@ -2158,17 +2186,20 @@ wh_status adjoint_nt(wh_ctx* ctx, const wh_grid& G, const double* c2, const wh_p
 extern "C" {
 
 size_t wh_workspace_bytes_adjoint(const wh_grid* grid, const wh_params* params, int32_t ckpt_every) {
+  return guard_size([&]() -> size_t {
   if (!grid || !params || check_grid(nullptr, grid) != WH_OK || grid->dim != 2 || grid->order != 2) return 0;
   if (!(params->c_max > 0)) return 0;
   TimeParams tp;
   if (make_time_params(nullptr, 2, grid->n, *params, params->c_max, tp) != WH_OK) return 0;
   return make_vjp_layout(*grid, *params, ckpt_every, tp.nt).total;
+  });
 }
 
 wh_status wh_solve_vjp(wh_ctx* ctx, const wh_grid* grid, const double* c2, const double* f,
                        const double* u, const double* grad_u, const wh_params* params,
                        int32_t ckpt_every, double* grad_c2, void* ws, size_t ws_bytes,
                        wh_info* info) {
+  return guard(ctx, [&]() -> wh_status {
   if (!ctx) return WH_EINVAL;
   const double t0 = now_ms();
   if (info) std::memset(info, 0, sizeof(*info));
@@ -2191,12 +2222,14 @@ wh_status wh_solve_vjp(wh_ctx* ctx, const wh_grid* grid, const double* c2, const
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   if (info) info->ms = now_ms() - t0;
   return WH_OK;
+  });
 }
 
 wh_status wh_adjoint_grad(wh_ctx* ctx, const wh_grid* grid, const double* c2, int32_t n_src,
                           const double* const* f, int32_t n_rec, const int64_t* rec_idx,
                           const double* d, const wh_params* params, int32_t ckpt_every,
                           double* grad_c2, double* J, void* ws, size_t ws_bytes, wh_info* info) {
+  return guard(ctx, [&]() -> wh_status {
   if (!ctx) return WH_EINVAL;
   const double t0 = now_ms();
   if (info) std::memset(info, 0, sizeof(*info));
@@ -2262,6 +2295,7 @@ wh_status wh_adjoint_grad(wh_ctx* ctx, const wh_grid* grid, const double* c2, in
     info->ms = now_ms() - t0;
   }
   return worst;
+  });
 }
 
 }  // extern "C"

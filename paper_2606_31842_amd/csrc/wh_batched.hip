@@ -832,6 +832,7 @@ wh_status deflated_start(wh_ctx* ctx, const wh_problem& pr, const TimeParams& tp
 extern "C" {
 
 size_t wh_workspace_bytes_batched(int32_t nb, const wh_problem* probs, const wh_params* params) {
+  return guard_size([&]() -> size_t {
   if (batch_validate(nullptr, nb, probs, params) != WH_OK) return 0;
   const bool mixed = params->precision == WH_MIXED;
   const bool varc = probs[0].c2 != nullptr;
@@ -854,10 +855,12 @@ size_t wh_workspace_bytes_batched(int32_t nb, const wh_problem* probs, const wh_
   total += ((sizeof(BDesc) * nb + 255) & ~(size_t)255) + ((sizeof(BState) * nb + 255) & ~(size_t)255);
   total += ((4 * (size_t)ntiles + 255) & ~(size_t)255) + 256;
   return total;
+  });
 }
 
 wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
                            const wh_params* params, void* ws, size_t ws_bytes, wh_info* infos) {
+  return guard(ctx, [&]() -> wh_status {
   if (!ctx) return WH_EINVAL;
   const auto t0 = std::chrono::steady_clock::now();
   wh_status vs = batch_validate(ctx, nb, probs, params);
@@ -1112,6 +1115,7 @@ wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
   }
   if (st == WH_ENOCONV) ctx->err = "some batched problems did not reach the tolerance";
   return st;
+  });
 }
 
 }  // extern "C"

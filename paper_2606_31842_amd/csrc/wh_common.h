@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <exception>
 #include <map>
 #include <string>
 #include <tuple>
@@ -24,6 +25,41 @@ struct wh_ctx {
 };
 
 namespace wh {
+
+// Error message of a failure with no context to hold it (thread-local; wh_last_error(NULL)).
+void set_thread_error(const char* msg);
+
+// Entry-point guard: runs body() and turns any C++ exception into WH_EHOST with the
+// message in the context (or the thread-local slot), so nothing throws across the ABI.
+template <typename F>
+wh_status guard(wh_ctx* ctx, F&& body) noexcept {
+  const char* what = nullptr;
+  try {
+    return body();
+  } catch (const std::exception& e) {
+    what = e.what();
+  } catch (...) {
+    what = "unknown exception";
+  }
+  try {
+    std::string m = std::string("internal host failure: ") + (what ? what : "");
+    if (ctx) ctx->err = m;
+    else set_thread_error(m.c_str());
+  } catch (...) {
+  }
+  return WH_EHOST;
+}
+
+// The same for entry points that return a size (0 signals failure).
+template <typename F>
+size_t guard_size(F&& body) noexcept {
+  try {
+    return body();
+  } catch (...) {
+    set_thread_error("internal host failure while sizing the workspace");
+    return 0;
+  }
+}
 
 // Time discretisation of one wave solve (host, FP64).
 struct TimeParams {

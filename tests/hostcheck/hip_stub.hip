@@ -1,0 +1,660 @@
+// Host-only stand-in for the HIP runtime, for checking libwaveholtz's host code on a
+// machine without a GPU.  The library's sources are compiled host-only (no device code)
+// with AddressSanitizer and UBSan and linked against this file instead of libamdhip64.
+//
+// "Device" memory is ordinary host memory that the driver program allocates and
+// registers (hostcheck_register); copies and fills really run (memcpy / memset, so the
+// sanitizer checks both ranges).  Kernels do not run.  Instead every launch is checked:
+// for the kernels modelled below, the exact index range each thread of the launch would
+// touch through every pointer argument is computed with the kernel's own index formulas
+// and must lie inside one registered allocation; the launch geometry must match what the
+// kernel assumes (tile grids, partial-sum counts).  A violation prints the launch and
+// aborts the program, so the calling test fails with the message.
+//
+// Scalar read-backs into the pinned block return synthetic values that let the Krylov
+// drivers run through several iterations (a residual that shrinks by a fixed factor per
+// read-back), so that their loops, look-ahead and replacement logic are exercised too.
+#include <cxxabi.h>
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../paper_2606_31842_amd/csrc/wh_fused_kernel.h"
+
+using namespace wh;
+
+namespace {
+
+struct Alloc {
+  size_t bytes;
+  std::string name;
+};
+std::map<uintptr_t, Alloc>& allocs() {
+  static std::map<uintptr_t, Alloc> m;
+  return m;
+}
+std::map<const void*, std::string>& kernels() {
+  static std::map<const void*, std::string> m;
+  return m;
+}
+uintptr_t g_pinned = 0;
+size_t g_pinned_bytes = 0;
+long g_launches = 0, g_modelled = 0, g_readbacks = 0, g_timings = 0, g_rb_base = 0;
+std::map<std::string, long> g_unmodelled;
+unsigned g_seed = 1;
+std::string g_current;   // name of the launch being checked
+
+[[noreturn]] void fail(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  fprintf(stderr, "HOSTCHECK FAILURE in %s: ", g_current.c_str());
+  vfprintf(stderr, fmt, ap);
+  fprintf(stderr, "\n");
+  va_end(ap);
+  fflush(stderr);
+  abort();
+}
+
+// the registered allocation containing [p, p + bytes), or fail
+void check_range(const void* p, int64_t lo_bytes, int64_t hi_bytes, const char* what) {
+  if (hi_bytes <= lo_bytes) return;
+  const uintptr_t a = (uintptr_t)p + lo_bytes, b = (uintptr_t)p + hi_bytes;
+  if (!p) fail("%s: null pointer accessed at bytes [%lld, %lld)", what, (long long)lo_bytes, (long long)hi_bytes);
+  auto& m = allocs();
+  auto it = m.upper_bound(a);
+  if (it != m.begin()) {
+    --it;
+    if (a >= it->first && b <= it->first + it->second.bytes) return;
+    fail("%s: bytes [%lld, %lld) from %p leave allocation '%s' (%zu bytes at offset %lld)", what,
+         (long long)lo_bytes, (long long)hi_bytes, p, it->second.name.c_str(), it->second.bytes,
+         (long long)((uintptr_t)p - it->first));
+  }
+  fail("%s: bytes [%lld, %lld) from %p are in no registered allocation", what, (long long)lo_bytes,
+       (long long)hi_bytes, p);
+}
+
+// element index range [lo, hi] touched through one pointer
+struct Span {
+  const void* p = nullptr;
+  size_t esz = 8;
+  int64_t lo = INT64_MAX, hi = INT64_MIN;
+  const char* what = "";
+  void touch(int64_t i) {
+    if (i < lo) lo = i;
+    if (i > hi) hi = i;
+  }
+  void check() const {
+    if (hi < lo) return;
+    check_range(p, lo * (int64_t)esz, (hi + 1) * (int64_t)esz, what);
+  }
+};
+
+template <typename T>
+T arg(void** args, int i) {
+  T v;
+  std::memcpy(&v, args[i], sizeof(T));
+  return v;
+}
+
+// ------------------------------------------------------------------ name parsing
+std::string demangle(const std::string& m) {
+  int st = 0;
+  char* d = abi::__cxa_demangle(m.c_str(), nullptr, nullptr, &st);
+  std::string r = st == 0 && d ? d : m;
+  free(d);
+  return r;
+}
+// "void wh::k_fused2d<double, 8, 4, 16, true, false, 0>(wh::FusedDev)" -> base, template args
+void parse(const std::string& dm, std::string& base, std::vector<std::string>& targs) {
+  size_t s = dm.find("wh::");
+  s = s == std::string::npos ? 0 : s + 4;
+  size_t e = dm.find_first_of("<(", s);
+  base = dm.substr(s, e - s);
+  targs.clear();
+  if (e != std::string::npos && dm[e] == '<') {
+    size_t c = dm.find('>', e);
+    std::string in = dm.substr(e + 1, c - e - 1);
+    size_t q = 0;
+    while (q <= in.size()) {
+      size_t k = in.find(',', q);
+      if (k == std::string::npos) k = in.size();
+      std::string t = in.substr(q, k - q);
+      while (!t.empty() && t[0] == ' ') t.erase(0, 1);
+      targs.push_back(t);
+      q = k + 1;
+    }
+  }
+}
+int ti(const std::vector<std::string>& t, size_t i) {
+  if (i >= t.size()) fail("missing template argument %zu", i);
+  if (t[i] == "true") return 1;
+  if (t[i] == "false") return 0;
+  return atoi(t[i].c_str());
+}
+size_t tsize(const std::vector<std::string>& t, size_t i) {
+  if (i >= t.size()) fail("missing template argument %zu", i);
+  return t[i] == "float" ? 4 : 8;
+}
+
+// ------------------------------------------------------------------ kernel models
+int xcd_tile_host(int bid, int nb) {
+  const int xcd = bid & 7, idx = bid >> 3;
+  const int q = nb >> 3, r = nb & 7;
+  return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+void model_fused2d(const std::vector<std::string>& t, dim3 g, dim3 b, void** args) {
+  const size_t TS = tsize(t, 0);
+  const int K = ti(t, 1), R = ti(t, 2), NW = ti(t, 3), VARC = ti(t, 4), FORCE = ti(t, 5), PH = ti(t, 6);
+  const FusedDev a = arg<FusedDev>(args, 0);
+  const int n = a.n;
+  const int64_t P = (int64_t)n + 1;
+  const int TXO = 64 - 2 * K, TYO = NW * R - 2 * K;
+  if (TXO <= 0 || TYO <= 0) fail("tile too small");
+  if ((int)b.x != 64 || (int)b.y != NW || b.z != 1) fail("block (%u,%u,%u) != (64,%d,1)", b.x, b.y, b.z, NW);
+  if (a.gx != (n - 1 + TXO - 1) / TXO || a.gy != (n - 1 + TYO - 1) / TYO) fail("tile grid %d x %d wrong", a.gx, a.gy);
+  const int nb = a.gx * a.gy;
+  if ((int)g.x != nb || g.y != 1 || g.z != 1) fail("grid %u != %d tiles", g.x, nb);
+  if (K > 16) fail("K = %d exceeds the weight arrays", K);
+  const bool first = PH == kPhaseFirst, lastp = PH == kPhaseLast;
+  const bool dirupd = first && a.dr != nullptr;
+  Span cur{a.cur, TS}, prv{a.prev, TS}, kap{a.kap, TS}, fs{a.fs, TS}, V{a.V, 8}, vin{a.vin, 8};
+  Span dr{a.dr, 8}, dp{a.dp, 8}, dsl{a.dslots, 8}, dout{a.dout, 8}, co{a.cur_out, TS}, po{a.prev_out, TS};
+  Span x{a.x, 8}, out{a.out, 8}, part{a.partials, 8};
+  cur.what = "cur"; prv.what = "prev"; kap.what = "kap"; fs.what = "fs"; V.what = "V"; vin.what = "vin";
+  dr.what = "dr"; dp.what = "dp"; dsl.what = "dslots"; dout.what = "dout"; co.what = "cur_out";
+  po.what = "prev_out"; x.what = "x"; out.what = "out"; part.what = "partials";
+  std::vector<char> seen(nb, 0);
+  if (dirupd) dsl.touch(S_BETA);
+  for (int bid = 0; bid < nb; ++bid) {
+    const int tt = xcd_tile_host(bid, nb);
+    if (tt < 0 || tt >= nb || seen[tt]) fail("XCD tile map is not a permutation (block %d -> %d)", bid, tt);
+    seen[tt] = 1;
+    const int tx = tt % a.gx, ty = tt / a.gx;
+    const int x0 = 1 + tx * TXO, y0 = 1 + ty * TYO;
+    const int64_t p_in = (int64_t)y0 * P + x0;
+    for (int wv = 0; wv < NW; ++wv)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int xg = x0 - K + lane, yb = y0 - K + wv * R;
+        const bool xin = xg >= 1 && xg <= n - 1;
+        const bool xout = lane >= K && lane < 64 - K && xin;
+        for (int r = 0; r < R; ++r) {
+          const int y = yb + r;
+          const bool in = xin && y >= 1 && y <= n - 1;
+          const int64_t p = (int64_t)y * P + xg;
+          const int ry = wv * R + r;
+          const bool o = in && xout && ry >= K && ry < NW * R - K;
+          if (!first && in) { cur.touch(p); prv.touch(p); }
+          if (o && !first) V.touch(p);
+          if (VARC && in) { kap.touch(p); kap.touch(p - 1); kap.touch(p + 1); kap.touch(p - P); kap.touch(p + P); }
+          if (FORCE && in) fs.touch(p);
+          if (first) {
+            const int64_t ps = in ? p : p_in;
+            if (dirupd) { dr.touch(ps); dp.touch(ps); if (o) dout.touch(p); }
+            else if (a.vin) vin.touch(ps);
+          }
+          if (PH != kPhaseMid && xg >= 0 && xg <= n && y >= 0 && y <= n && (xg == 0 || xg == n || y == 0 || y == n)) {
+            if (first || a.last == M_LAST_V) V.touch(p); else out.touch(p);
+          }
+          if (!lastp) {
+            if (o) { co.touch(p); po.touch(p); V.touch(p); }
+          } else {
+            if (a.last != M_LAST_V) x.touch(o ? p : p_in);
+            if (o) { if (a.last == M_LAST_V) V.touch(p); else out.touch(p); }
+          }
+        }
+        if (lastp && a.last != M_LAST_V && wv == 0 && lane == 0) part.touch(bid);
+      }
+  }
+  for (Span* s : {&cur, &prv, &kap, &fs, &V, &vin, &dr, &dp, &dsl, &dout, &co, &po, &x, &out, &part}) s->check();
+}
+
+void model_step2d(const std::vector<std::string>& t, dim3 g, dim3 b, void** args) {
+  const size_t TS = tsize(t, 0);
+  const int MODE = ti(t, 1), VARC = ti(t, 2), FORCE = ti(t, 3);
+  const bool INC = TS == 4;
+  const StepArgs a = arg<StepArgs>(args, 0);
+  const int n = a.n;
+  const int64_t P = (int64_t)n + 1;
+  if (b.x != 64 || b.y != 4) fail("block shape");
+  if ((int)g.x != (n - 1 + 63) / 64 || (int)g.y != (n - 1 + 15) / 16) fail("grid (%u,%u)", g.x, g.y);
+  Span cur{a.cur, TS}, prv{a.prev, TS}, kap{a.kap, TS}, fs{a.fs, TS}, V{a.V, 8}, x{a.x, 8}, out{a.out, 8};
+  Span cn{a.cur_next, TS}, part{a.partials, 8};
+  cur.what = "cur"; prv.what = "prev"; kap.what = "kap"; fs.what = "fs"; V.what = "V"; x.what = "x";
+  out.what = "out"; cn.what = "cur_next"; part.what = "partials";
+  for (unsigned by = 0; by < g.y; ++by)
+    for (unsigned bx = 0; bx < g.x; ++bx) {
+      for (int ty = 0; ty < 4; ++ty)
+        for (int tx = 0; tx < 64; ++tx) {
+          const int i = 1 + bx * 64 + tx;
+          const int j0 = 1 + (by * 4 + ty) * 4;
+          if (!(i < n && j0 < n)) continue;
+          const int jend = std::min(j0 + 4, n);
+          int64_t p = (int64_t)j0 * P + i;
+          cur.touch(p - P); cur.touch(p);
+          if (VARC) { kap.touch(p - P); kap.touch(p); }
+          for (int j = j0; j < jend; ++j, p += P) {
+            cur.touch(p + P); cur.touch(p - 1); cur.touch(p + 1); prv.touch(p);
+            if (VARC) { kap.touch(p + P); kap.touch(p - 1); kap.touch(p + 1); }
+            if (FORCE) fs.touch(p);
+            if (INC && MODE == M_MID) { prv.touch(p); cn.touch(p); V.touch(p); continue; }
+            switch (MODE) {
+              case M_MID: prv.touch(p); V.touch(p); break;
+              case M_LAST_V: V.touch(p); break;
+              case M_LAST_AQ: case M_LAST_EQ: case M_LAST_FPI: V.touch(p); x.touch(p); out.touch(p); break;
+              default: fail("mode %d", MODE);
+            }
+          }
+        }
+      if (MODE == M_LAST_AQ || MODE == M_LAST_FPI || MODE == M_LAST_EQ) part.touch(by * g.x + bx);
+    }
+  for (Span* s : {&cur, &prv, &kap, &fs, &V, &x, &out, &cn, &part}) s->check();
+}
+
+void model_first(const std::vector<std::string>& t, dim3 g, dim3, void** args) {
+  const size_t TS = tsize(t, 0);
+  const int DIM = ti(t, 1), VARC = ti(t, 2), FORCE = ti(t, 3);
+  const StepArgs a = arg<StepArgs>(args, 0);
+  const int n = a.n;
+  const int64_t P = (int64_t)n + 1, N = DIM == 2 ? P * P : P * P * P;
+  if ((int64_t)g.x * 256 < N) fail("grid covers %lld of %lld nodes", (long long)g.x * 256, (long long)N);
+  Span w0{a.prev, TS}, w1{a.cur_out, TS}, z0{a.zb0, TS}, z1{a.zb1, TS}, V{a.V, 8}, v{a.vin, 8}, kap{a.kap, TS},
+      fs{a.fs, TS};
+  w0.what = "prev"; w1.what = "cur_out"; z0.what = "zb0"; z1.what = "zb1"; V.what = "V"; v.what = "vin";
+  kap.what = "kap"; fs.what = "fs";
+  for (int64_t p = 0; p < N; ++p) {
+    const int i = (int)(p % P), j = (int)((p / P) % P), k = DIM == 3 ? (int)(p / (P * P)) : 1;
+    const bool interior = i > 0 && i < n && j > 0 && j < n && (DIM == 2 || (k > 0 && k < n));
+    w0.touch(p); w1.touch(p); V.touch(p);
+    if (!interior) { if (a.zb0) z0.touch(p); if (a.zb1) z1.touch(p); continue; }
+    if (FORCE) fs.touch(p);
+    if (!a.vin) continue;
+    v.touch(p);
+    if (i > 1) v.touch(p - 1);
+    if (i < n - 1) v.touch(p + 1);
+    if (j > 1) v.touch(p - P);
+    if (j < n - 1) v.touch(p + P);
+    if (DIM == 3) { if (k > 1) v.touch(p - P * P); if (k < n - 1) v.touch(p + P * P); }
+    if (VARC) {
+      kap.touch(p); kap.touch(p - 1); kap.touch(p + 1); kap.touch(p - P); kap.touch(p + P);
+      if (DIM == 3) { kap.touch(p - P * P); kap.touch(p + P * P); }
+    }
+  }
+  for (Span* s : {&w0, &w1, &z0, &z1, &V, &v, &kap, &fs}) s->check();
+}
+
+void model_fwd_out2d(dim3 g, dim3 b, void** args) {
+  const double* cur = arg<const double*>(args, 0);
+  const double* prev = arg<const double*>(args, 1);
+  double* out = arg<double*>(args, 2);
+  const double* kap = arg<const double*>(args, 3);
+  const double* fs = arg<const double*>(args, 4);
+  const int first = arg<int>(args, 6), n = arg<int>(args, 7);
+  const int64_t P = (int64_t)n + 1;
+  Span C{cur, 8, INT64_MAX, INT64_MIN, "cur"}, Pv{prev, 8, INT64_MAX, INT64_MIN, "prev"},
+      O{out, 8, INT64_MAX, INT64_MIN, "out"}, Kp{kap, 8, INT64_MAX, INT64_MIN, "kap"},
+      F{fs, 8, INT64_MAX, INT64_MIN, "fs"};
+  if (b.x != 64 || b.y != 4) fail("block shape");
+  for (unsigned by = 0; by < g.y; ++by)
+    for (unsigned bx = 0; bx < g.x; ++bx)
+      for (int ty = 0; ty < 4; ++ty)
+        for (int tx = 0; tx < 64; ++tx) {
+          const int i = 1 + bx * 64 + tx, j = 1 + by * 4 + ty;
+          if (i >= n || j >= n) continue;
+          const int64_t p = (int64_t)j * P + i;
+          for (int64_t q : {p, p - 1, p + 1, p - P, p + P}) { C.touch(q); Kp.touch(q); }
+          if (fs) F.touch(p);
+          if (!first) Pv.touch(p);
+          O.touch(p);
+        }
+  if ((int)g.x * 64 < n - 1 || (int)g.y * 4 < n - 1) fail("grid does not cover the interior");
+  for (Span* s : {&C, &Pv, &O, &Kp, &F}) s->check();
+}
+
+void model_adj_step2d(dim3 g, dim3 b, void** args) {
+  const double* lam1 = arg<const double*>(args, 0);
+  const double* lam2 = arg<const double*>(args, 1);
+  double* lout = arg<double*>(args, 2);
+  const double* W = arg<const double*>(args, 3);
+  const double* kap = arg<const double*>(args, 4);
+  const double* z = arg<const double*>(args, 5);
+  double* grad = arg<double*>(args, 8);
+  const int do_lam = arg<int>(args, 9), n = arg<int>(args, 10);
+  const int64_t P = (int64_t)n + 1;
+  Span L1{lam1, 8, INT64_MAX, INT64_MIN, "lam1"}, L2{lam2, 8, INT64_MAX, INT64_MIN, "lam2"},
+      LO{lout, 8, INT64_MAX, INT64_MIN, "lam_out"}, WW{W, 8, INT64_MAX, INT64_MIN, "W"},
+      Kp{kap, 8, INT64_MAX, INT64_MIN, "kap"}, Z{z, 8, INT64_MAX, INT64_MIN, "z"},
+      G{grad, 8, INT64_MAX, INT64_MIN, "grad"};
+  if (b.x != 64 || b.y != 4) fail("block shape");
+  for (unsigned by = 0; by < g.y; ++by)
+    for (unsigned bx = 0; bx < g.x; ++bx)
+      for (int ty = 0; ty < 4; ++ty)
+        for (int tx = 0; tx < 64; ++tx) {
+          const int i = bx * 64 + tx, j = by * 4 + ty;
+          if (i > n || j > n) continue;
+          const int64_t p = (int64_t)j * P + i;
+          L1.touch(p); WW.touch(p); G.touch(p);
+          if (i > 0) { L1.touch(p - 1); WW.touch(p - 1); }
+          if (i < n) { L1.touch(p + 1); WW.touch(p + 1); }
+          if (j > 0) { L1.touch(p - P); WW.touch(p - P); }
+          if (j < n) { L1.touch(p + P); WW.touch(p + P); }
+          if (do_lam && i > 0 && i < n && j > 0 && j < n) {
+            for (int64_t q : {p, p - 1, p + 1, p - P, p + P}) Kp.touch(q);
+            L2.touch(p); Z.touch(p); LO.touch(p);
+          }
+        }
+  if ((int)g.x * 64 < n + 1 || (int)g.y * 4 < n + 1) fail("grid does not cover the grid");
+  for (Span* s : {&L1, &L2, &LO, &WW, &Kp, &Z, &G}) s->check();
+}
+
+void vec(const void* p, int64_t count, size_t esz, const char* what) {
+  if (p && count > 0) check_range(p, 0, count * (int64_t)esz, what);
+}
+
+bool model_generic(const std::string& base, const std::vector<std::string>& t, dim3 g, dim3, void** args) {
+  const int64_t G = g.x;
+  if (base == "k_prep") {
+    const size_t TS = tsize(t, 0);
+    const int64_t N = arg<int64_t>(args, 6);
+    const double* c2 = arg<const double*>(args, 0);
+    const double* f = arg<const double*>(args, 1);
+    vec(c2, N, 8, "c2"); vec(f, N, 8, "f");
+    if (c2) vec(arg<void*>(args, 2), N, TS, "kap");
+    if (f) vec(arg<void*>(args, 3), N, TS, "fs");
+  } else if (base == "k_zero_boundary") {
+    vec(arg<void*>(args, 0), arg<int64_t>(args, 3), 8, "u");
+  } else if (base == "k_defect") {
+    const int64_t N = arg<int64_t>(args, 7);
+    vec(arg<void*>(args, 0), N, 8, "v"); vec(arg<void*>(args, 1), N, 8, "kap");
+    vec(arg<void*>(args, 4), N, tsize(t, 0), "fs");
+  } else if (base == "k_max_partials") {
+    vec(arg<void*>(args, 0), arg<int64_t>(args, 1), 8, "a"); vec(arg<void*>(args, 2), G, 8, "partials");
+  } else if (base == "k_max_finalize") {
+    vec(arg<void*>(args, 0), arg<int>(args, 1), 8, "partials"); vec(arg<void*>(args, 2), 1, 8, "out");
+  } else if (base == "k_dot_partials") {
+    const int64_t N = arg<int64_t>(args, 2);
+    vec(arg<void*>(args, 0), N, 8, "a"); vec(arg<void*>(args, 1), N, 8, "b");
+    vec(arg<void*>(args, 3), G, 8, "partials");
+  } else if (base == "k_reduce") {
+    vec(arg<void*>(args, 0), arg<int>(args, 1), 8, "partials");
+    const int dst = arg<int>(args, 3), mode = arg<int>(args, 4);
+    vec(arg<void*>(args, 2), mode == 0 ? dst + 1 : 4, 8, "slots");
+  } else if (base == "k_set_beta") {
+    vec(arg<void*>(args, 0), std::max(arg<int>(args, 1), 3) + 1, 8, "slots");
+  } else if (base == "k_cg_update1") {
+    const int64_t N = arg<int64_t>(args, 5);
+    for (int i = 0; i < 4; ++i) vec(arg<void*>(args, i), N, 8, "vector");
+    vec(arg<void*>(args, 4), 4, 8, "slots"); vec(arg<void*>(args, 6), G, 8, "partials");
+    vec(arg<void*>(args, 7), arg<int>(args, 8), 8, "pq_parts");
+  } else if (base == "k_cg_update2") {
+    const int64_t N = arg<int64_t>(args, 3);
+    vec(arg<void*>(args, 0), N, 8, "p"); vec(arg<void*>(args, 1), N, 8, "r"); vec(arg<void*>(args, 2), 4, 8, "slots");
+  } else if (base == "k_cg_update2_to") {
+    const int64_t N = arg<int64_t>(args, 4);
+    for (int i = 0; i < 3; ++i) vec(arg<void*>(args, i), N, 8, "vector");
+    vec(arg<void*>(args, 3), 4, 8, "slots");
+  } else if (base == "k_axpy_slot") {
+    const int64_t N = arg<int64_t>(args, 5);
+    vec(arg<void*>(args, 0), N, 8, "y"); vec(arg<void*>(args, 1), N, 8, "x");
+    vec(arg<void*>(args, 2), arg<int>(args, 3) + 1, 8, "slots");
+  } else if (base == "k_axpy") {
+    const int64_t N = arg<int64_t>(args, 3);
+    vec(arg<void*>(args, 0), N, 8, "y"); vec(arg<void*>(args, 1), N, 8, "x");
+  } else if (base == "k_lincomb3") {
+    const int64_t N = arg<int64_t>(args, 7);
+    for (int i : {0, 2, 4, 6}) vec(arg<void*>(args, i), N, 8, "vector");
+  } else if (base == "k_scale_copy") {
+    const int64_t N = arg<int64_t>(args, 4);
+    vec(arg<void*>(args, 0), N, 8, "y"); vec(arg<void*>(args, 1), N, 8, "x");
+    vec(arg<void*>(args, 2), arg<int>(args, 3) + 1, 8, "slots");
+  } else if (base == "k_sub") {
+    const int64_t N = arg<int64_t>(args, 3);
+    for (int i = 0; i < 3; ++i) vec(arg<void*>(args, i), N, 8, "vector");
+  } else if (base == "k_copy") {
+    const int64_t N = arg<int64_t>(args, 2);
+    for (int i = 0; i < 2; ++i) vec(arg<void*>(args, i), N, 8, "vector");
+  } else if (base == "k_gemv_acc") {
+    const int64_t ldv = arg<int64_t>(args, 2), N = arg<int64_t>(args, 5);
+    const int k = arg<int>(args, 3);
+    vec(arg<void*>(args, 0), N, 8, "x");
+    if (k > 0) vec(arg<void*>(args, 1), (k - 1) * ldv + N, 8, "V");
+    vec(arg<void*>(args, 4), k, 8, "y");
+  } else if (base == "k_helm_res") {
+    const int n = arg<int>(args, 5), dim = arg<int>(args, 6);
+    const int64_t P = n + 1, N = dim == 2 ? P * P : P * P * P;
+    for (int i = 0; i < 3; ++i) vec(arg<void*>(args, i), N, 8, "vector");
+    vec(arg<void*>(args, 8), G, 8, "pr"); vec(arg<void*>(args, 9), G, 8, "pf");
+  } else if (base == "k_misfit") {
+    const int64_t* idx = arg<const int64_t*>(args, 1);
+    const int nrec = arg<int>(args, 3);
+    vec(idx, nrec, 8, "rec_idx"); vec(arg<void*>(args, 2), nrec, 8, "d");
+    vec(arg<void*>(args, 5), 1, 8, "out");
+    Span u{arg<const double*>(args, 0), 8, INT64_MAX, INT64_MIN, "u"}, gg{arg<double*>(args, 4), 8, INT64_MAX, INT64_MIN, "g"};
+    for (int k = 0; k < nrec; ++k) { u.touch(idx[k]); gg.touch(idx[k]); }
+    u.check(); gg.check();
+  } else if (base == "k_check_idx") {
+    vec(arg<void*>(args, 0), arg<int>(args, 1), 8, "rec_idx"); vec(arg<void*>(args, 3), 1, 4, "bad");
+  } else {
+    return false;
+  }
+  return true;
+}
+
+void check_launch(const void* fn, dim3 g, dim3 b, void** args) {
+  ++g_launches;
+  auto it = kernels().find(fn);
+  if (it == kernels().end()) fail("launch of an unregistered kernel handle %p", fn);
+  g_current = demangle(it->second);
+  if (g.x == 0 || g.y == 0 || g.z == 0) fail("empty grid (%u,%u,%u)", g.x, g.y, g.z);
+  if ((uint64_t)b.x * b.y * b.z > 1024 || b.x == 0) fail("block (%u,%u,%u)", b.x, b.y, b.z);
+  std::string base;
+  std::vector<std::string> t;
+  parse(g_current, base, t);
+  bool done = true;
+  if (base == "k_fused2d") model_fused2d(t, g, b, args);
+  else if (base == "k_step2d") model_step2d(t, g, b, args);
+  else if (base == "k_first") model_first(t, g, b, args);
+  else if (base == "k_fwd_out2d") model_fwd_out2d(g, b, args);
+  else if (base == "k_adj_step2d") model_adj_step2d(g, b, args);
+  else done = model_generic(base, t, g, b, args);
+  if (done) ++g_modelled;
+  else ++g_unmodelled[base];
+  g_current.clear();
+}
+
+// ------------------------------------------------------------------ launch configuration
+struct Cfg {
+  dim3 g, b;
+  size_t sh;
+  hipStream_t s;
+};
+std::vector<Cfg>& cfgs() {
+  static std::vector<Cfg> v;
+  return v;
+}
+
+double synth(int i, long k) {
+  // slots: 0 r.r, 1 p.Ap, 2 alpha, 3 beta, 4 scratch (true residual), 5 ||b||^2, 6 scratch
+  const double d = std::pow(0.35, (double)k);
+  switch (i) {
+    case 0: case 4: return d;
+    case 1: case 2: case 5: case 6: return 1.0;
+    case 3: return 0.5;
+    default: return 0.1 * d + 1e-3 * (i % 7);
+  }
+}
+
+struct Ev {
+  int dummy;
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------- program interface
+extern "C" {
+void hostcheck_register(const void* p, size_t bytes, const char* name) {
+  allocs()[(uintptr_t)p] = Alloc{bytes, name ? name : "?"};
+}
+void hostcheck_unregister(const void* p) { allocs().erase((uintptr_t)p); }
+void hostcheck_seed(unsigned s) { g_seed = s; }
+// the synthetic residual starts again from 1 (call before each solve)
+void hostcheck_restart_residual(void) { g_rb_base = g_readbacks; }
+void hostcheck_report(void) {
+  fprintf(stdout, "hostcheck: %ld launches, %ld checked by a model, %ld read-backs, %ld timings\n", g_launches,
+          g_modelled, g_readbacks, g_timings);
+  for (auto& kv : g_unmodelled) fprintf(stdout, "hostcheck: not modelled: %s x%ld\n", kv.first.c_str(), kv.second);
+}
+}
+
+// ---------------------------------------------------------------------- HIP runtime stand-in
+extern "C" {
+void** __hipRegisterFatBinary(const void*) {
+  static void* h = nullptr;
+  return &h;
+}
+void __hipRegisterFunction(void**, const void* hostFunction, char* deviceFunction, const char*, unsigned int,
+                           uint3*, uint3*, dim3*, dim3*, int*) {
+  kernels()[hostFunction] = deviceFunction;
+}
+void __hipUnregisterFatBinary(void**) {}
+}
+
+hipError_t __hipPushCallConfiguration(dim3 g, dim3 b, size_t sh, hipStream_t s) {
+  cfgs().push_back(Cfg{g, b, sh, s});
+  return hipSuccess;
+}
+hipError_t __hipPopCallConfiguration(dim3* g, dim3* b, size_t* sh, hipStream_t* s) {
+  if (cfgs().empty()) fail("pop without push");
+  const Cfg c = cfgs().back();
+  cfgs().pop_back();
+  *g = c.g;
+  *b = c.b;
+  *sh = c.sh;
+  *s = c.s;
+  return hipSuccess;
+}
+hipError_t hipLaunchKernel(const void* f, dim3 g, dim3 b, void** args, size_t, hipStream_t) {
+  check_launch(f, g, b, args);
+  return hipSuccess;
+}
+
+hipError_t hipGetDeviceCount(int* c) {
+  *c = 1;
+  return hipSuccess;
+}
+hipError_t hipSetDevice(int d) { return d == 0 ? hipSuccess : hipErrorInvalidDevice; }
+hipError_t hipGetDevice(int* d) {
+  *d = 0;
+  return hipSuccess;
+}
+hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t a, int) {
+  *v = a == hipDeviceAttributeMultiprocessorCount ? 256 : 1;
+  return hipSuccess;
+}
+hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, const void*, int, size_t) {
+  *n = 2;
+  return hipSuccess;
+}
+hipError_t hipHostMalloc(void** p, size_t bytes, unsigned int) {
+  *p = malloc(bytes);
+  if (!*p) return hipErrorOutOfMemory;
+  g_pinned = (uintptr_t)*p;
+  g_pinned_bytes = bytes;
+  hostcheck_register(*p, bytes, "pinned host block");
+  return hipSuccess;
+}
+hipError_t hipHostFree(void* p) {
+  hostcheck_unregister(p);
+  free(p);
+  return hipSuccess;
+}
+hipError_t hipMemcpyAsync(void* dst, const void* src, size_t bytes, hipMemcpyKind kind, hipStream_t) {
+  if (!bytes) return hipSuccess;
+  g_current = "hipMemcpyAsync";
+  // device-side ends only: host ends (pageable vectors) are checked by the sanitizer
+  if (kind != hipMemcpyDeviceToHost) check_range(dst, 0, (int64_t)bytes, "copy destination");
+  if (kind != hipMemcpyHostToDevice) check_range(src, 0, (int64_t)bytes, "copy source");
+  g_current.clear();
+  std::memcpy(dst, src, bytes);
+  if (kind == hipMemcpyDeviceToHost && (uintptr_t)dst == g_pinned && bytes % 8 == 0) {
+    ++g_readbacks;
+    double* h = (double*)dst;
+    for (size_t i = 0; i < bytes / 8; ++i) h[i] = synth((int)i, g_readbacks - g_rb_base);
+  }
+  return hipSuccess;
+}
+hipError_t hipMemcpy2DAsync(void* dst, size_t dpitch, const void* src, size_t spitch, size_t width, size_t height,
+                            hipMemcpyKind, hipStream_t) {
+  g_current = "hipMemcpy2DAsync";
+  for (size_t r = 0; r < height; ++r) {
+    check_range((char*)dst + r * dpitch, 0, (int64_t)width, "2D copy destination");
+    check_range((const char*)src + r * spitch, 0, (int64_t)width, "2D copy source");
+    std::memcpy((char*)dst + r * dpitch, (const char*)src + r * spitch, width);
+  }
+  g_current.clear();
+  return hipSuccess;
+}
+hipError_t hipMemsetAsync(void* dst, int v, size_t bytes, hipStream_t) {
+  if (!bytes) return hipSuccess;
+  g_current = "hipMemsetAsync";
+  check_range(dst, 0, (int64_t)bytes, "fill destination");
+  g_current.clear();
+  std::memset(dst, v, bytes);
+  return hipSuccess;
+}
+hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+hipError_t hipGetLastError(void) { return hipSuccess; }
+const char* hipGetErrorString(hipError_t) { return "stub"; }
+hipError_t hipEventCreate(hipEvent_t* e) {
+  *e = (hipEvent_t) new Ev{0};
+  return hipSuccess;
+}
+hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { return hipEventCreate(e); }
+hipError_t hipEventDestroy(hipEvent_t e) {
+  delete (Ev*)e;
+  return hipSuccess;
+}
+hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
+hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
+hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) {
+  // deterministic, seed-dependent "timings" so that the autotuner's choices vary by seed
+  ++g_timings;
+  const unsigned h = (unsigned)(g_timings * 2654435761u) ^ (g_seed * 40503u);
+  *ms = 0.5f + (float)(h % 1000u) / 1000.0f;
+  return hipSuccess;
+}
+hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned) {
+  *s = (hipStream_t) new Ev{1};
+  return hipSuccess;
+}
+hipError_t hipStreamDestroy(hipStream_t s) {
+  delete (Ev*)s;
+  return hipSuccess;
+}
+hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned) { return hipSuccess; }
+hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode) { return hipSuccess; }
+hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t* g) {
+  *g = (hipGraph_t) new Ev{2};
+  return hipSuccess;
+}
+hipError_t hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t, hipGraphNode_t*, char*, size_t) {
+  *e = (hipGraphExec_t) new Ev{3};
+  return hipSuccess;
+}
+hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { return hipSuccess; }
+hipError_t hipGraphExecDestroy(hipGraphExec_t e) {
+  delete (Ev*)e;
+  return hipSuccess;
+}
+hipError_t hipGraphDestroy(hipGraph_t g) {
+  delete (Ev*)g;
+  return hipSuccess;
+}

@@ -130,3 +130,47 @@ def test_invalid_arguments_rejected_on_host():
     p.solver = nat.WH_GMRES
     b1 = lib.wh_workspace_bytes(C.byref(g), C.byref(p), None)
     assert b1 > b0 > 0
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C compiler's size and field offsets
+    (a shorter mirror would let the library write past a Python-owned buffer)."""
+    from paper_2606_31842_amd import _native as nat
+    structs = {"wh_grid": nat.WhGrid, "wh_params": nat.WhParams, "wh_deflation": nat.WhDeflation,
+               "wh_info": nat.WhInfo, "wh_problem": nat.WhProblem}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln.strip():
+            c, f, v = ln.split()
+            got[(c, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_entry_points_report_errors_without_context():
+    """Host helpers return an error status with a message (nothing aborts or throws across the
+    ABI); a failure without a context is reported by wh_last_error(NULL)."""
+    from paper_2606_31842_amd import _native as nat
+    lib = nat.load()
+    g = nat.WhGrid(2, 2, 2)      # n < 4: rejected
+    p = nat.WhParams()
+    lib.wh_params_default(C.byref(p))
+    m, nt = C.c_int32(), C.c_int32()
+    dt, om = C.c_double(), C.c_double()
+    st = lib.wh_time_params(C.byref(g), C.byref(p), 1.0, C.byref(m), C.byref(nt), C.byref(dt), C.byref(om))
+    assert st == nat.WH_EINVAL
+    assert b"n must be" in lib.wh_last_error(None)
+    assert lib.wh_status_string(nat.WH_EHOST) == b"host-side failure inside the library"
