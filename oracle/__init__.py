@@ -20,8 +20,12 @@ krylov          FPI, CG, DCG, GMRES(m), augmented GMRES, augmented BiCGStab
 devd            direct eigenvector deflation (forcing deflation + inflation)
 adjoint         misfit, direct-solve adjoint gradient, time-domain VJP, FD check
 
-Parity status: every public function is pinned by a test in
-``tests/test_oracle_*.py`` against a closed form, an invariant, brute force or
-a value the paper prints; none is "parity unpinned".
+Parity status: every public function is pinned by a ``-m "not gpu"`` test in
+``tests/test_oracle_*.py`` against a closed form, an invariant, brute force, a
+library routine applied to an independently built object (dense A from wave
+solves, sparse LU) or a value the paper prints.  Among them: devd_solve in both
+branches (CG; FPI with and without deflated iterates, against the direct solve
+and the deflated rate of eq. WaveHoltzFPIconvergence) and transfer.kappa (the
+2-norm condition number of the dense A).  No function is "parity unpinned".
 """
 from . import discretization, timeparams, wavesolve, transfer, modes, krylov, devd, adjoint  # noqa: F401

@@ -24,10 +24,6 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 
-def n_unknowns(dim: int, n: int) -> int:
-    return (n - 1) ** dim
-
-
 def to_interior(a: np.ndarray) -> np.ndarray:
     """Nodal array (n+1,)*dim -> flat interior vector (x fastest)."""
     return np.ascontiguousarray(a[(slice(1, -1),) * a.ndim]).reshape(-1)
@@ -102,7 +98,7 @@ def direct_solve(L: sp.spmatrix, omega: float, f: np.ndarray) -> np.ndarray:
 
 
 def helmholtz_residual(L, omega, U, f) -> float:
-    """||f - (L_h + omega^2) U|| / ||f||."""
+    """||f - (L_h + omega^2) U|| / ||f|| (eq. discreteHelmholtz), interior vectors."""
     r = f - (L @ U + omega ** 2 * U)
     return float(np.linalg.norm(r) / np.linalg.norm(f))
 

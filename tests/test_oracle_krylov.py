@@ -84,6 +84,51 @@ def test_fpi_rate_is_max_abs_beta():
     assert rho_d < rho and abs(obs - rho_d) < 5e-3
 
 
+@pytest.mark.parametrize("deflate_iterates", [False, True])
+def test_devd_fpi_matches_direct_solve_at_the_deflated_rate(deflate_iterates):
+    # Algorithm 2 around the fixed-point iteration (devd_solve(method="fpi")): the inflated
+    # result is the discrete Helmholtz solution, the iterates stay orthogonal to W, and the
+    # observed rate is max |beta_h| over the modes that are not deflated
+    # (eq. WaveHoltzFPIconvergence applied to the deflated problem).
+    n, omega = 16, 9.0
+    L, tp, f = setup(2, n, omega)
+    U = disc.direct_solve(L, omega, f)
+    ev = np.linalg.eigvalsh(L.toarray())
+    beta = np.abs(tr.beta_discrete(-ev, tp))
+    sel, lam2 = modes.select_modes(2, n, omega, 5)
+    W = modes.mode_matrix(2, n, sel)
+    rest = list(beta)
+    for bm in np.abs(tr.beta_discrete(lam2, tp)):
+        rest.remove(min(rest, key=lambda x: abs(x - bm)))
+    rho_d = max(rest)
+    assert rho_d < beta.max()
+    x, info = devd.devd_solve(L, f, tp, W, lam2, method="fpi", tol=1e-12, maxit=2000,
+                              deflate_iterates=deflate_iterates)
+    assert _err(x, U) < 1e-10
+    r = np.array(info["res"])
+    k = len(r) - 1
+    obs = (r[k] / r[k - 20]) ** (1 / 20)
+    assert abs(obs - rho_d) < 5e-3, (obs, rho_d)
+    # the deflated part of the solution is orthogonal to W; inflation restores W^T U
+    v = devd.deflate(W, x)
+    assert np.abs(W.T @ v).max() < 1e-13 * np.abs(x).max()
+    assert np.abs(W.T @ x - W.T @ U).max() < 1e-10 * np.abs(W.T @ U).max()
+
+
+def test_kappa_equals_condition_number_of_dense_A():
+    # kappa_A = max|mu| / min|mu| over the spectrum {1 - beta_h(lambda)} equals the 2-norm
+    # condition number of the dense A = I - S_h assembled column by column from wave solves
+    for n, omega, c2 in [(10, 7.3, None), (9, 5.1, varc2(2, 9))]:
+        L, tp, _ = setup(2, n, omega, c2=c2)
+        A = ws.dense_A(L, tp)
+        ev = np.linalg.eigvalsh(L.toarray())
+        k_formula = tr.kappa(tr.mu_discrete(-ev, tp))
+        k_dense = np.linalg.cond(A, 2)
+        assert abs(k_formula - k_dense) < 1e-9 * k_dense, (k_formula, k_dense)
+        # and kappa of the eigenvalues of the dense matrix itself
+        assert abs(tr.kappa(np.linalg.eigvalsh(0.5 * (A + A.T))) - k_dense) < 1e-9 * k_dense
+
+
 # ------------------------------------------------------------ CG / DCG
 def test_beta_h_overshoot_window_is_small():
     # With the time-corrected frequency, beta_h peaks at 1 + O(dt^4) slightly below
