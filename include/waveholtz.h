@@ -226,6 +226,23 @@ wh_status wh_apply_filter(wh_ctx* ctx, const wh_grid* grid, const double* c2, co
                           const double* v_in, double* v_out, const wh_params* params,
                           void* ws, size_t ws_bytes, wh_info* info);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): wh_apply_filter without a workspace argument.  The
+ * state pairs, scaled coefficients, partial sums and scalars live in a fixed device array
+ * inside the library (64 MiB, one copy per GPU, held until the process ends; its address is
+ * looked up once per device by wh_create).  Grids whose buffers exceed it are rejected with
+ * WH_EWORKSPACE and the size they need (2D: up to about 1024^2 cells; 3D: about 100^3).  No
+ * device or pinned memory is allocated and no timing runs: the steps per launch are
+ * params->k_fuse / k_shape, else the autotuner's cached choice for this grid from an earlier
+ * call of another entry point, else 8 (2D) or 3 (3D) with the default block shape.  With
+ * params->c_max > 0 the call is asynchronous on the context stream and host-synchronisation
+ * free; c_max = 0 reads the computed maximum of c back.  Every call on one GPU shares that
+ * GPU's array and the array keeps the last call's contents: calls that overlap on one GPU
+ * (two streams, two threads, two contexts) race.  v_in, v_out, f, c2 as in wh_apply_filter. */
+wh_status wh_apply_filter_noalloc(wh_ctx* ctx, const wh_grid* grid, const double* c2, const double* f,
+                                  const double* v_in, double* v_out, const wh_params* params,
+                                  wh_info* info);
+
 /* Solve A u = b, b = Pi_h(0; f), by params->solver; the fixed point is the discrete
  * Helmholtz solution (L_h + omega^2) u = f (Sections 2.1-2.2).  u: device nodal, in:
  * initial guess, out: solution.  defl (exact eigenvectors) is required for WH_DCG

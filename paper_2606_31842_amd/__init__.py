@@ -255,6 +255,26 @@ def apply_filter(v, omega, f=None, c2=None, out=None, **kw):
     return out, info.as_dict()
 
 
+def apply_filter_noalloc(v, omega, f=None, c2=None, out=None, **kw):
+    """Pi_h(v; f) through wh_apply_filter_noalloc (no workspace; the library's fixed device
+    scratch).  Returns (out, info)."""
+    torch = _torch()
+    dim = v.dim()
+    n = v.shape[0] - 1
+    _nodal(v, dim, n, "v"); _nodal(f, dim, n, "f"); _nodal(c2, dim, n, "c2")
+    lib = nat.load()
+    ctx = context(v.device.index)
+    order = kw.pop("order", 2)
+    p = params(omega, **kw)
+    g = _grid(dim, n, order)
+    out = torch.empty_like(v) if out is None else _nodal(out, dim, n, "out")
+    info = nat.WhInfo()
+    st = lib.wh_apply_filter_noalloc(ctx, C.byref(g), _ptr(c2), _ptr(f), _ptr(v), _ptr(out), C.byref(p),
+                                     C.byref(info))
+    _check(lib, ctx, st)
+    return out, info.as_dict()
+
+
 def solve(f, omega, c2=None, u0=None, defl: Optional[Deflation] = None, workspace=None, **kw):
     """Solve the WaveHoltz system for L u + omega^2 u = f.  Returns (u, info)."""
     torch = _torch()

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <cmath>
 #include <cstdio>
@@ -224,6 +225,30 @@ Layout make_layout(const wh_grid& g, const wh_params& P, const wh_deflation* def
     L.ones = take(L, 8 * (size_t)nd);
     L.tsum = take(L, 8 * 2 * (size_t)nrow);   // factored: per-term sums and coefficients
   }
+  return L;
+}
+
+// The buffers one wave solve needs when its accumulator is the caller's output: the two
+// state pairs, the scaled coefficients in each stepping precision, partial sums and scalars.
+Layout make_filter_layout(const wh_grid& g, const wh_params& P) {
+  Layout L;
+  const int64_t N = nodal_count(g.dim, g.n);
+  L.N = N;
+  L.Wa = take(L, 8 * N);
+  L.Wb = take(L, 8 * N);
+  L.Wc = take(L, 8 * N);
+  L.Wd = take(L, 8 * N);
+  L.kap64 = take(L, 8 * N);
+  L.fs64 = take(L, 8 * N);
+  if (P.precision == WH_MIXED) {
+    L.kap32 = take(L, 4 * N);
+    L.fs32 = take(L, 4 * N);
+  }
+  L.npart = kReduceBlocks;
+  L.partials = take(L, 8 * (size_t)kReduceBlocks);
+  L.partials2 = take(L, 8 * (size_t)kReduceBlocks);
+  L.nslots = S_NSLOTS_FIXED;
+  L.slots = take(L, 8 * (size_t)L.nslots);
   return L;
 }
 
@@ -655,6 +680,16 @@ int autotune_k(wh_ctx* ctx, const WaveOp& op, bool force, int k_fixed = 0) {
   (void)hipEventDestroy(e1);
   ctx->ktune[key] = best;
   return best;
+}
+
+// Steps per launch and shape without timing anything: the autotuner's cached choice for
+// this grid if there is one, else K (8 by default) with the default block shape.
+int untuned_k(wh_ctx* ctx, const WaveOp& op, int k_fixed) {
+  auto it = ctx->ktune.find(std::make_tuple(op.dim, op.n, (int)op.f32, (int)op.varc, 2 * k_fixed));
+  if (it != ctx->ktune.end()) return it->second;
+  const int K = k_fixed > 1 ? k_fixed : (op.dim == 2 ? 8 : 3);
+  if (!fused_supported(op.dim, op.f32, K)) return 1;
+  return K | ((op.dim == 2 ? fused2d_default_shape(op.f32, op.n) : 0) << 8);
 }
 
 // ----------------------------------------------------------------- solver state
@@ -1249,7 +1284,8 @@ double now_ms() {
 // Common setup for wh_apply_filter / wh_solve: c_max, time parameters, coefficient
 // arrays in the stepping precisions.
 wh_status setup_ops(wh_ctx* ctx, const wh_grid& g, const wh_params& P, const double* c2,
-                    const double* f, void* ws, const Layout& L, TimeParams& tp, Solver& S) {
+                    const double* f, void* ws, const Layout& L, TimeParams& tp, Solver& S,
+                    bool may_tune = true) {
   hipStream_t s = ctx->stream;
   const bool varc = c2 != nullptr;
   const bool mixed = P.precision == WH_MIXED;
@@ -1328,7 +1364,8 @@ wh_status setup_ops(wh_ctx* ctx, const wh_grid& g, const wh_params& P, const dou
     int code = 1;
     if (g.order == 4 || P.k_fuse == 1 || (P.k_fuse > 1 && !fused_supported(g.dim, op.f32, P.k_fuse))) code = 1;
     else if (P.k_fuse > 1 && P.k_shape >= 0) code = P.k_fuse | (P.k_shape << 8);
-    else code = autotune_k(ctx, op, false, P.k_fuse);
+    else if (may_tune) code = autotune_k(ctx, op, false, P.k_fuse);
+    else code = untuned_k(ctx, op, P.k_fuse);
     op.k_fuse = code & 0xff;
     op.k_shape = code >> 8;
   };
@@ -1357,6 +1394,15 @@ void fill_info(wh_info* info, const TimeParams& tp, int k_fuse, const WaveOp* op
 // (wh_create, the host helpers, workspace sizing).
 namespace {
 thread_local std::string g_create_err;
+
+// Fixed device scratch of wh_apply_filter_noalloc (one copy per GPU, held until the process
+// ends).  Host code never uses the name itself: wh_create looks up its device address once
+// per device (with that device current) and every use goes through that address.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
 }  // namespace
 
 namespace wh {
@@ -1419,6 +1465,23 @@ wh_status wh_create(wh_ctx** out, int device, void* stream) {
   if (e != hipSuccess) {
     g_create_err = std::string("hipSetDevice: ") + hipGetErrorString(e);
     return WH_EHIP;
+  }
+  if (device >= kMaxDevices) {
+    g_create_err = "device index too large";
+    return WH_EINVAL;
+  }
+  {
+    // address of this device's copy of the no-allocation scratch array
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+      void* ptr = nullptr;
+      e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr) {
+        g_create_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+        return WH_EHIP;
+      }
+      g_scratch_ptr[device] = ptr;
+    }
   }
   wh_ctx* c = new wh_ctx();
   c->device = device;
@@ -1608,6 +1671,42 @@ wh_status wh_apply_filter(wh_ctx* ctx, const wh_grid* grid, const double* c2, co
     std::memset(info, 0, sizeof(*info));
     fill_info(info, tp, params->precision == WH_MIXED ? S.op32.k_fuse : S.op64.k_fuse,
               params->precision == WH_MIXED ? &S.op32 : &S.op64);
+    info->wave_solves = params->precision == WH_MIXED ? 0 : 1;
+    info->wave_solves_f32 = params->precision == WH_MIXED ? 1 : 0;
+    info->ms = now_ms() - t0;
+  }
+  return WH_OK;
+  });
+}
+
+wh_status wh_apply_filter_noalloc(wh_ctx* ctx, const wh_grid* grid, const double* c2, const double* f,
+                                  const double* v_in, double* v_out, const wh_params* params,
+                                  wh_info* info) {
+  return guard(ctx, [&]() -> wh_status {
+  if (!ctx) return WH_EINVAL;
+  const double t0 = now_ms();
+  WHCHK(check_grid(ctx, grid));
+  WHCHK(check_params(ctx, grid, params));
+  if (!v_in || !v_out) WH_FAIL(ctx, WH_EINVAL, "v_in / v_out is NULL");
+  if (v_in == v_out) WH_FAIL(ctx, WH_EINVAL, "v_in and v_out must not overlap");
+  const Layout L = make_filter_layout(*grid, *params);
+  if (L.total > kScratchBytes)
+    WH_FAIL(ctx, WH_EWORKSPACE,
+            "grid too large for the fixed scratch of wh_apply_filter_noalloc: needs %zu bytes, "
+            "the scratch holds %zu (use wh_apply_filter with a workspace)", L.total, kScratchBytes);
+  void* ws = g_scratch_ptr[ctx->device];
+  if (!ws) WH_FAIL(ctx, WH_EHIP, "no scratch address for device %d", ctx->device);
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  TimeParams tp;
+  Solver S{};
+  WHCHK(setup_ops(ctx, *grid, *params, c2, f, ws, L, tp, S, false));
+  WaveOp op = params->precision == WH_MIXED ? S.op32 : S.op64;
+  op.V = v_out;
+  wave_solve(op, v_in, f != nullptr, M_LAST_V, nullptr, nullptr, ctx->stream);
+  HIPCHK(ctx, hipGetLastError());
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    fill_info(info, tp, op.k_fuse, &op);
     info->wave_solves = params->precision == WH_MIXED ? 0 : 1;
     info->wave_solves_f32 = params->precision == WH_MIXED ? 1 : 0;
     info->ms = now_ms() - t0;

@@ -241,6 +241,31 @@ void filter_case(int dim, int n, int order, bool varc, bool force, int precision
   delete c2;
 }
 
+// the allocation-free filter: two calls in a row (the second on a smaller grid), and a grid
+// beyond its fixed scratch, which must be rejected with WH_EWORKSPACE
+void noalloc_case(int dim, int n, int precision, bool varc, unsigned seed) {
+  const wh_grid g{dim, n, 2};
+  const size_t N = nodal(dim, n);
+  Buf v(8 * N, "v_in"), out(8 * N, "v_out"), f(8 * N, "f");
+  Buf* c2 = varc ? new Buf(8 * N, "c2") : nullptr;
+  if (c2) fill_field(c2->d(), dim, n, 1.1, 0.2, seed);
+  fill_field(v.d(), dim, n, 0.0, 1.0, seed + 1);
+  fill_field(f.d(), dim, n, 0.0, 1.0, seed + 2);
+  wh_params p = params(0.3 * n + 2.1);
+  p.precision = precision;
+  if (c2) {
+    double m = 0;
+    for (size_t i = 0; i < N; ++i) m = std::max(m, c2->d()[i]);
+    p.c_max = std::sqrt(m);
+  }
+  wh_info info;
+  int st = wh_apply_filter_noalloc(g_ctx, &g, c2 ? c2->d() : nullptr, f.d(), v.d(), out.d(), &p, &info);
+  const bool fits = dim == 2 ? n <= 1024 : n <= 96;
+  expect(fits ? st == 0 : st == WH_EWORKSPACE, "wh_apply_filter_noalloc", st);
+  printf("noalloc dim=%d n=%d prec=%d varc=%d -> %d (K %d)\n", dim, n, precision, (int)varc, st, info.k_fuse);
+  delete c2;
+}
+
 void batched_case(int precision, int solver, bool deflate, unsigned seed) {
   const int ns[] = {8, 16, 24, 33, 12};
   const int nb = 5;
@@ -342,6 +367,18 @@ int main(int argc, char** argv) {
       filter_case(2, n, 4, false, true, 0, 0, seed);
       filter_case(3, n, 4, false, true, 1, 0, seed);
     }
+  }
+  if (all || group == "filter") {
+    for (int prec : {0, 1})
+      for (bool varc : {false, true}) {
+        noalloc_case(2, 96, prec, varc, seed);
+        noalloc_case(2, 40, prec, varc, seed);
+        noalloc_case(2, 5, prec, varc, seed);
+        noalloc_case(3, 20, prec, varc, seed);
+      }
+    noalloc_case(2, 1024, 1, false, seed);
+    noalloc_case(2, 1100, 1, false, seed);
+    noalloc_case(3, 120, 0, false, seed);
   }
   if (all || group == "batched") {
     for (int prec : {0, 1}) {

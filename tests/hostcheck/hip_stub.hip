@@ -41,6 +41,10 @@ std::map<uintptr_t, Alloc>& allocs() {
   static std::map<uintptr_t, Alloc> m;
   return m;
 }
+std::map<const void*, void*>& vars() {
+  static std::map<const void*, void*> m;
+  return m;
+}
 std::map<const void*, std::string>& kernels() {
   static std::map<const void*, std::string> m;
   return m;
@@ -525,6 +529,14 @@ void __hipRegisterFunction(void**, const void* hostFunction, char* deviceFunctio
   kernels()[hostFunction] = deviceFunction;
 }
 void __hipUnregisterFatBinary(void**) {}
+void __hipRegisterVar(void**, void* var, char*, char* deviceVar, int, size_t size, int, int) {
+  // a device variable: its "device copy" is a host block of the same size, registered under
+  // its name, returned by hipGetSymbolAddress
+  void* p = aligned_alloc(256, (size + 255) / 256 * 256);
+  std::memset(p, 0, size);
+  vars()[var] = p;
+  hostcheck_register(p, size, deviceVar);
+}
 }
 
 hipError_t __hipPushCallConfiguration(dim3 g, dim3 b, size_t sh, hipStream_t s) {
@@ -546,6 +558,12 @@ hipError_t hipLaunchKernel(const void* f, dim3 g, dim3 b, void** args, size_t, h
   return hipSuccess;
 }
 
+hipError_t hipGetSymbolAddress(void** p, const void* symbol) {
+  auto it = vars().find(symbol);
+  if (it == vars().end()) return hipErrorInvalidSymbol;
+  *p = it->second;
+  return hipSuccess;
+}
 hipError_t hipGetDeviceCount(int* c) {
   *c = 1;
   return hipSuccess;
