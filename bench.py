@@ -1,16 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of the WaveHoltz hot path on one MI355X.
 
-One step = one complete Helmholtz solve to a true FP64 WaveHoltz residual of 1e-8
-on the 2D workload: unit square, homogeneous Dirichlet, 1024x1024 cells, c = 1,
-omega = 100.3, Gaussian source of width 0.02 at a seeded centre, deflated CG with
-the 32 analytic sine modes nearest resonance, FP32 stepping with FP64 filter sum,
-Krylov and deflation.  Inputs are resident on the GPU before timing starts.
+One step = one batched solve of 256 2D Helmholtz problems to a true FP64 WaveHoltz
+residual of 1e-8 each: 64 problems on each of 128^2, 256^2, 512^2 and 1024^2 cells
+(unit square, homogeneous Dirichlet, c = 1), omega ~ U(10, 80) kept off the discrete
+resonances, Gaussian sources omega^2 exp(-omega^2 r^2) at seeded centres; deflated CG with
+the floor(1.5 omega) sine modes nearest omega^2 per problem, FP32 stepping with FP64
+filter sum, Krylov and deflation, rounds replayed from hipGraphs.  Inputs are resident on
+the GPU before timing starts.
 
-Prints one JSON line: the metric is wave-step throughput (interior points x time
-steps of every wave solve in the solve, divided by the solve's wall time), with
-the roofline of the dominant kernel (the FP32 leapfrog + filter step) and the CPU
-oracle timed on a bounded sample.
+Prints one JSON line: the metric is wave-step throughput (interior points x time steps of
+every wave solve of the batch, divided by the batch's wall time), with the roofline of the
+dominant kernel (the batched FP32 work kernel), the same problems in the FP64 single-solve
+forms and in batched mixed CG for comparison, and the CPU oracle timed on a bounded sample
+together with every solution's error against the oracle's direct solve.  Other workloads:
+--workload cfg1 | cfg2 | cfg3 | cfg5 | solvers | ndsweep.
 """
 from __future__ import annotations
 
@@ -31,6 +35,13 @@ HBM_PEAK_GBS = 8000.0
 # kernel (c = 1, no forcing): read W^n 4 + W^{n-1} 4, write W^{n+1} 4, V read+write 16
 B_PER_PT_STEP_F32 = 28.0
 B_PER_PT_STEP_F64 = 40.0
+# fused-form algorithmic bytes per interior point per launch of a K-step FP32 kernel (no forcing):
+# state pair in 4 + 4, state pair out 4 + 4, V read + write 8 + 8
+B_FUSED_F32 = 32.0
+# HBM KiB per dispatch (FETCH_SIZE, WRITE_SIZE) of the tagged batch work kernel on the config-4
+# batch, from the two counter passes in profiles/hbm_traffic_batch_work_cfg4.md, with the copy-kernel
+# scale factors; valid only for the kernel source it was taken on
+BATCH_TRAFFIC = {"src_sha1": "", "fetch_scale": 2.0, "write_scale": 1.0, "kib": None}
 # HBM KiB per dispatch (FETCH_SIZE, WRITE_SIZE) of every FP32 temporally blocked kernel
 # variant "K,R,NW" on this grid, from the two rocprofv3 counter passes summarised in
 # profiles/hbm_traffic_fused2d_f32_2d1024.md (scaled by FETCH x 2.000, WRITE x 1.000 from a
@@ -135,45 +146,9 @@ def direct_splu(dim, n, omega, f_nodal, c2=None):
                 "note": "scipy SuperLU of the same discrete Helmholtz matrix, one thread"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-f64", action="store_true", help="skip the FP64 single-solve comparison")
-    ap.add_argument("--no-direct", action="store_true",
-                    help="skip the CPU direct solves (scipy sparse LU, about 25 s, and the oracle's sine-transform solve)")
-    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5", "solvers", "ndsweep"],
-                    help="cfg2 (default) is the benchmark line; the others report the remaining "
-                         "workloads (2D 64^2 FP64 CG; 3D 256^3 variable c; 256 batched solves; "
-                         "513^2 adjoint gradient; the config-2 problem by every solver; "
-                         "iterations against omega for two deflation-size rules)")
-    ap.add_argument("--max-iters", type=int, default=0, help="iteration cap (cfg3, solvers)")
-    ap.add_argument("--omegas", default="5:30", help="ndsweep: first:last (step 1) or a comma list")
-    ap.add_argument("--runs", default="", help="solvers: comma-separated subset of the run names "
-                                               "(cg, dcg_nd8, dcg_nd32, dcg_nd64, devd_cg_nd32, "
-                                               "devd_fpi_nd32, gmres, agmres_nd32, bicgstab, "
-                                               "abicgstab_nd32, agmres_nd32_dense, agmres_nd32_factored)")
-    ap.add_argument("--per-size", type=int, default=64, help="problems per grid size (cfg4)")
-    ap.add_argument("--probe-traffic", action="store_true",
-                    help="for hardware-counter runs: a plain 256 MiB device copy, then 5 wave solves "
-                         "of the workload's FP32 operator, and exit")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solves of this workload are "
-              "single-GPU and nothing here shards across GPUs", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-    import paper_2606_31842_amd as wh
-    import workloads as wl
-
-    if args.workload != "cfg2":
-        print(json.dumps(EXTRA[args.workload](args, np, torch, wh, wl)), flush=True)
-        return
-
+def run_cfg2(args, np, torch, wh, wl):
+    """Single 2D 1024^2 solve, c = 1, omega = 100.3, mixed DCG with the 32 sine modes nearest
+    resonance, true residual 1e-8 (the previous benchmark line, kept as an extra workload)."""
     p = wl.config2()
     n = p.n
     pts = (n - 1) ** 2
@@ -318,7 +293,248 @@ def main():
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(p, nt, wave_solves=steps_per_solve // nt, direct=not args.no_direct)
+    return line
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-f64", action="store_true", help="skip the FP64 single-solve comparisons")
+    ap.add_argument("--no-direct", action="store_true",
+                    help="cfg2: skip the CPU direct solves (scipy sparse LU, about 25 s)")
+    ap.add_argument("--workload", default="cfg4",
+                    choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5", "solvers", "ndsweep"],
+                    help="cfg4 (default) is the benchmark line: 256 batched 2D solves; the others report "
+                         "the remaining workloads (2D 64^2 FP64 CG; 2D 1024^2 single mixed DCG solve; 3D 256^3 "
+                         "variable c; 513^2 adjoint gradient; the config-2 problem by every solver; "
+                         "iterations against omega for two deflation-size rules)")
+    ap.add_argument("--max-iters", type=int, default=0, help="iteration cap (cfg3, solvers)")
+    ap.add_argument("--omegas", default="5:30", help="ndsweep: first:last (step 1) or a comma list")
+    ap.add_argument("--runs", default="", help="solvers: comma-separated subset of the run names "
+                                               "(cg, dcg_nd8, dcg_nd32, dcg_nd64, devd_cg_nd32, "
+                                               "devd_fpi_nd32, gmres, agmres_nd32, bicgstab, "
+                                               "abicgstab_nd32, agmres_nd32_dense, agmres_nd32_factored)")
+    ap.add_argument("--per-size", type=int, default=64, help="problems per grid size (cfg4)")
+    ap.add_argument("--no-cg", action="store_true", help="cfg4: skip the batched mixed CG comparison run")
+    ap.add_argument("--probe-traffic", action="store_true",
+                    help="for hardware-counter runs: a plain 256 MiB device copy, then the workload's "
+                         "dominant kernel (cfg4: the batched FP32 work kernel, 5 launches), and exit")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solves of this workload are "
+              "single-GPU and nothing here shards across GPUs", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2606_31842_amd as wh
+    import workloads as wl
+
+    if args.workload != "cfg4":
+        print(json.dumps(EXTRA[args.workload](args, np, torch, wh, wl)), flush=True)
+        return
+
+    probs = wl.config4(per_size=args.per_size)
+    fs = [torch.from_numpy(q.f).cuda() for q in probs]
+    nds = [int(math.floor(1.5 * q.omega)) for q in probs]
+    batch = [(f, q.omega) for f, q in zip(fs, probs)]
+    K = 8
+    kw = dict(solver="dcg", precision="mixed", tol=1e-8, k_fuse=K, max_iters=10000)
+    wsp = torch.empty(wh.batch_workspace_bytes(batch, nds, **kw), dtype=torch.uint8, device="cuda")
+    if args.probe_traffic:
+        a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        wh.time_batch_kernel(batch, reps=5, workspace=wsp, n_defl=nds, **kw)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "traffic", "copy_bytes_each_way": a.numel() * 8}), flush=True)
+        return
+
+    log(f"bench: {len(probs)} problems, warmup {args.warmup}, steps {args.steps}")
+    for i in range(args.warmup):
+        us, infos = wh.solve_batched(batch, workspace=wsp, n_defl=nds, **kw)
+        log(f"warmup {i}: {infos[0]['ms']:.1f} ms")
+    torch.cuda.synchronize()
+    step_s = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        us, infos = wh.solve_batched(batch, workspace=wsp, n_defl=nds, **kw)
+        step_s.append(time.perf_counter() - ts)      # each batched solve ends in a host read-back
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / args.steps * 1e3
+    # wave-step throughput of the batch: interior points x N_t of every wave solve (FP32 and FP64)
+    psteps = sum((i["wave_solves"] + i["wave_solves_f32"]) * i["nt"] * (q.n - 1) ** 2 for i, q in zip(infos, probs))
+    value = psteps / (ms / 1e3) / 1e9
+    statuses = {str(k): sum(1 for i in infos if i["status"] == k) for k in sorted(set(i["status"] for i in infos))}
+    log(f"timed: {ms:.1f} ms per batch, {value:.1f} Gpts/s, statuses {statuses}")
+    hres = [wh.helmholtz_residual(u, f, q.omega) for u, f, q in zip(us, fs, probs)]
+
+    # roofline of the dominant kernel: the batched FP32 work kernel (K register-tiled leapfrog
+    # steps + FP64 filter sum on every tile of every problem), every problem in its stepping
+    # phase, timed with HIP events on the library's stream (torch's current stream)
+    launch_us, pts = wh.time_batch_kernel(batch, reps=20, workspace=wsp, n_defl=nds, **kw)
+    bytes_launch = B_FUSED_F32 * pts
+    achieved = bytes_launch / (launch_us * 1e-6) / 1e9
+    stream_eq = B_PER_PT_STEP_F32 * pts * K / (launch_us * 1e-6) / 1e9
+    log(f"batch kernel: {launch_us:.1f} us per launch, {pts} points x {K} steps, {achieved:.0f} GB/s fused-form")
+    copy_gbs = _copy_gbs(torch)
+    traffic = _traffic_lookup()
+
+    line = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gpts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32/f64",
+        "data": "synthetic",
+        "config": {"workload": f"{len(probs)} batched 2D Dirichlet solves, {args.per_size} each on 128^2, 256^2, "
+                               "512^2, 1024^2, omega~U(10,80) off resonance, source omega^2 exp(-omega^2 r^2) at "
+                               "seeded centres (seed 4), DCG with the floor(1.5 omega) sine modes nearest omega^2, "
+                               "FP32 stepping / FP64 filter+Krylov, graph-replayed rounds, true residual 1e-8",
+                   "problems": len(probs), "solver": "dcg", "precision": "mixed", "tol": 1e-8, "k_fuse": K,
+                   "block": "8 rows x 8 waves", "n_defl_rule": "floor(1.5 omega)"},
+        "time_to_tol_ms_per_batch": round(ms, 3),
+        "time_to_tol_ms_per_solve": round(ms / len(probs), 4),
+        "ms_per_step_min_median": [round(min(step_s) * 1e3, 3), round(sorted(step_s)[len(step_s) // 2] * 1e3, 3)],
+        "solve": {"status_counts": statuses, "iters": int(sum(i["iters"] for i in infos)),
+                  "wave_solves_f32": int(sum(i["wave_solves_f32"] for i in infos)),
+                  "wave_solves_f64": int(sum(i["wave_solves"] for i in infos)),
+                  "point_steps": int(psteps),
+                  "max_true_rel_res": max(i["true_rel_res"] for i in infos),
+                  "max_helmholtz_rel_res": max(hres), "median_helmholtz_rel_res": float(np.median(hres))},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": f"k_batch_work<float,{K},8,8,false,1> (the solver's FP32 work kernel under its "
+                               "measurement tag: K leapfrog steps + FP64 filter sum per launch on every tile)",
+                     "bytes_per_point_per_launch": B_FUSED_F32, "points_per_launch": pts, "k_fuse": K,
+                     "bytes_per_launch": bytes_launch, "launch_us": round(launch_us, 3),
+                     "streaming_equivalent_gbs": round(stream_eq, 1),
+                     "streaming_equivalent_bytes_per_pt_step": B_PER_PT_STEP_F32,
+                     "hbm_gbs_from_traffic": None if traffic is None else round(traffic / (launch_us * 1e-6) / 1e9, 1),
+                     "copy_gbs": round(copy_gbs, 1)},
+    }
+    # same 256 problems in the other forms, once each
+    if not args.no_f64:
+        for solver in ("dcg", "cg"):
+            dk = dict(solver=solver, tol=1e-8, max_iters=100000, precision="f64")
+            for f, q in zip(fs[:: args.per_size], probs[:: args.per_size]):     # autotune per size first
+                wh.solve(f, q.omega, **{**dk, "max_iters": 2},
+                         **({"defl": wh.sine_deflation(2, q.n, q.omega, 4)} if solver == "dcg" else {}))
+            defl = [wh.sine_deflation(2, q.n, q.omega, nd) for q, nd in zip(probs, nds)] if solver == "dcg" else None
+            res, dt = _timed(torch, lambda: [wh.solve(f, q.omega, **dk, **({"defl": defl[j]} if defl else {}))
+                                            for j, (f, q) in enumerate(zip(fs, probs))])
+            line[f"single_f64_{solver}"] = {
+                "seconds": round(dt, 3), "iters": int(sum(i["iters"] for _, i in res)),
+                "status_counts": {str(k): sum(1 for _, i in res if i["status"] == k)
+                                  for k in sorted(set(i["status"] for _, i in res))},
+                "speedup_of_batched_mixed_dcg": round(dt / (ms / 1e3), 2)}
+    if not args.no_cg:
+        kcg = dict(kw, solver="cg")
+        (ucg, icg), dt = _timed(torch, lambda: wh.solve_batched(batch, **kcg))
+        blk = {"seconds": round(dt, 3), "iters": int(sum(i["iters"] for i in icg)),
+               "status_counts": {str(k): sum(1 for i in icg if i["status"] == k) for k in sorted(set(i["status"] for i in icg))},
+               "max_true_rel_res": max(i["true_rel_res"] for i in icg),
+               "not_converged": [{"n": q.n, "omega": round(q.omega, 4), "status": i["status"], "iters": i["iters"],
+                                  "outer": i["outer"], "true_rel_res": i["true_rel_res"]}
+                                 for i, q in zip(icg, probs) if i["status"] != 0]}
+        if "single_f64_cg" in line:
+            blk["speedup_vs_single_f64_cg"] = round(line["single_f64_cg"]["seconds"] / dt, 3)
+        line["batched_mixed_cg"] = blk
+    # the previous single-solve line (1024^2 mixed DCG), kept as an extra key
+    line["cfg2_single_solve"] = _cfg2_brief(np, torch, wh, wl)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline_cfg4(probs, [u.cpu().numpy() for u in us], infos)
     print(json.dumps(line), flush=True)
+
+
+def _copy_gbs(torch):
+    """The box's attainable HBM rate: a plain 1 GiB device-to-device copy (read + write)."""
+    ca = torch.empty(128 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(1.0)
+    cb = torch.empty_like(ca)
+    cb.copy_(ca)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        cb.copy_(ca)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2 * ca.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
+def _traffic_lookup():
+    """HBM bytes per launch of the tagged batch kernel from the two counter passes summarised in
+    profiles/hbm_traffic_batch_work_cfg4.md, or None when the kernel source has changed since."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2606_31842_amd", "csrc", "wh_batched.hip")
+    if not BATCH_TRAFFIC["kib"] or hashlib.sha1(open(src, "rb").read()).hexdigest() != BATCH_TRAFFIC["src_sha1"]:
+        return None
+    fk, wk = BATCH_TRAFFIC["kib"]
+    return round(1024 * (fk * BATCH_TRAFFIC["fetch_scale"] + wk * BATCH_TRAFFIC["write_scale"]))
+
+
+def _cfg2_brief(np, torch, wh, wl):
+    p = wl.config2()
+    f = torch.from_numpy(p.f).cuda()
+    kw = dict(solver="dcg", defl=wh.sine_deflation(2, p.n, p.omega, 32), precision="mixed", tol=1e-8,
+              max_iters=50000, k_fuse=8, k_shape=1)
+    wh.solve(f, p.omega, **kw)
+    (u, info), dt = _timed(torch, lambda: wh.solve(f, p.omega, **kw))
+    steps = (info["wave_solves"] + info["wave_solves_f32"]) * info["nt"]
+    return {"workload": "2D 1024^2, c=1, omega=100.3, mixed DCG with 32 sine modes, tol 1e-8",
+            "time_to_tol_ms": round(dt * 1e3, 2), "gpts": round((p.n - 1) ** 2 * steps / dt / 1e9, 1),
+            "iters": info["iters"], "true_rel_res": info["true_rel_res"],
+            "helmholtz_rel_res": wh.helmholtz_residual(u, f, p.omega)}
+
+
+def _dst_job(args):
+    from oracle import discretization as disc
+    n, omega, f = args
+    return disc.direct_solve_dst(2, n, omega, f)
+
+
+def cpu_baseline_cfg4(probs, sols, infos, budget_s=20.0):
+    """The oracle on the host for the batch: (1) its FP64 WaveHoltz CG (the iteration the GPU
+    runs, step by step in scipy) on a bounded sample -- the 128^2 problems over a spawn pool of
+    every visible core, until about budget_s -- as wave-step Gpts/s; (2) its direct solve of every
+    problem's discrete Helmholtz system (sine transform, exact for c = 1), timed, and the
+    element-wise error of each GPU solution against it."""
+    import multiprocessing as mp
+    import numpy as np
+    cores = len(os.sched_getaffinity(0))
+    ctx = mp.get_context("spawn")
+    small = [q for q in probs if q.n == min(q.n for q in probs)]
+    with ctx.Pool(cores) as pool:
+        t0 = time.perf_counter()
+        res = []
+        for k in range(0, len(small), cores):
+            res += pool.map(_oracle_cg_job, [(2, q.n, q.omega, q.f, 1e-8) for q in small[k:k + cores]])
+            if time.perf_counter() - t0 > budget_s:
+                break
+        wall = time.perf_counter() - t0
+        done = small[:len(res)]
+        psteps = sum((it + 1) * nt * (q.n - 1) ** 2 for (it, nt, _), q in zip(res, done))
+        t1 = time.perf_counter()
+        exact = pool.map(_dst_job, [(q.n, q.omega, q.f) for q in probs])
+        t_dst = time.perf_counter() - t1
+    errs = [float(np.abs(u - U).max() / np.abs(U).max()) for u, U in zip(sols, exact)]
+    by_n = {}
+    for q, e in zip(probs, errs):
+        by_n.setdefault(q.n, []).append(e)
+    return {"value": round(psteps / wall / 1e9, 4), "unit": "Gpts/s", "cores": cores, "kind": "oracle",
+            "sample": f"oracle FP64 WaveHoltz CG (scipy CSR leapfrog) to 1e-8 on {len(res)} of the {len(small)} "
+                      f"problems of size {small[0].n}, a spawn pool of {cores} processes, {wall:.1f} s; host "
+                      f"{cpu_model()}",
+            "sample_wall_s": round(wall, 2), "sample_iters": int(sum(r[0] for r in res)),
+            "direct_dst_all_s": round(t_dst, 2),
+            "error_vs_oracle_max_elementwise": max(errs),
+            "error_vs_oracle_by_size_max": {str(k): max(v) for k, v in sorted(by_n.items())},
+            "error_vs_oracle_each": [float(f"{e:.3g}") for e in errs],
+            "error_note": "max_i |u_i - U_i| / max|U| per solution against the oracle's direct solve (sine "
+                          "transform) of the same discrete Helmholtz system"}
+
 
 
 def _timed(torch, fn):
@@ -391,78 +607,6 @@ def run_cfg3(args, np, torch, wh, wl):
             nws = out[solver]["wave_solves_f32"] + out[solver]["wave_solves_f64"]
             cb[f"{solver}_extrapolated_seconds"] = round(per * nws, 1)
         out["cpu_baseline"] = cb
-    return out
-
-
-def run_cfg4(args, np, torch, wh, wl):
-    """256 (64 per size) 2D solves of mixed sizes and frequencies.  Baseline: the plain FP64
-    single-solve form (wh_solve, CG, one problem after another).  Batched forms: one
-    graph-replayed wh_solve_batched call, CG and DCG (the floor(3 omega / 2) sine modes
-    nearest omega^2 per problem), FP64 and mixed precision; FP64 single DCG for reference."""
-    probs = wl.config4(per_size=args.per_size)
-    fs = [torch.from_numpy(q.f).cuda() for q in probs]
-    nds = [int(math.floor(1.5 * q.omega)) for q in probs]
-    defl = [wh.sine_deflation(2, q.n, q.omega, nd) for q, nd in zip(probs, nds)]
-    seen = set()
-    for f, q in zip(fs, probs):     # warm-up (autotuner) per grid size
-        if q.n not in seen:
-            for prec in ("f64", "mixed"):
-                wh.solve(f, q.omega, solver="cg", tol=1e-8, max_iters=100000, precision=prec)
-            seen.add(q.n)
-    out = {"workload": f"cfg4 {len(probs)} 2D solves n in 128..1024, omega~U(10,80), tol 1e-8",
-           "n_defl_rule": "floor(1.5 omega)"}
-    singles, dt1 = _timed(torch, lambda: [wh.solve(f, q.omega, solver="cg", tol=1e-8, max_iters=100000)
-                                          for f, q in zip(fs, probs)])
-    out["single_f64_cg_seconds"] = dt1
-    out["single_f64_cg_iters"] = int(sum(i["iters"] for _, i in singles))
-    sd, dtd = _timed(torch, lambda: [wh.solve(f, q.omega, solver="dcg", defl=d, tol=1e-8, max_iters=100000)
-                                     for f, q, d in zip(fs, probs, defl)])
-    out["single_f64_dcg_seconds"] = dtd
-    out["single_f64_dcg_iters"] = int(sum(i["iters"] for _, i in sd))
-
-    def residuals(us):
-        return [wh.helmholtz_residual(u, f, q.omega) for u, f, q in zip(us, fs, probs)]
-
-    if not args.no_cpu:
-        # the oracle's FP64 CG over a process pool (one problem per process, all host
-        # cores) on the smallest grid size; the whole batch is extrapolated from its
-        # point-step rate and the point-steps the FP64 single solves above took
-        import multiprocessing as mp
-        cores = len(os.sched_getaffinity(0))
-        sub = [q for q in probs if q.n == min(q.n for q in probs)]
-        ctx = mp.get_context("spawn")
-        t0 = time.perf_counter()
-        with ctx.Pool(cores) as pool:
-            res = pool.map(_oracle_cg_job, [(2, q.n, q.omega, q.f, 1e-8) for q in sub])
-        wall = time.perf_counter() - t0
-        sub_psteps = sum((it + 1) * nt * (q.n - 1) ** 2 for (it, nt, _), q in zip(res, sub))
-        all_psteps = sum((i["iters"] + 1) * i["nt"] * (q.n - 1) ** 2 for (_, i), q in zip(singles, probs))
-        out["cpu_baseline"] = {
-            "kind": "oracle", "cores": cores, "host": cpu_model(),
-            "sample": f"oracle FP64 CG to 1e-8 on the {len(sub)} problems of size {sub[0].n}, "
-                      f"a spawn pool of {cores} processes",
-            "sample_wall_s": round(wall, 2), "sample_iters": int(sum(r[0] for r in res)),
-            "pool_gpts": sub_psteps / wall / 1e9,
-            "extrapolated_batch_seconds": round(wall * all_psteps / sub_psteps, 1)}
-
-    for solver in ("dcg", "cg"):
-        for prec in ("mixed", "f64"):
-            kw = dict(precision=prec, tol=1e-8, k_fuse=8, max_iters=10000, solver=solver)
-            if solver == "dcg":
-                kw["n_defl"] = nds
-            (us, infos), dt = _timed(torch, lambda: wh.solve_batched([(f, q.omega) for f, q in zip(fs, probs)], **kw))
-            errs = residuals(us)
-            # wave-step throughput of the whole batch: every wave solve (FP32 and FP64) x N_t x points
-            psteps = sum((i["wave_solves"] + i["wave_solves_f32"]) * i["nt"] * (q.n - 1) ** 2
-                         for i, q in zip(infos, probs))
-            out[f"batched_{solver}_{prec}"] = {
-                "seconds": dt, "wave_gpts": psteps / dt / 1e9, "iters": int(sum(i["iters"] for i in infos)),
-                "fp64_residual_solves": int(sum(i["outer"] for i in infos)),
-                "max_true_rel_res": max(i["true_rel_res"] for i in infos),
-                "status_counts": {str(k): sum(1 for i in infos if i["status"] == k)
-                                  for k in sorted(set(i["status"] for i in infos))},
-                "max_helmholtz_rel_res": max(errs), "median_helmholtz_rel_res": float(np.median(errs)),
-                "speedup_vs_single_f64_cg": dt1 / dt, "speedup_vs_single_f64_dcg": dtd / dt}
     return out
 
 
@@ -589,7 +733,7 @@ def run_ndsweep(args, np, torch, wh, wl):
             "rows": rows}
 
 
-EXTRA = {"cfg1": run_cfg1, "solvers": run_solvers, "ndsweep": run_ndsweep, "cfg3": run_cfg3, "cfg4": run_cfg4, "cfg5": run_cfg5}
+EXTRA = {"cfg1": run_cfg1, "cfg2": run_cfg2, "solvers": run_solvers, "ndsweep": run_ndsweep, "cfg3": run_cfg3, "cfg5": run_cfg5}
 
 
 if __name__ == "__main__":

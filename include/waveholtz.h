@@ -282,6 +282,17 @@ size_t wh_workspace_bytes_batched(int32_t nb, const wh_problem* probs, const wh_
 wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
                            const wh_params* params, void* ws, size_t ws_bytes, wh_info* infos);
 
+/* Measurement helper of the batched solver: the average duration in microseconds of one launch
+ * of its FP32 work kernel (the K-step register-tiled leapfrog + filter sweep over every tile of
+ * every problem) with every problem of the batch in the FP32 time-stepping phase of an A-apply,
+ * over `reps` back-to-back launches on the context stream between two HIP events.  *points
+ * (may be NULL) receives the interior points one launch advances by K steps, sum (n-1)^2.
+ * Arguments and workspace as for wh_solve_batched with params->precision = WH_MIXED (the
+ * workspace contents are overwritten; every problem needs N_t >= K + 2).  The launches carry a
+ * kernel tag of their own, so that profiles list them apart from the solver's launches. */
+wh_status wh_time_batch_kernel(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const wh_params* params,
+                               int32_t reps, void* ws, size_t ws_bytes, double* us_per_launch, int64_t* points);
+
 /* ------------------------------------------------------------------ gradient (2D) */
 /* Workspace for wh_solve_vjp / wh_adjoint_grad (params->c_max > 0 required). */
 size_t wh_workspace_bytes_adjoint(const wh_grid* grid, const wh_params* params, int32_t ckpt_every);

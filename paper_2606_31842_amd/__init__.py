@@ -334,14 +334,9 @@ def time_step_kernel(v, omega, c2=None, reps=50, shape=False, **kw):
     return us.value / 1e3
 
 
-def solve_batched(problems, workspace=None, n_defl=0, **kw):
-    """Solve many 2D problems in one device-driven batch (wh_solve_batched).
-
-    problems: sequence of (f, omega) or (f, omega, c2) with nodal float64 CUDA tensors.
-    n_defl: sine modes deflated per problem (an int for all, or one per problem; needs
-    solver="dcg" and c == 1).  Returns (list of solutions, list of info dicts)."""
+def _batch(problems, n_defl):
+    """ctypes problem array (and the output tensors) for wh_solve_batched / wh_time_batch_kernel."""
     torch = _torch()
-    lib = nat.load()
     nb = len(problems)
     nds = [int(n_defl)] * nb if np.isscalar(n_defl) else [int(v) for v in n_defl]
     if len(nds) != nb:
@@ -364,6 +359,26 @@ def solve_batched(problems, workspace=None, n_defl=0, **kw):
         arr[i].n_defl = nds[i]
         if ctx is None:
             ctx = context(f.device.index)
+    return arr, outs, ctx
+
+
+def batch_workspace_bytes(problems, n_defl=0, **kw) -> int:
+    """Workspace bytes wh_solve_batched needs for these problems and parameters."""
+    lib = nat.load()
+    arr, _, _ = _batch(problems, n_defl)
+    p = params(float(problems[0][1]), **kw)
+    return int(lib.wh_workspace_bytes_batched(len(problems), arr, C.byref(p)))
+
+
+def solve_batched(problems, workspace=None, n_defl=0, **kw):
+    """Solve many 2D problems in one device-driven batch (wh_solve_batched).
+
+    problems: sequence of (f, omega) or (f, omega, c2) with nodal float64 CUDA tensors.
+    n_defl: sine modes deflated per problem (an int for all, or one per problem; needs
+    solver="dcg" and c == 1).  Returns (list of solutions, list of info dicts)."""
+    lib = nat.load()
+    nb = len(problems)
+    arr, outs, ctx = _batch(problems, n_defl)
     p = params(float(problems[0][1]), **kw)
     need = lib.wh_workspace_bytes_batched(nb, arr, C.byref(p))
     if need == 0:
@@ -373,6 +388,25 @@ def solve_batched(problems, workspace=None, n_defl=0, **kw):
     st = lib.wh_solve_batched(ctx, nb, arr, C.byref(p), _ptr(ws), ws.numel(), infos)
     _check(lib, ctx, st)
     return outs, [infos[i].as_dict() for i in range(nb)]
+
+
+def time_batch_kernel(problems, reps=20, workspace=None, n_defl=0, **kw):
+    """(microseconds per launch, interior points per launch) of the batched solver's FP32 work
+    kernel with every problem in its time-stepping phase (wh_time_batch_kernel)."""
+    lib = nat.load()
+    nb = len(problems)
+    arr, _, ctx = _batch(problems, n_defl)
+    kw = dict(kw, precision="mixed")
+    p = params(float(problems[0][1]), **kw)
+    need = lib.wh_workspace_bytes_batched(nb, arr, C.byref(p))
+    if need == 0:
+        raise WaveHoltzError(-1, "invalid batch (wh_workspace_bytes_batched returned 0)")
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need)
+    us, pts = C.c_double(), C.c_int64()
+    st = lib.wh_time_batch_kernel(ctx, nb, arr, C.byref(p), int(reps), _ptr(ws), ws.numel(), C.byref(us),
+                                  C.byref(pts))
+    _check(lib, ctx, st)
+    return us.value, pts.value
 
 
 def solve_vjp(u, grad_u, f, omega, c2, ckpt_every=16, grad_c2=None, **kw):

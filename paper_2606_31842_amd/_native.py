@@ -89,6 +89,8 @@ _OPTIONAL = {
     "wh_workspace_bytes_batched": (C.c_size_t, [C.c_int32, P(WhProblem), P(WhParams)]),
     "wh_solve_batched": (C.c_int, [C.c_void_p, C.c_int32, P(WhProblem), P(WhParams), C.c_void_p, C.c_size_t,
                                    P(WhInfo)]),
+    "wh_time_batch_kernel": (C.c_int, [C.c_void_p, C.c_int32, P(WhProblem), P(WhParams), C.c_int32, C.c_void_p,
+                                       C.c_size_t, P(C.c_double), P(C.c_int64)]),
     "wh_apply_filter_noalloc": (C.c_int, [C.c_void_p, P(WhGrid), C.c_void_p, C.c_void_p, C.c_void_p,
                                           C.c_void_p, P(WhParams), P(WhInfo)]),
     "wh_time_step_kernel": (C.c_int, [C.c_void_p, P(WhGrid), C.c_void_p, P(WhParams), C.c_int32, C.c_void_p,

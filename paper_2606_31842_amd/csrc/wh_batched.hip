@@ -67,7 +67,7 @@ struct BDesc {
 };
 
 struct BState {
-  int phase, step, pair, iters, outer, status, stalls, force64, last_repl, pad_[3];
+  int phase, step, pair, iters, outer, status, stalls, force64, last_repl, restart, pad_[2];
   double r2, rhs2, nb2, alpha, beta, rel, itol, pq, prev_rel, it64;  // it64: FP64 inner iterations
 };
 
@@ -116,7 +116,9 @@ __device__ __forceinline__ T lap_term(const T* c, const T* kap, int64_t p, int64
   return A * (((c[p - 1] + c[p + 1]) + (c[p - P] + c[p + P])) - T(4) * cc);
 }
 
-template <typename T, int K, int R, int NW, bool VARC>
+// TAG only separates the measurement launches of wh_time_batch_kernel (TAG = 1) from the
+// solver's (TAG = 0) in profiles; the code is the same.
+template <typename T, int K, int R, int NW, bool VARC, int TAG = 0>
 __global__ __launch_bounds__(64 * NW) void k_batch_work(const BDesc* __restrict__ descs,
                                                         const BState* __restrict__ states,
                                                         const int* __restrict__ tile_solve,
@@ -155,9 +157,12 @@ __global__ __launch_bounds__(64 * NW) void k_batch_work(const BDesc* __restrict_
 
   switch (ph) {
     case BP_INIT: {
+      // r_0 = p_0 = b - A x_0 (deflated start) or b (x = 0; a restart clears x first)
       reduce = true;
+      const bool clear = S.restart != 0;
       TILE_FOR(p) {
         const double v = D.x0 ? D.b[p] - D.q[p] : D.b[p];
+        if (clear) D.x[p] = 0.0;
         D.r[p] = v;
         D.p[p] = v;
         acc += v * v;
@@ -481,6 +486,7 @@ __global__ __launch_bounds__(256) void k_batch_control(const BDesc* __restrict__
       break;
     case BP_INIT: {
       // r_0 = b (no start vector) or b - A x_0 (deflated start), both exact in FP64
+      S.restart = 0;
       if (!(S.nb2 > 0)) {
         // b = 0: the solution is 0, and x is 0 here (no start, or the start from a zero f)
         S.r2 = 0.0;
@@ -539,8 +545,13 @@ __global__ __launch_bounds__(256) void k_batch_control(const BDesc* __restrict__
         } else {
           S.phase = BP_UPD2;
         }
-      } else if (rel <= D.itol * S.prev_rel || rel >= 10.0 * S.prev_rel || rel <= D.tol || cap ||
-                 S.iters - S.last_repl >= 500) {
+      } else if (S.force64 ? (rel <= D.tol || cap)
+                           : (rel <= D.itol * S.prev_rel || rel >= 10.0 * S.prev_rel || rel <= D.tol || cap ||
+                              S.iters - S.last_repl >= 500)) {
+        // FP32 operator: the recursive residual is replaced by the true one whenever it has
+        // fallen by itol (or grown tenfold, or 500 iterations passed).  After the fallback to
+        // FP64 the recurrence runs as plain CG and the true residual is formed only when the
+        // recursive one meets the tolerance (a replacement then continues the iteration)
         S.pq = r2_old;                 // kept for beta after the replacement
         S.phase = BP_R_FIRST;
       } else {
@@ -564,10 +575,19 @@ __global__ __launch_bounds__(256) void k_batch_control(const BDesc* __restrict__
       S.stalls = rel > 0.5 * S.prev_rel ? S.stalls + 1 : 0;
       S.last_repl = S.iters;
       if (S.stalls >= 2 && !S.force64) {
-        // the FP32 operator error dominates: continue in FP64, restarting the
-        // recurrence from the true residual (p = r)
+        // the FP32 operator error dominates: continue in FP64.  A problem without a
+        // deflated start begins again from x = 0 as plain FP64 CG (the iterate the FP32
+        // operator left can hold large components along near-singular, possibly negative
+        // modes of A, from which CG need not recover); a deflated one continues from the
+        // true residual (p = r)
         S.force64 = 1;
         S.beta = 0.0;
+        if (!D.x0) {
+          S.restart = 1;
+          S.prev_rel = 1.0;
+          S.phase = BP_INIT;
+          break;
+        }
       }
       S.prev_rel = rel;
       if (!isfinite(rel)) {
@@ -648,6 +668,25 @@ static void launch_round(int K, bool varc, int nb, const BDesc* descs, BState* s
                   : launch_round_k<8, false>(descs, states, ts, ntiles, s, rf); break;
   }
   hipLaunchKernelGGL(k_batch_control, dim3(nb), dim3(256), 0, s, descs, states, K);
+}
+
+// The FP32 work kernel alone, under its measurement tag (wh_time_batch_kernel).
+template <int K, bool VARC>
+static void launch_work_tagged(const BDesc* descs, const BState* states, const int* ts, int ntiles, hipStream_t s) {
+  hipLaunchKernelGGL((k_batch_work<float, K, kBR, kBW, VARC, 1>), dim3(ntiles), dim3(64, kBW), 0, s, descs, states,
+                     ts, ntiles, 1);
+}
+
+static void launch_work_timing(int K, bool varc, const BDesc* descs, const BState* states, const int* ts, int ntiles,
+                               hipStream_t s) {
+  switch (K) {
+    case 2: varc ? launch_work_tagged<2, true>(descs, states, ts, ntiles, s)
+                 : launch_work_tagged<2, false>(descs, states, ts, ntiles, s); break;
+    case 4: varc ? launch_work_tagged<4, true>(descs, states, ts, ntiles, s)
+                 : launch_work_tagged<4, false>(descs, states, ts, ntiles, s); break;
+    default: varc ? launch_work_tagged<8, true>(descs, states, ts, ntiles, s)
+                  : launch_work_tagged<8, false>(descs, states, ts, ntiles, s); break;
+  }
 }
 
 static int tile_dim(int n, int K, int axis) {
@@ -827,42 +866,22 @@ wh_status deflated_start(wh_ctx* ctx, const wh_problem& pr, const TimeParams& tp
   return WH_OK;
 }
 
-}  // namespace
+// Validation, workspace carving, coefficient arrays, zeroed states, weight tables, deflated
+// starts, and the descriptors, tile table and initial states on the device: everything a
+// batched solve (or a timing of its work kernel) needs before the first round.
+struct BatchSetup {
+  std::vector<TimeParams> tps;
+  std::vector<BDesc> D;
+  int ntiles = 0, K = 4;
+  bool mixed = false, varc = false;
+  BDesc* ddesc = nullptr;
+  BState* dstate = nullptr;
+  int* dtiles = nullptr;
+  int* dremain = nullptr;
+};
 
-extern "C" {
-
-size_t wh_workspace_bytes_batched(int32_t nb, const wh_problem* probs, const wh_params* params) {
-  return guard_size([&]() -> size_t {
-  if (batch_validate(nullptr, nb, probs, params) != WH_OK) return 0;
-  const bool mixed = params->precision == WH_MIXED;
-  const bool varc = probs[0].c2 != nullptr;
-  const int K = batch_K(params);
-  const double cmax = params->c_max > 0 ? params->c_max : 1.0;
-  size_t total = 0;
-  int ntiles = 0;
-  for (int i = 0; i < nb; ++i) {
-    wh_params p = *params;
-    p.omega = probs[i].omega;
-    TimeParams tp;
-    if (make_time_params(nullptr, 2, probs[i].grid.n, p, cmax, tp) != WH_OK) return 0;
-    total += problem_bytes(probs[i].grid.n, tp.nt, K, mixed, varc);
-    ntiles += tile_dim(probs[i].grid.n, K, 0) * tile_dim(probs[i].grid.n, K, 1);
-  }
-  size_t dscr = 0;
-  for (int i = 0; i < nb; ++i) dscr = std::max(dscr, defl_scratch_bytes(probs[i].grid.n, probs[i].n_defl));
-  total += dscr;
-  total += 16 * (size_t)kReduceBlocks;  // c_max reductions (multiple of 256)
-  total += ((sizeof(BDesc) * nb + 255) & ~(size_t)255) + ((sizeof(BState) * nb + 255) & ~(size_t)255);
-  total += ((4 * (size_t)ntiles + 255) & ~(size_t)255) + 256;
-  return total;
-  });
-}
-
-wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
-                           const wh_params* params, void* ws, size_t ws_bytes, wh_info* infos) {
-  return guard(ctx, [&]() -> wh_status {
-  if (!ctx) return WH_EINVAL;
-  const auto t0 = std::chrono::steady_clock::now();
+wh_status prepare_batch(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const wh_params* params,
+                        void* ws, size_t ws_bytes, BatchSetup& B) {
   wh_status vs = batch_validate(ctx, nb, probs, params);
   if (vs != WH_OK) return vs;
   const size_t need = wh_workspace_bytes_batched(nb, probs, params);
@@ -997,6 +1016,71 @@ wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
   HIPB(ctx, hipMemcpyAsync(dstate, S0.data(), sizeof(BState) * nb, hipMemcpyHostToDevice, s));
   HIPB(ctx, hipStreamSynchronize(s));
   HIPB(ctx, hipGetLastError());
+  B.tps = std::move(tps);
+  B.D = std::move(D);
+  B.ntiles = ntiles;
+  B.K = K;
+  B.mixed = mixed;
+  B.varc = varc;
+  B.ddesc = ddesc;
+  B.dstate = dstate;
+  B.dtiles = dtiles;
+  B.dremain = dremain;
+  return WH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t wh_workspace_bytes_batched(int32_t nb, const wh_problem* probs, const wh_params* params) {
+  return guard_size([&]() -> size_t {
+  if (batch_validate(nullptr, nb, probs, params) != WH_OK) return 0;
+  const bool mixed = params->precision == WH_MIXED;
+  const bool varc = probs[0].c2 != nullptr;
+  const int K = batch_K(params);
+  const double cmax = params->c_max > 0 ? params->c_max : 1.0;
+  size_t total = 0;
+  int ntiles = 0;
+  for (int i = 0; i < nb; ++i) {
+    wh_params p = *params;
+    p.omega = probs[i].omega;
+    TimeParams tp;
+    if (make_time_params(nullptr, 2, probs[i].grid.n, p, cmax, tp) != WH_OK) return 0;
+    total += problem_bytes(probs[i].grid.n, tp.nt, K, mixed, varc);
+    ntiles += tile_dim(probs[i].grid.n, K, 0) * tile_dim(probs[i].grid.n, K, 1);
+  }
+  size_t dscr = 0;
+  for (int i = 0; i < nb; ++i) dscr = std::max(dscr, defl_scratch_bytes(probs[i].grid.n, probs[i].n_defl));
+  total += dscr;
+  total += 16 * (size_t)kReduceBlocks;  // c_max reductions (multiple of 256)
+  total += ((sizeof(BDesc) * nb + 255) & ~(size_t)255) + ((sizeof(BState) * nb + 255) & ~(size_t)255);
+  total += ((4 * (size_t)ntiles + 255) & ~(size_t)255) + 256;
+  return total;
+  });
+}
+
+wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
+                           const wh_params* params, void* ws, size_t ws_bytes, wh_info* infos) {
+  return guard(ctx, [&]() -> wh_status {
+  if (!ctx) return WH_EINVAL;
+  const auto t0 = std::chrono::steady_clock::now();
+  BatchSetup B;
+  {
+    const wh_status ps = prepare_batch(ctx, nb, probs, params, ws, ws_bytes, B);
+    if (ps != WH_OK) return ps;
+  }
+  hipStream_t s = ctx->stream;
+  const bool mixed = B.mixed;
+  const bool varc = B.varc;
+  const int K = B.K;
+  const int ntiles = B.ntiles;
+  std::vector<BDesc>& D = B.D;
+  std::vector<TimeParams>& tps = B.tps;
+  BDesc* ddesc = B.ddesc;
+  BState* dstate = B.dstate;
+  int* dtiles = B.dtiles;
+  int* dremain = B.dremain;
 
   // Capture G rounds + the counter in a graph on a private stream, twice (two
   // executables whose counters go to different slots).  Replays alternate between
@@ -1115,6 +1199,56 @@ wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
   }
   if (st == WH_ENOCONV) ctx->err = "some batched problems did not reach the tolerance";
   return st;
+  });
+}
+
+wh_status wh_time_batch_kernel(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const wh_params* params,
+                               int32_t reps, void* ws, size_t ws_bytes, double* us_per_launch, int64_t* points) {
+  return guard(ctx, [&]() -> wh_status {
+  if (!ctx) return WH_EINVAL;
+  if (reps < 1 || !us_per_launch) WHB_FAIL(ctx, WH_EINVAL, "reps must be >= 1 and us_per_launch set");
+  if (!params || params->precision != WH_MIXED)
+    WHB_FAIL(ctx, WH_EINVAL, "the FP32 work kernel is timed with params->precision = WH_MIXED");
+  BatchSetup B;
+  {
+    const wh_status ps = prepare_batch(ctx, nb, probs, params, ws, ws_bytes, B);
+    if (ps != WH_OK) return ps;
+  }
+  hipStream_t s = ctx->stream;
+  int64_t pts = 0;
+  for (int i = 0; i < nb; ++i) {
+    if (B.D[i].nt - 2 < B.K)
+      WHB_FAIL(ctx, WH_EINVAL, "problem %d has fewer than K + 2 time steps (N_t = %d)", i, B.D[i].nt);
+    pts += (int64_t)(B.D[i].n - 1) * (B.D[i].n - 1);
+  }
+  // every problem in the FP32 time-stepping phase of an A-apply, K steps per launch
+  std::vector<BState> S(nb);
+  std::memset(S.data(), 0, sizeof(BState) * nb);
+  for (auto& st : S) {
+    st.phase = BP_A_STEP;
+    st.step = 1;
+  }
+  HIPB(ctx, hipMemcpyAsync(B.dstate, S.data(), sizeof(BState) * nb, hipMemcpyHostToDevice, s));
+  HIPB(ctx, hipStreamSynchronize(s));
+  launch_work_timing(B.K, B.varc, B.ddesc, B.dstate, B.dtiles, B.ntiles, s);
+  hipEvent_t e0, e1;
+  HIPB(ctx, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    WHB_FAIL(ctx, WH_EHIP, "hipEventCreate failed");
+  }
+  (void)hipEventRecord(e0, s);
+  for (int r = 0; r < reps; ++r) launch_work_timing(B.K, B.varc, B.ddesc, B.dstate, B.dtiles, B.ntiles, s);
+  (void)hipEventRecord(e1, s);
+  hipError_t e = hipEventSynchronize(e1);
+  float ms = 0;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) WHB_FAIL(ctx, WH_EHIP, "event timing failed: %s", hipGetErrorString(e));
+  *us_per_launch = 1e3 * (double)ms / reps;
+  if (points) *points = pts;
+  return WH_OK;
   });
 }
 

@@ -297,6 +297,12 @@ void batched_case(int precision, int solver, bool deflate, unsigned seed) {
   int st = wh_solve_batched(g_ctx, nb, probs.data(), &p, ws.p, need, infos.data());
   expect(st >= 0, "wh_solve_batched", st);
   printf("batched prec=%d solver=%d defl=%d -> %d\n", precision, solver, (int)deflate, st);
+  if (precision == WH_MIXED) {
+    double us = 0;
+    int64_t pts = 0;
+    st = wh_time_batch_kernel(g_ctx, nb, probs.data(), &p, 3, ws.p, need, &us, &pts);
+    expect(st == 0, "wh_time_batch_kernel", st);
+  }
   for (Buf* b : keep) delete b;
 }
 

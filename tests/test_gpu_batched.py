@@ -140,3 +140,43 @@ def test_batched_dcg_rejects_bad_input():
                          c_max=1.0)                                   # sine modes need c == 1
     with pytest.raises(wh.WaveHoltzError):
         wh.solve_batched([(f, 5.0)], solver="dcg", n_defl=15 * 15 + 1)
+
+
+def test_time_batch_kernel_reports_points_and_time():
+    # the measurement helper of the batched FP32 work kernel: every problem in its stepping
+    # phase; it returns the interior points one launch advances and a positive duration, and
+    # leaves the solver usable (a solve afterwards still matches the direct solution)
+    import torch
+    import paper_2606_31842_amd as wh
+    probs = [(wl.gaussian(2, n, (0.4, 0.6), 0.1), om) for n, om in ((40, 11.3), (64, 17.9), (33, 9.1))]
+    batch = [(cuda(f), om) for f, om in probs]
+    us, pts = wh.time_batch_kernel(batch, reps=5, k_fuse=4, solver="cg")
+    assert pts == sum((f.shape[0] - 2) ** 2 for f, _ in probs)
+    assert 0 < us < 1e5
+    sols, infos = wh.solve_batched(batch, precision="mixed", tol=1e-9, k_fuse=4)
+    for (f, om), u, info in zip(probs, sols, infos):
+        n = f.shape[0] - 1
+        U = direct(2, n, om, f)
+        assert info["status"] == 0
+        assert rel(host(u), U) < 2e-5
+
+
+def test_batched_mixed_cg_near_indefinite_problem_converges():
+    # the 128^2 problem at omega = 76.0139 of the 256-problem workload has a degenerate pair of
+    # modes whose A-eigenvalue is slightly negative (beta_h overshoots 1 just below omega with
+    # 22 steps per period); the FP32 operator stalls on it, the problem falls back to FP64 and
+    # restarts from zero as plain CG, and reaches the tolerance like the FP64 single solve
+    import paper_2606_31842_amd as wh
+    q = [p for p in wl.config4() if p.n == 128 and abs(p.omega - 76.0139) < 1e-3][0]
+    other = [p for p in wl.config4() if p.n == 128][:2]
+    probs = [q] + other
+    sols, infos = wh.solve_batched([(cuda(p.f), p.omega) for p in probs], precision="mixed", solver="cg",
+                                   tol=1e-8, k_fuse=8, max_iters=10000)
+    for p, u, info in zip(probs, sols, infos):
+        U = direct(2, p.n, p.omega, p.f)
+        err = rel(host(u), U)
+        print(f"omega {p.omega:.4f}: status {info['status']} iters {info['iters']} fp64 solves "
+              f"{info['wave_solves']} err {err:.2e}", flush=True)
+        assert info["status"] == 0 and info["true_rel_res"] <= 1e-8
+        assert err < 2e-5
+    assert infos[0]["wave_solves"] > infos[0]["outer"] + 1    # it did run in FP64
