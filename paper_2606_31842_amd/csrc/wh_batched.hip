@@ -36,47 +36,10 @@
 #include <cstring>
 #include <vector>
 
-#include "wh_common.h"
+#include "wh_batched.h"
 #include "wh_reduce.h"
 
 namespace wh {
-
-enum BPhase : int {
-  BP_B_FIRST = 0, BP_B_STEP, BP_B_LAST,
-  BP_INIT,
-  BP_A_FIRST, BP_A_STEP, BP_A_LAST,
-  BP_UPD1, BP_UPD2,
-  BP_R_FIRST, BP_R_STEP, BP_R_LAST,
-  BP_DONE
-};
-
-struct BDesc {
-  int n, nt, ntx, nty, tile0, mixed, max_iters, max_outer, defect, x0;  // x0: start from x_0, A x_0 in q
-  double a, tol, itol, om2dt2;   // om2dt2 = (omega dt)^2 of the fixed point
-  double *x, *b, *r, *p, *q, *V;
-  void* W[4];                 // FP64 (prev, cur) pairs 0 and 1; 8 bytes per node each
-  void* W32[4];               // FP32 pairs (mixed only): the FP32 view of W[] would alias
-                              // boundary nodes onto halves of interior doubles
-  const double* kap64;
-  const double* fs64;
-  const float* kap32;
-  const float* fs32;
-  const double* w;            // trapezoid weights, N_t + 1
-  const double* cosv;         // cos(omega_w t^n), N_t + 1
-  double* partials;           // one per tile
-};
-
-struct BState {
-  int phase, step, pair, iters, outer, status, stalls, force64, last_repl, restart, pad_[2];
-  double r2, rhs2, nb2, alpha, beta, rel, itol, pq, prev_rel, it64;  // it64: FP64 inner iterations
-};
-
-// Stepping precision of a phase: 1 = FP32 (inner CG of a mixed problem that has not
-// fallen back to FP64), 0 = FP64 (everything else, including element-wise phases).
-__device__ __forceinline__ int phase_prec(int ph, int mixed) {
-  if (ph == BP_A_FIRST || ph == BP_A_STEP || ph == BP_A_LAST) return mixed ? 1 : 0;
-  return 0;
-}
 
 __device__ __forceinline__ int xcd_tile_b(int bid, int nb) {
   const int xcd = bid & 7, idx = bid >> 3;
@@ -116,31 +79,20 @@ __device__ __forceinline__ T lap_term(const T* c, const T* kap, int64_t p, int64
   return A * (((c[p - 1] + c[p + 1]) + (c[p - P] + c[p + P])) - T(4) * cc);
 }
 
-// TAG only separates the measurement launches of wh_time_batch_kernel (TAG = 1) from the
-// solver's (TAG = 0) in profiles; the code is the same.
-template <typename T, int K, int R, int NW, bool VARC, int TAG = 0>
-__global__ __launch_bounds__(64 * NW) void k_batch_work(const BDesc* __restrict__ descs,
-                                                        const BState* __restrict__ states,
-                                                        const int* __restrict__ tile_solve,
-                                                        int ntiles, int want) {
+// The work of one tile of problem sid in its current phase (lt: the tile within the problem).
+template <typename T, int K, int R, int NW, bool VARC>
+__device__ __forceinline__ void batch_tile(const BDesc* __restrict__ descs, const BState* __restrict__ states,
+                                           int sid, int lt) {
   constexpr int TXO = 64 - 2 * K;
   constexpr int TYO = NW * R - 2 * K;
   constexpr int NT = 64 * NW;
   // FP32 state pairs are (W^n, D^{n-1/2} = W^n - W^{n-1}), stepped in the increment form
   // D += dt^2 (L_h W - f cos), W += D; FP64 pairs are (W^n, W^{n-1}).
   constexpr bool INC = sizeof(T) == 4;
-  const int gt = xcd_tile_b(blockIdx.x, ntiles);
-  const int sid = tile_solve[gt];
   const BDesc& D = descs[sid];
   const int ph = states[sid].phase;
-  if (ph == BP_DONE) return;
-  const int prec = phase_prec(ph, D.mixed && !states[sid].force64);
-  const bool stepping = ph != BP_INIT && ph != BP_UPD1 && ph != BP_UPD2;
-  if (want == 1 && !(stepping && prec == 1)) return;
-  if (want == 0 && stepping && prec == 1) return;
   const int n = D.n;
   const int64_t P = (int64_t)n + 1;
-  const int lt = gt - D.tile0;
   const int x0 = 1 + (lt % D.ntx) * TXO;
   const int y0 = 1 + (lt / D.ntx) * TYO;
   const int tid = threadIdx.y * 64 + threadIdx.x;
@@ -433,6 +385,139 @@ __global__ __launch_bounds__(64 * NW) void k_batch_work(const BDesc* __restrict_
   }
 }
 
+// One work kernel: persistent blocks take the active tiles of their class that the plan lists.
+// The item range is cut into 8 contiguous chunks, one per XCD (blocks are dispatched
+// round-robin over the XCDs), so that neighbouring tiles of a problem share an L2; a block
+// takes items of its XCD's chunk from that chunk's counter, then helps with the other chunks.
+// The plan kernel resets the counters.  TAG only separates the measurement launches of
+// wh_time_batch_kernel (TAG = 1) from the solver's in profiles; the code is the same.
+// The occupancy bound keeps the register budget of the one-tile-per-block form (constant c:
+// 6 waves per SIMD in FP32, i.e. three 8-wave blocks per CU, 4 in FP64; variable c: 4 and 2).
+template <typename T, int K, int R, int NW, bool VARC, int TAG = 0>
+__global__ __launch_bounds__(64 * NW, sizeof(T) == 4 ? (VARC ? 4 : 6) : (VARC ? 2 : 4))
+void k_batch_work(const BDesc* __restrict__ descs,
+                                                        const BState* __restrict__ states,
+                                                        int* __restrict__ plan, int nb, int want) {
+  constexpr int kCache = kMaxBatch;   // item offsets of the active problems, searched in LDS
+  const int* pl = plan + want * plan_stride(nb);
+  int* ctr = plan + 2 * plan_stride(nb) + 8 * want;
+  const int total = pl[0], nact = pl[1];
+  if (total == 0) return;
+  const int* pid = pl + 2;
+  const int* start = pl + 2 + nb;
+  const int tid = threadIdx.y * 64 + threadIdx.x;
+  __shared__ int s_start[kCache + 1];
+  __shared__ int s_item;
+  for (int k = tid; k <= nact; k += 64 * NW) s_start[k] = start[k];
+  const int xcd = blockIdx.x & 7;
+  int q = 0, c = xcd;
+  int c0 = (int)((int64_t)total * c / 8), c1 = (int)((int64_t)total * (c + 1) / 8);
+  if (tid == 0) s_item = c0 + atomicAdd(&ctr[c], 1);
+  __syncthreads();
+  while (true) {
+    const int it = s_item;
+    __syncthreads();
+    if (it >= c1) {
+      // this chunk is done: help with the next XCD's chunk
+      if (++q == 8) break;
+      c = (xcd + q) & 7;
+      c0 = (int)((int64_t)total * c / 8);
+      c1 = (int)((int64_t)total * (c + 1) / 8);
+      if (tid == 0) s_item = c0 + atomicAdd(&ctr[c], 1);
+      __syncthreads();
+      continue;
+    }
+    // the next item's index is requested now and stored after this item's work, so the
+    // atomic's latency overlaps the tile
+    int nxt = 0;
+    if (tid == 0) nxt = atomicAdd(&ctr[c], 1);
+    // the active problem holding item it: start[k] <= it < start[k + 1]
+    int lo = 0, hi = nact - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_start[mid] <= it) lo = mid;
+      else hi = mid - 1;
+    }
+    const int k0 = s_start[lo];
+    batch_tile<T, K, R, NW, VARC>(descs, states, pid[lo], it - k0);
+    if (tid == 0) s_item = c0 + nxt;
+    __syncthreads();
+  }
+}
+
+// The same work, one tile per block over every tile of every problem (block -> tile through
+// the static tile table, in XCD-contiguous order); blocks whose problem is not in class `want`
+// return at once.  Used for the class that holds most of the tiles (the FP32 stepping of a
+// mixed batch, everything in an FP64 batch), where the hardware's block dispatch balances the
+// work best.
+template <typename T, int K, int R, int NW, bool VARC, int TAG = 0>
+__global__ __launch_bounds__(64 * NW, sizeof(T) == 4 ? (VARC ? 4 : 6) : (VARC ? 2 : 4))
+void k_batch_tile(const BDesc* __restrict__ descs, const BState* __restrict__ states,
+                  const int* __restrict__ tile_solve, int ntiles, int want) {
+  const int gt = xcd_tile_b(blockIdx.x, ntiles);
+  const int sid = tile_solve[gt];
+  const BDesc& D = descs[sid];
+  const BState& S = states[sid];
+  const int ph = S.phase;
+  if (ph == BP_DONE) return;
+  const bool stepping = ph != BP_INIT && ph != BP_UPD1 && ph != BP_UPD2;
+  const int cls = (stepping && phase_prec(ph, D.mixed && !S.force64) == 1) ? 1 : 0;
+  if (cls != want) return;
+  batch_tile<T, K, R, NW, VARC>(descs, states, sid, gt - D.tile0);
+}
+
+// The plan of the next round from the problems' phases (one block; problems in index order,
+// so that the tiles of a problem stay consecutive).
+__global__ __launch_bounds__(256) void k_batch_plan(const BDesc* __restrict__ descs,
+                                                    const BState* __restrict__ states, int nb, int* plan) {
+  __shared__ int sc[4][256];
+  __shared__ int base[4];   // tiles class 0, problems class 0, tiles class 1, problems class 1
+  const int tid = threadIdx.x;
+  if (tid < 4) base[tid] = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < nb; c0 += 256) {
+    const int i = c0 + tid;
+    int cls = -1, nt = 0;
+    if (i < nb) {
+      const int ph = states[i].phase;
+      if (ph != BP_DONE) {
+        const int prec = phase_prec(ph, descs[i].mixed && !states[i].force64);
+        const bool stepping = ph != BP_INIT && ph != BP_UPD1 && ph != BP_UPD2;
+        cls = (stepping && prec == 1) ? 1 : 0;
+        nt = descs[i].ntx * descs[i].nty;
+      }
+    }
+    int v[4] = {cls == 0 ? nt : 0, cls == 0 ? 1 : 0, cls == 1 ? nt : 0, cls == 1 ? 1 : 0};
+    // inclusive scans (Hillis-Steele) of the four values
+    for (int q = 0; q < 4; ++q) sc[q][tid] = v[q];
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+      int t[4];
+      for (int q = 0; q < 4; ++q) t[q] = tid >= o ? sc[q][tid - o] : 0;
+      __syncthreads();
+      for (int q = 0; q < 4; ++q) sc[q][tid] += t[q];
+      __syncthreads();
+    }
+    if (cls >= 0) {
+      int* pl = plan + cls * plan_stride(nb);
+      const int k = base[2 * cls + 1] + sc[2 * cls + 1][tid] - 1;        // position among the active
+      pl[2 + k] = i;
+      pl[2 + nb + k] = base[2 * cls] + sc[2 * cls][tid] - nt;          // first item of problem i
+    }
+    __syncthreads();
+    if (tid == 0)
+      for (int q = 0; q < 4; ++q) base[q] += sc[q][255];
+    __syncthreads();
+  }
+  if (tid < 2) {
+    int* pl = plan + tid * plan_stride(nb);
+    pl[0] = base[2 * tid];
+    pl[1] = base[2 * tid + 1];
+    pl[2 + nb + base[2 * tid + 1]] = base[2 * tid];
+  }
+  if (tid < 16) plan[2 * plan_stride(nb) + tid] = 0;   // the work kernels' item counters
+}
+
 // One block per problem: reduce the tile partials in order and advance the phase.
 __global__ __launch_bounds__(256) void k_batch_control(const BDesc* __restrict__ descs,
                                                        BState* __restrict__ states, int K) {
@@ -629,63 +714,109 @@ constexpr int kBW = 8;
 static bool batch_k_ok(int K) { return K == 2 || K == 4 || K == 8; }
 
 // Second stream of a round: the FP64 work kernel runs beside the FP32 one.  Every problem
-// is in one phase, and each phase's tiles are worked by exactly one of the two kernels
-// (the other returns before touching anything), so the two write disjoint data; both
-// only read the states, which the control kernel updates after both have finished.
+// is in one phase, and the plan gives each problem's tiles to exactly one of the two kernels,
+// so the two write disjoint data; both only read the states, which the control kernel updates
+// after both have finished.
 struct RoundFork {
   hipStream_t s2 = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
 };
 
+// Persistent grid of a work kernel: the blocks that fit on the device at once (a multiple of
+// 8, one share per XCD).
+template <typename T, int K, bool VARC, int TAG>
+static int work_grid() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_work<T, K, kBR, kBW, VARC, TAG>, 64 * kBW, 0) !=
+          hipSuccess)
+    return 512;
+  const int g = (std::max(1, cus * per) / 8) * 8;
+  return std::max(8, g);
+}
+
+struct BatchGrids {
+  int g64 = 512;   // persistent blocks of the FP64 work kernel (mixed batches)
+};
+
 template <int K, bool VARC>
-static void launch_round_k(const BDesc* descs, BState* states, const int* ts, int ntiles,
-                           hipStream_t s, const RoundFork* rf) {
-  dim3 g(ntiles), b(64, kBW);
+static BatchGrids batch_grids_k() {
+  return BatchGrids{work_grid<double, K, VARC, 0>()};
+}
+
+static BatchGrids batch_grids(int K, bool varc) {
+  switch (K) {
+    case 2: return varc ? batch_grids_k<2, true>() : batch_grids_k<2, false>();
+    case 4: return varc ? batch_grids_k<4, true>() : batch_grids_k<4, false>();
+    default: return varc ? batch_grids_k<8, true>() : batch_grids_k<8, false>();
+  }
+}
+
+// What the launches of a round need.
+struct RoundArgs {
+  const BDesc* descs;
+  BState* states;
+  int* plan;
+  const int* tiles;
+  int ntiles, nb;
+  bool mixed;
+  BatchGrids grids;
+};
+
+template <int K, bool VARC>
+static void launch_round_k(const RoundArgs& a, hipStream_t s, const RoundFork* rf) {
+  const dim3 b(64, kBW);
+  const BState* st = a.states;
+  if (!a.mixed) {
+    // FP64 batch: every phase is FP64, one tile per block
+    hipLaunchKernelGGL((k_batch_tile<double, K, kBR, kBW, VARC>), dim3(a.ntiles), b, 0, s, a.descs, st, a.tiles,
+                       a.ntiles, 0);
+    return;
+  }
   hipStream_t s64 = s;
   if (rf) {
     (void)hipEventRecord(rf->fork, s);
     (void)hipStreamWaitEvent(rf->s2, rf->fork, 0);
     s64 = rf->s2;
   }
-  hipLaunchKernelGGL((k_batch_work<double, K, kBR, kBW, VARC>), g, b, 0, s64, descs,
-                     (const BState*)states, ts, ntiles, 0);
-  hipLaunchKernelGGL((k_batch_work<float, K, kBR, kBW, VARC>), g, b, 0, s, descs,
-                     (const BState*)states, ts, ntiles, 1);
+  // mixed batch: the few FP64 and element-wise tiles by persistent blocks over the plan, the
+  // FP32 stepping tiles one per block
+  hipLaunchKernelGGL((k_batch_work<double, K, kBR, kBW, VARC>), dim3(a.grids.g64), b, 0, s64, a.descs, st, a.plan,
+                     a.nb, 0);
+  hipLaunchKernelGGL((k_batch_tile<float, K, kBR, kBW, VARC>), dim3(a.ntiles), b, 0, s, a.descs, st, a.tiles,
+                     a.ntiles, 1);
   if (rf) {
     (void)hipEventRecord(rf->join, rf->s2);
     (void)hipStreamWaitEvent(s, rf->join, 0);
   }
 }
 
-static void launch_round(int K, bool varc, int nb, const BDesc* descs, BState* states,
-                         const int* ts, int ntiles, hipStream_t s, const RoundFork* rf = nullptr) {
+// One round: the work kernels, the control kernel (phases advance), and in mixed batches the
+// plan of the next round.
+static void launch_round(int K, bool varc, const RoundArgs& a, hipStream_t s, const RoundFork* rf = nullptr) {
   switch (K) {
-    case 2: varc ? launch_round_k<2, true>(descs, states, ts, ntiles, s, rf)
-                 : launch_round_k<2, false>(descs, states, ts, ntiles, s, rf); break;
-    case 4: varc ? launch_round_k<4, true>(descs, states, ts, ntiles, s, rf)
-                 : launch_round_k<4, false>(descs, states, ts, ntiles, s, rf); break;
-    default: varc ? launch_round_k<8, true>(descs, states, ts, ntiles, s, rf)
-                  : launch_round_k<8, false>(descs, states, ts, ntiles, s, rf); break;
+    case 2: varc ? launch_round_k<2, true>(a, s, rf) : launch_round_k<2, false>(a, s, rf); break;
+    case 4: varc ? launch_round_k<4, true>(a, s, rf) : launch_round_k<4, false>(a, s, rf); break;
+    default: varc ? launch_round_k<8, true>(a, s, rf) : launch_round_k<8, false>(a, s, rf); break;
   }
-  hipLaunchKernelGGL(k_batch_control, dim3(nb), dim3(256), 0, s, descs, states, K);
+  hipLaunchKernelGGL(k_batch_control, dim3(a.nb), dim3(256), 0, s, a.descs, a.states, K);
+  if (a.mixed)
+    hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(256), 0, s, a.descs, (const BState*)a.states, a.nb, a.plan);
 }
 
-// The FP32 work kernel alone, under its measurement tag (wh_time_batch_kernel).
+// The FP32 stepping kernel alone, under its measurement tag (wh_time_batch_kernel).
 template <int K, bool VARC>
-static void launch_work_tagged(const BDesc* descs, const BState* states, const int* ts, int ntiles, hipStream_t s) {
-  hipLaunchKernelGGL((k_batch_work<float, K, kBR, kBW, VARC, 1>), dim3(ntiles), dim3(64, kBW), 0, s, descs, states,
-                     ts, ntiles, 1);
+static void launch_work_tagged(const RoundArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_batch_tile<float, K, kBR, kBW, VARC, 1>), dim3(a.ntiles), dim3(64, kBW), 0, s, a.descs,
+                     (const BState*)a.states, a.tiles, a.ntiles, 1);
 }
 
-static void launch_work_timing(int K, bool varc, const BDesc* descs, const BState* states, const int* ts, int ntiles,
-                               hipStream_t s) {
+static void launch_work_timing(int K, bool varc, const RoundArgs& a, hipStream_t s) {
   switch (K) {
-    case 2: varc ? launch_work_tagged<2, true>(descs, states, ts, ntiles, s)
-                 : launch_work_tagged<2, false>(descs, states, ts, ntiles, s); break;
-    case 4: varc ? launch_work_tagged<4, true>(descs, states, ts, ntiles, s)
-                 : launch_work_tagged<4, false>(descs, states, ts, ntiles, s); break;
-    default: varc ? launch_work_tagged<8, true>(descs, states, ts, ntiles, s)
-                  : launch_work_tagged<8, false>(descs, states, ts, ntiles, s); break;
+    case 2: varc ? launch_work_tagged<2, true>(a, s) : launch_work_tagged<2, false>(a, s); break;
+    case 4: varc ? launch_work_tagged<4, true>(a, s) : launch_work_tagged<4, false>(a, s); break;
+    default: varc ? launch_work_tagged<8, true>(a, s) : launch_work_tagged<8, false>(a, s); break;
   }
 }
 
@@ -766,6 +897,7 @@ struct Prepared {
 
 wh_status batch_validate(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const wh_params* P) {
   if (nb < 1 || !probs || !P) WHB_FAIL(ctx, WH_EINVAL, "need nb >= 1 problems and params");
+  if (nb > kMaxBatch) WHB_FAIL(ctx, WH_EINVAL, "at most %d problems per batch", kMaxBatch);
   if (P->precision != WH_F64 && P->precision != WH_MIXED) WHB_FAIL(ctx, WH_EINVAL, "bad precision");
   if (P->solver != WH_CG && P->solver != WH_DCG)
     WHB_FAIL(ctx, WH_EUNSUPPORTED, "batched solves use CG or DCG");
@@ -876,8 +1008,10 @@ struct BatchSetup {
   bool mixed = false, varc = false;
   BDesc* ddesc = nullptr;
   BState* dstate = nullptr;
-  int* dtiles = nullptr;
+  int* dplan = nullptr;      // the two class plans of the next round (plan_stride(nb) ints each)
+  int* dtiles = nullptr;     // block -> problem of every tile (one-tile-per-block kernels)
   int* dremain = nullptr;
+  BatchGrids grids;
 };
 
 wh_status prepare_batch(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const wh_params* params,
@@ -966,6 +1100,7 @@ wh_status prepare_batch(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const 
   char* dscratch = dscr ? (char*)take(dscr) : nullptr;
   BDesc* ddesc = (BDesc*)take(sizeof(BDesc) * nb);
   BState* dstate = (BState*)take(sizeof(BState) * nb);
+  int* dplan = (int*)take(4 * (2 * (size_t)plan_stride(nb) + 16));
   int* dtiles = (int*)take(4 * (size_t)ntiles);
   int* dremain = (int*)take(256);
   if (cur_off > ws_bytes) WHB_FAIL(ctx, WH_EWORKSPACE, "workspace too small (layout %zu)", cur_off);
@@ -1014,6 +1149,8 @@ wh_status prepare_batch(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const 
   std::memset(S0.data(), 0, sizeof(BState) * nb);
   for (auto& st : S0) st.phase = BP_B_FIRST;
   HIPB(ctx, hipMemcpyAsync(dstate, S0.data(), sizeof(BState) * nb, hipMemcpyHostToDevice, s));
+  // the plan of the first round
+  hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(256), 0, s, (const BDesc*)ddesc, (const BState*)dstate, nb, dplan);
   HIPB(ctx, hipStreamSynchronize(s));
   HIPB(ctx, hipGetLastError());
   B.tps = std::move(tps);
@@ -1024,7 +1161,9 @@ wh_status prepare_batch(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const 
   B.varc = varc;
   B.ddesc = ddesc;
   B.dstate = dstate;
+  B.dplan = dplan;
   B.dtiles = dtiles;
+  B.grids = batch_grids(K, varc);
   B.dremain = dremain;
   return WH_OK;
 }
@@ -1041,21 +1180,22 @@ size_t wh_workspace_bytes_batched(int32_t nb, const wh_problem* probs, const wh_
   const int K = batch_K(params);
   const double cmax = params->c_max > 0 ? params->c_max : 1.0;
   size_t total = 0;
-  int ntiles = 0;
   for (int i = 0; i < nb; ++i) {
     wh_params p = *params;
     p.omega = probs[i].omega;
     TimeParams tp;
     if (make_time_params(nullptr, 2, probs[i].grid.n, p, cmax, tp) != WH_OK) return 0;
     total += problem_bytes(probs[i].grid.n, tp.nt, K, mixed, varc);
-    ntiles += tile_dim(probs[i].grid.n, K, 0) * tile_dim(probs[i].grid.n, K, 1);
   }
   size_t dscr = 0;
   for (int i = 0; i < nb; ++i) dscr = std::max(dscr, defl_scratch_bytes(probs[i].grid.n, probs[i].n_defl));
   total += dscr;
   total += 16 * (size_t)kReduceBlocks;  // c_max reductions (multiple of 256)
   total += ((sizeof(BDesc) * nb + 255) & ~(size_t)255) + ((sizeof(BState) * nb + 255) & ~(size_t)255);
-  total += ((4 * (size_t)ntiles + 255) & ~(size_t)255) + 256;
+  total += ((4 * (2 * (size_t)plan_stride(nb) + 16) + 255) & ~(size_t)255) + 256;
+  size_t ntl = 0;
+  for (int i = 0; i < nb; ++i) ntl += (size_t)tile_dim(probs[i].grid.n, K, 0) * tile_dim(probs[i].grid.n, K, 1);
+  total += (4 * ntl + 255) & ~(size_t)255;
   return total;
   });
 }
@@ -1074,12 +1214,11 @@ wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
   const bool mixed = B.mixed;
   const bool varc = B.varc;
   const int K = B.K;
-  const int ntiles = B.ntiles;
   std::vector<BDesc>& D = B.D;
   std::vector<TimeParams>& tps = B.tps;
   BDesc* ddesc = B.ddesc;
   BState* dstate = B.dstate;
-  int* dtiles = B.dtiles;
+  int* dplan = B.dplan;
   int* dremain = B.dremain;
 
   // Capture G rounds + the counter in a graph on a private stream, twice (two
@@ -1104,7 +1243,8 @@ wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
       for (int g = 0; g < G; ++g)
-        launch_round(K, varc, nb, ddesc, dstate, dtiles, ntiles, cs, use_fork ? &rf : nullptr);
+        launch_round(K, varc, RoundArgs{ddesc, dstate, dplan, B.dtiles, B.ntiles, nb, mixed, B.grids}, cs,
+                     use_fork ? &rf : nullptr);
       hipLaunchKernelGGL(k_batch_count, dim3(1), dim3(256), 0, cs, (const BState*)dstate, nb, dcount[gi]);
       e = hipStreamEndCapture(cs, &graph[gi]);
     }
@@ -1229,8 +1369,10 @@ wh_status wh_time_batch_kernel(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
     st.step = 1;
   }
   HIPB(ctx, hipMemcpyAsync(B.dstate, S.data(), sizeof(BState) * nb, hipMemcpyHostToDevice, s));
+  const RoundArgs ra{B.ddesc, B.dstate, B.dplan, B.dtiles, B.ntiles, nb, true, B.grids};
+  auto one = [&]() { launch_work_timing(B.K, B.varc, ra, s); };
   HIPB(ctx, hipStreamSynchronize(s));
-  launch_work_timing(B.K, B.varc, B.ddesc, B.dstate, B.dtiles, B.ntiles, s);
+  one();
   hipEvent_t e0, e1;
   HIPB(ctx, hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -1238,7 +1380,7 @@ wh_status wh_time_batch_kernel(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
     WHB_FAIL(ctx, WH_EHIP, "hipEventCreate failed");
   }
   (void)hipEventRecord(e0, s);
-  for (int r = 0; r < reps; ++r) launch_work_timing(B.K, B.varc, B.ddesc, B.dstate, B.dtiles, B.ntiles, s);
+  for (int r = 0; r < reps; ++r) one();
   (void)hipEventRecord(e1, s);
   hipError_t e = hipEventSynchronize(e1);
   float ms = 0;

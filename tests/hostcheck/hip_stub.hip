@@ -27,6 +27,7 @@
 #include <string>
 #include <vector>
 
+#include "../../paper_2606_31842_amd/csrc/wh_batched.h"
 #include "../../paper_2606_31842_amd/csrc/wh_fused_kernel.h"
 
 using namespace wh;
@@ -359,6 +360,140 @@ void model_adj_step2d(dim3 g, dim3 b, void** args) {
   for (Span* s : {&L1, &L2, &LO, &WW, &Kp, &Z, &G}) s->check();
 }
 
+
+// ---- batched solver: the plan kernel is emulated (so that the work kernels see a real plan)
+// and every work item's tile is checked against its problem's arrays
+int batch_class(const BDesc& d, const BState& st) {
+  if (st.phase == BP_DONE) return -1;
+  const int prec = phase_prec(st.phase, d.mixed && !st.force64);
+  const bool stepping = st.phase != BP_INIT && st.phase != BP_UPD1 && st.phase != BP_UPD2;
+  return (stepping && prec == 1) ? 1 : 0;
+}
+
+void model_batch_plan(dim3 g, dim3 b, void** args) {
+  const BDesc* descs = arg<const BDesc*>(args, 0);
+  const BState* states = arg<const BState*>(args, 1);
+  const int nb = arg<int>(args, 2);
+  int* plan = arg<int*>(args, 3);
+  if (g.x != 1 || b.x != 256) fail("plan launch shape");
+  check_range(descs, 0, (int64_t)sizeof(BDesc) * nb, "descs");
+  check_range(states, 0, (int64_t)sizeof(BState) * nb, "states");
+  check_range(plan, 0, 4LL * (2 * plan_stride(nb) + 16), "plan");
+  int tiles[2] = {0, 0}, act[2] = {0, 0};
+  for (int i = 0; i < nb; ++i) {
+    const int c = batch_class(descs[i], states[i]);
+    if (c < 0) continue;
+    int* pl = plan + c * plan_stride(nb);
+    pl[2 + act[c]] = i;
+    pl[2 + nb + act[c]] = tiles[c];
+    act[c]++;
+    tiles[c] += descs[i].ntx * descs[i].nty;
+  }
+  for (int c = 0; c < 2; ++c) {
+    int* pl = plan + c * plan_stride(nb);
+    pl[0] = tiles[c];
+    pl[1] = act[c];
+    pl[2 + nb + act[c]] = tiles[c];
+  }
+  for (int k = 0; k < 16; ++k) plan[2 * plan_stride(nb) + k] = 0;
+}
+
+void check_batch_item(const BDesc* descs, const BState* states, int nb, int sid, int lt, int want, int K, int R,
+                      int NW, int VARC, int it) {
+  const int TXO = 64 - 2 * K, TYO = NW * R - 2 * K;
+      if (sid < 0 || sid >= nb) fail("item %d maps to problem %d", it, sid);
+      const BDesc& d = descs[sid];
+      const BState& st = states[sid];
+      if (batch_class(d, st) != want) fail("item %d of problem %d is in the other class", it, sid);
+      if (lt < 0 || lt >= d.ntx * d.nty) fail("item %d: tile %d of problem %d out of %d", it, lt, sid, d.ntx * d.nty);
+      const int n = d.n;
+      const int64_t P = (int64_t)n + 1, N = P * P;
+      const int x0 = 1 + (lt % d.ntx) * TXO, y0 = 1 + (lt / d.ntx) * TYO;
+      if (x0 > n - 1 || y0 > n - 1) fail("tile origin (%d, %d) outside the grid n = %d", x0, y0, n);
+      // nodes the phase can touch: the tile's register region (with its halo) clipped to the
+      // interior, and their neighbours
+      const int ya = std::max(1, y0 - K), yb = std::min(n - 1, y0 - K + NW * R - 1);
+      const int xa = std::max(1, x0 - K), xb = std::min(n - 1, x0 - K + 63);
+      const int64_t lo_i = (int64_t)(ya - 1) * P + xa - 1, hi_i = (int64_t)(yb + 1) * P + xb + 1;
+      if (lo_i < 0 || hi_i >= N) fail("tile node range [%lld, %lld] outside 0..%lld", (long long)lo_i,
+                                      (long long)hi_i, (long long)N - 1);
+      const size_t TS = want == 1 ? 4 : 8;
+      auto arr = [&](const void* ptr, size_t esz, const char* what) {
+        if (ptr) check_range(ptr, lo_i * (int64_t)esz, (hi_i + 1) * (int64_t)esz, what);
+      };
+      arr(d.x, 8, "x"); arr(d.b, 8, "b"); arr(d.r, 8, "r"); arr(d.p, 8, "p"); arr(d.q, 8, "q"); arr(d.V, 8, "V");
+      for (int k = 0; k < 4; ++k) arr(TS == 8 ? d.W[k] : d.W32[k], TS, "state");
+      if (VARC) arr(TS == 8 ? (const void*)d.kap64 : (const void*)d.kap32, TS, "kap");
+      arr(TS == 8 ? (const void*)d.fs64 : (const void*)d.fs32, TS, "fs");
+      check_range(d.partials, 8LL * lt, 8LL * (lt + 1), "partials");
+      check_range(d.w, 0, 8LL * (d.nt + 1), "weights");
+      check_range(d.cosv, 0, 8LL * (d.nt + 1), "cosines");
+      if (st.phase == BP_A_STEP || st.phase == BP_B_STEP || st.phase == BP_R_STEP) {
+        const int Kp = std::min(K, d.nt - 1 - st.step);
+        if (Kp < 1 || st.step + Kp > d.nt) fail("step %d + %d beyond N_t = %d", st.step, Kp, d.nt);
+      }
+}
+
+void model_batch_work(const std::vector<std::string>& t, dim3 g, dim3 b, void** args) {
+  const int K = ti(t, 1), R = ti(t, 2), NW = ti(t, 3), VARC = ti(t, 4);
+  const BDesc* descs = arg<const BDesc*>(args, 0);
+  const BState* states = arg<const BState*>(args, 1);
+  const int* plan = arg<const int*>(args, 2);
+  const int nb = arg<int>(args, 3), want = arg<int>(args, 4);
+  if (g.x % 8 != 0 || g.x == 0) fail("persistent grid %u is not a positive multiple of 8", g.x);
+  (void)g;
+  if ((int)b.x != 64 || (int)b.y != NW) fail("block shape");
+  const int* pl = plan + want * plan_stride(nb);
+  const int total = pl[0], nact = pl[1];
+  if (nact < 0 || nact > nb || total < 0) fail("plan header (%d tiles, %d problems)", total, nact);
+  const int* pid = pl + 2;
+  const int* start = pl + 2 + nb;
+  std::vector<int> hit(total, 0);
+  check_range(plan + 2 * plan_stride(nb) + 8 * want, 0, 32, "item counters");
+  const int TXO = 64 - 2 * K, TYO = NW * R - 2 * K;
+  // items are taken dynamically from the 8 chunk counters; every item of [0, total) is taken once
+  for (int c = 0; c < 8; ++c) {
+    const int c0 = (int)((int64_t)total * c / 8), c1 = (int)((int64_t)total * (c + 1) / 8);
+    for (int it = c0; it < c1; ++it) {
+      int lo = 0, hi = nact - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= it) lo = mid;
+        else hi = mid - 1;
+      }
+      hit[it]++;
+      check_batch_item(descs, states, nb, pid[lo], it - start[lo], want, K, R, NW, VARC, it);
+    }
+  }
+  for (int i = 0; i < total; ++i)
+    if (hit[i] != 1) fail("work item %d visited %d times", i, hit[i]);
+}
+
+void model_batch_tile(const std::vector<std::string>& t, dim3 g, dim3 b, void** args) {
+  const int K = ti(t, 1), R = ti(t, 2), NW = ti(t, 3), VARC = ti(t, 4);
+  const BDesc* descs = arg<const BDesc*>(args, 0);
+  const BState* states = arg<const BState*>(args, 1);
+  const int* tiles = arg<const int*>(args, 2);
+  const int ntiles = arg<int>(args, 3), want = arg<int>(args, 4);
+  if ((int)g.x != ntiles) fail("grid %u != %d tiles", g.x, ntiles);
+  if ((int)b.x != 64 || (int)b.y != NW) fail("block shape");
+  check_range(tiles, 0, 4LL * ntiles, "tile table");
+  std::vector<char> seen(ntiles, 0);
+  int nb = 0;
+  for (int i = 0; i < ntiles; ++i) nb = std::max(nb, tiles[i] + 1);
+  for (int bid = 0; bid < ntiles; ++bid) {
+    const int gt = xcd_tile_host(bid, ntiles);
+    if (gt < 0 || gt >= ntiles || seen[gt]) fail("XCD tile map is not a permutation");
+    seen[gt] = 1;
+    const int sid = tiles[gt];
+    const BDesc& d = descs[sid];
+    const BState& st = states[sid];
+    if (batch_class(d, st) != want) continue;
+    if (gt < d.tile0 || gt >= d.tile0 + d.ntx * d.nty) fail("tile %d outside problem %d's range", gt, sid);
+    check_batch_item(descs, states, nb, sid, gt - d.tile0, want, K, R, NW, VARC, gt);
+  }
+}
+
 void vec(const void* p, int64_t count, size_t esz, const char* what) {
   if (p && count > 0) check_range(p, 0, count * (int64_t)esz, what);
 }
@@ -468,6 +603,9 @@ void check_launch(const void* fn, dim3 g, dim3 b, void** args) {
   else if (base == "k_first") model_first(t, g, b, args);
   else if (base == "k_fwd_out2d") model_fwd_out2d(g, b, args);
   else if (base == "k_adj_step2d") model_adj_step2d(g, b, args);
+  else if (base == "k_batch_plan") model_batch_plan(g, b, args);
+  else if (base == "k_batch_work") model_batch_work(t, g, b, args);
+  else if (base == "k_batch_tile") model_batch_tile(t, g, b, args);
   else done = model_generic(base, t, g, b, args);
   if (done) ++g_modelled;
   else ++g_unmodelled[base];
