@@ -75,7 +75,7 @@ typedef enum {
   WH_DEFL_SINE = 1,        /* analytic Dirichlet modes (2/n)^{dim/2} prod sin(k pi x) (c == 1 only);
                               the eigenvalues of A on them are known in closed form      */
   WH_DEFL_DENSE_EXACT = 2, /* dense columns that are eigenvectors of L_h with given lambda2 */
-  WH_DEFL_DENSE = 3,       /* any dense l2-orthonormal columns; A W costs n_d wave solves   */
+  WH_DEFL_DENSE = 3,       /* any dense l2-orthonormal columns (DCG); A W costs n_d wave solves */
   WH_DEFL_FACTORED = 4     /* 2D eigenvectors of L_h with given lambda2, each a sum of separable
                               terms fy_t(y) fx_t(x) (e.g. a truncated SVD of the mode as an
                               (n+1) x (n+1) array, the compression of Section 4.3); projected
@@ -245,8 +245,12 @@ wh_status wh_apply_filter_noalloc(wh_ctx* ctx, const wh_grid* grid, const double
 
 /* Solve A u = b, b = Pi_h(0; f), by params->solver; the fixed point is the discrete
  * Helmholtz solution (L_h + omega^2) u = f (Sections 2.1-2.2).  u: device nodal, in:
- * initial guess, out: solution.  defl (exact eigenvectors) is required for WH_DCG
- * (Algorithm 3), augments WH_GMRES (Algorithm 4: W heads the Arnoldi basis, A W =
+ * initial guess, out: solution.  defl is required for WH_DCG (Algorithm 3): exact
+ * eigenvectors (sine, dense-exact, factored) or, with WH_DEFL_DENSE, any l2-orthonormal
+ * columns, for which A W is formed by n_d FP64 wave solves before the iteration, (W^T A W)^{-1}
+ * is formed on the host from the symmetrised projections, and every iteration re-projects
+ * (eta = (A W)^T r, mu = (W^T A W)^{-1} eta, p = beta p + r - W mu).  Exact eigenvectors also
+ * augment WH_GMRES (Algorithm 4: W heads the Arnoldi basis, A W =
  * W diag(mu)) and WH_BICGSTAB (Algorithm 5: the thin QR of A W is W diag(mu), every
  * A-product is projected off W and the W part of the solution is recovered at the
  * end), or with params->devd wraps FPI / CG / GMRES / BiCGStab in Algorithm 2; else

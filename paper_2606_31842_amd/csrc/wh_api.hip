@@ -138,6 +138,7 @@ struct Layout {
   size_t b = 0, r = 0, p = 0, q = 0, ro = 0, d = 0, basis = 0, p2 = 0;
   bool has_p2 = false;   // CG/DCG: second direction buffer for the look-ahead
   size_t partials = 0, partials2 = 0, slots = 0, tab = 0, modes = 0, invmu = 0, ones = 0, tsum = 0;
+  size_t aw = 0, einv = 0;   // general deflation vectors: A W (N x n_d) and (W^T A W)^{-1}
   int64_t N = 0;
   int nslots = 0, npart = 0;
 };
@@ -224,6 +225,10 @@ Layout make_layout(const wh_grid& g, const wh_params& P, const wh_deflation* def
     L.invmu = take(L, 8 * (size_t)nd);
     L.ones = take(L, 8 * (size_t)nd);
     L.tsum = take(L, 8 * 2 * (size_t)nrow);   // factored: per-term sums and coefficients
+    if (dd.kind == WH_DEFL_DENSE) {
+      L.aw = take(L, 8 * (size_t)N * nd);
+      L.einv = take(L, 8 * (size_t)nd * nd);
+    }
   }
   return L;
 }
@@ -297,7 +302,8 @@ wh_status check_defl(wh_ctx* ctx, const wh_grid* g, const wh_deflation* d, bool 
     if (!d->V || !d->lambda2) WH_FAIL(ctx, WH_EINVAL, "dense deflation needs V and lambda2");
     if (d->ldv < nodal_count(g->dim, g->n)) WH_FAIL(ctx, WH_EINVAL, "ldv too small");
   } else if (d->kind == WH_DEFL_DENSE) {
-    WH_FAIL(ctx, WH_EUNSUPPORTED, "general dense deflation (A W by wave solves) is not built");
+    if (!d->V) WH_FAIL(ctx, WH_EINVAL, "dense deflation needs V");
+    if (d->ldv < nodal_count(g->dim, g->n)) WH_FAIL(ctx, WH_EINVAL, "ldv too small");
   } else if (d->kind == WH_DEFL_FACTORED) {
     if (g->dim != 2) WH_FAIL(ctx, WH_EUNSUPPORTED, "factored deflation vectors are 2D");
     if (!d->fx || !d->fy || !d->lambda2 || !d->term_mode)
@@ -711,6 +717,10 @@ struct Solver {
   double om2dt2 = 0;               // omega^2 dt^2
   double reliable_drop = 0.1;  // mixed CG: residual reduction between FP64 replacements
   std::vector<double> mu;          // mu_k = 1 - beta_h(lambda_k^2) of the deflation set (host)
+  // general deflation vectors (not eigenvectors): A W and (W^T A W)^{-1}, row-major (device)
+  bool general = false;
+  Defl defl_aw;
+  const double* einv = nullptr;
 };
 
 // q = A x (x nonzero).  Leaves partial sums of x.q in op.partials.
@@ -785,7 +795,21 @@ wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_non
   } else {
     launch_copy(r, rhs, N, S.s);
   }
-  if (nd) {
+  if (nd && S.general) {
+    // general vectors: x_0 = x_{-1} + W (W^T A W)^{-1} W^T r_{-1}; r_0 = rhs - A x_0;
+    // mu_0 = (W^T A W)^{-1} (A W)^T r_0 (A symmetric); p_0 = r_0 - W mu_0.  The coefficients
+    // are formed in slots [S_H + nd, S_H + 2 nd) from the projections in [S_H, S_H + nd).
+    launch_defl_project(S.defl, r, S.partials, S.s);
+    launch_defl_reduce_set(S.defl, S.partials, S.slots, S_H, nullptr, S.s);
+    launch_small_matvec(S.einv, nd, S.slots, S_H, S_H + nd, -1.0, S.s);
+    launch_defl_combine(S.defl, x, 1.0, nullptr, 0.0, S.slots, S_H + nd, N, S.s);
+    applyA(S, f32_true, x, q);
+    launch_sub(r, rhs, q, N, S.s);
+    launch_defl_project(S.defl_aw, r, S.partials, S.s);
+    launch_defl_reduce_set(S.defl_aw, S.partials, S.slots, S_H, nullptr, S.s);
+    launch_small_matvec(S.einv, nd, S.slots, S_H, S_H + nd, 1.0, S.s);
+    launch_defl_combine(S.defl, p, 0.0, r, 1.0, S.slots, S_H + nd, N, S.s);
+  } else if (nd) {
     // x_0 = x_{-1} + W (W^T A W)^{-1} W^T r_{-1}
     launch_defl_project(S.defl, r, S.partials, S.s);
     launch_defl_reduce_set(S.defl, S.partials, S.slots, S_H, S.negmu, S.s);
@@ -826,7 +850,7 @@ wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_non
   double* pc = p;                 // this iteration's direction
   int nb_ahead = -1;              // >= 0: A pc is already queued (its partial-sum count)
   bool ahead_f32 = false;
-  const bool can_ahead = S.p2 != nullptr && !(nd && reproject);
+  const bool can_ahead = S.p2 != nullptr && !(nd && (reproject || S.general));
   auto discard_ahead = [&]() {
     if (nb_ahead >= 0) (ahead_f32 ? S.ws32 : S.ws64)--;
     nb_ahead = -1;
@@ -890,6 +914,12 @@ wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_non
     }
     if (nb_ahead >= 0) {
       pc = pn;   // the look-ahead direction stands
+    } else if (nd && S.general) {
+      // Algorithm 3: eta = (A W)^T r, mu = (W^T A W)^{-1} eta, p = beta p + r - W mu
+      launch_defl_project(S.defl_aw, r, S.partials, S.s);
+      launch_defl_reduce_set(S.defl_aw, S.partials, S.slots, S_H, nullptr, S.s);
+      launch_small_matvec(S.einv, nd, S.slots, S_H, S_H + nd, 1.0, S.s);
+      launch_dcg_update2(S.defl, pc, r, S.slots, S_H + nd, N, S.s);
     } else if (nd && reproject) {
       launch_defl_project(S.defl, r, S.partials, S.s);
       launch_defl_reduce_set(S.defl, S.partials, S.slots, S_H, nullptr, S.s);
@@ -1375,6 +1405,73 @@ wh_status setup_ops(wh_ctx* ctx, const wh_grid& g, const wh_params& P, const dou
   return WH_OK;
 }
 
+// Inverse of a small dense matrix (row-major, n x n) by Gauss-Jordan elimination with partial
+// pivoting; false if a pivot vanishes.
+bool invert_small(std::vector<double> a, int n, std::vector<double>& inv) {
+  inv.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(a[(size_t)r * n + c]) > std::fabs(a[(size_t)piv * n + c])) piv = r;
+    const double pv = a[(size_t)piv * n + c];
+    if (!(std::fabs(pv) > 0) || !std::isfinite(pv)) return false;
+    if (piv != c)
+      for (int j = 0; j < n; ++j) {
+        std::swap(a[(size_t)piv * n + j], a[(size_t)c * n + j]);
+        std::swap(inv[(size_t)piv * n + j], inv[(size_t)c * n + j]);
+      }
+    const double d = 1.0 / pv;
+    for (int j = 0; j < n; ++j) {
+      a[(size_t)c * n + j] *= d;
+      inv[(size_t)c * n + j] *= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double m = a[(size_t)r * n + c];
+      if (m == 0.0) continue;
+      for (int j = 0; j < n; ++j) {
+        a[(size_t)r * n + j] -= m * a[(size_t)c * n + j];
+        inv[(size_t)r * n + j] -= m * inv[(size_t)c * n + j];
+      }
+    }
+  }
+  return true;
+}
+
+// Algorithm 3 with any l2-orthonormal deflation vectors W (not eigenvectors): A W by n_d FP64
+// wave solves (the start-up cost of Section 5.1), E = W^T A W by projections, and E^{-1} formed
+// on the host (E symmetrised, A being symmetric) for the per-iteration mu = E^{-1} (A W)^T r.
+wh_status setup_general_deflation(Solver& S, void* ws, const Layout& L, const double* V, int64_t ldv, int nd) {
+  wh_ctx* ctx = S.ctx;
+  hipStream_t s = S.s;
+  const int64_t N = S.N;
+  double* aw = at<double>(ws, L.aw);
+  for (int k = 0; k < nd; ++k) applyA(S, false, V + (size_t)k * ldv, aw + (size_t)k * N);
+  double* E = at<double>(ws, L.einv);   // E first, then its inverse
+  for (int k = 0; k < nd; ++k) {
+    launch_defl_project(S.defl, aw + (size_t)k * N, S.partials, s);
+    launch_defl_reduce(S.partials, defl_partial_blocks(S.defl), nd, E, k * nd, nullptr, s);  // E[k][i] = w_i^T A w_k
+  }
+  std::vector<double> eh((size_t)nd * nd), es((size_t)nd * nd), inv;
+  HIPCHK(ctx, hipMemcpyAsync(eh.data(), E, 8 * eh.size(), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  for (int i = 0; i < nd; ++i)
+    for (int j = 0; j < nd; ++j) es[(size_t)i * nd + j] = 0.5 * (eh[(size_t)i * nd + j] + eh[(size_t)j * nd + i]);
+  if (!invert_small(es, nd, inv)) WH_FAIL(ctx, WH_EBREAKDOWN, "W^T A W is singular");
+  HIPCHK(ctx, hipMemcpyAsync(E, inv.data(), 8 * inv.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  S.general = true;
+  S.defl_aw.kind = WH_DEFL_DENSE;
+  S.defl_aw.nd = nd;
+  S.defl_aw.dim = S.defl.dim;
+  S.defl_aw.n = S.defl.n;
+  S.defl_aw.V = aw;
+  S.defl_aw.ldv = N;
+  S.einv = E;
+  return WH_OK;
+}
+
 void fill_info(wh_info* info, const TimeParams& tp, int k_fuse, const WaveOp* op = nullptr) {
   if (!info) return;
   info->nt = tp.nt;
@@ -1741,6 +1838,8 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
   if (P.devd == 2 && P.solver != WH_FPI) WH_FAIL(ctx, WH_EINVAL, "devd = 2 (deflated iterates) is for FPI");
   if (!devd && (P.solver == WH_FPI || P.solver == WH_CG) && nd > 0)
     WH_FAIL(ctx, WH_EUNSUPPORTED, "a deflation set is used by DCG, augmented GMRES / BiCGStab or devd");
+  if (nd > 0 && defl->kind == WH_DEFL_DENSE && P.solver != WH_DCG)
+    WH_FAIL(ctx, WH_EUNSUPPORTED, "general deflation vectors (WH_DEFL_DENSE) are used by DCG");
   // GMRES / BiCGStab with a deflation set (and no devd) are the augmented methods of
   // Algorithms 4 and 5
   const bool agmres = (P.solver == WH_GMRES || P.solver == WH_BICGSTAB) && nd > 0 && !devd;
@@ -1826,6 +1925,10 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
       S.defl.toff = mdev + T;
       S.defl.tsum = at<double>(ws, L.tsum);
       S.defl.tcoef = at<double>(ws, L.tsum) + T;
+    } else if (defl->kind == WH_DEFL_DENSE) {
+      S.defl.V = defl->V;
+      S.defl.ldv = defl->ldv;
+      WHCHK(setup_general_deflation(S, ws, L, defl->V, defl->ldv, nd));
     } else {
       for (int k = 0; k < nd; ++k) lam2[k] = defl->lambda2[k];
       S.defl.V = defl->V;
@@ -1833,17 +1936,19 @@ wh_status wh_solve(wh_ctx* ctx, const wh_grid* grid, const double* c2, const dou
     }
     std::vector<double> inv(nd), neg(nd);
     S.mu.assign(nd, 0.0);
-    for (int k = 0; k < nd; ++k) {
+    for (int k = 0; k < nd && !S.general; ++k) {
       const double mu = 1.0 - transfer(tp, lam2[k]);
       S.mu[k] = mu;
       if (mu == 0.0) WH_FAIL(ctx, WH_EBREAKDOWN, "deflation vector %d is at resonance (mu = 0)", k);
       inv[k] = 1.0 / mu;
       neg[k] = -1.0 / mu;
     }
-    WHCHK(upload(ctx, at<double>(ws, L.invmu), inv.data(), nd));
-    WHCHK(upload(ctx, at<double>(ws, L.ones), neg.data(), nd));
-    S.invmu = at<double>(ws, L.invmu);
-    S.negmu = at<double>(ws, L.ones);
+    if (!S.general) {
+      WHCHK(upload(ctx, at<double>(ws, L.invmu), inv.data(), nd));
+      WHCHK(upload(ctx, at<double>(ws, L.ones), neg.data(), nd));
+      S.invmu = at<double>(ws, L.invmu);
+      S.negmu = at<double>(ws, L.ones);
+    }
     if (devd) {
       // Algorithm 2: f_d = f - W W^T f (into r, then the forcing arrays are rebuilt from it);
       // ones <- -(phi_k^T f) / (omega_fp^2 - lambda_k^2), added to the solution at the end

@@ -768,4 +768,22 @@ void launch_dcg_update2(const Defl& d, double* p, const double* r, const double*
   combine_impl(d, p, 0.0, S_BETA, r, 1.0, slots, src, N, s);
 }
 
+// slots[dst + k] = scale * sum_j M[k][j] slots[src + j], k < nd (M row-major nd x nd; the two
+// slot ranges do not overlap).  One block; the right-hand side is staged in LDS.
+__global__ __launch_bounds__(256) void k_small_matvec(const double* M, int nd, double* slots, int src, int dst,
+                                                      double scale) {
+  __shared__ double v[1024];
+  for (int j = threadIdx.x; j < nd; j += blockDim.x) v[j] = slots[src + j];
+  __syncthreads();
+  for (int k = threadIdx.x; k < nd; k += blockDim.x) {
+    double acc = 0.0;
+    for (int j = 0; j < nd; ++j) acc += M[(int64_t)k * nd + j] * v[j];
+    slots[dst + k] = scale * acc;
+  }
+}
+
+void launch_small_matvec(const double* M, int nd, double* slots, int src, int dst, double scale, hipStream_t s) {
+  hipLaunchKernelGGL(k_small_matvec, dim3(1), dim3(256), 0, s, M, nd, slots, src, dst, scale);
+}
+
 }  // namespace wh

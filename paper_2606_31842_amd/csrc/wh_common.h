@@ -302,5 +302,7 @@ void launch_dcg_update2(const Defl& d, double* p, const double* r, const double*
                         int64_t N, hipStream_t s);
 void launch_sine_tables(double* tab, const int32_t* modes_dev, int nd, int dim, int n,
                         hipStream_t s);
+// slots[dst + k] = scale * (M slots[src ..])_k for a row-major nd x nd matrix M (nd <= 1024)
+void launch_small_matvec(const double* M, int nd, double* slots, int src, int dst, double scale, hipStream_t s);
 
 }  // namespace wh

@@ -177,6 +177,11 @@ void solve_case(int dim, int n, int solver, int precision, bool varc, int k_fuse
     d.n_d = nd;
     if (defl_kind == WH_DEFL_SINE) {
       d.modes = modes.data();
+    } else if (defl_kind == WH_DEFL_DENSE) {
+      V = new Buf(8 * N * nd, "deflation columns");
+      fill_field(V->d(), dim, n, 0.0, 0.1, seed + 7);
+      d.V = V->d();
+      d.ldv = (int64_t)N;
     } else if (defl_kind == WH_DEFL_DENSE_EXACT) {
       V = new Buf(8 * N * nd, "deflation columns");
       fill_field(V->d(), dim, n, 0.0, 0.1, seed + 7);
@@ -341,6 +346,8 @@ int main(int argc, char** argv) {
         solve_case(2, n, WH_DCG, prec, false, 0, -1, 3, WH_DEFL_SINE, seed);
         solve_case(2, n, WH_DCG, prec, false, 0, -1, 3, WH_DEFL_DENSE_EXACT, seed);
         solve_case(2, n, WH_DCG, prec, false, 0, -1, 3, WH_DEFL_FACTORED, seed);
+        solve_case(2, n, WH_DCG, prec, true, 0, -1, 4, WH_DEFL_DENSE, seed);
+        solve_case(3, n / 4 + 4, WH_DCG, prec, true, 0, -1, 3, WH_DEFL_DENSE, seed);
         solve_case(2, n, WH_GMRES, prec, false, 0, -1, 3, WH_DEFL_SINE, seed, 0, 5);
         solve_case(2, n, WH_BICGSTAB, prec, false, 0, -1, 3, WH_DEFL_SINE, seed);
         solve_case(2, n, WH_CG, prec, false, 0, -1, 3, WH_DEFL_SINE, seed, 1);

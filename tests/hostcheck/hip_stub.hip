@@ -579,6 +579,12 @@ bool model_generic(const std::string& base, const std::vector<std::string>& t, d
     Span u{arg<const double*>(args, 0), 8, INT64_MAX, INT64_MIN, "u"}, gg{arg<double*>(args, 4), 8, INT64_MAX, INT64_MIN, "g"};
     for (int k = 0; k < nrec; ++k) { u.touch(idx[k]); gg.touch(idx[k]); }
     u.check(); gg.check();
+  } else if (base == "k_small_matvec") {
+    const int nd = arg<int>(args, 1), src = arg<int>(args, 3), dst = arg<int>(args, 4);
+    if (nd > 1024) fail("n_d = %d beyond the staging array", nd);
+    if (!(src + nd <= dst || dst + nd <= src)) fail("source and destination slot ranges overlap");
+    vec(arg<void*>(args, 0), (int64_t)nd * nd, 8, "matrix");
+    vec(arg<void*>(args, 2), std::max(src, dst) + nd, 8, "slots");
   } else if (base == "k_check_idx") {
     vec(arg<void*>(args, 0), arg<int>(args, 1), 8, "rec_idx"); vec(arg<void*>(args, 3), 1, 4, "bad");
   } else {

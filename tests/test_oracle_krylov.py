@@ -188,6 +188,28 @@ def test_dcg_invariants_and_solution():
     assert _err(x2, U) < 1e-9 and abs(info2["iters"] - info["iters"]) <= 2
 
 
+def test_dcg_with_general_vectors():
+    # Algorithm 3 with vectors that are not eigenvectors (perturbed sine modes, re-orthonormalised):
+    # A W costs wave solves, (W^T A W) is dense, and the per-iteration A-orthogonalisation is
+    # what keeps W^T r_k = 0; the iterate still converges to the discrete Helmholtz solution
+    L, tp, f, U, b, A = _near_resonant()
+    sel, lam2 = modes.select_modes(2, 32, tp.omega, 8)
+    E = modes.mode_matrix(2, 32, sel)
+    rng = np.random.default_rng(3)
+    W, _ = np.linalg.qr(E + 1e-3 * rng.standard_normal(E.shape) / np.sqrt(E.shape[0]))
+    AW = np.column_stack([A(W[:, k]) for k in range(W.shape[1])])
+    assert np.abs(W.T @ AW - (W.T @ AW).T).max() < 1e-12     # W^T A W symmetric (A symmetric)
+    x, info = krylov.dcg(A, b, W, AW, tol=1e-11)
+    assert _err(x, U) < 1e-9
+    assert max(info["wtr"]) < 1e-10 * np.linalg.norm(b)
+    _, infc = krylov.cg(A, b, tol=1e-11)
+    _, infe = krylov.dcg(A, b, E, E * tr.mu_discrete(lam2, tp), tol=1e-11)
+    assert infe["iters"] <= info["iters"] < infc["iters"]
+    # dropping the re-projection (allowed only for eigenvectors) loses the invariant
+    _, info2 = krylov.dcg(A, b, W, AW, tol=1e-11, maxit=40, reproject=False)
+    assert max(info2["wtr"]) > 1e3 * max(info["wtr"])
+
+
 def test_dcg_error_bound_theorem():
     # Theorem 3.1 with kappa_D of Theorem 3.2 on a dense A
     n, omega = 10, 13.0
