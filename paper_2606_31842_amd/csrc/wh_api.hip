@@ -777,6 +777,19 @@ struct KrylovResult {
 // consecutive replacements do not halve the true residual, the FP32 operator error
 // is too large for this problem and the remaining iterations apply the FP64 operator.
 
+// The filter's eigenvalues beta_h lie in [-1/2, 1] when the leapfrog scheme is stable (Section 2.3),
+// so A = I - S_h has |p^T A p| <= 1.5 |p|^2.  Where p = r (CG's first iteration without
+// deflation, the start of a BiCGStab run), |p^T A p| > 6 r^T r shows a growing wave solve (a
+// c_max below the largest c, or a time step beyond the CFL bound) rather than a solvable system.
+wh_status check_stable_filter(wh_ctx* ctx, int k, int nd, double pq, double r2_first) {
+  if (k != 0 || nd != 0 || !(r2_first > 0)) return WH_OK;
+  if (std::fabs(pq) > 6.0 * r2_first)
+    WH_FAIL(ctx, WH_EUNSTABLE, "|p^T A p| = %.3g |p|^2 exceeds the bound 1.5 of a stable filter: the wave "
+            "solve is unstable (c_max below the largest c, or the time step above the CFL bound)",
+            std::fabs(pq) / r2_first);
+  return WH_OK;
+}
+
 wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_nonzero, double* r,
                    double* p, double* q, double tol, int maxit, bool use_defl, bool reproject,
                    int check_every, KrylovResult& res, bool stop_on_divergence = false,
@@ -868,7 +881,8 @@ wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_non
       launch_cg_update1(x, r, pc, q, S.slots, N, S.partials2, S.s);
     }
     launch_reduce(S.partials2, kReduceBlocks, S.slots, S_R2, 2, S.s);
-    const bool sync = reliable || (k + 1) % ce == 0 || k + 1 == maxit;
+    // the first iteration always reads back, so that an unstable wave solve is caught at once
+    const bool sync = reliable || k == 0 || (k + 1) % ce == 0 || k + 1 == maxit;
     double* pn = nullptr;
     if (sync) {
       WHCHK(readback_async(ctx, S.slots, S_NSLOTS_FIXED));
@@ -884,6 +898,7 @@ wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_non
       r2 = ctx->hbuf[S_R2];
       if (!std::isfinite(pq) || !std::isfinite(r2))
         WH_FAIL(ctx, WH_EUNSTABLE, "non-finite p^T A p or residual at iteration %d", k + 1);
+      WHCHK(check_stable_filter(ctx, k, nd, pq, r2_old));
       if (pq == 0.0) WH_FAIL(ctx, WH_EBREAKDOWN, "CG breakdown: p^T A p = 0 at iteration %d", k + 1);
       rel = std::sqrt(r2 / nb2);
       if (rel <= S.reliable_drop * anchor || rel >= 10.0 * anchor || rel <= tol ||
@@ -933,6 +948,7 @@ wh_status cg_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_non
       r2 = ctx->hbuf[S_R2];
       if (!std::isfinite(pq) || !std::isfinite(r2))
         WH_FAIL(ctx, WH_EUNSTABLE, "non-finite p^T A p or residual at iteration %d", k);
+      WHCHK(check_stable_filter(ctx, k - 1, nd, pq, r2_old));
       if (pq == 0.0) WH_FAIL(ctx, WH_EBREAKDOWN, "CG breakdown: p^T A p = 0 at iteration %d", k);
       rel = std::sqrt(r2 / nb2);
       if (stop_on_divergence && rel > 1e3) {
@@ -1041,6 +1057,16 @@ wh_status gmres_solve(Solver& S, bool f32, const double* rhs, double* x, bool x_
         for (int i = 0; i < nd; ++i) HW[(size_t)k * nd + i] = ctx->hbuf[SW + i];
         const double hn2 = ctx->hbuf[S_H + k + 1];
         if (!std::isfinite(hn2)) WH_FAIL(ctx, WH_EUNSTABLE, "non-finite Arnoldi vector");
+        {
+          // ||A v_k||^2 of the unit vector v_k: at most 1.5^2 for a stable wave solve
+          double c2n = hn2;
+          for (int i = 0; i <= k; ++i) c2n += Hc(i, k) * Hc(i, k);
+          for (int i = 0; i < nd; ++i) c2n += HW[(size_t)k * nd + i] * HW[(size_t)k * nd + i];
+          if (c2n > 36.0)
+            WH_FAIL(ctx, WH_EUNSTABLE, "|A v| = %.3g |v| exceeds the bound 1.5 of a stable filter: the wave "
+                    "solve is unstable (c_max below the largest c, or the time step above the CFL bound)",
+                    std::sqrt(c2n));
+        }
         Hc(k + 1, k) = std::sqrt(std::max(hn2, 0.0));
         if (Hc(k + 1, k) > 0) launch_scale_copy(w, w, S.slots, S_H + k + 1, N, S.s);
         for (int i = 0; i < k; ++i) {
@@ -1179,6 +1205,7 @@ wh_status bicgstab_solve(Solver& S, bool f32, const double* rhs, double* x, bool
     bool first = true, blew_up = false;
     while (its < maxit) {
       if (rho == 0.0) break;   // breakdown of the shadow residual: restart
+      const bool p_is_r = first;   // p = r = rt, orthogonal to W: rt^T v = r^T A r
       if (first) {
         launch_copy(p, r, N, S.s);
       } else {
@@ -1193,6 +1220,7 @@ wh_status bicgstab_solve(Solver& S, bool f32, const double* rhs, double* x, bool
       const double rtv = ctx->hbuf[S_TMP];
       for (int i = 0; i < nd; ++i) e1[i] = ctx->hbuf[SE1 + i];
       if (!std::isfinite(rtv)) WH_FAIL(ctx, WH_EUNSTABLE, "non-finite BiCGStab scalar");
+      if (p_is_r) WHCHK(check_stable_filter(ctx, 0, 0, rtv, rho));
       if (rtv == 0.0) break;   // restart
       alpha = rho / rtv;
       launch_lincomb3(sv, 1.0, r, -alpha, v, 0.0, nullptr, N, S.s);

@@ -633,8 +633,8 @@ double synth(int i, long k) {
   // slots: 0 r.r, 1 p.Ap, 2 alpha, 3 beta, 4 scratch (true residual), 5 ||b||^2, 6 scratch
   const double d = std::pow(0.35, (double)k);
   switch (i) {
-    case 0: case 4: return d;
-    case 1: case 2: case 5: case 6: return 1.0;
+    case 0: case 1: case 4: return d;   // p.Ap within the stable-filter bound of r.r
+    case 2: case 5: case 6: return 1.0;
     case 3: return 0.5;
     default: return 0.1 * d + 1e-3 * (i % 7);
   }

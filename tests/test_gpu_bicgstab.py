@@ -5,7 +5,7 @@ import pytest
 
 import workloads as wl
 from oracle import discretization as disc, modes, krylov, wavesolve as ws, transfer as tr
-from _gpu import cuda, host, rel, oracle_tp
+from _gpu import cuda, host, rel, oracle_tp, assert_close
 
 pytestmark = pytest.mark.gpu
 
@@ -32,7 +32,7 @@ def test_bicgstab_f64_matches_oracle(nd):
     print(f"case bicgstab f64 nd={nd}", flush=True)
     import paper_2606_31842_amd as wh
     n, omega, f, sel, lam2, W = _case(nd=max(nd, 1))
-    tol = 1e-10
+    tol = 1e-12 if nd else 1e-10
     kw = dict(solver="bicgstab", tol=tol, max_iters=4000)
     if nd:
         kw["defl"] = wh.sine_deflation(2, n, omega, nd)
@@ -59,8 +59,12 @@ def test_bicgstab_f64_matches_oracle(nd):
     # residual, the library checks the true residual and may restart from it once
     assert abs(info["iters"] - oi["iters"]) <= max(5, oi["iters"] // 4)
     if nd:
-        # the near-resonant modes are projected out: the system left is well conditioned
-        assert rel(host(u), disc.to_nodal(xo, 2, n)) < 1e-8
+        # the near-resonant modes are projected out and the Krylov part is well conditioned; the
+        # solution's component on the nearest mode is (W^T b) / mu with mu = 1 - beta_h = 2.4e-6,
+        # whose rounding (about 1e-16 / mu relative, on both sides) leaves 2.2e-10 against the
+        # direct solve in the oracle as well, at any tolerance
+        assert_close(host(u), disc.to_nodal(xo, 2, n), 1e-10, "vs oracle ABICGSTAB")
+        assert_close(host(u), disc.to_nodal(U, 2, n), 1e-9, "vs direct")
 
 
 def test_augmented_bicgstab_needs_fewer_iterations():
@@ -91,10 +95,10 @@ def test_devd_bicgstab_and_variable_c():
     import paper_2606_31842_amd as wh
     n, omega, f, sel, lam2, W = _case(nd=6)
     d = wh.sine_deflation(2, n, omega, 6)
-    u, info = wh.solve(cuda(f), omega, solver="bicgstab", defl=d, devd=1, tol=1e-10, max_iters=4000)
+    u, info = wh.solve(cuda(f), omega, solver="bicgstab", defl=d, devd=1, tol=1e-12, max_iters=4000)
     assert info["status"] == 0
     U = disc.direct_solve(disc.laplacian(2, n), omega, disc.to_interior(f))
-    assert rel(host(u), disc.to_nodal(U, 2, n)) < 1e-8
+    assert_close(host(u), disc.to_nodal(U, 2, n), 1e-10, "DEVD + BiCGStab vs direct")
     # variable c (32^2, so that the oracle's dense A gives kappa): plain BiCGStab against
     # the direct solve of the variable-c operator, within kappa(A) times the residual
     n = 32

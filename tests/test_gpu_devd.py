@@ -5,7 +5,7 @@ import pytest
 
 import workloads as wl
 from oracle import discretization as disc, modes, devd
-from _gpu import cuda, host, rel, oracle_tp
+from _gpu import cuda, host, rel, oracle_tp, assert_close
 
 pytestmark = pytest.mark.gpu
 
@@ -26,7 +26,7 @@ def test_devd_matches_oracle_and_direct(solver, devd_mode):
     import paper_2606_31842_amd as wh
     # FPI converges at the rate max |beta_h| over the modes left: deflate more of them
     n, omega, f, sel, lam2, W = _case(nd=40 if solver == "fpi" else 6)
-    tol = 1e-9 if solver == "fpi" else 1e-10
+    tol = 1e-12
     d = wh.sine_deflation(2, n, omega, len(sel))
     u, info = wh.solve(cuda(f), omega, solver=solver, defl=d, devd=devd_mode, tol=tol, max_iters=20000,
                        restart=30)
@@ -38,7 +38,8 @@ def test_devd_matches_oracle_and_direct(solver, devd_mode):
                              tol=tol, maxit=20000, deflate_iterates=devd_mode == 2)
     e, eo = rel(host(u), disc.to_nodal(U, 2, n)), rel(xo, U)
     print(f"gpu err {e:.2e} oracle err {eo:.2e} iters {info['iters']} / {oi['iters']}", flush=True)
-    assert e < max(1e-8, 10 * eo)
+    assert_close(host(u), disc.to_nodal(U, 2, n), 1e-10, "vs direct")
+    assert_close(host(u), disc.to_nodal(xo, 2, n), 1e-10, "vs oracle DEVD")
     if solver == "fpi":
         # the fixed-point iteration is deterministic up to rounding: same iteration count
         assert abs(info["iters"] - oi["iters"]) <= 1
@@ -89,15 +90,14 @@ def test_augmented_gmres(precision):
     from oracle import krylov, wavesolve as ws, transfer as tr
     n, omega, f, sel, lam2, W = _case(nd=8)
     d = wh.sine_deflation(2, n, omega, len(sel))
-    tol = 1e-9
+    tol = 1e-12 if precision == "f64" else 1e-9
     u, info = wh.solve(cuda(f), omega, solver="gmres", defl=d, restart=20, tol=tol, max_iters=3000,
                        precision=precision)
-    u0, info0 = wh.solve(cuda(f), omega, solver="gmres", restart=20, tol=tol, max_iters=3000,
+    u0, info0 = wh.solve(cuda(f), omega, solver="gmres", restart=20, tol=1e-9, max_iters=3000,
                          precision=precision)
     assert info["status"] == 0, info
-    assert info["iters"] < info0["iters"]
     U = disc.direct_solve_dst(2, n, omega, f)
-    assert rel(host(u), U) < (1e-7 if precision == "f64" else 2e-5)
+    assert_close(host(u), U, 1e-10 if precision == "f64" else 2e-5, "vs direct")
     if precision == "f64":
         L = disc.laplacian(2, n)
         tp = oracle_tp(2, n, omega)
@@ -107,7 +107,10 @@ def test_augmented_gmres(precision):
                                maxit=3000)
         print(f"gpu iters {info['iters']} oracle iters {oi['iters']} (plain gpu {info0['iters']})", flush=True)
         assert abs(info["iters"] - oi["iters"]) <= max(3, oi["iters"] // 10)
-        assert rel(host(u), disc.to_nodal(xo, 2, n)) < 1e-7
+        assert_close(host(u), disc.to_nodal(xo, 2, n), 1e-10, "vs oracle AGMRES")
+        # to the same tolerance, plain GMRES(20) needs more iterations than the augmented form
+        _, ia = wh.solve(cuda(f), omega, solver="gmres", defl=d, restart=20, tol=1e-9, max_iters=3000)
+        assert ia["iters"] < info0["iters"]
 
 
 @pytest.mark.parametrize("solver,devd_mode", [("cg", 1), ("gmres", 0)])
@@ -121,10 +124,10 @@ def test_deflation_3d(solver, devd_mode):
     omega = float(np.sqrt(e[2] + e[3] + e[4]) * 1.002)
     f = wl.gaussian(3, n, (0.41, 0.57, 0.5), 0.12)
     d = wh.sine_deflation(3, n, omega, 10)
-    kw = dict(solver=solver, defl=d, tol=1e-10, max_iters=3000, restart=20)
+    kw = dict(solver=solver, defl=d, tol=1e-12, max_iters=3000, restart=20)
     if devd_mode:
         kw["devd"] = devd_mode
     u, info = wh.solve(cuda(f), omega, **kw)
     assert info["status"] == 0, info
     U = disc.direct_solve_dst(3, n, omega, f)
-    assert rel(host(u), U) < 1e-8
+    assert_close(host(u), U, 1e-10, "vs direct")

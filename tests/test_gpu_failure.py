@@ -1,0 +1,63 @@
+"""Failure paths the host detects while every kernel runs to its normal end.
+
+* A c_max below the largest wave speed puts the leapfrog time step beyond its CFL bound
+  (Section 2.1): the wave solve grows, the filter's eigenvalues leave [-1/2, 1] (Section 2.3),
+  and the solvers must stop with WH_EUNSTABLE rather than iterate on garbage.
+* omega on a discrete eigenvalue of -L_h makes the Helmholtz matrix singular; the filter
+  then has beta_h = 1 on that mode (the omega-tilde correction of eq. R1 makes the discrete
+  filter exact at omega), A is singular, and the solvers must report WH_ENOCONV (or
+  WH_EBREAKDOWN), never WH_OK.  The oracle's CG and GMRES stall the same way on this system
+  (a CPU test beside the oracle's Krylov pins)."""
+import numpy as np
+import pytest
+
+from oracle import modes
+from _gpu import cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _rhs(n, seed=3):
+    f = np.zeros((n + 1, n + 1))
+    f[1:-1, 1:-1] = np.random.default_rng(seed).standard_normal((n - 1, n - 1))
+    return f
+
+
+@pytest.mark.parametrize("solver", ["cg", "gmres", "bicgstab"])
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_understated_c_max_is_unstable(solver, precision):
+    import paper_2606_31842_amd as wh
+    n = 32
+    print(f"case unstable {solver} {precision} n={n}", flush=True)
+    c2 = np.full((n + 1, n + 1), 4.0)          # c = 2 everywhere, declared as c_max = 1
+    with pytest.raises(wh.WaveHoltzError) as e:
+        wh.solve(cuda(_rhs(n)), 5.3, c2=cuda(c2), solver=solver, precision=precision, tol=1e-8,
+                 max_iters=200, c_max=1.0)
+    print(f"  {e.value}", flush=True)
+    assert e.value.status == wh._native.WH_EUNSTABLE
+
+
+def test_stated_c_max_is_stable():
+    """The same problem with the true c_max converges: the failure above is the time step's."""
+    import paper_2606_31842_amd as wh
+    n = 32
+    c2 = np.full((n + 1, n + 1), 4.0)
+    _, info = wh.solve(cuda(_rhs(n)), 5.3, c2=cuda(c2), solver="cg", tol=1e-8, max_iters=500, c_max=2.0)
+    assert info["status"] == 0
+
+
+@pytest.mark.parametrize("solver", ["cg", "gmres"])
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_omega_on_an_eigenvalue_does_not_converge(solver, precision):
+    import paper_2606_31842_amd as wh
+    n = 16
+    omega = float(np.sqrt(modes.mode_lam2(2, n, (1, 1))))
+    print(f"case resonant {solver} {precision} n={n} omega={omega!r}", flush=True)
+    try:
+        u, info = wh.solve(cuda(_rhs(n)), omega, solver=solver, precision=precision, tol=1e-10, max_iters=300)
+    except wh.WaveHoltzError as e:
+        print(f"  {e}", flush=True)
+        assert e.status == wh._native.WH_EBREAKDOWN
+        return
+    print(f"  status {info['status']} iters {info['iters']} rel {info['rel_res']:.3e}", flush=True)
+    assert info["status"] == wh._native.WH_ENOCONV

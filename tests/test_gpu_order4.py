@@ -6,7 +6,7 @@ import pytest
 
 import workloads as wl
 from oracle import discretization as disc, modes, krylov, wavesolve as ws, transfer as tr
-from _gpu import cuda, host, rel, oracle_tp
+from _gpu import assert_close, cuda, host, rel, oracle_tp
 
 pytestmark = pytest.mark.gpu
 
@@ -51,16 +51,18 @@ def test_order4_solves_match_direct(solver, precision):
     e = modes.eig1d(n, order=4)
     omega = float(np.sqrt(e[6] + e[7]) * 1.0015)
     f = wl.gaussian(2, n, (0.41, 0.57), 0.08)
-    kw = dict(solver=solver, tol=1e-10 if precision == "f64" else 1e-9, max_iters=6000, order=4,
+    kw = dict(solver=solver, tol=1e-12 if precision == "f64" else 1e-9, max_iters=6000, order=4,
               precision=precision, restart=30)
     if solver in ("dcg", "gmres", "bicgstab"):
         kw["defl"] = wh.sine_deflation(2, n, omega, 8, order=4)
     u, info = wh.solve(cuda(f), omega, **kw)
     assert info["status"] == 0, info
     U = disc.direct_solve_dst(2, n, omega, f, order=4)
-    err = rel(host(u), U)
-    print(f"err {err:.2e} iters {info['iters']}", flush=True)
-    assert err < (1e-8 if precision == "f64" else 2e-5)
+    print(f"iters {info['iters']}", flush=True)
+    # omega sits 0.15% above an eigenvalue pair: the solution's error against the direct solve
+    # is bounded by kappa(A) times the residual, and by the rounding of mu = 1 - beta_h on the
+    # nearest modes (the oracle's DCG at the same tolerance is 3e-10 from it)
+    assert_close(host(u), U, 1e-9 if precision == "f64" else 2e-5, "vs direct")
     assert wh.helmholtz_residual(u, cuda(f), omega, order=4) < 1e-6
     if solver == "dcg" and precision == "f64":
         L = disc.laplacian(2, n, order=4)
@@ -68,9 +70,10 @@ def test_order4_solves_match_direct(solver, precision):
         sel, lam2 = modes.select_modes(2, n, omega, 8, order=4)
         W = modes.mode_matrix(2, n, sel)
         b = ws.rhs(L, disc.to_interior(f), tp)
-        _, oi = krylov.dcg(lambda v: ws.apply_A(L, v, tp), b, W, W * tr.mu_discrete(lam2, tp), tol=1e-10,
-                           reproject=False)
+        xo, oi = krylov.dcg(lambda v: ws.apply_A(L, v, tp), b, W, W * tr.mu_discrete(lam2, tp), tol=1e-12,
+                            reproject=False)
         assert abs(info["iters"] - oi["iters"]) <= 2
+        assert_close(host(u), disc.to_nodal(xo, 2, n), 1e-10, "vs oracle DCG")
 
 
 def test_order4_is_fourth_order_accurate():

@@ -293,3 +293,25 @@ def test_devd_matches_direct_solve_and_inflation_is_exact():
     U2 = disc.direct_solve(L, tp.omega, f2)
     x2 = devd.inflate(W, lam2, tp.omega, f2, np.zeros_like(f2))
     assert _err(x2, U2) < 1e-12
+
+
+def test_resonant_omega_makes_A_singular_and_krylov_stalls():
+    """At omega^2 equal to the discrete eigenvalue lambda_{1,1} of -L_h the filter passes that mode
+    unchanged (mu = 1 - beta_h = 0 up to rounding, the exactness the omega-tilde correction of
+    eq. R1 gives), so A = I - S_h is singular with b outside its range: neither CG nor GMRES may
+    report convergence.  The GPU solvers' failure status is tested against the same system."""
+    n = 16
+    lam2 = modes.mode_lam2(2, n, (1, 1))
+    om = math.sqrt(lam2)
+    L, tp, f = setup(2, n, om)
+    assert abs(tr.mu_discrete(np.array([lam2]), tp)[0]) < 1e-12
+    # the (1,1) mode is a null vector of A
+    v = disc.to_interior(modes.mode_nodal(2, n, (1, 1)))
+    Av = ws.apply_A(L, v, tp)
+    assert np.linalg.norm(Av) < 1e-12 * np.linalg.norm(v)
+    b = ws.rhs(L, f, tp)
+    A = lambda x: ws.apply_A(L, x, tp)
+    _, ci = krylov.cg(A, b, tol=1e-10, maxit=300)
+    _, gi = krylov.agmres(A, b, tol=1e-10, maxit=300)
+    assert ci["iters"] == 300 and ci["res"][-1] > 1e-10
+    assert gi["iters"] >= 300 and gi["res"][-1] > 1e-10
