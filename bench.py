@@ -658,7 +658,8 @@ def _explicit_modes(np, torch, wh, n, omega, nd, form):
     if form == "dense":
         Vt = torch.from_numpy(V.reshape(nd, -1)).cuda()
         return wh.Deflation(wh.WH_DEFL_DENSE_EXACT, V=Vt, lambda2=lam2)
-    fx, fy, tm, ranks = wh.compress_modes(V, tol=1e-12)
+    from compress_modes import compress_modes
+    fx, fy, tm, ranks = compress_modes(V, tol=1e-12)
     return wh.factored_deflation(fx, fy, tm, lam2)
 
 

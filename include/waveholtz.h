@@ -197,6 +197,13 @@ wh_status wh_set_stream(wh_ctx* ctx, void* hip_stream);
 const char* wh_last_error(const wh_ctx* ctx);
 const char* wh_status_string(wh_status s);
 
+/* The wave speed bound c_max = sqrt(max c2) of a nodal coefficient array (device, float64,
+ * (n+1)^dim nodes, the layout of wh_apply_filter's c2) that fixes the CFL time step of
+ * Section 2.2; every node must hold a finite c2 > 0 (WH_EINVAL otherwise).  Two reductions
+ * on the context's stream into the context's own device buffer, then a synchronous
+ * read-back into *c_max (host).  c2 == NULL means c == 1 and returns 1. */
+wh_status wh_coeff_bound(wh_ctx* ctx, const wh_grid* grid, const double* c2, double* c_max);
+
 /* ------------------------------------------------------------------ host helpers */
 /* Time step, steps per period, N_t and adjusted frequency for given c_max (Section 2.2). */
 wh_status wh_time_params(const wh_grid* grid, const wh_params* params, double c_max,

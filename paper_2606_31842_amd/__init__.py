@@ -151,28 +151,11 @@ class Deflation:
         return d
 
 
-def compress_modes(V, tol: float = 1e-5):
-    """Host-side preparation of a factored deflation set (not part of any solve): each 2D
-    nodal mode V[k] ((n+1, n+1), y rows, x columns) is replaced by its truncated SVD,
-    keeping the singular values above tol times the largest (the compression of
-    Section 4.3).  Returns (fx, fy, term_mode, ranks) as numpy arrays: term t is
-    fy[t](y) fx[t](x) with the singular value folded into fy."""
-    V = np.asarray(V, dtype=np.float64)
-    fxs, fys, tm, ranks = [], [], [], []
-    for k in range(V.shape[0]):
-        U, sv, Vt = np.linalg.svd(V[k])
-        r = max(1, int(np.sum(sv > tol * sv[0])))
-        ranks.append(r)
-        for j in range(r):
-            fys.append(U[:, j] * sv[j])
-            fxs.append(Vt[j])
-            tm.append(k)
-    return np.array(fxs), np.array(fys), np.array(tm, dtype=np.int32), np.array(ranks)
-
-
 def factored_deflation(fx, fy, term_mode, lambda2) -> Deflation:
-    """Deflation set of 2D eigenvectors of L_h given as separable terms (see
-    compress_modes); fx, fy: (T, n+1) arrays (numpy or CUDA tensors)."""
+    """Deflation set of 2D eigenvectors of L_h given as separable terms: term t is
+    fy[t](y) fx[t](x) and belongs to eigenvector term_mode[t] (non-decreasing), the form the
+    compress_modes.py preprocessing script writes (Section 4.3); fx, fy: (T, n+1) arrays
+    (numpy or CUDA tensors)."""
     torch = _torch()
 
     def dev(a):
@@ -409,6 +392,18 @@ def time_batch_kernel(problems, reps=20, workspace=None, n_defl=0, **kw):
     return us.value, pts.value
 
 
+def coeff_bound(c2) -> float:
+    """c_max = sqrt(max c2) of a nodal float64 CUDA coefficient array (wh_coeff_bound)."""
+    dim, n = c2.dim(), c2.shape[0] - 1
+    _nodal(c2, dim, n, "c2")
+    lib = nat.load()
+    ctx = context(c2.device.index)
+    g = _grid(dim, n)
+    out = C.c_double()
+    _check(lib, ctx, lib.wh_coeff_bound(ctx, C.byref(g), _ptr(c2), C.byref(out)))
+    return out.value
+
+
 def solve_vjp(u, grad_u, f, omega, c2, ckpt_every=16, grad_c2=None, **kw):
     """grad_c2 (+)= (dPi_h/dc2)^T A^{-1} grad_u at the fixed point u (wh_solve_vjp)."""
     torch = _torch()
@@ -418,7 +413,7 @@ def solve_vjp(u, grad_u, f, omega, c2, ckpt_every=16, grad_c2=None, **kw):
     lib = nat.load()
     ctx = context(u.device.index)
     if "c_max" not in kw:
-        kw["c_max"] = float(torch.sqrt(c2.max()).item())
+        kw["c_max"] = coeff_bound(c2)
     p = params(omega, **kw)
     g = _grid(2, n)
     need = lib.wh_workspace_bytes_adjoint(C.byref(g), C.byref(p), int(ckpt_every))
@@ -441,7 +436,7 @@ def adjoint_grad(c2, sources, rec_idx, data, omega, ckpt_every=16, **kw):
     lib = nat.load()
     ctx = context(c2.device.index)
     if "c_max" not in kw:
-        kw["c_max"] = float(torch.sqrt(c2.max()).item())
+        kw["c_max"] = coeff_bound(c2)
     p = params(omega, **kw)
     g = _grid(2, n)
     srcs = [_nodal(f, 2, n, "source") for f in sources]

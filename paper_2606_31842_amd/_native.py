@@ -62,6 +62,7 @@ _SIGS = {
     "wh_destroy": (C.c_int, [C.c_void_p]),
     "wh_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "wh_last_error": (C.c_char_p, [C.c_void_p]),
+    "wh_coeff_bound": (C.c_int, [C.c_void_p, P(WhGrid), C.c_void_p, P(C.c_double)]),
     "wh_status_string": (C.c_char_p, [C.c_int]),
     "wh_time_params": (C.c_int, [P(WhGrid), P(WhParams), C.c_double, P(C.c_int32), P(C.c_int32),
                                  P(C.c_double), P(C.c_double)]),

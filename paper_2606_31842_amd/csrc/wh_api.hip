@@ -1625,6 +1625,14 @@ wh_status wh_create(wh_ctx** out, int device, void* stream) {
     delete c;
     return WH_EHIP;
   }
+  e = hipMalloc((void**)&c->dred, sizeof(double) * (kReduceBlocks + 8));
+  if (e != hipSuccess) {
+    g_create_err = std::string("hipMalloc: ") + hipGetErrorString(e);
+    (void)hipEventDestroy(c->rb_event);
+    (void)hipHostFree(c->hbuf);
+    delete c;
+    return WH_EHIP;
+  }
   *out = c;
   return WH_OK;
   });
@@ -1634,6 +1642,7 @@ wh_status wh_destroy(wh_ctx* ctx) {
   if (!ctx) return WH_EINVAL;
   if (ctx->rb_event) (void)hipEventDestroy(ctx->rb_event);
   if (ctx->hbuf) (void)hipHostFree(ctx->hbuf);
+  if (ctx->dred) (void)hipFree(ctx->dred);
   delete ctx;
   return WH_OK;
 }
@@ -1642,6 +1651,33 @@ wh_status wh_set_stream(wh_ctx* ctx, void* stream) {
   if (!ctx) return WH_EINVAL;
   ctx->stream = (hipStream_t)stream;
   return WH_OK;
+}
+
+wh_status wh_coeff_bound(wh_ctx* ctx, const wh_grid* grid, const double* c2, double* c_max) {
+  return guard(ctx, [&]() -> wh_status {
+  if (!ctx) return WH_EINVAL;
+  if (!grid || !c_max) WH_FAIL(ctx, WH_EINVAL, "NULL argument");
+  WHCHK(check_grid(ctx, grid));
+  *c_max = 0;
+  if (!c2) {
+    *c_max = 1.0;
+    return WH_OK;
+  }
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  const int64_t N = nodal_count(grid->dim, grid->n);
+  double* part = ctx->dred;
+  double* res = ctx->dred + kReduceBlocks;
+  launch_max_partials(c2, N, part, false, ctx->stream);
+  launch_max_finalize(part, kReduceBlocks, res, ctx->stream);
+  launch_max_partials(c2, N, part, true, ctx->stream);
+  launch_max_finalize(part, kReduceBlocks, res + 1, ctx->stream);
+  WHCHK(readback(ctx, res, 2));
+  const double m = ctx->hbuf[0], negmin = ctx->hbuf[1];
+  if (!(m > 0) || !std::isfinite(m) || !(negmin < 0))
+    WH_FAIL(ctx, WH_EINVAL, "c2 must be positive and finite at every node");
+  *c_max = std::sqrt(m);
+  return WH_OK;
+  });
 }
 
 const char* wh_last_error(const wh_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }

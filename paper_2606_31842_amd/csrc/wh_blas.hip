@@ -91,9 +91,14 @@ void launch_defect_forcing(const double* v, const double* kap64, double a, doubl
 }
 
 // ----------------------------------------------------------------- reductions
+// max of a (or of -a); a NaN counts as +infinity in both, so that it reaches the result
+// (fmax alone would drop it)
 __global__ void k_max_partials(const double* a, int64_t N, double* partials, bool neg) {
   double m = -1.0e308;
-  GRID_STRIDE(p, N) m = fmax(m, neg ? -a[p] : a[p]);
+  GRID_STRIDE(p, N) {
+    const double v = a[p];
+    m = fmax(m, v == v ? (neg ? -v : v) : HUGE_VAL);
+  }
   double r = block_max256(m, threadIdx.x);
   if (threadIdx.x == 0) partials[blockIdx.x] = r;
 }

@@ -20,6 +20,7 @@ struct wh_ctx {
   double* hbuf = nullptr;  // pinned host scalars
   int hbuf_len = 0;
   hipEvent_t rb_event = nullptr;   // marks the end of an asynchronous scalar read-back
+  double* dred = nullptr;          // device: kReduceBlocks + 8 doubles for the context's own reductions
   // (dim, n, f32, varc, force) -> steps per launch K | (block shape << 8)
   std::map<std::tuple<int, int, int, int, int>, int> ktune;
 };

@@ -738,6 +738,17 @@ hipError_t hipHostFree(void* p) {
   free(p);
   return hipSuccess;
 }
+hipError_t hipMalloc(void** p, size_t bytes) {
+  *p = malloc(bytes);
+  if (!*p) return hipErrorOutOfMemory;
+  hostcheck_register(*p, bytes, "library device buffer");
+  return hipSuccess;
+}
+hipError_t hipFree(void* p) {
+  hostcheck_unregister(p);
+  free(p);
+  return hipSuccess;
+}
 hipError_t hipMemcpyAsync(void* dst, const void* src, size_t bytes, hipMemcpyKind kind, hipStream_t) {
   if (!bytes) return hipSuccess;
   g_current = "hipMemcpyAsync";

@@ -6,6 +6,7 @@ import pytest
 
 import workloads as wl
 from oracle import discretization as disc, modes, krylov, wavesolve as ws, transfer as tr
+from compress_modes import compress_modes
 from _gpu import cuda, host, rel, oracle_tp
 
 pytestmark = pytest.mark.gpu
@@ -40,7 +41,7 @@ def test_factored_matches_dense_and_oracle(solver):
     f = wl.gaussian(2, n, (0.41, 0.57), 0.08)
     V, lam2, npairs = _rotated_sine_set(n, omega, 10)
     assert npairs >= 2
-    fx, fy, tm, ranks = wh.compress_modes(V, tol=1e-12)
+    fx, fy, tm, ranks = compress_modes(V, tol=1e-12)
     assert max(ranks) == 2
     dfac = wh.factored_deflation(fx, fy, tm, lam2)
     dden = wh.Deflation(wh.WH_DEFL_DENSE_EXACT, V=torch.stack([cuda(v).reshape(-1) for v in V]), lambda2=lam2)
@@ -88,7 +89,7 @@ def test_factored_variable_c_compressed_eigenvectors():
     # full accuracy: DCG to 1e-9
     kw = dict(solver="dcg", tol=1e-9, max_iters=4000, c2=cuda(c2))
     ud, ind = wh.solve(cuda(f), omega, defl=dden, **kw)
-    fx, fy, tm, ranks = wh.compress_modes(V, tol=1e-10)
+    fx, fy, tm, ranks = compress_modes(V, tol=1e-10)
     uf, inf_ = wh.solve(cuda(f), omega, defl=wh.factored_deflation(fx, fy, tm, lam2), **kw)
     print(f"tau 1e-10: ranks {list(ranks)} iters {inf_['iters']} (dense {ind['iters']}) "
           f"err {rel(host(uf), U):.1e}", flush=True)
@@ -99,7 +100,7 @@ def test_factored_variable_c_compressed_eigenvectors():
     # the compression experiment: CG with f_d, tol 1e-4
     kw = dict(solver="cg", devd=1, tol=1e-4, max_iters=4000, c2=cuda(c2))
     ud, ind = wh.solve(cuda(f), omega, defl=dden, **kw)
-    fx, fy, tm, ranks = wh.compress_modes(V, tol=1e-5)
+    fx, fy, tm, ranks = compress_modes(V, tol=1e-5)
     uf, inf_ = wh.solve(cuda(f), omega, defl=wh.factored_deflation(fx, fy, tm, lam2), **kw)
     print(f"tau 1e-5, CG with f_d to 1e-4: ranks {list(ranks)} iters {inf_['iters']} (full {ind['iters']}) "
           f"err {rel(host(uf), U):.1e} (full {rel(host(ud), U):.1e})", flush=True)
@@ -114,7 +115,7 @@ def test_factored_rejects_bad_input():
     n = 24
     sel, lam2 = modes.select_modes(2, n, 7.7, 2)
     V = np.stack([modes.mode_nodal(2, n, m) for m in sel])
-    fx, fy, tm, _ = wh.compress_modes(V, tol=1e-12)
+    fx, fy, tm, _ = compress_modes(V, tol=1e-12)
     f = cuda(wl.gaussian(2, n, (0.4, 0.6), 0.1))
     bad = wh.factored_deflation(fx, fy, tm[::-1].copy(), lam2)          # decreasing term_mode
     with pytest.raises(wh.WaveHoltzError):
@@ -134,7 +135,7 @@ def test_factored_mixed_dcg():
     omega = float(np.sqrt(e[9] + e[11]) * 1.001)
     f = wl.gaussian(2, n, (0.37, 0.6), 0.07)
     V, lam2, npairs = _rotated_sine_set(n, omega, 12)
-    fx, fy, tm, ranks = wh.compress_modes(V, tol=1e-12)
+    fx, fy, tm, ranks = compress_modes(V, tol=1e-12)
     dfac = wh.factored_deflation(fx, fy, tm, lam2)
     dden = wh.Deflation(wh.WH_DEFL_DENSE_EXACT, V=torch.stack([cuda(v).reshape(-1) for v in V]), lambda2=lam2)
     kw = dict(solver="dcg", tol=1e-9, max_iters=4000, precision="mixed")

@@ -61,3 +61,20 @@ def test_omega_on_an_eigenvalue_does_not_converge(solver, precision):
         return
     print(f"  status {info['status']} iters {info['iters']} rel {info['rel_res']:.3e}", flush=True)
     assert info["status"] == wh._native.WH_ENOCONV
+
+
+@pytest.mark.parametrize("dim,n", [(2, 40), (3, 12)])
+def test_coeff_bound_is_the_largest_wave_speed(dim, n):
+    """wh_coeff_bound: c_max = sqrt(max c2), the bound the CFL time step needs (Section 2.2);
+    a node with c2 <= 0 or a non-finite one is rejected."""
+    import paper_2606_31842_amd as wh
+    from _oracle_cases import varc2
+    print(f"case coeff_bound dim={dim} n={n}", flush=True)
+    c2 = varc2(dim, n)
+    assert wh.coeff_bound(cuda(c2)) == float(np.sqrt(c2.max()))
+    for bad in (0.0, -1.0, np.inf, np.nan):
+        b = c2.copy()
+        b.flat[b.size // 3] = bad
+        with pytest.raises(wh.WaveHoltzError) as e:
+            wh.coeff_bound(cuda(b))
+        assert e.value.status == wh._native.WH_EINVAL

@@ -38,7 +38,7 @@ def test_ndsweep_problem_shape_and_source():
 def test_compress_modes_round_trip():
     """The SVD compression of 2D nodal modes: exact rank for separable and rotated
     degenerate sine modes, reconstruction within the cut-off otherwise."""
-    import paper_2606_31842_amd as wh
+    from compress_modes import compress_modes
     from oracle import modes
     n = 24
     a, b = modes.mode_nodal(2, n, (2, 5)), modes.mode_nodal(2, n, (5, 2))
@@ -49,14 +49,14 @@ def test_compress_modes_round_trip():
     g[0] = g[-1] = 0
     g[:, 0] = g[:, -1] = 0
     V = np.stack([a, rot, g])
-    fx, fy, tm, ranks = wh.compress_modes(V, tol=1e-12)
+    fx, fy, tm, ranks = compress_modes(V, tol=1e-12)
     assert list(ranks[:2]) == [1, 2] and ranks[2] == n - 1
     assert list(tm) == [0] + [1] * 2 + [2] * int(ranks[2])
     for k in range(3):
         rec = sum(np.outer(fy[t], fx[t]) for t in range(len(tm)) if tm[t] == k)
         assert np.abs(rec - V[k]).max() < 1e-12 * np.abs(V[k]).max() * n
     # a loose cut-off keeps the leading singular values only; the error is bounded by them
-    fx, fy, tm, ranks = wh.compress_modes(V[2:], tol=0.3)
+    fx, fy, tm, ranks = compress_modes(V[2:], tol=0.3)
     s = np.linalg.svd(g, compute_uv=False)
     rec = sum(np.outer(fy[t], fx[t]) for t in range(len(tm)))
     assert ranks[0] == int(np.sum(s > 0.3 * s[0]))
