@@ -326,7 +326,8 @@ wh_status wh_solve_vjp(wh_ctx* ctx, const wh_grid* grid, const double* c2, const
  * dJ/dc2 (overwrites grad_c2).  f: host array of n_src device source pointers;
  * rec_idx: device array of n_rec nodal linear indices (interior nodes, checked);
  * d: device n_src x n_rec data; J: host.  Each source costs two CG solves and one
- * checkpointed reverse sweep. */
+ * checkpointed reverse sweep.  grad_c2 == NULL evaluates J alone (one CG solve per
+ * source), as a finite-difference check of the gradient needs. */
 wh_status wh_adjoint_grad(wh_ctx* ctx, const wh_grid* grid, const double* c2, int32_t n_src,
                           const double* const* f, int32_t n_rec, const int64_t* rec_idx,
                           const double* d, const wh_params* params, int32_t ckpt_every,

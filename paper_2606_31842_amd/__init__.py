@@ -428,8 +428,9 @@ def solve_vjp(u, grad_u, f, omega, c2, ckpt_every=16, grad_c2=None, **kw):
     return out, info.as_dict()
 
 
-def adjoint_grad(c2, sources, rec_idx, data, omega, ckpt_every=16, **kw):
-    """(J, dJ/dc2, info) for J = 1/2 sum_s ||R u_s - d_s||^2 (wh_adjoint_grad)."""
+def adjoint_grad(c2, sources, rec_idx, data, omega, ckpt_every=16, need_grad=True, **kw):
+    """(J, dJ/dc2, info) for J = 1/2 sum_s ||R u_s - d_s||^2 (wh_adjoint_grad); with
+    need_grad=False the misfit alone, (J, None, info)."""
     torch = _torch()
     n = c2.shape[0] - 1
     _nodal(c2, 2, n, "c2")
@@ -448,7 +449,7 @@ def adjoint_grad(c2, sources, rec_idx, data, omega, ckpt_every=16, **kw):
     if need == 0:
         raise WaveHoltzError(-1, "invalid arguments for the adjoint workspace")
     ws = _workspace(need)
-    grad = torch.empty_like(c2)
+    grad = torch.empty_like(c2) if need_grad else None
     J = C.c_double()
     info = nat.WhInfo()
     st = lib.wh_adjoint_grad(ctx, C.byref(g), _ptr(c2), len(srcs), fptr, idx.numel(), _ptr(idx), _ptr(d),

@@ -2502,7 +2502,7 @@ wh_status wh_adjoint_grad(wh_ctx* ctx, const wh_grid* grid, const double* c2, in
   const double t0 = now_ms();
   if (info) std::memset(info, 0, sizeof(*info));
   WHCHK(adjoint_validate(ctx, grid, c2, params, ckpt_every));
-  if (n_src < 1 || !f || n_rec < 1 || !rec_idx || !d || !grad_c2 || !J)
+  if (n_src < 1 || !f || n_rec < 1 || !rec_idx || !d || !J)
     WH_FAIL(ctx, WH_EINVAL, "need n_src >= 1 sources, n_rec >= 1 receivers and outputs");
   for (int s_ = 0; s_ < n_src; ++s_)
     if (!f[s_]) WH_FAIL(ctx, WH_EINVAL, "source %d is NULL", s_);
@@ -2523,7 +2523,7 @@ wh_status wh_adjoint_grad(wh_ctx* ctx, const wh_grid* grid, const double* c2, in
   int badv = 0;
   std::memcpy(&badv, ctx->hbuf, 4);
   if (badv) WH_FAIL(ctx, WH_EINVAL, "receiver indices must be interior nodes of the grid");
-  HIPCHK(ctx, hipMemsetAsync(grad_c2, 0, 8 * N, s));
+  if (grad_c2) HIPCHK(ctx, hipMemsetAsync(grad_c2, 0, 8 * N, s));
   double* u = at<double>(ws, V.u);
   double* g = at<double>(ws, V.g);
   double* jslot = at<double>(ws, V.misc) + 8;
@@ -2542,7 +2542,7 @@ wh_status wh_adjoint_grad(wh_ctx* ctx, const wh_grid* grid, const double* c2, in
     WHCHK(readback(ctx, jslot, 1));
     Jsum += ctx->hbuf[0];
     wh_info vi{};
-    WHCHK(vjp_core(ctx, *grid, c2, f[si], u, g, P, ws, V, grad_c2, &vi));
+    if (grad_c2) WHCHK(vjp_core(ctx, *grid, c2, f[si], u, g, P, ws, V, grad_c2, &vi));
     if (info) {
       info->iters += in.iters + vi.iters;
       info->wave_solves += in.wave_solves + vi.wave_solves;
