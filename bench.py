@@ -39,9 +39,10 @@ B_PER_PT_STEP_F64 = 40.0
 # state pair in 4 + 4, state pair out 4 + 4, V read + write 8 + 8
 B_FUSED_F32 = 32.0
 # HBM KiB per dispatch (FETCH_SIZE, WRITE_SIZE) of the tagged batch work kernel on the config-4
-# batch, from the two counter passes in profiles/hbm_traffic_batch_work_cfg4.md, with the copy-kernel
-# scale factors; valid only for the kernel source it was taken on
-BATCH_TRAFFIC = {"src_sha1": "", "fetch_scale": 2.0, "write_scale": 1.0, "kib": None}
+# batch, from the two counter passes in profiles/hbm_traffic_batch_tile_cfg4.md, with the copy-kernel
+# scale factors; valid only for the kernel sources it was taken on (sha1 over the three files)
+BATCH_TRAFFIC = {"src_sha1": "78196abcbd37005bf84e5186a55d32a4399fd03e", "fetch_scale": 2.0, "write_scale": 1.0,
+                 "kib": [864565.7, 1433502.9]}
 # HBM KiB per dispatch (FETCH_SIZE, WRITE_SIZE) of every FP32 temporally blocked kernel
 # variant "K,R,NW" on this grid, from the two rocprofv3 counter passes summarised in
 # profiles/hbm_traffic_fused2d_f32_2d1024.md (scaled by FETCH x 2.000, WRITE x 1.000 from a
@@ -397,7 +398,8 @@ def main():
                                "seeded centres (seed 4), DCG with the floor(1.5 omega) sine modes nearest omega^2, "
                                "FP32 stepping / FP64 filter+Krylov, graph-replayed rounds, true residual 1e-8",
                    "problems": len(probs), "solver": "dcg", "precision": "mixed", "tol": 1e-8, "k_fuse": K,
-                   "block": "8 rows x 8 waves", "n_defl_rule": "floor(1.5 omega)"},
+                   "tile": f"{infos[0]['k_waves']} row-marching strips of {64 - 2 * K} columns x "
+                           f"{infos[0]['k_rows']} rows", "n_defl_rule": "floor(1.5 omega)"},
         "time_to_tol_ms_per_batch": round(ms, 3),
         "time_to_tol_ms_per_solve": round(ms / len(probs), 4),
         "ms_per_step_min_median": [round(min(step_s) * 1e3, 3), round(sorted(step_s)[len(step_s) // 2] * 1e3, 3)],
@@ -409,7 +411,7 @@ def main():
                   "max_helmholtz_rel_res": max(hres), "median_helmholtz_rel_res": float(np.median(hres))},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": f"k_batch_work<float,{K},8,8,false,1> (the solver's FP32 work kernel under its "
+                     "kernel": f"k_batch_tile<float,{K},false,1> (the solver's FP32 row-marching work kernel under its "
                                "measurement tag: K leapfrog steps + FP64 filter sum per launch on every tile)",
                      "bytes_per_point_per_launch": B_FUSED_F32, "points_per_launch": pts, "k_fuse": K,
                      "bytes_per_launch": bytes_launch, "launch_us": round(launch_us, 3),
@@ -466,12 +468,19 @@ def _copy_gbs(torch):
     return 2 * ca.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
+def _batch_src_sha1():
+    """sha1 over the sources of the batched work kernel (driver, state header, row-marching pipeline)."""
+    import hashlib
+    h = hashlib.sha1()
+    for f in ("wh_batched.hip", "wh_batched.h", "wh_march2d.h"):
+        h.update(open(os.path.join(ROOT, "paper_2606_31842_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def _traffic_lookup():
     """HBM bytes per launch of the tagged batch kernel from the two counter passes summarised in
-    profiles/hbm_traffic_batch_work_cfg4.md, or None when the kernel source has changed since."""
-    import hashlib
-    src = os.path.join(ROOT, "paper_2606_31842_amd", "csrc", "wh_batched.hip")
-    if not BATCH_TRAFFIC["kib"] or hashlib.sha1(open(src, "rb").read()).hexdigest() != BATCH_TRAFFIC["src_sha1"]:
+    profiles/hbm_traffic_batch_tile_cfg4.md, or None when the kernel sources have changed since."""
+    if not BATCH_TRAFFIC["kib"] or _batch_src_sha1() != BATCH_TRAFFIC["src_sha1"]:
         return None
     fk, wk = BATCH_TRAFFIC["kib"]
     return round(1024 * (fk * BATCH_TRAFFIC["fetch_scale"] + wk * BATCH_TRAFFIC["write_scale"]))

@@ -171,7 +171,8 @@ typedef struct {
   double dt;               /* time step                                                     */
   double c_max;            /* wave speed bound used for the time step                       */
   double ms;               /* wall time of the call in milliseconds                         */
-  int32_t k_rows;          /* 2D blocked kernel: register rows per thread (0: streaming)    */
+  int32_t k_rows;          /* 2D blocked kernel: register rows per thread (0: streaming);
+                              batched solver: rows per tile of its row-marching kernel      */
   int32_t k_waves;         /* 2D blocked kernel: wavefronts per block (0: streaming)        */
 } wh_info;
 

@@ -42,6 +42,16 @@ __host__ __device__ inline int phase_prec(int ph, int mixed) {
   return 0;
 }
 
+// Tile of the work kernels: kBW wavefronts side by side, each a strip of 64 * kBC columns
+// of which the inner 64 * kBC - 2K are written (the row-marching K-step pipeline), over
+// kBSeg rows.  Element-wise phases cover the same tile with all 64 * kBW threads.
+constexpr int kBW = 4;
+constexpr int kBC = 1;
+constexpr int kBSeg = 32;
+__host__ __device__ constexpr int batch_strip(int K) { return 64 * kBC - 2 * K; }
+__host__ __device__ constexpr int batch_txo(int K) { return kBW * batch_strip(K); }
+__host__ __device__ constexpr int batch_tyo() { return kBSeg; }
+
 // Problems per batch (the work kernels search the plan's item offsets in LDS).
 constexpr int kMaxBatch = 4096;
 

@@ -37,6 +37,7 @@
 #include <vector>
 
 #include "wh_batched.h"
+#include "wh_march2d.h"
 #include "wh_reduce.h"
 
 namespace wh {
@@ -80,12 +81,12 @@ __device__ __forceinline__ T lap_term(const T* c, const T* kap, int64_t p, int64
 }
 
 // The work of one tile of problem sid in its current phase (lt: the tile within the problem).
-template <typename T, int K, int R, int NW, bool VARC>
+template <typename T, int K, bool VARC>
 __device__ __forceinline__ void batch_tile(const BDesc* __restrict__ descs, const BState* __restrict__ states,
                                            int sid, int lt) {
-  constexpr int TXO = 64 - 2 * K;
-  constexpr int TYO = NW * R - 2 * K;
-  constexpr int NT = 64 * NW;
+  constexpr int TXO = batch_txo(K);
+  constexpr int TYO = batch_tyo();
+  constexpr int NT = 64 * kBW;
   // FP32 state pairs are (W^n, D^{n-1/2} = W^n - W^{n-1}), stepped in the increment form
   // D += dt^2 (L_h W - f cos), W += D; FP64 pairs are (W^n, W^{n-1}).
   constexpr bool INC = sizeof(T) == 4;
@@ -252,127 +253,24 @@ __device__ __forceinline__ void batch_tile(const BDesc* __restrict__ descs, cons
     case BP_B_STEP:
     case BP_A_STEP:
     case BP_R_STEP: {
-      // K' <= K fused steps on a register tile (see k_fused2d)
-      const int Kp = min(K, D.nt - 1 - S.step);
-      const bool force = ph == BP_B_STEP || (sizeof(T) == 4 && D.defect && ph == BP_A_STEP);
+      // K' <= K steps by the row-marching pipeline, one strip per wavefront
       const int pr = S.pair;
-      const T* cin = state_of<T>(D, 2 * pr + 1);
-      const T* pin = state_of<T>(D, 2 * pr);
-      T* cout = state_of<T>(D, 2 * (pr ^ 1) + 1);
-      T* pout = state_of<T>(D, 2 * (pr ^ 1));
-      const T* kap = kap_of<T>(D);
-      const T* fsv = fs_of<T>(D);
-      const int lane = threadIdx.x, wv = threadIdx.y;
-      const int xg = x0 - K + lane;
-      const int yb = y0 - K + wv * R;
-      const bool xin = xg >= 1 && xg <= n - 1;
-      const bool xout = lane >= K && lane < 64 - K && xin;
-      T cur[R], prv[R];
-      double ac[R];
-      T cw[VARC ? R : 1], ce[VARC ? R : 1], cu[VARC ? R : 1], cd[VARC ? R : 1];
-      T frc[R];
-      uint32_t mask = 0, omask = 0;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int y = yb + r;
-        const bool in = xin && y >= 1 && y <= n - 1;
-        const int64_t p = (int64_t)y * P + xg;
-        cur[r] = in ? cin[p] : T(0);
-        prv[r] = in ? pin[p] : T(0);
-        if (in) mask |= 1u << r;
-        // inner-tile nodes start from V (loaded with the state, written back below)
-        const int ry = wv * R + r;
-        const bool o = in && xout && ry >= K && ry < NW * R - K;
-        if (o) omask |= 1u << r;
-        ac[r] = o ? D.V[p] : 0.0;
-        if (VARC) {
-          T kc = T(0), kw = T(0), ke = T(0), ku = T(0), kd = T(0);
-          if (in) {
-            kc = kap[p];
-            kw = kap[p - 1];
-            ke = kap[p + 1];
-            ku = kap[p - P];
-            kd = kap[p + P];
-          }
-          cw[VARC ? r : 0] = kc + kw;
-          ce[VARC ? r : 0] = kc + ke;
-          cu[VARC ? r : 0] = kc + ku;
-          cd[VARC ? r : 0] = kc + kd;
-        }
-        frc[r] = (force && in) ? fsv[p] : T(0);
-      }
-      __shared__ T edge[2][NW][2][64];
-      for (int s = 0; s < Kp; ++s) {
-        const int bb = s & 1;
-        edge[bb][wv][0][threadIdx.x] = cur[0];
-        edge[bb][wv][1][threadIdx.x] = cur[R - 1];
-        __syncthreads();
-        const T up_e = wv > 0 ? edge[bb][wv - 1][1][lane] : T(0);
-        const T dn_e = wv < NW - 1 ? edge[bb][wv + 1][0][lane] : T(0);
-        const T cn = (T)D.cosv[S.step + s];
-        const double ws = D.w[S.step + s + 1];
-        if constexpr (INC) {
-          T uo = up_e;             // old value of the row above (overwritten in place)
-#pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const T c = cur[r];
-            const T dd = r < R - 1 ? cur[r + 1] : dn_e;
-            const T w = from_prev_lane(c);
-            const T e = from_next_lane(c);
-            T lap;
-            if (VARC) {
-              const int q = VARC ? r : 0;
-              lap = (cw[q] * (w - c) + ce[q] * (e - c)) + (cu[q] * (uo - c) + cd[q] * (dd - c));
-            } else {
-              lap = A * (((w - c) + (e - c)) + ((uo - c) + (dd - c)));
-            }
-            lap -= cn * frc[r];
-            // outside the open domain W = D = 0: masking D suffices, branch-free
-            const T dn = __int_as_float(__float_as_int(prv[r] + lap) & (int)(0u - ((mask >> r) & 1u)));
-            const T nw = c + dn;
-            prv[r] = dn;
-            uo = c;
-            cur[r] = nw;
-            ac[r] += ws * (double)nw;
-          }
-        } else {
-#pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const T c = cur[r];
-            const T u = r > 0 ? cur[r - 1] : up_e;
-            const T dd = r < R - 1 ? cur[r + 1] : dn_e;
-            const T w = from_prev_lane(c);
-            const T e = from_next_lane(c);
-            T nw;
-            if (VARC) {
-              const int q = VARC ? r : 0;
-              nw = (c + c) - prv[r] +
-                   (cw[q] * (w - c) + ce[q] * (e - c) + (cu[q] * (u - c) + cd[q] * (dd - c)));
-            } else {
-              nw = (c + c) - prv[r] + A * (((w + e) + (u + dd)) - T(4) * c);
-            }
-            nw -= cn * frc[r];
-            nw = ((mask >> r) & 1u) ? nw : T(0);
-            prv[r] = nw;            // rows r+1.. still read the old cur[r]
-            ac[r] += ws * (double)nw;
-          }
-#pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const T tmp = cur[r];
-            cur[r] = prv[r];
-            prv[r] = tmp;
-          }
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if ((omask >> r) & 1u) {
-          const int64_t p = (int64_t)(yb + r) * P + xg;
-          cout[p] = cur[r];
-          pout[p] = prv[r];
-          D.V[p] = ac[r];
-        }
-      }
+      MarchIO<T> io;
+      io.cin = state_of<T>(D, 2 * pr + 1);
+      io.pin = state_of<T>(D, 2 * pr);
+      io.cout = state_of<T>(D, 2 * (pr ^ 1) + 1);
+      io.pout = state_of<T>(D, 2 * (pr ^ 1));
+      io.V = D.V;
+      io.kap = kap_of<T>(D);
+      io.fs = fs_of<T>(D);
+      io.w = D.w + S.step;
+      io.cs = D.cosv + S.step;
+      io.A = A;
+      io.n = n;
+      io.Kp = min(K, D.nt - 1 - S.step);
+      io.force = ph == BP_B_STEP || (sizeof(T) == 4 && D.defect && ph == BP_A_STEP);
+      const int xs = x0 + (int)threadIdx.y * batch_strip(K);
+      if (xs <= n - 1) march2d<T, K, kBC, VARC>(io, xs, y0, min(y0 + TYO, n));
       break;
     }
     default:
@@ -380,9 +278,17 @@ __device__ __forceinline__ void batch_tile(const BDesc* __restrict__ descs, cons
   }
 #undef TILE_FOR
   if (reduce) {
-    const double sres = block_sum<NW>(acc, tid);
+    const double sres = block_sum<kBW>(acc, tid);
     if (tid == 0) D.partials[lt] = sres;
   }
+}
+
+// Occupancy bound of the work kernels (waves per SIMD): what the row-marching pipeline's
+// registers allow without spilling.
+template <typename T, int K, bool VARC>
+constexpr int batch_waves_per_eu() {
+  if (sizeof(T) == 4) return VARC ? (K <= 2 ? 4 : (K <= 4 ? 3 : 2)) : (K <= 2 ? 6 : (K <= 4 ? 5 : 3));
+  return VARC ? (K <= 2 ? 4 : (K <= 4 ? 3 : 2)) : (K <= 2 ? 6 : (K <= 4 ? 4 : 3));
 }
 
 // One work kernel: persistent blocks take the active tiles of their class that the plan lists.
@@ -393,8 +299,8 @@ __device__ __forceinline__ void batch_tile(const BDesc* __restrict__ descs, cons
 // wh_time_batch_kernel (TAG = 1) from the solver's in profiles; the code is the same.
 // The occupancy bound keeps the register budget of the one-tile-per-block form (constant c:
 // 6 waves per SIMD in FP32, i.e. three 8-wave blocks per CU, 4 in FP64; variable c: 4 and 2).
-template <typename T, int K, int R, int NW, bool VARC, int TAG = 0>
-__global__ __launch_bounds__(64 * NW, sizeof(T) == 4 ? (VARC ? 4 : 6) : (VARC ? 2 : 4))
+template <typename T, int K, bool VARC, int TAG = 0>
+__global__ __launch_bounds__(64 * kBW, (batch_waves_per_eu<T, K, VARC>()))
 void k_batch_work(const BDesc* __restrict__ descs,
                                                         const BState* __restrict__ states,
                                                         int* __restrict__ plan, int nb, int want) {
@@ -408,7 +314,7 @@ void k_batch_work(const BDesc* __restrict__ descs,
   const int tid = threadIdx.y * 64 + threadIdx.x;
   __shared__ int s_start[kCache + 1];
   __shared__ int s_item;
-  for (int k = tid; k <= nact; k += 64 * NW) s_start[k] = start[k];
+  for (int k = tid; k <= nact; k += 64 * kBW) s_start[k] = start[k];
   const int xcd = blockIdx.x & 7;
   int q = 0, c = xcd;
   int c0 = (int)((int64_t)total * c / 8), c1 = (int)((int64_t)total * (c + 1) / 8);
@@ -439,7 +345,7 @@ void k_batch_work(const BDesc* __restrict__ descs,
       else hi = mid - 1;
     }
     const int k0 = s_start[lo];
-    batch_tile<T, K, R, NW, VARC>(descs, states, pid[lo], it - k0);
+    batch_tile<T, K, VARC>(descs, states, pid[lo], it - k0);
     if (tid == 0) s_item = c0 + nxt;
     __syncthreads();
   }
@@ -450,8 +356,8 @@ void k_batch_work(const BDesc* __restrict__ descs,
 // return at once.  Used for the class that holds most of the tiles (the FP32 stepping of a
 // mixed batch, everything in an FP64 batch), where the hardware's block dispatch balances the
 // work best.
-template <typename T, int K, int R, int NW, bool VARC, int TAG = 0>
-__global__ __launch_bounds__(64 * NW, sizeof(T) == 4 ? (VARC ? 4 : 6) : (VARC ? 2 : 4))
+template <typename T, int K, bool VARC, int TAG = 0>
+__global__ __launch_bounds__(64 * kBW, (batch_waves_per_eu<T, K, VARC>()))
 void k_batch_tile(const BDesc* __restrict__ descs, const BState* __restrict__ states,
                   const int* __restrict__ tile_solve, int ntiles, int want) {
   const int gt = xcd_tile_b(blockIdx.x, ntiles);
@@ -463,7 +369,7 @@ void k_batch_tile(const BDesc* __restrict__ descs, const BState* __restrict__ st
   const bool stepping = ph != BP_INIT && ph != BP_UPD1 && ph != BP_UPD2;
   const int cls = (stepping && phase_prec(ph, D.mixed && !S.force64) == 1) ? 1 : 0;
   if (cls != want) return;
-  batch_tile<T, K, R, NW, VARC>(descs, states, sid, gt - D.tile0);
+  batch_tile<T, K, VARC>(descs, states, sid, gt - D.tile0);
 }
 
 // The plan of the next round from the problems' phases (one block; problems in index order,
@@ -707,9 +613,6 @@ __global__ void k_batch_count(const BState* states, int nb, int* remaining) {
 }
 
 // ------------------------------------------------------------------ host side
-// Batched tile: NW = 8 waves of R = 8 rows each, a 64 x 64 register region.
-constexpr int kBR = 8;
-constexpr int kBW = 8;
 
 static bool batch_k_ok(int K) { return K == 2 || K == 4 || K == 8; }
 
@@ -729,7 +632,7 @@ static int work_grid() {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_work<T, K, kBR, kBW, VARC, TAG>, 64 * kBW, 0) !=
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_work<T, K, VARC, TAG>, 64 * kBW, 0) !=
           hipSuccess)
     return 512;
   const int g = (std::max(1, cus * per) / 8) * 8;
@@ -770,7 +673,7 @@ static void launch_round_k(const RoundArgs& a, hipStream_t s, const RoundFork* r
   const BState* st = a.states;
   if (!a.mixed) {
     // FP64 batch: every phase is FP64, one tile per block
-    hipLaunchKernelGGL((k_batch_tile<double, K, kBR, kBW, VARC>), dim3(a.ntiles), b, 0, s, a.descs, st, a.tiles,
+    hipLaunchKernelGGL((k_batch_tile<double, K, VARC>), dim3(a.ntiles), b, 0, s, a.descs, st, a.tiles,
                        a.ntiles, 0);
     return;
   }
@@ -782,9 +685,9 @@ static void launch_round_k(const RoundArgs& a, hipStream_t s, const RoundFork* r
   }
   // mixed batch: the few FP64 and element-wise tiles by persistent blocks over the plan, the
   // FP32 stepping tiles one per block
-  hipLaunchKernelGGL((k_batch_work<double, K, kBR, kBW, VARC>), dim3(a.grids.g64), b, 0, s64, a.descs, st, a.plan,
+  hipLaunchKernelGGL((k_batch_work<double, K, VARC>), dim3(a.grids.g64), b, 0, s64, a.descs, st, a.plan,
                      a.nb, 0);
-  hipLaunchKernelGGL((k_batch_tile<float, K, kBR, kBW, VARC>), dim3(a.ntiles), b, 0, s, a.descs, st, a.tiles,
+  hipLaunchKernelGGL((k_batch_tile<float, K, VARC>), dim3(a.ntiles), b, 0, s, a.descs, st, a.tiles,
                      a.ntiles, 1);
   if (rf) {
     (void)hipEventRecord(rf->join, rf->s2);
@@ -808,7 +711,7 @@ static void launch_round(int K, bool varc, const RoundArgs& a, hipStream_t s, co
 // The FP32 stepping kernel alone, under its measurement tag (wh_time_batch_kernel).
 template <int K, bool VARC>
 static void launch_work_tagged(const RoundArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_batch_tile<float, K, kBR, kBW, VARC, 1>), dim3(a.ntiles), dim3(64, kBW), 0, s, a.descs,
+  hipLaunchKernelGGL((k_batch_tile<float, K, VARC, 1>), dim3(a.ntiles), dim3(64, kBW), 0, s, a.descs,
                      (const BState*)a.states, a.tiles, a.ntiles, 1);
 }
 
@@ -821,7 +724,7 @@ static void launch_work_timing(int K, bool varc, const RoundArgs& a, hipStream_t
 }
 
 static int tile_dim(int n, int K, int axis) {
-  const int t = axis == 0 ? 64 - 2 * K : kBW * kBR - 2 * K;
+  const int t = axis == 0 ? batch_txo(K) : batch_tyo();
   return (n - 1 + t - 1) / t;
 }
 
@@ -1327,7 +1230,7 @@ wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
       in.nt = tps[i].nt;
       in.m = tps[i].m;
       in.k_fuse = K;
-      in.k_rows = kBR;
+      in.k_rows = kBSeg;
       in.k_waves = kBW;
       in.rel_res = SF[i].rel;
       in.true_rel_res = mixed ? SF[i].rel : SF[i].pq;

@@ -1,0 +1,271 @@
+// K leapfrog steps of the 2D wave equation with the filter sum, as a row-marching pipeline
+// run by one wavefront on its own (no LDS, no barriers).
+//
+// The scheme is that of eq. discreteWaveExplicit with the trapezoid sum of eq. quadrature
+// folded in (Section 2.2).  A wavefront owns a strip of 64*C columns (lane l holds columns
+// xs - K + C l .. + C - 1) and marches over the rows of its tile.  When row t of the input
+// state (time level 0) arrives, level 1 can be formed on row t-1, level 2 on row t-2, ...,
+// level K on row t-K: each level s+1 needs level s on three consecutive rows and nothing
+// else, so every level keeps a ring of its last rows in registers.  x-neighbours come from
+// the adjacent columns of the lane and, at the lane's edge, from the adjacent lane (DPP
+// wavefront shift).  The strip's K outermost columns on each side are halo: their values
+// go stale by one column per level, so the inner 64*C - 2K columns are written.  Along y
+// the pipeline starts K rows before the tile and ends K rows after it, which costs 2K rows
+// of loads and work per tile (the tile is much taller than K).
+//
+// HBM traffic per written point is the state pair in and out and V read and written once
+// per launch (FP32: 8 + 8 + 16 bytes), with the halo columns read again by the neighbour
+// strip (mostly from L2).
+//
+// Rings: with the loop over rows unrolled U times (U a multiple of 4 and of K), every ring
+// slot is a compile-time index, so the rings stay in registers:
+//   W level s (s < K): 4 rows (3 needed), slot = (row - tstart) & 3
+//   FP32 increment D (one register per row in flight: D_s(r) becomes D_{s+1}(r)),
+//     and the FP64 sum of V: K rows, slot = (row - tstart) % K
+//   FP64 previous level -1: 2 rows.
+// Rows of the next input are loaded PF iterations ahead.
+//
+// Points outside the open domain are held at zero (Dirichlet data).  When the launch
+// advances Kp < K steps (the last launch of a wave solve), the levels above Kp are still
+// formed but carry no filter weight, and the output is level Kp on row t - Kp.
+//
+// The unrolled body has no branches, so that the compiler can interleave the level chains
+// of consecutive rows (level s+1 of row t-s needs level s of rows t-s-1 .. t-s+1 only):
+// every load and store is a buffer access whose offset is moved out of the buffer's range
+// when the point is masked (the hardware returns 0 for such a load and drops such a store),
+// and masked results are selected, not branched around.
+#pragma once
+#include "wh_common.h"
+
+namespace wh {
+
+template <typename T>
+struct MarchIO {
+  const T* cin;        // W^n
+  const T* pin;        // FP32: D^{n-1/2}; FP64: W^{n-1}
+  T* cout;             // W^{n+Kp}
+  T* pout;             // FP32: D^{n+Kp-1/2}; FP64: W^{n+Kp-1}
+  double* V;           // filter sum, += sum_s w_s W^{n+s}
+  const T* kap;        // VARC: c2 dt^2 / (2 h^2) per node
+  const T* fs;         // forcing dt^2 f (used when force)
+  const double* w;     // w[s] = weight of W^{n+s}, s = 1..Kp (w[0] unused)
+  const double* cs;    // cs[s] = cos(omega t^{n+s}), s = 0..Kp-1
+  T A;                 // constant c: dt^2 / h^2
+  int n;
+  int Kp;
+  bool force;
+};
+
+// Raw buffer accesses (offsets in bytes); an offset at or beyond the buffer's size reads 0
+// and writes nothing.
+constexpr int kBufOff = 0x7ffffff0;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int off);
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, int off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, int off) {
+  using u2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, off, 0, 0);
+}
+
+// Node arrays must hold (n+1)^2 elements of at most 2^31 bytes.
+// FULL: the launch advances K steps (Kp == K), so the output is fixed at level K and the
+// body stays free of branches; otherwise the store of level Kp is a uniform branch.
+template <typename T, int K, int C, bool VARC, bool FORCE, bool FULL>
+__device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int ys, int ye) {
+  constexpr bool INC = sizeof(T) == 4;
+  constexpr int U = K < 4 ? 4 : K;
+  static_assert(U % 4 == 0 && U % K == 0, "unroll must be a multiple of the ring sizes");
+  constexpr int PF = 2;
+  constexpr int DK = INC ? K : 1;
+  constexpr int PK = INC ? 1 : 2;
+  constexpr int TS = (int)sizeof(T);
+  const int n = io.n;
+  const int P = n + 1;
+  const int64_t NN = (int64_t)P * P;
+  const int Kp = io.Kp;
+  const int lane = threadIdx.x;
+  const int xb = xs - K + C * lane;
+  const __amdgpu_buffer_rsrc_t rc = buf_rsrc(io.cin, NN * TS), rp = buf_rsrc(io.pin, NN * TS);
+  const __amdgpu_buffer_rsrc_t rco = buf_rsrc(io.cout, NN * TS), rpo = buf_rsrc(io.pout, NN * TS);
+  const __amdgpu_buffer_rsrc_t rv = buf_rsrc(io.V, NN * 8);
+  const __amdgpu_buffer_rsrc_t rk = buf_rsrc(VARC ? (const void*)io.kap : (const void*)io.cin, NN * TS);
+  const __amdgpu_buffer_rsrc_t rf = buf_rsrc(FORCE ? (const void*)io.fs : (const void*)io.cin, NN * TS);
+
+  bool colin[C], colout[C];
+  int colm[C];   // all ones inside the open domain, else 0
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int col = xb + c;
+    colin[c] = col >= 1 && col <= n - 1;
+    const int lc = C * lane + c;
+    colout[c] = colin[c] && lc >= K && lc < 64 * C - K;
+    colm[c] = colin[c] ? -1 : 0;
+    // opaque to the optimiser, which would otherwise turn the masking below back into a
+    // select and then into a branch around the stencil
+    asm("" : "+v"(colm[c]));
+  }
+  double wts[K + 1];
+  T cn[K];
+#pragma unroll
+  for (int s = 0; s < K; ++s) {
+    wts[s + 1] = s < Kp ? io.w[s + 1] : 0.0;
+    cn[s] = (FORCE && s < Kp) ? (T)io.cs[s] : T(0);
+  }
+
+  T Wr[K][4][C];
+  T Dr[DK][C];
+  T Pr[PK][C];
+  double acc[K][C];
+#pragma unroll
+  for (int s = 0; s < K; ++s)
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Wr[s][q][c] = T(0);
+      acc[s][c] = 0.0;
+    }
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+#pragma unroll
+    for (int q = 0; q < DK; ++q) Dr[q][c] = T(0);
+#pragma unroll
+    for (int q = 0; q < PK; ++q) Pr[q][c] = T(0);
+  }
+
+  const int tstart = ys - K;
+  const int tlast = ye + K - 1;   // last input row the pipeline needs
+  const int nit = ((ye - ys + 2 * K) + U - 1) / U * U;
+
+  T sW[PF][C], sP[PF][C];
+  double sV[PF][C];
+#define WH_MARCH_LOAD(y_, q_)                                                    \
+  {                                                                             \
+    const int y = (y_);                                                         \
+    const bool rin = y >= 1 && y <= n - 1 && y <= tlast;                        \
+    const bool rout = y >= ys && y < ye;                                        \
+    _Pragma("unroll") for (int c = 0; c < C; ++c) {                             \
+      const int p = y * P + xb + c;                                             \
+      const int o = (rin && colin[c]) ? p * TS : kBufOff;                       \
+      sW[q_][c] = buf_load<T>(rc, o);                                           \
+      sP[q_][c] = buf_load<T>(rp, o);                                           \
+      sV[q_][c] = buf_load<double>(rv, (rout && colout[c]) ? p * 8 : kBufOff);  \
+    }                                                                           \
+  }
+#pragma unroll
+  for (int q = 0; q < PF; ++q) WH_MARCH_LOAD(tstart + q, q)
+
+  for (int i0 = 0; i0 < nit; i0 += U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = tstart + i0 + u;
+      // row t of level 0 (and of level -1 in FP64) enters the rings
+      T newD[C];
+      double newV[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        Wr[0][u & 3][c] = sW[u % PF][c];
+        if constexpr (INC) newD[c] = sP[u % PF][c];
+        else Pr[u & 1][c] = sP[u % PF][c];
+        newV[c] = sV[u % PF][c];
+      }
+      WH_MARCH_LOAD(t + PF, u % PF)
+#pragma unroll
+      for (int s = 0; s < K; ++s) {
+        // level s+1 on row r from level s on rows r-1, r, r+1
+        const int r = t - s - 1;
+        const bool rowok = r >= 1 && r <= n - 1;
+        const int rowm = ~(((r - 1) | (n - 1 - r)) >> 31);   // all ones for 1 <= r <= n-1
+        const bool rowout = r >= ys && r < ye;
+        const int qc = (u - s - 1) & 3, qu = (u - s - 2) & 3, qd = (u - s) & 3;
+        const int qk = ((u - s - 1) % K + K) % K;
+        T wv[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) wv[c] = Wr[s][qc][c];
+        const T wl = from_prev_lane(wv[C - 1]);
+        const T er = from_next_lane(wv[0]);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const T cc = wv[c];
+          const T we = c > 0 ? wv[c - 1] : wl;
+          const T ea = c < C - 1 ? wv[c + 1] : er;
+          const T up = Wr[s][qu][c];
+          const T dn = Wr[s][qd][c];
+          const bool ok = rowok && colin[c];
+          const int p = r * P + xb + c;
+          T lap;
+          if constexpr (VARC) {
+            const T kc = buf_load<T>(rk, ok ? p * TS : kBufOff);
+            const T kw = buf_load<T>(rk, ok ? (p - 1) * TS : kBufOff);
+            const T ke = buf_load<T>(rk, ok ? (p + 1) * TS : kBufOff);
+            const T ku = buf_load<T>(rk, ok ? (p - P) * TS : kBufOff);
+            const T kd = buf_load<T>(rk, ok ? (p + P) * TS : kBufOff);
+            lap = ((kc + kw) * (we - cc) + (kc + ke) * (ea - cc)) + ((kc + ku) * (up - cc) + (kc + kd) * (dn - cc));
+          } else if constexpr (INC) {
+            lap = io.A * (((we - cc) + (ea - cc)) + ((up - cc) + (dn - cc)));
+          } else {
+            lap = io.A * (((we + ea) + (up + dn)) - T(4) * cc);
+          }
+          if constexpr (FORCE) lap -= cn[s] * buf_load<T>(rf, ok ? p * TS : kBufOff);
+          const int m = colm[c] & rowm;
+          T nw, pn;
+          if constexpr (INC) {
+            const T d = __int_as_float(__float_as_int(Dr[qk][c] + lap) & m);
+            Dr[qk][c] = d;
+            nw = cc + d;
+            pn = d;
+          } else {
+            const T pv = s == 0 ? Pr[(u - 1) & 1][c] : Wr[s - 1][qc][c];
+            nw = __longlong_as_double(__double_as_longlong((cc + cc) - pv + lap) & (long long)m);
+            pn = cc;
+          }
+          if (s + 1 < K) Wr[s + 1][qc][c] = nw;
+          const double a = acc[qk][c] + wts[s + 1] * (double)nw;
+          acc[qk][c] = a;
+          if (FULL ? s == K - 1 : s + 1 == Kp) {
+            // level Kp on an output row and column is written (a masked store is dropped)
+            const bool o = rowout && colout[c];
+            buf_store(nw, rco, o ? p * TS : kBufOff);
+            buf_store(pn, rpo, o ? p * TS : kBufOff);
+            buf_store(a, rv, o ? p * 8 : kBufOff);
+          }
+        }
+      }
+      // row t starts its D and its filter sum (the slots of row t-K, finished above)
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        if constexpr (INC) Dr[u % K][c] = newD[c];
+        acc[u % K][c] = newV[c];
+      }
+      // FP64: keep the scheduler from overlapping consecutive rows, whose live rings would
+      // otherwise cost more registers than the overlap gains
+      if constexpr (!INC) __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+#undef WH_MARCH_LOAD
+}
+
+template <typename T, int K, int C, bool VARC>
+__device__ __forceinline__ void march2d(const MarchIO<T>& io, int xs, int ys, int ye) {
+  if (io.force) {
+    if (io.Kp == K) march2d_body<T, K, C, VARC, true, true>(io, xs, ys, ye);
+    else march2d_body<T, K, C, VARC, true, false>(io, xs, ys, ye);
+  } else {
+    if (io.Kp == K) march2d_body<T, K, C, VARC, false, true>(io, xs, ys, ye);
+    else march2d_body<T, K, C, VARC, false, false>(io, xs, ys, ye);
+  }
+}
+
+}  // namespace wh

@@ -398,9 +398,9 @@ void model_batch_plan(dim3 g, dim3 b, void** args) {
   for (int k = 0; k < 16; ++k) plan[2 * plan_stride(nb) + k] = 0;
 }
 
-void check_batch_item(const BDesc* descs, const BState* states, int nb, int sid, int lt, int want, int K, int R,
-                      int NW, int VARC, int it) {
-  const int TXO = 64 - 2 * K, TYO = NW * R - 2 * K;
+void check_batch_item(const BDesc* descs, const BState* states, int nb, int sid, int lt, int want, int K,
+                      int VARC, int it) {
+  const int TXO = batch_txo(K), TYO = batch_tyo();
       if (sid < 0 || sid >= nb) fail("item %d maps to problem %d", it, sid);
       const BDesc& d = descs[sid];
       const BState& st = states[sid];
@@ -410,10 +410,11 @@ void check_batch_item(const BDesc* descs, const BState* states, int nb, int sid,
       const int64_t P = (int64_t)n + 1, N = P * P;
       const int x0 = 1 + (lt % d.ntx) * TXO, y0 = 1 + (lt / d.ntx) * TYO;
       if (x0 > n - 1 || y0 > n - 1) fail("tile origin (%d, %d) outside the grid n = %d", x0, y0, n);
-      // nodes the phase can touch: the tile's register region (with its halo) clipped to the
-      // interior, and their neighbours
-      const int ya = std::max(1, y0 - K), yb = std::min(n - 1, y0 - K + NW * R - 1);
-      const int xa = std::max(1, x0 - K), xb = std::min(n - 1, x0 - K + 63);
+      // nodes the phase can touch: the tile with its K-point halo (the strips' halo columns,
+      // the pipeline's rows before and after the tile) clipped to the interior, and their
+      // neighbours
+      const int ya = std::max(1, y0 - K), yb = std::min(n - 1, y0 + TYO + K - 1);
+      const int xa = std::max(1, x0 - K), xb = std::min(n - 1, x0 + TXO + K - 1);
       const int64_t lo_i = (int64_t)(ya - 1) * P + xa - 1, hi_i = (int64_t)(yb + 1) * P + xb + 1;
       if (lo_i < 0 || hi_i >= N) fail("tile node range [%lld, %lld] outside 0..%lld", (long long)lo_i,
                                       (long long)hi_i, (long long)N - 1);
@@ -435,7 +436,7 @@ void check_batch_item(const BDesc* descs, const BState* states, int nb, int sid,
 }
 
 void model_batch_work(const std::vector<std::string>& t, dim3 g, dim3 b, void** args) {
-  const int K = ti(t, 1), R = ti(t, 2), NW = ti(t, 3), VARC = ti(t, 4);
+  const int K = ti(t, 1), VARC = ti(t, 2), NW = kBW;
   const BDesc* descs = arg<const BDesc*>(args, 0);
   const BState* states = arg<const BState*>(args, 1);
   const int* plan = arg<const int*>(args, 2);
@@ -450,7 +451,6 @@ void model_batch_work(const std::vector<std::string>& t, dim3 g, dim3 b, void** 
   const int* start = pl + 2 + nb;
   std::vector<int> hit(total, 0);
   check_range(plan + 2 * plan_stride(nb) + 8 * want, 0, 32, "item counters");
-  const int TXO = 64 - 2 * K, TYO = NW * R - 2 * K;
   // items are taken dynamically from the 8 chunk counters; every item of [0, total) is taken once
   for (int c = 0; c < 8; ++c) {
     const int c0 = (int)((int64_t)total * c / 8), c1 = (int)((int64_t)total * (c + 1) / 8);
@@ -462,7 +462,7 @@ void model_batch_work(const std::vector<std::string>& t, dim3 g, dim3 b, void** 
         else hi = mid - 1;
       }
       hit[it]++;
-      check_batch_item(descs, states, nb, pid[lo], it - start[lo], want, K, R, NW, VARC, it);
+      check_batch_item(descs, states, nb, pid[lo], it - start[lo], want, K, VARC, it);
     }
   }
   for (int i = 0; i < total; ++i)
@@ -470,7 +470,7 @@ void model_batch_work(const std::vector<std::string>& t, dim3 g, dim3 b, void** 
 }
 
 void model_batch_tile(const std::vector<std::string>& t, dim3 g, dim3 b, void** args) {
-  const int K = ti(t, 1), R = ti(t, 2), NW = ti(t, 3), VARC = ti(t, 4);
+  const int K = ti(t, 1), VARC = ti(t, 2), NW = kBW;
   const BDesc* descs = arg<const BDesc*>(args, 0);
   const BState* states = arg<const BState*>(args, 1);
   const int* tiles = arg<const int*>(args, 2);
@@ -490,7 +490,7 @@ void model_batch_tile(const std::vector<std::string>& t, dim3 g, dim3 b, void** 
     const BState& st = states[sid];
     if (batch_class(d, st) != want) continue;
     if (gt < d.tile0 || gt >= d.tile0 + d.ntx * d.nty) fail("tile %d outside problem %d's range", gt, sid);
-    check_batch_item(descs, states, nb, sid, gt - d.tile0, want, K, R, NW, VARC, gt);
+    check_batch_item(descs, states, nb, sid, gt - d.tile0, want, K, VARC, gt);
   }
 }
 
