@@ -277,8 +277,8 @@ wh_status wh_helmholtz_residual(wh_ctx* ctx, const wh_grid* grid, const double* 
 /* Bytes of device workspace needed by wh_solve_batched for these problems. */
 size_t wh_workspace_bytes_batched(int32_t nb, const wh_problem* probs, const wh_params* params);
 
-/* Solve nb independent 2D problems (1 <= nb <= 4096; grids of any size, own omega, source and
- * optional c2) with CG on the WaveHoltz system, in one device-driven batch: every
+/* Solve nb independent 2D problems (1 <= nb <= 4096; grids of any size 4 <= n <= 16000, own
+ * omega, source and optional c2) with CG on the WaveHoltz system, in one device-driven batch: every
  * problem's wave solves and Krylov updates are advanced by shared launches captured
  * in a hipGraph (the paper's motivation of many right-hand sides and frequencies,
  * Section 1).  params->solver WH_CG: Algorithm 3 without deflation.  WH_DCG:

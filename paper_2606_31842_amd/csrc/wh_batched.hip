@@ -810,7 +810,8 @@ wh_status batch_validate(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const
     const wh_problem& q = probs[i];
     if (q.grid.dim != 2) WHB_FAIL(ctx, WH_EUNSUPPORTED, "batched solves are 2D (problem %d)", i);
     if (q.grid.order != 2) WHB_FAIL(ctx, WH_EUNSUPPORTED, "order must be 2 (problem %d)", i);
-    if (q.grid.n < 4 || q.grid.n > 46340) WHB_FAIL(ctx, WH_EINVAL, "bad n (problem %d)", i);
+    // the work kernels address each node array with 32-bit byte offsets
+    if (q.grid.n < 4 || q.grid.n > 16000) WHB_FAIL(ctx, WH_EINVAL, "n must lie in [4, 16000] (problem %d)", i);
     if (!(q.omega > 0)) WHB_FAIL(ctx, WH_EINVAL, "omega must be > 0 (problem %d)", i);
     if (!q.f || !q.u) WHB_FAIL(ctx, WH_EINVAL, "f / u is NULL (problem %d)", i);
     if ((q.c2 != nullptr) != varc0)
