@@ -287,8 +287,8 @@ __device__ __forceinline__ void batch_tile(const BDesc* __restrict__ descs, cons
 // registers allow without spilling.
 template <typename T, int K, bool VARC>
 constexpr int batch_waves_per_eu() {
-  if (sizeof(T) == 4) return VARC ? (K <= 2 ? 4 : (K <= 4 ? 3 : 2)) : (K <= 2 ? 6 : (K <= 4 ? 5 : 3));
-  return VARC ? (K <= 2 ? 4 : (K <= 4 ? 3 : 2)) : (K <= 2 ? 6 : (K <= 4 ? 4 : 3));
+  if (sizeof(T) == 4) return VARC ? (K <= 2 ? 4 : (K <= 4 ? 3 : 2)) : (K <= 2 ? 6 : (K <= 4 ? 4 : 3));
+  return VARC ? (K <= 2 ? 4 : (K <= 4 ? 3 : 2)) : (K <= 2 ? 6 : (K <= 4 ? 4 : 2));
 }
 
 // One work kernel: persistent blocks take the active tiles of their class that the plan lists.

@@ -21,7 +21,7 @@
 // slot is a compile-time index, so the rings stay in registers:
 //   W level s (s < K): 4 rows (3 needed), slot = (row - tstart) & 3
 //   FP32 increment D (one register per row in flight: D_s(r) becomes D_{s+1}(r)),
-//     and the FP64 sum of V: K rows, slot = (row - tstart) % K
+//     the forcing, and the FP64 sum of V: K rows, slot = (row - tstart) % K
 //   FP64 previous level -1: 2 rows.
 // Rows of the next input are loaded PF iterations ahead.
 //
@@ -125,9 +125,11 @@ __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int y
     cn[s] = (FORCE && s < Kp) ? (T)io.cs[s] : T(0);
   }
 
+  constexpr int FK = FORCE ? K : 1;
   T Wr[K][4][C];
   T Dr[DK][C];
   T Pr[PK][C];
+  T Fr[FK][C];   // forcing of the rows in flight (same slots as D)
   double acc[K][C];
 #pragma unroll
   for (int s = 0; s < K; ++s)
@@ -143,13 +145,15 @@ __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int y
     for (int q = 0; q < DK; ++q) Dr[q][c] = T(0);
 #pragma unroll
     for (int q = 0; q < PK; ++q) Pr[q][c] = T(0);
+#pragma unroll
+    for (int q = 0; q < FK; ++q) Fr[q][c] = T(0);
   }
 
   const int tstart = ys - K;
   const int tlast = ye + K - 1;   // last input row the pipeline needs
   const int nit = ((ye - ys + 2 * K) + U - 1) / U * U;
 
-  T sW[PF][C], sP[PF][C];
+  T sW[PF][C], sP[PF][C], sF[PF][C];
   double sV[PF][C];
 #define WH_MARCH_LOAD(y_, q_)                                                    \
   {                                                                             \
@@ -161,6 +165,7 @@ __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int y
       const int o = (rin && colin[c]) ? p * TS : kBufOff;                       \
       sW[q_][c] = buf_load<T>(rc, o);                                           \
       sP[q_][c] = buf_load<T>(rp, o);                                           \
+      if (FORCE) sF[q_][c] = buf_load<T>(rf, o);                                \
       sV[q_][c] = buf_load<double>(rv, (rout && colout[c]) ? p * 8 : kBufOff);  \
     }                                                                           \
   }
@@ -172,13 +177,14 @@ __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int y
     for (int u = 0; u < U; ++u) {
       const int t = tstart + i0 + u;
       // row t of level 0 (and of level -1 in FP64) enters the rings
-      T newD[C];
+      T newD[C], newF[C];
       double newV[C];
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         Wr[0][u & 3][c] = sW[u % PF][c];
         if constexpr (INC) newD[c] = sP[u % PF][c];
         else Pr[u & 1][c] = sP[u % PF][c];
+        if constexpr (FORCE) newF[c] = sF[u % PF][c];
         newV[c] = sV[u % PF][c];
       }
       WH_MARCH_LOAD(t + PF, u % PF)
@@ -218,7 +224,7 @@ __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int y
           } else {
             lap = io.A * (((we + ea) + (up + dn)) - T(4) * cc);
           }
-          if constexpr (FORCE) lap -= cn[s] * buf_load<T>(rf, ok ? p * TS : kBufOff);
+          if constexpr (FORCE) lap -= cn[s] * Fr[qk][c];
           const int m = colm[c] & rowm;
           T nw, pn;
           if constexpr (INC) {
@@ -247,6 +253,7 @@ __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int y
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         if constexpr (INC) Dr[u % K][c] = newD[c];
+        if constexpr (FORCE) Fr[u % K][c] = newF[c];
         acc[u % K][c] = newV[c];
       }
       // FP64: keep the scheduler from overlapping consecutive rows, whose live rings would
