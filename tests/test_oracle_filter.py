@@ -140,6 +140,23 @@ def test_beta_lower_bound_and_mu_upper_bound():
     assert abs(tr.beta_continuous(0.0, 5.0) - (-0.5)) < 1e-15
 
 
+@pytest.mark.parametrize("omega,n,cfl", [(5.3, 64, 0.5), (17.1, 64, 0.5), (40.0, 128, 0.5), (23.4, 96, 0.7)])
+def test_discrete_beta_bounded_for_a_stable_step(omega, n, cfl):
+    """With a stable leapfrog step (c dt/h below 1/sqrt(2) in 2D) the discrete filter's
+    eigenvalue beta_h stays in [-1/2, 1 + O(dt^4)] over the whole 2D spectrum
+    lambda^2 in [0, 8/h^2], so |A| <= 1.5 (the bound the solvers test for instability);
+    beyond the CFL bound it leaves that range by orders of magnitude."""
+    h = 1.0 / n
+    tp = tpm.time_parameters(omega, h, 1.0, cfl=cfl)
+    lam2 = np.linspace(0.0, 8.0 / h ** 2, 400001)
+    b = tr.beta_discrete(lam2, tp)
+    assert b.min() >= -0.5 - 1e-12 and b.max() <= 1.0 + 1e-3
+    assert np.abs(1.0 - b).max() <= 1.5 + 1e-12
+    # the same time step applied to c = 2 (an understated c_max of 1): unstable
+    bu = tr.beta_discrete(4.0 * lam2, tp)
+    assert np.abs(bu).max() > 1e6
+
+
 # ------------------------------------------------------------ the matrix A
 @pytest.mark.parametrize("dim,n,omega,varc", [(2, 8, 6.1, False), (2, 8, 6.1, True), (3, 5, 5.3, True)])
 def test_dense_A_symmetric_spectrum(dim, n, omega, varc):
