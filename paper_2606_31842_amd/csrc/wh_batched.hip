@@ -270,7 +270,7 @@ __device__ __forceinline__ void batch_tile(const BDesc* __restrict__ descs, cons
       io.Kp = min(K, D.nt - 1 - S.step);
       io.force = ph == BP_B_STEP || (sizeof(T) == 4 && D.defect && ph == BP_A_STEP);
       const int xs = x0 + (int)threadIdx.y * batch_strip(K);
-      if (xs <= n - 1) march2d<T, K, kBC, VARC>(io, xs, y0, min(y0 + TYO, n));
+      if (xs <= n - 1) march2d<T, K, kBC, VARC>(io, xs, y0, min(y0 + TYO, n), ((lt / D.ntx) & 1) != 0);
       break;
     }
     default:

@@ -83,7 +83,7 @@ __device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, in
 // Node arrays must hold (n+1)^2 elements of at most 2^31 bytes.
 // FULL: the launch advances K steps (Kp == K), so the output is fixed at level K and the
 // body stays free of branches; otherwise the store of level Kp is a uniform branch.
-template <typename T, int K, int C, bool VARC, bool FORCE, bool FULL>
+template <typename T, int K, int C, bool VARC, bool FORCE, bool FULL, bool UP>
 __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int ys, int ye) {
   constexpr bool INC = sizeof(T) == 4;
   constexpr int U = K < 4 ? 4 : K;
@@ -151,6 +151,10 @@ __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int y
 
   const int tstart = ys - K;
   const int tlast = ye + K - 1;   // last input row the pipeline needs
+  // pipeline row t is grid row rb + sg * t: downwards from row ys - K, or upwards from row
+  // ye + K - 1 (the stencil is symmetric in y, so only the addresses change)
+  const int rb = UP ? ys + ye - 1 : 0;
+  constexpr int sg = UP ? -1 : 1;
   const int nit = ((ye - ys + 2 * K) + U - 1) / U * U;
 
   T sW[PF][C], sP[PF][C], sF[PF][C];
@@ -158,10 +162,11 @@ __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int y
 #define WH_MARCH_LOAD(y_, q_)                                                    \
   {                                                                             \
     const int y = (y_);                                                         \
-    const bool rin = y >= 1 && y <= n - 1 && y <= tlast;                        \
-    const bool rout = y >= ys && y < ye;                                        \
+    const int ya = rb + sg * y;                                                 \
+    const bool rin = ya >= 1 && ya <= n - 1 && y <= tlast;                      \
+    const bool rout = ya >= ys && ya < ye;                                      \
     _Pragma("unroll") for (int c = 0; c < C; ++c) {                             \
-      const int p = y * P + xb + c;                                             \
+      const int p = ya * P + xb + c;                                            \
       const int o = (rin && colin[c]) ? p * TS : kBufOff;                       \
       sW[q_][c] = buf_load<T>(rc, o);                                           \
       sP[q_][c] = buf_load<T>(rp, o);                                           \
@@ -191,7 +196,7 @@ __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int y
 #pragma unroll
       for (int s = 0; s < K; ++s) {
         // level s+1 on row r from level s on rows r-1, r, r+1
-        const int r = t - s - 1;
+        const int r = rb + sg * (t - s - 1);   // its grid row
         const bool rowok = r >= 1 && r <= n - 1;
         const int rowm = ~(((r - 1) | (n - 1 - r)) >> 31);   // all ones for 1 <= r <= n-1
         const bool rowout = r >= ys && r < ye;
@@ -216,8 +221,9 @@ __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int y
             const T kc = buf_load<T>(rk, ok ? p * TS : kBufOff);
             const T kw = buf_load<T>(rk, ok ? (p - 1) * TS : kBufOff);
             const T ke = buf_load<T>(rk, ok ? (p + 1) * TS : kBufOff);
-            const T ku = buf_load<T>(rk, ok ? (p - P) * TS : kBufOff);
-            const T kd = buf_load<T>(rk, ok ? (p + P) * TS : kBufOff);
+            // the pipeline's previous row is grid row r - sg
+            const T ku = buf_load<T>(rk, ok ? (p - sg * P) * TS : kBufOff);
+            const T kd = buf_load<T>(rk, ok ? (p + sg * P) * TS : kBufOff);
             lap = ((kc + kw) * (we - cc) + (kc + ke) * (ea - cc)) + ((kc + ku) * (up - cc) + (kc + kd) * (dn - cc));
           } else if constexpr (INC) {
             lap = io.A * (((we - cc) + (ea - cc)) + ((up - cc) + (dn - cc)));
@@ -264,15 +270,25 @@ __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int y
 #undef WH_MARCH_LOAD
 }
 
-template <typename T, int K, int C, bool VARC>
-__device__ __forceinline__ void march2d(const MarchIO<T>& io, int xs, int ys, int ye) {
+// up: march from the tile's last row towards its first.  Vertically adjacent tiles march in
+// opposite directions, so the halo rows two tiles share are read by both at about the same
+// time (both at the start or both at the end of their marches) and the second read finds them
+// in L2.
+template <typename T, int K, int C, bool VARC, bool UP>
+__device__ __forceinline__ void march2d_dir(const MarchIO<T>& io, int xs, int ys, int ye) {
   if (io.force) {
-    if (io.Kp == K) march2d_body<T, K, C, VARC, true, true>(io, xs, ys, ye);
-    else march2d_body<T, K, C, VARC, true, false>(io, xs, ys, ye);
+    if (io.Kp == K) march2d_body<T, K, C, VARC, true, true, UP>(io, xs, ys, ye);
+    else march2d_body<T, K, C, VARC, true, false, UP>(io, xs, ys, ye);
   } else {
-    if (io.Kp == K) march2d_body<T, K, C, VARC, false, true>(io, xs, ys, ye);
-    else march2d_body<T, K, C, VARC, false, false>(io, xs, ys, ye);
+    if (io.Kp == K) march2d_body<T, K, C, VARC, false, true, UP>(io, xs, ys, ye);
+    else march2d_body<T, K, C, VARC, false, false, UP>(io, xs, ys, ye);
   }
+}
+
+template <typename T, int K, int C, bool VARC>
+__device__ __forceinline__ void march2d(const MarchIO<T>& io, int xs, int ys, int ye, bool up) {
+  if (up) march2d_dir<T, K, C, VARC, true>(io, xs, ys, ye);
+  else march2d_dir<T, K, C, VARC, false>(io, xs, ys, ye);
 }
 
 }  // namespace wh
