@@ -324,7 +324,8 @@ def main():
     ap.add_argument("--no-cg", action="store_true", help="cfg4: skip the batched mixed CG comparison run")
     ap.add_argument("--probe-traffic", action="store_true",
                     help="for hardware-counter runs: a plain 256 MiB device copy, then the workload's "
-                         "dominant kernel (cfg4: the batched FP32 work kernel, 5 launches), and exit")
+                         "dominant kernel (cfg4: the batched FP32 work kernel, 5 launches; cfg3: the "
+                         "autotuner's trials and the timed 3D stepping kernels, no solves), and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solves of this workload are "
@@ -594,6 +595,8 @@ def run_cfg3(args, np, torch, wh, wl):
         out[f"step_kernel_{prec}"] = {"us_per_launch": us, "k_fuse": k, "rows": sh["rows"], "waves": sh["waves"],
                                       "us_per_step": us / k, "gpts": pts * k / us / 1e3, "bytes_per_pt_step": bpp,
                                       "achieved_gbs": bpp * pts * k / (us * 1e-6) / 1e9}
+    if args.probe_traffic:
+        return out
     # GMRES(40) as the workload states it (capped: it stalls near resonance); CG to the
     # tolerance in both precisions
     runs = [("gmres", "mixed", args.max_iters or 2000), ("cg", "f64", 20000), ("cg", "mixed", 20000)]
