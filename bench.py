@@ -599,7 +599,9 @@ def run_cfg3(args, np, torch, wh, wl):
         return out
     # GMRES(40) as the workload states it (capped: it stalls near resonance); CG to the
     # tolerance in both precisions
-    runs = [("gmres", "mixed", args.max_iters or 2000), ("cg", "f64", 20000), ("cg", "mixed", 20000)]
+    # FP64 GMRES(40) beside the mixed one separates restart stagnation from the FP32 operator
+    runs = [("gmres", "mixed", args.max_iters or 2000), ("gmres", "f64", args.max_iters or 2000),
+            ("cg", "f64", 20000), ("cg", "mixed", 20000)]
     for solver, prec, cap in runs:
         wh.solve(f, p.omega, c2=c2, solver=solver, precision=prec, tol=1e-8, max_iters=2, restart=40)
         (u, info), dt = _timed(torch, lambda: wh.solve(f, p.omega, c2=c2, solver=solver, precision=prec,
@@ -622,7 +624,7 @@ def run_cfg3(args, np, torch, wh, wl):
         cb = {"kind": "oracle", "cores": 1, "host": cpu_model(), "s_per_wave_solve": round(per, 2), "nt": tp.nt,
               "oracle_gpts": pts * tp.nt / per / 1e9,
               "sample": "3 FP64 wave solves of the variable-c 256^3 operator (scipy CSR, one thread)"}
-        for key in ("gmres_mixed", "cg_f64", "cg_mixed"):
+        for key in ("gmres_mixed", "gmres_f64", "cg_f64", "cg_mixed"):
             nws = out[key]["wave_solves_f32"] + out[key]["wave_solves_f64"]
             cb[f"{key}_extrapolated_seconds"] = round(per * nws, 1)
         out["cpu_baseline"] = cb
