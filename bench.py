@@ -577,7 +577,7 @@ def run_cfg1(args, np, torch, wh, wl):
 
 
 def run_cfg3(args, np, torch, wh, wl):
-    """3D 256^3, seeded variable c, omega = 40: GMRES(40) (mixed, capped) and CG (FP64 and mixed) to
+    """3D 256^3, seeded variable c, omega = 40: GMRES(40) (mixed and FP64, capped) and CG (FP64 and mixed) to
     a true residual of 1e-8, with the Helmholtz residual as the accuracy check at this size."""
     p = wl.config3()
     f = torch.from_numpy(p.f).cuda()
