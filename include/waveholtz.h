@@ -116,8 +116,10 @@ typedef struct {
                                for DCG, 1e-4 for deflated batch problems)                   */
   int32_t max_outer;        /* WH_MIXED GMRES: FP64 refinement sweeps (default 30)           */
   int32_t k_fuse;           /* time steps per stencil launch; 0: library choice.  Blocked
-                               2D launches take 2, 3, 4, 6, 8 (FP32 also 9), 3D 2 or 3; any
-                               other value, fourth order, or too few steps: one per launch  */
+                               2D launches take 2, 3, 4, 6, 8 (FP32 also 9), 3D 2 or 3;
+                               fourth order in 2D 2 or 4 (0 and values above 4: 4, 3: 2);
+                               any other value, fourth order in 3D, or too few steps: one
+                               per launch                                                  */
   int32_t reproject;        /* DCG A-orthogonalisation against W each iteration (Algorithm 3,
                                optional for exact eigenvectors): -1 auto (= off, every
                                deflation kind here is exact), 0 off, 1 on                  */

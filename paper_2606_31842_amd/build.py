@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwaveholtz.so")
 OBJDIR = os.path.join(HERE, "_build")
 SOURCES = ["wh_stencil.hip", "wh_fused.hip", "wh_fused_first.hip", "wh_fused_last.hip", "wh_fused3d.hip",
-           "wh_blas.hip", "wh_batched.hip", "wh_adjoint.hip", "wh_api.hip"]
+           "wh_blas.hip", "wh_batched.hip", "wh_march4.hip", "wh_adjoint.hip", "wh_api.hip"]
 
 CFLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

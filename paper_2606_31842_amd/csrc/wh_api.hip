@@ -546,6 +546,31 @@ int wave_solve(const WaveOp& op, const double* vin, bool force, StepMode last, c
   void* oc = op.Wc;
   void* op_ = op.Wd;
   int nn = 1;  // cur holds W^nn
+  if (op.order == 4 && op.dim == 2 && op.k_fuse > 1) {
+    // fourth order: the steps between the first and the last by the row-marching launches
+    // (the largest supported K that still leaves the last step to the epilogue)
+    int Kc = op.k_fuse;
+    while (true) {
+      while (Kc > 1 && (nn + Kc > tp.nt - 1 || !march4_supported(Kc))) --Kc;
+      if (Kc <= 1) break;
+      March4Args m{};
+      m.cur = cur;
+      m.prev = prev;
+      m.cur_out = oc;
+      m.prev_out = op_;
+      m.V = op.V;
+      m.fs = force ? op.fs : nullptr;
+      m.a12 = op.a / 12.0;
+      for (int j = 1; j <= Kc; ++j) m.w[j] = tp.w[nn + j];
+      for (int j = 0; j < Kc; ++j) m.cs[j] = tp.cosv[nn + j];
+      m.n = op.n;
+      m.kp = Kc;
+      launch_march4(op.f32, Kc, m, s);
+      std::swap(cur, oc);
+      std::swap(prev, op_);
+      nn += Kc;
+    }
+  }
   const int K = op.order == 2 ? op.k_fuse : 1;
   if (K > 1 && fused_supported(op.dim, op.f32, K)) {
     FusedArgs fa{};
@@ -1339,6 +1364,14 @@ double now_ms() {
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
+// Steps per launch of a fourth-order solve: the row-marching launches take 2 or 4 (2D only);
+// 0 asks for 4, 1 keeps one step per launch, other values take the largest supported below.
+int order4_k(int dim, int k_fuse) {
+  if (dim != 2 || k_fuse == 1) return 1;
+  if (k_fuse == 0 || k_fuse >= 4) return 4;
+  return k_fuse >= 2 ? 2 : 1;
+}
+
 // Common setup for wh_apply_filter / wh_solve: c_max, time parameters, coefficient
 // arrays in the stepping precisions.
 wh_status setup_ops(wh_ctx* ctx, const wh_grid& g, const wh_params& P, const double* c2,
@@ -1420,7 +1453,8 @@ wh_status setup_ops(wh_ctx* ctx, const wh_grid& g, const wh_params& P, const dou
   // operator without forcing dominates every solve, so it sets K for both precisions.
   auto pick = [&](WaveOp& op) {
     int code = 1;
-    if (g.order == 4 || P.k_fuse == 1 || (P.k_fuse > 1 && !fused_supported(g.dim, op.f32, P.k_fuse))) code = 1;
+    if (g.order == 4) code = order4_k(g.dim, P.k_fuse);
+    else if (P.k_fuse == 1 || (P.k_fuse > 1 && !fused_supported(g.dim, op.f32, P.k_fuse))) code = 1;
     else if (P.k_fuse > 1 && P.k_shape >= 0) code = P.k_fuse | (P.k_shape << 8);
     else if (may_tune) code = autotune_k(ctx, op, false, P.k_fuse);
     else code = untuned_k(ctx, op, P.k_fuse);
@@ -1509,7 +1543,12 @@ void fill_info(wh_info* info, const TimeParams& tp, int k_fuse, const WaveOp* op
   info->c_max = tp.c_max;
   info->k_fuse = k_fuse;
   info->k_rows = info->k_waves = 0;
-  if (op && k_fuse > 1) fused_shape_dims(op->dim, op->f32, k_fuse, op->k_shape, &info->k_rows, &info->k_waves);
+  if (op && k_fuse > 1 && op->order == 4) {
+    info->k_rows = 32;
+    info->k_waves = 4;
+  } else if (op && k_fuse > 1) {
+    fused_shape_dims(op->dim, op->f32, k_fuse, op->k_shape, &info->k_rows, &info->k_waves);
+  }
 }
 
 }  // namespace
@@ -2232,7 +2271,21 @@ wh_status wh_time_step_kernel(wh_ctx* ctx, const wh_grid* grid, const double* c2
   const int K = op.k_fuse;
   if (K > 1 && K + 2 > tp.nt) WH_FAIL(ctx, WH_EINVAL, "K larger than the wave solve");
   auto run = [&](int r) {
-    if (K <= 1) {
+    if (K > 1 && op.order == 4) {
+      March4Args m{};
+      m.cur = (r & 1) ? op.Wc : op.Wb;
+      m.prev = (r & 1) ? op.Wd : op.Wa;
+      m.cur_out = (r & 1) ? op.Wb : op.Wc;
+      m.prev_out = (r & 1) ? op.Wa : op.Wd;
+      m.V = op.V;
+      m.fs = nullptr;
+      m.a12 = op.a / 12.0;
+      for (int j = 1; j <= K; ++j) m.w[j] = tp.w[j + 1];
+      for (int j = 0; j < K; ++j) m.cs[j] = tp.cosv[j + 1];
+      m.n = op.n;
+      m.kp = K;
+      launch_march4(op.f32, K, m, s);
+    } else if (K <= 1) {
       StepArgs a{};
       a.n = op.n;
       a.kap = op.kap;
@@ -2277,7 +2330,12 @@ wh_status wh_time_step_kernel(wh_ctx* ctx, const wh_grid* grid, const double* c2
   *us_per_launch = 1e3 * (double)ms / reps;
   if (k_used) *k_used = K;
   int rr = 0, wv = 0;
-  if (K > 1) fused_shape_dims(op.dim, op.f32, K, op.k_shape, &rr, &wv);
+  if (K > 1 && op.order == 4) {
+    rr = 32;   // rows per tile of the row-marching launch
+    wv = 4;    // strips (wavefronts) per block
+  } else if (K > 1) {
+    fused_shape_dims(op.dim, op.f32, K, op.k_shape, &rr, &wv);
+  }
   if (rows) *rows = rr;
   if (waves) *waves = wv;
   return WH_OK;

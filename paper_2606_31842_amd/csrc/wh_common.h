@@ -175,6 +175,28 @@ int fused2d_default_shape(bool f32, int n);
 // Register rows per thread and wavefronts per block of a block shape.
 void fused2d_shape_dims(bool f32, int k, int shape, int* rows, int* waves);
 void launch_fused2d(bool f32, bool varc, bool force, const FusedArgs& a, hipStream_t s);
+
+// K (2 or 4) fourth-order steps of a 2D single solve (c == 1) by the row-marching pipeline
+// (wh_march4.hip).  The state pair is read from (cur, prev) and written to (cur_out, prev_out)
+// with the conventions of the other stepping kernels (FP32: W, D; FP64: W^n, W^{n-1}).
+struct March4Args {
+  const void* cur;
+  const void* prev;
+  void* cur_out;
+  void* prev_out;
+  double* V;
+  const void* fs;     // dt^2 f in the state type, or NULL (no forcing)
+  double a12;         // dt^2 / (12 h^2)
+  double w[5];        // w[s] = filter weight of W^{n+s}, s = 1..K
+  double cs[4];       // cs[s] = cos(omega t^{n+s}), s = 0..K-1
+  int n;
+  int kp;             // steps of this launch (<= K)
+};
+bool march4_supported(int K);
+int march4_strip(int K);
+int march4_tiles_x(int n, int K);
+int march4_tiles_y(int n);
+void launch_march4(bool f32, int K, const March4Args& a, hipStream_t s);
 // Blocks (= partial sums) of a 2D blocked launch with this K and shape.
 int fused2d_blocks(bool f32, int k, int shape, int n);
 // 3D: K in {2, 3}; shapes give rows per thread, waves per block and output planes per block.

@@ -83,35 +83,48 @@ __device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, in
 // Node arrays must hold (n+1)^2 elements of at most 2^31 bytes.
 // FULL: the launch advances K steps (Kp == K), so the output is fixed at level K and the
 // body stays free of branches; otherwise the store of level Kp is a uniform branch.
-template <typename T, int K, int C, bool VARC, bool FORCE, bool FULL, bool UP>
+// RAD: stencil radius, 1 (second-order differences, variable c allowed) or 2 (fourth-order
+// differences for c == 1, closed at the Dirichlet boundary by odd reflection: the neighbour
+// two points beyond the last interior point is minus that point).  Level s+1 is formed on
+// the row RAD rows behind level s, and the halo is RAD * K points on each side.
+template <typename T, int K, int C, int RAD, bool VARC, bool FORCE, bool FULL, bool UP>
 __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int ys, int ye) {
   constexpr bool INC = sizeof(T) == 4;
-  constexpr int U = K < 4 ? 4 : K;
-  static_assert(U % 4 == 0 && U % K == 0, "unroll must be a multiple of the ring sizes");
+  constexpr int H = RAD * K;                 // halo points per side, rows before and after
+  constexpr int WR = RAD == 1 ? 4 : 8;       // rows kept per level (>= 2 RAD + 1)
+  constexpr int RK = RAD * K;                // rows in flight for D, the forcing and V
+  constexpr int U = RK > WR ? RK : WR;
+  static_assert(U % WR == 0 && U % RK == 0, "unroll must be a multiple of the ring sizes");
+  static_assert(RAD == 1 || (C == 1 && !VARC), "fourth order: one column per lane, c == 1");
   constexpr int PF = 2;
-  constexpr int DK = INC ? K : 1;
-  constexpr int PK = INC ? 1 : 2;
+  constexpr int DK = INC ? RK : 1;
+  constexpr int PK = INC ? 1 : (RAD == 1 ? 2 : 4);
   constexpr int TS = (int)sizeof(T);
   const int n = io.n;
   const int P = n + 1;
   const int64_t NN = (int64_t)P * P;
   const int Kp = io.Kp;
   const int lane = threadIdx.x;
-  const int xb = xs - K + C * lane;
+  const int xb = xs - H + C * lane;
   const __amdgpu_buffer_rsrc_t rc = buf_rsrc(io.cin, NN * TS), rp = buf_rsrc(io.pin, NN * TS);
   const __amdgpu_buffer_rsrc_t rco = buf_rsrc(io.cout, NN * TS), rpo = buf_rsrc(io.pout, NN * TS);
   const __amdgpu_buffer_rsrc_t rv = buf_rsrc(io.V, NN * 8);
   const __amdgpu_buffer_rsrc_t rk = buf_rsrc(VARC ? (const void*)io.kap : (const void*)io.cin, NN * TS);
   const __amdgpu_buffer_rsrc_t rf = buf_rsrc(FORCE ? (const void*)io.fs : (const void*)io.cin, NN * TS);
 
-  bool colin[C], colout[C];
+  constexpr int CR = RAD == 2 ? C : 1;
+  bool colin[C], colout[C], refl_w[CR], refl_e[CR];
   int colm[C];   // all ones inside the open domain, else 0
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const int col = xb + c;
     colin[c] = col >= 1 && col <= n - 1;
     const int lc = C * lane + c;
-    colout[c] = colin[c] && lc >= K && lc < 64 * C - K;
+    colout[c] = colin[c] && lc >= H && lc < 64 * C - H;
+    if constexpr (RAD == 2) {
+      refl_w[c] = col == 1;       // its west neighbour at distance 2 is the reflection
+      refl_e[c] = col == n - 1;
+    }
     colm[c] = colin[c] ? -1 : 0;
     // opaque to the optimiser, which would otherwise turn the masking below back into a
     // select and then into a branch around the stencil
@@ -125,18 +138,20 @@ __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int y
     cn[s] = (FORCE && s < Kp) ? (T)io.cs[s] : T(0);
   }
 
-  constexpr int FK = FORCE ? K : 1;
-  T Wr[K][4][C];
+  constexpr int FK = FORCE ? RK : 1;
+  T Wr[K][WR][C];
   T Dr[DK][C];
   T Pr[PK][C];
   T Fr[FK][C];   // forcing of the rows in flight (same slots as D)
-  double acc[K][C];
+  double acc[RK][C];
 #pragma unroll
-  for (int s = 0; s < K; ++s)
+  for (int s = 0; s < RK; ++s)
 #pragma unroll
     for (int c = 0; c < C; ++c) {
+      if (s < K) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) Wr[s][q][c] = T(0);
+        for (int q = 0; q < WR; ++q) Wr[s < K ? s : 0][q][c] = T(0);
+      }
       acc[s][c] = 0.0;
     }
 #pragma unroll
@@ -149,13 +164,13 @@ __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int y
     for (int q = 0; q < FK; ++q) Fr[q][c] = T(0);
   }
 
-  const int tstart = ys - K;
-  const int tlast = ye + K - 1;   // last input row the pipeline needs
-  // pipeline row t is grid row rb + sg * t: downwards from row ys - K, or upwards from row
-  // ye + K - 1 (the stencil is symmetric in y, so only the addresses change)
+  const int tstart = ys - H;
+  const int tlast = ye + H - 1;   // last input row the pipeline needs
+  // pipeline row t is grid row rb + sg * t: downwards from row ys - H, or upwards from row
+  // ye + H - 1 (the stencil is symmetric in y, so only the addresses change)
   const int rb = UP ? ys + ye - 1 : 0;
   constexpr int sg = UP ? -1 : 1;
-  const int nit = ((ye - ys + 2 * K) + U - 1) / U * U;
+  const int nit = ((ye - ys + 2 * H) + U - 1) / U * U;
 
   T sW[PF][C], sP[PF][C], sF[PF][C];
   double sV[PF][C];
@@ -186,22 +201,23 @@ __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int y
       double newV[C];
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        Wr[0][u & 3][c] = sW[u % PF][c];
+        Wr[0][u & (WR - 1)][c] = sW[u % PF][c];
         if constexpr (INC) newD[c] = sP[u % PF][c];
-        else Pr[u & 1][c] = sP[u % PF][c];
+        else Pr[u & (PK - 1)][c] = sP[u % PF][c];
         if constexpr (FORCE) newF[c] = sF[u % PF][c];
         newV[c] = sV[u % PF][c];
       }
       WH_MARCH_LOAD(t + PF, u % PF)
 #pragma unroll
       for (int s = 0; s < K; ++s) {
-        // level s+1 on row r from level s on rows r-1, r, r+1
-        const int r = rb + sg * (t - s - 1);   // its grid row
+        // level s+1 on row r from level s on rows r-RAD .. r+RAD
+        const int o = u - RAD * (s + 1);   // slot offset of row r
+        const int r = rb + sg * (t - RAD * (s + 1));   // its grid row
         const bool rowok = r >= 1 && r <= n - 1;
         const int rowm = ~(((r - 1) | (n - 1 - r)) >> 31);   // all ones for 1 <= r <= n-1
         const bool rowout = r >= ys && r < ye;
-        const int qc = (u - s - 1) & 3, qu = (u - s - 2) & 3, qd = (u - s) & 3;
-        const int qk = ((u - s - 1) % K + K) % K;
+        const int qc = o & (WR - 1), qu = (o - 1) & (WR - 1), qd = (o + 1) & (WR - 1);
+        const int qk = (o % RK + RK) % RK;
         T wv[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) wv[c] = Wr[s][qc][c];
@@ -217,7 +233,18 @@ __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int y
           const bool ok = rowok && colin[c];
           const int p = r * P + xb + c;
           T lap;
-          if constexpr (VARC) {
+          if constexpr (RAD == 2) {
+            // the rows two away in the pipeline are grid rows r -/+ 2 sg; a grid row -1 or
+            // n+1 (beyond the boundary) is the odd reflection -W(r)
+            const int ru2 = r - 2 * sg, rd2 = r + 2 * sg;
+            const T up2 = (ru2 == -1 || ru2 == n + 1) ? -cc : Wr[s][(o - 2) & (WR - 1)][c];
+            const T dn2 = (rd2 == -1 || rd2 == n + 1) ? -cc : Wr[s][(o + 2) & (WR - 1)][c];
+            const T we2 = refl_w[c] ? -cc : from_prev_lane(wl);
+            const T ea2 = refl_e[c] ? -cc : from_next_lane(er);
+            const T sx = T(16) * ((we - cc) + (ea - cc)) - ((we2 - cc) + (ea2 - cc));
+            const T sy = T(16) * ((up - cc) + (dn - cc)) - ((up2 - cc) + (dn2 - cc));
+            lap = io.A * (sx + sy);
+          } else if constexpr (VARC) {
             const T kc = buf_load<T>(rk, ok ? p * TS : kBufOff);
             const T kw = buf_load<T>(rk, ok ? (p - 1) * TS : kBufOff);
             const T ke = buf_load<T>(rk, ok ? (p + 1) * TS : kBufOff);
@@ -239,7 +266,7 @@ __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int y
             nw = cc + d;
             pn = d;
           } else {
-            const T pv = s == 0 ? Pr[(u - 1) & 1][c] : Wr[s - 1][qc][c];
+            const T pv = s == 0 ? Pr[(u - RAD) & (PK - 1)][c] : Wr[s - 1][qc][c];
             nw = __longlong_as_double(__double_as_longlong((cc + cc) - pv + lap) & (long long)m);
             pn = cc;
           }
@@ -248,19 +275,19 @@ __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int y
           acc[qk][c] = a;
           if (FULL ? s == K - 1 : s + 1 == Kp) {
             // level Kp on an output row and column is written (a masked store is dropped)
-            const bool o = rowout && colout[c];
-            buf_store(nw, rco, o ? p * TS : kBufOff);
-            buf_store(pn, rpo, o ? p * TS : kBufOff);
-            buf_store(a, rv, o ? p * 8 : kBufOff);
+            const bool ob = rowout && colout[c];
+            buf_store(nw, rco, ob ? p * TS : kBufOff);
+            buf_store(pn, rpo, ob ? p * TS : kBufOff);
+            buf_store(a, rv, ob ? p * 8 : kBufOff);
           }
         }
       }
-      // row t starts its D and its filter sum (the slots of row t-K, finished above)
+      // row t starts its D and its filter sum (the slots of row t - RK, finished above)
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        if constexpr (INC) Dr[u % K][c] = newD[c];
-        if constexpr (FORCE) Fr[u % K][c] = newF[c];
-        acc[u % K][c] = newV[c];
+        if constexpr (INC) Dr[u % RK][c] = newD[c];
+        if constexpr (FORCE) Fr[u % RK][c] = newF[c];
+        acc[u % RK][c] = newV[c];
       }
       // FP64: keep the scheduler from overlapping consecutive rows, whose live rings would
       // otherwise cost more registers than the overlap gains
@@ -274,21 +301,21 @@ __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int y
 // opposite directions, so the halo rows two tiles share are read by both at about the same
 // time (both at the start or both at the end of their marches) and the second read finds them
 // in L2.
-template <typename T, int K, int C, bool VARC, bool UP>
+template <typename T, int K, int C, int RAD, bool VARC, bool UP>
 __device__ __forceinline__ void march2d_dir(const MarchIO<T>& io, int xs, int ys, int ye) {
   if (io.force) {
-    if (io.Kp == K) march2d_body<T, K, C, VARC, true, true, UP>(io, xs, ys, ye);
-    else march2d_body<T, K, C, VARC, true, false, UP>(io, xs, ys, ye);
+    if (io.Kp == K) march2d_body<T, K, C, RAD, VARC, true, true, UP>(io, xs, ys, ye);
+    else march2d_body<T, K, C, RAD, VARC, true, false, UP>(io, xs, ys, ye);
   } else {
-    if (io.Kp == K) march2d_body<T, K, C, VARC, false, true, UP>(io, xs, ys, ye);
-    else march2d_body<T, K, C, VARC, false, false, UP>(io, xs, ys, ye);
+    if (io.Kp == K) march2d_body<T, K, C, RAD, VARC, false, true, UP>(io, xs, ys, ye);
+    else march2d_body<T, K, C, RAD, VARC, false, false, UP>(io, xs, ys, ye);
   }
 }
 
-template <typename T, int K, int C, bool VARC>
+template <typename T, int K, int C, bool VARC, int RAD = 1>
 __device__ __forceinline__ void march2d(const MarchIO<T>& io, int xs, int ys, int ye, bool up) {
-  if (up) march2d_dir<T, K, C, VARC, true>(io, xs, ys, ye);
-  else march2d_dir<T, K, C, VARC, false>(io, xs, ys, ye);
+  if (up) march2d_dir<T, K, C, RAD, VARC, true>(io, xs, ys, ye);
+  else march2d_dir<T, K, C, RAD, VARC, false>(io, xs, ys, ye);
 }
 
 }  // namespace wh

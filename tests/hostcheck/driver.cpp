@@ -237,7 +237,7 @@ void filter_case(int dim, int n, int order, bool varc, bool force, int precision
                            need, &info);
   // a device-computed c_max reads a synthetic maximum; only argument errors are unexpected
   expect(st >= 0 || (varc && st == WH_EINVAL), "wh_apply_filter", st);
-  if (dim == 2 && order == 2 && !varc) {
+  if (dim == 2 && !varc) {
     double us = 0;
     int32_t k = 0, rows = 0, waves = 0;
     st = wh_time_step_kernel(g_ctx, &g, nullptr, &p, 3, ws.p, need, &us, &k, &rows, &waves);
@@ -377,9 +377,14 @@ int main(int argc, char** argv) {
           }
     for (int n : {6, 10}) {
       filter_case(3, n, 2, false, true, 0, 0, seed);
-      filter_case(2, n, 4, false, true, 0, 0, seed);
       filter_case(3, n, 4, false, true, 1, 0, seed);
     }
+    // fourth order in 2D: the blocked launches (K = 4 by default, 2 on request) and one step
+    // per launch
+    for (int n : {6, 10, 40, 129})
+      for (int prec : {0, 1})
+        for (int k : {0, 2, 3, 1})
+          filter_case(2, n, 4, false, n != 40, prec, k, seed);
   }
   if (all || group == "filter") {
     for (int prec : {0, 1})

@@ -593,6 +593,33 @@ bool model_generic(const std::string& base, const std::vector<std::string>& t, d
   return true;
 }
 
+// Blocked fourth-order launch: K steps of a 2D single solve by the row-marching pipeline.
+// Every access goes through a buffer resource sized to the (n+1)^2 grid, so the model checks
+// that each pointer holds the whole grid, and that the grid and block match the tiling.
+void model_march4(const std::vector<std::string>& t, dim3 g, dim3 b, void** args) {
+  const size_t TS = t.at(0) == "float" ? 4 : 8;
+  const int K = ti(t, 1);
+  const March4Args a = arg<March4Args>(args, 0);
+  if (!march4_supported(K)) fail("K = %d has no blocked fourth-order kernel", K);
+  if (a.kp < 1 || a.kp > K) fail("steps per launch %d outside 1..%d", a.kp, K);
+  if (a.n < 2) fail("n = %d", a.n);
+  const int nt = march4_tiles_x(a.n, K) * march4_tiles_y(a.n);
+  if ((int)g.x != nt || g.y != 1) fail("grid %u != %d tiles", g.x, nt);
+  if ((int)b.x != 64 || (int)b.y != 4) fail("block shape (%u,%u)", b.x, b.y);
+  // the strips of the last tile column start inside the grid or return at once; every
+  // interior column is covered by exactly one strip
+  const int strip = march4_strip(K);
+  if ((int64_t)march4_tiles_x(a.n, K) * 4 * strip < a.n - 1) fail("strips do not cover the columns");
+  if ((int64_t)march4_tiles_y(a.n) * 32 < a.n - 1) fail("tiles do not cover the rows");
+  const int64_t N = (int64_t)(a.n + 1) * (a.n + 1);
+  vec(a.cur, N, TS, "cur"); vec(a.prev, N, TS, "prev");
+  vec(a.cur_out, N, TS, "cur_out"); vec(a.prev_out, N, TS, "prev_out");
+  vec(a.V, N, 8, "V");
+  if (a.fs) vec(a.fs, N, TS, "fs");
+  if (a.cur_out == a.cur || a.prev_out == a.prev || a.cur_out == a.prev || a.prev_out == a.cur)
+    fail("the launch writes a state array that it reads");
+}
+
 void check_launch(const void* fn, dim3 g, dim3 b, void** args) {
   ++g_launches;
   auto it = kernels().find(fn);
@@ -612,6 +639,7 @@ void check_launch(const void* fn, dim3 g, dim3 b, void** args) {
   else if (base == "k_batch_plan") model_batch_plan(g, b, args);
   else if (base == "k_batch_work") model_batch_work(t, g, b, args);
   else if (base == "k_batch_tile") model_batch_tile(t, g, b, args);
+  else if (base == "k_march4") model_march4(t, g, b, args);
   else done = model_generic(base, t, g, b, args);
   if (done) ++g_modelled;
   else ++g_unmodelled[base];

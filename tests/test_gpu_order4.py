@@ -21,14 +21,19 @@ def test_filter_order4_matches_oracle(dim, n, omega, force):
     tp = oracle_tp(dim, n, omega)
     ref = disc.to_nodal(ws.wave_filter(L, disc.to_interior(v), None if f is None else disc.to_interior(f), tp),
                         dim, n)
-    out, info = wh.apply_filter(cuda(v), omega, f=None if f is None else cuda(f), order=4)
-    assert info["nt"] == tp.nt and info["k_fuse"] == 1
-    e = rel(host(out), ref)
-    out32, _ = wh.apply_filter(cuda(v), omega, f=None if f is None else cuda(f), order=4, precision="mixed")
-    e32 = rel(host(out32), ref)
-    print(f"f64 err {e:.2e} mixed err {e32:.2e}", flush=True)
-    assert e < 1e-12 and e32 < 2e-5
-    assert np.all(host(out)[0] == 0)
+    # 2D: blocked launches of 4 steps by default, 2 and one step per launch on request; 3D:
+    # one step per launch
+    for k in ((0, 4, 2, 1) if dim == 2 else (0,)):
+        out, info = wh.apply_filter(cuda(v), omega, f=None if f is None else cuda(f), order=4, k_fuse=k)
+        assert info["nt"] == tp.nt and info["k_fuse"] == ((k or 4) if dim == 2 else 1)
+        e = rel(host(out), ref)
+        out32, i32 = wh.apply_filter(cuda(v), omega, f=None if f is None else cuda(f), order=4,
+                                     precision="mixed", k_fuse=k)
+        assert i32["k_fuse"] == info["k_fuse"]
+        e32 = rel(host(out32), ref)
+        print(f"k_fuse {info['k_fuse']}: f64 err {e:.2e} mixed err {e32:.2e}", flush=True)
+        assert e < 1e-12 and e32 < 2e-5
+        assert np.all(host(out)[0] == 0) and np.all(host(out32)[0] == 0)
 
 
 @pytest.mark.parametrize("dim,n,omega", [(2, 96, 23.4), (3, 20, 11.1)])
