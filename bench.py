@@ -41,8 +41,8 @@ B_FUSED_F32 = 32.0
 # HBM KiB per dispatch (FETCH_SIZE, WRITE_SIZE) of the tagged batch work kernel on the config-4
 # batch, from the two counter passes in profiles/hbm_traffic_batch_tile_cfg4.md, with the copy-kernel
 # scale factors; valid only for the kernel sources it was taken on (sha1 over the three files)
-BATCH_TRAFFIC = {"src_sha1": "a096de64e9a3c7d1310b873061b56b90dc89518e", "fetch_scale": 2.0, "write_scale": 1.0,
-                 "kib": [733799.6, 1444656.9]}
+BATCH_TRAFFIC = {"src_sha1": "43cbc99d570aea9b5bc09b38b13f9db28ea758c4", "fetch_scale": 2.0, "write_scale": 1.0,
+                 "kib": [734884.6, 1447137.5]}
 # HBM KiB per dispatch (FETCH_SIZE, WRITE_SIZE) of every FP32 temporally blocked kernel
 # variant "K,R,NW" on this grid, from the two rocprofv3 counter passes summarised in
 # profiles/hbm_traffic_fused2d_f32_2d1024.md (scaled by FETCH x 2.000, WRITE x 1.000 from a
@@ -307,11 +307,11 @@ def main():
     ap.add_argument("--no-direct", action="store_true",
                     help="cfg2: skip the CPU direct solves (scipy sparse LU, about 25 s)")
     ap.add_argument("--workload", default="cfg4",
-                    choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5", "solvers", "ndsweep"],
+                    choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5", "solvers", "ndsweep", "order4"],
                     help="cfg4 (default) is the benchmark line: 256 batched 2D solves; the others report "
                          "the remaining workloads (2D 64^2 FP64 CG; 2D 1024^2 single mixed DCG solve; 3D 256^3 "
                          "variable c; 513^2 adjoint gradient; the config-2 problem by every solver; "
-                         "iterations against omega for two deflation-size rules)")
+                         "iterations against omega for two deflation-size rules; fourth-order stepping rates)")
     ap.add_argument("--max-iters", type=int, default=0, help="iteration cap (cfg3, solvers)")
     ap.add_argument("--omegas", default="5:30", help="ndsweep: first:last (step 1) or a comma list")
     ap.add_argument("--runs", default="", help="solvers: comma-separated subset of the run names "
@@ -767,7 +767,50 @@ def run_ndsweep(args, np, torch, wh, wl):
             "rows": rows}
 
 
-EXTRA = {"cfg1": run_cfg1, "cfg2": run_cfg2, "solvers": run_solvers, "ndsweep": run_ndsweep, "cfg3": run_cfg3, "cfg5": run_cfg5}
+def run_order4(args, np, torch, wh, wl):
+    """Fourth-order differences (c = 1), 2D: the stepping rate of the blocked launches (K = 4,
+    the row-marching pipeline with the radius-2 stencil) against one step per launch, FP64 and
+    FP32, on 2048^2 and 4096^2 grids; and a 1024^2 DCG solve (16 sine modes, tol 1e-8) timed
+    both ways.  Fused-form bytes of a K-step launch per interior point: FP64 48 (state pair in
+    and out, V read and written), FP32 32."""
+    rows = []
+    for n in (2048, 4096):
+        v = torch.zeros((n + 1, n + 1), dtype=torch.float64, device="cuda")
+        for prec in ("f64", "mixed"):
+            for k in (1, 4):
+                ms, sh = wh.time_step_kernel(v, 0.3 * n, precision=prec, reps=30, shape=True, order=4, k_fuse=k)
+                K = max(sh["k"], 1)
+                pts = (n - 1) ** 2
+                row = {"n": n, "precision": prec, "k": sh["k"], "us_per_launch": round(1e3 * ms, 2),
+                       "gpts_steps_per_s": round(pts * K / ms / 1e6, 1)}
+                if K > 1:
+                    bpp = 48 if prec == "f64" else 32
+                    gbs = bpp * pts / (ms * 1e-3) / 1e9
+                    row["roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
+                                       "frac": round(gbs / 8000.0, 3)}
+                log(f"order 4 stepping n={n} {prec} K={sh['k']}: {row['us_per_launch']} us per launch, "
+                    f"{row['gpts_steps_per_s']} G point-steps/s")
+                rows.append(row)
+        del v
+    n = 1024
+    f = torch.from_numpy(wl.gaussian(2, n, (0.41, 0.57), 0.02)).cuda()
+    om = 0.25 * n
+    d = wh.sine_deflation(2, n, om, 16, order=4)
+    solves = []
+    for prec in ("f64", "mixed"):
+        for k in (1, 4):
+            kw = dict(solver="dcg", defl=d, tol=1e-8, max_iters=5000, order=4, precision=prec, k_fuse=k)
+            wh.solve(f, om, **{**kw, "max_iters": 2})
+            (u, i), dt = _timed(torch, lambda: wh.solve(f, om, **kw))
+            solves.append({"precision": prec, "k": i["k_fuse"], "status": i["status"], "iters": i["iters"],
+                           "seconds": round(dt, 3), "true_rel_res": i["true_rel_res"]})
+            log(f"order 4 DCG n={n} {prec} K={i['k_fuse']}: {i['iters']} iterations, {dt:.3f} s")
+    return {"workload": "fourth-order 2D stepping (c = 1) and a 1024^2 DCG solve (omega = 256, 16 sine modes)",
+            "stepping": rows, "solves": solves}
+
+
+EXTRA = {"cfg1": run_cfg1, "cfg2": run_cfg2, "solvers": run_solvers, "ndsweep": run_ndsweep, "cfg3": run_cfg3, "cfg5": run_cfg5,
+         "order4": run_order4}
 
 
 if __name__ == "__main__":
