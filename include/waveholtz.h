@@ -291,8 +291,11 @@ size_t wh_workspace_bytes_batched(int32_t nb, const wh_problem* probs, const wh_
  * problem's omega overrides params->omega; u is output only (batched solves start
  * from zero, or from x_0).  All problems must have c2 or none; with c2,
  * params->c_max must bound c and n_defl must be 0.  params->k_fuse in {2, 4, 8}
- * sets the time steps per launch (0: 4).  infos: host array of nb (may be NULL).
- * Returns the worst status over problems. */
+ * sets the time steps per launch (0: 4).  Every problem's grid must have the same order: 2,
+ * or 4 (fourth-order differences, c == 1 only; a launch then advances k_fuse / 2 steps, whose
+ * halo of 2 points per step keeps the tiles of k_fuse second-order steps; the sine modes and
+ * their eigenvalues are those of the fourth-order operator).  infos: host array of nb (may be
+ * NULL).  Returns the worst status over problems. */
 wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
                            const wh_params* params, void* ws, size_t ws_bytes, wh_info* infos);
 
@@ -302,7 +305,8 @@ wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
  * over `reps` back-to-back launches on the context stream between two HIP events.  *points
  * (may be NULL) receives the interior points one launch advances by K steps, sum (n-1)^2.
  * Arguments and workspace as for wh_solve_batched with params->precision = WH_MIXED (the
- * workspace contents are overwritten; every problem needs N_t >= K + 2).  The launches carry a
+ * workspace contents are overwritten; every problem needs N_t >= K + 2; second-order grids
+ * only, else WH_EUNSUPPORTED).  The launches carry a
  * kernel tag of their own, so that profiles list them apart from the solver's launches. */
 wh_status wh_time_batch_kernel(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const wh_params* params,
                                int32_t reps, void* ws, size_t ws_bytes, double* us_per_launch, int64_t* points);

@@ -317,7 +317,7 @@ def time_step_kernel(v, omega, c2=None, reps=50, shape=False, **kw):
     return us.value / 1e3
 
 
-def _batch(problems, n_defl):
+def _batch(problems, n_defl, order=2):
     """ctypes problem array (and the output tensors) for wh_solve_batched / wh_time_batch_kernel."""
     torch = _torch()
     nb = len(problems)
@@ -334,7 +334,7 @@ def _batch(problems, n_defl):
         _nodal(f, 2, n, "f"); _nodal(c2, 2, n, "c2")
         u = torch.empty_like(f)
         outs.append(u)
-        arr[i].grid = _grid(2, n)
+        arr[i].grid = _grid(2, n, order)
         arr[i].c2 = None if c2 is None else c2.data_ptr()
         arr[i].f = f.data_ptr()
         arr[i].omega = float(om)
@@ -348,7 +348,7 @@ def _batch(problems, n_defl):
 def batch_workspace_bytes(problems, n_defl=0, **kw) -> int:
     """Workspace bytes wh_solve_batched needs for these problems and parameters."""
     lib = nat.load()
-    arr, _, _ = _batch(problems, n_defl)
+    arr, _, _ = _batch(problems, n_defl, kw.pop("order", 2))
     p = params(float(problems[0][1]), **kw)
     return int(lib.wh_workspace_bytes_batched(len(problems), arr, C.byref(p)))
 
@@ -358,10 +358,11 @@ def solve_batched(problems, workspace=None, n_defl=0, **kw):
 
     problems: sequence of (f, omega) or (f, omega, c2) with nodal float64 CUDA tensors.
     n_defl: sine modes deflated per problem (an int for all, or one per problem; needs
-    solver="dcg" and c == 1).  Returns (list of solutions, list of info dicts)."""
+    solver="dcg" and c == 1).  order=4: fourth-order differences (c == 1) for every problem.
+    Returns (list of solutions, list of info dicts)."""
     lib = nat.load()
     nb = len(problems)
-    arr, outs, ctx = _batch(problems, n_defl)
+    arr, outs, ctx = _batch(problems, n_defl, kw.pop("order", 2))
     p = params(float(problems[0][1]), **kw)
     need = lib.wh_workspace_bytes_batched(nb, arr, C.byref(p))
     if need == 0:
@@ -378,7 +379,7 @@ def time_batch_kernel(problems, reps=20, workspace=None, n_defl=0, **kw):
     kernel with every problem in its time-stepping phase (wh_time_batch_kernel)."""
     lib = nat.load()
     nb = len(problems)
-    arr, _, ctx = _batch(problems, n_defl)
+    arr, _, ctx = _batch(problems, n_defl, kw.pop("order", 2))
     kw = dict(kw, precision="mixed")
     p = params(float(problems[0][1]), **kw)
     need = lib.wh_workspace_bytes_batched(nb, arr, C.byref(p))

@@ -80,8 +80,30 @@ __device__ __forceinline__ T lap_term(const T* c, const T* kap, int64_t p, int64
   return A * (((c[p - 1] + c[p + 1]) + (c[p - P] + c[p + P])) - T(4) * cc);
 }
 
+// Fourth-order differences (c = 1), dt^2 L_h W at interior node (i, j) as A12 (sx + sy) with
+// A12 = dt^2 / (12 h^2) and, per axis, 16 ((W_-1 - W) + (W_+1 - W)) - ((W_-2 - W) + (W_+2 - W)).
+// The neighbour two points beyond the last interior point is the odd reflection -W (row or
+// column -1 and n+1); the boundary rows and columns are zero (not read).  get(q) reads the
+// interior node of flat index q.
+template <typename T, typename Get>
+__device__ __forceinline__ T lap4_at(Get get, int64_t p, int i, int j, int n, int64_t P, T A12) {
+  const T cc = get(p);
+  const T w1 = i > 1 ? get(p - 1) : T(0), e1 = i < n - 1 ? get(p + 1) : T(0);
+  const T s1 = j > 1 ? get(p - P) : T(0), n1 = j < n - 1 ? get(p + P) : T(0);
+  const T w2 = i == 1 ? -cc : (i == 2 ? T(0) : get(p - 2));
+  const T e2 = i == n - 1 ? -cc : (i == n - 2 ? T(0) : get(p + 2));
+  const T s2 = j == 1 ? -cc : (j == 2 ? T(0) : get(p - 2 * P));
+  const T n2 = j == n - 1 ? -cc : (j == n - 2 ? T(0) : get(p + 2 * P));
+  const T sx = T(16) * ((w1 - cc) + (e1 - cc)) - ((w2 - cc) + (e2 - cc));
+  const T sy = T(16) * ((s1 - cc) + (n1 - cc)) - ((s2 - cc) + (n2 - cc));
+  return A12 * (sx + sy);
+}
+
 // The work of one tile of problem sid in its current phase (lt: the tile within the problem).
-template <typename T, int K, bool VARC>
+// ORD: 2 (the five-point Laplacian, variable c allowed) or 4 (fourth-order differences for
+// c == 1; the stepping launches advance K/2 steps, so that the halo, 2 points per step, and with
+// it the tile geometry stay those of K second-order steps).
+template <typename T, int K, bool VARC, int ORD = 2>
 __device__ __forceinline__ void batch_tile(const BDesc* __restrict__ descs, const BState* __restrict__ states,
                                            int sid, int lt) {
   constexpr int TXO = batch_txo(K);
@@ -90,6 +112,8 @@ __device__ __forceinline__ void batch_tile(const BDesc* __restrict__ descs, cons
   // FP32 state pairs are (W^n, D^{n-1/2} = W^n - W^{n-1}), stepped in the increment form
   // D += dt^2 (L_h W - f cos), W += D; FP64 pairs are (W^n, W^{n-1}).
   constexpr bool INC = sizeof(T) == 4;
+  static_assert(ORD == 2 || (ORD == 4 && !VARC && K % 2 == 0), "fourth order: c == 1, even K");
+  constexpr int KS = ORD == 4 ? K / 2 : K;   // steps per stepping launch
   const BDesc& D = descs[sid];
   const int ph = states[sid].phase;
   const int n = D.n;
@@ -140,7 +164,7 @@ __device__ __forceinline__ void batch_tile(const BDesc* __restrict__ descs, cons
       break;
     }
     case BP_A_FIRST:
-      if (sizeof(T) == 4 && D.defect) {
+      if (ORD == 2 && sizeof(T) == 4 && D.defect) {
         // FP32 inner operator in the defect form A p = Pi_h(0; H p): forcing
         // fs = -dt^2 H p, W^0 = 0, W^1 = -fs/2, V = w1 W^1
         T* w0o = state_of<T>(D, 0);
@@ -176,7 +200,11 @@ __device__ __forceinline__ void batch_tile(const BDesc* __restrict__ descs, cons
       const T* fs = fs_of<T>(D);
       TILE_FOR(p) {
         T c = T(0), lap = T(0);
-        if (src) {
+        if (src && ORD == 4) {
+          const int i = (int)(p % P), j = (int)(p / P);
+          c = (T)src[p];
+          lap = lap4_at<T>([&](int64_t q) { return (T)src[q]; }, p, i, j, n, P, (T)(D.a / 12.0));
+        } else if (src) {
           const int i = (int)(p % P), j = (int)(p / P);
           c = (T)src[p];
           const T wv = i > 1 ? (T)src[p - 1] : T(0);
@@ -224,7 +252,16 @@ __device__ __forceinline__ void batch_tile(const BDesc* __restrict__ descs, cons
       reduce = true;
       TILE_FOR(p) {
         T nw;
-        if (INC) {
+        if (ORD == 4) {
+          const T lap = lap4_at<T>([&](int64_t q) { return cur[q]; }, p, (int)(p % P), (int)(p / P), n, P,
+                                   (T)(D.a / 12.0));
+          if (INC) {
+            nw = cur[p] + (prv[p] + (ph == BP_B_LAST ? lap - cn * fs[p] : lap));
+          } else {
+            nw = (cur[p] + cur[p]) - prv[p] + lap;
+            if (ph == BP_B_LAST) nw -= cn * fs[p];
+          }
+        } else if (INC) {
           T lap = lap_term<T, VARC, true>(cur, kap, p, P, A);
           if (ph == BP_B_LAST || defect) lap -= cn * fs[p];
           nw = cur[p] + (prv[p] + lap);
@@ -265,12 +302,16 @@ __device__ __forceinline__ void batch_tile(const BDesc* __restrict__ descs, cons
       io.fs = fs_of<T>(D);
       io.w = D.w + S.step;
       io.cs = D.cosv + S.step;
-      io.A = A;
+      io.A = ORD == 4 ? (T)(D.a / 12.0) : A;
       io.n = n;
-      io.Kp = min(K, D.nt - 1 - S.step);
+      io.Kp = min(KS, D.nt - 1 - S.step);
       io.force = ph == BP_B_STEP || (sizeof(T) == 4 && D.defect && ph == BP_A_STEP);
       const int xs = x0 + (int)threadIdx.y * batch_strip(K);
-      if (xs <= n - 1) march2d<T, K, kBC, VARC>(io, xs, y0, min(y0 + TYO, n), ((lt / D.ntx) & 1) != 0);
+      const bool up = ((lt / D.ntx) & 1) != 0;
+      if (xs <= n - 1) {
+        if constexpr (ORD == 4) march2d<T, KS, kBC, false, 2>(io, xs, y0, min(y0 + TYO, n), up);
+        else march2d<T, K, kBC, VARC>(io, xs, y0, min(y0 + TYO, n), up);
+      }
       break;
     }
     default:
@@ -285,8 +326,10 @@ __device__ __forceinline__ void batch_tile(const BDesc* __restrict__ descs, cons
 
 // Occupancy bound of the work kernels (waves per SIMD): what the row-marching pipeline's
 // registers allow without spilling.
-template <typename T, int K, bool VARC>
+template <typename T, int K, bool VARC, int ORD = 2>
 constexpr int batch_waves_per_eu() {
+  // fourth order: the radius-2 pipeline keeps 8 rows per level
+  if (ORD == 4) return sizeof(T) == 4 ? (K <= 4 ? 4 : 3) : (K <= 2 ? 4 : (K <= 4 ? 3 : 2));
   if (sizeof(T) == 4) return VARC ? (K <= 2 ? 4 : (K <= 4 ? 3 : 2)) : (K <= 2 ? 6 : (K <= 4 ? 4 : 3));
   return VARC ? (K <= 2 ? 4 : (K <= 4 ? 3 : 2)) : (K <= 2 ? 6 : (K <= 4 ? 4 : 2));
 }
@@ -299,8 +342,8 @@ constexpr int batch_waves_per_eu() {
 // wh_time_batch_kernel (TAG = 1) from the solver's in profiles; the code is the same.
 // The occupancy bound keeps the register budget of the one-tile-per-block form (constant c:
 // 6 waves per SIMD in FP32, i.e. three 8-wave blocks per CU, 4 in FP64; variable c: 4 and 2).
-template <typename T, int K, bool VARC, int TAG = 0>
-__global__ __launch_bounds__(64 * kBW, (batch_waves_per_eu<T, K, VARC>()))
+template <typename T, int K, bool VARC, int TAG = 0, int ORD = 2>
+__global__ __launch_bounds__(64 * kBW, (batch_waves_per_eu<T, K, VARC, ORD>()))
 void k_batch_work(const BDesc* __restrict__ descs,
                                                         const BState* __restrict__ states,
                                                         int* __restrict__ plan, int nb, int want) {
@@ -345,7 +388,7 @@ void k_batch_work(const BDesc* __restrict__ descs,
       else hi = mid - 1;
     }
     const int k0 = s_start[lo];
-    batch_tile<T, K, VARC>(descs, states, pid[lo], it - k0);
+    batch_tile<T, K, VARC, ORD>(descs, states, pid[lo], it - k0);
     if (tid == 0) s_item = c0 + nxt;
     __syncthreads();
   }
@@ -356,8 +399,8 @@ void k_batch_work(const BDesc* __restrict__ descs,
 // return at once.  Used for the class that holds most of the tiles (the FP32 stepping of a
 // mixed batch, everything in an FP64 batch), where the hardware's block dispatch balances the
 // work best.
-template <typename T, int K, bool VARC, int TAG = 0>
-__global__ __launch_bounds__(64 * kBW, (batch_waves_per_eu<T, K, VARC>()))
+template <typename T, int K, bool VARC, int TAG = 0, int ORD = 2>
+__global__ __launch_bounds__(64 * kBW, (batch_waves_per_eu<T, K, VARC, ORD>()))
 void k_batch_tile(const BDesc* __restrict__ descs, const BState* __restrict__ states,
                   const int* __restrict__ tile_solve, int ntiles, int want) {
   const int gt = xcd_tile_b(blockIdx.x, ntiles);
@@ -369,7 +412,7 @@ void k_batch_tile(const BDesc* __restrict__ descs, const BState* __restrict__ st
   const bool stepping = ph != BP_INIT && ph != BP_UPD1 && ph != BP_UPD2;
   const int cls = (stepping && phase_prec(ph, D.mixed && !S.force64) == 1) ? 1 : 0;
   if (cls != want) return;
-  batch_tile<T, K, VARC>(descs, states, sid, gt - D.tile0);
+  batch_tile<T, K, VARC, ORD>(descs, states, sid, gt - D.tile0);
 }
 
 // The plan of the next round from the problems' phases (one block; problems in index order,
@@ -665,15 +708,16 @@ struct RoundArgs {
   int ntiles, nb;
   bool mixed;
   BatchGrids grids;
+  bool ord4;   // fourth-order differences (c == 1): K/2 steps per stepping launch
 };
 
-template <int K, bool VARC>
-static void launch_round_k(const RoundArgs& a, hipStream_t s, const RoundFork* rf) {
+template <int K, bool VARC, int ORD>
+static void launch_round_ko(const RoundArgs& a, hipStream_t s, const RoundFork* rf) {
   const dim3 b(64, kBW);
   const BState* st = a.states;
   if (!a.mixed) {
     // FP64 batch: every phase is FP64, one tile per block
-    hipLaunchKernelGGL((k_batch_tile<double, K, VARC>), dim3(a.ntiles), b, 0, s, a.descs, st, a.tiles,
+    hipLaunchKernelGGL((k_batch_tile<double, K, VARC, 0, ORD>), dim3(a.ntiles), b, 0, s, a.descs, st, a.tiles,
                        a.ntiles, 0);
     return;
   }
@@ -685,15 +729,26 @@ static void launch_round_k(const RoundArgs& a, hipStream_t s, const RoundFork* r
   }
   // mixed batch: the few FP64 and element-wise tiles by persistent blocks over the plan, the
   // FP32 stepping tiles one per block
-  hipLaunchKernelGGL((k_batch_work<double, K, VARC>), dim3(a.grids.g64), b, 0, s64, a.descs, st, a.plan,
+  hipLaunchKernelGGL((k_batch_work<double, K, VARC, 0, ORD>), dim3(a.grids.g64), b, 0, s64, a.descs, st, a.plan,
                      a.nb, 0);
-  hipLaunchKernelGGL((k_batch_tile<float, K, VARC>), dim3(a.ntiles), b, 0, s, a.descs, st, a.tiles,
+  hipLaunchKernelGGL((k_batch_tile<float, K, VARC, 0, ORD>), dim3(a.ntiles), b, 0, s, a.descs, st, a.tiles,
                      a.ntiles, 1);
   if (rf) {
     (void)hipEventRecord(rf->join, rf->s2);
     (void)hipStreamWaitEvent(s, rf->join, 0);
   }
 }
+
+template <int K, bool VARC>
+static void launch_round_k(const RoundArgs& a, hipStream_t s, const RoundFork* rf) {
+  if constexpr (!VARC) {
+    if (a.ord4) return launch_round_ko<K, false, 4>(a, s, rf);
+  }
+  launch_round_ko<K, VARC, 2>(a, s, rf);
+}
+
+// Time steps of one stepping launch.
+static int batch_steps(int K, bool ord4) { return ord4 ? K / 2 : K; }
 
 // One round: the work kernels, the control kernel (phases advance), and in mixed batches the
 // plan of the next round.
@@ -703,7 +758,7 @@ static void launch_round(int K, bool varc, const RoundArgs& a, hipStream_t s, co
     case 4: varc ? launch_round_k<4, true>(a, s, rf) : launch_round_k<4, false>(a, s, rf); break;
     default: varc ? launch_round_k<8, true>(a, s, rf) : launch_round_k<8, false>(a, s, rf); break;
   }
-  hipLaunchKernelGGL(k_batch_control, dim3(a.nb), dim3(256), 0, s, a.descs, a.states, K);
+  hipLaunchKernelGGL(k_batch_control, dim3(a.nb), dim3(256), 0, s, a.descs, a.states, batch_steps(K, a.ord4));
   if (a.mixed)
     hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(256), 0, s, a.descs, (const BState*)a.states, a.nb, a.plan);
 }
@@ -809,7 +864,12 @@ wh_status batch_validate(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const
   for (int i = 0; i < nb; ++i) {
     const wh_problem& q = probs[i];
     if (q.grid.dim != 2) WHB_FAIL(ctx, WH_EUNSUPPORTED, "batched solves are 2D (problem %d)", i);
-    if (q.grid.order != 2) WHB_FAIL(ctx, WH_EUNSUPPORTED, "order must be 2 (problem %d)", i);
+    if (q.grid.order != 2 && q.grid.order != 4)
+      WHB_FAIL(ctx, WH_EUNSUPPORTED, "order must be 2 or 4 (problem %d)", i);
+    if (q.grid.order != probs[0].grid.order)
+      WHB_FAIL(ctx, WH_EUNSUPPORTED, "all problems of a batch must have one order (problem %d)", i);
+    if (q.grid.order == 4 && q.c2)
+      WHB_FAIL(ctx, WH_EUNSUPPORTED, "fourth-order differences need c == 1 (problem %d)", i);
     // the work kernels address each node array with 32-bit byte offsets
     if (q.grid.n < 4 || q.grid.n > 16000) WHB_FAIL(ctx, WH_EINVAL, "n must lie in [4, 16000] (problem %d)", i);
     if (!(q.omega > 0)) WHB_FAIL(ctx, WH_EINVAL, "omega must be > 0 (problem %d)", i);
@@ -871,7 +931,7 @@ wh_status deflated_start(wh_ctx* ctx, const wh_problem& pr, const TimeParams& tp
   double* coef = (double*)take(8 * (size_t)nd * 2);
   std::vector<int32_t> modes(2 * (size_t)nd);
   std::vector<double> lam2(nd);
-  if (wh_select_sine_modes(2, n, 2, pr.omega, nd, modes.data(), lam2.data()) != WH_OK)
+  if (wh_select_sine_modes(2, n, pr.grid.order, pr.omega, nd, modes.data(), lam2.data()) != WH_OK)
     WHB_FAIL(ctx, WH_EINVAL, "sine mode selection failed (n = %d, n_defl = %d)", n, nd);
   // the frequency whose Helmholtz problem the fixed point solves: (2/dt) sin(omega_w dt / 2)
   const double sh = std::sin(0.5 * tp.omega_w * tp.dt);
@@ -909,7 +969,7 @@ struct BatchSetup {
   std::vector<TimeParams> tps;
   std::vector<BDesc> D;
   int ntiles = 0, K = 4;
-  bool mixed = false, varc = false;
+  bool mixed = false, varc = false, ord4 = false;
   BDesc* ddesc = nullptr;
   BState* dstate = nullptr;
   int* dplan = nullptr;      // the two class plans of the next round (plan_stride(nb) ints each)
@@ -944,7 +1004,7 @@ wh_status prepare_batch(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const 
     const double cmax = params->c_max > 0 ? params->c_max : 1.0;
     wh_params p = *params;
     p.omega = probs[i].omega;
-    wh_status st = make_time_params(ctx, 2, probs[i].grid.n, p, cmax, tps[i]);
+    wh_status st = make_time_params(ctx, 2, probs[i].grid.n, p, cmax, tps[i], probs[i].grid.order);
     if (st != WH_OK) return st;
   }
   const int K = batch_K(params);
@@ -974,7 +1034,9 @@ wh_status prepare_batch(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const 
                                                               : (probs[i].n_defl > 0 ? 1e-4 : 0.1);
     // FP32 A-apply: the defect form for undeflated problems (near-resonant modes present),
     // direct stepping when the near-resonant modes are deflated
-    d.defect = params->mixed_form == 0 || (params->mixed_form < 0 && probs[i].n_defl == 0);
+    // (second order only, as in the single solves)
+    d.defect = probs[i].grid.order == 2 &&
+               (params->mixed_form == 0 || (params->mixed_form < 0 && probs[i].n_defl == 0));
     d.om2dt2 = 4.0 * std::sin(0.5 * tps[i].omega_w * tps[i].dt) * std::sin(0.5 * tps[i].omega_w * tps[i].dt);
     for (int k = 0; k < 4; ++k) d.W[k] = take(8 * N);
     if (mixed)
@@ -1063,6 +1125,7 @@ wh_status prepare_batch(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const 
   B.K = K;
   B.mixed = mixed;
   B.varc = varc;
+  B.ord4 = probs[0].grid.order == 4;
   B.ddesc = ddesc;
   B.dstate = dstate;
   B.dplan = dplan;
@@ -1088,7 +1151,7 @@ size_t wh_workspace_bytes_batched(int32_t nb, const wh_problem* probs, const wh_
     wh_params p = *params;
     p.omega = probs[i].omega;
     TimeParams tp;
-    if (make_time_params(nullptr, 2, probs[i].grid.n, p, cmax, tp) != WH_OK) return 0;
+    if (make_time_params(nullptr, 2, probs[i].grid.n, p, cmax, tp, probs[i].grid.order) != WH_OK) return 0;
     total += problem_bytes(probs[i].grid.n, tp.nt, K, mixed, varc);
   }
   size_t dscr = 0;
@@ -1147,7 +1210,7 @@ wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
       for (int g = 0; g < G; ++g)
-        launch_round(K, varc, RoundArgs{ddesc, dstate, dplan, B.dtiles, B.ntiles, nb, mixed, B.grids}, cs,
+        launch_round(K, varc, RoundArgs{ddesc, dstate, dplan, B.dtiles, B.ntiles, nb, mixed, B.grids, B.ord4}, cs,
                      use_fork ? &rf : nullptr);
       hipLaunchKernelGGL(k_batch_count, dim3(1), dim3(256), 0, cs, (const BState*)dstate, nb, dcount[gi]);
       e = hipStreamEndCapture(cs, &graph[gi]);
@@ -1174,7 +1237,8 @@ wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
   // (N_t/K + 6) rounds plus its outer sweeps
   long long max_rounds = 0;
   for (int i = 0; i < nb; ++i) {
-    const long long per_it = (D[i].nt + K - 1) / K + 6;
+    const int ks = batch_steps(K, B.ord4);
+    const long long per_it = (D[i].nt + ks - 1) / ks + 6;
     // an iteration is at most one A wave solve plus one residual replacement
     max_rounds = std::max(max_rounds, (long long)D[i].max_iters * 2 * per_it + 2 * per_it + 8);
   }
@@ -1253,6 +1317,8 @@ wh_status wh_time_batch_kernel(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
   if (reps < 1 || !us_per_launch) WHB_FAIL(ctx, WH_EINVAL, "reps must be >= 1 and us_per_launch set");
   if (!params || params->precision != WH_MIXED)
     WHB_FAIL(ctx, WH_EINVAL, "the FP32 work kernel is timed with params->precision = WH_MIXED");
+  if (nb >= 1 && probs && probs[0].grid.order != 2)
+    WHB_FAIL(ctx, WH_EUNSUPPORTED, "the work kernel is timed for second-order batches");
   BatchSetup B;
   {
     const wh_status ps = prepare_batch(ctx, nb, probs, params, ws, ws_bytes, B);
@@ -1273,7 +1339,7 @@ wh_status wh_time_batch_kernel(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
     st.step = 1;
   }
   HIPB(ctx, hipMemcpyAsync(B.dstate, S.data(), sizeof(BState) * nb, hipMemcpyHostToDevice, s));
-  const RoundArgs ra{B.ddesc, B.dstate, B.dplan, B.dtiles, B.ntiles, nb, true, B.grids};
+  const RoundArgs ra{B.ddesc, B.dstate, B.dplan, B.dtiles, B.ntiles, nb, true, B.grids, false};
   auto one = [&]() { launch_work_timing(B.K, B.varc, ra, s); };
   HIPB(ctx, hipStreamSynchronize(s));
   one();

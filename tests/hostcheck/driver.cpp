@@ -271,8 +271,8 @@ void noalloc_case(int dim, int n, int precision, bool varc, unsigned seed) {
   delete c2;
 }
 
-void batched_case(int precision, int solver, bool deflate, unsigned seed) {
-  const int ns[] = {8, 16, 24, 33, 12};
+void batched_case(int precision, int solver, bool deflate, unsigned seed, int order = 2, int k_fuse = 0) {
+  const int ns[] = {8, 16, 24, 33, order == 4 ? 200 : 12};
   const int nb = 5;
   std::vector<Buf*> keep;
   std::vector<wh_problem> probs(nb);
@@ -284,7 +284,7 @@ void batched_case(int precision, int solver, bool deflate, unsigned seed) {
     fill_field(f->d(), 2, n, 0.0, 1.0, seed + i);
     keep.push_back(f);
     keep.push_back(u);
-    probs[i].grid = wh_grid{2, n, 2};
+    probs[i].grid = wh_grid{2, n, order};
     probs[i].c2 = nullptr;
     probs[i].f = f->d();
     probs[i].omega = 0.31 * n + 1.7;
@@ -295,18 +295,20 @@ void batched_case(int precision, int solver, bool deflate, unsigned seed) {
   p.precision = precision;
   p.solver = solver;
   p.max_iters = 40;
+  p.k_fuse = k_fuse;
   const size_t need = wh_workspace_bytes_batched(nb, probs.data(), &p);
   expect(need > 0, "wh_workspace_bytes_batched", 0);
   Buf ws(need, "batched workspace");
   std::vector<wh_info> infos(nb);
   int st = wh_solve_batched(g_ctx, nb, probs.data(), &p, ws.p, need, infos.data());
   expect(st >= 0, "wh_solve_batched", st);
-  printf("batched prec=%d solver=%d defl=%d -> %d\n", precision, solver, (int)deflate, st);
+  printf("batched prec=%d solver=%d defl=%d order=%d k=%d -> %d\n", precision, solver, (int)deflate, order,
+         k_fuse, st);
   if (precision == WH_MIXED) {
     double us = 0;
     int64_t pts = 0;
     st = wh_time_batch_kernel(g_ctx, nb, probs.data(), &p, 3, ws.p, need, &us, &pts);
-    expect(st == 0, "wh_time_batch_kernel", st);
+    expect(order == 2 ? st == 0 : st == WH_EUNSUPPORTED, "wh_time_batch_kernel", st);
   }
   for (Buf* b : keep) delete b;
 }
@@ -402,6 +404,8 @@ int main(int argc, char** argv) {
     for (int prec : {0, 1}) {
       batched_case(prec, WH_CG, false, seed);
       batched_case(prec, WH_DCG, true, seed);
+      // fourth order (a 200^2 problem spans two tile columns); K = 8, 4, 2 steps of halo
+      for (int k : {0, 8, 2}) batched_case(prec, k == 2 ? WH_CG : WH_DCG, k != 2, seed, 4, k);
     }
   }
   wh_destroy(g_ctx);
