@@ -792,8 +792,9 @@ struct BatchLayout {
 };
 
 // per problem: 4 state arrays + V, b, r, p, q (8N each), FP32 states (4 x 4N, mixed), kap64/fs64 (8N),
-// kap32/fs32 (4N, mixed), partials (tiles), weights 2(N_t+1)
-static size_t problem_bytes(int n, int nt, int K, bool mixed, bool varc) {
+// kap32/fs32 (4N, mixed), partials (tiles).  The weight tables (2(N_t+1) doubles per problem) sit
+// in one region after all problems.
+static size_t problem_bytes(int n, int K, bool mixed, bool varc) {
   const size_t N = (size_t)(n + 1) * (n + 1);
   size_t b = 0;
   auto add = [&](size_t x) { b += (x + 255) & ~(size_t)255; };
@@ -804,12 +805,13 @@ static size_t problem_bytes(int n, int nt, int K, bool mixed, bool varc) {
   add(8 * N);
   if (mixed) { if (varc) add(4 * N); add(4 * N); }
   add(8 * (size_t)tile_dim(n, K, 0) * tile_dim(n, K, 1));
-  add(16 * (size_t)(nt + 1));
   return b;
 }
 
-// Scratch for the deflated start of one problem (reused problem by problem): sine
-// tables, projection partials, mode numbers, two scale vectors and two coefficient sets.
+// Scratch of the deflated start of one problem (each deflated problem has its own, so the
+// starts of all problems run without host synchronisation): sine tables, projection partials
+// and the two coefficient sets.  The mode numbers and scales of all problems sit in two shared
+// upload regions (2 n_defl ints and 2 n_defl doubles per problem).
 static size_t defl_scratch_bytes(int n, int nd) {
   if (nd <= 0) return 0;
   Defl dl;
@@ -821,8 +823,6 @@ static size_t defl_scratch_bytes(int n, int nd) {
   auto add = [&](size_t x) { b += (x + 255) & ~(size_t)255; };
   add(8 * (size_t)nd * 2 * (n + 1));
   add(8 * (size_t)defl_partial_blocks(dl) * nd);
-  add(4 * (size_t)nd * 2);
-  add(8 * (size_t)nd * 2);
   add(8 * (size_t)nd * 2);
   return b;
 }
@@ -907,9 +907,39 @@ wh_status stage_to_device(wh_ctx* ctx, void* dev, const void* host, size_t bytes
 // omega^2 (eigenvectors of L_h, L_h phi_k = -lambda_k^2 phi_k, and of A with
 // mu_k = 1 - beta_h(lambda_k^2)), the fixed point's coefficients are
 // c_k = phi_k^T f / (omega_fp^2 - lambda_k^2); x = sum c_k phi_k, q = A x = sum mu_k c_k phi_k.
+// Host part: the modes (2 nd ints) and the two scale vectors (2 nd doubles: -1/den, -mu/den;
+// launch_defl_combine subtracts sum_k slot_k phi_k, so the coefficients are stored negated).
+wh_status deflated_start_host(wh_ctx* ctx, const wh_problem& pr, const TimeParams& tp, int32_t* modes,
+                              double* sc) {
+  const int n = pr.grid.n, nd = pr.n_defl;
+  std::vector<double> lam2(nd);
+  if (wh_select_sine_modes(2, n, pr.grid.order, pr.omega, nd, modes, lam2.data()) != WH_OK)
+    WHB_FAIL(ctx, WH_EINVAL, "sine mode selection failed (n = %d, n_defl = %d)", n, nd);
+  // the frequency whose Helmholtz problem the fixed point solves: (2/dt) sin(omega_w dt / 2)
+  const double sh = std::sin(0.5 * tp.omega_w * tp.dt);
+  const double om2 = 4.0 * sh * sh / (tp.dt * tp.dt);
+  for (int k = 0; k < nd; ++k) {
+    const double den = om2 - lam2[k];
+    if (den == 0.0) WHB_FAIL(ctx, WH_EBREAKDOWN, "sine mode %d is at resonance", k);
+    const double mu = 1.0 - transfer(tp, lam2[k]);
+    sc[k] = -1.0 / den;
+    sc[nd + k] = -mu / den;
+  }
+  return WH_OK;
+}
+
+// Device part, from the uploaded modes and scales, in the problem's own scratch (no host
+// synchronisation): the sine tables, the projections of f, the coefficients, x and q = A x.
 // x and q must be zero on entry.
-wh_status deflated_start(wh_ctx* ctx, const wh_problem& pr, const TimeParams& tp, BDesc& d,
-                         char* scratch, hipStream_t s) {
+struct DeflScratch {
+  double* tab = nullptr;
+  double* partials = nullptr;
+  double* coef = nullptr;
+  int32_t* modes = nullptr;   // in the shared upload region
+  double* scales = nullptr;
+};
+
+void deflated_start_launch(const wh_problem& pr, BDesc& d, const DeflScratch& w, hipStream_t s) {
   const int n = pr.grid.n, nd = pr.n_defl;
   const int64_t N = (int64_t)(n + 1) * (n + 1);
   Defl dl;
@@ -918,48 +948,14 @@ wh_status deflated_start(wh_ctx* ctx, const wh_problem& pr, const TimeParams& tp
   dl.dim = 2;
   dl.n = n;
   const int blocks = defl_partial_blocks(dl);
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    char* p = scratch + off;
-    off += (bytes + 255) & ~(size_t)255;
-    return (void*)p;
-  };
-  double* tab = (double*)take(8 * (size_t)nd * 2 * (n + 1));
-  double* partials = (double*)take(8 * (size_t)blocks * nd);
-  int32_t* modes_dev = (int32_t*)take(4 * (size_t)nd * 2);
-  double* scales = (double*)take(8 * (size_t)nd * 2);
-  double* coef = (double*)take(8 * (size_t)nd * 2);
-  std::vector<int32_t> modes(2 * (size_t)nd);
-  std::vector<double> lam2(nd);
-  if (wh_select_sine_modes(2, n, pr.grid.order, pr.omega, nd, modes.data(), lam2.data()) != WH_OK)
-    WHB_FAIL(ctx, WH_EINVAL, "sine mode selection failed (n = %d, n_defl = %d)", n, nd);
-  // the frequency whose Helmholtz problem the fixed point solves: (2/dt) sin(omega_w dt / 2)
-  const double sh = std::sin(0.5 * tp.omega_w * tp.dt);
-  const double om2 = 4.0 * sh * sh / (tp.dt * tp.dt);
-  std::vector<double> sc(2 * (size_t)nd);
-  for (int k = 0; k < nd; ++k) {
-    const double den = om2 - lam2[k];
-    if (den == 0.0) WHB_FAIL(ctx, WH_EBREAKDOWN, "sine mode %d is at resonance", k);
-    const double mu = 1.0 - transfer(tp, lam2[k]);
-    // launch_defl_combine subtracts sum_k slot_k phi_k: store the negated coefficients
-    sc[k] = -1.0 / den;
-    sc[nd + k] = -mu / den;
-  }
-  wh_status st = stage_to_device(ctx, modes_dev, modes.data(), 4 * modes.size(), s);
-  if (st != WH_OK) return st;
-  st = stage_to_device(ctx, scales, sc.data(), 8 * sc.size(), s);
-  if (st != WH_OK) return st;
-  launch_sine_tables(tab, modes_dev, nd, 2, n, s);
-  dl.tab = tab;
-  launch_defl_project(dl, pr.f, partials, s);
-  launch_defl_reduce(partials, blocks, nd, coef, 0, scales, s);
-  launch_defl_reduce(partials, blocks, nd, coef, nd, scales + nd, s);
-  launch_defl_combine(dl, d.x, 1.0, nullptr, 0.0, coef, 0, N, s);
-  launch_defl_combine(dl, d.q, 1.0, nullptr, 0.0, coef, nd, N, s);
-  HIPB(ctx, hipStreamSynchronize(s));
-  HIPB(ctx, hipGetLastError());
+  launch_sine_tables(w.tab, w.modes, nd, 2, n, s);
+  dl.tab = w.tab;
+  launch_defl_project(dl, pr.f, w.partials, s);
+  launch_defl_reduce(w.partials, blocks, nd, w.coef, 0, w.scales, s);
+  launch_defl_reduce(w.partials, blocks, nd, w.coef, nd, w.scales + nd, s);
+  launch_defl_combine(dl, d.x, 1.0, nullptr, 0.0, w.coef, 0, N, s);
+  launch_defl_combine(dl, d.q, 1.0, nullptr, 0.0, w.coef, nd, N, s);
   d.x0 = 1;
-  return WH_OK;
 }
 
 // Validation, workspace carving, coefficient arrays, zeroed states, weight tables, deflated
@@ -1011,6 +1007,7 @@ wh_status prepare_batch(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const 
   // pass 1: carve the workspace (no device writes until the layout is known to fit)
   std::vector<BDesc> D(nb);
   std::vector<int> tile_solve;
+  const size_t probs_begin = cur_off;   // the problems' arrays, zeroed by one fill
   for (int i = 0; i < nb; ++i) {
     const int n = probs[i].grid.n;
     const size_t N = (size_t)(n + 1) * (n + 1);
@@ -1056,58 +1053,103 @@ wh_status prepare_batch(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const 
     d.kap32 = kap32;
     d.fs32 = fs32;
     d.partials = (double*)take(8 * (size_t)d.ntx * d.nty);
-    double* wtab = (double*)take(16 * (size_t)(d.nt + 1));
-    d.w = wtab;
-    d.cosv = wtab + d.nt + 1;
+  }
+  const size_t probs_end = cur_off;
+  // weight tables of all problems (w then cos, N_t + 1 each), uploaded in one copy
+  size_t wtot = 0;
+  for (int i = 0; i < nb; ++i) wtot += 2 * (size_t)(D[i].nt + 1);
+  double* wall = (double*)take(8 * wtot);
+  {
+    size_t o = 0;
+    for (int i = 0; i < nb; ++i) {
+      D[i].w = wall + o;
+      D[i].cosv = wall + o + D[i].nt + 1;
+      o += 2 * (size_t)(D[i].nt + 1);
+    }
+  }
+  // deflated starts: per-problem scratch, and the shared upload regions of modes and scales
+  std::vector<DeflScratch> dsc(nb);
+  size_t ndt = 0;
+  for (int i = 0; i < nb; ++i) {
+    const int nd = probs[i].n_defl, n = probs[i].grid.n;
+    if (nd <= 0) continue;
+    Defl dl;
+    dl.kind = WH_DEFL_SINE;
+    dl.nd = nd;
+    dl.dim = 2;
+    dl.n = n;
+    dsc[i].tab = (double*)take(8 * (size_t)nd * 2 * (n + 1));
+    dsc[i].partials = (double*)take(8 * (size_t)defl_partial_blocks(dl) * nd);
+    dsc[i].coef = (double*)take(8 * (size_t)nd * 2);
+    ndt += 2 * (size_t)nd;
+  }
+  int32_t* modes_all = (int32_t*)take(4 * ndt);
+  double* scales_all = (double*)take(8 * ndt);
+  {
+    size_t o = 0;
+    for (int i = 0; i < nb; ++i) {
+      if (probs[i].n_defl <= 0) continue;
+      dsc[i].modes = modes_all + o;
+      dsc[i].scales = scales_all + o;
+      o += 2 * (size_t)probs[i].n_defl;
+    }
   }
   const int ntiles = (int)tile_solve.size();
-  size_t dscr = 0;
-  for (int i = 0; i < nb; ++i) dscr = std::max(dscr, defl_scratch_bytes(probs[i].grid.n, probs[i].n_defl));
-  char* dscratch = dscr ? (char*)take(dscr) : nullptr;
   BDesc* ddesc = (BDesc*)take(sizeof(BDesc) * nb);
   BState* dstate = (BState*)take(sizeof(BState) * nb);
   int* dplan = (int*)take(4 * (2 * (size_t)plan_stride(nb) + 16));
   int* dtiles = (int*)take(4 * (size_t)ntiles);
   int* dremain = (int*)take(256);
   if (cur_off > ws_bytes) WHB_FAIL(ctx, WH_EWORKSPACE, "workspace too small (layout %zu)", cur_off);
-  // pass 2: coefficient arrays, zeroed state, weight tables
+  // host part of the deflated starts (mode selection can fail: before any device write)
+  std::vector<int32_t> hmodes(ndt);
+  std::vector<double> hscales(ndt);
+  {
+    size_t o = 0;
+    for (int i = 0; i < nb; ++i) {
+      if (probs[i].n_defl <= 0) continue;
+      wh_status ds = deflated_start_host(ctx, probs[i], tps[i], hmodes.data() + o, hscales.data() + o);
+      if (ds != WH_OK) return ds;
+      o += 2 * (size_t)probs[i].n_defl;
+    }
+  }
+  // pass 2 (stream-ordered, no host synchronisation until the end): zeroed states, coefficient
+  // arrays, the weight tables, the deflated starts
+  HIPB(ctx, hipMemsetAsync(base + probs_begin, 0, probs_end - probs_begin, s));
   for (int i = 0; i < nb; ++i) {
     const int n = probs[i].grid.n;
     const size_t N = (size_t)(n + 1) * (n + 1);
     const double h = 1.0 / n;
     BDesc& d = D[i];
-    double* kap64 = (double*)d.kap64;
-    double* fs64 = (double*)d.fs64;
-    float* kap32 = (float*)d.kap32;
-    float* fs32 = (float*)d.fs32;
-    double* wtab = (double*)d.w;
     const double dt2 = tps[i].dt * tps[i].dt;
     const double ks = dt2 / (2.0 * h * h);
-    launch_prep_coeffs(probs[i].c2, probs[i].f, kap64, fs64, false, ks, dt2, (int64_t)N, n, 2, s);
-    if (mixed) launch_prep_coeffs(probs[i].c2, probs[i].f, kap32, fs32, true, ks, dt2, (int64_t)N, n, 2, s);
-    for (int k = 0; k < 4; ++k) HIPB(ctx, hipMemsetAsync(d.W[k], 0, 8 * N, s));
+    launch_prep_coeffs(probs[i].c2, probs[i].f, (double*)d.kap64, (double*)d.fs64, false, ks, dt2, (int64_t)N, n, 2,
+                       s);
     if (mixed)
-      for (int k = 0; k < 4; ++k) HIPB(ctx, hipMemsetAsync(d.W32[k], 0, 4 * N, s));
-    for (double* v : {d.V, d.b, d.r, d.p, d.q}) HIPB(ctx, hipMemsetAsync(v, 0, 8 * N, s));
+      launch_prep_coeffs(probs[i].c2, probs[i].f, (float*)d.kap32, (float*)d.fs32, true, ks, dt2, (int64_t)N, n, 2,
+                         s);
     HIPB(ctx, hipMemsetAsync(d.x, 0, 8 * N, s));   // batched solves start from zero
-    // weights (staged through the pinned block)
-    std::vector<double> tab(2 * (d.nt + 1));
-    for (int k = 0; k <= d.nt; ++k) {
-      tab[k] = tps[i].w[k];
-      tab[d.nt + 1 + k] = tps[i].cosv[k];
-    }
-    for (size_t o = 0; o < tab.size(); o += ctx->hbuf_len) {
-      const size_t cnt = std::min(tab.size() - o, (size_t)ctx->hbuf_len);
-      HIPB(ctx, hipStreamSynchronize(s));
-      std::memcpy(ctx->hbuf, tab.data() + o, cnt * sizeof(double));
-      HIPB(ctx, hipMemcpyAsync(wtab + o, ctx->hbuf, cnt * sizeof(double), hipMemcpyHostToDevice, s));
-    }
-    HIPB(ctx, hipStreamSynchronize(s));
-    if (probs[i].n_defl > 0) {
-      wh_status ds = deflated_start(ctx, probs[i], tps[i], d, dscratch, s);
-      if (ds != WH_OK) return ds;
+  }
+  // (copies from pageable host memory return once the data is staged)
+  std::vector<double> tab(wtot);
+  {
+    size_t o = 0;
+    for (int i = 0; i < nb; ++i) {
+      const int nt = D[i].nt;
+      for (int k = 0; k <= nt; ++k) {
+        tab[o + k] = tps[i].w[k];
+        tab[o + nt + 1 + k] = tps[i].cosv[k];
+      }
+      o += 2 * (size_t)(nt + 1);
     }
   }
+  HIPB(ctx, hipMemcpyAsync(wall, tab.data(), 8 * wtot, hipMemcpyHostToDevice, s));
+  if (ndt) {
+    HIPB(ctx, hipMemcpyAsync(modes_all, hmodes.data(), 4 * ndt, hipMemcpyHostToDevice, s));
+    HIPB(ctx, hipMemcpyAsync(scales_all, hscales.data(), 8 * ndt, hipMemcpyHostToDevice, s));
+  }
+  for (int i = 0; i < nb; ++i)
+    if (probs[i].n_defl > 0) deflated_start_launch(probs[i], D[i], dsc[i], s);
   // upload descriptors, tile table and the initial states (synchronous copies from host memory)
   HIPB(ctx, hipMemcpyAsync(ddesc, D.data(), sizeof(BDesc) * nb, hipMemcpyHostToDevice, s));
   HIPB(ctx, hipMemcpyAsync(dtiles, tile_solve.data(), 4 * (size_t)ntiles, hipMemcpyHostToDevice, s));
@@ -1146,17 +1188,22 @@ size_t wh_workspace_bytes_batched(int32_t nb, const wh_problem* probs, const wh_
   const bool varc = probs[0].c2 != nullptr;
   const int K = batch_K(params);
   const double cmax = params->c_max > 0 ? params->c_max : 1.0;
-  size_t total = 0;
+  size_t total = 0, wtot = 0;
   for (int i = 0; i < nb; ++i) {
     wh_params p = *params;
     p.omega = probs[i].omega;
     TimeParams tp;
     if (make_time_params(nullptr, 2, probs[i].grid.n, p, cmax, tp, probs[i].grid.order) != WH_OK) return 0;
-    total += problem_bytes(probs[i].grid.n, tp.nt, K, mixed, varc);
+    total += problem_bytes(probs[i].grid.n, K, mixed, varc);
+    wtot += 2 * (size_t)(tp.nt + 1);
   }
-  size_t dscr = 0;
-  for (int i = 0; i < nb; ++i) dscr = std::max(dscr, defl_scratch_bytes(probs[i].grid.n, probs[i].n_defl));
-  total += dscr;
+  total += (8 * wtot + 255) & ~(size_t)255;
+  size_t ndt = 0;
+  for (int i = 0; i < nb; ++i) {
+    total += defl_scratch_bytes(probs[i].grid.n, probs[i].n_defl);
+    ndt += 2 * (size_t)std::max(0, probs[i].n_defl);
+  }
+  total += ((4 * ndt + 255) & ~(size_t)255) + ((8 * ndt + 255) & ~(size_t)255);
   total += 16 * (size_t)kReduceBlocks;  // c_max reductions (multiple of 256)
   total += ((sizeof(BDesc) * nb + 255) & ~(size_t)255) + ((sizeof(BState) * nb + 255) & ~(size_t)255);
   total += ((4 * (2 * (size_t)plan_stride(nb) + 16) + 255) & ~(size_t)255) + 256;
