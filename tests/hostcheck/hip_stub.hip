@@ -585,6 +585,37 @@ bool model_generic(const std::string& base, const std::vector<std::string>& t, d
     if (!(src + nd <= dst || dst + nd <= src)) fail("source and destination slot ranges overlap");
     vec(arg<void*>(args, 0), (int64_t)nd * nd, 8, "matrix");
     vec(arg<void*>(args, 2), std::max(src, dst) + nd, 8, "slots");
+  } else if (base == "k_sine_tables") {
+    // tab[(k dim + axis)(n + 1) + i] for every k < nd, axis < dim, i <= n; modes[k dim + axis]
+    const int nd = arg<int>(args, 2), dim = arg<int>(args, 3), n = arg<int>(args, 4);
+    const int64_t total = (int64_t)nd * dim * (n + 1);
+    if (nd < 1 || (dim != 2 && dim != 3) || n < 2) fail("nd %d dim %d n %d", nd, dim, n);
+    vec(arg<void*>(args, 0), total, 8, "tab");
+    vec(arg<void*>(args, 1), (int64_t)nd * dim, 4, "modes");
+  } else if (base == "k_sine_project" || base == "k_sine_combine") {
+    // 64 columns x 32 rows per block over the rows of length n + 1 (2D: n + 1 rows, 3D: (n + 1)^2)
+    const int nd = arg<int>(args, 1), dim = arg<int>(args, 2), n = arg<int>(args, 3);
+    const int64_t P = n + 1, rows = dim == 2 ? P : P * P;
+    if ((int64_t)g.x != (P + 63) / 64 || (int64_t)g.y != (rows + 31) / 32 || g.z != 1)
+      fail("grid (%u, %u) for n = %d, dim = %d", g.x, g.y, n, dim);
+    if (nd < 1) fail("nd = %d", nd);
+    vec(arg<void*>(args, 0), (int64_t)nd * dim * P, 8, "tab");
+    if (base == "k_sine_project") {
+      vec(arg<void*>(args, 4), rows * P, 8, "r");
+      vec(arg<void*>(args, 5), (int64_t)g.x * g.y * nd, 8, "partials");
+    } else {
+      vec(arg<void*>(args, 4), rows * P, 8, "y");
+      vec(arg<void*>(args, 6), 1, 8, "alpha slot");
+      vec(arg<void*>(args, 7), rows * P, 8, "r");
+      vec(arg<void*>(args, 9), nd, 8, "coef");
+    }
+  } else if (base == "k_defl_reduce") {
+    const int count = arg<int>(args, 1), nd = arg<int>(args, 2), dst = arg<int>(args, 4);
+    if ((int)g.x != nd) fail("grid %u for %d slots", g.x, nd);
+    vec(arg<void*>(args, 0), (int64_t)count * nd, 8, "partials");
+    double* slots = arg<double*>(args, 3);
+    if (slots) check_range(slots, 8LL * dst, 8LL * (dst + nd), "slots");
+    vec(arg<void*>(args, 5), nd, 8, "scale");
   } else if (base == "k_check_idx") {
     vec(arg<void*>(args, 0), arg<int>(args, 1), 8, "rec_idx"); vec(arg<void*>(args, 3), 1, 4, "bad");
   } else {
