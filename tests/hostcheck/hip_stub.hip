@@ -624,6 +624,35 @@ bool model_generic(const std::string& base, const std::vector<std::string>& t, d
   return true;
 }
 
+// Fourth-order single step: one thread per node of the (n+1)^dim grid (p < N guard), so every
+// array the mode uses must hold N elements; partial sums one per block in the epilogues.
+void model_step4(const std::vector<std::string>& t, dim3 g, dim3 b, void** args) {
+  const size_t TS = tsize(t, 0);
+  const int DIM = ti(t, 1), MODE = ti(t, 2), FORCE = ti(t, 3);
+  const StepArgs a = arg<StepArgs>(args, 0);
+  const int64_t P = (int64_t)a.n + 1, N = DIM == 2 ? P * P : P * P * P;
+  if (b.x != 256 || b.y != 1) fail("block shape (%u,%u)", b.x, b.y);
+  if ((int64_t)g.x != (N + 255) / 256) fail("grid %u for %lld nodes", g.x, (long long)N);
+  if (a.n < 4) fail("n = %d", a.n);
+  if (FORCE) vec(a.fs, N, TS, "fs");
+  vec(a.V, N, 8, "V");
+  if (MODE == M_FIRST) {
+    vec(a.prev, N, TS, "prev"); vec(a.cur_out, N, TS, "cur_out");
+    vec(a.zb0, N, TS, "zb0"); vec(a.zb1, N, TS, "zb1"); vec(a.vin, N, 8, "vin");
+    return;
+  }
+  vec(a.cur, N, TS, "cur"); vec(a.prev, N, TS, "prev");
+  if (MODE == M_MID) {
+    if (TS == 4) vec(a.cur_next, N, TS, "cur_next");
+    return;
+  }
+  if (MODE == M_LAST_AQ || MODE == M_LAST_FPI || MODE == M_LAST_EQ) {
+    vec(a.x, N, 8, "x"); vec(a.out, N, 8, "out");
+    if (!a.partials) fail("no partials");
+    vec(a.partials, g.x, 8, "partials");
+  }
+}
+
 // Blocked fourth-order launch: K steps of a 2D single solve by the row-marching pipeline.
 // Every access goes through a buffer resource sized to the (n+1)^2 grid, so the model checks
 // that each pointer holds the whole grid, and that the grid and block match the tiling.
@@ -671,6 +700,7 @@ void check_launch(const void* fn, dim3 g, dim3 b, void** args) {
   else if (base == "k_batch_work") model_batch_work(t, g, b, args);
   else if (base == "k_batch_tile") model_batch_tile(t, g, b, args);
   else if (base == "k_march4") model_march4(t, g, b, args);
+  else if (base == "k_step4") model_step4(t, g, b, args);
   else done = model_generic(base, t, g, b, args);
   if (done) ++g_modelled;
   else ++g_unmodelled[base];
