@@ -41,7 +41,7 @@ B_FUSED_F32 = 32.0
 # HBM KiB per dispatch (FETCH_SIZE, WRITE_SIZE) of the tagged batch work kernel on the config-4
 # batch, from the two counter passes in profiles/hbm_traffic_batch_tile_cfg4.md, with the copy-kernel
 # scale factors; valid only for the kernel sources it was taken on (sha1 over the three files)
-BATCH_TRAFFIC = {"src_sha1": "0e24a4778a0e3d3cab2ecd6e61f273e6a1b80929", "fetch_scale": 2.0, "write_scale": 1.0,
+BATCH_TRAFFIC = {"src_sha1": "453dce2f5f6f879970d302b3464ed1549f8466d7", "fetch_scale": 2.0, "write_scale": 1.0,
                  "kib": [734884.6, 1447137.5]}
 # HBM KiB per dispatch (FETCH_SIZE, WRITE_SIZE) of every FP32 temporally blocked kernel
 # variant "K,R,NW" on this grid, from the two rocprofv3 counter passes summarised in

@@ -721,18 +721,20 @@ static void launch_round_ko(const RoundArgs& a, hipStream_t s, const RoundFork* 
                        a.ntiles, 0);
     return;
   }
+  // mixed batch: the FP32 stepping tiles one per block, and beside them the few FP64 and
+  // element-wise tiles by persistent blocks over the plan.  The FP32 kernel, which holds most
+  // rounds' critical path, is issued first (in a captured graph the kernel issued second starts
+  // about 9 us later).
   hipStream_t s64 = s;
+  if (rf) (void)hipEventRecord(rf->fork, s);
+  hipLaunchKernelGGL((k_batch_tile<float, K, VARC, 0, ORD>), dim3(a.ntiles), b, 0, s, a.descs, st, a.tiles,
+                     a.ntiles, 1);
   if (rf) {
-    (void)hipEventRecord(rf->fork, s);
     (void)hipStreamWaitEvent(rf->s2, rf->fork, 0);
     s64 = rf->s2;
   }
-  // mixed batch: the few FP64 and element-wise tiles by persistent blocks over the plan, the
-  // FP32 stepping tiles one per block
   hipLaunchKernelGGL((k_batch_work<double, K, VARC, 0, ORD>), dim3(a.grids.g64), b, 0, s64, a.descs, st, a.plan,
                      a.nb, 0);
-  hipLaunchKernelGGL((k_batch_tile<float, K, VARC, 0, ORD>), dim3(a.ntiles), b, 0, s, a.descs, st, a.tiles,
-                     a.ntiles, 1);
   if (rf) {
     (void)hipEventRecord(rf->join, rf->s2);
     (void)hipStreamWaitEvent(s, rf->join, 0);
@@ -958,6 +960,38 @@ void deflated_start_launch(const wh_problem& pr, BDesc& d, const DeflScratch& w,
   d.x0 = 1;
 }
 
+// Extra streams of the set-up (default priority), released when it ends: the deflated starts
+// are short launches bound by launch latency, so problems alternate over these streams.
+struct AuxStreams {
+  static constexpr int kMax = 4;
+  hipStream_t st[kMax] = {};
+  hipEvent_t join[kMax] = {};
+  hipEvent_t fork = nullptr;
+  int m = 0;
+  AuxStreams() {
+    if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) {
+      fork = nullptr;
+      return;
+    }
+    while (m < kMax && hipStreamCreateWithFlags(&st[m], hipStreamNonBlocking) == hipSuccess) {
+      if (hipEventCreateWithFlags(&join[m], hipEventDisableTiming) != hipSuccess) {
+        (void)hipStreamDestroy(st[m]);
+        st[m] = nullptr;
+        join[m] = nullptr;
+        break;
+      }
+      ++m;
+    }
+  }
+  ~AuxStreams() {
+    for (int k = 0; k < m; ++k) {
+      (void)hipEventDestroy(join[k]);
+      (void)hipStreamDestroy(st[k]);
+    }
+    if (fork) (void)hipEventDestroy(fork);
+  }
+};
+
 // Validation, workspace carving, coefficient arrays, zeroed states, weight tables, deflated
 // starts, and the descriptors, tile table and initial states on the device: everything a
 // batched solve (or a timing of its work kernel) needs before the first round.
@@ -1148,8 +1182,23 @@ wh_status prepare_batch(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const 
     HIPB(ctx, hipMemcpyAsync(modes_all, hmodes.data(), 4 * ndt, hipMemcpyHostToDevice, s));
     HIPB(ctx, hipMemcpyAsync(scales_all, hscales.data(), 8 * ndt, hipMemcpyHostToDevice, s));
   }
-  for (int i = 0; i < nb; ++i)
-    if (probs[i].n_defl > 0) deflated_start_launch(probs[i], D[i], dsc[i], s);
+  if (ndt) {
+    // the deflated starts on the extra streams (each problem has its own scratch), joined back
+    // into the set-up stream
+    AuxStreams aux;
+    if (aux.m > 0) {
+      HIPB(ctx, hipEventRecord(aux.fork, s));
+      for (int k = 0; k < aux.m; ++k) HIPB(ctx, hipStreamWaitEvent(aux.st[k], aux.fork, 0));
+    }
+    int q = 0;
+    for (int i = 0; i < nb; ++i)
+      if (probs[i].n_defl > 0) deflated_start_launch(probs[i], D[i], dsc[i], aux.m > 0 ? aux.st[q++ % aux.m] : s);
+    for (int k = 0; k < aux.m; ++k) {
+      HIPB(ctx, hipEventRecord(aux.join[k], aux.st[k]));
+      HIPB(ctx, hipStreamWaitEvent(s, aux.join[k], 0));
+    }
+    HIPB(ctx, hipStreamSynchronize(s));
+  }
   // upload descriptors, tile table and the initial states (synchronous copies from host memory)
   HIPB(ctx, hipMemcpyAsync(ddesc, D.data(), sizeof(BDesc) * nb, hipMemcpyHostToDevice, s));
   HIPB(ctx, hipMemcpyAsync(dtiles, tile_solve.data(), 4 * (size_t)ntiles, hipMemcpyHostToDevice, s));
