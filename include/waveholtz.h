@@ -244,7 +244,8 @@ wh_status wh_apply_filter(wh_ctx* ctx, const wh_grid* grid, const double* c2, co
  * WH_EWORKSPACE and the size they need (2D: up to about 1024^2 cells; 3D: about 100^3).  No
  * device or pinned memory is allocated and no timing runs: the steps per launch are
  * params->k_fuse / k_shape, else the autotuner's cached choice for this grid from an earlier
- * call of another entry point, else 8 (2D) or 3 (3D) with the default block shape.  With
+ * call of another entry point, else 8 (2D) or 3 (3D) with the default block shape (fourth
+ * order: the choice wh_params.k_fuse describes).  With
  * params->c_max > 0 the call is asynchronous on the context stream and host-synchronisation
  * free; c_max = 0 reads the computed maximum of c back.  Every call on one GPU shares that
  * GPU's array and the array keeps the last call's contents: calls that overlap on one GPU

@@ -68,3 +68,20 @@ def test_noalloc_rejects_grids_beyond_its_scratch():
     with pytest.raises(wh.WaveHoltzError) as e:
         wh.apply_filter_noalloc(v, 50.0, precision="mixed")
     assert e.value.status == wh._native.WH_EWORKSPACE
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_noalloc_fourth_order_matches_workspace_filter_twice(precision):
+    # fourth order (c = 1) runs the blocked radius-2 launches in the same fixed scratch
+    import paper_2606_31842_amd as wh
+    for n, omega, k in [(150, 31.7, 4), (61, 13.2, 2)]:
+        print(f"noalloc order-4 case {precision} n={n} K={k}", flush=True)
+        v, f, _ = _inputs(n, False, seed=n + 1)
+        vd, fd = cuda(v), cuda(f)
+        ref, iref = wh.apply_filter(vd, omega, f=fd, precision=precision, k_fuse=k, order=4)
+        got, info = wh.apply_filter_noalloc(vd, omega, f=fd, precision=precision, k_fuse=k, order=4)
+        assert info["k_fuse"] == iref["k_fuse"] == k
+        r, g = host(ref), host(got)
+        diff = np.abs(g - r).max() / np.abs(r).max()
+        print(f"  max rel diff {diff:.2e} bit-identical {np.array_equal(g, r)}", flush=True)
+        assert diff <= 1e-13
