@@ -48,10 +48,15 @@ __device__ __forceinline__ int xcd_tile_b(int bid, int nb) {
   return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
+// State slot k of a problem: pair k/2, k odd W^n, k even the other member.  FP32 pairs are
+// interleaved (W at 8 bytes per node, D 4 bytes after it), so their nodes are
+// state_stride<float>() elements apart.
 template <typename T>
 __device__ __forceinline__ T* state_of(const BDesc& D, int k) {
   return sizeof(T) == 8 ? (T*)D.W[k] : (T*)D.W32[k];
 }
+template <typename T>
+constexpr int state_stride() { return sizeof(T) == 4 ? 2 : 1; }
 
 template <typename T>
 __device__ __forceinline__ const T* kap_of(const BDesc& D);
@@ -66,18 +71,20 @@ __device__ __forceinline__ const double* fs_of<double>(const BDesc& D) { return 
 template <>
 __device__ __forceinline__ const float* fs_of<float>(const BDesc& D) { return D.fs32; }
 
-// dt^2 L_h W at interior node p from state arrays (global reads); DIFF sums the
-// constant-c stencil as differences to the centre (FP32 increment form).
-template <typename T, bool VARC, bool DIFF>
+// dt^2 L_h W at interior node p from a state array whose nodes are SS elements apart
+// (global reads); DIFF sums the constant-c stencil as differences to the centre (FP32
+// increment form).
+template <typename T, bool VARC, bool DIFF, int SS>
 __device__ __forceinline__ T lap_term(const T* c, const T* kap, int64_t p, int64_t P, T A) {
-  const T cc = c[p];
+  const T cc = c[SS * p];
+  const T cw = c[SS * (p - 1)], ce = c[SS * (p + 1)], cs = c[SS * (p - P)], cn = c[SS * (p + P)];
   if (VARC) {
     const T kc = kap[p];
-    return (kc + kap[p - 1]) * (c[p - 1] - cc) + (kc + kap[p + 1]) * (c[p + 1] - cc) +
-           ((kc + kap[p - P]) * (c[p - P] - cc) + (kc + kap[p + P]) * (c[p + P] - cc));
+    return (kc + kap[p - 1]) * (cw - cc) + (kc + kap[p + 1]) * (ce - cc) +
+           ((kc + kap[p - P]) * (cs - cc) + (kc + kap[p + P]) * (cn - cc));
   }
-  if (DIFF) return A * (((c[p - 1] - cc) + (c[p + 1] - cc)) + ((c[p - P] - cc) + (c[p + P] - cc)));
-  return A * (((c[p - 1] + c[p + 1]) + (c[p - P] + c[p + P])) - T(4) * cc);
+  if (DIFF) return A * (((cw - cc) + (ce - cc)) + ((cs - cc) + (cn - cc)));
+  return A * (((cw + ce) + (cs + cn)) - T(4) * cc);
 }
 
 // Fourth-order differences (c = 1), dt^2 L_h W at interior node (i, j) as A12 (sx + sy) with
@@ -114,6 +121,7 @@ __device__ __forceinline__ void batch_tile(const BDesc* __restrict__ descs, cons
   constexpr bool INC = sizeof(T) == 4;
   static_assert(ORD == 2 || (ORD == 4 && !VARC && K % 2 == 0), "fourth order: c == 1, even K");
   constexpr int KS = ORD == 4 ? K / 2 : K;   // steps per stepping launch
+  constexpr int SS = state_stride<T>();
   const BDesc& D = descs[sid];
   const int ph = states[sid].phase;
   const int n = D.n;
@@ -182,8 +190,8 @@ __device__ __forceinline__ void batch_tile(const BDesc* __restrict__ descs, cons
           const T fsv = (T)(-(lap + D.om2dt2 * pc));
           fso[p] = fsv;
           const T w1 = T(-0.5) * fsv;
-          w0o[p] = w1;           // FP32 pair: D^{1/2} = W^1 - W^0 = W^1
-          w1o[p] = w1;
+          w0o[SS * p] = w1;           // FP32 pair: D^{1/2} = W^1 - W^0 = W^1
+          w1o[SS * p] = w1;
           D.V[p] = D.w[1] * (double)w1;
         }
         break;
@@ -225,13 +233,13 @@ __device__ __forceinline__ void batch_tile(const BDesc* __restrict__ descs, cons
         if (INC) {               // FP32 pair (W^1, D^{1/2})
           const T d = T(0.5) * lap;
           const T w1 = c + d;
-          w0o[p] = d;
-          w1o[p] = w1;
+          w0o[SS * p] = d;
+          w1o[SS * p] = w1;
           D.V[p] = D.w[0] * (src ? src[p] : 0.0) + D.w[1] * (double)w1;
         } else {
           const T w1 = c + T(0.5) * lap;
-          w0o[p] = c;
-          w1o[p] = w1;
+          w0o[SS * p] = c;
+          w1o[SS * p] = w1;
           D.V[p] = D.w[0] * (src ? src[p] : 0.0) + D.w[1] * (double)w1;
         }
       }
@@ -253,20 +261,20 @@ __device__ __forceinline__ void batch_tile(const BDesc* __restrict__ descs, cons
       TILE_FOR(p) {
         T nw;
         if (ORD == 4) {
-          const T lap = lap4_at<T>([&](int64_t q) { return cur[q]; }, p, (int)(p % P), (int)(p / P), n, P,
+          const T lap = lap4_at<T>([&](int64_t q) { return cur[SS * q]; }, p, (int)(p % P), (int)(p / P), n, P,
                                    (T)(D.a / 12.0));
           if (INC) {
-            nw = cur[p] + (prv[p] + (ph == BP_B_LAST ? lap - cn * fs[p] : lap));
+            nw = cur[SS * p] + (prv[SS * p] + (ph == BP_B_LAST ? lap - cn * fs[p] : lap));
           } else {
-            nw = (cur[p] + cur[p]) - prv[p] + lap;
+            nw = (cur[SS * p] + cur[SS * p]) - prv[SS * p] + lap;
             if (ph == BP_B_LAST) nw -= cn * fs[p];
           }
         } else if (INC) {
-          T lap = lap_term<T, VARC, true>(cur, kap, p, P, A);
+          T lap = lap_term<T, VARC, true, SS>(cur, kap, p, P, A);
           if (ph == BP_B_LAST || defect) lap -= cn * fs[p];
-          nw = cur[p] + (prv[p] + lap);
+          nw = cur[SS * p] + (prv[SS * p] + lap);
         } else {
-          nw = (cur[p] + cur[p]) - prv[p] + lap_term<T, VARC, false>(cur, kap, p, P, A);
+          nw = (cur[SS * p] + cur[SS * p]) - prv[SS * p] + lap_term<T, VARC, false, SS>(cur, kap, p, P, A);
           if (ph == BP_B_LAST || defect) nw -= cn * fs[p];
         }
         const double vf = D.V[p] + wn * (double)nw;
@@ -309,8 +317,8 @@ __device__ __forceinline__ void batch_tile(const BDesc* __restrict__ descs, cons
       const int xs = x0 + (int)threadIdx.y * batch_strip(K);
       const bool up = ((lt / D.ntx) & 1) != 0;
       if (xs <= n - 1) {
-        if constexpr (ORD == 4) march2d<T, KS, kBC, false, 2>(io, xs, y0, min(y0 + TYO, n), up);
-        else march2d<T, K, kBC, VARC>(io, xs, y0, min(y0 + TYO, n), up);
+        if constexpr (ORD == 4) march2d<T, KS, kBC, false, 2, INC>(io, xs, y0, min(y0 + TYO, n), up);
+        else march2d<T, K, kBC, VARC, 1, INC>(io, xs, y0, min(y0 + TYO, n), up);
       }
       break;
     }
@@ -793,7 +801,7 @@ struct BatchLayout {
   int ntiles = 0;
 };
 
-// per problem: 4 state arrays + V, b, r, p, q (8N each), FP32 states (4 x 4N, mixed), kap64/fs64 (8N),
+// per problem: 4 state arrays + V, b, r, p, q (8N each), FP32 state pairs (2 x 8N, mixed), kap64/fs64 (8N),
 // kap32/fs32 (4N, mixed), partials (tiles).  The weight tables (2(N_t+1) doubles per problem) sit
 // in one region after all problems.
 static size_t problem_bytes(int n, int K, bool mixed, bool varc) {
@@ -801,7 +809,7 @@ static size_t problem_bytes(int n, int K, bool mixed, bool varc) {
   size_t b = 0;
   auto add = [&](size_t x) { b += (x + 255) & ~(size_t)255; };
   for (int i = 0; i < 4; ++i) add(8 * N);
-  if (mixed) for (int i = 0; i < 4; ++i) add(4 * N);
+  if (mixed) for (int i = 0; i < 2; ++i) add(8 * N);
   for (int i = 0; i < 5; ++i) add(8 * N);
   if (varc) add(8 * N);
   add(8 * N);
@@ -1071,7 +1079,12 @@ wh_status prepare_batch(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const 
     d.om2dt2 = 4.0 * std::sin(0.5 * tps[i].omega_w * tps[i].dt) * std::sin(0.5 * tps[i].omega_w * tps[i].dt);
     for (int k = 0; k < 4; ++k) d.W[k] = take(8 * N);
     if (mixed)
-      for (int k = 0; k < 4; ++k) d.W32[k] = take(4 * N);
+      for (int k = 0; k < 2; ++k) {
+        // interleaved FP32 pair k: W^n (slot 2k+1) at 8 bytes per node, D (slot 2k) 4 after
+        char* pk = (char*)take(8 * N);
+        d.W32[2 * k + 1] = pk;
+        d.W32[2 * k] = pk + 4;
+      }
     d.V = (double*)take(8 * N);
     d.b = (double*)take(8 * N);
     d.r = (double*)take(8 * N);

@@ -79,6 +79,22 @@ __device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, in
   using u2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, off, 0, 0);
 }
+// An interleaved FP32 pair (a at off, b at off + 4) in one 8-byte access.  The loaded vector is
+// reinterpreted as a whole before its halves are taken: reading the halves of the integer
+// vector the builtin returns got compiled into a single 4-byte load whose value served as both.
+typedef float wh_float2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void buf_load_pair(__amdgpu_buffer_rsrc_t r, int off, float& a, float& b) {
+  const wh_float2v f = __builtin_bit_cast(wh_float2v, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  a = f.x;
+  b = f.y;
+}
+__device__ __forceinline__ void buf_store_pair(float a, float b, __amdgpu_buffer_rsrc_t r, int off) {
+  using u2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+  wh_float2v f;
+  f.x = a;
+  f.y = b;
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, f), r, off, 0, 0);
+}
 
 // Node arrays must hold (n+1)^2 elements of at most 2^31 bytes.
 // FULL: the launch advances K steps (Kp == K), so the output is fixed at level K and the
@@ -87,7 +103,9 @@ __device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, in
 // differences for c == 1, closed at the Dirichlet boundary by odd reflection: the neighbour
 // two points beyond the last interior point is minus that point).  Level s+1 is formed on
 // the row RAD rows behind level s, and the halo is RAD * K points on each side.
-template <typename T, int K, int C, int RAD, bool VARC, bool FORCE, bool FULL, bool UP>
+// PAIR (FP32 only): the state pair is one interleaved array, (W, D) in 8 bytes per node, at
+// cin / cout (pin and pout unused), so that each row of the state is one access per lane.
+template <typename T, int K, int C, int RAD, bool VARC, bool FORCE, bool FULL, bool UP, bool PAIR>
 __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int ys, int ye) {
   constexpr bool INC = sizeof(T) == 4;
   constexpr int H = RAD * K;                 // halo points per side, rows before and after
@@ -96,6 +114,7 @@ __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int y
   constexpr int U = RK > WR ? RK : WR;
   static_assert(U % WR == 0 && U % RK == 0, "unroll must be a multiple of the ring sizes");
   static_assert(RAD == 1 || (C == 1 && !VARC), "fourth order: one column per lane, c == 1");
+  static_assert(!PAIR || sizeof(T) == 4, "interleaved pairs are FP32");
   constexpr int PF = 2;
   constexpr int DK = INC ? RK : 1;
   constexpr int PK = INC ? 1 : (RAD == 1 ? 2 : 4);
@@ -106,8 +125,9 @@ __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int y
   const int Kp = io.Kp;
   const int lane = threadIdx.x;
   const int xb = xs - H + C * lane;
-  const __amdgpu_buffer_rsrc_t rc = buf_rsrc(io.cin, NN * TS), rp = buf_rsrc(io.pin, NN * TS);
-  const __amdgpu_buffer_rsrc_t rco = buf_rsrc(io.cout, NN * TS), rpo = buf_rsrc(io.pout, NN * TS);
+  constexpr int SB = PAIR ? 2 * TS : TS;   // bytes per node of a state array
+  const __amdgpu_buffer_rsrc_t rc = buf_rsrc(io.cin, NN * SB), rp = buf_rsrc(PAIR ? io.cin : io.pin, NN * SB);
+  const __amdgpu_buffer_rsrc_t rco = buf_rsrc(io.cout, NN * SB), rpo = buf_rsrc(PAIR ? io.cout : io.pout, NN * SB);
   const __amdgpu_buffer_rsrc_t rv = buf_rsrc(io.V, NN * 8);
   const __amdgpu_buffer_rsrc_t rk = buf_rsrc(VARC ? (const void*)io.kap : (const void*)io.cin, NN * TS);
   const __amdgpu_buffer_rsrc_t rf = buf_rsrc(FORCE ? (const void*)io.fs : (const void*)io.cin, NN * TS);
@@ -182,10 +202,14 @@ __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int y
     const bool rout = ya >= ys && ya < ye;                                      \
     _Pragma("unroll") for (int c = 0; c < C; ++c) {                             \
       const int p = ya * P + xb + c;                                            \
-      const int o = (rin && colin[c]) ? p * TS : kBufOff;                       \
-      sW[q_][c] = buf_load<T>(rc, o);                                           \
-      sP[q_][c] = buf_load<T>(rp, o);                                           \
-      if (FORCE) sF[q_][c] = buf_load<T>(rf, o);                                \
+      const bool in_ = rin && colin[c];                                         \
+      if constexpr (PAIR) {                                                     \
+        buf_load_pair(rc, in_ ? p * SB : kBufOff, sW[q_][c], sP[q_][c]);        \
+      } else {                                                                  \
+        sW[q_][c] = buf_load<T>(rc, in_ ? p * TS : kBufOff);                    \
+        sP[q_][c] = buf_load<T>(rp, in_ ? p * TS : kBufOff);                    \
+      }                                                                         \
+      if (FORCE) sF[q_][c] = buf_load<T>(rf, in_ ? p * TS : kBufOff);           \
       sV[q_][c] = buf_load<double>(rv, (rout && colout[c]) ? p * 8 : kBufOff);  \
     }                                                                           \
   }
@@ -276,8 +300,12 @@ __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int y
           if (FULL ? s == K - 1 : s + 1 == Kp) {
             // level Kp on an output row and column is written (a masked store is dropped)
             const bool ob = rowout && colout[c];
-            buf_store(nw, rco, ob ? p * TS : kBufOff);
-            buf_store(pn, rpo, ob ? p * TS : kBufOff);
+            if constexpr (PAIR) {
+              buf_store_pair(nw, pn, rco, ob ? p * SB : kBufOff);
+            } else {
+              buf_store(nw, rco, ob ? p * TS : kBufOff);
+              buf_store(pn, rpo, ob ? p * TS : kBufOff);
+            }
             buf_store(a, rv, ob ? p * 8 : kBufOff);
           }
         }
@@ -301,21 +329,21 @@ __device__ __forceinline__ void march2d_body(const MarchIO<T>& io, int xs, int y
 // opposite directions, so the halo rows two tiles share are read by both at about the same
 // time (both at the start or both at the end of their marches) and the second read finds them
 // in L2.
-template <typename T, int K, int C, int RAD, bool VARC, bool UP>
+template <typename T, int K, int C, int RAD, bool VARC, bool UP, bool PAIR>
 __device__ __forceinline__ void march2d_dir(const MarchIO<T>& io, int xs, int ys, int ye) {
   if (io.force) {
-    if (io.Kp == K) march2d_body<T, K, C, RAD, VARC, true, true, UP>(io, xs, ys, ye);
-    else march2d_body<T, K, C, RAD, VARC, true, false, UP>(io, xs, ys, ye);
+    if (io.Kp == K) march2d_body<T, K, C, RAD, VARC, true, true, UP, PAIR>(io, xs, ys, ye);
+    else march2d_body<T, K, C, RAD, VARC, true, false, UP, PAIR>(io, xs, ys, ye);
   } else {
-    if (io.Kp == K) march2d_body<T, K, C, RAD, VARC, false, true, UP>(io, xs, ys, ye);
-    else march2d_body<T, K, C, RAD, VARC, false, false, UP>(io, xs, ys, ye);
+    if (io.Kp == K) march2d_body<T, K, C, RAD, VARC, false, true, UP, PAIR>(io, xs, ys, ye);
+    else march2d_body<T, K, C, RAD, VARC, false, false, UP, PAIR>(io, xs, ys, ye);
   }
 }
 
-template <typename T, int K, int C, bool VARC, int RAD = 1>
+template <typename T, int K, int C, bool VARC, int RAD = 1, bool PAIR = false>
 __device__ __forceinline__ void march2d(const MarchIO<T>& io, int xs, int ys, int ye, bool up) {
-  if (up) march2d_dir<T, K, C, RAD, VARC, true>(io, xs, ys, ye);
-  else march2d_dir<T, K, C, RAD, VARC, false>(io, xs, ys, ye);
+  if (up) march2d_dir<T, K, C, RAD, VARC, true, PAIR>(io, xs, ys, ye);
+  else march2d_dir<T, K, C, RAD, VARC, false, PAIR>(io, xs, ys, ye);
 }
 
 }  // namespace wh

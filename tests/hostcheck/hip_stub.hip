@@ -423,7 +423,16 @@ void check_batch_item(const BDesc* descs, const BState* states, int nb, int sid,
         if (ptr) check_range(ptr, lo_i * (int64_t)esz, (hi_i + 1) * (int64_t)esz, what);
       };
       arr(d.x, 8, "x"); arr(d.b, 8, "b"); arr(d.r, 8, "r"); arr(d.p, 8, "p"); arr(d.q, 8, "q"); arr(d.V, 8, "V");
-      for (int k = 0; k < 4; ++k) arr(TS == 8 ? d.W[k] : d.W32[k], TS, "state");
+      if (TS == 8) {
+        for (int k = 0; k < 4; ++k) arr(d.W[k], 8, "state");
+      } else {
+        // interleaved FP32 pairs: slot 2k+1 starts the pair's array, slot 2k is 4 bytes further;
+        // node i of either slot is at 8 i
+        for (int k = 0; k < 2; ++k) {
+          if ((const char*)d.W32[2 * k] != (const char*)d.W32[2 * k + 1] + 4) fail("FP32 pair %d is not interleaved", k);
+          check_range(d.W32[2 * k + 1], lo_i * 8, (hi_i + 1) * 8, "state pair");
+        }
+      }
       if (VARC) arr(TS == 8 ? (const void*)d.kap64 : (const void*)d.kap32, TS, "kap");
       arr(TS == 8 ? (const void*)d.fs64 : (const void*)d.fs32, TS, "fs");
       check_range(d.partials, 8LL * lt, 8LL * (lt + 1), "partials");

@@ -179,3 +179,27 @@ def test_batched_mixed_cg_near_indefinite_problem_converges():
         assert info["status"] == 0 and info["true_rel_res"] <= 1e-8
         assert err < 2e-5
     assert infos[0]["wave_solves"] > infos[0]["outer"] + 1    # it did run in FP64
+
+
+@pytest.mark.parametrize("k_fuse", [8, 4])
+def test_batched_mixed_operator_needs_no_fp64_fallback(k_fuse):
+    """Grids of two and more tile columns: the FP32 operator of the mixed batch must be accurate
+    enough that no problem falls back to FP64 stepping (FP64 wave solves = the right-hand side
+    plus one per residual replacement), and the mixed DCG takes about the iterations of the FP64
+    one.  (A wrong FP32 operator still converges through the fallback; this catches it.)"""
+    print(f"case batched mixed operator K={k_fuse}", flush=True)
+    import paper_2606_31842_amd as wh
+    probs = _batch(sizes=(130, 200, 260), per=2, seed=33, omega=(10.0, 30.0))
+    batch = [(cuda(f), om) for (n, om, f) in probs]
+    nds = [int(1.5 * om) for (n, om, f) in probs]
+    kw = dict(solver="dcg", n_defl=nds, k_fuse=k_fuse, tol=1e-8, max_iters=20000)
+    um, im = wh.solve_batched(batch, precision="mixed", **kw)
+    u64, i64 = wh.solve_batched(batch, precision="f64", **kw)
+    for (n, om, f), u, a, b in zip(probs, um, im, i64):
+        U = disc.direct_solve_dst(2, n, om, f)
+        e = rel(host(u), U)
+        print(f"n={n} omega={om:.3f} mixed iters={a['iters']} fp64 solves={a['wave_solves']} outer={a['outer']} "
+              f"| f64 iters={b['iters']} err={e:.2e}", flush=True)
+        assert a["status"] == 0 and e < 2e-5
+        assert a["wave_solves"] == a["outer"] + 1, a
+        assert a["iters"] <= 1.25 * b["iters"] + 5
