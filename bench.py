@@ -41,8 +41,8 @@ B_FUSED_F32 = 32.0
 # HBM KiB per dispatch (FETCH_SIZE, WRITE_SIZE) of the tagged batch work kernel on the config-4
 # batch, from the two counter passes in profiles/hbm_traffic_batch_tile_cfg4.md, with the copy-kernel
 # scale factors; valid only for the kernel sources it was taken on (sha1 over the three files)
-BATCH_TRAFFIC = {"src_sha1": "453dce2f5f6f879970d302b3464ed1549f8466d7", "fetch_scale": 2.0, "write_scale": 1.0,
-                 "kib": [734884.6, 1447137.5]}
+BATCH_TRAFFIC = {"src_sha1": "b5f7c138f08eb9721adee5bf51778f0c29dbf0b3", "fetch_scale": 2.0, "write_scale": 1.0,
+                 "kib": [732972.1, 1417027.8]}
 # HBM KiB per dispatch (FETCH_SIZE, WRITE_SIZE) of every FP32 temporally blocked kernel
 # variant "K,R,NW" on this grid, from the two rocprofv3 counter passes summarised in
 # profiles/hbm_traffic_fused2d_f32_2d1024.md (scaled by FETCH x 2.000, WRITE x 1.000 from a

@@ -19,9 +19,9 @@ struct BDesc {
   double a, tol, itol, om2dt2;   // om2dt2 = (omega dt)^2 of the fixed point
   double *x, *b, *r, *p, *q, *V;
   void* W[4];                 // FP64 (prev, cur) pairs 0 and 1; 8 bytes per node each
-  void* W32[4];               // FP32 pairs (mixed only), each one interleaved array of
-                              // (W^n, D) at 8 bytes per node: slot 2k+1 is its start, slot 2k
-                              // is 4 bytes further
+  void* W32[4];               // FP32 pairs (mixed only): four arrays, or (batches without
+                              // forced FP32 steps) each pair one interleaved array of (W^n, D)
+                              // at 8 bytes per node, slot 2k+1 its start, slot 2k 4 bytes further
   const double* kap64;
   const double* fs64;
   const float* kap32;

@@ -48,15 +48,13 @@ __device__ __forceinline__ int xcd_tile_b(int bid, int nb) {
   return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
-// State slot k of a problem: pair k/2, k odd W^n, k even the other member.  FP32 pairs are
-// interleaved (W at 8 bytes per node, D 4 bytes after it), so their nodes are
-// state_stride<float>() elements apart.
+// State slot k of a problem: pair k/2, k odd W^n, k even the other member.  Interleaved FP32
+// pairs (W at 8 bytes per node, D 4 bytes after it) have their nodes 2 elements apart.
 template <typename T>
 __device__ __forceinline__ T* state_of(const BDesc& D, int k) {
   return sizeof(T) == 8 ? (T*)D.W[k] : (T*)D.W32[k];
 }
-template <typename T>
-constexpr int state_stride() { return sizeof(T) == 4 ? 2 : 1; }
+
 
 template <typename T>
 __device__ __forceinline__ const T* kap_of(const BDesc& D);
@@ -109,8 +107,9 @@ __device__ __forceinline__ T lap4_at(Get get, int64_t p, int i, int j, int n, in
 // The work of one tile of problem sid in its current phase (lt: the tile within the problem).
 // ORD: 2 (the five-point Laplacian, variable c allowed) or 4 (fourth-order differences for
 // c == 1; the stepping launches advance K/2 steps, so that the halo, 2 points per step, and with
-// it the tile geometry stay those of K second-order steps).
-template <typename T, int K, bool VARC, int ORD = 2>
+// it the tile geometry stay those of K second-order steps).  PAIR: the batch keeps each FP32
+// state pair in one interleaved array (batches without forced FP32 steps; see prepare_batch).
+template <typename T, int K, bool VARC, int ORD = 2, bool PAIR = false>
 __device__ __forceinline__ void batch_tile(const BDesc* __restrict__ descs, const BState* __restrict__ states,
                                            int sid, int lt) {
   constexpr int TXO = batch_txo(K);
@@ -121,7 +120,8 @@ __device__ __forceinline__ void batch_tile(const BDesc* __restrict__ descs, cons
   constexpr bool INC = sizeof(T) == 4;
   static_assert(ORD == 2 || (ORD == 4 && !VARC && K % 2 == 0), "fourth order: c == 1, even K");
   constexpr int KS = ORD == 4 ? K / 2 : K;   // steps per stepping launch
-  constexpr int SS = state_stride<T>();
+  constexpr bool PR = PAIR && INC;             // interleaved FP32 pairs
+  constexpr int SS = PR ? 2 : 1;
   const BDesc& D = descs[sid];
   const int ph = states[sid].phase;
   const int n = D.n;
@@ -317,8 +317,8 @@ __device__ __forceinline__ void batch_tile(const BDesc* __restrict__ descs, cons
       const int xs = x0 + (int)threadIdx.y * batch_strip(K);
       const bool up = ((lt / D.ntx) & 1) != 0;
       if (xs <= n - 1) {
-        if constexpr (ORD == 4) march2d<T, KS, kBC, false, 2, INC>(io, xs, y0, min(y0 + TYO, n), up);
-        else march2d<T, K, kBC, VARC, 1, INC>(io, xs, y0, min(y0 + TYO, n), up);
+        if constexpr (ORD == 4) march2d<T, KS, kBC, false, 2, PR>(io, xs, y0, min(y0 + TYO, n), up);
+        else march2d<T, K, kBC, VARC, 1, PR>(io, xs, y0, min(y0 + TYO, n), up);
       }
       break;
     }
@@ -407,7 +407,7 @@ void k_batch_work(const BDesc* __restrict__ descs,
 // return at once.  Used for the class that holds most of the tiles (the FP32 stepping of a
 // mixed batch, everything in an FP64 batch), where the hardware's block dispatch balances the
 // work best.
-template <typename T, int K, bool VARC, int TAG = 0, int ORD = 2>
+template <typename T, int K, bool VARC, int TAG = 0, int ORD = 2, bool PAIR = false>
 __global__ __launch_bounds__(64 * kBW, (batch_waves_per_eu<T, K, VARC, ORD>()))
 void k_batch_tile(const BDesc* __restrict__ descs, const BState* __restrict__ states,
                   const int* __restrict__ tile_solve, int ntiles, int want) {
@@ -420,7 +420,7 @@ void k_batch_tile(const BDesc* __restrict__ descs, const BState* __restrict__ st
   const bool stepping = ph != BP_INIT && ph != BP_UPD1 && ph != BP_UPD2;
   const int cls = (stepping && phase_prec(ph, D.mixed && !S.force64) == 1) ? 1 : 0;
   if (cls != want) return;
-  batch_tile<T, K, VARC, ORD>(descs, states, sid, gt - D.tile0);
+  batch_tile<T, K, VARC, ORD, PAIR>(descs, states, sid, gt - D.tile0);
 }
 
 // The plan of the next round from the problems' phases (one block; problems in index order,
@@ -717,6 +717,7 @@ struct RoundArgs {
   bool mixed;
   BatchGrids grids;
   bool ord4;   // fourth-order differences (c == 1): K/2 steps per stepping launch
+  bool pair;   // interleaved FP32 state pairs
 };
 
 template <int K, bool VARC, int ORD>
@@ -735,8 +736,12 @@ static void launch_round_ko(const RoundArgs& a, hipStream_t s, const RoundFork* 
   // about 9 us later).
   hipStream_t s64 = s;
   if (rf) (void)hipEventRecord(rf->fork, s);
-  hipLaunchKernelGGL((k_batch_tile<float, K, VARC, 0, ORD>), dim3(a.ntiles), b, 0, s, a.descs, st, a.tiles,
-                     a.ntiles, 1);
+  if (!VARC && a.pair)
+    hipLaunchKernelGGL((k_batch_tile<float, K, VARC, 0, ORD, true>), dim3(a.ntiles), b, 0, s, a.descs, st, a.tiles,
+                       a.ntiles, 1);
+  else
+    hipLaunchKernelGGL((k_batch_tile<float, K, VARC, 0, ORD>), dim3(a.ntiles), b, 0, s, a.descs, st, a.tiles,
+                       a.ntiles, 1);
   if (rf) {
     (void)hipStreamWaitEvent(rf->s2, rf->fork, 0);
     s64 = rf->s2;
@@ -776,8 +781,12 @@ static void launch_round(int K, bool varc, const RoundArgs& a, hipStream_t s, co
 // The FP32 stepping kernel alone, under its measurement tag (wh_time_batch_kernel).
 template <int K, bool VARC>
 static void launch_work_tagged(const RoundArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_batch_tile<float, K, VARC, 1>), dim3(a.ntiles), dim3(64, kBW), 0, s, a.descs,
-                     (const BState*)a.states, a.tiles, a.ntiles, 1);
+  if (!VARC && a.pair)
+    hipLaunchKernelGGL((k_batch_tile<float, K, VARC, 1, 2, true>), dim3(a.ntiles), dim3(64, kBW), 0, s, a.descs,
+                       (const BState*)a.states, a.tiles, a.ntiles, 1);
+  else
+    hipLaunchKernelGGL((k_batch_tile<float, K, VARC, 1>), dim3(a.ntiles), dim3(64, kBW), 0, s, a.descs,
+                       (const BState*)a.states, a.tiles, a.ntiles, 1);
 }
 
 static void launch_work_timing(int K, bool varc, const RoundArgs& a, hipStream_t s) {
@@ -801,7 +810,7 @@ struct BatchLayout {
   int ntiles = 0;
 };
 
-// per problem: 4 state arrays + V, b, r, p, q (8N each), FP32 state pairs (2 x 8N, mixed), kap64/fs64 (8N),
+// per problem: 4 state arrays + V, b, r, p, q (8N each), FP32 states (4 x 4N or 2 x 8N, mixed), kap64/fs64 (8N),
 // kap32/fs32 (4N, mixed), partials (tiles).  The weight tables (2(N_t+1) doubles per problem) sit
 // in one region after all problems.
 static size_t problem_bytes(int n, int K, bool mixed, bool varc) {
@@ -809,7 +818,7 @@ static size_t problem_bytes(int n, int K, bool mixed, bool varc) {
   size_t b = 0;
   auto add = [&](size_t x) { b += (x + 255) & ~(size_t)255; };
   for (int i = 0; i < 4; ++i) add(8 * N);
-  if (mixed) for (int i = 0; i < 2; ++i) add(8 * N);
+  if (mixed) for (int i = 0; i < 4; ++i) add(4 * N);   // covers 2 x 8N as well
   for (int i = 0; i < 5; ++i) add(8 * N);
   if (varc) add(8 * N);
   add(8 * N);
@@ -1007,7 +1016,7 @@ struct BatchSetup {
   std::vector<TimeParams> tps;
   std::vector<BDesc> D;
   int ntiles = 0, K = 4;
-  bool mixed = false, varc = false, ord4 = false;
+  bool mixed = false, varc = false, ord4 = false, pair = false;
   BDesc* ddesc = nullptr;
   BState* dstate = nullptr;
   int* dplan = nullptr;      // the two class plans of the next round (plan_stride(nb) ints each)
@@ -1046,6 +1055,18 @@ wh_status prepare_batch(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const 
     if (st != WH_OK) return st;
   }
   const int K = batch_K(params);
+  // FP32 A-apply: the defect form for undeflated problems (near-resonant modes present), direct
+  // stepping when the near-resonant modes are deflated (second order only, as in the single
+  // solves).  A batch whose FP32 steps are never forced keeps each FP32 state pair in one
+  // interleaved array (one 8-byte access per node and row: 724 -> 696 us per launch on the
+  // 256-problem batch); with forced steps the interleaved form ran slower (1013 -> 1118 us),
+  // so such batches keep two arrays.
+  auto defect_of = [&](int i) {
+    return probs[i].grid.order == 2 &&
+           (params->mixed_form == 0 || (params->mixed_form < 0 && probs[i].n_defl == 0));
+  };
+  bool pair = mixed && !varc;
+  for (int i = 0; i < nb && pair; ++i) pair = !defect_of(i);
   // pass 1: carve the workspace (no device writes until the layout is known to fit)
   std::vector<BDesc> D(nb);
   std::vector<int> tile_solve;
@@ -1071,20 +1092,19 @@ wh_status prepare_batch(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const 
     // solve per problem against 1e-3 (256-problem batch: 512 instead of 768, same iterations)
     d.itol = (params->inner_tol > 0 && params->inner_tol < 1) ? params->inner_tol
                                                               : (probs[i].n_defl > 0 ? 1e-4 : 0.1);
-    // FP32 A-apply: the defect form for undeflated problems (near-resonant modes present),
-    // direct stepping when the near-resonant modes are deflated
-    // (second order only, as in the single solves)
-    d.defect = probs[i].grid.order == 2 &&
-               (params->mixed_form == 0 || (params->mixed_form < 0 && probs[i].n_defl == 0));
+    d.defect = defect_of(i);
     d.om2dt2 = 4.0 * std::sin(0.5 * tps[i].omega_w * tps[i].dt) * std::sin(0.5 * tps[i].omega_w * tps[i].dt);
     for (int k = 0; k < 4; ++k) d.W[k] = take(8 * N);
-    if (mixed)
+    if (mixed && pair) {
       for (int k = 0; k < 2; ++k) {
         // interleaved FP32 pair k: W^n (slot 2k+1) at 8 bytes per node, D (slot 2k) 4 after
         char* pk = (char*)take(8 * N);
         d.W32[2 * k + 1] = pk;
         d.W32[2 * k] = pk + 4;
       }
+    } else if (mixed) {
+      for (int k = 0; k < 4; ++k) d.W32[k] = take(4 * N);
+    }
     d.V = (double*)take(8 * N);
     d.b = (double*)take(8 * N);
     d.r = (double*)take(8 * N);
@@ -1230,6 +1250,7 @@ wh_status prepare_batch(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const 
   B.mixed = mixed;
   B.varc = varc;
   B.ord4 = probs[0].grid.order == 4;
+  B.pair = pair;
   B.ddesc = ddesc;
   B.dstate = dstate;
   B.dplan = dplan;
@@ -1319,7 +1340,7 @@ wh_status wh_solve_batched(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
       for (int g = 0; g < G; ++g)
-        launch_round(K, varc, RoundArgs{ddesc, dstate, dplan, B.dtiles, B.ntiles, nb, mixed, B.grids, B.ord4}, cs,
+        launch_round(K, varc, RoundArgs{ddesc, dstate, dplan, B.dtiles, B.ntiles, nb, mixed, B.grids, B.ord4, B.pair}, cs,
                      use_fork ? &rf : nullptr);
       hipLaunchKernelGGL(k_batch_count, dim3(1), dim3(256), 0, cs, (const BState*)dstate, nb, dcount[gi]);
       e = hipStreamEndCapture(cs, &graph[gi]);
@@ -1448,7 +1469,7 @@ wh_status wh_time_batch_kernel(wh_ctx* ctx, int32_t nb, const wh_problem* probs,
     st.step = 1;
   }
   HIPB(ctx, hipMemcpyAsync(B.dstate, S.data(), sizeof(BState) * nb, hipMemcpyHostToDevice, s));
-  const RoundArgs ra{B.ddesc, B.dstate, B.dplan, B.dtiles, B.ntiles, nb, true, B.grids, false};
+  const RoundArgs ra{B.ddesc, B.dstate, B.dplan, B.dtiles, B.ntiles, nb, true, B.grids, false, B.pair};
   auto one = [&]() { launch_work_timing(B.K, B.varc, ra, s); };
   HIPB(ctx, hipStreamSynchronize(s));
   one();

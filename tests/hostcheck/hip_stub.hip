@@ -426,11 +426,15 @@ void check_batch_item(const BDesc* descs, const BState* states, int nb, int sid,
       if (TS == 8) {
         for (int k = 0; k < 4; ++k) arr(d.W[k], 8, "state");
       } else {
-        // interleaved FP32 pairs: slot 2k+1 starts the pair's array, slot 2k is 4 bytes further;
-        // node i of either slot is at 8 i
+        // FP32 pairs: interleaved (slot 2k+1 starts the pair's array, slot 2k is 4 bytes further,
+        // node i of either slot at 8 i; only where no FP32 step is forced) or four arrays
         for (int k = 0; k < 2; ++k) {
-          if ((const char*)d.W32[2 * k] != (const char*)d.W32[2 * k + 1] + 4) fail("FP32 pair %d is not interleaved", k);
-          check_range(d.W32[2 * k + 1], lo_i * 8, (hi_i + 1) * 8, "state pair");
+          if ((const char*)d.W32[2 * k] == (const char*)d.W32[2 * k + 1] + 4) {
+            if (d.defect) fail("FP32 pair %d interleaved in a batch with forced steps", k);
+            check_range(d.W32[2 * k + 1], lo_i * 8, (hi_i + 1) * 8, "state pair");
+          } else {
+            arr(d.W32[2 * k], 4, "state"); arr(d.W32[2 * k + 1], 4, "state");
+          }
         }
       }
       if (VARC) arr(TS == 8 ? (const void*)d.kap64 : (const void*)d.kap32, TS, "kap");
