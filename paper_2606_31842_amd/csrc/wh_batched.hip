@@ -15,20 +15,25 @@
 //   R_FIRST -> R_STEP* -> R_LAST         r = b - A x, partial r.r              (FP64)
 //   UPD2                                 p = r + beta p            -> A_FIRST
 //
-// One round = FP64 work kernel + FP32 work kernel + control kernel.  A work kernel
-// covers every tile of every problem (a static block -> (problem, tile) table laid
-// out so each XCD gets a contiguous run of tiles); a block does the work of its
-// problem's current phase on its tile, or returns.  The control kernel (one block
-// per problem) reduces the tile partial sums in a fixed order, updates alpha/beta
-// and the convergence state and advances the phase.  Rounds contain no host
-// decisions, so the host captures several of them in one hipGraph and replays it,
-// reading back one counter of unfinished problems per replay.
+// One round = the FP32 work kernel (one block per tile of every problem, through a static
+// block -> (problem, tile) table laid out so each XCD gets a contiguous run of tiles), beside
+// it on a second stream the FP64 work kernel (persistent blocks over the round's plan of FP64
+// and element-wise tiles), then the control kernel and, in mixed batches, the plan kernel.  A
+// block does the work of its problem's current phase on its tile, or returns.  The control
+// kernel (one block per problem) reduces the tile partial sums in a fixed order, updates
+// alpha/beta and the convergence state and advances the phase.  Rounds contain no host
+// decisions, so the host captures several of them in one hipGraph and replays it, reading
+// back one counter of unfinished problems per replay.
+//
+// In mixed batches whose FP32 steps are never forced (no defect form), each FP32 state pair
+// is one interleaved array, (W, D) in 8 bytes per node; otherwise two arrays.
 //
 // Deflated problems (c = 1, n_defl sine modes W nearest omega^2) start from
 // x_0 = W (W^T A W)^{-1} W^T b.  With exact eigenvectors this is the projection of the
 // solution onto span W, W^T u = (omega^2 - lambda^2)^{-1} W^T f, and A x_0 =
-// W diag(mu) W^T u: the host computes both from f before the batch (x_0 into x,
-// A x_0 into q) and INIT forms r_0 = b - A x_0.  r_0 is orthogonal to W, and CG
+// W diag(mu) W^T u: the set-up computes both from f before the batch (the host selects the
+// modes and scales, the device projects and combines; x_0 into x, A x_0 into q) and INIT
+// forms r_0 = b - A x_0.  r_0 is orthogonal to W, and CG
 // continues without re-projection (Algorithm 3 with exact eigenvectors).
 #include <algorithm>
 #include <chrono>
