@@ -41,7 +41,7 @@ B_FUSED_F32 = 32.0
 # HBM KiB per dispatch (FETCH_SIZE, WRITE_SIZE) of the tagged batch work kernel on the config-4
 # batch, from the two counter passes in profiles/hbm_traffic_batch_tile_cfg4.md, with the copy-kernel
 # scale factors; valid only for the kernel sources it was taken on (sha1 over the three files)
-BATCH_TRAFFIC = {"src_sha1": "b9fee11a467b7c951f0af385e5c6c855c840a147", "fetch_scale": 2.0, "write_scale": 1.0,
+BATCH_TRAFFIC = {"src_sha1": "9dbd7bea7a323d2d01d727de27ce8102b9df8477", "fetch_scale": 2.0, "write_scale": 1.0,
                  "kib": [732972.1, 1417027.8]}
 # HBM KiB per dispatch (FETCH_SIZE, WRITE_SIZE) of every FP32 temporally blocked kernel
 # variant "K,R,NW" on this grid, from the two rocprofv3 counter passes summarised in

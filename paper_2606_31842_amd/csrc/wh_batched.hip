@@ -17,8 +17,8 @@
 //
 // One round = the FP32 work kernel (one block per tile of every problem, through a static
 // block -> (problem, tile) table laid out so each XCD gets a contiguous run of tiles), beside
-// it on a second stream the FP64 work kernel (persistent blocks over the round's plan of FP64
-// and element-wise tiles), then the control kernel and, in mixed batches, the plan kernel.  A
+// it on a second stream the plan kernel and the FP64 work kernel (persistent blocks over the
+// round's plan of FP64 and element-wise tiles), then the control kernel.  A
 // block does the work of its problem's current phase on its tile, or returns.  The control
 // kernel (one block per problem) reduces the tile partial sums in a fixed order, updates
 // alpha/beta and the convergence state and advances the phase.  Rounds contain no host
@@ -735,10 +735,11 @@ static void launch_round_ko(const RoundArgs& a, hipStream_t s, const RoundFork* 
                        a.ntiles, 0);
     return;
   }
-  // mixed batch: the FP32 stepping tiles one per block, and beside them the few FP64 and
-  // element-wise tiles by persistent blocks over the plan.  The FP32 kernel, which holds most
-  // rounds' critical path, is issued first (in a captured graph the kernel issued second starts
-  // about 9 us later).
+  // mixed batch: the FP32 stepping tiles one per block, and beside them the plan of the round
+  // and the few FP64 and element-wise tiles by persistent blocks over it.  The FP32 kernel,
+  // which holds most rounds' critical path, is issued first (in a captured graph the kernel
+  // issued second starts about 9 us later) and does not wait for the plan (it finds its tiles
+  // through the static table; plan and FP32 kernel only read the states).
   hipStream_t s64 = s;
   if (rf) (void)hipEventRecord(rf->fork, s);
   if (!VARC && a.pair)
@@ -751,6 +752,7 @@ static void launch_round_ko(const RoundArgs& a, hipStream_t s, const RoundFork* 
     (void)hipStreamWaitEvent(rf->s2, rf->fork, 0);
     s64 = rf->s2;
   }
+  hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(256), 0, s64, a.descs, st, a.nb, a.plan);
   hipLaunchKernelGGL((k_batch_work<double, K, VARC, 0, ORD>), dim3(a.grids.g64), b, 0, s64, a.descs, st, a.plan,
                      a.nb, 0);
   if (rf) {
@@ -770,8 +772,8 @@ static void launch_round_k(const RoundArgs& a, hipStream_t s, const RoundFork* r
 // Time steps of one stepping launch.
 static int batch_steps(int K, bool ord4) { return ord4 ? K / 2 : K; }
 
-// One round: the work kernels, the control kernel (phases advance), and in mixed batches the
-// plan of the next round.
+// One round: the work kernels (in mixed batches after the round's plan, which runs beside the
+// FP32 kernel) and the control kernel (phases advance).
 static void launch_round(int K, bool varc, const RoundArgs& a, hipStream_t s, const RoundFork* rf = nullptr) {
   switch (K) {
     case 2: varc ? launch_round_k<2, true>(a, s, rf) : launch_round_k<2, false>(a, s, rf); break;
@@ -779,8 +781,6 @@ static void launch_round(int K, bool varc, const RoundArgs& a, hipStream_t s, co
     default: varc ? launch_round_k<8, true>(a, s, rf) : launch_round_k<8, false>(a, s, rf); break;
   }
   hipLaunchKernelGGL(k_batch_control, dim3(a.nb), dim3(256), 0, s, a.descs, a.states, batch_steps(K, a.ord4));
-  if (a.mixed)
-    hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(256), 0, s, a.descs, (const BState*)a.states, a.nb, a.plan);
 }
 
 // The FP32 stepping kernel alone, under its measurement tag (wh_time_batch_kernel).
