@@ -1093,8 +1093,9 @@ wh_status prepare_batch(wh_ctx* ctx, int32_t nb, const wh_problem* probs, const 
     const double h = 1.0 / n;
     d.a = tps[i].dt * tps[i].dt / (h * h);
     d.tol = params->tol;
-    // deflated problems tolerate long FP32 stretches: 1e-4 per replacement saves one FP64 wave
-    // solve per problem against 1e-3 (256-problem batch: 512 instead of 768, same iterations)
+    // deflated problems tolerate long FP32 stretches: 1e-4 per replacement needs 2 residual
+    // replacements (FP64 wave solves) per problem where 1e-3 needs 3 (256-problem batch: 512
+    // instead of 768 besides the 256 right-hand sides, same iterations)
     d.itol = (params->inner_tol > 0 && params->inner_tol < 1) ? params->inner_tol
                                                               : (probs[i].n_defl > 0 ? 1e-4 : 0.1);
     d.defect = defect_of(i);
