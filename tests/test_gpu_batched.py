@@ -181,7 +181,7 @@ def test_batched_mixed_cg_near_indefinite_problem_converges():
     assert infos[0]["wave_solves"] > infos[0]["outer"] + 1    # it did run in FP64
 
 
-@pytest.mark.parametrize("k_fuse", [8, 4])
+@pytest.mark.parametrize("k_fuse", [8, 4, 2])
 def test_batched_mixed_operator_needs_no_fp64_fallback(k_fuse):
     """Grids of two and more tile columns: the FP32 operator of the mixed batch must be accurate
     enough that no problem falls back to FP64 stepping (FP64 wave solves = the right-hand side
@@ -191,7 +191,7 @@ def test_batched_mixed_operator_needs_no_fp64_fallback(k_fuse):
     import paper_2606_31842_amd as wh
     probs = _batch(sizes=(130, 200, 260), per=2, seed=33, omega=(10.0, 30.0))
     batch = [(cuda(f), om) for (n, om, f) in probs]
-    nds = [int(1.5 * om) for (n, om, f) in probs]
+    nds = [int(1.5 * om) for (n, om, f) in probs]   # every problem deflated: interleaved FP32 pairs
     kw = dict(solver="dcg", n_defl=nds, k_fuse=k_fuse, tol=1e-8, max_iters=20000)
     um, im = wh.solve_batched(batch, precision="mixed", **kw)
     u64, i64 = wh.solve_batched(batch, precision="f64", **kw)
