@@ -176,6 +176,24 @@ int fused2d_default_shape(bool f32, int n);
 void fused2d_shape_dims(bool f32, int k, int shape, int* rows, int* waves);
 void launch_fused2d(bool f32, bool varc, bool force, const FusedArgs& a, hipStream_t s);
 
+// Kernel arguments of the K-step 3D launch (wh_fused3d.hip): the state pair in and out, V, the
+// coefficients, the tile grid (gx x gy x gz blocks, zs output planes per block) and the weights
+// and cosines of the launch's steps.
+struct Fused3Dev {
+  const void* cur;
+  const void* prev;
+  void* cur_out;
+  void* prev_out;
+  double* V;
+  const void* kap;
+  const void* fs;
+  double a;
+  int n;
+  int gx, gy, gz, zs;
+  double w[8];    // w_{n+1..n+K}
+  double cs[8];   // cos(omega_w t^{n..n+K-1})
+};
+
 // K (2 or 4) fourth-order steps of a 2D single solve (c == 1) by the row-marching pipeline
 // (wh_march4.hip).  The state pair is read from (cur, prev) and written to (cur_out, prev_out)
 // with the conventions of the other stepping kernels (FP32: W, D; FP64: W^n, W^{n-1}).

@@ -25,21 +25,6 @@
 
 namespace wh {
 
-struct Fused3Dev {
-  const void* cur;
-  const void* prev;
-  void* cur_out;
-  void* prev_out;
-  double* V;
-  const void* kap;
-  const void* fs;
-  double a;
-  int n;
-  int gx, gy, gz, zs;
-  double w[8];    // w_{n+1..n+K}
-  double cs[8];   // cos(omega_w t^{n..n+K-1})
-};
-
 __device__ __forceinline__ int xcd_tile3(int bid, int nb) {
   const int xcd = bid & 7, idx = bid >> 3;
   const int q = nb >> 3, r = nb & 7;

@@ -264,6 +264,53 @@ void model_step2d(const std::vector<std::string>& t, dim3 g, dim3 b, void** args
   for (Span* s : {&cur, &prv, &kap, &fs, &V, &x, &out, &cn, &part}) s->check();
 }
 
+// 3D streaming step: (64, 4) threads per block over (x, y), 8 planes per thread in z
+void model_step3d(const std::vector<std::string>& t, dim3 g, dim3 b, void** args) {
+  const size_t TS = tsize(t, 0);
+  const int MODE = ti(t, 1), VARC = ti(t, 2), FORCE = ti(t, 3);
+  const bool INC = TS == 4;
+  const StepArgs a = arg<StepArgs>(args, 0);
+  const int n = a.n;
+  const int64_t P = (int64_t)n + 1, P2 = P * P;
+  constexpr int RB = 8;
+  if (b.x != 64 || b.y != 4) fail("block shape");
+  if ((int)g.x != (n - 1 + 63) / 64 || (int)g.y != (n - 1 + 3) / 4 || (int)g.z != (n - 1 + RB - 1) / RB)
+    fail("grid (%u,%u,%u) for n = %d", g.x, g.y, g.z, n);
+  Span cur{a.cur, TS}, prv{a.prev, TS}, kap{a.kap, TS}, fs{a.fs, TS}, V{a.V, 8}, x{a.x, 8}, out{a.out, 8};
+  Span cn{a.cur_next, TS}, part{a.partials, 8};
+  cur.what = "cur"; prv.what = "prev"; kap.what = "kap"; fs.what = "fs"; V.what = "V"; x.what = "x";
+  out.what = "out"; cn.what = "cur_next"; part.what = "partials";
+  for (unsigned bz = 0; bz < g.z; ++bz)
+    for (unsigned by = 0; by < g.y; ++by)
+      for (unsigned bx = 0; bx < g.x; ++bx) {
+        for (int ty = 0; ty < 4; ++ty)
+          for (int tx = 0; tx < 64; ++tx) {
+            const int i = 1 + bx * 64 + tx, j = 1 + by * 4 + ty, k0 = 1 + bz * RB;
+            if (!(i < n && j < n && k0 < n)) continue;
+            const int kend = std::min(k0 + RB, n);
+            for (int k = k0; k < kend; ++k) {
+              const int64_t p = (int64_t)k * P2 + (int64_t)j * P + i;
+              for (int64_t o : {-P2, -P, (int64_t)-1, (int64_t)0, (int64_t)1, P, P2}) {
+                cur.touch(p + o);
+                if (VARC) kap.touch(p + o);
+              }
+              prv.touch(p);
+              if (FORCE) fs.touch(p);
+              V.touch(p);
+              if (MODE == M_MID) {
+                if (INC) cn.touch(p);
+              } else if (MODE == M_LAST_AQ || MODE == M_LAST_EQ || MODE == M_LAST_FPI) {
+                x.touch(p); out.touch(p);
+              } else if (MODE != M_LAST_V) {
+                fail("mode %d", MODE);
+              }
+            }
+          }
+        if (MODE == M_LAST_AQ || MODE == M_LAST_FPI || MODE == M_LAST_EQ) part.touch((bz * g.y + by) * g.x + bx);
+      }
+  for (Span* sp : {&cur, &prv, &kap, &fs, &V, &x, &out, &cn, &part}) sp->check();
+}
+
 void model_first(const std::vector<std::string>& t, dim3 g, dim3, void** args) {
   const size_t TS = tsize(t, 0);
   const int DIM = ti(t, 1), VARC = ti(t, 2), FORCE = ti(t, 3);
@@ -666,6 +713,29 @@ void model_step4(const std::vector<std::string>& t, dim3 g, dim3 b, void** args)
   }
 }
 
+// K-step 3D launch: a block of NW wavefronts owns a 64 x NW R column tile of a z-run of zs planes
+// with a K-point halo; every access is guarded to the (n+1)^3 grid, so the model checks the tile
+// grid against the Fused3Dev fields and that each array holds the grid.
+void model_fused3d(const std::vector<std::string>& t, dim3 g, dim3 b, void** args) {
+  const size_t TS = tsize(t, 0);
+  const int K = ti(t, 1), R = ti(t, 2), NW = ti(t, 3), VARC = ti(t, 4), FORCE = ti(t, 5);
+  const Fused3Dev d = arg<Fused3Dev>(args, 0);
+  const int n = d.n;
+  if ((int)b.x != 64 || (int)b.y != NW) fail("block (%u,%u) for %d waves", b.x, b.y, NW);
+  if (K < 2 || K > 3) fail("K = %d", K);
+  const int txo = 64 - 2 * K, tyo = NW * R - 2 * K;
+  if (d.gx != (n - 1 + txo - 1) / txo || d.gy != (n - 1 + tyo - 1) / tyo) fail("tile grid %d x %d", d.gx, d.gy);
+  if (d.zs < 1 || d.gz != (n - 1 + d.zs - 1) / d.zs) fail("z-runs: %d of %d planes", d.gz, d.zs);
+  if ((int64_t)g.x != (int64_t)d.gx * d.gy * d.gz || g.y != 1) fail("grid %u for %d tiles", g.x, d.gx * d.gy * d.gz);
+  const int64_t P = (int64_t)n + 1, N = P * P * P;
+  vec(d.cur, N, TS, "cur"); vec(d.prev, N, TS, "prev");
+  vec(d.cur_out, N, TS, "cur_out"); vec(d.prev_out, N, TS, "prev_out");
+  vec(d.V, N, 8, "V");
+  if (VARC) vec(d.kap, N, TS, "kap");
+  if (FORCE) vec(d.fs, N, TS, "fs");
+  if (d.cur_out == d.cur || d.prev_out == d.prev) fail("the launch writes a state array that it reads");
+}
+
 // Blocked fourth-order launch: K steps of a 2D single solve by the row-marching pipeline.
 // Every access goes through a buffer resource sized to the (n+1)^2 grid, so the model checks
 // that each pointer holds the whole grid, and that the grid and block match the tiling.
@@ -706,6 +776,8 @@ void check_launch(const void* fn, dim3 g, dim3 b, void** args) {
   bool done = true;
   if (base == "k_fused2d") model_fused2d(t, g, b, args);
   else if (base == "k_step2d") model_step2d(t, g, b, args);
+  else if (base == "k_step3d") model_step3d(t, g, b, args);
+  else if (base == "k_fused3d") model_fused3d(t, g, b, args);
   else if (base == "k_first") model_first(t, g, b, args);
   else if (base == "k_fwd_out2d") model_fwd_out2d(g, b, args);
   else if (base == "k_adj_step2d") model_adj_step2d(g, b, args);
