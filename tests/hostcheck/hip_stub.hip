@@ -417,6 +417,28 @@ int batch_class(const BDesc& d, const BState& st) {
   return (stepping && prec == 1) ? 1 : 0;
 }
 
+// control: one block per problem reduces that problem's tile partials and updates its state
+void model_batch_control(dim3 g, dim3 b, void** args) {
+  const BDesc* descs = arg<const BDesc*>(args, 0);
+  const BState* states = arg<const BState*>(args, 1);
+  const int K = arg<int>(args, 2);
+  const int nb = (int)g.x;
+  if (b.x != 256 || g.y != 1) fail("control launch shape");
+  if (K < 1 || K > 8) fail("steps per launch %d", K);
+  check_range(descs, 0, (int64_t)sizeof(BDesc) * nb, "descs");
+  check_range(states, 0, (int64_t)sizeof(BState) * nb, "states");
+  for (int i = 0; i < nb; ++i)
+    check_range(descs[i].partials, 0, 8LL * descs[i].ntx * descs[i].nty, "tile partials");
+}
+
+// count of unfinished problems (one block)
+void model_batch_count(dim3 g, dim3 b, void** args) {
+  const int nb = arg<int>(args, 1);
+  if (g.x != 1 || b.x != 256) fail("count launch shape");
+  check_range(arg<const BState*>(args, 0), 0, (int64_t)sizeof(BState) * nb, "states");
+  check_range(arg<int*>(args, 2), 0, 4, "counter");
+}
+
 void model_batch_plan(dim3 g, dim3 b, void** args) {
   const BDesc* descs = arg<const BDesc*>(args, 0);
   const BState* states = arg<const BState*>(args, 1);
@@ -645,6 +667,54 @@ bool model_generic(const std::string& base, const std::vector<std::string>& t, d
     if (!(src + nd <= dst || dst + nd <= src)) fail("source and destination slot ranges overlap");
     vec(arg<void*>(args, 0), (int64_t)nd * nd, 8, "matrix");
     vec(arg<void*>(args, 2), std::max(src, dst) + nd, 8, "slots");
+  } else if (base == "k_cols_project") {
+    // columns c0 .. c0+KC-1 of V (stride ldv) against r over N points; partials [block][ncols]
+    const int KC = ti(t, 0);
+    const int64_t ldv = arg<int64_t>(args, 1), N = arg<int64_t>(args, 3);
+    const int ncols = arg<int>(args, 2);
+    if (ncols < 1 || (int)g.y != (ncols + KC - 1) / KC) fail("%d columns in %u chunks of %d", ncols, g.y, KC);
+    if (ldv < N) fail("column stride %lld below N = %lld", (long long)ldv, (long long)N);
+    vec(arg<void*>(args, 0), (int64_t)(ncols - 1) * ldv + N, 8, "V");
+    vec(arg<void*>(args, 4), N, 8, "r");
+    vec(arg<void*>(args, 5), (int64_t)g.x * ncols, 8, "partials");
+  } else if (base == "k_dense_combine") {
+    const int64_t ldv = arg<int64_t>(args, 1), N = arg<int64_t>(args, 3);
+    const int nd = arg<int>(args, 2), aslot = arg<int>(args, 6), src = arg<int>(args, 10);
+    if (nd > 0) vec(arg<void*>(args, 0), (int64_t)(nd - 1) * ldv + N, 8, "V");
+    vec(arg<void*>(args, 4), N, 8, "y");
+    vec(arg<void*>(args, 7), N, 8, "r");
+    const double* slots = arg<const double*>(args, 9);
+    if (nd > 0) check_range(slots, 8LL * src, 8LL * (src + nd), "coefficient slots");
+    if (aslot >= 0) check_range(slots, 8LL * aslot, 8LL * (aslot + 1), "alpha slot");
+  } else if (base == "k_gs_sub" || base == "k_gs_update") {
+    // w -= V h over the first nv columns (stride N); k_gs_update holds h in KC registers
+    const int64_t N = arg<int64_t>(args, 1);
+    const int nv = arg<int>(args, 2), hsrc = arg<int>(args, 4);
+    if (base == "k_gs_update" && nv > ti(t, 0)) fail("%d columns beyond the %d registers", nv, ti(t, 0));
+    vec(arg<void*>(args, 0), (int64_t)nv * N, 8, "basis");
+    check_range(arg<const double*>(args, 3), 8LL * hsrc, 8LL * (hsrc + nv), "h slots");
+    vec(arg<void*>(args, 5), N, 8, "w");
+    if (base == "k_gs_update") {
+      const bool proj = ti(t, 1) != 0;
+      vec(arg<void*>(args, 6), (int64_t)g.x * (proj ? nv + 1 : 1), 8, "partials");
+    }
+  } else if (base == "k_terms_to_modes") {
+    const int* toff = arg<const int*>(args, 1);
+    const int nd = arg<int>(args, 2), dst = arg<int>(args, 4);
+    vec(toff, nd + 1, 4, "term offsets");
+    for (int k = 0; k < nd; ++k)
+      if (toff[k + 1] < toff[k]) fail("term offsets decrease at %d", k);
+    vec(arg<void*>(args, 0), toff[nd], 8, "term sums");
+    check_range(arg<const double*>(args, 3), 8LL * dst, 8LL * (dst + nd), "slots");
+    vec(arg<void*>(args, 5), nd, 8, "scale");
+  } else if (base == "k_modes_to_terms") {
+    const int* tmap = arg<const int*>(args, 1);
+    const int nt = arg<int>(args, 2);
+    vec(tmap, nt, 4, "term map");
+    int mx = -1;
+    for (int q = 0; q < nt; ++q) mx = std::max(mx, tmap[q]);
+    vec(arg<void*>(args, 0), mx + 1, 8, "mode coefficients");
+    vec(arg<void*>(args, 3), nt, 8, "term coefficients");
   } else if (base == "k_sine_tables") {
     // tab[(k dim + axis)(n + 1) + i] for every k < nd, axis < dim, i <= n; modes[k dim + axis]
     const int nd = arg<int>(args, 2), dim = arg<int>(args, 3), n = arg<int>(args, 4);
@@ -782,6 +852,8 @@ void check_launch(const void* fn, dim3 g, dim3 b, void** args) {
   else if (base == "k_fwd_out2d") model_fwd_out2d(g, b, args);
   else if (base == "k_adj_step2d") model_adj_step2d(g, b, args);
   else if (base == "k_batch_plan") model_batch_plan(g, b, args);
+  else if (base == "k_batch_control") model_batch_control(g, b, args);
+  else if (base == "k_batch_count") model_batch_count(g, b, args);
   else if (base == "k_batch_work") model_batch_work(t, g, b, args);
   else if (base == "k_batch_tile") model_batch_tile(t, g, b, args);
   else if (base == "k_march4") model_march4(t, g, b, args);

@@ -1,7 +1,7 @@
 """Host-side checks of libwaveholtz without a GPU (tests/hostcheck): the library's host code,
 built without device code under AddressSanitizer and UBSan, drives every entry point
-against a stand-in HIP runtime that checks every modelled kernel launch and every copy
-against the buffers it touches (the index ranges each launch would reach are computed with
+against a stand-in HIP runtime that checks every kernel launch (each kernel has a model) and
+every copy against the buffers it touches (the index ranges each launch would reach are computed with
 the kernels' own formulas).  The adjoint group replays the arguments of the GPU adjoint tests
 (n = 24, checkpoints every 2, 5, 16 steps)."""
 import os
@@ -31,3 +31,5 @@ def test_host_code_under_sanitizers(exe, group, seed):
     tail = (r.stdout[-3000:] + "\n" + r.stderr[-6000:])
     assert r.returncode == 0, tail
     assert "HOSTCHECK OK" in r.stdout, tail
+    # every kernel the library launches has a model: a launch no model checks is a failure
+    assert "not modelled" not in r.stdout, tail
