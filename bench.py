@@ -421,7 +421,9 @@ def main():
                      "hbm_gbs_from_traffic": None if traffic is None else round(traffic / (launch_us * 1e-6) / 1e9, 1),
                      "copy_gbs": round(copy_gbs, 1)},
     }
-    # same 256 problems in the other forms, once each
+    # same 256 problems in the other forms, once each (their solutions kept on the host for the
+    # oracle comparison of the CPU leg)
+    others = {}
     if not args.no_f64:
         for solver in ("dcg", "cg"):
             dk = dict(solver=solver, tol=1e-8, max_iters=100000, precision="f64")
@@ -431,6 +433,7 @@ def main():
             defl = [wh.sine_deflation(2, q.n, q.omega, nd) for q, nd in zip(probs, nds)] if solver == "dcg" else None
             res, dt = _timed(torch, lambda: [wh.solve(f, q.omega, **dk, **({"defl": defl[j]} if defl else {}))
                                             for j, (f, q) in enumerate(zip(fs, probs))])
+            others[f"single_f64_{solver}"] = [u.cpu().numpy() for u, _ in res]
             line[f"single_f64_{solver}"] = {
                 "seconds": round(dt, 3), "iters": int(sum(i["iters"] for _, i in res)),
                 "status_counts": {str(k): sum(1 for _, i in res if i["status"] == k)
@@ -439,6 +442,7 @@ def main():
     if not args.no_cg:
         kcg = dict(kw, solver="cg")
         (ucg, icg), dt = _timed(torch, lambda: wh.solve_batched(batch, **kcg))
+        others["batched_mixed_cg"] = [u.cpu().numpy() for u in ucg]
         blk = {"seconds": round(dt, 3), "iters": int(sum(i["iters"] for i in icg)),
                "status_counts": {str(k): sum(1 for i in icg if i["status"] == k) for k in sorted(set(i["status"] for i in icg))},
                "max_true_rel_res": max(i["true_rel_res"] for i in icg),
@@ -449,9 +453,10 @@ def main():
             blk["speedup_vs_single_f64_cg"] = round(line["single_f64_cg"]["seconds"] / dt, 3)
         line["batched_mixed_cg"] = blk
     # the previous single-solve line (1024^2 mixed DCG), kept as an extra key
-    line["cfg2_single_solve"] = _cfg2_brief(np, torch, wh, wl)
+    line["cfg2_single_solve"], cfg2_u = _cfg2_brief(np, torch, wh, wl)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline_cfg4(probs, [u.cpu().numpy() for u in us], infos)
+        line["cpu_baseline"] = cpu_baseline_cfg4(probs, [u.cpu().numpy() for u in us], infos, others,
+                                                 (wl.config2(), cfg2_u))
     print(json.dumps(line), flush=True)
 
 
@@ -504,7 +509,7 @@ def _cfg2_brief(np, torch, wh, wl):
     return {"workload": "2D 1024^2, c=1, omega=100.3, mixed DCG with 32 sine modes, tol 1e-8",
             "time_to_tol_ms": round(dt * 1e3, 2), "gpts": round((p.n - 1) ** 2 * steps / dt / 1e9, 1),
             "iters": info["iters"], "true_rel_res": info["true_rel_res"],
-            "helmholtz_rel_res": wh.helmholtz_residual(u, f, p.omega)}
+            "helmholtz_rel_res": wh.helmholtz_residual(u, f, p.omega)}, u.cpu().numpy()
 
 
 def _dst_job(args):
@@ -513,12 +518,14 @@ def _dst_job(args):
     return disc.direct_solve_dst(2, n, omega, f)
 
 
-def cpu_baseline_cfg4(probs, sols, infos, budget_s=20.0):
+def cpu_baseline_cfg4(probs, sols, infos, others=None, single=None, budget_s=20.0):
     """The oracle on the host for the batch: (1) its FP64 WaveHoltz CG (the iteration the GPU
     runs, step by step in scipy) on a bounded sample -- the 128^2 problems over a spawn pool of
     every visible core, until about budget_s -- as wave-step Gpts/s; (2) its direct solve of every
     problem's discrete Helmholtz system (sine transform, exact for c = 1), timed, and the
-    element-wise error of each GPU solution against it."""
+    element-wise error of each GPU solution against it: the batch's, those of the comparison
+    runs on the same problems (`others`: name -> solutions), and that of the single 1024^2
+    solve (`single`: (problem, solution))."""
     import multiprocessing as mp
     import numpy as np
     cores = len(os.sched_getaffinity(0))
@@ -537,7 +544,18 @@ def cpu_baseline_cfg4(probs, sols, infos, budget_s=20.0):
         t1 = time.perf_counter()
         exact = pool.map(_dst_job, [(q.n, q.omega, q.f) for q in probs])
         t_dst = time.perf_counter() - t1
-    errs = [float(np.abs(u - U).max() / np.abs(U).max()) for u, U in zip(sols, exact)]
+    def err(u, U):
+        return float(np.abs(u - U).max() / np.abs(U).max())
+    errs = [err(u, U) for u, U in zip(sols, exact)]
+    other_errs = {}
+    for k, v in (others or {}).items():
+        e = [err(u, U) for u, U in zip(v, exact)]
+        j = int(np.argmax(e))
+        other_errs[k] = {"max": e[j], "median": float(np.median(e)),
+                         "at_max": {"n": probs[j].n, "omega": round(probs[j].omega, 4)}}
+    if single is not None:
+        q, u = single
+        other_errs["cfg2_single_solve"] = {"max": err(u, _dst_job((q.n, q.omega, q.f)))}
     by_n = {}
     for q, e in zip(probs, errs):
         by_n.setdefault(q.n, []).append(e)
@@ -550,8 +568,10 @@ def cpu_baseline_cfg4(probs, sols, infos, budget_s=20.0):
             "error_vs_oracle_max_elementwise": max(errs),
             "error_vs_oracle_by_size_max": {str(k): max(v) for k, v in sorted(by_n.items())},
             "error_vs_oracle_each": [float(f"{e:.3g}") for e in errs],
+            "error_vs_oracle_max_other_runs": other_errs,
             "error_note": "max_i |u_i - U_i| / max|U| per solution against the oracle's direct solve (sine "
-                          "transform) of the same discrete Helmholtz system"}
+                          "transform) of the same discrete Helmholtz system; for the other runs the maximum "
+                          "and median over their solutions and the problem at the maximum"}
 
 
 
