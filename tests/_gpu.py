@@ -17,6 +17,11 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
+def relmx(a, b):
+    """The larger of the 2-norm relative error and the element-wise one (relative to max |b|)."""
+    return max(rel(a, b), maxrel(a, b))
+
+
 def maxrel(a, b):
     """Element-wise: max_i |a_i - b_i| / max_i |b_i|."""
     return float(np.abs(np.asarray(a) - np.asarray(b)).max() / np.abs(np.asarray(b)).max())

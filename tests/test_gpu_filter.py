@@ -4,7 +4,7 @@ import pytest
 
 import workloads as wl
 from oracle import discretization as disc, wavesolve as ws, transfer as tr, modes
-from _gpu import cuda, host, rel, oracle_tp
+from _gpu import cuda, host, oracle_tp, relmx
 
 pytestmark = pytest.mark.gpu
 
@@ -48,7 +48,7 @@ def test_filter_f64_matches_oracle(dim, n, omega, varc, force):
                                 c2=None if c2 is None else cuda(c2))
     ref = _oracle_filter(dim, n, omega, v, f, c2)
     got = host(out)
-    assert rel(got, ref) < 1e-12
+    assert relmx(got, ref) < 1e-12
     # boundary written as zero
     assert np.all(got[0] == 0) and np.all(got[-1] == 0)
     assert info["nt"] == oracle_tp(dim, n, omega, c2).nt
@@ -69,9 +69,9 @@ def test_filter_mixed_within_fp32_bound(dim, n, omega, varc, force):
     out, _ = wh.apply_filter(cuda(v), omega, f=None if f is None else cuda(f),
                              c2=None if c2 is None else cuda(c2), precision="mixed")
     ref = _oracle_filter(dim, n, omega, v, f, c2)
-    e = rel(host(out), ref)
+    e = relmx(host(out), ref)
     # FP32 stepping over N_t steps: the oracle's own FP32 emulation predicts ~1e-6
-    emu = rel(_oracle_filter(dim, n, omega, v, f, c2, state_dtype=np.float32), ref)
+    emu = relmx(_oracle_filter(dim, n, omega, v, f, c2, state_dtype=np.float32), ref)
     print(f"mixed error {e:.2e} (oracle fp32 emulation {emu:.2e})", flush=True)
     assert e < 2e-5 and e < 20 * emu + 1e-7
 
@@ -92,7 +92,7 @@ def test_filter_fixed_point_config1():
     L = disc.laplacian(2, p.n)
     U = disc.to_nodal(disc.direct_solve(L, p.omega, disc.to_interior(p.f)), 2, p.n)
     out, _ = wh.apply_filter(cuda(U), p.omega, f=cuda(p.f))
-    assert rel(host(out), U) < 1e-13
+    assert relmx(host(out), U) < 1e-13
 
 
 @pytest.mark.parametrize("k_fuse", [1, 2, 3, 4, 6, 8])
@@ -130,10 +130,10 @@ def _fused_case(k_fuse, shape, dim, n, omega, varc, force):
                 k_shape=shape)
     out, info = wh.apply_filter(cuda(v), omega, **args)
     assert info["k_fuse"] == k_fuse or (k_fuse > 1 and info["k_fuse"] < k_fuse and info["nt"] < k_fuse + 2)
-    assert rel(host(out), ref) < 1e-12
+    assert relmx(host(out), ref) < 1e-12
     out32, _ = wh.apply_filter(cuda(v), omega, precision="mixed", **args)
-    emu = rel(_oracle_filter(dim, n, omega, v, f, c2, state_dtype=np.float32), ref)
-    assert rel(host(out32), ref) < 20 * emu + 1e-7
+    emu = relmx(_oracle_filter(dim, n, omega, v, f, c2, state_dtype=np.float32), ref)
+    assert relmx(host(out32), ref) < 20 * emu + 1e-7
 
 
 @pytest.mark.parametrize("n,omega,force", [(96, 29.5, True), (130, 11.3, False), (64, 19.7, True)])
@@ -156,5 +156,5 @@ def test_fused2d_k9_every_shape(shape):
     ref = _oracle_filter(2, n, omega, v, f, None)
     out32, info = wh.apply_filter(cuda(v), omega, f=cuda(f), precision="mixed", k_fuse=9, k_shape=shape)
     assert info["k_fuse"] == 9
-    emu = rel(_oracle_filter(2, n, omega, v, f, None, state_dtype=np.float32), ref)
-    assert rel(host(out32), ref) < 20 * emu + 1e-7
+    emu = relmx(_oracle_filter(2, n, omega, v, f, None, state_dtype=np.float32), ref)
+    assert relmx(host(out32), ref) < 20 * emu + 1e-7
