@@ -8,7 +8,7 @@ import pytest
 
 import workloads as wl
 from oracle import adjoint, discretization as disc, wavesolve as ws, transfer as tr, modes
-from _gpu import cuda, host, oracle_tp, relmx
+from _gpu import assert_close, cuda, host, oracle_tp, relmx
 
 pytestmark = pytest.mark.gpu
 
@@ -85,6 +85,44 @@ def test_config3_filter_properties_full_size():
     a, b = float((u * Sv).sum()), float((v * Su).sum())
     print(f"symmetry {a:.12e} {b:.12e}", flush=True)
     assert abs(a - b) <= 1e-11 * (float(u.norm()) * float(Sv.norm()))
+
+
+def test_config3_varc_wave_solve_and_residuals_full_size():
+    """256^3 with the benchmarked variable c and forcing, against two of the oracle's FP64
+    wave solves (about a minute on one core).  x is the iterate after 40 FP64 CG steps on the
+    config-3 system (the solve stops at its cap, far from the tolerance, so x is not close to
+    the fixed point).  Checked: Pi_h(x; f) element-wise in FP64 (eq. discreteWaveExplicit with
+    the trapezoid sum of eq. quadrature) and FP32-stepped; the true residual the solver reports
+    at exit, ||Pi_h(x; f) - x|| / ||Pi_h(0; f)|| (eq. WaveHoltzDiscreteFPI); the Helmholtz
+    residual ||f - (L_h + omega^2) x|| / ||f|| of the verification kernel."""
+    print("case config3 variable-c wave solve 256^3", flush=True)
+    import paper_2606_31842_amd as wh
+    p = wl.config3()
+    f, c2 = cuda(p.f), cuda(p.c2)
+    x, info = wh.solve(f, p.omega, c2=c2, solver="cg", precision="f64", tol=1e-8, max_iters=40)
+    print(f"cg status {info['status']} iters {info['iters']} true res {info['true_rel_res']:.3e}", flush=True)
+    assert info["iters"] == 40 and info["true_rel_res"] > 1e-6
+    pix64, _ = wh.apply_filter(x, p.omega, f=f, c2=c2)
+    pix32, i32 = wh.apply_filter(x, p.omega, f=f, c2=c2, precision="mixed")
+    hres = wh.helmholtz_residual(x, f, p.omega, c2)
+    xh, pix64, pix32 = host(x), host(pix64), host(pix32)
+    del x
+    L = disc.laplacian(3, p.n, p.c2)
+    tp = oracle_tp(3, p.n, p.omega, c2=p.c2)
+    xi, fi = disc.to_interior(xh), disc.to_interior(p.f)
+    ref = ws.wave_filter(L, xi, fi, tp)
+    assert_close(disc.to_interior(pix64), ref, 1e-11, "Pi_h(x;f) FP64")
+    # FP32 stepping: about 1e-6 relative per wave solve on the small grids of the filter tests
+    # (where the oracle's own FP32 emulation bounds it); 96 steps of a 256^3 grid, blocked K-step launches
+    print(f"  mixed launches: K = {i32['k_fuse']}", flush=True)
+    assert_close(disc.to_interior(pix32), ref, 2e-5, "Pi_h(x;f) FP32-stepped")
+    b = ws.rhs(L, fi, tp)
+    res = float(np.linalg.norm(ref - xi) / np.linalg.norm(b))
+    print(f"  true residual: solver {info['true_rel_res']:.12e} oracle {res:.12e}", flush=True)
+    assert abs(info["true_rel_res"] - res) <= 1e-9 * res
+    hres_o = disc.helmholtz_residual(L, p.omega, xi, fi)
+    print(f"  Helmholtz residual: kernel {hres:.12e} oracle {hres_o:.12e}", flush=True)
+    assert abs(hres - hres_o) <= 1e-10 * hres_o
 
 
 def test_config4_batched_every_size():
