@@ -41,8 +41,8 @@ B_FUSED_F32 = 32.0
 # HBM KiB per dispatch (FETCH_SIZE, WRITE_SIZE) of the tagged batch work kernel on the config-4
 # batch, from the two counter passes in profiles/hbm_traffic_batch_tile_cfg4.md, with the copy-kernel
 # scale factors; valid only for the kernel sources it was taken on (sha1 over the three files)
-BATCH_TRAFFIC = {"src_sha1": "9dbd7bea7a323d2d01d727de27ce8102b9df8477", "fetch_scale": 2.0, "write_scale": 1.0,
-                 "kib": [732972.1, 1417027.8]}
+BATCH_TRAFFIC = {"src_sha1": "77f221ac8450026321c4cc81a015087f729457f0", "fetch_scale": 2.0, "write_scale": 1.0,
+                 "kib": [744030.1, 1410878.1]}
 # HBM KiB per dispatch (FETCH_SIZE, WRITE_SIZE) of every FP32 temporally blocked kernel
 # variant "K,R,NW" on this grid, from the two rocprofv3 counter passes summarised in
 # profiles/hbm_traffic_fused2d_f32_2d1024.md (scaled by FETCH x 2.000, WRITE x 1.000 from a

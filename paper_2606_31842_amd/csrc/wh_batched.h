@@ -46,7 +46,10 @@ __host__ __device__ inline int phase_prec(int ph, int mixed) {
 // Tile of the work kernels: kBW wavefronts side by side, each a strip of 64 * kBC columns
 // of which the inner 64 * kBC - 2K are written (the row-marching K-step pipeline), over
 // kBSeg rows.  Element-wise phases cover the same tile with all 64 * kBW threads.
-constexpr int kBW = 4;
+// Two-wave blocks: on the 256-problem batch (FP32, K = 8) the stepping launch takes 665 us
+// against 698 us with four waves per block, and the batch 1.284 s against 1.346 s; one-wave
+// blocks step faster still (658 us) but lengthen the other phases (batch 1.387 s).
+constexpr int kBW = 2;
 constexpr int kBC = 1;
 constexpr int kBSeg = 32;
 __host__ __device__ constexpr int batch_strip(int K) { return 64 * kBC - 2 * K; }

@@ -353,8 +353,8 @@ constexpr int batch_waves_per_eu() {
 // takes items of its XCD's chunk from that chunk's counter, then helps with the other chunks.
 // The plan kernel resets the counters.  TAG only separates the measurement launches of
 // wh_time_batch_kernel (TAG = 1) from the solver's in profiles; the code is the same.
-// The occupancy bound keeps the register budget of the one-tile-per-block form (constant c:
-// 6 waves per SIMD in FP32, i.e. three 8-wave blocks per CU, 4 in FP64; variable c: 4 and 2).
+// The occupancy bound keeps the register budget of the one-tile-per-block form
+// (batch_waves_per_eu: the waves per SIMD that the row pipeline's registers allow).
 template <typename T, int K, bool VARC, int TAG = 0, int ORD = 2>
 __global__ __launch_bounds__(64 * kBW, (batch_waves_per_eu<T, K, VARC, ORD>()))
 void k_batch_work(const BDesc* __restrict__ descs,

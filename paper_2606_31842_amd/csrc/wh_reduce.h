@@ -21,7 +21,7 @@ __device__ __forceinline__ double wave_max(double v) {
 // reproducible run to run.  Every thread of the block must call it.
 template <int NWAVES>
 __device__ __forceinline__ double block_sum(double v, int tid) {
-  static_assert(NWAVES == 4 || NWAVES == 8 || NWAVES == 16, "waves per block");
+  static_assert(NWAVES == 2 || NWAVES == 4 || NWAVES == 8 || NWAVES == 16, "waves per block");
   __shared__ double sm[NWAVES];
   v = wave_sum(v);
   if ((tid & 63) == 0) sm[tid >> 6] = v;
