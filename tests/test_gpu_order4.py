@@ -141,7 +141,7 @@ def _batch4(sizes=(24, 40, 101, 200), per=2, seed=17, omega=(8.0, 30.0)):
 @pytest.mark.parametrize("precision,solver,k_fuse", [("f64", "cg", 8), ("mixed", "dcg", 8), ("mixed", "cg", 4),
                                                      ("f64", "dcg", 2)])
 def test_order4_batched_matches_direct_and_single(precision, solver, k_fuse):
-    """Fourth-order batched solves (one 200^2 problem per pair spans two tile columns) against
+    """Fourth-order batched solves (one 200^2 problem per pair spans two or three tile columns, by K) against
     the oracle's direct fourth-order solve, and FP64 against the single-solve path."""
     print(f"case order4 batched {precision} {solver} K={k_fuse}", flush=True)
     import paper_2606_31842_amd as wh
