@@ -454,6 +454,12 @@ def main():
         line["batched_mixed_cg"] = blk
     # the previous single-solve line (1024^2 mixed DCG), kept as an extra key
     line["cfg2_single_solve"], cfg2_u = _cfg2_brief(np, torch, wh, wl)
+    # the stepping kernels of the largest single solve (256^3, variable c), kept as an extra key;
+    # its solves take minutes and run under --workload cfg3
+    p3 = wl.config3()
+    line["cfg3_stepping"] = {"workload": "3D 256^3, variable c (seed 3), omega=40: one blocked launch",
+                             **_cfg3_step_kernels(torch, wh, wl, p3, torch.from_numpy(p3.c2).cuda())}
+    del p3
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline_cfg4(probs, [u.cpu().numpy() for u in us], infos, others,
                                                  (wl.config2(), cfg2_u))
@@ -602,14 +608,11 @@ def run_cfg1(args, np, torch, wh, wl):
     return out
 
 
-def run_cfg3(args, np, torch, wh, wl):
-    """3D 256^3, seeded variable c, omega = 40: GMRES(40) (mixed and FP64, capped) and CG (FP64 and mixed) to
-    a true residual of 1e-8, with the Helmholtz residual as the accuracy check at this size."""
-    p = wl.config3()
-    f = torch.from_numpy(p.f).cuda()
-    c2 = torch.from_numpy(p.c2).cuda()
+def _cfg3_step_kernels(torch, wh, wl, p, c2):
+    """Per-launch time of the autotuned 3D blocked stepping kernel on the 256^3 variable-c grid,
+    FP32 and FP64 (HIP events inside the library, 20 launches)."""
     pts = (p.n - 1) ** 3
-    out = {"workload": "cfg3 3D 256^3 variable c omega=40 mixed tol 1e-8"}
+    out = {}
     v = torch.from_numpy(wl.random_nodal(3, p.n, 1)).cuda()
     for prec in ("mixed", "f64"):
         ms, sh = wh.time_step_kernel(v, p.omega, c2=c2, precision=prec, reps=20, shape=True)
@@ -621,6 +624,18 @@ def run_cfg3(args, np, torch, wh, wl):
         out[f"step_kernel_{prec}"] = {"us_per_launch": us, "k_fuse": k, "rows": sh["rows"], "waves": sh["waves"],
                                       "us_per_step": us / k, "gpts": pts * k / us / 1e3, "bytes_per_pt_step": bpp,
                                       "achieved_gbs": bpp * pts * k / (us * 1e-6) / 1e9}
+    return out
+
+
+def run_cfg3(args, np, torch, wh, wl):
+    """3D 256^3, seeded variable c, omega = 40: GMRES(40) (mixed and FP64, capped) and CG (FP64 and mixed) to
+    a true residual of 1e-8, with the Helmholtz residual as the accuracy check at this size."""
+    p = wl.config3()
+    f = torch.from_numpy(p.f).cuda()
+    c2 = torch.from_numpy(p.c2).cuda()
+    pts = (p.n - 1) ** 3
+    out = {"workload": "cfg3 3D 256^3 variable c omega=40 mixed tol 1e-8"}
+    out.update(_cfg3_step_kernels(torch, wh, wl, p, c2))
     if args.probe_traffic:
         return out
     # GMRES(40) as the workload states it (capped: it stalls near resonance); CG to the
